@@ -1,0 +1,196 @@
+/*
+ * ptafs.h -- C ABI of the Fourier-space PTA log-posterior library (gfx950).
+ *
+ * The library evaluates, for many parameter vectors ("chains") at once, the
+ * whitened Fourier-space log-posterior of a pulsar timing array and its full
+ * gradient, and runs fixed-step HMC on it.  The density is the one of the
+ * paper's Sec. IV (Eqs. likelihood, WN_cov, Fourier_series, RN=Fa, prior_cov,
+ * HD, power_law, a_prior, raw_det_posterior) with the Fourier coefficients
+ * reparameterised as a = L(eta) z per frequency, L the Cholesky factor of the
+ * per-frequency prior covariance (Sec. II.B, Eqs. standardizing_transform and
+ * standardized_density with mu = 0, Sigma = phi):
+ *
+ *   r      = dt - M b - F a - w F a_dm - h(theta_cw)      per TOA
+ *   log p  = -1/2 sum_i (r_i^2/N_i + ln N_i + ln 2pi)
+ *            - 1/2 (|z|^2 + |z_dm|^2 + |u|^2) - d_z/2 ln 2pi + log pi(theta)
+ *   N_i    = (EFAC_mu sigma_i)^2 + EQUAD_mu^2
+ *   rho_k  = A^2/(12 pi^2) yr^3 (f_k yr)^-gamma / T      (power law; yr^3 reading)
+ *   phi_k  = rho_k Gamma_HD + diag(kappa_.k),  L_k = chol(phi_k)
+ *   a_.k,sin = L_k z_.k,sin,  a_.k,cos = L_k z_.k,cos,  a_dm = sqrt(kappa_dm) z_dm,
+ *   b = sigma_b u on M = [1, tau, tau^2], tau = (t - mid_I)/halfspan_I.
+ *
+ * Units: seconds and Hz; every floating-point value is IEEE binary64.
+ *
+ * Conventions
+ *   - Return codes: 0 = success, negative = call-level error (ptafs_strerror).
+ *   - Per-chain conditions are not call errors: such a chain gets
+ *     logp = -INFINITY, an all-zero gradient and a nonzero status:
+ *       1 hyper-parameter outside its prior box (or not finite),
+ *       2 phi_k not positive definite,
+ *       3 CW evolution variable y >= 1 within the data span (coalescence),
+ *       4 non-finite input coordinate or non-finite result.
+ *     Other chains are unaffected.
+ *   - "device" pointers are HIP device pointers on the dataset's device and are
+ *     owned by the caller; all device work is enqueued on the given stream
+ *     (hipStream_t passed as void*, NULL = default stream) and the calls return
+ *     without synchronising, except where stated.
+ *   - Threading: a dataset may be used by one stream at a time (its workspace
+ *     is shared by all its calls).
+ */
+#ifndef PTAFS_H
+#define PTAFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PTAFS_OK 0
+#define PTAFS_E_ARG (-1)       /* invalid argument or unsupported shape */
+#define PTAFS_E_HIP (-2)       /* a HIP runtime call failed */
+#define PTAFS_E_NOMEM (-3)     /* device allocation failed */
+#define PTAFS_E_LIMIT (-4)     /* a size exceeds a documented limit */
+
+/* Status values written per chain. */
+#define PTAFS_ST_OK 0
+#define PTAFS_ST_PRIOR 1
+#define PTAFS_ST_NOTPD 2
+#define PTAFS_ST_CW 3
+#define PTAFS_ST_NONFINITE 4
+
+/* Limits of this implementation (PTAFS_E_LIMIT beyond them). */
+#define PTAFS_MAX_PSR 128      /* pulsars per data set */
+#define PTAFS_MAX_HARM 30      /* max(nf_rn, nf_gw, nf_dm) */
+
+typedef struct ptafs_dataset ptafs_dataset;   /* opaque */
+
+/*
+ * Description of one data set (Sec. III: TOAs, uncertainties, backends and
+ * their white-noise parameters, radio frequencies, sky positions; Sec. IV.A:
+ * basis sizes and hyper-prior box).  All pointers are HOST pointers; the
+ * library copies everything during ptafs_dataset_create, so the caller may
+ * free them afterwards.
+ */
+typedef struct {
+  int32_t n_psr;                 /* number of pulsars, 1..PTAFS_MAX_PSR */
+  const int64_t *toa_offsets;    /* n_psr+1 ascending offsets into the TOA arrays
+                                    (CSR over the concatenated pulsars); every
+                                    pulsar needs at least one TOA */
+  const double *t;               /* TOA times from the array epoch, s, in [0, tspan] */
+  const double *dt;              /* timing residuals, s */
+  const double *sigma;           /* TOA uncertainties, s (> 0) */
+  const double *nu;              /* radio frequency per TOA, Hz (> 0) */
+  const int32_t *backend;        /* backend index per TOA, 0..n_backend-1 */
+  int32_t n_backend;
+  const double *efac;            /* per backend, Eq. WN_cov */
+  const double *equad;           /* per backend, s */
+  const double *psr_pos;         /* 3*n_psr unit vectors (x, y, z per pulsar) */
+  double tspan;                  /* T of Eq. Fourier_series, s (> 0) */
+  int32_t nf_rn;                 /* intrinsic red-noise frequencies k = 1..nf_rn (0 = off) */
+  int32_t nf_gw;                 /* common HD-correlated frequencies (0 = off) */
+  int32_t nf_dm;                 /* DM-noise frequencies (0 = off) */
+  double dm_scale;               /* DM basis weight w_i = dm_scale / nu_i^2 */
+  double sigma_b;                /* scale of the timing-model coefficients, b = sigma_b u */
+  int32_t has_cw;                /* 1: eight CW parameters in theta (Earth term) */
+  const double *prior_lo;        /* n_theta lower box edges, theta order below */
+  const double *prior_hi;        /* n_theta upper box edges */
+} ptafs_dataset_desc;
+
+/*
+ * Flat parameter vector of one chain (length d), in this order:
+ *   theta: [gw (log10A, gamma) if nf_gw>0 | rn (log10A_I, gamma_I) x n_psr if nf_rn>0 |
+ *           dm (log10A_I, gamma_I) x n_psr if nf_dm>0 |
+ *           cw (cos theta, phi, log10 Mc, log10 f_gw, Phi0, cos iota, psi, log10 h) if has_cw]
+ *   u    : 3 x n_psr (pulsar-major)
+ *   z    : n_psr x 2K, K = max(nf_rn, nf_gw), per pulsar k=1 sin, k=1 cos, k=2 sin, ...
+ *   z_dm : n_psr x 2 nf_dm, same ordering
+ * Offsets below are in elements.
+ */
+typedef struct {
+  int64_t d, n_theta;
+  int64_t off_gw, off_rn, off_dm, off_cw, off_u, off_z, off_zdm;
+  int64_t n_psr, n_toa, k_coef, k_dm;
+  size_t dataset_bytes;          /* device memory held by the data set itself */
+  size_t workspace_bytes;        /* workspace needed for the requested n_chains */
+} ptafs_layout_info;
+
+/* Copy a data set to the current HIP device and prepare it (per-pulsar tau
+ * centring, HD matrix of Eq. HD, backend table).  Synchronises `stream`.
+ * On success *out owns device memory until ptafs_dataset_destroy. */
+int ptafs_dataset_create(const ptafs_dataset_desc *desc, void *stream, ptafs_dataset **out);
+
+/* Release a data set and its workspace (synchronises the device). NULL is a no-op. */
+void ptafs_dataset_destroy(ptafs_dataset *ds);
+
+/* Layout of the parameter vector and memory needs for n_chains (>= 0). */
+int ptafs_layout(const ptafs_dataset *ds, int32_t n_chains, ptafs_layout_info *out);
+
+/* Grow the data set's workspace to serve up to n_chains per call
+ * (synchronises the device when it allocates).  Calls with more chains than
+ * reserved grow it themselves. */
+int ptafs_reserve(ptafs_dataset *ds, int32_t n_chains);
+
+/*
+ * Batched log-posterior and gradient (the fused form): one launch of the
+ * per-frequency Cholesky + transform, one ragged launch of the TOA pass over
+ * all pulsars (FP64 MFMA over 16-chain blocks), a fixed-order reduction, the
+ * per-frequency Cholesky adjoint and the assembly.
+ *   x      device, [n_chains][d]  input
+ *   logp   device, [n_chains]     output
+ *   grad   device, [n_chains][d]  output, d log p / d x
+ *   status device, [n_chains]     output (values above)
+ * n_chains == 0 is a no-op.  Results are bit-identical for identical inputs
+ * and the same tuning (fixed reduction order, no floating-point atomics).
+ */
+int ptafs_logp_grad(ptafs_dataset *ds, int32_t n_chains, const double *x, double *logp,
+                    double *grad, int32_t *status, void *stream);
+
+/*
+ * Same result through the plain form: one TOA-pass launch per pulsar with a
+ * vector-ALU kernel (no matrix cores), everything else as above.  A
+ * reference point for the batched form; same arguments and outputs.
+ */
+int ptafs_logp_grad_plain(ptafs_dataset *ds, int32_t n_chains, const double *x, double *logp,
+                          double *grad, int32_t *status, void *stream);
+
+/*
+ * Tuning of the batched TOA pass.  tiles_per_chunk: 16-TOA tiles a workgroup
+ * covers (ragged pulsars are cut into chunks of this many tiles);
+ * waves_per_block: 1, 2 or 4 waves splitting a chunk; xcd_map: 1 places the
+ * chain blocks of one chunk on the same XCD.  Takes effect on the next call.
+ */
+int ptafs_set_tuning(ptafs_dataset *ds, int32_t tiles_per_chunk, int32_t waves_per_block,
+                     int32_t xcd_map);
+int ptafs_get_tuning(const ptafs_dataset *ds, int32_t *tiles_per_chunk, int32_t *waves_per_block,
+                     int32_t *xcd_map);
+
+/*
+ * Fixed-step HMC (App. A: Eqs. Hamiltonian, Gaussian_momentum, HMC_acceptance)
+ * with a diagonal inverse mass.  For each trajectory j = traj0 .. traj0+n_traj-1
+ * and chain c: momenta p_i = n_i / sqrt(m_i) (n standard normal, Philox4x32-10
+ * with key (seed lo, seed hi) and counter (i>>1, c, j, 0), Box-Muller; p_i = 0
+ * where the inverse mass m_i is 0), a half kick, n_leapfrog drift/kick steps
+ * (the last kick a half kick), and acceptance when ln u < H0 - H1 with u from
+ * counter (0, c, j, 1).  Rejected chains keep their state.
+ *   inv_mass     device [d] or NULL (identity)
+ *   x, logp, grad device, in/out: the chains' state; logp and grad must be the
+ *                values at x on entry (e.g. from ptafs_logp_grad)
+ *   n_accept     device [n_chains] int64, incremented per accepted trajectory
+ *   samples      device [n_traj][n_chains][d] or NULL: state after each trajectory
+ * use_graph: 1 captures one trajectory as a HIP graph and replays it.
+ */
+int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n_leapfrog,
+                  double eps, const double *inv_mass, uint64_t seed, uint64_t traj0, double *x,
+                  double *logp, double *grad, int64_t *n_accept, double *samples, int32_t use_graph,
+                  void *stream);
+
+/* Human-readable text for a return code (static storage). */
+const char *ptafs_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTAFS_H */

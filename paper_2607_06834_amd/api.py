@@ -1,0 +1,179 @@
+"""Python binding of libptafs with the same names as the C ABI.
+
+PyTorch provides device memory and streams; every arithmetic step runs in the
+HIP library.  Tensors passed in must be float64 on the data set's device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Dataset:
+    """A PTA data set resident on the current GPU (ptafs_dataset_create).
+
+    ``desc`` is a mapping with the fields of ``ptafs_dataset_desc``: n_psr,
+    toa_offsets, t, dt, sigma, nu, backend, efac, equad, psr_pos, tspan,
+    nf_rn, nf_gw, nf_dm, dm_scale, sigma_b, has_cw, prior_lo, prior_hi
+    (NumPy arrays or scalars; n_backend is taken from efac)."""
+
+    def __init__(self, desc, stream=None):
+        lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libptafs needs a HIP GPU")
+        self._keep = []
+
+        def arr(name, dtype):
+            a = np.ascontiguousarray(np.asarray(desc[name]), dtype=dtype)
+            self._keep.append(a)
+            return a
+
+        offs = arr("toa_offsets", np.int64)
+        t, dt = arr("t", np.float64), arr("dt", np.float64)
+        sig, nu = arr("sigma", np.float64), arr("nu", np.float64)
+        be = arr("backend", np.int32)
+        efac, equad = arr("efac", np.float64), arr("equad", np.float64)
+        pos = arr("psr_pos", np.float64)
+        lo, hi = arr("prior_lo", np.float64), arr("prior_hi", np.float64)
+        d = _lib.DatasetDesc()
+        d.n_psr = int(desc["n_psr"])
+        d.toa_offsets = _ptr(offs, C.c_int64)
+        d.t, d.dt, d.sigma, d.nu = (_ptr(a, C.c_double) for a in (t, dt, sig, nu))
+        d.backend = _ptr(be, C.c_int32)
+        d.n_backend = int(efac.size)
+        d.efac, d.equad, d.psr_pos = (_ptr(a, C.c_double) for a in (efac, equad, pos))
+        d.tspan = float(desc["tspan"])
+        d.nf_rn, d.nf_gw, d.nf_dm = int(desc["nf_rn"]), int(desc["nf_gw"]), int(desc["nf_dm"])
+        d.dm_scale = float(desc["dm_scale"])
+        d.sigma_b = float(desc["sigma_b"])
+        d.has_cw = int(desc["has_cw"])
+        d.prior_lo, d.prior_hi = _ptr(lo, C.c_double), _ptr(hi, C.c_double)
+        h = C.c_void_p()
+        _lib.check(lib.ptafs_dataset_create(C.byref(d), _stream_handle(stream), C.byref(h)),
+                   "ptafs_dataset_create")
+        self._h = h
+        self._keep = None
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.layout = self.ptafs_layout(0)
+        self.d = int(self.layout.d)
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().ptafs_dataset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ptafs_layout(self, n_chains):
+        out = _lib.LayoutInfo()
+        _lib.check(_lib.load().ptafs_layout(self._h, int(n_chains), C.byref(out)), "ptafs_layout")
+        return out
+
+    def ptafs_reserve(self, n_chains):
+        _lib.check(_lib.load().ptafs_reserve(self._h, int(n_chains)), "ptafs_reserve")
+
+    def ptafs_set_tuning(self, tiles_per_chunk, waves_per_block=1, xcd_map=1):
+        _lib.check(_lib.load().ptafs_set_tuning(self._h, int(tiles_per_chunk), int(waves_per_block),
+                                                int(xcd_map)), "ptafs_set_tuning")
+
+    def ptafs_get_tuning(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        _lib.check(_lib.load().ptafs_get_tuning(self._h, C.byref(a), C.byref(b), C.byref(c)),
+                   "ptafs_get_tuning")
+        return a.value, b.value, c.value
+
+    def _check_x(self, x):
+        if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.is_cuda):
+            raise TypeError("x must be a float64 CUDA tensor")
+        if x.dim() != 2 or x.shape[1] != self.d:
+            raise ValueError(f"x must have shape (n_chains, {self.d})")
+        return x.contiguous()
+
+    def _call(self, fn, x, out=None, stream=None):
+        x = self._check_x(x)
+        n = x.shape[0]
+        if out is None:
+            logp = torch.empty(n, dtype=torch.float64, device=x.device)
+            grad = torch.empty_like(x)
+            status = torch.empty(n, dtype=torch.int32, device=x.device)
+        else:
+            logp, grad, status = out
+        _lib.check(fn(self._h, n, C.c_void_p(x.data_ptr()), C.c_void_p(logp.data_ptr()),
+                      C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()),
+                      _stream_handle(stream)), fn.__name__)
+        return logp, grad, status
+
+    def ptafs_logp_grad(self, x, out=None, stream=None):
+        """Batched form: returns (logp [C], grad [C, d], status [C])."""
+        return self._call(_lib.load().ptafs_logp_grad, x, out, stream)
+
+    def ptafs_logp_grad_plain(self, x, out=None, stream=None):
+        """Plain (launch per pulsar, vector ALU) form; same outputs."""
+        return self._call(_lib.load().ptafs_logp_grad_plain, x, out, stream)
+
+    def ptafs_hmc_run(self, x, logp, grad, n_accept, *, n_traj, n_leapfrog, eps, seed, traj0=0,
+                      inv_mass=None, samples=None, use_graph=True, stream=None):
+        """Fixed-step HMC in place on (x, logp, grad); n_accept int64 [C]."""
+        x = self._check_x(x)
+        n = x.shape[0]
+        for t in (logp, grad):
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+        assert n_accept.dtype == torch.int64 and n_accept.is_cuda
+        im = C.c_void_p(inv_mass.data_ptr()) if inv_mass is not None else C.c_void_p()
+        sm = C.c_void_p(samples.data_ptr()) if samples is not None else C.c_void_p()
+        if samples is not None:
+            assert samples.shape == (n_traj, n, self.d) and samples.dtype == torch.float64
+        _lib.check(_lib.load().ptafs_hmc_run(
+            self._h, n, int(n_traj), int(n_leapfrog), float(eps), im, C.c_uint64(seed),
+            C.c_uint64(traj0), C.c_void_p(x.data_ptr()), C.c_void_p(logp.data_ptr()),
+            C.c_void_p(grad.data_ptr()), C.c_void_p(n_accept.data_ptr()), sm,
+            int(bool(use_graph)), _stream_handle(stream)), "ptafs_hmc_run")
+
+
+def ptafs_dataset_create(desc, stream=None):
+    return Dataset(desc, stream)
+
+
+def ptafs_logp_grad(ds: Dataset, x, stream=None):
+    return ds.ptafs_logp_grad(x, stream=stream)
+
+
+def ptafs_logp_grad_plain(ds: Dataset, x, stream=None):
+    return ds.ptafs_logp_grad_plain(x, stream=stream)
+
+
+class LogPosterior(torch.autograd.Function):
+    """log p(x) per chain with the hand-written adjoint as its backward.
+
+    forward runs ptafs_logp_grad (which always produces the gradient) and
+    saves it; backward returns grad_out[:, None] * d log p / d x."""
+
+    @staticmethod
+    def forward(ctx, x, ds):
+        logp, grad, status = ds.ptafs_logp_grad(x.detach())
+        ctx.save_for_backward(grad)
+        ctx.mark_non_differentiable(status)
+        return logp, status
+
+    @staticmethod
+    def backward(ctx, g_logp, g_status):
+        (grad,) = ctx.saved_tensors
+        return g_logp[:, None] * grad, None

@@ -1,0 +1,144 @@
+// Internal definitions shared by the HIP translation units of libptafs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ptafs.h"
+
+namespace pt {
+
+constexpr double kYear = 365.25 * 86400.0;      // Julian year, s
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.14159265358979323846264338328;
+constexpr double kLn10 = 2.30258509299404568401799145468;
+constexpr double kLn2Pi = 1.83787706640934548356065947281;
+constexpr double kTsun = 4.925490947641e-6;      // G Msun / c^3, s
+
+constexpr int kChainBlock = 16;                  // chains per MFMA column block
+constexpr int kTile = 16;                        // TOAs per MFMA row tile
+
+// ---------------------------------------------------------------------------
+// Basis slots of the TOA pass.
+//
+// The TOA pass contracts over basis "rows" j.  Row j sits at MFMA K-step
+// s = j / 4 and lane group q = j % 4 of the forward F-operand; pairs of steps
+// (2m, 2m+1) give lane group q the sin and cos of harmonic h + 1, h = 4m + q,
+// so every lane walks the harmonics q+1, q+5, q+9, ... with one angle-addition
+// step per pair.  In the red-noise block, slots with h >= kb carry the timing
+// model columns (1, tau, tau^2) and then zeros; in the DM block slots with
+// h >= kdm are zero.
+// ---------------------------------------------------------------------------
+struct Slot {
+  int kind;   // 0 Fourier harmonic, 1 timing-model column, 2 padding
+  int harm;   // harmonic k (1-based) for kind 0
+  int sc;     // 0 sin, 1 cos (kind 0)
+  int tm;     // 0,1,2 -> 1, tau, tau^2 (kind 1)
+};
+
+__host__ __device__ inline Slot rn_slot(int row, int kb) {
+  const int s = row >> 2, q = row & 3, m = s >> 1, h = 4 * m + q, sc = s & 1;
+  Slot r{2, 0, 0, 0};
+  if (h < kb) {
+    r.kind = 0; r.harm = h + 1; r.sc = sc;
+  } else {
+    const int ti = 2 * (h - kb) + sc;
+    if (ti < 3) { r.kind = 1; r.tm = ti; }
+  }
+  return r;
+}
+
+__host__ __device__ inline Slot dm_slot(int row, int kdm) {
+  const int s = row >> 2, q = row & 3, m = s >> 1, h = 4 * m + q, sc = s & 1;
+  Slot r{2, 0, 0, 0};
+  if (h < kdm) { r.kind = 0; r.harm = h + 1; r.sc = sc; }
+  return r;
+}
+
+// Row of harmonic k (1-based) / sin-cos sc in either block.
+__host__ __device__ inline int harm_row(int k, int sc) {
+  const int h = k - 1, m = h >> 2, q = h & 3;
+  return 4 * (2 * m + sc) + q;
+}
+// Row of timing-model column ti in the red-noise block.
+__host__ __device__ inline int tm_row(int ti, int kb) {
+  const int h = kb + (ti >> 1), m = h >> 2, q = h & 3;
+  return 4 * (2 * m + (ti & 1)) + q;
+}
+
+// 16-row tiles of a block holding `nslots_pairs` harmonic/TM pair slots.
+__host__ __device__ inline int tiles_for_pairs(int pairs) {
+  const int steps = 2 * ((pairs + 3) / 4);
+  return (steps + 3) / 4;
+}
+
+// ---------------------------------------------------------------------------
+// Device view of a data set plus the workspace of one call.
+// ---------------------------------------------------------------------------
+struct Dev {
+  // sizes
+  int n_psr, n_toa, n_backend;
+  int nf_rn, nf_gw, nf_dm, has_cw;
+  int ka;        // coefficient frequencies max(nf_rn, nf_gw)
+  int kb;        // basis harmonics of the TOA pass max(ka, nf_dm)
+  int jt_rn, jt_dm, rows_rn, rows_dm;
+  int n_theta, d;
+  int off_gw, off_rn, off_dm, off_cw, off_u, off_z, off_zdm;
+  double tspan, dm_scale, sigma_b, tmax, prior_const;
+  // data-set arrays (device)
+  const double *t, *dt, *sigma, *nu;
+  const int32_t *backend;
+  const double *efac, *equad;
+  const int64_t *toa_off;
+  const double *tau_c, *tau_sinv;
+  const double *pos, *gamma;
+  const double *prior_lo, *prior_hi;
+  // chunk table of the batched TOA pass
+  int n_chunks, tiles_per_chunk;
+  const int32_t *chunk_psr, *chunk_begin, *chunk_end, *psr_chunk0;
+  // call
+  int n_chains, c_pad, n_cb;
+  // workspace
+  double *coef_rn, *coef_dm;   // [n_psr][rows][c_pad]
+  double *lstore;              // [c_pad][nf_gw][n_psr*(n_psr+1)/2]
+  double *cwc;                 // [c_pad][n_psr][kCwConst] per chain/pulsar CW constants
+  double *part_rn, *part_dm;   // [n_wg][rows][16]
+  double *part_chi, *part_lnn, *part_cw;  // [n_wg][16], [n_wg], [n_wg][8][16]
+  double *bar_rn, *bar_dm;     // [n_psr][rows][c_pad]
+  double *chi_p, *lnn_p, *cw_p; // [n_psr][c_pad], [n_psr], [n_psr][8][c_pad]
+  double *dth_k;               // [c_pad][K][2] gw parts per frequency
+  double *drn_k;               // [c_pad][ka][n_psr][2]
+  double *ddm_k;               // [c_pad][nf_dm][n_psr][2]
+  int32_t *flag_k;             // [c_pad][max(ka, nf_dm)] per-frequency status
+  int32_t *st_pre;             // [c_pad] status from the input checks
+};
+
+constexpr int kCwConst = 10;   // F+, Fx, dF+/dcos, dFx/dcos, dF+/dphi, dFx/dphi
+
+}  // namespace pt
+
+// Launch helpers implemented in the kernel translation units.
+namespace ptk {
+hipError_t launch_spec_fwd(const pt::Dev &D, const double *x, hipStream_t s);
+hipError_t launch_toa_mfma(const pt::Dev &D, int waves_per_block, int xcd_map, hipStream_t s);
+hipError_t launch_toa_plain_psr(const pt::Dev &D, int p, int n_chunks_p, hipStream_t s);
+hipError_t set_plain_lds_limit(size_t bytes);
+hipError_t set_spec_lds_limits(size_t fwd_bytes, size_t bwd_bytes);
+hipError_t launch_reduce_chunks(const pt::Dev &D, hipStream_t s);
+hipError_t launch_spec_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s);
+hipError_t launch_finalize(const pt::Dev &D, const double *x, double *logp, double *grad,
+                           int32_t *status, hipStream_t s);
+// HMC pieces
+hipError_t launch_hmc_begin(const pt::Dev &D, int d, double eps, const double *inv_mass,
+                            uint64_t seed, const uint64_t *traj, double *x, const double *logp,
+                            const double *grad, double *p, double *x0, double *lp0, double *g0,
+                            double *h0, hipStream_t s);
+hipError_t launch_hmc_kick_drift(int n_chains, int d, double eps, const double *inv_mass,
+                                 double *x, double *p, const double *grad, hipStream_t s);
+hipError_t launch_hmc_end(int n_chains, int d, double eps, const double *inv_mass, uint64_t seed,
+                          const uint64_t *traj, uint64_t traj0, double *x, double *logp,
+                          double *grad, double *p, const double *x0, const double *lp0,
+                          const double *g0, const double *h0, int64_t *n_accept, double *samples,
+                          hipStream_t s);
+hipError_t launch_traj_inc(uint64_t *traj, hipStream_t s);
+}  // namespace ptk

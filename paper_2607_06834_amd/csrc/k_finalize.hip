@@ -1,0 +1,129 @@
+// Assembly of log p and the hyper-parameter / timing-model gradient per chain
+// (Sec. IV: Eqs. likelihood and a_prior under the whitening a = L z, with the
+// uniform hyper-priors of Sec. IV.A):
+//
+//   log p = sum_I (-1/2 chi2_I) - 1/2 sum_i ln N_i - n/2 ln 2pi
+//           - 1/2 (|u|^2 + |z|^2 + |z_dm|^2) - d_z/2 ln 2pi - sum ln(hi - lo)
+//
+// Per-frequency contributions to the hyper-parameter gradient are summed in
+// frequency order; chains flagged by any stage get log p = -inf, gradient 0.
+#include "common.h"
+
+namespace {
+
+using pt::Dev;
+
+template <typename T>
+__device__ T block_sum256(T v, T *red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] = red[t] + red[t + o];
+    __syncthreads();
+  }
+  const T r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restrict__ x,
+                                                  double *__restrict__ logp,
+                                                  double *__restrict__ grad,
+                                                  int32_t *__restrict__ status) {
+  __shared__ double red[256];
+  __shared__ int ired[256];
+  const int c = blockIdx.x;
+  const int t = threadIdx.x;
+  const double *xc = x + (size_t)c * D.d;
+  double *gc = grad + (size_t)c * D.d;
+  const size_t cp = D.c_pad;
+  const int n = D.n_psr;
+  const int kmax = max(D.ka, D.nf_dm);
+
+  int st = D.st_pre[c];
+  int fl = 0;
+  for (int k = t; k < kmax; k += 256) fl |= D.flag_k[(size_t)c * kmax + k];
+  fl = block_sum256<int>(fl != 0 ? 1 : 0, ired);
+  if (st == 0 && fl) st = PTAFS_ST_NOTPD;
+
+  // ---- log p
+  double zz = 0.0;
+  for (int i = D.off_u + t; i < D.d; i += 256) zz += xc[i] * xc[i];
+  double ch = 0.0, ln = 0.0;
+  for (int p = t; p < n; p += 256) {
+    ch += D.chi_p[(size_t)p * cp + c];
+    ln += D.lnn_p[p];
+  }
+  zz = block_sum256(zz, red);
+  ch = block_sum256(ch, red);
+  ln = block_sum256(ln, red);
+  const double dz = (double)(D.d - D.off_u);
+  double lp = -0.5 * ch - 0.5 * ln - 0.5 * (double)D.n_toa * pt::kLn2Pi - 0.5 * zz -
+              0.5 * dz * pt::kLn2Pi + D.prior_const;
+
+  // ---- hyper-parameter gradient (sums over frequency in order)
+  if (st == 0) {
+    if (D.nf_gw > 0 && t < 2) {
+      double s = 0.0;
+      for (int k = 0; k < D.ka; ++k) s += D.dth_k[((size_t)c * D.ka + k) * 2 + t];
+      gc[D.off_gw + t] = s;
+    }
+    if (D.nf_rn > 0) {
+      for (int e = t; e < 2 * n; e += 256) {
+        double s = 0.0;
+        for (int k = 0; k < D.ka; ++k) s += D.drn_k[((size_t)c * D.ka + k) * n * 2 + e];
+        gc[D.off_rn + e] = s;
+      }
+    }
+    if (D.nf_dm > 0) {
+      for (int e = t; e < 2 * n; e += 256) {
+        double s = 0.0;
+        for (int k = 0; k < D.nf_dm; ++k) s += D.ddm_k[((size_t)c * D.nf_dm + k) * n * 2 + e];
+        gc[D.off_dm + e] = s;
+      }
+    }
+    if (D.has_cw && t < 8) {
+      double s = 0.0;
+      for (int p = 0; p < n; ++p) s += D.cw_p[((size_t)p * 8 + t) * cp + c];
+      gc[D.off_cw + t] = s;
+    }
+    // timing model: d/du = sigma_b M^T g - u
+    for (int e = t; e < 3 * n; e += 256) {
+      const int I = e / 3, ti = e % 3;
+      const int row = pt::tm_row(ti, D.kb);
+      gc[D.off_u + e] = D.sigma_b * D.bar_rn[((size_t)I * D.rows_rn + row) * cp + c] - xc[D.off_u + e];
+    }
+  }
+  __syncthreads();
+  __threadfence_block();
+
+  // ---- non-finite result check
+  int bad = 0;
+  if (st == 0) {
+    for (int i = t; i < D.d; i += 256) bad |= !isfinite(gc[i]);
+    bad = block_sum256<int>(bad, ired);
+    if (bad || !isfinite(lp)) st = PTAFS_ST_NONFINITE;
+  }
+  if (st != 0) {
+    for (int i = t; i < D.d; i += 256) gc[i] = 0.0;
+    lp = -INFINITY;
+  }
+  if (t == 0) {
+    logp[c] = lp;
+    status[c] = st;
+  }
+}
+
+}  // namespace
+
+namespace ptk {
+
+hipError_t launch_finalize(const pt::Dev &D, const double *x, double *logp, double *grad,
+                           int32_t *status, hipStream_t s) {
+  if (D.n_chains == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(D.n_chains), dim3(256), 0, s, D, x, logp, grad, status);
+  return hipGetLastError();
+}
+
+}  // namespace ptk

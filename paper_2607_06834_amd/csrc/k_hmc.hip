@@ -1,0 +1,189 @@
+// Fixed-step leapfrog HMC pieces (App. A: Eqs. Hamiltonian, Hamilton's_eq,
+// Gaussian_momentum, HMC_acceptance) with a diagonal inverse mass.
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten
+// rounds of two 32x32->64-bit multiplications by fixed constants with the
+// high halves xor-ed into the other counter words and the key, the key
+// advanced by two Weyl increments between rounds.  Normals by Box-Muller.
+#include "common.h"
+
+namespace {
+
+constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
+constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+
+__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += kW0;
+      k1 += kW1;
+    }
+    const uint32_t lo0 = kM0 * c[0], hi0 = __umulhi(kM0, c[0]);
+    const uint32_t lo1 = kM1 * c[2], hi1 = __umulhi(kM1, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__device__ inline double u53(uint32_t a, uint32_t b) {
+  return (double)(((uint64_t)a << 21) | (uint64_t)(b >> 11));
+}
+
+template <typename T>
+__device__ T block_sum256(T v, T *red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) red[t] = red[t] + red[t + o];
+    __syncthreads();
+  }
+  const T r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// grid = n_chains, block = 256
+__global__ __launch_bounds__(256) void k_hmc_begin(int d, double eps, const double *inv_mass,
+                                                   uint64_t seed, const uint64_t *traj, double *x,
+                                                   const double *logp, const double *grad,
+                                                   double *p, double *x0, double *lp0, double *g0,
+                                                   double *h0) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  const uint32_t j = (uint32_t)(*traj);
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const size_t off = (size_t)c * d;
+  double kin = 0.0;
+  const int npair = (d + 1) / 2;
+  for (int m = threadIdx.x; m < npair; m += 256) {
+    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)c, j, 0u};
+    philox10(ctr, k0, k1);
+    const double u1 = (u53(ctr[0], ctr[1]) + 1.0) * 0x1.0p-53;
+    const double u2 = u53(ctr[2], ctr[3]) * 0x1.0p-53;
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(pt::kTwoPi * u2, &sn, &cs);
+    const double nz[2] = {rad * cs, rad * sn};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = 2 * m + h;
+      if (i >= d) break;
+      const double im = inv_mass ? inv_mass[i] : 1.0;
+      double pi = im > 0.0 ? nz[h] / sqrt(im) : 0.0;
+      kin += 0.5 * im * pi * pi;
+      const double xi = x[off + i], gi = grad[off + i];
+      x0[off + i] = xi;
+      g0[off + i] = gi;
+      pi += 0.5 * eps * gi;                  // half kick
+      x[off + i] = xi + eps * im * pi;       // first drift
+      p[off + i] = pi;
+    }
+  }
+  kin = block_sum256(kin, red);
+  if (threadIdx.x == 0) {
+    lp0[c] = logp[c];
+    h0[c] = -logp[c] + kin;
+  }
+}
+
+// p += eps grad; x += eps M^-1 p  over n_chains * d elements
+__global__ __launch_bounds__(256) void k_hmc_kick_drift(size_t n, int d, double eps,
+                                                        const double *inv_mass, double *x,
+                                                        double *p, const double *grad) {
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const int i = (int)(e % d);
+  const double im = inv_mass ? inv_mass[i] : 1.0;
+  const double pi = p[e] + eps * grad[e];
+  p[e] = pi;
+  x[e] += eps * im * pi;
+}
+
+// final half kick, H1, accept / restore, optional sample
+__global__ __launch_bounds__(256) void k_hmc_end(int d, double eps, const double *inv_mass,
+                                                 uint64_t seed, const uint64_t *traj, uint64_t traj0,
+                                                 int n_chains, double *x, double *logp, double *grad,
+                                                 double *p, const double *x0, const double *lp0,
+                                                 const double *g0, const double *h0,
+                                                 int64_t *n_accept, double *samples) {
+  __shared__ double red[256];
+  __shared__ int acc_s;
+  const int c = blockIdx.x;
+  const uint64_t jj = *traj;
+  const uint32_t j = (uint32_t)jj;
+  const size_t off = (size_t)c * d;
+  double kin = 0.0;
+  for (int i = threadIdx.x; i < d; i += 256) {
+    const double im = inv_mass ? inv_mass[i] : 1.0;
+    const double pi = p[off + i] + 0.5 * eps * grad[off + i];
+    kin += 0.5 * im * pi * pi;
+  }
+  kin = block_sum256(kin, red);
+  if (threadIdx.x == 0) {
+    const double H1 = -logp[c] + kin;
+    uint32_t ctr[4] = {0u, (uint32_t)c, j, 1u};
+    philox10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u = (u53(ctr[0], ctr[1]) + 1.0) * 0x1.0p-53;
+    const int a = (isfinite(H1) && log(u) < h0[c] - H1) ? 1 : 0;
+    acc_s = a;
+    if (a) n_accept[c] += 1;
+    else logp[c] = lp0[c];
+  }
+  __syncthreads();
+  const int a = acc_s;
+  double *smp = samples ? samples + ((size_t)(jj - traj0) * n_chains + c) * d : nullptr;
+  for (int i = threadIdx.x; i < d; i += 256) {
+    double xi = x[off + i];
+    if (!a) {
+      xi = x0[off + i];
+      x[off + i] = xi;
+      grad[off + i] = g0[off + i];
+    }
+    if (smp) smp[i] = xi;
+  }
+}
+
+__global__ void k_traj_inc(uint64_t *traj) { *traj += 1; }
+
+}  // namespace
+
+namespace ptk {
+
+hipError_t launch_hmc_begin(const pt::Dev &D, int d, double eps, const double *inv_mass,
+                            uint64_t seed, const uint64_t *traj, double *x, const double *logp,
+                            const double *grad, double *p, double *x0, double *lp0, double *g0,
+                            double *h0, hipStream_t s) {
+  hipLaunchKernelGGL(k_hmc_begin, dim3(D.n_chains), dim3(256), 0, s, d, eps, inv_mass, seed, traj,
+                     x, logp, grad, p, x0, lp0, g0, h0);
+  return hipGetLastError();
+}
+
+hipError_t launch_hmc_kick_drift(int n_chains, int d, double eps, const double *inv_mass,
+                                 double *x, double *p, const double *grad, hipStream_t s) {
+  const size_t n = (size_t)n_chains * d;
+  hipLaunchKernelGGL(k_hmc_kick_drift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, d,
+                     eps, inv_mass, x, p, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_hmc_end(int n_chains, int d, double eps, const double *inv_mass, uint64_t seed,
+                          const uint64_t *traj, uint64_t traj0, double *x, double *logp,
+                          double *grad, double *p, const double *x0, const double *lp0,
+                          const double *g0, const double *h0, int64_t *n_accept, double *samples,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_hmc_end, dim3(n_chains), dim3(256), 0, s, d, eps, inv_mass, seed, traj,
+                     traj0, n_chains, x, logp, grad, p, x0, lp0, g0, h0, n_accept, samples);
+  return hipGetLastError();
+}
+
+hipError_t launch_traj_inc(uint64_t *traj, hipStream_t s) {
+  hipLaunchKernelGGL(k_traj_inc, dim3(1), dim3(1), 0, s, traj);
+  return hipGetLastError();
+}
+
+}  // namespace ptk

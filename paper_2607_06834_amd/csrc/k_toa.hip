@@ -1,0 +1,420 @@
+// TOA pass: per-TOA residual, white-noise chi^2 and log-determinant, and the
+// adjoint contractions, for every chain (Sec. IV, Eq. likelihood with the
+// bases of Eqs. Fourier_series / RN=Fa, F_DM = w F of Sec. III.C and the
+// timing model M = [1, tau, tau^2] of Eq. TM=Me; N of Eq. WN_cov):
+//
+//   r  = dt - F_tile . A - w (F_tile . A_dm)          (A includes M b)
+//   g  = r / N,  chi2 += r g,  logdet += ln N
+//   Abar += F_tile^T g,  Abar_dm += F_tile^T (w g)
+//
+// The batched form runs F.A and F^T.G as FP64 MFMA 16x16x4 contractions
+// over 16-TOA x 16-chain tiles; the basis is generated in registers from one
+// sincos per TOA and an angle-addition step, and transposed through LDS for
+// the adjoint.  The plain form is a vector-ALU kernel launched per pulsar.
+#include "common.h"
+
+namespace {
+
+using pt::Dev;
+using v4d = double __attribute__((ext_vector_type(4)));
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline double tm_value(int i, double tau) {
+  return i == 0 ? 1.0 : (i == 1 ? tau : (i == 2 ? tau * tau : 0.0));
+}
+
+// Map a hardware workgroup id to a work item so that consecutive items (the
+// chain blocks of one chunk, then the next chunk of the same pulsar) land on
+// the same XCD: workgroups are dispatched to the 8 XCDs round-robin.
+__device__ inline int xcd_remap(int b, int G) {
+  const int x = b & 7, idx = b >> 3;
+  const int base = G >> 3, rem = G & 7;
+  const int start = x * base + min(x, rem);
+  return start + idx;
+}
+
+// ---------------------------------------------------------------------------
+// Batched MFMA TOA pass.  grid = n_chunks * n_cb, block = 64 * WPB.
+// ---------------------------------------------------------------------------
+template <int JTR, int JTD, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
+  constexpr int NSR = 4 * JTR;
+  constexpr int NSD = 4 * JTD;
+  constexpr int ROWS = 16 * JTR;
+  constexpr int FS = ROWS + 1;                 // padded LDS row stride (doubles)
+  __shared__ double ftab[WPB][16 * FS];
+  __shared__ double ttab[WPB][16 * 4];
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int col = lane & 15, q = lane >> 4;
+  int wg = blockIdx.x;
+  if (xcd_map) wg = xcd_remap(wg, gridDim.x);
+  const int chunk = wg / D.n_cb, cb = wg - chunk * D.n_cb;
+  const int p = D.chunk_psr[chunk];
+  const int tb = D.chunk_begin[chunk], te = D.chunk_end[chunk];
+  const int chain = cb * 16 + col;
+  const size_t cp = D.c_pad;
+  const int kb = D.kb;
+
+  // B operands: coefficient rows 4s + q for this lane's chain
+  double cr[NSR], cd[NSD > 0 ? NSD : 1];
+  {
+    const double *pr = D.coef_rn + (size_t)p * D.rows_rn * cp + chain;
+#pragma unroll
+    for (int s = 0; s < NSR; ++s) cr[s] = pr[(size_t)(4 * s + q) * cp];
+    if constexpr (NSD > 0) {
+      const double *pd = D.coef_dm + (size_t)p * D.rows_dm * cp + chain;
+#pragma unroll
+      for (int s = 0; s < NSD; ++s) cd[s] = pd[(size_t)(4 * s + q) * cp];
+    }
+  }
+  v4d ar[JTR];
+  v4d ad[JTD > 0 ? JTD : 1];
+#pragma unroll
+  for (int t = 0; t < JTR; ++t) ar[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < (JTD > 0 ? JTD : 1); ++t) ad[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  double chi = 0.0, lnn = 0.0;
+  const double tc = D.tau_c[p], tsi = D.tau_sinv[p];
+  const double wfac = pt::kTwoPi / D.tspan;
+  double *ft = ftab[wv];
+  double *tt = ttab[wv];
+
+  for (int base = tb + 16 * wv; base < te; base += 16 * WPB) {
+    // ---- forward layout: lane (col, q) -> TOA base + col, slots 4s + q
+    const int i = base + col;
+    const bool ok = i < te;
+    const double ti = ok ? D.t[i] : 0.0;
+    if (q == 0) {
+      double dtv = 0.0, invn = 0.0, w = 0.0;
+      if (ok) {
+        const int be = D.backend[i];
+        const double es = D.efac[be] * D.sigma[i], eq = D.equad[be];
+        const double N = es * es + eq * eq;
+        const double nu = D.nu[i];
+        dtv = D.dt[i];
+        invn = 1.0 / N;
+        w = D.dm_scale / (nu * nu);
+        if (cb == 0) lnn += log(N);
+      }
+      tt[col * 4 + 0] = dtv;
+      tt[col * 4 + 1] = invn;
+      tt[col * 4 + 2] = w;
+    }
+    double s1, c1;
+    sincos(wfac * ti, &s1, &c1);
+    const double s2 = 2.0 * s1 * c1, c2 = (c1 - s1) * (c1 + s1);
+    const double s3 = s2 * c1 + c2 * s1, c3 = c2 * c1 - s2 * s1;
+    const double s4 = 2.0 * s2 * c2, c4 = (c2 - s2) * (c2 + s2);
+    double sh = q == 0 ? s1 : (q == 1 ? s2 : (q == 2 ? s3 : s4));
+    double ch = q == 0 ? c1 : (q == 1 ? c2 : (q == 2 ? c3 : c4));
+    const double tau = (ti - tc) * tsi;
+    double fv[NSR];
+#pragma unroll
+    for (int m = 0; m < NSR / 2; ++m) {
+      const int h = 4 * m + q;
+      double fa, fb;
+      if (h < kb) {
+        fa = sh;
+        fb = ch;
+      } else {
+        const int t2 = 2 * (h - kb);
+        fa = tm_value(t2, tau);
+        fb = tm_value(t2 + 1, tau);
+      }
+      if (!ok) { fa = 0.0; fb = 0.0; }
+      fv[2 * m] = fa;
+      fv[2 * m + 1] = fb;
+      ft[col * FS + 8 * m + q] = fa;
+      ft[col * FS + 8 * m + 4 + q] = fb;
+      const double sn = sh * c4 + ch * s4;
+      ch = ch * c4 - sh * s4;
+      sh = sn;
+    }
+    // ---- forward contraction: R = F A, R_dm = F A_dm (16 TOA x 16 chains)
+    v4d rr = v4d{0.0, 0.0, 0.0, 0.0};
+    v4d rd = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < NSR; ++s) {
+      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fv[s], cr[s], rr, 0, 0, 0);
+      if (s < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fv[s], cd[s], rd, 0, 0, 0);
+    }
+    wave_sync();
+    // ---- residuals: lane (col, q) holds TOAs base + q + 4v, chain col
+    // (v_mfma_f64_16x16x4f64 returns D[q + 4v][col] in item v of lane col + 16q)
+    double gr[4], gd[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = q + 4 * v;
+      const double dtv = tt[j * 4 + 0], invn = tt[j * 4 + 1], w = tt[j * 4 + 2];
+      const double r = dtv - rr[v] - w * rd[v];
+      const double g = r * invn;
+      chi += r * g;
+      gr[v] = g;
+      gd[v] = w * g;
+    }
+    // ---- adjoint contraction: Abar += F^T G, Abar_dm += F^T (w G)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+#pragma unroll
+      for (int t = 0; t < JTR; ++t) {
+        const double fb = ft[(q + 4 * v) * FS + 16 * t + col];
+        ar[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, gr[v], ar[t], 0, 0, 0);
+        if (t < JTD) ad[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, gd[v], ad[t], 0, 0, 0);
+      }
+    }
+    wave_sync();
+  }
+
+  // ---- per-wave partial sums over q and lanes (fixed order)
+  chi += __shfl_xor(chi, 16, 64);
+  chi += __shfl_xor(chi, 32, 64);
+  for (int o = 1; o < 64; o <<= 1) lnn += __shfl_xor(lnn, o, 64);
+
+  // ---- combine the waves of the block in LDS, then one partial per block
+  double *pr = D.part_rn + (size_t)wg * D.rows_rn * 16;
+  double *pd = D.part_dm + (size_t)wg * D.rows_dm * 16;
+  if constexpr (WPB == 1) {
+#pragma unroll
+    for (int t = 0; t < JTR; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pr[(16 * t + q + 4 * v) * 16 + col] = ar[t][v];
+#pragma unroll
+    for (int t = 0; t < JTD; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pd[(16 * t + q + 4 * v) * 16 + col] = ad[t][v];
+    if (q == 0) D.part_chi[(size_t)wg * 16 + col] = chi;
+    if (lane == 0) D.part_lnn[wg] = lnn;
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < JTR; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ftab[wv][(16 * t + q + 4 * v) * 16 + col] = ar[t][v];
+    if (q == 0) ttab[wv][col] = chi;
+    if (lane == 0) ttab[wv][16] = lnn;
+    __syncthreads();
+    if (wv == 0) {
+      for (int e = lane; e < ROWS * 16; e += 64) {
+        double s = ftab[0][e];
+#pragma unroll
+        for (int w = 1; w < WPB; ++w) s += ftab[w][e];
+        pr[e] = s;
+      }
+      if (lane < 16) {
+        double s = ttab[0][lane];
+#pragma unroll
+        for (int w = 1; w < WPB; ++w) s += ttab[w][lane];
+        D.part_chi[(size_t)wg * 16 + lane] = s;
+      }
+      if (lane == 0) {
+        double s = ttab[0][16];
+#pragma unroll
+        for (int w = 1; w < WPB; ++w) s += ttab[w][16];
+        D.part_lnn[wg] = s;
+      }
+    }
+    if constexpr (JTD > 0) {
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < JTD; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ftab[wv][(16 * t + q + 4 * v) * 16 + col] = ad[t][v];
+      __syncthreads();
+      if (wv == 0) {
+        for (int e = lane; e < 16 * JTD * 16; e += 64) {
+          double s = ftab[0][e];
+#pragma unroll
+          for (int w = 1; w < WPB; ++w) s += ftab[w][e];
+          pd[e] = s;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Plain TOA pass: one launch per pulsar, lane = chain, vector ALU only.
+// grid = (chunks of pulsar p, ceil(c_pad / 64)), block = 64.
+// LDS: coef [rows][64] for both blocks, then the adjoint accumulators.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_toa_plain(Dev D, int p) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x;
+  const int chunk = D.psr_chunk0[p] + blockIdx.x;
+  const int chain = blockIdx.y * 64 + lane;
+  const bool real = chain < D.c_pad;
+  const int nr = D.rows_rn, nd = D.rows_dm;
+  double *cf = lds;                       // [nr][64]
+  double *cfd = cf + nr * 64;             // [nd][64]
+  double *ab = cfd + nd * 64;             // [nr][64]
+  double *abd = ab + nr * 64;             // [nd][64]
+  const size_t cp = D.c_pad;
+  for (int r = 0; r < nr; ++r) {
+    cf[r * 64 + lane] = real ? D.coef_rn[((size_t)p * nr + r) * cp + chain] : 0.0;
+    ab[r * 64 + lane] = 0.0;
+  }
+  for (int r = 0; r < nd; ++r) {
+    cfd[r * 64 + lane] = real ? D.coef_dm[((size_t)p * nd + r) * cp + chain] : 0.0;
+    abd[r * 64 + lane] = 0.0;
+  }
+  const int tb = D.chunk_begin[chunk], te = D.chunk_end[chunk];
+  const double tc = D.tau_c[p], tsi = D.tau_sinv[p];
+  const double wfac = pt::kTwoPi / D.tspan;
+  const int kb = D.kb, kdm = D.nf_dm;
+  const int t0 = pt::tm_row(0, kb), t1 = pt::tm_row(1, kb), t2 = pt::tm_row(2, kb);
+  double chi = 0.0, lnn = 0.0;
+  for (int i = tb; i < te; ++i) {
+    const double t = D.t[i];
+    const int be = D.backend[i];
+    const double es = D.efac[be] * D.sigma[i], eq = D.equad[be];
+    const double N = es * es + eq * eq;
+    const double w = D.dm_scale / (D.nu[i] * D.nu[i]);
+    lnn += log(N);
+    double s1, c1;
+    sincos(wfac * t, &s1, &c1);
+    const double tau = (t - tc) * tsi;
+    double R = cf[t0 * 64 + lane] + tau * cf[t1 * 64 + lane] + tau * tau * cf[t2 * 64 + lane];
+    double Rd = 0.0;
+    double sk = s1, ck = c1;
+    for (int k = 1; k <= kb; ++k) {
+      const int rs = pt::harm_row(k, 0), rc = pt::harm_row(k, 1);
+      R += sk * cf[rs * 64 + lane] + ck * cf[rc * 64 + lane];
+      if (k <= kdm) Rd += sk * cfd[rs * 64 + lane] + ck * cfd[rc * 64 + lane];
+      const double sn = sk * c1 + ck * s1;
+      ck = ck * c1 - sk * s1;
+      sk = sn;
+    }
+    const double r = D.dt[i] - R - w * Rd;
+    const double g = r / N;
+    const double wg = w * g;
+    chi += r * g;
+    sk = s1;
+    ck = c1;
+    for (int k = 1; k <= kb; ++k) {
+      const int rs = pt::harm_row(k, 0), rc = pt::harm_row(k, 1);
+      ab[rs * 64 + lane] += sk * g;
+      ab[rc * 64 + lane] += ck * g;
+      if (k <= kdm) {
+        abd[rs * 64 + lane] += sk * wg;
+        abd[rc * 64 + lane] += ck * wg;
+      }
+      const double sn = sk * c1 + ck * s1;
+      ck = ck * c1 - sk * s1;
+      sk = sn;
+    }
+    ab[t0 * 64 + lane] += g;
+    ab[t1 * 64 + lane] += tau * g;
+    ab[t2 * 64 + lane] += tau * tau * g;
+  }
+  if (!real) return;
+  const int cb = chain >> 4, col = chain & 15;
+  const size_t wg = (size_t)chunk * D.n_cb + cb;
+  for (int r = 0; r < nr; ++r) D.part_rn[(wg * nr + r) * 16 + col] = ab[r * 64 + lane];
+  for (int r = 0; r < nd; ++r) D.part_dm[(wg * nd + r) * 16 + col] = abd[r * 64 + lane];
+  D.part_chi[wg * 16 + col] = chi;
+  if (chain == 0) D.part_lnn[(size_t)chunk * D.n_cb] = lnn;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order reduction of chunk partials into per-pulsar panels.
+// grid = (n_psr, n_cb), block = 256.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce(Dev D) {
+  const int p = blockIdx.x, cb = blockIdx.y;
+  const int c0 = D.psr_chunk0[p], c1 = D.psr_chunk0[p + 1];
+  const int nr = D.rows_rn, nd = D.rows_dm;
+  const size_t cp = D.c_pad;
+  const size_t ncb = D.n_cb;
+  for (int e = threadIdx.x; e < (nr + nd) * 16; e += 256) {
+    const int row = e >> 4, col = e & 15;
+    double s = 0.0;
+    if (row < nr) {
+      for (int ch = c0; ch < c1; ++ch) s += D.part_rn[(((size_t)ch * ncb + cb) * nr + row) * 16 + col];
+      D.bar_rn[((size_t)p * nr + row) * cp + cb * 16 + col] = s;
+    } else {
+      const int r2 = row - nr;
+      for (int ch = c0; ch < c1; ++ch) s += D.part_dm[(((size_t)ch * ncb + cb) * nd + r2) * 16 + col];
+      D.bar_dm[((size_t)p * nd + r2) * cp + cb * 16 + col] = s;
+    }
+  }
+  if (threadIdx.x < 16) {
+    double s = 0.0;
+    for (int ch = c0; ch < c1; ++ch) s += D.part_chi[((size_t)ch * ncb + cb) * 16 + threadIdx.x];
+    D.chi_p[(size_t)p * cp + cb * 16 + threadIdx.x] = s;
+  }
+  if (cb == 0 && threadIdx.x == 32) {
+    double s = 0.0;
+    for (int ch = c0; ch < c1; ++ch) s += D.part_lnn[(size_t)ch * ncb];
+    D.lnn_p[p] = s;
+  }
+}
+
+template <int JTR, int JTD, int WPB>
+hipError_t launch_mfma_t(const Dev &D, int xcd, hipStream_t s) {
+  const int grid = D.n_chunks * D.n_cb;
+  hipLaunchKernelGGL((k_toa_mfma<JTR, JTD, WPB>), dim3(grid), dim3(64 * WPB), 0, s, D, xcd);
+  return hipGetLastError();
+}
+
+template <int JTR, int WPB>
+hipError_t launch_mfma_d(const Dev &D, int xcd, hipStream_t s) {
+  switch (D.jt_dm) {
+    case 0: return launch_mfma_t<JTR, 0, WPB>(D, xcd, s);
+    case 1: if constexpr (JTR >= 1) return launch_mfma_t<JTR, 1, WPB>(D, xcd, s); break;
+    case 2: if constexpr (JTR >= 2) return launch_mfma_t<JTR, 2, WPB>(D, xcd, s); break;
+    case 3: if constexpr (JTR >= 3) return launch_mfma_t<JTR, 3, WPB>(D, xcd, s); break;
+    case 4: if constexpr (JTR >= 4) return launch_mfma_t<JTR, 4, WPB>(D, xcd, s); break;
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int WPB>
+hipError_t launch_mfma_r(const Dev &D, int xcd, hipStream_t s) {
+  switch (D.jt_rn) {
+    case 1: return launch_mfma_d<1, WPB>(D, xcd, s);
+    case 2: return launch_mfma_d<2, WPB>(D, xcd, s);
+    case 3: return launch_mfma_d<3, WPB>(D, xcd, s);
+    case 4: return launch_mfma_d<4, WPB>(D, xcd, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+namespace ptk {
+
+hipError_t launch_toa_mfma(const pt::Dev &D, int wpb, int xcd, hipStream_t s) {
+  if (D.n_chunks == 0 || D.n_cb == 0) return hipSuccess;
+  switch (wpb) {
+    case 1: return launch_mfma_r<1>(D, xcd, s);
+    case 2: return launch_mfma_r<2>(D, xcd, s);
+    case 4: return launch_mfma_r<4>(D, xcd, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_toa_plain_psr(const pt::Dev &D, int p, int n_chunks_p, hipStream_t s) {
+  const size_t lds = (size_t)2 * (D.rows_rn + D.rows_dm) * 64 * sizeof(double);
+  const int cg = (D.c_pad + 63) / 64;
+  hipLaunchKernelGGL(k_toa_plain, dim3(n_chunks_p, cg), dim3(64), lds, s, D, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_chunks(const pt::Dev &D, hipStream_t s) {
+  if (D.n_psr == 0 || D.n_cb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3(D.n_psr, D.n_cb), dim3(256), 0, s, D);
+  return hipGetLastError();
+}
+
+hipError_t set_plain_lds_limit(size_t bytes) {
+  return hipFuncSetAttribute((const void *)k_toa_plain, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+}  // namespace ptk

@@ -1,0 +1,569 @@
+// Host side of libptafs: data-set preparation, workspace management, the
+// evaluation pipeline and the HMC driver (with HIP-graph trajectories).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+struct ptafs_dataset {
+  int device = 0;
+  pt::Dev base{};
+  std::vector<int64_t> off;
+  std::vector<void *> allocs;
+  size_t ds_bytes = 0;
+  // tuning and chunk table of the TOA pass
+  int tiles_per_chunk = 16, wpb = 1, xcd_map = 1;
+  bool chunks_dirty = true;
+  int32_t *d_chunk = nullptr;
+  std::vector<int> psr_nchunks;
+  int n_chunks = 0;
+  // workspace
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  // HMC scratch
+  void *hmc = nullptr;
+  size_t hmc_bytes = 0;
+  // cached trajectory graph
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  struct GraphKey {
+    int n_chains, n_leapfrog;
+    double eps;
+    const void *inv_mass, *x, *logp, *grad, *acc, *samples;
+    uint64_t seed, traj0;
+    hipStream_t stream;
+    int tiles, wpb, xcd;
+    void *ws, *hmc;
+    bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
+  } gkey{};
+};
+
+namespace {
+
+#define PT_TRY(expr)                                  \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return PTAFS_E_HIP;         \
+  } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct WsLayout {
+  size_t coef_rn, coef_dm, lstore, part_rn, part_dm, part_chi, part_lnn, part_cw, bar_rn, bar_dm,
+      chi_p, lnn_p, cw_p, dth_k, drn_k, ddm_k, flag_k, st_pre, total;
+};
+
+WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
+  WsLayout L{};
+  const size_t n = B.n_psr, cp = c_pad, ncb = c_pad / 16, nwg = (size_t)n_chunks * ncb;
+  const size_t kmax = std::max(B.ka, B.nf_dm);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o += align256(std::max<size_t>(bytes, 8));
+    return r;
+  };
+  const size_t D8 = sizeof(double);
+  L.coef_rn = take(n * B.rows_rn * cp * D8);
+  L.coef_dm = take(n * B.rows_dm * cp * D8);
+  L.lstore = take(cp * B.nf_gw * (n * (n + 1) / 2) * D8);
+  L.part_rn = take(nwg * B.rows_rn * 16 * D8);
+  L.part_dm = take(nwg * B.rows_dm * 16 * D8);
+  L.part_chi = take(nwg * 16 * D8);
+  L.part_lnn = take(nwg * D8);
+  L.part_cw = take(nwg * 8 * 16 * D8);
+  L.bar_rn = take(n * B.rows_rn * cp * D8);
+  L.bar_dm = take(n * B.rows_dm * cp * D8);
+  L.chi_p = take(n * cp * D8);
+  L.lnn_p = take(n * D8);
+  L.cw_p = take(n * 8 * cp * D8);
+  L.dth_k = take(cp * B.ka * 2 * D8);
+  L.drn_k = take(cp * B.ka * n * 2 * D8);
+  L.ddm_k = take(cp * B.nf_dm * n * 2 * D8);
+  L.flag_k = take(cp * kmax * sizeof(int32_t));
+  L.st_pre = take(cp * sizeof(int32_t));
+  L.total = o;
+  return L;
+}
+
+int cpad_of(int n_chains) { return ((n_chains + 15) / 16) * 16; }
+
+// Split every pulsar into chunks of about `tpc` 16-TOA tiles (tile-aligned).
+void build_chunks(ptafs_dataset *ds, std::vector<int32_t> &tab) {
+  const int n = ds->base.n_psr;
+  const int tpc = std::max(1, ds->tiles_per_chunk);
+  std::vector<int32_t> cps, cbg, cen;
+  std::vector<int32_t> first(n + 1, 0);
+  ds->psr_nchunks.assign(n, 0);
+  for (int p = 0; p < n; ++p) {
+    const int64_t b = ds->off[p], e = ds->off[p + 1];
+    const int64_t tiles = (e - b + 15) / 16;
+    const int64_t nch = std::max<int64_t>(1, (tiles + tpc - 1) / tpc);
+    first[p] = (int32_t)cps.size();
+    for (int64_t i = 0; i < nch; ++i) {
+      const int64_t t0 = (i * tiles) / nch, t1 = ((i + 1) * tiles) / nch;
+      cps.push_back(p);
+      cbg.push_back((int32_t)(b + 16 * t0));
+      cen.push_back((int32_t)std::min<int64_t>(e, b + 16 * t1));
+    }
+    ds->psr_nchunks[p] = (int)nch;
+  }
+  first[n] = (int32_t)cps.size();
+  ds->n_chunks = (int)cps.size();
+  tab.clear();
+  tab.insert(tab.end(), cps.begin(), cps.end());
+  tab.insert(tab.end(), cbg.begin(), cbg.end());
+  tab.insert(tab.end(), cen.begin(), cen.end());
+  tab.insert(tab.end(), first.begin(), first.end());
+}
+
+int ensure_chunks(ptafs_dataset *ds) {
+  if (!ds->chunks_dirty) return PTAFS_OK;
+  std::vector<int32_t> tab;
+  build_chunks(ds, tab);
+  PT_TRY(hipDeviceSynchronize());
+  if (ds->d_chunk) PT_TRY(hipFree(ds->d_chunk));
+  ds->d_chunk = nullptr;
+  if (hipMalloc(&ds->d_chunk, tab.size() * sizeof(int32_t)) != hipSuccess) return PTAFS_E_NOMEM;
+  PT_TRY(hipMemcpy(ds->d_chunk, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  const int nc = ds->n_chunks;
+  ds->base.n_chunks = nc;
+  ds->base.tiles_per_chunk = ds->tiles_per_chunk;
+  ds->base.chunk_psr = ds->d_chunk;
+  ds->base.chunk_begin = ds->d_chunk + nc;
+  ds->base.chunk_end = ds->d_chunk + 2 * nc;
+  ds->base.psr_chunk0 = ds->d_chunk + 3 * nc;
+  ds->chunks_dirty = false;
+  return PTAFS_OK;
+}
+
+int ensure_ws(ptafs_dataset *ds, int n_chains) {
+  const WsLayout L = ws_layout(ds->base, cpad_of(n_chains), ds->n_chunks);
+  if (L.total <= ds->ws_bytes) return PTAFS_OK;
+  PT_TRY(hipDeviceSynchronize());
+  if (ds->ws) PT_TRY(hipFree(ds->ws));
+  ds->ws = nullptr;
+  ds->ws_bytes = 0;
+  if (hipMalloc(&ds->ws, L.total) != hipSuccess) return PTAFS_E_NOMEM;
+  ds->ws_bytes = L.total;
+  return PTAFS_OK;
+}
+
+pt::Dev make_dev(const ptafs_dataset *ds, int n_chains) {
+  pt::Dev D = ds->base;
+  D.n_chains = n_chains;
+  D.c_pad = cpad_of(n_chains);
+  D.n_cb = D.c_pad / 16;
+  const WsLayout L = ws_layout(ds->base, D.c_pad, ds->n_chunks);
+  char *w = static_cast<char *>(ds->ws);
+  D.coef_rn = reinterpret_cast<double *>(w + L.coef_rn);
+  D.coef_dm = reinterpret_cast<double *>(w + L.coef_dm);
+  D.lstore = reinterpret_cast<double *>(w + L.lstore);
+  D.part_rn = reinterpret_cast<double *>(w + L.part_rn);
+  D.part_dm = reinterpret_cast<double *>(w + L.part_dm);
+  D.part_chi = reinterpret_cast<double *>(w + L.part_chi);
+  D.part_lnn = reinterpret_cast<double *>(w + L.part_lnn);
+  D.part_cw = reinterpret_cast<double *>(w + L.part_cw);
+  D.bar_rn = reinterpret_cast<double *>(w + L.bar_rn);
+  D.bar_dm = reinterpret_cast<double *>(w + L.bar_dm);
+  D.chi_p = reinterpret_cast<double *>(w + L.chi_p);
+  D.lnn_p = reinterpret_cast<double *>(w + L.lnn_p);
+  D.cw_p = reinterpret_cast<double *>(w + L.cw_p);
+  D.dth_k = reinterpret_cast<double *>(w + L.dth_k);
+  D.drn_k = reinterpret_cast<double *>(w + L.drn_k);
+  D.ddm_k = reinterpret_cast<double *>(w + L.ddm_k);
+  D.flag_k = reinterpret_cast<int32_t *>(w + L.flag_k);
+  D.st_pre = reinterpret_cast<int32_t *>(w + L.st_pre);
+  return D;
+}
+
+std::once_flag g_lds_once;
+hipError_t g_lds_err = hipSuccess;
+
+void set_lds_limits() {
+  const size_t n = PTAFS_MAX_PSR;
+  const size_t fwd = (n * (n + 1) / 2 + 2 * n) * sizeof(double);
+  const size_t bwd = (n * (n | 1) + 4 * n) * sizeof(double);
+  const size_t plain = (size_t)2 * (64 + 64) * 64 * sizeof(double);
+  g_lds_err = ptk::set_spec_lds_limits(fwd, bwd);
+  if (g_lds_err == hipSuccess) g_lds_err = ptk::set_plain_lds_limit(plain);
+}
+
+int enqueue_eval(ptafs_dataset *ds, int C, const double *x, double *logp, double *grad,
+                 int32_t *status, hipStream_t s, bool plain) {
+  const pt::Dev D = make_dev(ds, C);
+  PT_TRY(ptk::launch_spec_fwd(D, x, s));
+  if (plain) {
+    for (int p = 0; p < D.n_psr; ++p) PT_TRY(ptk::launch_toa_plain_psr(D, p, ds->psr_nchunks[p], s));
+  } else {
+    PT_TRY(ptk::launch_toa_mfma(D, ds->wpb, ds->xcd_map, s));
+  }
+  PT_TRY(ptk::launch_reduce_chunks(D, s));
+  PT_TRY(ptk::launch_spec_bwd(D, x, grad, s));
+  PT_TRY(ptk::launch_finalize(D, x, logp, grad, status, s));
+  return PTAFS_OK;
+}
+
+int eval(ptafs_dataset *ds, int C, const double *x, double *logp, double *grad, int32_t *status,
+         void *stream, bool plain) {
+  if (!ds || C < 0) return PTAFS_E_ARG;
+  if (C == 0) return PTAFS_OK;
+  if (!x || !logp || !grad || !status) return PTAFS_E_ARG;
+  PT_TRY(hipSetDevice(ds->device));
+  int rc = ensure_chunks(ds);
+  if (rc) return rc;
+  rc = ensure_ws(ds, C);
+  if (rc) return rc;
+  return enqueue_eval(ds, C, x, logp, grad, status, (hipStream_t)stream, plain);
+}
+
+template <typename T>
+int upload(ptafs_dataset *ds, const T *src, size_t count, const T **dst) {
+  void *p = nullptr;
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  if (hipMalloc(&p, bytes) != hipSuccess) return PTAFS_E_NOMEM;
+  ds->allocs.push_back(p);
+  ds->ds_bytes += bytes;
+  if (count) PT_TRY(hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice));
+  *dst = static_cast<const T *>(p);
+  return PTAFS_OK;
+}
+
+void free_all(ptafs_dataset *ds) {
+  if (!ds) return;
+  (void)hipSetDevice(ds->device);
+  (void)hipDeviceSynchronize();
+  if (ds->gexec) (void)hipGraphExecDestroy(ds->gexec);
+  if (ds->graph) (void)hipGraphDestroy(ds->graph);
+  for (void *p : ds->allocs) (void)hipFree(p);
+  if (ds->d_chunk) (void)hipFree(ds->d_chunk);
+  if (ds->ws) (void)hipFree(ds->ws);
+  if (ds->hmc) (void)hipFree(ds->hmc);
+  delete ds;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ptafs_strerror(int code) {
+  switch (code) {
+    case PTAFS_OK: return "success";
+    case PTAFS_E_ARG: return "invalid argument or unsupported shape";
+    case PTAFS_E_HIP: return "HIP runtime call failed";
+    case PTAFS_E_NOMEM: return "device allocation failed";
+    case PTAFS_E_LIMIT: return "size exceeds an implementation limit";
+  }
+  return "unknown error";
+}
+
+int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_dataset **out) {
+  if (!d || !out) return PTAFS_E_ARG;
+  *out = nullptr;
+  const int n = d->n_psr;
+  if (n < 1 || !d->toa_offsets) return PTAFS_E_ARG;
+  if (n > PTAFS_MAX_PSR) return PTAFS_E_LIMIT;
+  if (d->nf_rn < 0 || d->nf_gw < 0 || d->nf_dm < 0) return PTAFS_E_ARG;
+  const int ka = std::max(d->nf_rn, d->nf_gw);
+  const int kb = std::max(ka, d->nf_dm);
+  if (kb > PTAFS_MAX_HARM) return PTAFS_E_LIMIT;
+  if (!(d->tspan > 0.0) || d->n_backend < 1 || !d->efac || !d->equad || !d->psr_pos) return PTAFS_E_ARG;
+  if (d->toa_offsets[0] != 0) return PTAFS_E_ARG;
+  for (int p = 0; p < n; ++p)
+    if (d->toa_offsets[p + 1] <= d->toa_offsets[p]) return PTAFS_E_ARG;
+  const int64_t ntoa = d->toa_offsets[n];
+  if (ntoa > (int64_t)INT32_MAX - 1024) return PTAFS_E_LIMIT;
+  if (!d->t || !d->dt || !d->sigma || !d->nu || !d->backend) return PTAFS_E_ARG;
+  for (int64_t i = 0; i < ntoa; ++i) {
+    if (d->backend[i] < 0 || d->backend[i] >= d->n_backend) return PTAFS_E_ARG;
+    if (!(d->sigma[i] > 0.0) || !(d->nu[i] > 0.0) || !std::isfinite(d->t[i]) || !std::isfinite(d->dt[i]))
+      return PTAFS_E_ARG;
+  }
+
+  ptafs_dataset *ds = new (std::nothrow) ptafs_dataset();
+  if (!ds) return PTAFS_E_NOMEM;
+  if (hipGetDevice(&ds->device) != hipSuccess) {
+    delete ds;
+    return PTAFS_E_HIP;
+  }
+  std::call_once(g_lds_once, set_lds_limits);
+  if (g_lds_err != hipSuccess) {
+    delete ds;
+    return PTAFS_E_HIP;
+  }
+  pt::Dev &B = ds->base;
+  B.n_psr = n;
+  B.n_toa = (int)ntoa;
+  B.n_backend = d->n_backend;
+  B.nf_rn = d->nf_rn;
+  B.nf_gw = d->nf_gw;
+  B.nf_dm = d->nf_dm;
+  B.has_cw = d->has_cw ? 1 : 0;
+  B.ka = ka;
+  B.kb = kb;
+  B.jt_rn = pt::tiles_for_pairs(kb + 2);
+  B.jt_dm = d->nf_dm > 0 ? pt::tiles_for_pairs(d->nf_dm) : 0;
+  B.rows_rn = 16 * B.jt_rn;
+  B.rows_dm = 16 * B.jt_dm;
+  int o = 0;
+  B.off_gw = o; o += d->nf_gw > 0 ? 2 : 0;
+  B.off_rn = o; o += d->nf_rn > 0 ? 2 * n : 0;
+  B.off_dm = o; o += d->nf_dm > 0 ? 2 * n : 0;
+  B.off_cw = o; o += B.has_cw ? 8 : 0;
+  B.n_theta = o;
+  B.off_u = o; o += 3 * n;
+  B.off_z = o; o += n * 2 * ka;
+  B.off_zdm = o; o += n * 2 * d->nf_dm;
+  B.d = o;
+  B.tspan = d->tspan;
+  B.dm_scale = d->dm_scale;
+  B.sigma_b = d->sigma_b;
+  if (B.n_theta > 0 && (!d->prior_lo || !d->prior_hi)) {
+    delete ds;
+    return PTAFS_E_ARG;
+  }
+  double pc = 0.0;
+  for (int i = 0; i < B.n_theta; ++i) {
+    if (!(d->prior_hi[i] > d->prior_lo[i])) {
+      delete ds;
+      return PTAFS_E_ARG;
+    }
+    pc -= std::log(d->prior_hi[i] - d->prior_lo[i]);
+  }
+  B.prior_const = pc;
+  double tmax = 0.0;
+  for (int64_t i = 0; i < ntoa; ++i) tmax = std::max(tmax, d->t[i]);
+  B.tmax = tmax;
+
+  // per-pulsar timing-model centring and the Hellings-Downs matrix
+  std::vector<double> tc(n), tsi(n), gam((size_t)n * n);
+  for (int p = 0; p < n; ++p) {
+    double lo = d->t[d->toa_offsets[p]], hi = lo;
+    for (int64_t i = d->toa_offsets[p]; i < d->toa_offsets[p + 1]; ++i) {
+      lo = std::min(lo, d->t[i]);
+      hi = std::max(hi, d->t[i]);
+    }
+    tc[p] = 0.5 * (lo + hi);
+    const double hs = 0.5 * (hi - lo);
+    tsi[p] = 1.0 / (hs > 0.0 ? hs : 1.0);
+  }
+  for (int I = 0; I < n; ++I)
+    for (int J = 0; J < n; ++J) {
+      if (I == J) {
+        gam[(size_t)I * n + J] = 1.0;
+        continue;
+      }
+      const double *a = d->psr_pos + 3 * I, *b = d->psr_pos + 3 * J;
+      const double beta = 0.5 * (1.0 - (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]));
+      const double blb = beta > 0.0 ? beta * std::log(beta) : 0.0;
+      gam[(size_t)I * n + J] = 1.5 * blb - 0.25 * beta + 0.5;
+    }
+  ds->off.assign(d->toa_offsets, d->toa_offsets + n + 1);
+
+  int rc = PTAFS_OK;
+  auto chk = [&](int r) { if (r && !rc) rc = r; };
+  chk(upload(ds, d->t, ntoa, &B.t));
+  chk(upload(ds, d->dt, ntoa, &B.dt));
+  chk(upload(ds, d->sigma, ntoa, &B.sigma));
+  chk(upload(ds, d->nu, ntoa, &B.nu));
+  chk(upload(ds, d->backend, ntoa, &B.backend));
+  chk(upload(ds, d->efac, d->n_backend, &B.efac));
+  chk(upload(ds, d->equad, d->n_backend, &B.equad));
+  chk(upload(ds, d->toa_offsets, (size_t)n + 1, &B.toa_off));
+  chk(upload(ds, tc.data(), n, &B.tau_c));
+  chk(upload(ds, tsi.data(), n, &B.tau_sinv));
+  chk(upload(ds, d->psr_pos, (size_t)3 * n, &B.pos));
+  chk(upload(ds, gam.data(), (size_t)n * n, &B.gamma));
+  chk(upload(ds, d->prior_lo, B.n_theta, &B.prior_lo));
+  chk(upload(ds, d->prior_hi, B.n_theta, &B.prior_hi));
+  if (!rc) rc = ensure_chunks(ds);
+  if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = PTAFS_E_HIP;
+  if (rc) {
+    free_all(ds);
+    return rc;
+  }
+  *out = ds;
+  return PTAFS_OK;
+}
+
+void ptafs_dataset_destroy(ptafs_dataset *ds) { free_all(ds); }
+
+int ptafs_layout(const ptafs_dataset *ds, int32_t n_chains, ptafs_layout_info *out) {
+  if (!ds || !out || n_chains < 0) return PTAFS_E_ARG;
+  const pt::Dev &B = ds->base;
+  out->d = B.d;
+  out->n_theta = B.n_theta;
+  out->off_gw = B.off_gw;
+  out->off_rn = B.off_rn;
+  out->off_dm = B.off_dm;
+  out->off_cw = B.off_cw;
+  out->off_u = B.off_u;
+  out->off_z = B.off_z;
+  out->off_zdm = B.off_zdm;
+  out->n_psr = B.n_psr;
+  out->n_toa = B.n_toa;
+  out->k_coef = B.ka;
+  out->k_dm = B.nf_dm;
+  out->dataset_bytes = ds->ds_bytes;
+  int nchunks = ds->n_chunks;
+  out->workspace_bytes = ws_layout(B, cpad_of(n_chains), nchunks).total;
+  return PTAFS_OK;
+}
+
+int ptafs_reserve(ptafs_dataset *ds, int32_t n_chains) {
+  if (!ds || n_chains < 0) return PTAFS_E_ARG;
+  PT_TRY(hipSetDevice(ds->device));
+  int rc = ensure_chunks(ds);
+  if (rc) return rc;
+  return ensure_ws(ds, n_chains);
+}
+
+int ptafs_logp_grad(ptafs_dataset *ds, int32_t n_chains, const double *x, double *logp,
+                    double *grad, int32_t *status, void *stream) {
+  return eval(ds, n_chains, x, logp, grad, status, stream, false);
+}
+
+int ptafs_logp_grad_plain(ptafs_dataset *ds, int32_t n_chains, const double *x, double *logp,
+                          double *grad, int32_t *status, void *stream) {
+  return eval(ds, n_chains, x, logp, grad, status, stream, true);
+}
+
+int ptafs_set_tuning(ptafs_dataset *ds, int32_t tiles_per_chunk, int32_t waves_per_block,
+                     int32_t xcd_map) {
+  if (!ds || tiles_per_chunk < 1 || tiles_per_chunk > 4096) return PTAFS_E_ARG;
+  if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4) return PTAFS_E_ARG;
+  if (tiles_per_chunk != ds->tiles_per_chunk) ds->chunks_dirty = true;
+  ds->tiles_per_chunk = tiles_per_chunk;
+  ds->wpb = waves_per_block;
+  ds->xcd_map = xcd_map ? 1 : 0;
+  PT_TRY(hipSetDevice(ds->device));
+  return ensure_chunks(ds);
+}
+
+int ptafs_get_tuning(const ptafs_dataset *ds, int32_t *tiles_per_chunk, int32_t *waves_per_block,
+                     int32_t *xcd_map) {
+  if (!ds) return PTAFS_E_ARG;
+  if (tiles_per_chunk) *tiles_per_chunk = ds->tiles_per_chunk;
+  if (waves_per_block) *waves_per_block = ds->wpb;
+  if (xcd_map) *xcd_map = ds->xcd_map;
+  return PTAFS_OK;
+}
+
+int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n_leapfrog,
+                  double eps, const double *inv_mass, uint64_t seed, uint64_t traj0, double *x,
+                  double *logp, double *grad, int64_t *n_accept, double *samples, int32_t use_graph,
+                  void *stream) {
+  if (!ds || n_chains < 0 || n_traj < 0 || n_leapfrog < 1 || !(eps > 0.0)) return PTAFS_E_ARG;
+  if (n_chains == 0 || n_traj == 0) return PTAFS_OK;
+  if (!x || !logp || !grad || !n_accept) return PTAFS_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  PT_TRY(hipSetDevice(ds->device));
+  int rc = ensure_chunks(ds);
+  if (rc) return rc;
+  rc = ensure_ws(ds, n_chains);
+  if (rc) return rc;
+  const int d = ds->base.d;
+  const size_t cd = (size_t)n_chains * d;
+  // scratch: p, x0, g0 [C][d], lp0, h0, status [C], trajectory counter
+  const size_t need = align256(3 * cd * sizeof(double)) + align256(2 * (size_t)n_chains * sizeof(double)) +
+                      align256((size_t)n_chains * sizeof(int32_t)) + 256;
+  if (need > ds->hmc_bytes) {
+    PT_TRY(hipDeviceSynchronize());
+    if (ds->gexec) (void)hipGraphExecDestroy(ds->gexec);
+    if (ds->graph) (void)hipGraphDestroy(ds->graph);
+    ds->gexec = nullptr;
+    ds->graph = nullptr;
+    if (ds->hmc) PT_TRY(hipFree(ds->hmc));
+    ds->hmc = nullptr;
+    ds->hmc_bytes = 0;
+    if (hipMalloc(&ds->hmc, need) != hipSuccess) return PTAFS_E_NOMEM;
+    ds->hmc_bytes = need;
+  }
+  char *h = static_cast<char *>(ds->hmc);
+  double *p = reinterpret_cast<double *>(h);
+  double *x0 = p + cd;
+  double *g0 = x0 + cd;
+  char *h2 = h + align256(3 * cd * sizeof(double));
+  double *lp0 = reinterpret_cast<double *>(h2);
+  double *h0 = lp0 + n_chains;
+  char *h3 = h2 + align256(2 * (size_t)n_chains * sizeof(double));
+  int32_t *st = reinterpret_cast<int32_t *>(h3);
+  uint64_t *traj = reinterpret_cast<uint64_t *>(h3 + align256((size_t)n_chains * sizeof(int32_t)));
+
+  PT_TRY(hipMemcpyAsync(traj, &traj0, sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  // the host value must stay valid until the copy ran
+  PT_TRY(hipStreamSynchronize(s));
+
+  const pt::Dev D = make_dev(ds, n_chains);
+  auto one_traj = [&]() -> int {
+    PT_TRY(ptk::launch_hmc_begin(D, d, eps, inv_mass, seed, traj, x, logp, grad, p, x0, lp0, g0, h0, s));
+    for (int l = 0; l < n_leapfrog; ++l) {
+      int r = enqueue_eval(ds, n_chains, x, logp, grad, st, s, false);
+      if (r) return r;
+      if (l + 1 < n_leapfrog) PT_TRY(ptk::launch_hmc_kick_drift(n_chains, d, eps, inv_mass, x, p, grad, s));
+    }
+    PT_TRY(ptk::launch_hmc_end(n_chains, d, eps, inv_mass, seed, traj, traj0, x, logp, grad, p, x0,
+                               lp0, g0, h0, n_accept, samples, s));
+    PT_TRY(ptk::launch_traj_inc(traj, s));
+    return PTAFS_OK;
+  };
+
+  if (!use_graph) {
+    for (int j = 0; j < n_traj; ++j) {
+      rc = one_traj();
+      if (rc) return rc;
+    }
+    return PTAFS_OK;
+  }
+  ptafs_dataset::GraphKey key{};
+  std::memset(&key, 0, sizeof(key));
+  key.n_chains = n_chains;
+  key.n_leapfrog = n_leapfrog;
+  key.eps = eps;
+  key.inv_mass = inv_mass;
+  key.x = x;
+  key.logp = logp;
+  key.grad = grad;
+  key.acc = n_accept;
+  key.samples = samples;
+  key.seed = seed;
+  key.traj0 = traj0;
+  key.stream = s;
+  key.tiles = ds->tiles_per_chunk;
+  key.wpb = ds->wpb;
+  key.xcd = ds->xcd_map;
+  key.ws = ds->ws;
+  key.hmc = ds->hmc;
+  if (!ds->gexec || !(key == ds->gkey)) {
+    if (ds->gexec) {
+      PT_TRY(hipStreamSynchronize(s));
+      (void)hipGraphExecDestroy(ds->gexec);
+      (void)hipGraphDestroy(ds->graph);
+      ds->gexec = nullptr;
+      ds->graph = nullptr;
+    }
+    PT_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    rc = one_traj();
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return PTAFS_E_HIP;
+    if (hipGraphInstantiate(&ds->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return PTAFS_E_HIP;
+    }
+    ds->graph = g;
+    ds->gkey = key;
+  }
+  for (int j = 0; j < n_traj; ++j) PT_TRY(hipGraphLaunch(ds->gexec, s));
+  return PTAFS_OK;
+}
+
+}  // extern "C"
