@@ -186,6 +186,17 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
                   double *logp, double *grad, int64_t *n_accept, double *samples, int32_t use_graph,
                   void *stream);
 
+/*
+ * Stage timing of the evaluation pipeline: runs `reps` evaluations (batched,
+ * or plain when plain != 0) with a HIP event between consecutive stages on
+ * `stream` and writes the mean duration in ms of each stage to the HOST
+ * array ms_out[5]: per-frequency forward, TOA pass, chunk reduction,
+ * per-frequency adjoint, assembly.  Synchronises the stream.
+ */
+int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, double *logp,
+                         double *grad, int32_t *status, int32_t reps, int32_t plain,
+                         double *ms_out, void *stream);
+
 /* Human-readable text for a return code (static storage). */
 const char *ptafs_strerror(int code);
 

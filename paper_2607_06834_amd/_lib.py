@@ -58,7 +58,7 @@ class LayoutInfo(C.Structure):
 EXPORTS = (
     "ptafs_dataset_create", "ptafs_dataset_destroy", "ptafs_layout", "ptafs_reserve",
     "ptafs_logp_grad", "ptafs_logp_grad_plain", "ptafs_set_tuning", "ptafs_get_tuning",
-    "ptafs_hmc_run", "ptafs_strerror",
+    "ptafs_hmc_run", "ptafs_profile_stages", "ptafs_strerror",
 )
 
 _lib = None
@@ -93,6 +93,9 @@ def load():
     lib.ptafs_hmc_run.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, vp,
                                   C.c_uint64, C.c_uint64, vp, vp, vp, vp, vp, C.c_int32, vp]
     lib.ptafs_hmc_run.restype = C.c_int
+    lib.ptafs_profile_stages.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.c_int32, C.c_int32,
+                                         c_double_p, vp]
+    lib.ptafs_profile_stages.restype = C.c_int
     lib.ptafs_strerror.argtypes = [C.c_int]
     lib.ptafs_strerror.restype = C.c_char_p
     _lib = lib

@@ -129,6 +129,22 @@ class Dataset:
         """Plain (launch per pulsar, vector ALU) form; same outputs."""
         return self._call(_lib.load().ptafs_logp_grad_plain, x, out, stream)
 
+    STAGES = ("spec_fwd", "toa", "reduce", "spec_bwd", "finalize")
+
+    def ptafs_profile_stages(self, x, reps=10, plain=False, stream=None):
+        """Mean ms per pipeline stage over ``reps`` evaluations (HIP events)."""
+        x = self._check_x(x)
+        n = x.shape[0]
+        logp = torch.empty(n, dtype=torch.float64, device=x.device)
+        grad = torch.empty_like(x)
+        status = torch.empty(n, dtype=torch.int32, device=x.device)
+        ms = (C.c_double * 5)()
+        _lib.check(_lib.load().ptafs_profile_stages(
+            self._h, n, C.c_void_p(x.data_ptr()), C.c_void_p(logp.data_ptr()),
+            C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()), int(reps), int(bool(plain)),
+            ms, _stream_handle(stream)), "ptafs_profile_stages")
+        return dict(zip(self.STAGES, list(ms)))
+
     def ptafs_hmc_run(self, x, logp, grad, n_accept, *, n_traj, n_leapfrog, eps, seed, traj0=0,
                       inv_mass=None, samples=None, use_graph=True, stream=None):
         """Fixed-step HMC in place on (x, logp, grad); n_accept int64 [C]."""

@@ -92,6 +92,7 @@ struct Dev {
   const int64_t *toa_off;
   const double *tau_c, *tau_sinv;
   const double *pos, *gamma;
+  const double *gchol;         // chol(Gamma), packed row-major lower
   const double *prior_lo, *prior_hi;
   // chunk table of the batched TOA pass
   int n_chunks, tiles_per_chunk;
@@ -109,9 +110,14 @@ struct Dev {
   double *dth_k;               // [c_pad][K][2] gw parts per frequency
   double *drn_k;               // [c_pad][ka][n_psr][2]
   double *ddm_k;               // [c_pad][nf_dm][n_psr][2]
-  int32_t *flag_k;             // [c_pad][max(ka, nf_dm)] per-frequency status
+  double *zsq_k;               // [c_pad][kmax] squared norm of the owned coordinates
+  int32_t *flag_k;             // [c_pad][kmax] per-frequency condition bits (kFlag*)
   int32_t *st_pre;             // [c_pad] status from the input checks
 };
+
+constexpr int kFlagNotPD = 1;          // phi_k not positive definite
+constexpr int kFlagInNonfinite = 2;    // a non-finite input coordinate
+constexpr int kFlagOutNonfinite = 4;   // a non-finite gradient entry
 
 constexpr int kCwConst = 10;   // F+, Fx, dF+/dcos, dFx/dcos, dF+/dphi, dFx/dphi
 
@@ -124,6 +130,8 @@ hipError_t launch_toa_mfma(const pt::Dev &D, int waves_per_block, int xcd_map, h
 hipError_t launch_toa_plain_psr(const pt::Dev &D, int p, int n_chunks_p, hipStream_t s);
 hipError_t set_plain_lds_limit(size_t bytes);
 hipError_t set_spec_lds_limits(size_t fwd_bytes, size_t bwd_bytes);
+size_t spec_fwd_lds(int n);
+size_t spec_bwd_lds(int n);
 hipError_t launch_reduce_chunks(const pt::Dev &D, hipStream_t s);
 hipError_t launch_spec_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s);
 hipError_t launch_finalize(const pt::Dev &D, const double *x, double *logp, double *grad,

@@ -14,7 +14,7 @@ namespace {
 using pt::Dev;
 
 template <typename T>
-__device__ T block_sum256(T v, T *red) {
+__device__ T block_sum(T v, T *red) {
   const int t = threadIdx.x;
   red[t] = v;
   __syncthreads();
@@ -41,39 +41,53 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restric
   const int n = D.n_psr;
   const int kmax = max(D.ka, D.nf_dm);
 
-  int st = D.st_pre[c];
+  // ---- per-chain condition, in the order: prior box, non-finite input,
+  //      CW coalescence, phi not positive definite, non-finite output
   int fl = 0;
-  for (int k = t; k < kmax; k += 256) fl |= D.flag_k[(size_t)c * kmax + k];
-  fl = block_sum256<int>(fl != 0 ? 1 : 0, ired);
-  if (st == 0 && fl) st = PTAFS_ST_NOTPD;
+  double zz = 0.0;
+  for (int k = t; k < kmax; k += 256) {
+    fl |= D.flag_k[(size_t)c * kmax + k];
+    zz += D.zsq_k[(size_t)c * kmax + k];
+  }
+  const int f_in = block_sum<int>((fl & pt::kFlagInNonfinite) ? 1 : 0, ired);
+  const int f_pd = block_sum<int>((fl & pt::kFlagNotPD) ? 1 : 0, ired);
+  const int f_out = block_sum<int>((fl & pt::kFlagOutNonfinite) ? 1 : 0, ired);
+  const int pre = D.st_pre[c];
+  int st = 0;
+  if (pre == PTAFS_ST_PRIOR) st = PTAFS_ST_PRIOR;
+  else if (f_in) st = PTAFS_ST_NONFINITE;
+  else if (pre == PTAFS_ST_CW) st = PTAFS_ST_CW;
+  else if (f_pd) st = PTAFS_ST_NOTPD;
+  else if (f_out) st = PTAFS_ST_NONFINITE;
 
   // ---- log p
-  double zz = 0.0;
-  for (int i = D.off_u + t; i < D.d; i += 256) zz += xc[i] * xc[i];
   double ch = 0.0, ln = 0.0;
   for (int p = t; p < n; p += 256) {
     ch += D.chi_p[(size_t)p * cp + c];
     ln += D.lnn_p[p];
   }
-  zz = block_sum256(zz, red);
-  ch = block_sum256(ch, red);
-  ln = block_sum256(ln, red);
+  zz = block_sum(zz, red);
+  ch = block_sum(ch, red);
+  ln = block_sum(ln, red);
   const double dz = (double)(D.d - D.off_u);
   double lp = -0.5 * ch - 0.5 * ln - 0.5 * (double)D.n_toa * pt::kLn2Pi - 0.5 * zz -
               0.5 * dz * pt::kLn2Pi + D.prior_const;
 
-  // ---- hyper-parameter gradient (sums over frequency in order)
+  // ---- hyper-parameter and timing-model gradient (frequency sums in order)
+  bool fin = true;
   if (st == 0) {
     if (D.nf_gw > 0 && t < 2) {
       double s = 0.0;
       for (int k = 0; k < D.ka; ++k) s += D.dth_k[((size_t)c * D.ka + k) * 2 + t];
       gc[D.off_gw + t] = s;
+      fin = fin && isfinite(s);
     }
     if (D.nf_rn > 0) {
       for (int e = t; e < 2 * n; e += 256) {
         double s = 0.0;
         for (int k = 0; k < D.ka; ++k) s += D.drn_k[((size_t)c * D.ka + k) * n * 2 + e];
         gc[D.off_rn + e] = s;
+        fin = fin && isfinite(s);
       }
     }
     if (D.nf_dm > 0) {
@@ -81,29 +95,25 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restric
         double s = 0.0;
         for (int k = 0; k < D.nf_dm; ++k) s += D.ddm_k[((size_t)c * D.nf_dm + k) * n * 2 + e];
         gc[D.off_dm + e] = s;
+        fin = fin && isfinite(s);
       }
     }
     if (D.has_cw && t < 8) {
       double s = 0.0;
       for (int p = 0; p < n; ++p) s += D.cw_p[((size_t)p * 8 + t) * cp + c];
       gc[D.off_cw + t] = s;
+      fin = fin && isfinite(s);
     }
     // timing model: d/du = sigma_b M^T g - u
     for (int e = t; e < 3 * n; e += 256) {
       const int I = e / 3, ti = e % 3;
       const int row = pt::tm_row(ti, D.kb);
-      gc[D.off_u + e] = D.sigma_b * D.bar_rn[((size_t)I * D.rows_rn + row) * cp + c] - xc[D.off_u + e];
+      const double g = D.sigma_b * D.bar_rn[((size_t)I * D.rows_rn + row) * cp + c] - xc[D.off_u + e];
+      gc[D.off_u + e] = g;
+      fin = fin && isfinite(g);
     }
-  }
-  __syncthreads();
-  __threadfence_block();
-
-  // ---- non-finite result check
-  int bad = 0;
-  if (st == 0) {
-    for (int i = t; i < D.d; i += 256) bad |= !isfinite(gc[i]);
-    bad = block_sum256<int>(bad, ired);
-    if (bad || !isfinite(lp)) st = PTAFS_ST_NONFINITE;
+    const int nbad = block_sum<int>(fin ? 0 : 1, ired);
+    if (nbad || !isfinite(lp)) st = PTAFS_ST_NONFINITE;
   }
   if (st != 0) {
     for (int i = t; i < D.d; i += 256) gc[i] = 0.0;

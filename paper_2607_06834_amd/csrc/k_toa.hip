@@ -323,7 +323,7 @@ __global__ __launch_bounds__(64) void k_toa_plain(Dev D, int p) {
 
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of chunk partials into per-pulsar panels.
-// grid = (n_psr, n_cb), block = 256.
+// grid = (n_psr, n_cb, row blocks of 256 elements), block = 256.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_reduce(Dev D) {
   const int p = blockIdx.x, cb = blockIdx.y;
@@ -331,24 +331,41 @@ __global__ __launch_bounds__(256) void k_reduce(Dev D) {
   const int nr = D.rows_rn, nd = D.rows_dm;
   const size_t cp = D.c_pad;
   const size_t ncb = D.n_cb;
-  for (int e = threadIdx.x; e < (nr + nd) * 16; e += 256) {
+  const int e = blockIdx.z * 256 + threadIdx.x;
+  if (e < (nr + nd) * 16) {
     const int row = e >> 4, col = e & 15;
-    double s = 0.0;
+    double s0 = 0.0, s1 = 0.0;
     if (row < nr) {
-      for (int ch = c0; ch < c1; ++ch) s += D.part_rn[(((size_t)ch * ncb + cb) * nr + row) * 16 + col];
-      D.bar_rn[((size_t)p * nr + row) * cp + cb * 16 + col] = s;
+      const double *src = D.part_rn + ((size_t)c0 * ncb + cb) * nr * 16 + e;
+      const size_t stride = ncb * nr * 16;
+      int ch = c0;
+      for (; ch + 1 < c1; ch += 2) {
+        s0 += src[0];
+        s1 += src[stride];
+        src += 2 * stride;
+      }
+      if (ch < c1) s0 += src[0];
+      D.bar_rn[((size_t)p * nr + row) * cp + cb * 16 + col] = s0 + s1;
     } else {
-      const int r2 = row - nr;
-      for (int ch = c0; ch < c1; ++ch) s += D.part_dm[(((size_t)ch * ncb + cb) * nd + r2) * 16 + col];
-      D.bar_dm[((size_t)p * nd + r2) * cp + cb * 16 + col] = s;
+      const int e2 = e - nr * 16, r2 = row - nr;
+      const double *src = D.part_dm + ((size_t)c0 * ncb + cb) * nd * 16 + e2;
+      const size_t stride = ncb * nd * 16;
+      int ch = c0;
+      for (; ch + 1 < c1; ch += 2) {
+        s0 += src[0];
+        s1 += src[stride];
+        src += 2 * stride;
+      }
+      if (ch < c1) s0 += src[0];
+      D.bar_dm[((size_t)p * nd + r2) * cp + cb * 16 + col] = s0 + s1;
     }
   }
-  if (threadIdx.x < 16) {
+  if (blockIdx.z == 0 && threadIdx.x < 16) {
     double s = 0.0;
     for (int ch = c0; ch < c1; ++ch) s += D.part_chi[((size_t)ch * ncb + cb) * 16 + threadIdx.x];
     D.chi_p[(size_t)p * cp + cb * 16 + threadIdx.x] = s;
   }
-  if (cb == 0 && threadIdx.x == 32) {
+  if (blockIdx.z == 0 && cb == 0 && threadIdx.x == 32) {
     double s = 0.0;
     for (int ch = c0; ch < c1; ++ch) s += D.part_lnn[(size_t)ch * ncb];
     D.lnn_p[p] = s;
@@ -408,7 +425,8 @@ hipError_t launch_toa_plain_psr(const pt::Dev &D, int p, int n_chunks_p, hipStre
 
 hipError_t launch_reduce_chunks(const pt::Dev &D, hipStream_t s) {
   if (D.n_psr == 0 || D.n_cb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(D.n_psr, D.n_cb), dim3(256), 0, s, D);
+  const int nz = ((D.rows_rn + D.rows_dm) * 16 + 255) / 256;
+  hipLaunchKernelGGL(k_reduce, dim3(D.n_psr, D.n_cb, nz), dim3(256), 0, s, D);
   return hipGetLastError();
 }
 

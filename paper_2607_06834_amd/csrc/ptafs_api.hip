@@ -30,12 +30,12 @@ struct ptafs_dataset {
   // cached trajectory graph
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
+  hipStream_t cap = nullptr;          // private stream used only for graph capture
   struct GraphKey {
     int n_chains, n_leapfrog;
     double eps;
     const void *inv_mass, *x, *logp, *grad, *acc, *samples;
     uint64_t seed, traj0;
-    hipStream_t stream;
     int tiles, wpb, xcd;
     void *ws, *hmc;
     bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
@@ -54,7 +54,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
   size_t coef_rn, coef_dm, lstore, part_rn, part_dm, part_chi, part_lnn, part_cw, bar_rn, bar_dm,
-      chi_p, lnn_p, cw_p, dth_k, drn_k, ddm_k, flag_k, st_pre, total;
+      chi_p, lnn_p, cw_p, dth_k, drn_k, ddm_k, zsq_k, flag_k, st_pre, total;
 };
 
 WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
@@ -84,6 +84,7 @@ WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
   L.dth_k = take(cp * B.ka * 2 * D8);
   L.drn_k = take(cp * B.ka * n * 2 * D8);
   L.ddm_k = take(cp * B.nf_dm * n * 2 * D8);
+  L.zsq_k = take(cp * kmax * D8);
   L.flag_k = take(cp * kmax * sizeof(int32_t));
   L.st_pre = take(cp * sizeof(int32_t));
   L.total = o;
@@ -176,6 +177,7 @@ pt::Dev make_dev(const ptafs_dataset *ds, int n_chains) {
   D.dth_k = reinterpret_cast<double *>(w + L.dth_k);
   D.drn_k = reinterpret_cast<double *>(w + L.drn_k);
   D.ddm_k = reinterpret_cast<double *>(w + L.ddm_k);
+  D.zsq_k = reinterpret_cast<double *>(w + L.zsq_k);
   D.flag_k = reinterpret_cast<int32_t *>(w + L.flag_k);
   D.st_pre = reinterpret_cast<int32_t *>(w + L.st_pre);
   return D;
@@ -185,11 +187,8 @@ std::once_flag g_lds_once;
 hipError_t g_lds_err = hipSuccess;
 
 void set_lds_limits() {
-  const size_t n = PTAFS_MAX_PSR;
-  const size_t fwd = (n * (n + 1) / 2 + 2 * n) * sizeof(double);
-  const size_t bwd = (n * (n | 1) + 4 * n) * sizeof(double);
   const size_t plain = (size_t)2 * (64 + 64) * 64 * sizeof(double);
-  g_lds_err = ptk::set_spec_lds_limits(fwd, bwd);
+  g_lds_err = ptk::set_spec_lds_limits(ptk::spec_fwd_lds(PTAFS_MAX_PSR), ptk::spec_bwd_lds(PTAFS_MAX_PSR));
   if (g_lds_err == hipSuccess) g_lds_err = ptk::set_plain_lds_limit(plain);
 }
 
@@ -239,6 +238,7 @@ void free_all(ptafs_dataset *ds) {
   (void)hipDeviceSynchronize();
   if (ds->gexec) (void)hipGraphExecDestroy(ds->gexec);
   if (ds->graph) (void)hipGraphDestroy(ds->graph);
+  if (ds->cap) (void)hipStreamDestroy(ds->cap);
   for (void *p : ds->allocs) (void)hipFree(p);
   if (ds->d_chunk) (void)hipFree(ds->d_chunk);
   if (ds->ws) (void)hipFree(ds->ws);
@@ -362,6 +362,28 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
       const double blb = beta > 0.0 ? beta * std::log(beta) : 0.0;
       gam[(size_t)I * n + J] = 1.5 * blb - 0.25 * beta + 0.5;
     }
+  // chol(Gamma) for the adjoint of the common-process amplitude
+  std::vector<double> gch((size_t)n * (n + 1) / 2, 0.0);
+  {
+    std::vector<double> Lf((size_t)n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+      double s = gam[(size_t)j * n + j];
+      for (int m = 0; m < j; ++m) s -= Lf[(size_t)j * n + m] * Lf[(size_t)j * n + m];
+      if (!(s > 0.0)) {
+        delete ds;
+        return PTAFS_E_ARG;      // Gamma must be positive definite
+      }
+      const double ljj = std::sqrt(s);
+      Lf[(size_t)j * n + j] = ljj;
+      for (int i = j + 1; i < n; ++i) {
+        double t = gam[(size_t)i * n + j];
+        for (int m = 0; m < j; ++m) t -= Lf[(size_t)i * n + m] * Lf[(size_t)j * n + m];
+        Lf[(size_t)i * n + j] = t / ljj;
+      }
+    }
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j <= i; ++j) gch[(size_t)i * (i + 1) / 2 + j] = Lf[(size_t)i * n + j];
+  }
   ds->off.assign(d->toa_offsets, d->toa_offsets + n + 1);
 
   int rc = PTAFS_OK;
@@ -378,6 +400,7 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
   chk(upload(ds, tsi.data(), n, &B.tau_sinv));
   chk(upload(ds, d->psr_pos, (size_t)3 * n, &B.pos));
   chk(upload(ds, gam.data(), (size_t)n * n, &B.gamma));
+  chk(upload(ds, gch.data(), gch.size(), &B.gchol));
   chk(upload(ds, d->prior_lo, B.n_theta, &B.prior_lo));
   chk(upload(ds, d->prior_hi, B.n_theta, &B.prior_hi));
   if (!rc) rc = ensure_chunks(ds);
@@ -453,6 +476,52 @@ int ptafs_get_tuning(const ptafs_dataset *ds, int32_t *tiles_per_chunk, int32_t 
   return PTAFS_OK;
 }
 
+int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, double *logp,
+                         double *grad, int32_t *status, int32_t reps, int32_t plain,
+                         double *ms_out, void *stream) {
+  if (!ds || n_chains < 1 || reps < 1 || !ms_out || !x || !logp || !grad || !status) return PTAFS_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  PT_TRY(hipSetDevice(ds->device));
+  int rc = ensure_chunks(ds);
+  if (rc) return rc;
+  rc = ensure_ws(ds, n_chains);
+  if (rc) return rc;
+  const pt::Dev D = make_dev(ds, n_chains);
+  constexpr int kStages = 5;
+  hipEvent_t ev[kStages + 1];
+  for (auto &e : ev) PT_TRY(hipEventCreate(&e));
+  double acc[kStages] = {0, 0, 0, 0, 0};
+  int err = PTAFS_OK;
+  for (int r = 0; r < reps && !err; ++r) {
+    auto step = [&](int i, hipError_t e) {
+      if (e != hipSuccess && !err) err = PTAFS_E_HIP;
+      (void)hipEventRecord(ev[i + 1], s);
+    };
+    (void)hipEventRecord(ev[0], s);
+    step(0, ptk::launch_spec_fwd(D, x, s));
+    if (plain) {
+      hipError_t e = hipSuccess;
+      for (int p = 0; p < D.n_psr && e == hipSuccess; ++p)
+        e = ptk::launch_toa_plain_psr(D, p, ds->psr_nchunks[p], s);
+      step(1, e);
+    } else {
+      step(1, ptk::launch_toa_mfma(D, ds->wpb, ds->xcd_map, s));
+    }
+    step(2, ptk::launch_reduce_chunks(D, s));
+    step(3, ptk::launch_spec_bwd(D, x, grad, s));
+    step(4, ptk::launch_finalize(D, x, logp, grad, status, s));
+    if (hipEventSynchronize(ev[kStages]) != hipSuccess) err = PTAFS_E_HIP;
+    for (int i = 0; i < kStages && !err; ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) err = PTAFS_E_HIP;
+      acc[i] += ms;
+    }
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  for (int i = 0; i < kStages; ++i) ms_out[i] = acc[i] / reps;
+  return err;
+}
+
 int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n_leapfrog,
                   double eps, const double *inv_mass, uint64_t seed, uint64_t traj0, double *x,
                   double *logp, double *grad, int64_t *n_accept, double *samples, int32_t use_graph,
@@ -499,22 +568,22 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   PT_TRY(hipStreamSynchronize(s));
 
   const pt::Dev D = make_dev(ds, n_chains);
-  auto one_traj = [&]() -> int {
-    PT_TRY(ptk::launch_hmc_begin(D, d, eps, inv_mass, seed, traj, x, logp, grad, p, x0, lp0, g0, h0, s));
+  auto one_traj = [&](hipStream_t q) -> int {
+    PT_TRY(ptk::launch_hmc_begin(D, d, eps, inv_mass, seed, traj, x, logp, grad, p, x0, lp0, g0, h0, q));
     for (int l = 0; l < n_leapfrog; ++l) {
-      int r = enqueue_eval(ds, n_chains, x, logp, grad, st, s, false);
+      int r = enqueue_eval(ds, n_chains, x, logp, grad, st, q, false);
       if (r) return r;
-      if (l + 1 < n_leapfrog) PT_TRY(ptk::launch_hmc_kick_drift(n_chains, d, eps, inv_mass, x, p, grad, s));
+      if (l + 1 < n_leapfrog) PT_TRY(ptk::launch_hmc_kick_drift(n_chains, d, eps, inv_mass, x, p, grad, q));
     }
     PT_TRY(ptk::launch_hmc_end(n_chains, d, eps, inv_mass, seed, traj, traj0, x, logp, grad, p, x0,
-                               lp0, g0, h0, n_accept, samples, s));
-    PT_TRY(ptk::launch_traj_inc(traj, s));
+                               lp0, g0, h0, n_accept, samples, q));
+    PT_TRY(ptk::launch_traj_inc(traj, q));
     return PTAFS_OK;
   };
 
   if (!use_graph) {
     for (int j = 0; j < n_traj; ++j) {
-      rc = one_traj();
+      rc = one_traj(s);
       if (rc) return rc;
     }
     return PTAFS_OK;
@@ -532,7 +601,6 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   key.samples = samples;
   key.seed = seed;
   key.traj0 = traj0;
-  key.stream = s;
   key.tiles = ds->tiles_per_chunk;
   key.wpb = ds->wpb;
   key.xcd = ds->xcd_map;
@@ -546,10 +614,13 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
       ds->gexec = nullptr;
       ds->graph = nullptr;
     }
-    PT_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-    rc = one_traj();
+    // Capture on a private stream (the caller's may be the null stream, which
+    // cannot be captured); the graph is then launched on the caller's stream.
+    if (!ds->cap) PT_TRY(hipStreamCreateWithFlags(&ds->cap, hipStreamNonBlocking));
+    PT_TRY(hipStreamBeginCapture(ds->cap, hipStreamCaptureModeRelaxed));
+    rc = one_traj(ds->cap);
     hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(s, &g);
+    const hipError_t ec = hipStreamEndCapture(ds->cap, &g);
     if (rc) {
       if (g) (void)hipGraphDestroy(g);
       return rc;

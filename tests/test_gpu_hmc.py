@@ -1,0 +1,111 @@
+"""GPU fixed-step HMC (App. A) against the oracle sampler and closed forms.
+
+Both samplers draw momenta and accept uniforms from Philox4x32-10 with the
+same key/counter convention, so trajectories can be compared one by one.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense, hmc, model
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_06834_amd import api as a
+    return a
+
+
+def small_ds(seed=5):
+    return synth.make_array(seed, 3, [25, 30, 35], 8 * synth.YEAR_S, backends_per_psr=[1, 2, 1],
+                            nu_range=(0.4e9, 2e9), nf_rn=3, nf_gw=3, nf_dm=2)
+
+
+def gpu_hmc(api, ds, X0, *, n_traj, L, eps, seed, inv_mass=None, use_graph=True, traj0=0):
+    g = api.Dataset(ds)
+    x = torch.tensor(X0, device="cuda")
+    lp, gr, st = g.ptafs_logp_grad(x)
+    acc = torch.zeros(x.shape[0], dtype=torch.int64, device="cuda")
+    samples = torch.empty((n_traj, x.shape[0], g.d), dtype=torch.float64, device="cuda")
+    im = None if inv_mass is None else torch.tensor(inv_mass, device="cuda")
+    g.ptafs_hmc_run(x, lp, gr, acc, n_traj=n_traj, n_leapfrog=L, eps=eps, seed=seed, traj0=traj0,
+                    inv_mass=im, samples=samples, use_graph=use_graph)
+    torch.cuda.synchronize()
+    out = (x.cpu().numpy(), lp.cpu().numpy(), gr.cpu().numpy(), acc.cpu().numpy(),
+           samples.cpu().numpy())
+    g.close()
+    return out
+
+
+def test_hmc_matches_oracle_trajectories(api):
+    ds = small_ds()
+    prep = model.Prepared(ds)
+    lay = prep.lay
+    th = synth.injected_theta(ds, 7, rn=(-14.0, 3.5), dm=(-14.0, 3.5))
+    m, Sw = dense.posterior_moments(prep, th)
+    X0 = synth.random_points(ds, 8, 8, theta=th, theta_jitter=0.2)
+    X0[:, lay.u:] = m + np.random.default_rng(1).standard_normal((8, m.size)) * np.sqrt(np.diag(Sw))
+    # inverse mass ~ posterior variances (App. A); a step size that both
+    # accepts and rejects (checked with the oracle sampler)
+    im = np.ones(lay.d)
+    im[: lay.n_theta] = 0.01
+    im[lay.u:] = np.diag(Sw)
+    eps = 0.3
+    x, lp, gr, acc, S = gpu_hmc(api, ds, X0, n_traj=4, L=6, eps=eps, seed=1234, inv_mass=im, traj0=3)
+
+    def lpg(Xb):
+        o = model.logp_grad(prep, Xb, with_scale=False)
+        return o["logp"], o["grad"]
+
+    ox, olp, ogr, oacc, OS = hmc.run(lpg, X0, n_traj=4, n_leapfrog=6, eps=eps, seed=1234,
+                                     traj0=3, inv_mass=im, keep_samples=True)
+    np.testing.assert_array_equal(acc, oacc)
+    assert 0 < acc.sum() < 32
+    np.testing.assert_allclose(S, OS, rtol=1e-8, atol=1e-10)
+    np.testing.assert_allclose(lp, olp, rtol=1e-9)
+
+
+def test_hmc_graph_replay_equals_eager(api):
+    ds = small_ds(6)
+    th = synth.injected_theta(ds, 9, rn=(-14.0, 3.5), dm=(-14.0, 3.5))
+    X0 = synth.random_points(ds, 16, 10, theta=th, theta_jitter=0.2)
+    a = gpu_hmc(api, ds, X0, n_traj=5, L=4, eps=0.03, seed=77, use_graph=True)
+    b = gpu_hmc(api, ds, X0, n_traj=5, L=4, eps=0.03, seed=77, use_graph=False)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_hmc_linear_gaussian_moments(api):
+    """Hyper-parameters frozen (inverse mass 0): the coefficients (u, z, z_dm)
+    have the closed-form Gaussian posterior of the dense time-domain model."""
+    ds = synth.make_array(3, 3, [12, 15, 18], 8 * synth.YEAR_S, backends_per_psr=[1, 2, 1],
+                          nu_range=(0.4e9, 2.0e9), nf_rn=2, nf_gw=2, nf_dm=1)
+    prep = model.Prepared(ds)
+    lay = prep.lay
+    theta = synth.injected_theta(ds, 4, rn=(-13.5, 3.0), dm=(-13.5, 3.0))
+    m, S = dense.posterior_moments(prep, theta)
+    im = np.zeros(lay.d)
+    im[lay.u:] = np.diag(S)
+    C = 256
+    rng = np.random.default_rng(5)
+    X0 = np.zeros((C, lay.d))
+    X0[:, : lay.n_theta] = theta
+    # start at stationarity (draws from the exact joint posterior), so that the
+    # sample moments are unbiased whatever the mixing speed of each direction
+    X0[:, lay.u:] = m + rng.standard_normal((C, m.size)) @ np.linalg.cholesky(S).T
+    x, lp, gr, acc, samp = gpu_hmc(api, ds, X0, n_traj=120, L=16, eps=0.08, seed=99, inv_mass=im)
+    assert np.all(samp[:, :, : lay.n_theta] == theta)
+    samp = samp[10:, :, lay.u:]
+    assert acc.mean() / 120 > 0.7
+    chm = samp.mean(0)
+    zsc = (chm.mean(0) - m) / (chm.std(0) / np.sqrt(C))
+    assert np.max(np.abs(zsc)) < 5.0, np.max(np.abs(zsc))
+    var = ((samp - m) ** 2).mean(0)
+    zv = (var.mean(0) - np.diag(S)) / (var.std(0) / np.sqrt(C))
+    assert np.max(np.abs(zv)) < 5.0, np.max(np.abs(zv))

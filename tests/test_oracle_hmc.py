@@ -73,7 +73,8 @@ def test_linear_gaussian_moments():
     rng = np.random.default_rng(5)
     x0 = np.zeros((C, lay.d))
     x0[:, : lay.n_theta] = theta
-    x0[:, lay.u:] = m + rng.standard_normal((C, m.size)) * np.sqrt(np.diag(S))
+    # start at stationarity (draws from the exact joint posterior)
+    x0[:, lay.u:] = m + rng.standard_normal((C, m.size)) @ np.linalg.cholesky(S).T
     _, _, _, nacc, samp = hmc.run(lpg, x0, n_traj=120, n_leapfrog=16, eps=0.08, seed=99,
                                   inv_mass=inv_mass, keep_samples=True)
     # frozen coordinates never move
