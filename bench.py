@@ -67,7 +67,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chains", type=int, default=64)
     ap.add_argument("--leapfrog", type=int, default=20)
-    ap.add_argument("--eps", type=float, default=0.02)
+    ap.add_argument("--eps", type=float, default=0.3, help="largest step tried")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
@@ -75,14 +75,14 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
-              "(chains shard across GPUs without communication; see DESIGN.md)", file=sys.stderr)
+              "(chains shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
 
     import synth
-    from paper_2607_06834_amd import api, autotune
+    from paper_2607_06834_amd import api, autotune, precond
 
     torch.cuda.set_device(0)
     ds = synth.cfg2()
@@ -96,22 +96,33 @@ def main():
     if not args.no_tune:
         tuning, tune_log = autotune.tune(g, x)
 
+    # diagonal inverse mass from the local precision at the injection (App. A),
+    # chains moved to the conditional mode of their coefficients, and the
+    # largest step whose trial trajectory stays valid (sampler warm-up)
+    inv_mass = precond.inverse_mass(g, x[0].clone())
+    x = precond.ascend_coefficients(g, x, inv_mass)
+    lp, gr, st = g.ptafs_logp_grad(x)
+    eps = precond.find_step(g, x, lp, gr, inv_mass, n_leapfrog=L, eps0=args.eps)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         lp, gr, st = g.ptafs_logp_grad(x)
         acc = torch.zeros(C, dtype=torch.int64, device="cuda")
+        bad = torch.zeros(C, dtype=torch.int64, device="cuda")
         # warmup (the first call captures the trajectory graph)
-        g.ptafs_hmc_run(x, lp, gr, acc, n_traj=max(args.warmup, 1), n_leapfrog=L, eps=args.eps,
-                        seed=203, traj0=0)
+        g.ptafs_hmc_run(x, lp, gr, acc, n_traj=max(args.warmup, 1), n_leapfrog=L, eps=eps,
+                        seed=203, traj0=0, inv_mass=inv_mass, n_invalid=bad)
         stream.synchronize()
         acc.zero_()
+        bad.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g.ptafs_hmc_run(x, lp, gr, acc, n_traj=args.steps, n_leapfrog=L, eps=args.eps,
-                        seed=203, traj0=max(args.warmup, 1))
+        g.ptafs_hmc_run(x, lp, gr, acc, n_traj=args.steps, n_leapfrog=L, eps=eps,
+                        seed=203, traj0=max(args.warmup, 1), inv_mass=inv_mass, n_invalid=bad)
         stream.synchronize()
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        # every timed leapfrog evaluation must have been a full, valid one
+        valid = 1.0 - float(bad.sum().item()) / (C * L * args.steps)
     ms_step = el / args.steps * 1e3
     value = C * L * args.steps / el
 
@@ -145,7 +156,7 @@ def main():
             "workload": "67 psr / 250000 TOA over 16 yr; RN 30 + DM 30 + HD common 14 freqs; "
                         f"{C} HMC chains x leapfrog {L}; step = one HIP-graph trajectory",
             "n_psr": int(ds["n_psr"]), "n_toa": int(ds["t"].size), "chains": C,
-            "leapfrog": L, "eps": args.eps, "d": int(g.d),
+            "leapfrog": L, "eps": eps, "d": int(g.d),
             "tuning": {"tiles_per_chunk": tuning[0], "waves_per_block": tuning[1],
                        "xcd_map": tuning[2]},
         },
@@ -165,6 +176,7 @@ def main():
                          "ms_per_eval": round(eval_ms, 5)},
         "plain": plain,
         "accept_rate": float(acc.sum().item()) / (C * args.steps),
+        "valid_eval_fraction": valid,
         "cpu_baseline": cpu,
     }
     if tune_log is not None:

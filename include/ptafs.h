@@ -179,12 +179,14 @@ int ptafs_get_tuning(const ptafs_dataset *ds, int32_t *tiles_per_chunk, int32_t 
  *                values at x on entry (e.g. from ptafs_logp_grad)
  *   n_accept     device [n_chains] int64, incremented per accepted trajectory
  *   samples      device [n_traj][n_chains][d] or NULL: state after each trajectory
+ *   n_invalid    device [n_chains] int64 or NULL: incremented for every leapfrog
+ *                evaluation of the chain that returned a nonzero status
  * use_graph: 1 captures one trajectory as a HIP graph and replays it.
  */
 int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n_leapfrog,
                   double eps, const double *inv_mass, uint64_t seed, uint64_t traj0, double *x,
-                  double *logp, double *grad, int64_t *n_accept, double *samples, int32_t use_graph,
-                  void *stream);
+                  double *logp, double *grad, int64_t *n_accept, double *samples,
+                  int64_t *n_invalid, int32_t use_graph, void *stream);
 
 /*
  * Stage timing of the evaluation pipeline: runs `reps` evaluations (batched,

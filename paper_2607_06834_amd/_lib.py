@@ -91,7 +91,7 @@ def load():
     lib.ptafs_get_tuning.argtypes = [vp, c_int32_p, c_int32_p, c_int32_p]
     lib.ptafs_get_tuning.restype = C.c_int
     lib.ptafs_hmc_run.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, vp,
-                                  C.c_uint64, C.c_uint64, vp, vp, vp, vp, vp, C.c_int32, vp]
+                                  C.c_uint64, C.c_uint64, vp, vp, vp, vp, vp, vp, C.c_int32, vp]
     lib.ptafs_hmc_run.restype = C.c_int
     lib.ptafs_profile_stages.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.c_int32, C.c_int32,
                                          c_double_p, vp]

@@ -66,6 +66,7 @@ class Dataset:
                    "ptafs_dataset_create")
         self._h = h
         self._keep = None
+        self.prior_lo, self.prior_hi = lo.copy(), hi.copy()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.layout = self.ptafs_layout(0)
         self.d = int(self.layout.d)
@@ -146,8 +147,10 @@ class Dataset:
         return dict(zip(self.STAGES, list(ms)))
 
     def ptafs_hmc_run(self, x, logp, grad, n_accept, *, n_traj, n_leapfrog, eps, seed, traj0=0,
-                      inv_mass=None, samples=None, use_graph=True, stream=None):
-        """Fixed-step HMC in place on (x, logp, grad); n_accept int64 [C]."""
+                      inv_mass=None, samples=None, n_invalid=None, use_graph=True, stream=None):
+        """Fixed-step HMC in place on (x, logp, grad); n_accept int64 [C];
+        n_invalid (int64 [C], optional) counts leapfrog evaluations with a
+        nonzero status."""
         x = self._check_x(x)
         n = x.shape[0]
         for t in (logp, grad):
@@ -155,12 +158,15 @@ class Dataset:
         assert n_accept.dtype == torch.int64 and n_accept.is_cuda
         im = C.c_void_p(inv_mass.data_ptr()) if inv_mass is not None else C.c_void_p()
         sm = C.c_void_p(samples.data_ptr()) if samples is not None else C.c_void_p()
+        nv = C.c_void_p(n_invalid.data_ptr()) if n_invalid is not None else C.c_void_p()
+        if n_invalid is not None:
+            assert n_invalid.dtype == torch.int64 and n_invalid.is_cuda
         if samples is not None:
             assert samples.shape == (n_traj, n, self.d) and samples.dtype == torch.float64
         _lib.check(_lib.load().ptafs_hmc_run(
             self._h, n, int(n_traj), int(n_leapfrog), float(eps), im, C.c_uint64(seed),
             C.c_uint64(traj0), C.c_void_p(x.data_ptr()), C.c_void_p(logp.data_ptr()),
-            C.c_void_p(grad.data_ptr()), C.c_void_p(n_accept.data_ptr()), sm,
+            C.c_void_p(grad.data_ptr()), C.c_void_p(n_accept.data_ptr()), sm, nv,
             int(bool(use_graph)), _stream_handle(stream)), "ptafs_hmc_run")
 
 

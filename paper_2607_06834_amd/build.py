@@ -18,6 +18,8 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep MFMA accumulators in ordinary VGPRs (no AGPR <-> VGPR copies in loops)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function",
 ]
 
@@ -49,5 +51,17 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_microbench() -> str:
+    """Peak-measurement program (FP64 MFMA / vector FMA / copy)."""
+    exe = os.path.join(HERE, "microbench", "peaks")
+    src = os.path.join(HERE, "microbench", "peaks.hip")
+    cmd = [HIPCC, *FLAGS, src, "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for peaks.hip:\n{r.stdout}\n{r.stderr}")
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_microbench())

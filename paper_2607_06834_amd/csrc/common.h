@@ -16,6 +16,8 @@ constexpr double kLn2Pi = 1.83787706640934548356065947281;
 constexpr double kTsun = 4.925490947641e-6;      // G Msun / c^3, s
 
 constexpr int kChainBlock = 16;                  // chains per MFMA column block
+constexpr int kToaPad = 128;                     // zero padding of per-TOA arrays
+constexpr int kPrepToas = 1024;                  // TOAs per preparation block
 constexpr int kTile = 16;                        // TOAs per MFMA row tile
 
 // ---------------------------------------------------------------------------
@@ -91,6 +93,9 @@ struct Dev {
   const double *efac, *equad;
   const int64_t *toa_off;
   const double *tau_c, *tau_sinv;
+  // per-TOA basis phases, padded by kToaPad zeros: sin, cos of 2 pi t / T,
+  // tau = (t - mid_I) / halfspan_I, DM weight w = dm_scale / nu^2
+  const double *sth, *cth, *tau, *wdm;
   const double *pos, *gamma;
   const double *gchol;         // chol(Gamma), packed row-major lower
   const double *prior_lo, *prior_hi;
@@ -104,9 +109,12 @@ struct Dev {
   double *lstore;              // [c_pad][nf_gw][n_psr*(n_psr+1)/2]
   double *cwc;                 // [c_pad][n_psr][kCwConst] per chain/pulsar CW constants
   double *part_rn, *part_dm;   // [n_wg][rows][16]
-  double *part_chi, *part_lnn, *part_cw;  // [n_wg][16], [n_wg], [n_wg][8][16]
+  double *part_chi, *part_cw;  // [n_wg][16], [n_wg][8][16]
+  double *invn;                // [n_toa + kToaPad] per-call 1/N (zeros in the padding)
+  double *lnn_blk;             // [n_prep] per-call partial sums of ln N
+  int n_prep;                  // TOA-preparation blocks (kPrepToas TOAs each)
   double *bar_rn, *bar_dm;     // [n_psr][rows][c_pad]
-  double *chi_p, *lnn_p, *cw_p; // [n_psr][c_pad], [n_psr], [n_psr][8][c_pad]
+  double *chi_p, *cw_p;        // [n_psr][c_pad], [n_psr][8][c_pad]
   double *dth_k;               // [c_pad][K][2] gw parts per frequency
   double *drn_k;               // [c_pad][ka][n_psr][2]
   double *ddm_k;               // [c_pad][nf_dm][n_psr][2]
@@ -142,11 +150,12 @@ hipError_t launch_hmc_begin(const pt::Dev &D, int d, double eps, const double *i
                             const double *grad, double *p, double *x0, double *lp0, double *g0,
                             double *h0, hipStream_t s);
 hipError_t launch_hmc_kick_drift(int n_chains, int d, double eps, const double *inv_mass,
-                                 double *x, double *p, const double *grad, hipStream_t s);
+                                 double *x, double *p, const double *grad, const int32_t *status,
+                                 int64_t *n_invalid, hipStream_t s);
 hipError_t launch_hmc_end(int n_chains, int d, double eps, const double *inv_mass, uint64_t seed,
                           const uint64_t *traj, uint64_t traj0, double *x, double *logp,
                           double *grad, double *p, const double *x0, const double *lp0,
                           const double *g0, const double *h0, int64_t *n_accept, double *samples,
-                          hipStream_t s);
+                          const int32_t *status, int64_t *n_invalid, hipStream_t s);
 hipError_t launch_traj_inc(uint64_t *traj, hipStream_t s);
 }  // namespace ptk

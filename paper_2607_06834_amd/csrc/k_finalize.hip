@@ -27,6 +27,19 @@ __device__ T block_sum(T v, T *red) {
   return r;
 }
 
+// Sum of K <= 32 strided values in index order, with every load issued
+// before the first add (the loads are independent; a plain loop would wait
+// for each one in turn).
+__device__ inline double sum32(const double *p, size_t stride, int K) {
+  double v[32];
+#pragma unroll
+  for (int k = 0; k < 32; ++k) v[k] = (k < K) ? p[(size_t)k * stride] : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) s += v[k];
+  return s;
+}
+
 __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restrict__ x,
                                                   double *__restrict__ logp,
                                                   double *__restrict__ grad,
@@ -62,10 +75,8 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restric
 
   // ---- log p
   double ch = 0.0, ln = 0.0;
-  for (int p = t; p < n; p += 256) {
-    ch += D.chi_p[(size_t)p * cp + c];
-    ln += D.lnn_p[p];
-  }
+  for (int p = t; p < n; p += 256) ch += D.chi_p[(size_t)p * cp + c];
+  for (int b = t; b < D.n_prep; b += 256) ln += D.lnn_blk[b];
   zz = block_sum(zz, red);
   ch = block_sum(ch, red);
   ln = block_sum(ln, red);
@@ -77,30 +88,28 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restric
   bool fin = true;
   if (st == 0) {
     if (D.nf_gw > 0 && t < 2) {
-      double s = 0.0;
-      for (int k = 0; k < D.ka; ++k) s += D.dth_k[((size_t)c * D.ka + k) * 2 + t];
+      const double s = sum32(D.dth_k + (size_t)c * D.ka * 2 + t, 2, D.ka);
       gc[D.off_gw + t] = s;
       fin = fin && isfinite(s);
     }
     if (D.nf_rn > 0) {
       for (int e = t; e < 2 * n; e += 256) {
-        double s = 0.0;
-        for (int k = 0; k < D.ka; ++k) s += D.drn_k[((size_t)c * D.ka + k) * n * 2 + e];
+        const double s = sum32(D.drn_k + (size_t)c * D.ka * n * 2 + e, (size_t)n * 2, D.ka);
         gc[D.off_rn + e] = s;
         fin = fin && isfinite(s);
       }
     }
     if (D.nf_dm > 0) {
       for (int e = t; e < 2 * n; e += 256) {
-        double s = 0.0;
-        for (int k = 0; k < D.nf_dm; ++k) s += D.ddm_k[((size_t)c * D.nf_dm + k) * n * 2 + e];
+        const double s = sum32(D.ddm_k + (size_t)c * D.nf_dm * n * 2 + e, (size_t)n * 2, D.nf_dm);
         gc[D.off_dm + e] = s;
         fin = fin && isfinite(s);
       }
     }
     if (D.has_cw && t < 8) {
       double s = 0.0;
-      for (int p = 0; p < n; ++p) s += D.cw_p[((size_t)p * 8 + t) * cp + c];
+      for (int p0 = 0; p0 < n; p0 += 32)
+        s += sum32(D.cw_p + ((size_t)p0 * 8 + t) * cp + c, 8 * cp, min(32, n - p0));
       gc[D.off_cw + t] = s;
       fin = fin && isfinite(s);
     }

@@ -94,10 +94,16 @@ __global__ __launch_bounds__(256) void k_hmc_begin(int d, double eps, const doub
 // p += eps grad; x += eps M^-1 p  over n_chains * d elements
 __global__ __launch_bounds__(256) void k_hmc_kick_drift(size_t n, int d, double eps,
                                                         const double *inv_mass, double *x,
-                                                        double *p, const double *grad) {
+                                                        double *p, const double *grad,
+                                                        const int32_t *status,
+                                                        int64_t *n_invalid) {
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
   const int i = (int)(e % d);
+  if (i == 0 && n_invalid) {
+    const size_t c = e / d;
+    if (status[c] != 0) n_invalid[c] += 1;
+  }
   const double im = inv_mass ? inv_mass[i] : 1.0;
   const double pi = p[e] + eps * grad[e];
   p[e] = pi;
@@ -110,7 +116,8 @@ __global__ __launch_bounds__(256) void k_hmc_end(int d, double eps, const double
                                                  int n_chains, double *x, double *logp, double *grad,
                                                  double *p, const double *x0, const double *lp0,
                                                  const double *g0, const double *h0,
-                                                 int64_t *n_accept, double *samples) {
+                                                 int64_t *n_accept, double *samples,
+                                                 const int32_t *status, int64_t *n_invalid) {
   __shared__ double red[256];
   __shared__ int acc_s;
   const int c = blockIdx.x;
@@ -125,6 +132,7 @@ __global__ __launch_bounds__(256) void k_hmc_end(int d, double eps, const double
   }
   kin = block_sum256(kin, red);
   if (threadIdx.x == 0) {
+    if (n_invalid && status[c] != 0) n_invalid[c] += 1;
     const double H1 = -logp[c] + kin;
     uint32_t ctr[4] = {0u, (uint32_t)c, j, 1u};
     philox10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -164,10 +172,11 @@ hipError_t launch_hmc_begin(const pt::Dev &D, int d, double eps, const double *i
 }
 
 hipError_t launch_hmc_kick_drift(int n_chains, int d, double eps, const double *inv_mass,
-                                 double *x, double *p, const double *grad, hipStream_t s) {
+                                 double *x, double *p, const double *grad, const int32_t *status,
+                                 int64_t *n_invalid, hipStream_t s) {
   const size_t n = (size_t)n_chains * d;
   hipLaunchKernelGGL(k_hmc_kick_drift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, d,
-                     eps, inv_mass, x, p, grad);
+                     eps, inv_mass, x, p, grad, status, n_invalid);
   return hipGetLastError();
 }
 
@@ -175,9 +184,10 @@ hipError_t launch_hmc_end(int n_chains, int d, double eps, const double *inv_mas
                           const uint64_t *traj, uint64_t traj0, double *x, double *logp,
                           double *grad, double *p, const double *x0, const double *lp0,
                           const double *g0, const double *h0, int64_t *n_accept, double *samples,
-                          hipStream_t s) {
+                          const int32_t *status, int64_t *n_invalid, hipStream_t s) {
   hipLaunchKernelGGL(k_hmc_end, dim3(n_chains), dim3(256), 0, s, d, eps, inv_mass, seed, traj,
-                     traj0, n_chains, x, logp, grad, p, x0, lp0, g0, h0, n_accept, samples);
+                     traj0, n_chains, x, logp, grad, p, x0, lp0, g0, h0, n_accept, samples, status,
+                     n_invalid);
   return hipGetLastError();
 }
 

@@ -48,18 +48,37 @@ __device__ T block_sum(T v, T *red) {
 __device__ inline bool block_all(bool v, int *ired) { return block_sum<int>(v ? 0 : 1, ired) == 0; }
 
 // ---------------------------------------------------------------------------
-// Forward: grid (kmax, c_pad), block 256.
+// Forward: 1-D grid of kmax * c_pad (frequency, chain) blocks followed by
+// n_prep white-noise preparation blocks, block 256.
 // LDS (dense frequencies): A [n][ns] row-major (ns = n | 1), z [2][n], diag [n].
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_spec_fwd(Dev D, const double *__restrict__ x) {
   extern __shared__ double lds[];
   __shared__ double red[256];
   __shared__ int ired[256];
-  const int k0 = blockIdx.x;           // frequency index, harmonic k = k0 + 1
-  const int c = blockIdx.y;            // chain (padded)
   const int tid = threadIdx.x;
   const int n = D.n_psr;
   const int kmax = max(D.ka, D.nf_dm);
+  const int nspec = kmax * D.c_pad;
+  if ((int)blockIdx.x >= nspec) {
+    // Heteroscedastic white noise (Eq. WN_cov): N_i = (EFAC sigma_i)^2 + EQUAD^2,
+    // its reciprocal per TOA and a fixed-partition partial sum of ln N_i.
+    const int pb = blockIdx.x - nspec;
+    const int i0 = pb * pt::kPrepToas, i1 = min(D.n_toa, i0 + pt::kPrepToas);
+    double s = 0.0;
+    for (int i = i0 + tid; i < i1; i += 256) {
+      const int be = D.backend[i];
+      const double es = D.efac[be] * D.sigma[i], eq = D.equad[be];
+      const double N = es * es + eq * eq;
+      D.invn[i] = 1.0 / N;
+      s += log(N);
+    }
+    s = block_sum(s, red);
+    if (tid == 0) D.lnn_blk[pb] = s;
+    return;
+  }
+  const int k0 = blockIdx.x % kmax;    // frequency index, harmonic k = k0 + 1
+  const int c = blockIdx.x / kmax;     // chain (padded)
   const double f = (k0 + 1) / D.tspan;
   const bool real = c < D.n_chains;
   const double *xc = x + (size_t)(real ? c : 0) * D.d;
@@ -509,9 +528,10 @@ hipError_t set_spec_lds_limits(size_t fwd_bytes, size_t bwd_bytes) {
 
 hipError_t launch_spec_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
   const int kmax = max(D.ka, D.nf_dm);
-  if (kmax == 0 || D.c_pad == 0) return hipSuccess;
+  const int nblk = kmax * D.c_pad + D.n_prep;
+  if (nblk == 0) return hipSuccess;
   const size_t lds = D.nf_gw > 0 ? spec_fwd_lds(D.n_psr) : 0;
-  hipLaunchKernelGGL(k_spec_fwd, dim3(kmax, D.c_pad), dim3(256), lds, s, D, x);
+  hipLaunchKernelGGL(k_spec_fwd, dim3(nblk), dim3(256), lds, s, D, x);
   return hipGetLastError();
 }
 

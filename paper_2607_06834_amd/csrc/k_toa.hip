@@ -40,6 +40,9 @@ __device__ inline int xcd_remap(int b, int G) {
 
 // ---------------------------------------------------------------------------
 // Batched MFMA TOA pass.  grid = n_chunks * n_cb, block = 64 * WPB.
+// Per-TOA inputs (padded by kToaPad so the one-tile-ahead prefetch never
+// leaves the arrays): sin/cos of 2 pi t / T, tau, DM weight w, residual dt,
+// and the per-call 1/N.
 // ---------------------------------------------------------------------------
 template <int JTR, int JTD, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
   constexpr int ROWS = 16 * JTR;
   constexpr int FS = ROWS + 1;                 // padded LDS row stride (doubles)
   __shared__ double ftab[WPB][16 * FS];
-  __shared__ double ttab[WPB][16 * 4];
+  __shared__ double cred[WPB][16];
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, q = lane >> 4;
@@ -79,55 +82,68 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
   for (int t = 0; t < JTR; ++t) ar[t] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int t = 0; t < (JTD > 0 ? JTD : 1); ++t) ad[t] = v4d{0.0, 0.0, 0.0, 0.0};
-  double chi = 0.0, lnn = 0.0;
-  const double tc = D.tau_c[p], tsi = D.tau_sinv[p];
-  const double wfac = pt::kTwoPi / D.tspan;
+  double chi = 0.0;
   double *ft = ftab[wv];
-  double *tt = ttab[wv];
+  const double *__restrict__ sth = D.sth;
+  const double *__restrict__ cth = D.cth;
+  const double *__restrict__ tau = D.tau;
+  const double *__restrict__ dtp = D.dt;
+  const double *__restrict__ ivn = D.invn;
+  const double *__restrict__ wdm = D.wdm;
 
-  for (int base = tb + 16 * wv; base < te; base += 16 * WPB) {
-    // ---- forward layout: lane (col, q) -> TOA base + col, slots 4s + q
-    const int i = base + col;
-    const bool ok = i < te;
-    const double ti = ok ? D.t[i] : 0.0;
-    if (q == 0) {
-      double dtv = 0.0, invn = 0.0, w = 0.0;
-      if (ok) {
-        const int be = D.backend[i];
-        const double es = D.efac[be] * D.sigma[i], eq = D.equad[be];
-        const double N = es * es + eq * eq;
-        const double nu = D.nu[i];
-        dtv = D.dt[i];
-        invn = 1.0 / N;
-        w = D.dm_scale / (nu * nu);
-        if (cb == 0) lnn += log(N);
-      }
-      tt[col * 4 + 0] = dtv;
-      tt[col * 4 + 1] = invn;
-      tt[col * 4 + 2] = w;
+  // one tile ahead: forward-layout (sin, cos, tau) of TOA base + col and
+  // output-layout (dt, 1/N, w) of TOAs base + q + 4v
+  int base = tb + 16 * wv;
+  double ps = sth[base + col], pc = cth[base + col], pt = tau[base + col];
+  double pdt[4], piv[4], pw[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    pdt[v] = dtp[base + q + 4 * v];
+    piv[v] = ivn[base + q + 4 * v];
+    pw[v] = wdm[base + q + 4 * v];
+  }
+
+  for (; base < te; base += 16 * WPB) {
+    const double s1 = ps, c1 = pc, tv = pt;
+    double cdt[4], civ[4], cw[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      cdt[v] = pdt[v];
+      civ[v] = (base + q + 4 * v < te) ? piv[v] : 0.0;   // rows past the chunk contribute nothing
+      cw[v] = pw[v];
     }
-    double s1, c1;
-    sincos(wfac * ti, &s1, &c1);
+    {
+      const int nb = base + 16 * WPB;
+      ps = sth[nb + col];
+      pc = cth[nb + col];
+      pt = tau[nb + col];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        pdt[v] = dtp[nb + q + 4 * v];
+        piv[v] = ivn[nb + q + 4 * v];
+        pw[v] = wdm[nb + q + 4 * v];
+      }
+    }
+    // ---- forward layout: lane (col, q) walks harmonics q+1, q+5, ... of TOA base + col
     const double s2 = 2.0 * s1 * c1, c2 = (c1 - s1) * (c1 + s1);
     const double s3 = s2 * c1 + c2 * s1, c3 = c2 * c1 - s2 * s1;
     const double s4 = 2.0 * s2 * c2, c4 = (c2 - s2) * (c2 + s2);
     double sh = q == 0 ? s1 : (q == 1 ? s2 : (q == 2 ? s3 : s4));
     double ch = q == 0 ? c1 : (q == 1 ? c2 : (q == 2 ? c3 : c4));
-    const double tau = (ti - tc) * tsi;
     double fv[NSR];
 #pragma unroll
     for (int m = 0; m < NSR / 2; ++m) {
-      const int h = 4 * m + q;
       double fa, fb;
-      if (h < kb) {
+      if (4 * m + 3 < kb) {            // every lane group on a harmonic (uniform branch)
         fa = sh;
         fb = ch;
-      } else {
-        const int t2 = 2 * (h - kb);
-        fa = tm_value(t2, tau);
-        fb = tm_value(t2 + 1, tau);
+      } else {                         // harmonic, timing-model column (1, tau, tau^2) or zero
+        const int h = 4 * m + q;
+        const double ta = (h == kb) ? 1.0 : ((h == kb + 1) ? tv * tv : 0.0);
+        const double tb2 = (h == kb) ? tv : 0.0;
+        fa = (h < kb) ? sh : ta;
+        fb = (h < kb) ? ch : tb2;
       }
-      if (!ok) { fa = 0.0; fb = 0.0; }
       fv[2 * m] = fa;
       fv[2 * m + 1] = fb;
       ft[col * FS + 8 * m + q] = fa;
@@ -150,13 +166,11 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
     double gr[4], gd[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int j = q + 4 * v;
-      const double dtv = tt[j * 4 + 0], invn = tt[j * 4 + 1], w = tt[j * 4 + 2];
-      const double r = dtv - rr[v] - w * rd[v];
-      const double g = r * invn;
+      const double r = cdt[v] - rr[v] - cw[v] * rd[v];
+      const double g = r * civ[v];
       chi += r * g;
       gr[v] = g;
-      gd[v] = w * g;
+      gd[v] = cw[v] * g;
     }
     // ---- adjoint contraction: Abar += F^T G, Abar_dm += F^T (w G)
 #pragma unroll
@@ -171,10 +185,9 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
     wave_sync();
   }
 
-  // ---- per-wave partial sums over q and lanes (fixed order)
+  // ---- per-wave chi^2 over the four lane groups (fixed order)
   chi += __shfl_xor(chi, 16, 64);
   chi += __shfl_xor(chi, 32, 64);
-  for (int o = 1; o < 64; o <<= 1) lnn += __shfl_xor(lnn, o, 64);
 
   // ---- combine the waves of the block in LDS, then one partial per block
   double *pr = D.part_rn + (size_t)wg * D.rows_rn * 16;
@@ -189,15 +202,13 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) pd[(16 * t + q + 4 * v) * 16 + col] = ad[t][v];
     if (q == 0) D.part_chi[(size_t)wg * 16 + col] = chi;
-    if (lane == 0) D.part_lnn[wg] = lnn;
   } else {
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < JTR; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) ftab[wv][(16 * t + q + 4 * v) * 16 + col] = ar[t][v];
-    if (q == 0) ttab[wv][col] = chi;
-    if (lane == 0) ttab[wv][16] = lnn;
+    if (q == 0) cred[wv][col] = chi;
     __syncthreads();
     if (wv == 0) {
       for (int e = lane; e < ROWS * 16; e += 64) {
@@ -207,16 +218,10 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
         pr[e] = s;
       }
       if (lane < 16) {
-        double s = ttab[0][lane];
+        double s = cred[0][lane];
 #pragma unroll
-        for (int w = 1; w < WPB; ++w) s += ttab[w][lane];
+        for (int w = 1; w < WPB; ++w) s += cred[w][lane];
         D.part_chi[(size_t)wg * 16 + lane] = s;
-      }
-      if (lane == 0) {
-        double s = ttab[0][16];
-#pragma unroll
-        for (int w = 1; w < WPB; ++w) s += ttab[w][16];
-        D.part_lnn[wg] = s;
       }
     }
     if constexpr (JTD > 0) {
@@ -268,14 +273,13 @@ __global__ __launch_bounds__(64) void k_toa_plain(Dev D, int p) {
   const double wfac = pt::kTwoPi / D.tspan;
   const int kb = D.kb, kdm = D.nf_dm;
   const int t0 = pt::tm_row(0, kb), t1 = pt::tm_row(1, kb), t2 = pt::tm_row(2, kb);
-  double chi = 0.0, lnn = 0.0;
+  double chi = 0.0;
   for (int i = tb; i < te; ++i) {
     const double t = D.t[i];
     const int be = D.backend[i];
     const double es = D.efac[be] * D.sigma[i], eq = D.equad[be];
     const double N = es * es + eq * eq;
     const double w = D.dm_scale / (D.nu[i] * D.nu[i]);
-    lnn += log(N);
     double s1, c1;
     sincos(wfac * t, &s1, &c1);
     const double tau = (t - tc) * tsi;
@@ -318,7 +322,19 @@ __global__ __launch_bounds__(64) void k_toa_plain(Dev D, int p) {
   for (int r = 0; r < nr; ++r) D.part_rn[(wg * nr + r) * 16 + col] = ab[r * 64 + lane];
   for (int r = 0; r < nd; ++r) D.part_dm[(wg * nd + r) * 16 + col] = abd[r * 64 + lane];
   D.part_chi[wg * 16 + col] = chi;
-  if (chain == 0) D.part_lnn[(size_t)chunk * D.n_cb] = lnn;
+}
+
+// Sum of n strided values in index order, eight loads in flight at a time.
+__device__ inline double sum_chunks(const double *src, size_t stride, int n) {
+  double s = 0.0;
+  for (int c0 = 0; c0 < n; c0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = (c0 + k < n) ? src[(size_t)(c0 + k) * stride] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k];
+  }
+  return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -334,41 +350,18 @@ __global__ __launch_bounds__(256) void k_reduce(Dev D) {
   const int e = blockIdx.z * 256 + threadIdx.x;
   if (e < (nr + nd) * 16) {
     const int row = e >> 4, col = e & 15;
-    double s0 = 0.0, s1 = 0.0;
     if (row < nr) {
       const double *src = D.part_rn + ((size_t)c0 * ncb + cb) * nr * 16 + e;
-      const size_t stride = ncb * nr * 16;
-      int ch = c0;
-      for (; ch + 1 < c1; ch += 2) {
-        s0 += src[0];
-        s1 += src[stride];
-        src += 2 * stride;
-      }
-      if (ch < c1) s0 += src[0];
-      D.bar_rn[((size_t)p * nr + row) * cp + cb * 16 + col] = s0 + s1;
+      D.bar_rn[((size_t)p * nr + row) * cp + cb * 16 + col] = sum_chunks(src, ncb * nr * 16, c1 - c0);
     } else {
       const int e2 = e - nr * 16, r2 = row - nr;
       const double *src = D.part_dm + ((size_t)c0 * ncb + cb) * nd * 16 + e2;
-      const size_t stride = ncb * nd * 16;
-      int ch = c0;
-      for (; ch + 1 < c1; ch += 2) {
-        s0 += src[0];
-        s1 += src[stride];
-        src += 2 * stride;
-      }
-      if (ch < c1) s0 += src[0];
-      D.bar_dm[((size_t)p * nd + r2) * cp + cb * 16 + col] = s0 + s1;
+      D.bar_dm[((size_t)p * nd + r2) * cp + cb * 16 + col] = sum_chunks(src, ncb * nd * 16, c1 - c0);
     }
   }
   if (blockIdx.z == 0 && threadIdx.x < 16) {
-    double s = 0.0;
-    for (int ch = c0; ch < c1; ++ch) s += D.part_chi[((size_t)ch * ncb + cb) * 16 + threadIdx.x];
-    D.chi_p[(size_t)p * cp + cb * 16 + threadIdx.x] = s;
-  }
-  if (blockIdx.z == 0 && cb == 0 && threadIdx.x == 32) {
-    double s = 0.0;
-    for (int ch = c0; ch < c1; ++ch) s += D.part_lnn[(size_t)ch * ncb];
-    D.lnn_p[p] = s;
+    D.chi_p[(size_t)p * cp + cb * 16 + threadIdx.x] =
+        sum_chunks(D.part_chi + ((size_t)c0 * ncb + cb) * 16 + threadIdx.x, ncb * 16, c1 - c0);
   }
 }
 

@@ -34,7 +34,7 @@ struct ptafs_dataset {
   struct GraphKey {
     int n_chains, n_leapfrog;
     double eps;
-    const void *inv_mass, *x, *logp, *grad, *acc, *samples;
+    const void *inv_mass, *x, *logp, *grad, *acc, *samples, *invalid;
     uint64_t seed, traj0;
     int tiles, wpb, xcd;
     void *ws, *hmc;
@@ -52,9 +52,11 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+int n_prep_of(int n_toa) { return (n_toa + pt::kPrepToas - 1) / pt::kPrepToas; }
+
 struct WsLayout {
-  size_t coef_rn, coef_dm, lstore, part_rn, part_dm, part_chi, part_lnn, part_cw, bar_rn, bar_dm,
-      chi_p, lnn_p, cw_p, dth_k, drn_k, ddm_k, zsq_k, flag_k, st_pre, total;
+  size_t coef_rn, coef_dm, lstore, part_rn, part_dm, part_chi, part_cw, invn, lnn_blk, bar_rn,
+      bar_dm, chi_p, cw_p, dth_k, drn_k, ddm_k, zsq_k, flag_k, st_pre, total;
 };
 
 WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
@@ -74,12 +76,12 @@ WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
   L.part_rn = take(nwg * B.rows_rn * 16 * D8);
   L.part_dm = take(nwg * B.rows_dm * 16 * D8);
   L.part_chi = take(nwg * 16 * D8);
-  L.part_lnn = take(nwg * D8);
   L.part_cw = take(nwg * 8 * 16 * D8);
+  L.invn = take(((size_t)B.n_toa + pt::kToaPad) * D8);
+  L.lnn_blk = take((size_t)n_prep_of(B.n_toa) * D8);
   L.bar_rn = take(n * B.rows_rn * cp * D8);
   L.bar_dm = take(n * B.rows_dm * cp * D8);
   L.chi_p = take(n * cp * D8);
-  L.lnn_p = take(n * D8);
   L.cw_p = take(n * 8 * cp * D8);
   L.dth_k = take(cp * B.ka * 2 * D8);
   L.drn_k = take(cp * B.ka * n * 2 * D8);
@@ -150,6 +152,7 @@ int ensure_ws(ptafs_dataset *ds, int n_chains) {
   ds->ws = nullptr;
   ds->ws_bytes = 0;
   if (hipMalloc(&ds->ws, L.total) != hipSuccess) return PTAFS_E_NOMEM;
+  PT_TRY(hipMemset(ds->ws, 0, L.total));   // keeps the 1/N padding at zero
   ds->ws_bytes = L.total;
   return PTAFS_OK;
 }
@@ -167,12 +170,13 @@ pt::Dev make_dev(const ptafs_dataset *ds, int n_chains) {
   D.part_rn = reinterpret_cast<double *>(w + L.part_rn);
   D.part_dm = reinterpret_cast<double *>(w + L.part_dm);
   D.part_chi = reinterpret_cast<double *>(w + L.part_chi);
-  D.part_lnn = reinterpret_cast<double *>(w + L.part_lnn);
+  D.invn = reinterpret_cast<double *>(w + L.invn);
+  D.lnn_blk = reinterpret_cast<double *>(w + L.lnn_blk);
+  D.n_prep = n_prep_of(D.n_toa);
   D.part_cw = reinterpret_cast<double *>(w + L.part_cw);
   D.bar_rn = reinterpret_cast<double *>(w + L.bar_rn);
   D.bar_dm = reinterpret_cast<double *>(w + L.bar_dm);
   D.chi_p = reinterpret_cast<double *>(w + L.chi_p);
-  D.lnn_p = reinterpret_cast<double *>(w + L.lnn_p);
   D.cw_p = reinterpret_cast<double *>(w + L.cw_p);
   D.dth_k = reinterpret_cast<double *>(w + L.dth_k);
   D.drn_k = reinterpret_cast<double *>(w + L.drn_k);
@@ -385,11 +389,27 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
       for (int j = 0; j <= i; ++j) gch[(size_t)i * (i + 1) / 2 + j] = Lf[(size_t)i * n + j];
   }
   ds->off.assign(d->toa_offsets, d->toa_offsets + n + 1);
+  // per-TOA basis phases, zero-padded for the prefetch of the TOA pass
+  const size_t npad = (size_t)ntoa + pt::kToaPad;
+  std::vector<double> vs(npad, 0.0), vc(npad, 0.0), vt(npad, 0.0), vw(npad, 0.0), vdt(npad, 0.0);
+  for (int p = 0; p < n; ++p)
+    for (int64_t i = d->toa_offsets[p]; i < d->toa_offsets[p + 1]; ++i) {
+      const double ph = pt::kTwoPi * (d->t[i] / d->tspan);
+      vs[i] = std::sin(ph);
+      vc[i] = std::cos(ph);
+      vt[i] = (d->t[i] - tc[p]) * tsi[p];
+      vw[i] = d->dm_scale / (d->nu[i] * d->nu[i]);
+      vdt[i] = d->dt[i];
+    }
 
   int rc = PTAFS_OK;
   auto chk = [&](int r) { if (r && !rc) rc = r; };
   chk(upload(ds, d->t, ntoa, &B.t));
-  chk(upload(ds, d->dt, ntoa, &B.dt));
+  chk(upload(ds, vdt.data(), npad, &B.dt));
+  chk(upload(ds, vs.data(), npad, &B.sth));
+  chk(upload(ds, vc.data(), npad, &B.cth));
+  chk(upload(ds, vt.data(), npad, &B.tau));
+  chk(upload(ds, vw.data(), npad, &B.wdm));
   chk(upload(ds, d->sigma, ntoa, &B.sigma));
   chk(upload(ds, d->nu, ntoa, &B.nu));
   chk(upload(ds, d->backend, ntoa, &B.backend));
@@ -524,8 +544,8 @@ int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, d
 
 int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n_leapfrog,
                   double eps, const double *inv_mass, uint64_t seed, uint64_t traj0, double *x,
-                  double *logp, double *grad, int64_t *n_accept, double *samples, int32_t use_graph,
-                  void *stream) {
+                  double *logp, double *grad, int64_t *n_accept, double *samples,
+                  int64_t *n_invalid, int32_t use_graph, void *stream) {
   if (!ds || n_chains < 0 || n_traj < 0 || n_leapfrog < 1 || !(eps > 0.0)) return PTAFS_E_ARG;
   if (n_chains == 0 || n_traj == 0) return PTAFS_OK;
   if (!x || !logp || !grad || !n_accept) return PTAFS_E_ARG;
@@ -573,10 +593,11 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
     for (int l = 0; l < n_leapfrog; ++l) {
       int r = enqueue_eval(ds, n_chains, x, logp, grad, st, q, false);
       if (r) return r;
-      if (l + 1 < n_leapfrog) PT_TRY(ptk::launch_hmc_kick_drift(n_chains, d, eps, inv_mass, x, p, grad, q));
+      if (l + 1 < n_leapfrog)
+        PT_TRY(ptk::launch_hmc_kick_drift(n_chains, d, eps, inv_mass, x, p, grad, st, n_invalid, q));
     }
     PT_TRY(ptk::launch_hmc_end(n_chains, d, eps, inv_mass, seed, traj, traj0, x, logp, grad, p, x0,
-                               lp0, g0, h0, n_accept, samples, q));
+                               lp0, g0, h0, n_accept, samples, st, n_invalid, q));
     PT_TRY(ptk::launch_traj_inc(traj, q));
     return PTAFS_OK;
   };
@@ -599,6 +620,7 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   key.grad = grad;
   key.acc = n_accept;
   key.samples = samples;
+  key.invalid = n_invalid;
   key.seed = seed;
   key.traj0 = traj0;
   key.tiles = ds->tiles_per_chunk;
