@@ -107,7 +107,7 @@ struct Dev {
   // workspace
   double *coef_rn, *coef_dm;   // [n_psr][rows][c_pad]
   double *lstore;              // [c_pad][nf_gw][n_psr*(n_psr+1)/2]
-  double *cwc;                 // [c_pad][n_psr][kCwConst] per chain/pulsar CW constants
+  double *cwc;                 // [n_psr][kCwConst][c_pad] per chain/pulsar CW constants
   double *part_rn, *part_dm;   // [n_wg][rows][16]
   double *part_chi, *part_cw;  // [n_wg][16], [n_wg][8][16]
   double *invn;                // [n_toa + kToaPad] per-call 1/N (zeros in the padding)
@@ -127,7 +127,7 @@ constexpr int kFlagNotPD = 1;          // phi_k not positive definite
 constexpr int kFlagInNonfinite = 2;    // a non-finite input coordinate
 constexpr int kFlagOutNonfinite = 4;   // a non-finite gradient entry
 
-constexpr int kCwConst = 10;   // F+, Fx, dF+/dcos, dFx/dcos, dF+/dphi, dFx/dphi
+constexpr int kCwConst = 16;   // rows of the per (chain, pulsar) CW constant table
 
 }  // namespace pt
 

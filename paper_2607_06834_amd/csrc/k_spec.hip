@@ -17,6 +17,7 @@
 // Both reductions are O(n^2) with prefix / suffix sums over the lower
 // triangle of P; W and M are formed with blocked triangular products.
 #include "common.h"
+#include "cw_dev.h"
 
 namespace {
 
@@ -140,6 +141,17 @@ __global__ __launch_bounds__(256) void k_spec_fwd(Dev D, const double *__restric
     }
     if (tid == 0) D.st_pre[c] = st;
     const bool zero = bad || st != 0;
+    if (D.has_cw) {
+      // CW constants per pulsar (zero delay for padding and rejected chains)
+      const double *th = (real && !zero) ? xc + D.off_cw : nullptr;
+      for (int I = tid; I < n; I += 256) {
+        double v[pt::kCwRows];
+        pt::cw_constants(th, D.pos + 3 * I, v);
+        double *dst = D.cwc + (size_t)I * pt::kCwConst * cp + c;
+#pragma unroll
+        for (int j = 0; j < pt::kCwRows; ++j) dst[(size_t)j * cp] = v[j];
+      }
+    }
     for (int idx = tid; idx < n * D.rows_rn; idx += 256) {
       const int I = idx / D.rows_rn, row = idx % D.rows_rn;
       const pt::Slot sl = pt::rn_slot(row, D.kb);

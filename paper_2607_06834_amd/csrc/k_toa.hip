@@ -3,15 +3,16 @@
 // bases of Eqs. Fourier_series / RN=Fa, F_DM = w F of Sec. III.C and the
 // timing model M = [1, tau, tau^2] of Eq. TM=Me; N of Eq. WN_cov):
 //
-//   r  = dt - F_tile . A - w (F_tile . A_dm)          (A includes M b)
+//   r  = dt - F_tile . A - w (F_tile . A_dm) - h_cw   (A includes M b)
 //   g  = r / N,  chi2 += r g,  logdet += ln N
-//   Abar += F_tile^T g,  Abar_dm += F_tile^T (w g)
+//   Abar += F_tile^T g,  Abar_dm += F_tile^T (w g),  cwbar += g dh_cw/dtheta
 //
 // The batched form runs F.A and F^T.G as FP64 MFMA 16x16x4 contractions
 // over 16-TOA x 16-chain tiles; the basis is generated in registers from one
 // sincos per TOA and an angle-addition step, and transposed through LDS for
 // the adjoint.  The plain form is a vector-ALU kernel launched per pulsar.
 #include "common.h"
+#include "cw_dev.h"
 
 namespace {
 
@@ -44,7 +45,7 @@ __device__ inline int xcd_remap(int b, int G) {
 // leaves the arrays): sin/cos of 2 pi t / T, tau, DM weight w, residual dt,
 // and the per-call 1/N.
 // ---------------------------------------------------------------------------
-template <int JTR, int JTD, int WPB>
+template <int JTR, int JTD, int WPB, bool CW>
 __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
   constexpr int NSR = 4 * JTR;
   constexpr int NSD = 4 * JTD;
@@ -52,6 +53,7 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
   constexpr int FS = ROWS + 1;                 // padded LDS row stride (doubles)
   __shared__ double ftab[WPB][16 * FS];
   __shared__ double cred[WPB][16];
+  __shared__ double cwred[CW ? WPB : 1][8][16];
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, q = lane >> 4;
@@ -83,6 +85,13 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
 #pragma unroll
   for (int t = 0; t < (JTD > 0 ? JTD : 1); ++t) ad[t] = v4d{0.0, 0.0, 0.0, 0.0};
   double chi = 0.0;
+  pt::CwLane cwl;
+  double cacc[8];
+  if constexpr (CW) {
+    cwl.load(D.cwc, cp, p, chain);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) cacc[j] = 0.0;
+  }
   double *ft = ftab[wv];
   const double *__restrict__ sth = D.sth;
   const double *__restrict__ cth = D.cth;
@@ -95,22 +104,24 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
   // output-layout (dt, 1/N, w) of TOAs base + q + 4v
   int base = tb + 16 * wv;
   double ps = sth[base + col], pc = cth[base + col], pt = tau[base + col];
-  double pdt[4], piv[4], pw[4];
+  double pdt[4], piv[4], pw[4], ptt[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     pdt[v] = dtp[base + q + 4 * v];
     piv[v] = ivn[base + q + 4 * v];
     pw[v] = wdm[base + q + 4 * v];
+    if constexpr (CW) ptt[v] = D.t[base + q + 4 * v];
   }
 
   for (; base < te; base += 16 * WPB) {
     const double s1 = ps, c1 = pc, tv = pt;
-    double cdt[4], civ[4], cw[4];
+    double cdt[4], civ[4], cw[4], ctt[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       cdt[v] = pdt[v];
       civ[v] = (base + q + 4 * v < te) ? piv[v] : 0.0;   // rows past the chunk contribute nothing
       cw[v] = pw[v];
+      ctt[v] = ptt[v];
     }
     {
       const int nb = base + 16 * WPB;
@@ -122,6 +133,7 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
         pdt[v] = dtp[nb + q + 4 * v];
         piv[v] = ivn[nb + q + 4 * v];
         pw[v] = wdm[nb + q + 4 * v];
+        if constexpr (CW) ptt[v] = D.t[nb + q + 4 * v];
       }
     }
     // ---- forward layout: lane (col, q) walks harmonics q+1, q+5, ... of TOA base + col
@@ -166,11 +178,17 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
     double gr[4], gd[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const double r = cdt[v] - rr[v] - cw[v] * rd[v];
+      double r = cdt[v] - rr[v] - cw[v] * rd[v];
+      pt::CwToa cs;
+      if constexpr (CW) {
+        cs = cwl.delay(ctt[v]);
+        r -= cs.h;
+      }
       const double g = r * civ[v];
       chi += r * g;
       gr[v] = g;
       gd[v] = cw[v] * g;
+      if constexpr (CW) cwl.adjoint(cs, g, cacc);
     }
     // ---- adjoint contraction: Abar += F^T G, Abar_dm += F^T (w G)
 #pragma unroll
@@ -188,6 +206,13 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
   // ---- per-wave chi^2 over the four lane groups (fixed order)
   chi += __shfl_xor(chi, 16, 64);
   chi += __shfl_xor(chi, 32, 64);
+  if constexpr (CW) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      cacc[j] += __shfl_xor(cacc[j], 16, 64);
+      cacc[j] += __shfl_xor(cacc[j], 32, 64);
+    }
+  }
 
   // ---- combine the waves of the block in LDS, then one partial per block
   double *pr = D.part_rn + (size_t)wg * D.rows_rn * 16;
@@ -202,6 +227,14 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) pd[(16 * t + q + 4 * v) * 16 + col] = ad[t][v];
     if (q == 0) D.part_chi[(size_t)wg * 16 + col] = chi;
+    if constexpr (CW) {
+      if (q == 0) {
+        double o[8];
+        pt::cw_finish(D.cwc, cp, p, chain, cacc, o);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) D.part_cw[((size_t)wg * 8 + j) * 16 + col] = o[j];
+      }
+    }
   } else {
     __syncthreads();
 #pragma unroll
@@ -209,6 +242,12 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) ftab[wv][(16 * t + q + 4 * v) * 16 + col] = ar[t][v];
     if (q == 0) cred[wv][col] = chi;
+    if constexpr (CW) {
+      if (q == 0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) cwred[wv][j][col] = cacc[j];
+      }
+    }
     __syncthreads();
     if (wv == 0) {
       for (int e = lane; e < ROWS * 16; e += 64) {
@@ -222,6 +261,18 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
 #pragma unroll
         for (int w = 1; w < WPB; ++w) s += cred[w][lane];
         D.part_chi[(size_t)wg * 16 + lane] = s;
+        if constexpr (CW) {
+          double a[8], o[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            a[j] = cwred[0][j][lane];
+#pragma unroll
+            for (int w = 1; w < WPB; ++w) a[j] += cwred[w][j][lane];
+          }
+          pt::cw_finish(D.cwc, cp, p, cb * 16 + lane, a, o);
+#pragma unroll
+          for (int j = 0; j < 8; ++j) D.part_cw[((size_t)wg * 8 + j) * 16 + lane] = o[j];
+        }
       }
     }
     if constexpr (JTD > 0) {
@@ -274,6 +325,11 @@ __global__ __launch_bounds__(64) void k_toa_plain(Dev D, int p) {
   const int kb = D.kb, kdm = D.nf_dm;
   const int t0 = pt::tm_row(0, kb), t1 = pt::tm_row(1, kb), t2 = pt::tm_row(2, kb);
   double chi = 0.0;
+  const bool cwon = D.has_cw && real;
+  pt::CwLane cwl;
+  double cacc[8];
+  for (int j = 0; j < 8; ++j) cacc[j] = 0.0;
+  if (cwon) cwl.load(D.cwc, cp, p, chain);
   for (int i = tb; i < te; ++i) {
     const double t = D.t[i];
     const int be = D.backend[i];
@@ -294,10 +350,16 @@ __global__ __launch_bounds__(64) void k_toa_plain(Dev D, int p) {
       ck = ck * c1 - sk * s1;
       sk = sn;
     }
-    const double r = D.dt[i] - R - w * Rd;
+    double r = D.dt[i] - R - w * Rd;
+    pt::CwToa cs;
+    if (cwon) {
+      cs = cwl.delay(t);
+      r -= cs.h;
+    }
     const double g = r / N;
     const double wg = w * g;
     chi += r * g;
+    if (cwon) cwl.adjoint(cs, g, cacc);
     sk = s1;
     ck = c1;
     for (int k = 1; k <= kb; ++k) {
@@ -322,6 +384,11 @@ __global__ __launch_bounds__(64) void k_toa_plain(Dev D, int p) {
   for (int r = 0; r < nr; ++r) D.part_rn[(wg * nr + r) * 16 + col] = ab[r * 64 + lane];
   for (int r = 0; r < nd; ++r) D.part_dm[(wg * nd + r) * 16 + col] = abd[r * 64 + lane];
   D.part_chi[wg * 16 + col] = chi;
+  if (cwon) {
+    double o[8];
+    pt::cw_finish(D.cwc, cp, p, chain, cacc, o);
+    for (int j = 0; j < 8; ++j) D.part_cw[(wg * 8 + j) * 16 + col] = o[j];
+  }
 }
 
 // Sum of n strided values in index order, eight loads in flight at a time.
@@ -348,9 +415,14 @@ __global__ __launch_bounds__(256) void k_reduce(Dev D) {
   const size_t cp = D.c_pad;
   const size_t ncb = D.n_cb;
   const int e = blockIdx.z * 256 + threadIdx.x;
-  if (e < (nr + nd) * 16) {
+  const int ncw = D.has_cw ? 8 : 0;
+  if (e < (nr + nd + ncw) * 16) {
     const int row = e >> 4, col = e & 15;
-    if (row < nr) {
+    if (row >= nr + nd) {
+      const int e3 = e - (nr + nd) * 16, j = row - nr - nd;
+      const double *src = D.part_cw + ((size_t)c0 * ncb + cb) * 8 * 16 + e3;
+      D.cw_p[((size_t)p * 8 + j) * cp + cb * 16 + col] = sum_chunks(src, ncb * 8 * 16, c1 - c0);
+    } else if (row < nr) {
       const double *src = D.part_rn + ((size_t)c0 * ncb + cb) * nr * 16 + e;
       D.bar_rn[((size_t)p * nr + row) * cp + cb * 16 + col] = sum_chunks(src, ncb * nr * 16, c1 - c0);
     } else {
@@ -368,7 +440,10 @@ __global__ __launch_bounds__(256) void k_reduce(Dev D) {
 template <int JTR, int JTD, int WPB>
 hipError_t launch_mfma_t(const Dev &D, int xcd, hipStream_t s) {
   const int grid = D.n_chunks * D.n_cb;
-  hipLaunchKernelGGL((k_toa_mfma<JTR, JTD, WPB>), dim3(grid), dim3(64 * WPB), 0, s, D, xcd);
+  if (D.has_cw)
+    hipLaunchKernelGGL((k_toa_mfma<JTR, JTD, WPB, true>), dim3(grid), dim3(64 * WPB), 0, s, D, xcd);
+  else
+    hipLaunchKernelGGL((k_toa_mfma<JTR, JTD, WPB, false>), dim3(grid), dim3(64 * WPB), 0, s, D, xcd);
   return hipGetLastError();
 }
 
@@ -418,7 +493,7 @@ hipError_t launch_toa_plain_psr(const pt::Dev &D, int p, int n_chunks_p, hipStre
 
 hipError_t launch_reduce_chunks(const pt::Dev &D, hipStream_t s) {
   if (D.n_psr == 0 || D.n_cb == 0) return hipSuccess;
-  const int nz = ((D.rows_rn + D.rows_dm) * 16 + 255) / 256;
+  const int nz = ((D.rows_rn + D.rows_dm + (D.has_cw ? 8 : 0)) * 16 + 255) / 256;
   hipLaunchKernelGGL(k_reduce, dim3(D.n_psr, D.n_cb, nz), dim3(256), 0, s, D);
   return hipGetLastError();
 }

@@ -55,7 +55,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 int n_prep_of(int n_toa) { return (n_toa + pt::kPrepToas - 1) / pt::kPrepToas; }
 
 struct WsLayout {
-  size_t coef_rn, coef_dm, lstore, part_rn, part_dm, part_chi, part_cw, invn, lnn_blk, bar_rn,
+  size_t coef_rn, coef_dm, lstore, cwc, part_rn, part_dm, part_chi, part_cw, invn, lnn_blk, bar_rn,
       bar_dm, chi_p, cw_p, dth_k, drn_k, ddm_k, zsq_k, flag_k, st_pre, total;
 };
 
@@ -73,6 +73,7 @@ WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
   L.coef_rn = take(n * B.rows_rn * cp * D8);
   L.coef_dm = take(n * B.rows_dm * cp * D8);
   L.lstore = take(cp * B.nf_gw * (n * (n + 1) / 2) * D8);
+  L.cwc = take(B.has_cw ? n * pt::kCwConst * cp * D8 : 0);
   L.part_rn = take(nwg * B.rows_rn * 16 * D8);
   L.part_dm = take(nwg * B.rows_dm * 16 * D8);
   L.part_chi = take(nwg * 16 * D8);
@@ -167,6 +168,7 @@ pt::Dev make_dev(const ptafs_dataset *ds, int n_chains) {
   D.coef_rn = reinterpret_cast<double *>(w + L.coef_rn);
   D.coef_dm = reinterpret_cast<double *>(w + L.coef_dm);
   D.lstore = reinterpret_cast<double *>(w + L.lstore);
+  D.cwc = reinterpret_cast<double *>(w + L.cwc);
   D.part_rn = reinterpret_cast<double *>(w + L.part_rn);
   D.part_dm = reinterpret_cast<double *>(w + L.part_dm);
   D.part_chi = reinterpret_cast<double *>(w + L.part_chi);
@@ -391,7 +393,8 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
   ds->off.assign(d->toa_offsets, d->toa_offsets + n + 1);
   // per-TOA basis phases, zero-padded for the prefetch of the TOA pass
   const size_t npad = (size_t)ntoa + pt::kToaPad;
-  std::vector<double> vs(npad, 0.0), vc(npad, 0.0), vt(npad, 0.0), vw(npad, 0.0), vdt(npad, 0.0);
+  std::vector<double> vs(npad, 0.0), vc(npad, 0.0), vt(npad, 0.0), vw(npad, 0.0), vdt(npad, 0.0),
+      vtt(npad, 0.0);
   for (int p = 0; p < n; ++p)
     for (int64_t i = d->toa_offsets[p]; i < d->toa_offsets[p + 1]; ++i) {
       const double ph = pt::kTwoPi * (d->t[i] / d->tspan);
@@ -400,11 +403,12 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
       vt[i] = (d->t[i] - tc[p]) * tsi[p];
       vw[i] = d->dm_scale / (d->nu[i] * d->nu[i]);
       vdt[i] = d->dt[i];
+      vtt[i] = d->t[i];
     }
 
   int rc = PTAFS_OK;
   auto chk = [&](int r) { if (r && !rc) rc = r; };
-  chk(upload(ds, d->t, ntoa, &B.t));
+  chk(upload(ds, vtt.data(), npad, &B.t));
   chk(upload(ds, vdt.data(), npad, &B.dt));
   chk(upload(ds, vs.data(), npad, &B.sth));
   chk(upload(ds, vc.data(), npad, &B.cth));

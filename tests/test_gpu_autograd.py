@@ -1,0 +1,104 @@
+"""The hand-written adjoint behind torch.autograd (LogPosterior) against
+finite differences of the library's own log p, and its composition with
+other autograd operations."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import model
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_06834_amd import api as a
+    return a
+
+
+CW = (0.3, 1.0, 9.3, -7.8, 1.0, 0.5, 0.7, -13.5)
+
+
+def tiny_ds():
+    return synth.make_array(12, 3, [25, 30, 35], 8 * synth.YEAR_S, backends_per_psr=[1, 2, 1],
+                            nu_range=(0.4e9, 2e9), nf_rn=3, nf_gw=3, nf_dm=2, has_cw=True)
+
+
+def points(ds, n, seed):
+    th = synth.injected_theta(ds, seed, rn=(-14.0, 3.5), dm=(-14.0, 3.5), cw=CW)
+    return synth.random_points(ds, n, seed + 1, theta=th, theta_jitter=0.2)
+
+
+def test_gradcheck_tiny(api):
+    """torch.autograd.gradcheck in FP64 on 2 chains of a 3-pulsar array with
+    red noise, DM, the HD common process and a CW."""
+    ds = tiny_ds()
+    g = api.Dataset(ds)
+    x = torch.tensor(points(ds, 2, 3), device="cuda", requires_grad=True)
+
+    def f(xx):
+        lp, st = api.LogPosterior.apply(xx, g)
+        return lp
+
+    assert torch.autograd.gradcheck(f, (x,), eps=1e-6, atol=1e-4, rtol=1e-5, nondet_tol=0.0)
+    g.close()
+
+
+def test_backward_composes(api):
+    """A weighted sum of log p through autograd gives the weighted gradient."""
+    ds = tiny_ds()
+    g = api.Dataset(ds)
+    X = points(ds, 5, 4)
+    x = torch.tensor(X, device="cuda", requires_grad=True)
+    w = torch.linspace(0.5, 2.0, 5, dtype=torch.float64, device="cuda")
+    lp, st = api.LogPosterior.apply(x, g)
+    (w * lp).sum().backward()
+    lp2, gr2, st2 = g.ptafs_logp_grad(torch.tensor(X, device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.equal(lp.detach(), lp2)
+    assert torch.equal(x.grad, w[:, None] * gr2)
+    ref = model.logp_grad(model.Prepared(ds), X)
+    tol = 1e-7 * np.maximum(np.abs(ref["grad"]), ref["scale"])
+    assert np.all(np.abs(gr2.cpu().numpy() - ref["grad"]) <= tol)
+    g.close()
+
+
+def test_finite_differences_cfg3(api):
+    """Every hyper-parameter (red noise, common process, CW) and a sample of
+    coefficients of the 3-pulsar CW array: the autograd gradient against a
+    Richardson-extrapolated central difference of the library's log p."""
+    ds = synth.cfg3()
+    g = api.Dataset(ds)
+    lay = model.Prepared(ds).lay
+    X = points(ds, 1, 9)[0]
+    x = torch.tensor(X[None], device="cuda", requires_grad=True)
+    lp, st = api.LogPosterior.apply(x, g)
+    lp.sum().backward()
+    grad = x.grad[0].cpu().numpy()
+    assert int(st[0]) == 0
+    rng = np.random.default_rng(2)
+    idx = list(range(lay.n_theta)) + list(rng.choice(np.arange(lay.u, lay.d), 24, replace=False))
+    H = 1e-3
+    # all shifted points evaluated in one batch
+    rows = []
+    for j in idx:
+        for s in (H, -H, H / 2, -H / 2):
+            v = X.copy()
+            v[j] += s
+            rows.append(v)
+    with torch.no_grad():
+        lpb, _, stb = g.ptafs_logp_grad(torch.tensor(np.array(rows), device="cuda"))
+    assert torch.all(stb == 0)
+    lpb = lpb.cpu().numpy().reshape(len(idx), 4)
+    d1 = (lpb[:, 0] - lpb[:, 1]) / (2 * H)
+    d2 = (lpb[:, 2] - lpb[:, 3]) / H
+    fd = (4.0 * d2 - d1) / 3.0
+    an = grad[idx]
+    err = np.abs(fd - an)
+    tol = 1e-5 * np.abs(an) + 1e-12 * np.abs(lp.item()) / H
+    assert np.all(err <= tol), (np.array(idx)[err > tol], fd[err > tol], an[err > tol])
+    g.close()

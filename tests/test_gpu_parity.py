@@ -102,6 +102,53 @@ def test_edge_shapes(api, name):
     check(ds, X, run(api, ds, X, plain=True), ref=ref)
 
 
+CW_NEAR = (0.3, 1.0, 9.3, -7.8, 1.0, 0.5, 0.7, -13.5)   # y(T) ~ 2e-3, delay ~ 0.3 us
+
+
+def cw_points(ds, n, seed, jitter=0.2):
+    th = synth.injected_theta(ds, seed, rn=(-14.0, 3.5), dm=(-14.0, 3.5), cw=CW_NEAR)
+    return synth.random_points(ds, n, seed + 1, theta=th, theta_jitter=jitter)
+
+
+def cfg3_wide():
+    """cfg3 with the chirp-mass and frequency ranges widened by one decade
+    upwards, so that part of the box coalesces within the data span."""
+    ds = synth.cfg3()
+    lay = model.Prepared(ds).lay
+    ds["prior_hi"] = ds["prior_hi"].copy()
+    ds["prior_hi"][lay.cw + 2] += 1.0
+    ds["prior_hi"][lay.cw + 3] += 1.0
+    return ds
+
+
+def test_cfg3_cw_random_points(api):
+    """3 pulsars x 500 TOAs with a CW: 100 points uniform in the (widened)
+    prior box, part of which coalesces inside the span (status 3), plus 40
+    near an injection."""
+    ds = cfg3_wide()
+    X = np.concatenate([synth.random_points(ds, 100, 301), cw_points(ds, 40, 302)])
+    ref = check(ds, X, run(api, ds, X))
+    assert (ref["status"] == 3).sum() >= 10 and (ref["status"] == 0).sum() >= 40
+    check(ds, X, run(api, ds, X, plain=True), ref=ref)
+
+
+@pytest.mark.parametrize("name", ["single_toa_and_tile_edges", "max_harmonics", "one_pulsar"])
+def test_cw_edge_shapes(api, name):
+    counts, nb, kr, kg, kd = EDGE[name]
+    ds = synth.make_array(33, len(counts), counts, 9 * synth.YEAR_S, backends_per_psr=nb,
+                          nu_range=(0.4e9, 2e9), nf_rn=kr, nf_gw=kg, nf_dm=kd, has_cw=True)
+    X = cw_points(ds, 17, 6)
+    ref = check(ds, X, run(api, ds, X))
+    check(ds, X, run(api, ds, X, plain=True), ref=ref)
+
+
+@pytest.mark.parametrize("tuning", [(1, 2, 0), (5, 4, 1)])
+def test_cw_tunings(api, tuning):
+    ds = synth.cfg3()
+    X = cw_points(ds, 33, 7)
+    check(ds, X, run(api, ds, X, tuning=tuning))
+
+
 def test_many_pulsars_max(api):
     """128 pulsars (the implementation limit), short data."""
     n = 128
