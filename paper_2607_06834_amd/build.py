@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libptafs.so")
-SOURCES = ["ptafs_api.hip", "k_spec.hip", "k_toa.hip", "k_finalize.hip", "k_hmc.hip"]
+SOURCES = ["ptafs_api.hip", "k_spec.hip", "k_chol.hip", "k_cholt.hip", "k_toa.hip", "k_finalize.hip", "k_hmc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -20,6 +20,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # keep MFMA accumulators in ordinary VGPRs (no AGPR <-> VGPR copies in loops)
     "-mllvm", "-amdgpu-mfma-vgpr-form=1",
+    # the per-frequency kernels keep a pulsar row in registers: their loops
+    # over the row must unroll completely whatever their size
+    "-mllvm", "-pragma-unroll-threshold=200000",
     "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function",
 ]
 

@@ -74,6 +74,26 @@ __host__ __device__ inline int tiles_for_pairs(int pairs) {
   return (steps + 3) / 4;
 }
 
+// Power-law spectrum A^2/(12 pi^2) yr^3 (f yr)^-gamma / T (Sec. IV.A, Eq.
+// power_law with yr^3), evaluated in logarithms.
+__device__ inline double powerlaw(double f, double log10A, double gamma, double tspan) {
+  const double c = 3.0 * log(kYear) - log(12.0 * kPi * kPi) - log(tspan);
+  return exp(2.0 * kLn10 * log10A - gamma * log(f * kYear) + c);
+}
+
+// Packed lower-triangular storage, row-major: row i holds columns 0..i.
+__host__ __device__ inline int pk(int i, int j) { return (i * (i + 1)) / 2 + j; }
+
+// Dense per-frequency factors: up to kTileMaxNT 16-row tiles they are kept
+// tile-major (the lower tiles of the padded matrix, 256 doubles each, row-major
+// inside a tile); beyond that packed row-major.
+constexpr int kTileMaxNT = 5;
+__host__ __device__ inline int chol_tiles(int n) { return (n + 15) / 16; }
+__host__ __device__ inline size_t chol_store_doubles(int n) {
+  const int nt = chol_tiles(n);
+  return nt <= kTileMaxNT ? (size_t)(nt * (nt + 1) / 2) * 256 : (size_t)n * (n + 1) / 2;
+}
+
 // ---------------------------------------------------------------------------
 // Device view of a data set plus the workspace of one call.
 // ---------------------------------------------------------------------------
@@ -98,6 +118,8 @@ struct Dev {
   const double *sth, *cth, *tau, *wdm;
   const double *pos, *gamma;
   const double *gchol;         // chol(Gamma), packed row-major lower
+  const double *gtile;         // chol(Gamma) zero-padded, lower 16x16 tiles (up to kTileMaxNT)
+  const double *gam_tile;      // Gamma zero-padded, lower 16x16 tiles (diagonal tiles full)
   const double *prior_lo, *prior_hi;
   // chunk table of the batched TOA pass
   int n_chunks, tiles_per_chunk;
@@ -137,9 +159,10 @@ hipError_t launch_spec_fwd(const pt::Dev &D, const double *x, hipStream_t s);
 hipError_t launch_toa_mfma(const pt::Dev &D, int waves_per_block, int xcd_map, hipStream_t s);
 hipError_t launch_toa_plain_psr(const pt::Dev &D, int p, int n_chunks_p, hipStream_t s);
 hipError_t set_plain_lds_limit(size_t bytes);
-hipError_t set_spec_lds_limits(size_t fwd_bytes, size_t bwd_bytes);
-size_t spec_fwd_lds(int n);
-size_t spec_bwd_lds(int n);
+hipError_t launch_chol_fwd(const pt::Dev &D, const double *x, hipStream_t s);
+hipError_t launch_chol_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s);
+hipError_t launch_cholt_fwd(const pt::Dev &D, const double *x, hipStream_t s);
+hipError_t launch_cholt_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s);
 hipError_t launch_reduce_chunks(const pt::Dev &D, hipStream_t s);
 hipError_t launch_spec_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s);
 hipError_t launch_finalize(const pt::Dev &D, const double *x, double *logp, double *grad,

@@ -1,0 +1,525 @@
+// Dense per-frequency prior covariance on FP64 matrix cores, for arrays of up
+// to 80 pulsars (five 16-row tiles): one 64-lane wave per (frequency, chain)
+// holds the lower tiles of the padded matrix in registers.
+//
+// Forward (Sec. IV.A, Eqs. HD, prior_cov; Sec. II.B, Eq.
+// standardizing_transform with mu = 0): C = chol(rho_k Gamma + diag kappa_.k)
+// by a right-looking blocked factorisation.  A block column is factorised by
+// 16 rank-1 steps on the vector unit (pivot broadcast by readlane, the scaled
+// column through LDS); the trailing tiles are updated with 16x16x4 MFMAs.
+// Then a_.k,{sin,cos} = C z_.k,{sin,cos}.
+//
+// Backward, with abar from the TOA pass and v_c = C^T abar_c:
+//   dz_c = v_c - z_c
+//   W = C^-1 (block forward substitution on MFMA: W_II = C_II^-1 from a
+//   16-lane substitution per diagonal tile, W_IJ = -W_II sum_K C_IK W_KJ)
+//   M = W chol(Gamma)  (MFMA)
+//   d/dkappa_I = w_I^T P w_I,  d/drho = sum_I m_I^T P m_I,  P = Phi(sum_c v_c z_c^T)
+// The quadratic forms with the semiseparable P are prefix sums down each
+// column, taken on the MFMA output layout.
+//
+// Register layouts of a 16x16 block X (lane l = c + 16 q, item v or slice s):
+//   forward, E(X):   X[c][q + 4s]       (operand A of X, operand B of X^T,
+//                                         and the result layout of X^T)
+//   backward, A(X):  X[pi(c)][4q + s]    operand A
+//             B(X):  X[4q + v][c]        operand B and result layout
+// with pi(c) = 4 (c mod 4) + c / 4, so that lane group q of a result holds the
+// consecutive rows 4q .. 4q + 3 of every tile.
+#include "common.h"
+
+namespace {
+
+using pt::Dev;
+using pt::pk;
+using v4d = double __attribute__((ext_vector_type(4)));
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// acc += X Y for one 16x16x16 product given the four k-slices of both operands
+__device__ inline v4d mfma4(const v4d &a, const v4d &b, v4d acc) {
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], acc, 0, 0, 0);
+  return acc;
+}
+
+__host__ __device__ constexpr int tidx(int I, int J) { return I * (I + 1) / 2 + J; }
+__device__ inline int pi16(int c) { return 4 * (c & 3) + (c >> 2); }
+
+// ---------------------------------------------------------------------------
+// Forward: grid (nf_gw, c_pad), block 64.
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(64) void k_cholt_fwd(Dev D, const double *__restrict__ x) {
+  constexpr int NP = 16 * NT;
+  constexpr int NTILE = NT * (NT + 1) / 2;
+  __shared__ double colb[NT][16];
+  __shared__ double zb[NP][2];
+  __shared__ double kb[NP];
+  const int k0 = blockIdx.x, c = blockIdx.y;
+  const int l = threadIdx.x, c16 = l & 15, q = l >> 4;
+  const int n = D.n_psr;
+  const size_t cp = D.c_pad;
+  const int rs = pt::harm_row(k0 + 1, 0), rc = pt::harm_row(k0 + 1, 1);
+  auto coef = [&](int r, int sc) -> double & {
+    return D.coef_rn[((size_t)r * D.rows_rn + (sc ? rc : rs)) * cp + c];
+  };
+  if (c >= D.n_chains || D.st_pre[c] == PTAFS_ST_PRIOR) {
+    for (int r = l; r < n; r += 64) {
+      coef(r, 0) = 0.0;
+      coef(r, 1) = 0.0;
+    }
+    return;
+  }
+  const double *xc = x + (size_t)c * D.d;
+  const double f = (k0 + 1) / D.tspan;
+  const double rho = pt::powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
+  for (int r = l; r < NP; r += 64) {
+    double kap = 0.0, zs = 0.0, zc = 0.0;
+    if (r < n) {
+      if (k0 < D.nf_rn) kap = pt::powerlaw(f, xc[D.off_rn + 2 * r], xc[D.off_rn + 2 * r + 1], D.tspan);
+      const double *z = xc + D.off_z + (size_t)r * 2 * D.ka + 2 * k0;
+      zs = z[0];
+      zc = z[1];
+    }
+    kb[r] = kap;
+    zb[r][0] = zs;
+    zb[r][1] = zc;
+  }
+  wave_sync();
+
+  // phi tiles in E layout: lane (c16, q), item v = phi[16I + c16][16J + q + 4v];
+  // the padding is the identity.  All tile loads are independent.
+  v4d A[NTILE];
+  const double *__restrict__ gt = D.gam_tile + c16 * 16 + q;
+#pragma unroll
+  for (int T = 0; T < NTILE; ++T)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) A[T][v] = rho * gt[T * 256 + 4 * v];
+#pragma unroll
+  for (int I = 0; I < NT; ++I) {
+    const int r = 16 * I + c16;
+    const double dadd = (r < n) ? kb[r] : 1.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (c16 == q + 4 * v) A[tidx(I, I)][v] += dadd;
+  }
+
+  bool pd = true;
+#pragma unroll
+  for (int J = 0; J < NT; ++J) {
+    // ---- block column J: 16 rank-1 steps
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const double piv = readlane_d(A[tidx(J, J)][cc >> 2], cc + 16 * (cc & 3));
+      pd = pd && (piv > 0.0) && isfinite(piv);
+      const double rd = 1.0 / sqrt(piv);
+      if (q == (cc & 3)) {
+#pragma unroll
+        for (int I = J; I < NT; ++I) {
+          const double s = A[tidx(I, J)][cc >> 2] * rd;
+          A[tidx(I, J)][cc >> 2] = s;
+          colb[I][c16] = s;
+        }
+      }
+      wave_sync();
+      double lk[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) lk[v] = colb[J][q + 4 * v];
+#pragma unroll
+      for (int I = J; I < NT; ++I) {
+        const double lr = colb[I][c16];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (q + 4 * v > cc) A[tidx(I, J)][v] -= lr * lk[v];
+      }
+      wave_sync();
+    }
+    // ---- trailing tiles: A_IK -= C_IJ C_KJ^T  (as A_IK^T -= C_KJ C_IJ^T)
+#pragma unroll
+    for (int K = J + 1; K < NT; ++K) {
+      const v4d nk = -A[tidx(K, J)];
+#pragma unroll
+      for (int I = K; I < NT; ++I) A[tidx(I, K)] = mfma4(nk, A[tidx(I, J)], A[tidx(I, K)]);
+    }
+  }
+  if (!pd) {
+    for (int r = l; r < n; r += 64) {
+      coef(r, 0) = 0.0;
+      coef(r, 1) = 0.0;
+    }
+    if (l == 0) {
+      const int kmax = max(D.ka, D.nf_dm);
+      D.flag_k[(size_t)c * kmax + k0] |= pt::kFlagNotPD;
+    }
+    return;
+  }
+  // zero the upper part of the diagonal tiles
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (q + 4 * v > c16) A[tidx(I, I)][v] = 0.0;
+
+  // a = C z: lane partial over its columns, then over the lane groups
+#pragma unroll
+  for (int I = 0; I < NT; ++I) {
+    double as = 0.0, ac = 0.0;
+#pragma unroll
+    for (int J = 0; J <= I; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = 16 * J + q + 4 * v;
+        as += A[tidx(I, J)][v] * zb[k][0];
+        ac += A[tidx(I, J)][v] * zb[k][1];
+      }
+    as += __shfl_xor(as, 16, 64);
+    ac += __shfl_xor(ac, 16, 64);
+    as += __shfl_xor(as, 32, 64);
+    ac += __shfl_xor(ac, 32, 64);
+    const int r = 16 * I + c16;
+    if (q == 0 && r < n) {
+      coef(r, 0) = as;
+      coef(r, 1) = ac;
+    }
+  }
+  // keep C for the adjoint, tile-major
+  double *dst = D.lstore + ((size_t)c * D.nf_gw + k0) * (NTILE * 256);
+#pragma unroll
+  for (int T = 0; T < NTILE; ++T)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[T * 256 + c16 * 16 + q + 4 * v] = A[T][v];
+}
+
+// ---------------------------------------------------------------------------
+// Backward: grid (nf_gw, n_chains), block 64.
+// ---------------------------------------------------------------------------
+struct ScanState {
+  double rs, rc, q;   // running column sums of z x (sin, cos) and the quadratic form
+};
+
+// One 16-row tile of 16 columns (B layout: item v of lane group q is row
+// row0 + 4q + v) added to the column quadratic forms x^T P x.
+__device__ inline void scan_tile(const v4d &X, int row0, const double (*vz)[4], ScanState &st,
+                                 int l, int c16, int q) {
+  double ls = 0.0, lc = 0.0, part = 0.0, sa = 0.0, ca = 0.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = row0 + 4 * q + v;
+    const double x = X[v];
+    const double bs = vz[r][2] * x, bc = vz[r][3] * x;
+    const double as = vz[r][0] * x, ac = vz[r][1] * x;
+    part += as * (ls + 0.5 * bs) + ac * (lc + 0.5 * bc);
+    ls += bs;
+    lc += bc;
+    sa += as;
+    ca += ac;
+  }
+  // exclusive prefix of the lane sums over the four lane groups of a column
+  double is = ls, ic = lc;
+  double us = __shfl_up(is, 16, 64), uc = __shfl_up(ic, 16, 64);
+  if (q >= 1) {
+    is += us;
+    ic += uc;
+  }
+  us = __shfl_up(is, 32, 64);
+  uc = __shfl_up(ic, 32, 64);
+  if (q >= 2) {
+    is += us;
+    ic += uc;
+  }
+  const double ts = __shfl(is, c16 + 48, 64), tc = __shfl(ic, c16 + 48, 64);
+  st.q += part + (st.rs + (is - ls)) * sa + (st.rc + (ic - lc)) * ca;
+  st.rs += ts;
+  st.rc += tc;
+}
+
+template <int NT>
+__global__ __launch_bounds__(64) void k_cholt_bwd(Dev D, const double *__restrict__ x,
+                                                  double *__restrict__ grad,
+                                                  const double *__restrict__ lst,
+                                                  const double *__restrict__ gch,
+                                                  const double *__restrict__ bar) {
+  constexpr int NP = 16 * NT;
+  constexpr int NTILE = NT * (NT + 1) / 2;
+  constexpr int TS = 17;                              // LDS row stride of a tile
+  __shared__ double vz[NP][4];                        // v_sin, v_cos, z_sin, z_cos
+  __shared__ double tl[NTILE > 2 * NT ? NTILE : 2 * NT][16 * TS];
+  const int k0 = blockIdx.x, c = blockIdx.y;
+  const int l = threadIdx.x, c16 = l & 15, q = l >> 4;
+  const int n = D.n_psr;
+  const int kmax = max(D.ka, D.nf_dm);
+  const size_t cp = D.c_pad;
+  const int rs = pt::harm_row(k0 + 1, 0), rc = pt::harm_row(k0 + 1, 1);
+  const int K2 = 2 * D.ka;
+  const double *xc = x + (size_t)c * D.d;
+  double *gz = grad + (size_t)c * D.d + D.off_z + 2 * k0;
+  double *drn = D.drn_k + ((size_t)c * D.ka + k0) * n * 2;
+  double *dth = D.dth_k + ((size_t)c * D.ka + k0) * 2;
+  const int fl0 = D.flag_k[(size_t)c * kmax + k0];
+  if (D.st_pre[c] != 0 || fl0 != 0) {
+    for (int I = l; I < n; I += 64) {
+      gz[(size_t)I * K2] = 0.0;
+      gz[(size_t)I * K2 + 1] = 0.0;
+      drn[2 * I] = 0.0;
+      drn[2 * I + 1] = 0.0;
+    }
+    if (l == 0) {
+      dth[0] = 0.0;
+      dth[1] = 0.0;
+    }
+    return;
+  }
+  const double *Cb = lst + ((size_t)c * D.nf_gw + k0) * (NTILE * 256);
+
+  // ---- v_c = C^T abar_c: lane (c16, q) sums rows 16K + 4q + v of column
+  //      16J + c16, then the four lane groups are added
+  __shared__ double ab[NP][2];
+  for (int m = l; m < NP; m += 64) {
+    double as = 0.0, ac = 0.0;
+    if (m < n) {
+      as = bar[((size_t)m * D.rows_rn + rs) * cp + c];
+      ac = bar[((size_t)m * D.rows_rn + rc) * cp + c];
+    }
+    ab[m][0] = as;
+    ab[m][1] = ac;
+  }
+  wave_sync();
+  double vcol[NT][2];
+#pragma unroll
+  for (int J = 0; J < NT; ++J) {
+    double ss = 0.0, sc = 0.0;
+#pragma unroll
+    for (int K = J; K < NT; ++K) {
+      const double *t = Cb + tidx(K, J) * 256 + 64 * q + c16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double e = t[16 * v];
+        ss += e * ab[16 * K + 4 * q + v][0];
+        sc += e * ab[16 * K + 4 * q + v][1];
+      }
+    }
+    ss += __shfl_xor(ss, 16, 64);
+    sc += __shfl_xor(sc, 16, 64);
+    ss += __shfl_xor(ss, 32, 64);
+    sc += __shfl_xor(sc, 32, 64);
+    vcol[J][0] = ss;
+    vcol[J][1] = sc;
+  }
+  double vv[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  double zz[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int I = l + 64 * h;
+#pragma unroll
+    for (int J = 0; J < NT; ++J)
+      if (J == (I >> 4)) {
+        vv[h][0] = vcol[J][0];
+        vv[h][1] = vcol[J][1];
+      }
+    if (I < n) {
+      zz[h][0] = xc[D.off_z + (size_t)I * K2 + 2 * k0];
+      zz[h][1] = xc[D.off_z + (size_t)I * K2 + 2 * k0 + 1];
+    }
+    if (I < NP) {
+      vz[I][0] = vv[h][0];
+      vz[I][1] = vv[h][1];
+      vz[I][2] = zz[h][0];
+      vz[I][3] = zz[h][1];
+    }
+  }
+
+  // ---- inverses of the diagonal tiles: lane group g solves tile J = g (+4)
+  //      column c16 by forward substitution; C_JJ in tl[J], W_JJ in tl[NT + J]
+#pragma unroll
+  for (int J = 0; J < NT; ++J)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      tl[J][(4 * q + v) * TS + c16] = Cb[tidx(J, J) * 256 + (4 * q + v) * 16 + c16];
+  wave_sync();
+#pragma unroll
+  for (int rnd = 0; rnd < (NT + 3) / 4; ++rnd) {
+    const int J = 4 * rnd + q;
+    if (J < NT) {
+      const double *T = tl[J];
+      double xs[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        __builtin_amdgcn_sched_barrier(0);     // bound the live LDS reads to one row
+        double s = (r == c16) ? 1.0 : 0.0;
+#pragma unroll
+        for (int m = 0; m < r; ++m) s -= T[r * TS + m] * xs[m];
+        xs[r] = s / T[r * TS + r];
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) tl[NT + J][r * TS + c16] = xs[r];
+    }
+  }
+  wave_sync();
+
+  // ---- W = C^-1 in B layout; -W_II in A layout
+  v4d Wb[NTILE];
+  v4d Wi[NT];
+  const int pc = pi16(c16);
+#pragma unroll
+  for (int I = 0; I < NT; ++I)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      Wb[tidx(I, I)][v] = tl[NT + I][(4 * q + v) * TS + c16];
+      Wi[I][v] = -tl[NT + I][pc * TS + 4 * q + v];
+    }
+#pragma unroll
+  for (int I = 1; I < NT; ++I)
+#pragma unroll
+    for (int J = 0; J < I; ++J) {
+      // keep the scheduler from hoisting every tile load of the kernel here
+      __builtin_amdgcn_sched_barrier(0);
+      v4d U = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int K = J; K < I; ++K) {
+        v4d a;
+        const double *t = Cb + tidx(I, K) * 256 + pc * 16 + 4 * q;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) a[s] = t[s];
+        U = mfma4(a, Wb[tidx(K, J)], U);
+      }
+      Wb[tidx(I, J)] = mfma4(Wi[I], U, v4d{0.0, 0.0, 0.0, 0.0});
+    }
+  wave_sync();
+
+  // ---- d/dkappa: quadratic forms down the columns of W
+  double dkap[NT];
+#pragma unroll
+  for (int J = 0; J < NT; ++J) {
+    __builtin_amdgcn_sched_barrier(0);
+    ScanState st{0.0, 0.0, 0.0};
+#pragma unroll
+    for (int I = J; I < NT; ++I) scan_tile(Wb[tidx(I, J)], 16 * I, vz, st, l, c16, q);
+    double qq = st.q;
+    qq += __shfl_xor(qq, 16, 64);
+    qq += __shfl_xor(qq, 32, 64);
+    dkap[J] = qq;
+  }
+
+  // ---- W to A layout through LDS
+#pragma unroll
+  for (int T = 0; T < NTILE; ++T)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tl[T][(4 * q + v) * TS + c16] = Wb[T][v];
+  wave_sync();
+  v4d Wa[NTILE];
+#pragma unroll
+  for (int T = 0; T < NTILE; ++T)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) Wa[T][s] = tl[T][pc * TS + 4 * q + s];
+
+  // ---- d/drho: M = W G column block by column block, quadratic forms
+  double dr = 0.0;
+#pragma unroll
+  for (int J = 0; J < NT; ++J) {
+    ScanState st{0.0, 0.0, 0.0};
+#pragma unroll
+    for (int I = J; I < NT; ++I) {
+      __builtin_amdgcn_sched_barrier(0);
+      v4d Mt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int K = J; K <= I; ++K) {
+        v4d g;
+        const double *gt = gch + tidx(K, J) * 256 + 64 * q + c16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) g[v] = gt[16 * v];
+        Mt = mfma4(Wa[tidx(I, K)], g, Mt);
+      }
+      scan_tile(Mt, 16 * I, vz, st, l, c16, q);
+    }
+    dr += st.q;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) dr += __shfl_xor(dr, o, 64);
+
+  // ---- outputs
+  const double f = (k0 + 1) / D.tspan;
+  const double lnfy = log(f * pt::kYear);
+  bool fin = true;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int I = l + 64 * h;
+    if (I < n) {
+      const double g0 = vv[h][0] - zz[h][0], g1 = vv[h][1] - zz[h][1];
+      gz[(size_t)I * K2] = g0;
+      gz[(size_t)I * K2 + 1] = g1;
+      // column I = 16 (I / 16) + l % 16: this lane's entry of its column block
+      double dk = 0.0;
+#pragma unroll
+      for (int J = 0; J < NT; ++J) dk = (J == (I >> 4)) ? dkap[J] : dk;
+      const double kap = (k0 < D.nf_rn)
+                             ? pt::powerlaw(f, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1], D.tspan)
+                             : 0.0;
+      const double d0 = dk * kap * 2.0 * pt::kLn10, d1 = dk * kap * (-lnfy);
+      drn[2 * I] = d0;
+      drn[2 * I + 1] = d1;
+      fin = fin && isfinite(g0) && isfinite(g1) && isfinite(d0) && isfinite(d1);
+    }
+  }
+  const int nbad = __popcll(__ballot(!fin));
+  if (l == 0) {
+    const double rho = pt::powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
+    dth[0] = dr * rho * 2.0 * pt::kLn10;
+    dth[1] = dr * rho * (-lnfy);
+    if (nbad || !isfinite(dth[0]) || !isfinite(dth[1]))
+      D.flag_k[(size_t)c * kmax + k0] = fl0 | pt::kFlagOutNonfinite;
+  }
+}
+
+template <int NT>
+hipError_t launch_fwd_t(const Dev &D, const double *x, hipStream_t s) {
+  hipLaunchKernelGGL(k_cholt_fwd<NT>, dim3(D.nf_gw, D.c_pad), dim3(64), 0, s, D, x);
+  return hipGetLastError();
+}
+
+template <int NT>
+hipError_t launch_bwd_t(const Dev &D, const double *x, double *grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_cholt_bwd<NT>, dim3(D.nf_gw, D.n_chains), dim3(64), 0, s, D, x, grad,
+                     (const double *)D.lstore, D.gtile, (const double *)D.bar_rn);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+namespace ptk {
+
+hipError_t launch_cholt_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
+  switch (pt::chol_tiles(D.n_psr)) {
+    case 1: return launch_fwd_t<1>(D, x, s);
+    case 2: return launch_fwd_t<2>(D, x, s);
+    case 3: return launch_fwd_t<3>(D, x, s);
+    case 4: return launch_fwd_t<4>(D, x, s);
+    case 5: return launch_fwd_t<5>(D, x, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cholt_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s) {
+  switch (pt::chol_tiles(D.n_psr)) {
+    case 1: return launch_bwd_t<1>(D, x, grad, s);
+    case 2: return launch_bwd_t<2>(D, x, grad, s);
+    case 3: return launch_bwd_t<3>(D, x, grad, s);
+    case 4: return launch_bwd_t<4>(D, x, grad, s);
+    case 5: return launch_bwd_t<5>(D, x, grad, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ptk

@@ -1,21 +1,15 @@
-// Per-frequency kernels: power-law spectra, prior covariance, Cholesky
-// factor and whitening transform (forward), and the Cholesky adjoint
-// (backward).  One 256-thread workgroup per (frequency, chain).
+// Per-frequency kernels that need no dense factorisation: power-law spectra
+// (Sec. IV.A, Eq. power_law), the diagonal prior of the frequencies without
+// the common process and the DM prior, with their whitening transforms
+// (Sec. II.B, Eq. standardizing_transform, mu = 0) and adjoints; the input
+// checks, the timing-model rows of the coefficient panels, the CW constants
+// and the per-TOA white-noise preparation (Eq. WN_cov).  One 256-thread
+// workgroup per (frequency, chain).  The frequencies that carry the common
+// process (dense phi_k = rho_k Gamma + diag kappa) are factorised in k_chol.
 //
-// Forward (Sec. IV.A, Eqs. power_law, HD, prior_cov; Sec. II.B, Eq.
-// standardizing_transform with mu = 0):
-//   rho_k = A^2/(12 pi^2) yr^3 (f_k yr)^-gamma / T,  kappa_Ik likewise
-//   phi_k = rho_k Gamma + diag(kappa_.k),  L_k = chol(phi_k)
-//   a_.k,sin = L_k z_.k,sin,  a_.k,cos = L_k z_.k,cos,  a_dm = sqrt(kdm) z_dm
-//
-// Backward, with abar = d log L / d a from the TOA pass and v_c = L^T abar_c:
-//   dz_c = v_c - z_c
-//   phibar = sym(W^T P W),  W = L^-1,  P = Phi(sum_c v_c z_c^T)
-//   (Phi = lower triangle with halved diagonal; the adjoint of phi = L L^T)
-//   d/dkappa_I = phibar_II = w_I^T P w_I        (w_I = column I of W)
-//   d/drho     = <phibar, Gamma> = <P, M M^T>,  M = W G,  G = chol(Gamma)
-// Both reductions are O(n^2) with prefix / suffix sums over the lower
-// triangle of P; W and M are formed with blocked triangular products.
+//   diagonal frequencies:  a_Ik = sqrt(kappa_Ik) z_Ik,  dz = sqrt(kappa) abar - z,
+//     d/dlog10A_I = ln10 sqrt(kappa) abar.z,  d/dgamma_I = -1/2 ln(f yr) sqrt(kappa) abar.z
+//   DM: the same with kappa^DM and abar^DM.
 #include "common.h"
 #include "cw_dev.h"
 
@@ -23,14 +17,8 @@ namespace {
 
 using pt::Dev;
 
-__device__ inline double powerlaw(double f, double log10A, double gamma, double tspan) {
-  // A^2/(12 pi^2) yr^3 (f yr)^-gamma / T, evaluated in logarithms.
-  const double c = 3.0 * log(pt::kYear) - log(12.0 * pt::kPi * pt::kPi) - log(tspan);
-  return exp(2.0 * pt::kLn10 * log10A - gamma * log(f * pt::kYear) + c);
-}
-
-// Packed lower-triangular storage, row-major: row i holds columns 0..i.
-__device__ inline int pk(int i, int j) { return (i * (i + 1)) / 2 + j; }
+using pt::pk;
+using pt::powerlaw;
 
 template <typename T>
 __device__ T block_sum(T v, T *red) {
@@ -54,7 +42,6 @@ __device__ inline bool block_all(bool v, int *ired) { return block_sum<int>(v ? 
 // LDS (dense frequencies): A [n][ns] row-major (ns = n | 1), z [2][n], diag [n].
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_spec_fwd(Dev D, const double *__restrict__ x) {
-  extern __shared__ double lds[];
   __shared__ double red[256];
   __shared__ int ired[256];
   const int tid = threadIdx.x;
@@ -192,80 +179,8 @@ __global__ __launch_bounds__(256) void k_spec_fwd(Dev D, const double *__restric
         D.coef_rn[((size_t)I * D.rows_rn + rc) * cp + c] = sq * zc[I * K2 + 2 * k0 + 1];
       }
       if (!block_all(pd, ired)) flag |= pt::kFlagNotPD;
-    } else {
-      // Right-looking Cholesky on the unscaled lower triangle: at column j,
-      // A_ik -= A_ij A_kj / A_jj for j < k <= i; afterwards L_jj = sqrt(A_jj),
-      // L_ij = A_ij / L_jj.  One barrier per column.
-      const int ns = n | 1;
-      double *A = lds;                      // [n][ns]
-      double *zs = A + (size_t)n * ns;      // [2][n]
-      double *dg = zs + 2 * n;              // [n]
-      const double rho = powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
-      for (int I = tid; I < n; I += 256) {
-        double kap = 0.0;
-        if (k0 < D.nf_rn) kap = powerlaw(f, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1], D.tspan);
-        dg[I] = kap;
-        zs[I] = zc[I * K2 + 2 * k0];
-        zs[n + I] = zc[I * K2 + 2 * k0 + 1];
-      }
-      __syncthreads();
-      for (int e = tid; e < n * n; e += 256) {
-        const int i = e / n, j = e - (e / n) * n;
-        if (j <= i) A[i * ns + j] = rho * D.gamma[e] + (i == j ? dg[i] : 0.0);
-      }
-      __syncthreads();
-      const int tx = tid & 15, ty = tid >> 4;
-      bool pd = true;
-      for (int j = 0; j < n; ++j) {
-        const double ajj = A[j * ns + j];
-        if (!(ajj > 0.0) || !isfinite(ajj)) {   // same value in every thread
-          pd = false;
-          break;
-        }
-        const double inv = 1.0 / ajj;
-        for (int i = j + 1 + ty; i < n; i += 16) {
-          const double aij = A[i * ns + j] * inv;
-          for (int k = j + 1 + tx; k <= i; k += 16) A[i * ns + k] -= aij * A[k * ns + j];
-        }
-        __syncthreads();
-      }
-      if (!pd) {
-        flag |= pt::kFlagNotPD;
-        for (int I = tid; I < n; I += 256) {
-          D.coef_rn[((size_t)I * D.rows_rn + rs) * cp + c] = 0.0;
-          D.coef_rn[((size_t)I * D.rows_rn + rc) * cp + c] = 0.0;
-        }
-      } else {
-        for (int j = tid; j < n; j += 256) dg[j] = sqrt(A[j * ns + j]);
-        __syncthreads();
-        for (int e = tid; e < n * n; e += 256) {
-          const int i = e / n, j = e - (e / n) * n;
-          if (j < i) A[i * ns + j] /= dg[j];
-          else if (j == i) A[i * ns + j] = dg[j];
-        }
-        __syncthreads();
-        // a = L z for sin and cos
-        for (int e = tid; e < 2 * n; e += 256) {
-          const int I = e >> 1, sc = e & 1;
-          const double *zv = zs + sc * n;
-          double s0 = 0.0, s1 = 0.0;
-          int m = 0;
-          for (; m + 1 <= I; m += 2) {
-            s0 += A[I * ns + m] * zv[m];
-            s1 += A[I * ns + m + 1] * zv[m + 1];
-          }
-          if (m <= I) s0 += A[I * ns + m] * zv[m];
-          D.coef_rn[((size_t)I * D.rows_rn + (sc ? rc : rs)) * cp + c] = s0 + s1;
-        }
-        // keep L (packed row-major) for the adjoint
-        const int np = (n * (n + 1)) / 2;
-        double *dst = D.lstore + ((size_t)c * D.nf_gw + k0) * np;
-        for (int e = tid; e < n * n; e += 256) {
-          const int i = e / n, j = e - (e / n) * n;
-          if (j <= i) dst[pk(i, j)] = A[i * ns + j];
-        }
-      }
     }
+    // dense frequencies: factorisation and transform in k_chol_fwd
   }
 
   // ---- DM block -------------------------------------------------------------
@@ -297,8 +212,6 @@ __global__ __launch_bounds__(256) void k_spec_fwd(Dev D, const double *__restric
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_spec_bwd(Dev D, const double *__restrict__ x,
                                                   double *__restrict__ grad) {
-  extern __shared__ double lds[];
-  __shared__ double red[256];
   __shared__ int ired[256];
   const int k0 = blockIdx.x;
   const int c = blockIdx.y;
@@ -321,7 +234,9 @@ __global__ __launch_bounds__(256) void k_spec_bwd(Dev D, const double *__restric
     const bool dense = k0 < D.nf_gw;
     double *dth = D.dth_k + ((size_t)c * D.ka + k0) * 2;
     double *drn = D.drn_k + ((size_t)c * D.ka + k0) * n * 2;
-    if (skip) {
+    if (dense) {
+      // dense frequencies: adjoint in k_chol_bwd
+    } else if (skip) {
       for (int I = tid; I < n; I += 256) {
         gc[D.off_z + I * K2 + 2 * k0] = 0.0;
         gc[D.off_z + I * K2 + 2 * k0 + 1] = 0.0;
@@ -348,142 +263,6 @@ __global__ __launch_bounds__(256) void k_spec_bwd(Dev D, const double *__restric
         fin = fin && isfinite(g_s) && isfinite(g_c) && isfinite(d0) && isfinite(d1);
       }
       if (tid == 0) { dth[0] = 0.0; dth[1] = 0.0; }
-    } else {
-      const int nb = (n + 15) >> 4, np = 16 * nb;        // padded size
-      const int npk = (np * (np + 1)) / 2;
-      double *Lp = lds;                                  // packed [np], later M
-      double *Wp = Lp + npk;                             // packed [np]
-      double *v = Wp + npk;                              // [2][np]
-      double *zv = v + 2 * np;                           // [2][np]
-      double *ab = zv + 2 * np;                          // [2][np]
-      const int nl = (n * (n + 1)) / 2;
-      const double *src = D.lstore + ((size_t)c * D.nf_gw + k0) * nl;
-      for (int e = tid; e < npk; e += 256) Lp[e] = 0.0;
-      __syncthreads();
-      for (int e = tid; e < nl; e += 256) Lp[e] = src[e];   // same packing for rows < n
-      for (int i = n + tid; i < np; i += 256) Lp[pk(i, i)] = 1.0;   // identity padding
-      for (int e = tid; e < 2 * np; e += 256) {
-        const int I = e % np, sc = e / np;
-        double zz = 0.0, aa = 0.0;
-        if (I < n) {
-          zz = zc[I * K2 + 2 * k0 + sc];
-          aa = D.bar_rn[((size_t)I * D.rows_rn + (sc ? rc : rs)) * cp + c];
-        }
-        zv[e] = zz;
-        ab[e] = aa;
-      }
-      __syncthreads();
-      // v_c = L^T abar_c ; dz = v - z
-      for (int e = tid; e < 2 * np; e += 256) {
-        const int I = e % np, sc = e / np;
-        double s = 0.0;
-        if (I < n)
-          for (int m = I; m < n; ++m) s += Lp[pk(m, I)] * ab[sc * np + m];
-        v[e] = s;
-        if (I < n) {
-          const double g = s - zv[e];
-          gc[D.off_z + I * K2 + 2 * k0 + sc] = g;
-          fin = fin && isfinite(g);
-        }
-      }
-      // W = L^-1, blocked 16x16: diagonal blocks first, then block rows.
-      for (int e = tid; e < 16 * nb; e += 256) {
-        const int B = e >> 4, col = e & 15, b0 = 16 * B;
-        // column col of the inverse of the diagonal block B
-        for (int a = col; a < 16; ++a) {
-          double s = (a == col) ? 1.0 : 0.0;
-          for (int m = col; m < a; ++m) s -= Lp[pk(b0 + a, b0 + m)] * Wp[pk(b0 + m, b0 + col)];
-          Wp[pk(b0 + a, b0 + col)] = s / Lp[pk(b0 + a, b0 + a)];
-        }
-      }
-      __syncthreads();
-      {
-        const int r = tid >> 4, cc = tid & 15;           // 256 threads = one 16x16 block
-        for (int I = 1; I < nb; ++I) {
-          // T_J = sum_{K=J}^{I-1} L_IK W_KJ for all J < I, stored in the (I, J)
-          // blocks of W, then W_IJ = -W_II T_J.
-          const int gi = 16 * I + r;
-#pragma unroll
-          for (int J = 0; J < 8; ++J) {
-            if (J < I) {
-              const int gj = 16 * J + cc;
-              double s = 0.0;
-              for (int m = gj; m < 16 * I; ++m) s += Lp[pk(gi, m)] * Wp[pk(m, gj)];
-              Wp[pk(gi, gj)] = s;
-            }
-          }
-          __syncthreads();
-          double tv[8];
-#pragma unroll
-          for (int J = 0; J < 8; ++J) {
-            tv[J] = 0.0;
-            if (J < I) {
-              const int gj = 16 * J + cc;
-              double s = 0.0;
-              for (int m = 0; m <= r; ++m) s += Wp[pk(gi, 16 * I + m)] * Wp[pk(16 * I + m, gj)];
-              tv[J] = -s;
-            }
-          }
-          __syncthreads();
-#pragma unroll
-          for (int J = 0; J < 8; ++J)
-            if (J < I) Wp[pk(gi, 16 * J + cc)] = tv[J];
-          __syncthreads();
-        }
-      }
-      // d/dkappa_I = sum_c sum_{a>=I} W_aI v_a (sum_{I<=b<a} z_b W_bI + z_a W_aI / 2)
-      for (int I = tid; I < n; I += 256) {
-        double acc = 0.0;
-        for (int sc = 0; sc < 2; ++sc) {
-          double pre = 0.0;
-          for (int a = I; a < n; ++a) {
-            const double w = Wp[pk(a, I)];
-            const double zw = zv[sc * np + a] * w;
-            acc += w * v[sc * np + a] * (pre + 0.5 * zw);
-            pre += zw;
-          }
-        }
-        const double kap = (k0 < D.nf_rn)
-                               ? powerlaw(f, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1], D.tspan)
-                               : 0.0;
-        const double d0 = acc * kap * 2.0 * pt::kLn10, d1 = acc * kap * (-lnfy);
-        drn[2 * I] = d0;
-        drn[2 * I + 1] = d1;
-        fin = fin && isfinite(d0) && isfinite(d1);
-      }
-      __syncthreads();
-      // M = W G (lower x lower) into Lp
-      for (int e = tid; e < nl; e += 256) {
-        // decode packed (a, I)
-        int a = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-        while (pk(a, 0) > e) --a;
-        while (pk(a + 1, 0) <= e) ++a;
-        const int I = e - pk(a, 0);
-        double s = 0.0;
-        for (int m = I; m <= a; ++m) s += Wp[pk(a, m)] * D.gchol[pk(m, I)];
-        Lp[e] = s;
-      }
-      __syncthreads();
-      // d/drho = sum_c sum_m sum_{b>=m} z_b M_bm (sum_{a>b} v_a M_am + v_b M_bm / 2)
-      double dr = 0.0;
-      for (int m = tid; m < n; m += 256) {
-        for (int sc = 0; sc < 2; ++sc) {
-          double suf = 0.0;
-          for (int b = n - 1; b >= m; --b) {
-            const double Mb = Lp[pk(b, m)];
-            const double vm = v[sc * np + b] * Mb;
-            dr += zv[sc * np + b] * Mb * (suf + 0.5 * vm);
-            suf += vm;
-          }
-        }
-      }
-      dr = block_sum(dr, red);
-      if (tid == 0) {
-        const double rho = powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
-        dth[0] = dr * rho * 2.0 * pt::kLn10;
-        dth[1] = dr * rho * (-lnfy);
-        fin = fin && isfinite(dth[0]) && isfinite(dth[1]);
-      }
     }
   }
 
@@ -523,35 +302,18 @@ __global__ __launch_bounds__(256) void k_spec_bwd(Dev D, const double *__restric
 
 namespace ptk {
 
-size_t spec_fwd_lds(int n) { return ((size_t)n * (n | 1) + 3 * (size_t)n) * sizeof(double); }
-
-size_t spec_bwd_lds(int n) {
-  const size_t np = 16 * (size_t)((n + 15) / 16);
-  return (np * (np + 1) + 6 * np) * sizeof(double);
-}
-
-hipError_t set_spec_lds_limits(size_t fwd_bytes, size_t bwd_bytes) {
-  hipError_t e = hipFuncSetAttribute((const void *)k_spec_fwd,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)fwd_bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void *)k_spec_bwd, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)bwd_bytes);
-}
-
 hipError_t launch_spec_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
   const int kmax = max(D.ka, D.nf_dm);
   const int nblk = kmax * D.c_pad + D.n_prep;
   if (nblk == 0) return hipSuccess;
-  const size_t lds = D.nf_gw > 0 ? spec_fwd_lds(D.n_psr) : 0;
-  hipLaunchKernelGGL(k_spec_fwd, dim3(nblk), dim3(256), lds, s, D, x);
+  hipLaunchKernelGGL(k_spec_fwd, dim3(nblk), dim3(256), 0, s, D, x);
   return hipGetLastError();
 }
 
 hipError_t launch_spec_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s) {
   const int kmax = max(D.ka, D.nf_dm);
   if (kmax == 0 || D.n_chains == 0) return hipSuccess;
-  const size_t lds = D.nf_gw > 0 ? spec_bwd_lds(D.n_psr) : 0;
-  hipLaunchKernelGGL(k_spec_bwd, dim3(kmax, D.n_chains), dim3(256), lds, s, D, x, grad);
+  hipLaunchKernelGGL(k_spec_bwd, dim3(kmax, D.n_chains), dim3(256), 0, s, D, x, grad);
   return hipGetLastError();
 }
 

@@ -72,7 +72,7 @@ WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
   const size_t D8 = sizeof(double);
   L.coef_rn = take(n * B.rows_rn * cp * D8);
   L.coef_dm = take(n * B.rows_dm * cp * D8);
-  L.lstore = take(cp * B.nf_gw * (n * (n + 1) / 2) * D8);
+  L.lstore = take(cp * B.nf_gw * pt::chol_store_doubles(B.n_psr) * D8);
   L.cwc = take(B.has_cw ? n * pt::kCwConst * cp * D8 : 0);
   L.part_rn = take(nwg * B.rows_rn * 16 * D8);
   L.part_dm = take(nwg * B.rows_dm * 16 * D8);
@@ -194,14 +194,14 @@ hipError_t g_lds_err = hipSuccess;
 
 void set_lds_limits() {
   const size_t plain = (size_t)2 * (64 + 64) * 64 * sizeof(double);
-  g_lds_err = ptk::set_spec_lds_limits(ptk::spec_fwd_lds(PTAFS_MAX_PSR), ptk::spec_bwd_lds(PTAFS_MAX_PSR));
-  if (g_lds_err == hipSuccess) g_lds_err = ptk::set_plain_lds_limit(plain);
+  g_lds_err = ptk::set_plain_lds_limit(plain);
 }
 
 int enqueue_eval(ptafs_dataset *ds, int C, const double *x, double *logp, double *grad,
                  int32_t *status, hipStream_t s, bool plain) {
   const pt::Dev D = make_dev(ds, C);
   PT_TRY(ptk::launch_spec_fwd(D, x, s));
+  PT_TRY(ptk::launch_chol_fwd(D, x, s));
   if (plain) {
     for (int p = 0; p < D.n_psr; ++p) PT_TRY(ptk::launch_toa_plain_psr(D, p, ds->psr_nchunks[p], s));
   } else {
@@ -209,6 +209,7 @@ int enqueue_eval(ptafs_dataset *ds, int C, const double *x, double *logp, double
   }
   PT_TRY(ptk::launch_reduce_chunks(D, s));
   PT_TRY(ptk::launch_spec_bwd(D, x, grad, s));
+  PT_TRY(ptk::launch_chol_bwd(D, x, grad, s));
   PT_TRY(ptk::launch_finalize(D, x, logp, grad, status, s));
   return PTAFS_OK;
 }
@@ -425,6 +426,35 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
   chk(upload(ds, d->psr_pos, (size_t)3 * n, &B.pos));
   chk(upload(ds, gam.data(), (size_t)n * n, &B.gamma));
   chk(upload(ds, gch.data(), gch.size(), &B.gchol));
+  {
+    // the same factor as 16x16 tiles (tile (K, J) at K (K + 1) / 2 + J, row-major
+    // inside), for the matrix-core adjoint of small arrays
+    const int nt = pt::chol_tiles(n);
+    std::vector<double> gt;
+    if (nt <= pt::kTileMaxNT) {
+      gt.assign((size_t)(nt * (nt + 1) / 2) * 256, 0.0);
+      for (int K = 0; K < nt; ++K)
+        for (int J = 0; J <= K; ++J)
+          for (int rr = 0; rr < 16; ++rr)
+            for (int cc = 0; cc < 16; ++cc) {
+              const int r = 16 * K + rr, k = 16 * J + cc;
+              if (r < n && k <= r) gt[(size_t)(K * (K + 1) / 2 + J) * 256 + rr * 16 + cc] = gch[pt::pk(r, k)];
+            }
+    }
+    chk(upload(ds, gt.data(), gt.size(), &B.gtile));
+    std::vector<double> ht;
+    if (nt <= pt::kTileMaxNT) {
+      ht.assign((size_t)(nt * (nt + 1) / 2) * 256, 0.0);
+      for (int K = 0; K < nt; ++K)
+        for (int J = 0; J <= K; ++J)
+          for (int rr = 0; rr < 16; ++rr)
+            for (int cc = 0; cc < 16; ++cc) {
+              const int r = 16 * K + rr, k = 16 * J + cc;
+              if (r < n && k < n) ht[(size_t)(K * (K + 1) / 2 + J) * 256 + rr * 16 + cc] = gam[(size_t)r * n + k];
+            }
+    }
+    chk(upload(ds, ht.data(), ht.size(), &B.gam_tile));
+  }
   chk(upload(ds, d->prior_lo, B.n_theta, &B.prior_lo));
   chk(upload(ds, d->prior_hi, B.n_theta, &B.prior_hi));
   if (!rc) rc = ensure_chunks(ds);
@@ -522,7 +552,11 @@ int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, d
       (void)hipEventRecord(ev[i + 1], s);
     };
     (void)hipEventRecord(ev[0], s);
-    step(0, ptk::launch_spec_fwd(D, x, s));
+    {
+      hipError_t e = ptk::launch_spec_fwd(D, x, s);
+      if (e == hipSuccess) e = ptk::launch_chol_fwd(D, x, s);
+      step(0, e);
+    }
     if (plain) {
       hipError_t e = hipSuccess;
       for (int p = 0; p < D.n_psr && e == hipSuccess; ++p)
@@ -532,7 +566,11 @@ int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, d
       step(1, ptk::launch_toa_mfma(D, ds->wpb, ds->xcd_map, s));
     }
     step(2, ptk::launch_reduce_chunks(D, s));
-    step(3, ptk::launch_spec_bwd(D, x, grad, s));
+    {
+      hipError_t e = ptk::launch_spec_bwd(D, x, grad, s);
+      if (e == hipSuccess) e = ptk::launch_chol_bwd(D, x, grad, s);
+      step(3, e);
+    }
     step(4, ptk::launch_finalize(D, x, logp, grad, status, s));
     if (hipEventSynchronize(ev[kStages]) != hipSuccess) err = PTAFS_E_HIP;
     for (int i = 0; i < kStages && !err; ++i) {
