@@ -46,6 +46,14 @@ __device__ inline double readlane_d(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// 1/sqrt(a): hardware estimate refined by two Newton steps
+__device__ inline double rsqrt_nr(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  y = y * (1.5 - 0.5 * a * y * y);
+  y = y * (1.5 - 0.5 * a * y * y);
+  return y;
+}
+
 // acc += X Y for one 16x16x16 product given the four k-slices of both operands
 __device__ inline v4d mfma4(const v4d &a, const v4d &b, v4d acc) {
   acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc, 0, 0, 0);
@@ -65,7 +73,7 @@ template <int NT>
 __global__ __launch_bounds__(64) void k_cholt_fwd(Dev D, const double *__restrict__ x) {
   constexpr int NP = 16 * NT;
   constexpr int NTILE = NT * (NT + 1) / 2;
-  __shared__ double colb[NT][16];
+  __shared__ double colb[2][NT][16];             // scaled column, double-buffered
   __shared__ double zb[NP][2];
   __shared__ double kb[NP];
   const int k0 = blockIdx.x, c = blockIdx.y;
@@ -120,32 +128,34 @@ __global__ __launch_bounds__(64) void k_cholt_fwd(Dev D, const double *__restric
   bool pd = true;
 #pragma unroll
   for (int J = 0; J < NT; ++J) {
-    // ---- block column J: 16 rank-1 steps
+    // ---- block column J: 16 rank-1 steps.  The broadcast column carries
+    //      zeros in the rows <= cc of the diagonal tile, so the update below
+    //      leaves the finished columns (and column cc) untouched.
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
       const double piv = readlane_d(A[tidx(J, J)][cc >> 2], cc + 16 * (cc & 3));
       pd = pd && (piv > 0.0) && isfinite(piv);
-      const double rd = 1.0 / sqrt(piv);
-      if (q == (cc & 3)) {
+      const double rd = rsqrt_nr(piv);
+      const bool own = q == (cc & 3);
+      double(*cb)[16] = colb[cc & 1];
 #pragma unroll
-        for (int I = J; I < NT; ++I) {
-          const double s = A[tidx(I, J)][cc >> 2] * rd;
-          A[tidx(I, J)][cc >> 2] = s;
-          colb[I][c16] = s;
+      for (int I = J; I < NT; ++I) {
+        const double sv = A[tidx(I, J)][cc >> 2] * rd;
+        if (own) {
+          A[tidx(I, J)][cc >> 2] = sv;
+          cb[I][c16] = (I == J && c16 <= cc) ? 0.0 : sv;
         }
       }
       wave_sync();
       double lk[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) lk[v] = colb[J][q + 4 * v];
+      for (int v = 0; v < 4; ++v) lk[v] = cb[J][q + 4 * v];
 #pragma unroll
       for (int I = J; I < NT; ++I) {
-        const double lr = colb[I][c16];
+        const double lr = cb[I][c16];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (q + 4 * v > cc) A[tidx(I, J)][v] -= lr * lk[v];
+        for (int v = 0; v < 4; ++v) A[tidx(I, J)][v] -= lr * lk[v];
       }
-      wave_sync();
     }
     // ---- trailing tiles: A_IK -= C_IJ C_KJ^T  (as A_IK^T -= C_KJ C_IJ^T)
 #pragma unroll
