@@ -114,6 +114,7 @@ typedef struct {
   int64_t n_psr, n_toa, k_coef, k_dm;
   size_t dataset_bytes;          /* device memory held by the data set itself */
   size_t workspace_bytes;        /* workspace needed for the requested n_chains */
+  size_t hmc_bytes;              /* scratch of ptafs_hmc_run for the requested n_chains */
 } ptafs_layout_info;
 
 /* Copy a data set to the current HIP device and prepare it (per-pulsar tau
@@ -126,6 +127,12 @@ void ptafs_dataset_destroy(ptafs_dataset *ds);
 
 /* Layout of the parameter vector and memory needs for n_chains (>= 0). */
 int ptafs_layout(const ptafs_dataset *ds, int32_t n_chains, ptafs_layout_info *out);
+
+/* The same layout and device footprint for a data set that has not been
+ * created: validates the descriptor (same checks and error codes as
+ * ptafs_dataset_create) and makes no GPU call, so a scheduler can admit work
+ * by memory footprint.  Chunking assumes the default tuning. */
+int ptafs_estimate(const ptafs_dataset_desc *desc, int32_t n_chains, ptafs_layout_info *out);
 
 /* Grow the data set's workspace to serve up to n_chains per call
  * (synchronises the device when it allocates).  Calls with more chains than

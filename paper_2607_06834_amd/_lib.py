@@ -52,11 +52,13 @@ class LayoutInfo(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "d", "n_theta", "off_gw", "off_rn", "off_dm", "off_cw", "off_u", "off_z", "off_zdm",
         "n_psr", "n_toa", "k_coef", "k_dm")] + [
-        ("dataset_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t)]
+        ("dataset_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t),
+        ("hmc_bytes", C.c_size_t)]
 
 
 EXPORTS = (
-    "ptafs_dataset_create", "ptafs_dataset_destroy", "ptafs_layout", "ptafs_reserve",
+    "ptafs_dataset_create", "ptafs_dataset_destroy", "ptafs_layout", "ptafs_estimate",
+    "ptafs_reserve",
     "ptafs_logp_grad", "ptafs_logp_grad_plain", "ptafs_set_tuning", "ptafs_get_tuning",
     "ptafs_hmc_run", "ptafs_profile_stages", "ptafs_strerror",
 )
@@ -80,6 +82,8 @@ def load():
     lib.ptafs_dataset_destroy.restype = None
     lib.ptafs_layout.argtypes = [vp, C.c_int32, C.POINTER(LayoutInfo)]
     lib.ptafs_layout.restype = C.c_int
+    lib.ptafs_estimate.argtypes = [C.POINTER(DatasetDesc), C.c_int32, C.POINTER(LayoutInfo)]
+    lib.ptafs_estimate.restype = C.c_int
     lib.ptafs_reserve.argtypes = [vp, C.c_int32]
     lib.ptafs_reserve.restype = C.c_int
     for name in ("ptafs_logp_grad", "ptafs_logp_grad_plain"):

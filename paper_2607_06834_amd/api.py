@@ -22,6 +22,48 @@ def _stream_handle(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def _make_desc(desc, keep):
+    """ptafs_dataset_desc for a mapping of NumPy arrays / scalars; the arrays
+    it points into are appended to ``keep`` (prior_lo, prior_hi last)."""
+    def arr(name, dtype):
+        a = np.ascontiguousarray(np.asarray(desc[name]), dtype=dtype)
+        keep.append(a)
+        return a
+
+    offs = arr("toa_offsets", np.int64)
+    t, dt = arr("t", np.float64), arr("dt", np.float64)
+    sig, nu = arr("sigma", np.float64), arr("nu", np.float64)
+    be = arr("backend", np.int32)
+    efac, equad = arr("efac", np.float64), arr("equad", np.float64)
+    pos = arr("psr_pos", np.float64)
+    lo, hi = arr("prior_lo", np.float64), arr("prior_hi", np.float64)
+    d = _lib.DatasetDesc()
+    d.n_psr = int(desc["n_psr"])
+    d.toa_offsets = _ptr(offs, C.c_int64)
+    d.t, d.dt, d.sigma, d.nu = (_ptr(a, C.c_double) for a in (t, dt, sig, nu))
+    d.backend = _ptr(be, C.c_int32)
+    d.n_backend = int(efac.size)
+    d.efac, d.equad, d.psr_pos = (_ptr(a, C.c_double) for a in (efac, equad, pos))
+    d.tspan = float(desc["tspan"])
+    d.nf_rn, d.nf_gw, d.nf_dm = int(desc["nf_rn"]), int(desc["nf_gw"]), int(desc["nf_dm"])
+    d.dm_scale = float(desc["dm_scale"])
+    d.sigma_b = float(desc["sigma_b"])
+    d.has_cw = int(desc["has_cw"])
+    d.prior_lo, d.prior_hi = _ptr(lo, C.c_double), _ptr(hi, C.c_double)
+    return d
+
+
+def ptafs_estimate(desc, n_chains):
+    """Layout and device footprint of a data set before it is created
+    (ptafs_estimate: host arithmetic only, no GPU needed)."""
+    keep = []
+    d = _make_desc(desc, keep)
+    out = _lib.LayoutInfo()
+    _lib.check(_lib.load().ptafs_estimate(C.byref(d), int(n_chains), C.byref(out)),
+               "ptafs_estimate")
+    return out
+
+
 class Dataset:
     """A PTA data set resident on the current GPU (ptafs_dataset_create).
 
@@ -34,38 +76,13 @@ class Dataset:
         lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("libptafs needs a HIP GPU")
-        self._keep = []
-
-        def arr(name, dtype):
-            a = np.ascontiguousarray(np.asarray(desc[name]), dtype=dtype)
-            self._keep.append(a)
-            return a
-
-        offs = arr("toa_offsets", np.int64)
-        t, dt = arr("t", np.float64), arr("dt", np.float64)
-        sig, nu = arr("sigma", np.float64), arr("nu", np.float64)
-        be = arr("backend", np.int32)
-        efac, equad = arr("efac", np.float64), arr("equad", np.float64)
-        pos = arr("psr_pos", np.float64)
-        lo, hi = arr("prior_lo", np.float64), arr("prior_hi", np.float64)
-        d = _lib.DatasetDesc()
-        d.n_psr = int(desc["n_psr"])
-        d.toa_offsets = _ptr(offs, C.c_int64)
-        d.t, d.dt, d.sigma, d.nu = (_ptr(a, C.c_double) for a in (t, dt, sig, nu))
-        d.backend = _ptr(be, C.c_int32)
-        d.n_backend = int(efac.size)
-        d.efac, d.equad, d.psr_pos = (_ptr(a, C.c_double) for a in (efac, equad, pos))
-        d.tspan = float(desc["tspan"])
-        d.nf_rn, d.nf_gw, d.nf_dm = int(desc["nf_rn"]), int(desc["nf_gw"]), int(desc["nf_dm"])
-        d.dm_scale = float(desc["dm_scale"])
-        d.sigma_b = float(desc["sigma_b"])
-        d.has_cw = int(desc["has_cw"])
-        d.prior_lo, d.prior_hi = _ptr(lo, C.c_double), _ptr(hi, C.c_double)
+        keep = []
+        d = _make_desc(desc, keep)
+        lo, hi = keep[-2], keep[-1]
         h = C.c_void_p()
         _lib.check(lib.ptafs_dataset_create(C.byref(d), _stream_handle(stream), C.byref(h)),
                    "ptafs_dataset_create")
         self._h = h
-        self._keep = None
         self.prior_lo, self.prior_hi = lo.copy(), hi.copy()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.layout = self.ptafs_layout(0)

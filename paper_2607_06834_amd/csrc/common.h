@@ -176,9 +176,10 @@ hipError_t launch_hmc_kick_drift(int n_chains, int d, double eps, const double *
                                  double *x, double *p, const double *grad, const int32_t *status,
                                  int64_t *n_invalid, hipStream_t s);
 hipError_t launch_hmc_end(int n_chains, int d, double eps, const double *inv_mass, uint64_t seed,
-                          const uint64_t *traj, uint64_t traj0, double *x, double *logp,
+                          const uint64_t *traj, double *x, double *logp,
                           double *grad, double *p, const double *x0, const double *lp0,
                           const double *g0, const double *h0, int64_t *n_accept, double *samples,
                           const int32_t *status, int64_t *n_invalid, hipStream_t s);
 hipError_t launch_traj_inc(uint64_t *traj, hipStream_t s);
+hipError_t launch_traj_set(uint64_t *traj, uint64_t traj0, hipStream_t s);
 }  // namespace ptk

@@ -112,8 +112,7 @@ __global__ __launch_bounds__(256) void k_hmc_kick_drift(size_t n, int d, double 
 
 // final half kick, H1, accept / restore, optional sample
 __global__ __launch_bounds__(256) void k_hmc_end(int d, double eps, const double *inv_mass,
-                                                 uint64_t seed, const uint64_t *traj, uint64_t traj0,
-                                                 int n_chains, double *x, double *logp, double *grad,
+                                                 uint64_t seed, const uint64_t *traj, int n_chains, double *x, double *logp, double *grad,
                                                  double *p, const double *x0, const double *lp0,
                                                  const double *g0, const double *h0,
                                                  int64_t *n_accept, double *samples,
@@ -121,7 +120,7 @@ __global__ __launch_bounds__(256) void k_hmc_end(int d, double eps, const double
   __shared__ double red[256];
   __shared__ int acc_s;
   const int c = blockIdx.x;
-  const uint64_t jj = *traj;
+  const uint64_t jj = traj[0];      // trajectory number; traj[1] = first of this run
   const uint32_t j = (uint32_t)jj;
   const size_t off = (size_t)c * d;
   double kin = 0.0;
@@ -144,7 +143,7 @@ __global__ __launch_bounds__(256) void k_hmc_end(int d, double eps, const double
   }
   __syncthreads();
   const int a = acc_s;
-  double *smp = samples ? samples + ((size_t)(jj - traj0) * n_chains + c) * d : nullptr;
+  double *smp = samples ? samples + ((size_t)(jj - traj[1]) * n_chains + c) * d : nullptr;
   for (int i = threadIdx.x; i < d; i += 256) {
     double xi = x[off + i];
     if (!a) {
@@ -156,7 +155,13 @@ __global__ __launch_bounds__(256) void k_hmc_end(int d, double eps, const double
   }
 }
 
-__global__ void k_traj_inc(uint64_t *traj) { *traj += 1; }
+__global__ void k_traj_inc(uint64_t *traj) { traj[0] += 1; }
+
+// start of a run: trajectory counter and the number of its first trajectory
+__global__ void k_traj_set(uint64_t *traj, uint64_t traj0) {
+  traj[0] = traj0;
+  traj[1] = traj0;
+}
 
 }  // namespace
 
@@ -181,18 +186,23 @@ hipError_t launch_hmc_kick_drift(int n_chains, int d, double eps, const double *
 }
 
 hipError_t launch_hmc_end(int n_chains, int d, double eps, const double *inv_mass, uint64_t seed,
-                          const uint64_t *traj, uint64_t traj0, double *x, double *logp,
+                          const uint64_t *traj, double *x, double *logp,
                           double *grad, double *p, const double *x0, const double *lp0,
                           const double *g0, const double *h0, int64_t *n_accept, double *samples,
                           const int32_t *status, int64_t *n_invalid, hipStream_t s) {
   hipLaunchKernelGGL(k_hmc_end, dim3(n_chains), dim3(256), 0, s, d, eps, inv_mass, seed, traj,
-                     traj0, n_chains, x, logp, grad, p, x0, lp0, g0, h0, n_accept, samples, status,
+                     n_chains, x, logp, grad, p, x0, lp0, g0, h0, n_accept, samples, status,
                      n_invalid);
   return hipGetLastError();
 }
 
 hipError_t launch_traj_inc(uint64_t *traj, hipStream_t s) {
   hipLaunchKernelGGL(k_traj_inc, dim3(1), dim3(1), 0, s, traj);
+  return hipGetLastError();
+}
+
+hipError_t launch_traj_set(uint64_t *traj, uint64_t traj0, hipStream_t s) {
+  hipLaunchKernelGGL(k_traj_set, dim3(1), dim3(1), 0, s, traj, traj0);
   return hipGetLastError();
 }
 

@@ -9,6 +9,8 @@
 
 #include "common.h"
 
+constexpr int kDefaultTilesPerChunk = 16;
+
 struct ptafs_dataset {
   int device = 0;
   pt::Dev base{};
@@ -16,7 +18,7 @@ struct ptafs_dataset {
   std::vector<void *> allocs;
   size_t ds_bytes = 0;
   // tuning and chunk table of the TOA pass
-  int tiles_per_chunk = 16, wpb = 1, xcd_map = 1;
+  int tiles_per_chunk = kDefaultTilesPerChunk, wpb = 1, xcd_map = 1;
   bool chunks_dirty = true;
   int32_t *d_chunk = nullptr;
   std::vector<int> psr_nchunks;
@@ -35,7 +37,7 @@ struct ptafs_dataset {
     int n_chains, n_leapfrog;
     double eps;
     const void *inv_mass, *x, *logp, *grad, *acc, *samples, *invalid;
-    uint64_t seed, traj0;
+    uint64_t seed;
     int tiles, wpb, xcd;
     void *ws, *hmc;
     bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
@@ -253,24 +255,11 @@ void free_all(ptafs_dataset *ds) {
   delete ds;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *ptafs_strerror(int code) {
-  switch (code) {
-    case PTAFS_OK: return "success";
-    case PTAFS_E_ARG: return "invalid argument or unsupported shape";
-    case PTAFS_E_HIP: return "HIP runtime call failed";
-    case PTAFS_E_NOMEM: return "device allocation failed";
-    case PTAFS_E_LIMIT: return "size exceeds an implementation limit";
-  }
-  return "unknown error";
-}
-
-int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_dataset **out) {
-  if (!d || !out) return PTAFS_E_ARG;
-  *out = nullptr;
+// Validate a descriptor and fill the sizes and offsets of a device view
+// (no device pointers, no GPU calls).
+int plan(const ptafs_dataset_desc *d, pt::Dev &B) {
+  B = pt::Dev{};
+  if (!d) return PTAFS_E_ARG;
   const int n = d->n_psr;
   if (n < 1 || !d->toa_offsets) return PTAFS_E_ARG;
   if (n > PTAFS_MAX_PSR) return PTAFS_E_LIMIT;
@@ -291,18 +280,6 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
       return PTAFS_E_ARG;
   }
 
-  ptafs_dataset *ds = new (std::nothrow) ptafs_dataset();
-  if (!ds) return PTAFS_E_NOMEM;
-  if (hipGetDevice(&ds->device) != hipSuccess) {
-    delete ds;
-    return PTAFS_E_HIP;
-  }
-  std::call_once(g_lds_once, set_lds_limits);
-  if (g_lds_err != hipSuccess) {
-    delete ds;
-    return PTAFS_E_HIP;
-  }
-  pt::Dev &B = ds->base;
   B.n_psr = n;
   B.n_toa = (int)ntoa;
   B.n_backend = d->n_backend;
@@ -329,23 +306,87 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
   B.tspan = d->tspan;
   B.dm_scale = d->dm_scale;
   B.sigma_b = d->sigma_b;
-  if (B.n_theta > 0 && (!d->prior_lo || !d->prior_hi)) {
-    delete ds;
-    return PTAFS_E_ARG;
-  }
+  if (B.n_theta > 0 && (!d->prior_lo || !d->prior_hi)) return PTAFS_E_ARG;
   double pc = 0.0;
   for (int i = 0; i < B.n_theta; ++i) {
-    if (!(d->prior_hi[i] > d->prior_lo[i])) {
-      delete ds;
-      return PTAFS_E_ARG;
-    }
+    if (!(d->prior_hi[i] > d->prior_lo[i])) return PTAFS_E_ARG;
     pc -= std::log(d->prior_hi[i] - d->prior_lo[i]);
   }
   B.prior_const = pc;
   double tmax = 0.0;
   for (int64_t i = 0; i < ntoa; ++i) tmax = std::max(tmax, d->t[i]);
   B.tmax = tmax;
+  return PTAFS_OK;
+}
 
+// Number of TOA chunks for a tiles-per-chunk setting (as build_chunks).
+int count_chunks(const int64_t *off, int n, int tpc) {
+  int64_t nc = 0;
+  for (int p = 0; p < n; ++p) {
+    const int64_t tiles = (off[p + 1] - off[p] + 15) / 16;
+    nc += std::max<int64_t>(1, (tiles + tpc - 1) / tpc);
+  }
+  return (int)nc;
+}
+
+// Device bytes held by a data set (the uploads of ptafs_dataset_create and
+// the chunk table).
+size_t dataset_bytes_of(const pt::Dev &B, int n_chunks) {
+  const size_t n = B.n_psr, ntoa = B.n_toa, npad = ntoa + pt::kToaPad;
+  auto a = [](size_t count, size_t size) { return std::max<size_t>(count, 1) * size; };
+  const int nt = pt::chol_tiles(B.n_psr);
+  const size_t tiles = nt <= pt::kTileMaxNT ? (size_t)(nt * (nt + 1) / 2) * 256 : 0;
+  size_t b = 6 * a(npad, 8) + 2 * a(ntoa, 8) + a(ntoa, 4) + 2 * a(B.n_backend, 8) + a(n + 1, 8) +
+             2 * a(n, 8) + a(3 * n, 8) + a(n * n, 8) + a(n * (n + 1) / 2, 8) + 2 * a(tiles, 8) +
+             2 * a(B.n_theta, 8);
+  b += (size_t)(3 * n_chunks + n + 1) * sizeof(int32_t);
+  return b;
+}
+
+// Scratch of ptafs_hmc_run for n_chains.
+size_t hmc_bytes_of(const pt::Dev &B, int n_chains) {
+  const size_t cd = (size_t)n_chains * B.d;
+  return align256(3 * cd * sizeof(double)) + align256(2 * (size_t)n_chains * sizeof(double)) +
+         align256((size_t)n_chains * sizeof(int32_t)) + 256;
+}
+
+}  // namespace
+
+extern "C" {
+
+
+const char *ptafs_strerror(int code) {
+  switch (code) {
+    case PTAFS_OK: return "success";
+    case PTAFS_E_ARG: return "invalid argument or unsupported shape";
+    case PTAFS_E_HIP: return "HIP runtime call failed";
+    case PTAFS_E_NOMEM: return "device allocation failed";
+    case PTAFS_E_LIMIT: return "size exceeds an implementation limit";
+  }
+  return "unknown error";
+}
+
+int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_dataset **out) {
+  if (!d || !out) return PTAFS_E_ARG;
+  *out = nullptr;
+  pt::Dev plan_view;
+  const int prc = plan(d, plan_view);
+  if (prc) return prc;
+  const int n = d->n_psr;
+  const int64_t ntoa = d->toa_offsets[n];
+  ptafs_dataset *ds = new (std::nothrow) ptafs_dataset();
+  if (!ds) return PTAFS_E_NOMEM;
+  if (hipGetDevice(&ds->device) != hipSuccess) {
+    delete ds;
+    return PTAFS_E_HIP;
+  }
+  std::call_once(g_lds_once, set_lds_limits);
+  if (g_lds_err != hipSuccess) {
+    delete ds;
+    return PTAFS_E_HIP;
+  }
+  pt::Dev &B = ds->base;
+  B = plan_view;
   // per-pulsar timing-model centring and the Hellings-Downs matrix
   std::vector<double> tc(n), tsi(n), gam((size_t)n * n);
   for (int p = 0; p < n; ++p) {
@@ -469,9 +510,8 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
 
 void ptafs_dataset_destroy(ptafs_dataset *ds) { free_all(ds); }
 
-int ptafs_layout(const ptafs_dataset *ds, int32_t n_chains, ptafs_layout_info *out) {
-  if (!ds || !out || n_chains < 0) return PTAFS_E_ARG;
-  const pt::Dev &B = ds->base;
+namespace {
+void fill_layout(const pt::Dev &B, int n_chains, int n_chunks, ptafs_layout_info *out) {
   out->d = B.d;
   out->n_theta = B.n_theta;
   out->off_gw = B.off_gw;
@@ -485,9 +525,24 @@ int ptafs_layout(const ptafs_dataset *ds, int32_t n_chains, ptafs_layout_info *o
   out->n_toa = B.n_toa;
   out->k_coef = B.ka;
   out->k_dm = B.nf_dm;
-  out->dataset_bytes = ds->ds_bytes;
-  int nchunks = ds->n_chunks;
-  out->workspace_bytes = ws_layout(B, cpad_of(n_chains), nchunks).total;
+  out->dataset_bytes = dataset_bytes_of(B, n_chunks);
+  out->workspace_bytes = ws_layout(B, cpad_of(n_chains), n_chunks).total;
+  out->hmc_bytes = hmc_bytes_of(B, n_chains);
+}
+}  // namespace
+
+int ptafs_layout(const ptafs_dataset *ds, int32_t n_chains, ptafs_layout_info *out) {
+  if (!ds || !out || n_chains < 0) return PTAFS_E_ARG;
+  fill_layout(ds->base, n_chains, count_chunks(ds->off.data(), ds->base.n_psr, ds->tiles_per_chunk), out);
+  return PTAFS_OK;
+}
+
+int ptafs_estimate(const ptafs_dataset_desc *desc, int32_t n_chains, ptafs_layout_info *out) {
+  if (!desc || !out || n_chains < 0) return PTAFS_E_ARG;
+  pt::Dev B;
+  const int rc = plan(desc, B);
+  if (rc) return rc;
+  fill_layout(B, n_chains, count_chunks(desc->toa_offsets, B.n_psr, kDefaultTilesPerChunk), out);
   return PTAFS_OK;
 }
 
@@ -600,8 +655,7 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   const int d = ds->base.d;
   const size_t cd = (size_t)n_chains * d;
   // scratch: p, x0, g0 [C][d], lp0, h0, status [C], trajectory counter
-  const size_t need = align256(3 * cd * sizeof(double)) + align256(2 * (size_t)n_chains * sizeof(double)) +
-                      align256((size_t)n_chains * sizeof(int32_t)) + 256;
+  const size_t need = hmc_bytes_of(ds->base, n_chains);
   if (need > ds->hmc_bytes) {
     PT_TRY(hipDeviceSynchronize());
     if (ds->gexec) (void)hipGraphExecDestroy(ds->gexec);
@@ -625,9 +679,9 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   int32_t *st = reinterpret_cast<int32_t *>(h3);
   uint64_t *traj = reinterpret_cast<uint64_t *>(h3 + align256((size_t)n_chains * sizeof(int32_t)));
 
-  PT_TRY(hipMemcpyAsync(traj, &traj0, sizeof(uint64_t), hipMemcpyHostToDevice, s));
-  // the host value must stay valid until the copy ran
-  PT_TRY(hipStreamSynchronize(s));
+  // trajectory counter and first trajectory of this run, set on the stream
+  // (no host memory to keep alive, no synchronisation)
+  PT_TRY(ptk::launch_traj_set(traj, traj0, s));
 
   const pt::Dev D = make_dev(ds, n_chains);
   auto one_traj = [&](hipStream_t q) -> int {
@@ -638,8 +692,8 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
       if (l + 1 < n_leapfrog)
         PT_TRY(ptk::launch_hmc_kick_drift(n_chains, d, eps, inv_mass, x, p, grad, st, n_invalid, q));
     }
-    PT_TRY(ptk::launch_hmc_end(n_chains, d, eps, inv_mass, seed, traj, traj0, x, logp, grad, p, x0,
-                               lp0, g0, h0, n_accept, samples, st, n_invalid, q));
+    PT_TRY(ptk::launch_hmc_end(n_chains, d, eps, inv_mass, seed, traj, x, logp, grad, p, x0, lp0,
+                               g0, h0, n_accept, samples, st, n_invalid, q));
     PT_TRY(ptk::launch_traj_inc(traj, q));
     return PTAFS_OK;
   };
@@ -664,7 +718,6 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   key.samples = samples;
   key.invalid = n_invalid;
   key.seed = seed;
-  key.traj0 = traj0;
   key.tiles = ds->tiles_per_chunk;
   key.wpb = ds->wpb;
   key.xcd = ds->xcd_map;

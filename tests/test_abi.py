@@ -53,3 +53,32 @@ def test_slot_mapping_covers_rows():
         pairs = kb + 2
         tiles = (2 * ((pairs + 3) // 4) + 3) // 4
         assert max(rows) < 16 * tiles
+
+
+def test_estimate_without_gpu():
+    """ptafs_estimate sizes a data set from its descriptor on the host: the
+    layout matches the oracle's, memory grows with the data, and invalid
+    descriptors are refused with the create call's error codes."""
+    import numpy as np
+    import synth
+    from oracle import model
+    from paper_2607_06834_amd import api
+    ds = synth.make_array(5, 4, [30, 40, 50, 60], 8 * synth.YEAR_S, backends_per_psr=[1, 2, 1, 2],
+                          nu_range=(0.4e9, 2e9), nf_rn=5, nf_gw=3, nf_dm=4, has_cw=True)
+    est = api.ptafs_estimate(ds, 16)
+    ref = model.Layout(4, 5, 3, 4, True)
+    assert (est.d, est.n_theta, est.off_u, est.off_z, est.off_zdm, est.off_cw) == \
+        (ref.d, ref.n_theta, ref.u, ref.z, ref.zdm, ref.cw)
+    big = synth.make_array(5, 4, [300, 400, 500, 600], 8 * synth.YEAR_S, backends_per_psr=[1, 2, 1, 2],
+                           nu_range=(0.4e9, 2e9), nf_rn=5, nf_gw=3, nf_dm=4, has_cw=True)
+    e2 = api.ptafs_estimate(big, 16)
+    assert e2.dataset_bytes > est.dataset_bytes and e2.workspace_bytes > est.workspace_bytes
+    assert api.ptafs_estimate(ds, 64).workspace_bytes > est.workspace_bytes
+    assert api.ptafs_estimate(ds, 64).hmc_bytes > est.hmc_bytes
+    bad = dict(ds)
+    bad["sigma"] = -np.asarray(ds["sigma"])
+    try:
+        api.ptafs_estimate(bad, 16)
+        raise AssertionError("negative sigma accepted")
+    except RuntimeError as e:
+        assert "invalid argument" in str(e)
