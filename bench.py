@@ -60,6 +60,74 @@ def cpu_baseline(ds, n_chains_sample=8, min_seconds=10.0, seed=204):
                        f"67 psr / 250k TOA workload, {el:.1f} s")
 
 
+def serving_bench(n_traj, rates, n_req, n_chains=16, n_leapfrog=20, quantum=10, max_slots=8,
+                  budget=None, seed0=501, eps=1e-4):
+    """Poisson arrivals of independent data sets (20-120 pulsars, 200-8000
+    TOAs each, 10-30 frequencies, CW with probability 1/2) served with
+    continuous batching; p50/p99 of completion - arrival per rate."""
+    import threading
+    import numpy as np
+    import synth
+    from paper_2607_06834_amd import serve
+
+    pool = []
+    for i in range(n_req):
+        ds = synth.serving_request(seed0 + i)
+        th = synth.injected_theta(ds, seed0 + 1000 + i)
+        x0 = synth.random_points(ds, n_chains, seed0 + 2000 + i, theta=th, theta_jitter=0.02)
+        im = np.ones(x0.shape[1])
+        im[: ds["prior_lo"].size] = 1e-8       # hyper-parameters held near their start
+        pool.append((ds, x0, im))
+    probe = serve.Server(budget_bytes=1 << 40, max_slots=1, quantum=quantum)
+    fps = [probe.footprint(ds, n_chains) for ds, _, _ in pool]
+    probe.close()
+    if budget is None:
+        budget = int(6 * np.median(fps))
+    evals_per_req = n_traj * n_leapfrog * n_chains
+
+    def run(rate, reqs, slots):
+        srv = serve.Server(budget_bytes=budget, max_slots=slots, quantum=quantum)
+        rng = np.random.default_rng(7)
+        gaps = rng.exponential(1.0 / rate, len(reqs)) if rate else np.zeros(len(reqs))
+        ids = []
+        t0 = time.perf_counter()
+        t_next = t0
+        for g, (ds, x0, im) in zip(gaps, reqs):
+            t_next += g
+            while time.perf_counter() < t_next:
+                time.sleep(min(1e-3, max(0.0, t_next - time.perf_counter())))
+            ids.append(srv.submit(ds, x0=x0, n_traj=n_traj, n_leapfrog=n_leapfrog, eps=eps,
+                                  seed=11 + len(ids), inv_mass=im))
+        res = [srv.wait(i, timeout=3600) for i in ids]
+        stats = dict(max_used_bytes=srv.max_used, max_active=srv.max_active)
+        srv.close()
+        lat = np.array([r["latency"] for r in res])
+        t_first = min(r["t_arrival"] for r in res)
+        t_last = max(r["t_done"] for r in res)
+        bad = sum(int(r["n_invalid"].sum()) for r in res)
+        acc = sum(int(r["n_accept"].sum()) for r in res) / (n_chains * n_traj * len(res))
+        return dict(rate=rate, completed=len(res), p50_ms=float(np.percentile(lat, 50) * 1e3),
+                    p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
+                    evals_per_s=evals_per_req * len(res) / (t_last - t_first),
+                    valid_eval_fraction=1.0 - bad / (evals_per_req * len(res) / 1.0),
+                    accept_rate=acc, **stats)
+
+    run(0.0, pool[:1], 1)                  # warm-up (code objects, first graph capture)
+    # service time of a request on an idle GPU (each submitted after the last finished)
+    alone = [run(0.0, [p], 1)["p50_ms"] for p in pool[:6]]
+    out = []
+    for rate in rates:
+        r = run(rate, pool, max_slots)
+        out.append(r)
+        if r["p50_ms"] > 20 * np.median(alone):
+            break                            # saturated
+    return dict(
+        requests_per_rate=n_req, n_traj=n_traj, n_leapfrog=n_leapfrog, n_chains=n_chains,
+        quantum=quantum, max_slots=max_slots, budget_bytes=budget,
+        footprint_bytes_median=int(np.median(fps)), footprint_bytes_max=int(max(fps)),
+        alone_ms_median=float(np.median(alone)), rates=out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +140,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="500 trajectories per request, rates 0.25..8 req/s (long)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -138,6 +209,12 @@ def main():
                      ms_per_eval=round(sum(ps.values()), 4),
                      toa_ms=round(ps["toa"], 4))
     cpu = None if args.no_cpu else cpu_baseline(ds, min_seconds=args.cpu_seconds)
+    serving = None
+    if not args.no_serve:
+        if args.serve_full:
+            serving = serving_bench(500, (0.25, 0.5, 1, 2, 4, 8), 48)
+        else:
+            serving = serving_bench(20, (4, 16, 64), 32)
 
     out = {
         "metric": "grad evals/s, 67 psr/250k TOA FP64: batched vs plain; serve p50/p99 latency",
@@ -178,6 +255,7 @@ def main():
         "accept_rate": float(acc.sum().item()) / (C * args.steps),
         "valid_eval_fraction": valid,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     if tune_log is not None:
         out["autotune"] = tune_log
