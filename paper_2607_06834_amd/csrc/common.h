@@ -17,7 +17,7 @@ constexpr double kTsun = 4.925490947641e-6;      // G Msun / c^3, s
 
 constexpr int kChainBlock = 16;                  // chains per MFMA column block
 constexpr int kToaPad = 128;                     // zero padding of per-TOA arrays
-constexpr int kPrepToas = 1024;                  // TOAs per preparation block
+constexpr int kSpecSeg = 8;                      // frequency segments per chain (spectral kernels)
 constexpr int kTile = 16;                        // TOAs per MFMA row tile
 
 // ---------------------------------------------------------------------------
@@ -104,6 +104,9 @@ struct Dev {
   int ka;        // coefficient frequencies max(nf_rn, nf_gw)
   int kb;        // basis harmonics of the TOA pass max(ka, nf_dm)
   int jt_rn, jt_dm, rows_rn, rows_dm;
+  // coefficient rows no frequency owns (timing model, padding), per block
+  int n_free_rn, n_free_dm;
+  int16_t free_rn[64], free_dm[64];
   int n_theta, d;
   int off_gw, off_rn, off_dm, off_cw, off_u, off_z, off_zdm;
   double tspan, dm_scale, sigma_b, tmax, prior_const;
@@ -116,6 +119,10 @@ struct Dev {
   // per-TOA basis phases, padded by kToaPad zeros: sin, cos of 2 pi t / T,
   // tau = (t - mid_I) / halfspan_I, DM weight w = dm_scale / nu^2
   const double *sth, *cth, *tau, *wdm;
+  // white noise (Eq. WN_cov; EFAC, EQUAD fixed per backend): 1/N per TOA
+  // (zeros in the padding) and sum_i ln N_i
+  const double *invn;
+  double lnn_total;
   const double *pos, *gamma;
   const double *gchol;         // chol(Gamma), packed row-major lower
   const double *gtile;         // chol(Gamma) zero-padded, lower 16x16 tiles (up to kTileMaxNT)
@@ -132,24 +139,55 @@ struct Dev {
   double *cwc;                 // [n_psr][kCwConst][c_pad] per chain/pulsar CW constants
   double *part_rn, *part_dm;   // [n_wg][rows][16]
   double *part_chi, *part_cw;  // [n_wg][16], [n_wg][8][16]
-  double *invn;                // [n_toa + kToaPad] per-call 1/N (zeros in the padding)
-  double *lnn_blk;             // [n_prep] per-call partial sums of ln N
-  int n_prep;                  // TOA-preparation blocks (kPrepToas TOAs each)
+  double *zz_seg;              // [c_pad][kSpecSeg] partial |(u, z, z_dm)|^2
+  int32_t *fin_seg;            // [c_pad][kSpecSeg] 1 if that slice is finite
   double *bar_rn, *bar_dm;     // [n_psr][rows][c_pad]
   double *chi_p, *cw_p;        // [n_psr][c_pad], [n_psr][8][c_pad]
   double *dth_k;               // [c_pad][K][2] gw parts per frequency
   double *drn_k;               // [c_pad][ka][n_psr][2]
   double *ddm_k;               // [c_pad][nf_dm][n_psr][2]
-  double *zsq_k;               // [c_pad][kmax] squared norm of the owned coordinates
+
   int32_t *flag_k;             // [c_pad][kmax] per-frequency condition bits (kFlag*)
   int32_t *st_pre;             // [c_pad] status from the input checks
 };
 
 constexpr int kFlagNotPD = 1;          // phi_k not positive definite
-constexpr int kFlagInNonfinite = 2;    // a non-finite input coordinate
 constexpr int kFlagOutNonfinite = 4;   // a non-finite gradient entry
 
 constexpr int kCwConst = 16;   // rows of the per (chain, pulsar) CW constant table
+
+}  // namespace pt
+
+namespace pt {
+
+// Wave64 / workgroup reductions in a fixed order (deterministic).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline int wave_or(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+// Sum over a 256-thread workgroup; every thread gets the result.
+__device__ inline double block_sum256(double v, double *red4) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red4[w] = v;
+  __syncthreads();
+  return (red4[0] + red4[1]) + (red4[2] + red4[3]);
+}
+__device__ inline int block_or256(int v, int *red4) {
+  v = wave_or(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red4[w] = v;
+  __syncthreads();
+  return red4[0] | red4[1] | red4[2] | red4[3];
+}
 
 }  // namespace pt
 

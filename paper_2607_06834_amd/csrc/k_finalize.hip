@@ -13,20 +13,6 @@ namespace {
 
 using pt::Dev;
 
-template <typename T>
-__device__ T block_sum(T v, T *red) {
-  const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) red[t] = red[t] + red[t + o];
-    __syncthreads();
-  }
-  const T r = red[0];
-  __syncthreads();
-  return r;
-}
-
 // Sum of K <= 32 strided values in index order, with every load issued
 // before the first add (the loads are independent; a plain loop would wait
 // for each one in turn).
@@ -44,8 +30,8 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restric
                                                   double *__restrict__ logp,
                                                   double *__restrict__ grad,
                                                   int32_t *__restrict__ status) {
-  __shared__ double red[256];
-  __shared__ int ired[256];
+  __shared__ double red[4];
+  __shared__ int ired[4];
   const int c = blockIdx.x;
   const int t = threadIdx.x;
   const double *xc = x + (size_t)c * D.d;
@@ -57,32 +43,31 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restric
   // ---- per-chain condition, in the order: prior box, non-finite input,
   //      CW coalescence, phi not positive definite, non-finite output
   int fl = 0;
+  for (int k = t; k < kmax; k += 256) fl |= D.flag_k[(size_t)c * kmax + k];
+  fl = pt::block_or256(fl, ired);
+  // finiteness and squared norm of (u, z, z_dm), from the slices of k_spec_fwd
+  const int nseg = max(1, min(pt::kSpecSeg, kmax));
   double zz = 0.0;
-  for (int k = t; k < kmax; k += 256) {
-    fl |= D.flag_k[(size_t)c * kmax + k];
-    zz += D.zsq_k[(size_t)c * kmax + k];
+  bool fin_in = true;
+  for (int s = 0; s < nseg; ++s) {
+    zz += D.zz_seg[(size_t)c * pt::kSpecSeg + s];
+    fin_in = fin_in && D.fin_seg[(size_t)c * pt::kSpecSeg + s] != 0;
   }
-  const int f_in = block_sum<int>((fl & pt::kFlagInNonfinite) ? 1 : 0, ired);
-  const int f_pd = block_sum<int>((fl & pt::kFlagNotPD) ? 1 : 0, ired);
-  const int f_out = block_sum<int>((fl & pt::kFlagOutNonfinite) ? 1 : 0, ired);
   const int pre = D.st_pre[c];
   int st = 0;
   if (pre == PTAFS_ST_PRIOR) st = PTAFS_ST_PRIOR;
-  else if (f_in) st = PTAFS_ST_NONFINITE;
+  else if (!fin_in) st = PTAFS_ST_NONFINITE;
   else if (pre == PTAFS_ST_CW) st = PTAFS_ST_CW;
-  else if (f_pd) st = PTAFS_ST_NOTPD;
-  else if (f_out) st = PTAFS_ST_NONFINITE;
+  else if (fl & pt::kFlagNotPD) st = PTAFS_ST_NOTPD;
+  else if (fl & pt::kFlagOutNonfinite) st = PTAFS_ST_NONFINITE;
 
   // ---- log p
-  double ch = 0.0, ln = 0.0;
+  double ch = 0.0;
   for (int p = t; p < n; p += 256) ch += D.chi_p[(size_t)p * cp + c];
-  for (int b = t; b < D.n_prep; b += 256) ln += D.lnn_blk[b];
-  zz = block_sum(zz, red);
-  ch = block_sum(ch, red);
-  ln = block_sum(ln, red);
+  ch = pt::block_sum256(ch, red);
   const double dz = (double)(D.d - D.off_u);
-  double lp = -0.5 * ch - 0.5 * ln - 0.5 * (double)D.n_toa * pt::kLn2Pi - 0.5 * zz -
-              0.5 * dz * pt::kLn2Pi + D.prior_const;
+  double lp = -0.5 * ch - 0.5 * D.lnn_total - 0.5 * (double)D.n_toa * pt::kLn2Pi -
+              0.5 * zz - 0.5 * dz * pt::kLn2Pi + D.prior_const;
 
   // ---- hyper-parameter and timing-model gradient (frequency sums in order)
   bool fin = true;
@@ -121,8 +106,8 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restric
       gc[D.off_u + e] = g;
       fin = fin && isfinite(g);
     }
-    const int nbad = block_sum<int>(fin ? 0 : 1, ired);
-    if (nbad || !isfinite(lp)) st = PTAFS_ST_NONFINITE;
+    const bool allfin = __syncthreads_and(fin);
+    if (!allfin || !isfinite(lp)) st = PTAFS_ST_NONFINITE;
   }
   if (st != 0) {
     for (int i = t; i < D.d; i += 256) gc[i] = 0.0;

@@ -1,11 +1,10 @@
-// Per-frequency kernels that need no dense factorisation: power-law spectra
-// (Sec. IV.A, Eq. power_law), the diagonal prior of the frequencies without
-// the common process and the DM prior, with their whitening transforms
-// (Sec. II.B, Eq. standardizing_transform, mu = 0) and adjoints; the input
-// checks, the timing-model rows of the coefficient panels, the CW constants
-// and the per-TOA white-noise preparation (Eq. WN_cov).  One 256-thread
-// workgroup per (frequency, chain).  The frequencies that carry the common
-// process (dense phi_k = rho_k Gamma + diag kappa) are factorised in k_chol.
+// Per-chain kernels of the spectral side that need no dense factorisation:
+// power-law spectra (Sec. IV.A, Eq. power_law), the diagonal prior of the
+// frequencies without the common process and the DM prior with their
+// whitening transforms (Sec. II.B, Eq. standardizing_transform, mu = 0) and
+// adjoints; the input checks, the timing-model rows of the coefficient
+// panels and the CW constants.  The frequencies that carry the common process (dense
+// phi_k = rho_k Gamma + diag kappa) are factorised in k_cholt / k_chol.
 //
 //   diagonal frequencies:  a_Ik = sqrt(kappa_Ik) z_Ik,  dz = sqrt(kappa) abar - z,
 //     d/dlog10A_I = ln10 sqrt(kappa) abar.z,  d/dgamma_I = -1/2 ln(f yr) sqrt(kappa) abar.z
@@ -16,107 +15,54 @@
 namespace {
 
 using pt::Dev;
-
-using pt::pk;
 using pt::powerlaw;
 
-template <typename T>
-__device__ T block_sum(T v, T *red) {
-  const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) red[t] = red[t] + red[t + o];
-    __syncthreads();
-  }
-  const T r = red[0];
-  __syncthreads();
-  return r;
-}
-
-__device__ inline bool block_all(bool v, int *ired) { return block_sum<int>(v ? 0 : 1, ired) == 0; }
-
 // ---------------------------------------------------------------------------
-// Forward: 1-D grid of kmax * c_pad (frequency, chain) blocks followed by
-// n_prep white-noise preparation blocks, block 256.
-// LDS (dense frequencies): A [n][ns] row-major (ns = n | 1), z [2][n], diag [n].
+// Forward: grid (c_pad, segments), block 256.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_spec_fwd(Dev D, const double *__restrict__ x) {
-  __shared__ double red[256];
-  __shared__ int ired[256];
+  __shared__ double red[4];
+  __shared__ int kflag[PTAFS_MAX_HARM];
   const int tid = threadIdx.x;
   const int n = D.n_psr;
   const int kmax = max(D.ka, D.nf_dm);
-  const int nspec = kmax * D.c_pad;
-  if ((int)blockIdx.x >= nspec) {
-    // Heteroscedastic white noise (Eq. WN_cov): N_i = (EFAC sigma_i)^2 + EQUAD^2,
-    // its reciprocal per TOA and a fixed-partition partial sum of ln N_i.
-    const int pb = blockIdx.x - nspec;
-    const int i0 = pb * pt::kPrepToas, i1 = min(D.n_toa, i0 + pt::kPrepToas);
-    double s = 0.0;
-    for (int i = i0 + tid; i < i1; i += 256) {
-      const int be = D.backend[i];
-      const double es = D.efac[be] * D.sigma[i], eq = D.equad[be];
-      const double N = es * es + eq * eq;
-      D.invn[i] = 1.0 / N;
-      s += log(N);
-    }
-    s = block_sum(s, red);
-    if (tid == 0) D.lnn_blk[pb] = s;
-    return;
-  }
-  const int k0 = blockIdx.x % kmax;    // frequency index, harmonic k = k0 + 1
-  const int c = blockIdx.x / kmax;     // chain (padded)
-  const double f = (k0 + 1) / D.tspan;
+  const int c = blockIdx.x;                  // chain (padded)
+  const int seg = blockIdx.y;                // frequency segment: k = seg, seg + kSpecSeg, ...
   const bool real = c < D.n_chains;
   const double *xc = x + (size_t)(real ? c : 0) * D.d;
   const size_t cp = D.c_pad;
 
-  bool inbox = real;
-  if (real) {
-    bool ok = true;
+  // ---- prior box (every segment needs it)
+  bool ok = real;
+  if (real)
     for (int i = tid; i < D.n_theta; i += 256) {
       const double v = xc[i];
       if (!(v >= D.prior_lo[i] && v <= D.prior_hi[i])) ok = false;
     }
-    inbox = block_all(ok, ired);
-  }
-  const bool bad = !inbox;
-
-  // finiteness and squared norm of the coordinates this frequency owns
-  double zz = 0.0;
-  bool fin = true;
-  if (!bad) {
-    if (k0 < D.ka) {
-      const double *zc = xc + D.off_z;
-      for (int e = tid; e < 2 * n; e += 256) {
-        const double v = zc[(e >> 1) * 2 * D.ka + 2 * k0 + (e & 1)];
+  const bool bad = !__syncthreads_and(ok);
+  if (tid < PTAFS_MAX_HARM) kflag[tid] = 0;
+  // finiteness and squared norm of this segment's slice of (u, z, z_dm)
+  {
+    const int nseg = gridDim.y, len = D.d - D.off_u;
+    const int e0 = D.off_u + (int)(((long long)len * seg) / nseg);
+    const int e1 = D.off_u + (int)(((long long)len * (seg + 1)) / nseg);
+    double zz = 0.0;
+    bool fin = true;
+    if (real)
+      for (int e = e0 + tid; e < e1; e += 256) {
+        const double v = xc[e];
         fin = fin && isfinite(v);
         zz += v * v;
       }
-    }
-    if (k0 < D.nf_dm) {
-      const double *zd = xc + D.off_zdm;
-      for (int e = tid; e < 2 * n; e += 256) {
-        const double v = zd[(e >> 1) * 2 * D.nf_dm + 2 * k0 + (e & 1)];
-        fin = fin && isfinite(v);
-        zz += v * v;
-      }
-    }
-    if (k0 == 0) {
-      for (int e = tid; e < 3 * n; e += 256) {
-        const double v = xc[D.off_u + e];
-        fin = fin && isfinite(v);
-        zz += v * v;
-      }
+    zz = pt::block_sum256(zz, red);
+    fin = __syncthreads_and(fin);
+    if (tid == 0) {
+      D.zz_seg[(size_t)c * pt::kSpecSeg + seg] = zz;
+      D.fin_seg[(size_t)c * pt::kSpecSeg + seg] = fin ? 1 : 0;
     }
   }
-  zz = block_sum(zz, red);
-  fin = block_all(fin, ired);
-  int flag = fin ? 0 : pt::kFlagInNonfinite;
 
-  if (k0 == 0) {
-    // per-chain status from the hyper-parameters, and the rows no frequency owns
+  if (seg == 0) {
     int st = 0;
     if (real && bad) st = PTAFS_ST_PRIOR;
     if (real && !bad && D.has_cw) {
@@ -139,163 +85,137 @@ __global__ __launch_bounds__(256) void k_spec_fwd(Dev D, const double *__restric
         for (int j = 0; j < pt::kCwRows; ++j) dst[(size_t)j * cp] = v[j];
       }
     }
-    for (int idx = tid; idx < n * D.rows_rn; idx += 256) {
-      const int I = idx / D.rows_rn, row = idx % D.rows_rn;
+    // coefficient rows no frequency owns: timing model b = sigma_b u, zeros
+    for (int idx = tid; idx < n * D.n_free_rn; idx += 256) {
+      const int I = idx / D.n_free_rn, row = D.free_rn[idx - I * D.n_free_rn];
       const pt::Slot sl = pt::rn_slot(row, D.kb);
-      double v;
-      if (sl.kind == 1) v = zero ? 0.0 : D.sigma_b * xc[D.off_u + 3 * I + sl.tm];
-      else if (sl.kind == 0 && sl.harm <= D.ka) continue;     // owned by frequency harm
-      else v = 0.0;
+      const double v = (sl.kind == 1 && !zero) ? D.sigma_b * xc[D.off_u + 3 * I + sl.tm] : 0.0;
       D.coef_rn[((size_t)I * D.rows_rn + row) * cp + c] = v;
     }
-    for (int idx = tid; idx < n * D.rows_dm; idx += 256) {
-      const int I = idx / D.rows_dm, row = idx % D.rows_dm;
-      const pt::Slot sl = pt::dm_slot(row, D.nf_dm);
-      if (sl.kind == 0) continue;
+    for (int idx = tid; idx < n * D.n_free_dm; idx += 256) {
+      const int I = idx / D.n_free_dm, row = D.free_dm[idx - I * D.n_free_dm];
       D.coef_dm[((size_t)I * D.rows_dm + row) * cp + c] = 0.0;
     }
   }
+  __syncthreads();
 
-  // ---- red-noise / common block, harmonic k0 + 1 ---------------------------
-  if (k0 < D.ka) {
+  // ---- this segment's frequencies: diagonal prior (no common process),
+  //      L = diag(sqrt(kappa)), and the DM prior; thread = (frequency, pulsar)
+  const int nks = (kmax - seg + pt::kSpecSeg - 1) / pt::kSpecSeg;
+  const int K2 = 2 * D.ka, K2d = 2 * D.nf_dm;
+  for (int idx = tid; idx < nks * n; idx += 256) {
+    const int j = idx / n, I = idx - j * n;
+    const int k0 = seg + pt::kSpecSeg * j;
     const int rs = pt::harm_row(k0 + 1, 0), rc = pt::harm_row(k0 + 1, 1);
-    const double *zc = xc + D.off_z;
-    const int K2 = 2 * D.ka;
-    const bool dense = k0 < D.nf_gw;
-    if (bad) {
-      for (int I = tid; I < n; I += 256) {
-        D.coef_rn[((size_t)I * D.rows_rn + rs) * cp + c] = 0.0;
-        D.coef_rn[((size_t)I * D.rows_rn + rc) * cp + c] = 0.0;
-      }
-    } else if (!dense) {
-      // phi_k = diag(kappa): L = diag(sqrt(kappa))
-      bool pd = true;
-      for (int I = tid; I < n; I += 256) {
-        const double *th = xc + D.off_rn + 2 * I;
-        const double kap = (k0 < D.nf_rn) ? powerlaw(f, th[0], th[1], D.tspan) : 0.0;
-        if (!(kap > 0.0) || !isfinite(kap)) pd = false;
-        const double sq = sqrt(kap);
-        D.coef_rn[((size_t)I * D.rows_rn + rs) * cp + c] = sq * zc[I * K2 + 2 * k0];
-        D.coef_rn[((size_t)I * D.rows_rn + rc) * cp + c] = sq * zc[I * K2 + 2 * k0 + 1];
-      }
-      if (!block_all(pd, ired)) flag |= pt::kFlagNotPD;
-    }
-    // dense frequencies: factorisation and transform in k_chol_fwd
-  }
-
-  // ---- DM block -------------------------------------------------------------
-  if (k0 < D.nf_dm) {
-    const int rs = pt::harm_row(k0 + 1, 0), rc = pt::harm_row(k0 + 1, 1);
-    const double *zd = xc + D.off_zdm;
-    const int K2 = 2 * D.nf_dm;
-    for (int I = tid; I < n; I += 256) {
+    const double f = (k0 + 1) / D.tspan;
+    if (k0 >= D.nf_gw && k0 < D.ka) {
       double vs = 0.0, vc = 0.0;
       if (!bad) {
-        const double *th = xc + D.off_dm + 2 * I;
-        const double sq = sqrt(powerlaw(f, th[0], th[1], D.tspan));
-        vs = sq * zd[I * K2 + 2 * k0];
-        vc = sq * zd[I * K2 + 2 * k0 + 1];
+        const double kap =
+            (k0 < D.nf_rn) ? powerlaw(f, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1], D.tspan) : 0.0;
+        if (!(kap > 0.0) || !isfinite(kap)) atomicOr(&kflag[k0], pt::kFlagNotPD);
+        const double sq = sqrt(kap);
+        vs = sq * xc[D.off_z + I * K2 + 2 * k0];
+        vc = sq * xc[D.off_z + I * K2 + 2 * k0 + 1];
+      }
+      D.coef_rn[((size_t)I * D.rows_rn + rs) * cp + c] = vs;
+      D.coef_rn[((size_t)I * D.rows_rn + rc) * cp + c] = vc;
+    }
+    if (k0 < D.nf_dm) {
+      double vs = 0.0, vc = 0.0;
+      if (!bad) {
+        const double sq = sqrt(powerlaw(f, xc[D.off_dm + 2 * I], xc[D.off_dm + 2 * I + 1], D.tspan));
+        vs = sq * xc[D.off_zdm + I * K2d + 2 * k0];
+        vc = sq * xc[D.off_zdm + I * K2d + 2 * k0 + 1];
       }
       D.coef_dm[((size_t)I * D.rows_dm + rs) * cp + c] = vs;
       D.coef_dm[((size_t)I * D.rows_dm + rc) * cp + c] = vc;
     }
   }
-  if (tid == 0) {
-    D.flag_k[(size_t)c * kmax + k0] = bad ? 0 : flag;
-    D.zsq_k[(size_t)c * kmax + k0] = bad ? 0.0 : zz;
+  __syncthreads();
+  // owned flags; the dense frequencies add kFlagNotPD later (k_cholt / k_chol)
+  for (int j = tid; j < nks; j += 256) {
+    const int k0 = seg + pt::kSpecSeg * j;
+    D.flag_k[(size_t)c * kmax + k0] = bad ? 0 : kflag[k0];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Backward: grid (kmax, n_chains), block 256.
-// LDS (dense frequencies): Lp, Wp packed over nb*16 rows, vectors.
+// Backward: grid (n_chains, segments), block 256 (the diagonal and DM
+// frequencies; the dense ones are in k_cholt / k_chol).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_spec_bwd(Dev D, const double *__restrict__ x,
                                                   double *__restrict__ grad) {
-  __shared__ int ired[256];
-  const int k0 = blockIdx.x;
-  const int c = blockIdx.y;
+  const int c = blockIdx.x, seg = blockIdx.y;
   const int tid = threadIdx.x;
   const int n = D.n_psr;
   const int kmax = max(D.ka, D.nf_dm);
-  const double f = (k0 + 1) / D.tspan;
-  const double lnfy = log(f * pt::kYear);
   const double *xc = x + (size_t)c * D.d;
   double *gc = grad + (size_t)c * D.d;
   const size_t cp = D.c_pad;
-  const int fl0 = D.flag_k[(size_t)c * kmax + k0];
-  const bool skip = D.st_pre[c] != 0 || fl0 != 0;
+  int fl = 0;
+  for (int k = tid; k < kmax; k += 256) fl |= D.flag_k[(size_t)c * kmax + k];
+  const bool skip = __syncthreads_or(fl != 0 || D.st_pre[c] != 0);
   bool fin = true;
 
-  if (k0 < D.ka) {
+  const int nks = (kmax - seg + pt::kSpecSeg - 1) / pt::kSpecSeg;
+  const int K2 = 2 * D.ka, K2d = 2 * D.nf_dm;
+  for (int idx = tid; idx < nks * n; idx += 256) {
+    const int j = idx / n, I = idx - j * n;
+    const int k0 = seg + pt::kSpecSeg * j;
     const int rs = pt::harm_row(k0 + 1, 0), rc = pt::harm_row(k0 + 1, 1);
-    const double *zc = xc + D.off_z;
-    const int K2 = 2 * D.ka;
-    const bool dense = k0 < D.nf_gw;
-    double *dth = D.dth_k + ((size_t)c * D.ka + k0) * 2;
-    double *drn = D.drn_k + ((size_t)c * D.ka + k0) * n * 2;
-    if (dense) {
-      // dense frequencies: adjoint in k_chol_bwd
-    } else if (skip) {
-      for (int I = tid; I < n; I += 256) {
-        gc[D.off_z + I * K2 + 2 * k0] = 0.0;
-        gc[D.off_z + I * K2 + 2 * k0 + 1] = 0.0;
-        drn[2 * I] = 0.0;
-        drn[2 * I + 1] = 0.0;
-      }
-      if (tid == 0) { dth[0] = 0.0; dth[1] = 0.0; }
-    } else if (!dense) {
-      for (int I = tid; I < n; I += 256) {
-        const double *th = xc + D.off_rn + 2 * I;
-        const double sq = sqrt(powerlaw(f, th[0], th[1], D.tspan));
+    const double f = (k0 + 1) / D.tspan;
+    const double lnfy = log(f * pt::kYear);
+    if (k0 >= D.nf_gw && k0 < D.ka) {
+      double *drn = D.drn_k + ((size_t)c * D.ka + k0) * n * 2;
+      double g_s = 0.0, g_c = 0.0, d0 = 0.0, d1 = 0.0;
+      if (!skip) {
+        const double sq = sqrt(powerlaw(f, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1], D.tspan));
         const double ab_s = D.bar_rn[((size_t)I * D.rows_rn + rs) * cp + c];
         const double ab_c = D.bar_rn[((size_t)I * D.rows_rn + rc) * cp + c];
-        const double z_s = zc[I * K2 + 2 * k0], z_c = zc[I * K2 + 2 * k0 + 1];
-        const double g_s = sq * ab_s - z_s, g_c = sq * ab_c - z_c;
-        gc[D.off_z + I * K2 + 2 * k0] = g_s;
-        gc[D.off_z + I * K2 + 2 * k0 + 1] = g_c;
+        const double z_s = xc[D.off_z + I * K2 + 2 * k0], z_c = xc[D.off_z + I * K2 + 2 * k0 + 1];
+        g_s = sq * ab_s - z_s;
+        g_c = sq * ab_c - z_c;
         // d sqrt(kappa)/d log10A = ln10 sqrt(kappa); d/dgamma = -1/2 ln(f yr) sqrt(kappa)
         const double az = (ab_s * z_s + ab_c * z_c) * sq;
-        const double d0 = (k0 < D.nf_rn) ? az * pt::kLn10 : 0.0;
-        const double d1 = (k0 < D.nf_rn) ? az * (-0.5 * lnfy) : 0.0;
-        drn[2 * I] = d0;
-        drn[2 * I + 1] = d1;
+        d0 = (k0 < D.nf_rn) ? az * pt::kLn10 : 0.0;
+        d1 = (k0 < D.nf_rn) ? az * (-0.5 * lnfy) : 0.0;
         fin = fin && isfinite(g_s) && isfinite(g_c) && isfinite(d0) && isfinite(d1);
       }
-      if (tid == 0) { dth[0] = 0.0; dth[1] = 0.0; }
-    }
-  }
-
-  if (k0 < D.nf_dm) {
-    const int rs = pt::harm_row(k0 + 1, 0), rc = pt::harm_row(k0 + 1, 1);
-    const double *zd = xc + D.off_zdm;
-    const int K2 = 2 * D.nf_dm;
-    double *ddm = D.ddm_k + ((size_t)c * D.nf_dm + k0) * n * 2;
-    for (int I = tid; I < n; I += 256) {
-      if (skip) {
-        gc[D.off_zdm + I * K2 + 2 * k0] = 0.0;
-        gc[D.off_zdm + I * K2 + 2 * k0 + 1] = 0.0;
-        ddm[2 * I] = 0.0;
-        ddm[2 * I + 1] = 0.0;
-        continue;
+      gc[D.off_z + I * K2 + 2 * k0] = g_s;
+      gc[D.off_z + I * K2 + 2 * k0 + 1] = g_c;
+      drn[2 * I] = d0;
+      drn[2 * I + 1] = d1;
+      if (I == 0) {
+        double *dth = D.dth_k + ((size_t)c * D.ka + k0) * 2;
+        dth[0] = 0.0;
+        dth[1] = 0.0;
       }
-      const double *th = xc + D.off_dm + 2 * I;
-      const double sq = sqrt(powerlaw(f, th[0], th[1], D.tspan));
-      const double ab_s = D.bar_dm[((size_t)I * D.rows_dm + rs) * cp + c];
-      const double ab_c = D.bar_dm[((size_t)I * D.rows_dm + rc) * cp + c];
-      const double z_s = zd[I * K2 + 2 * k0], z_c = zd[I * K2 + 2 * k0 + 1];
-      const double g_s = sq * ab_s - z_s, g_c = sq * ab_c - z_c;
-      gc[D.off_zdm + I * K2 + 2 * k0] = g_s;
-      gc[D.off_zdm + I * K2 + 2 * k0 + 1] = g_c;
-      const double az = (ab_s * z_s + ab_c * z_c) * sq;
-      const double d0 = az * pt::kLn10, d1 = az * (-0.5 * lnfy);
+    }
+    if (k0 < D.nf_dm) {
+      double *ddm = D.ddm_k + ((size_t)c * D.nf_dm + k0) * n * 2;
+      double g_s = 0.0, g_c = 0.0, d0 = 0.0, d1 = 0.0;
+      if (!skip) {
+        const double sq = sqrt(powerlaw(f, xc[D.off_dm + 2 * I], xc[D.off_dm + 2 * I + 1], D.tspan));
+        const double ab_s = D.bar_dm[((size_t)I * D.rows_dm + rs) * cp + c];
+        const double ab_c = D.bar_dm[((size_t)I * D.rows_dm + rc) * cp + c];
+        const double z_s = xc[D.off_zdm + I * K2d + 2 * k0], z_c = xc[D.off_zdm + I * K2d + 2 * k0 + 1];
+        g_s = sq * ab_s - z_s;
+        g_c = sq * ab_c - z_c;
+        const double az = (ab_s * z_s + ab_c * z_c) * sq;
+        d0 = az * pt::kLn10;
+        d1 = az * (-0.5 * lnfy);
+        fin = fin && isfinite(g_s) && isfinite(g_c) && isfinite(d0) && isfinite(d1);
+      }
+      gc[D.off_zdm + I * K2d + 2 * k0] = g_s;
+      gc[D.off_zdm + I * K2d + 2 * k0 + 1] = g_c;
       ddm[2 * I] = d0;
       ddm[2 * I + 1] = d1;
-      fin = fin && isfinite(g_s) && isfinite(g_c) && isfinite(d0) && isfinite(d1);
     }
   }
-  fin = block_all(fin, ired);
-  if (tid == 0 && !fin) D.flag_k[(size_t)c * kmax + k0] = fl0 | pt::kFlagOutNonfinite;
+  fin = __syncthreads_and(fin);
+  // this segment's first frequency carries the flag (read only by k_finalize)
+  if (tid == 0 && !fin) D.flag_k[(size_t)c * kmax + seg] |= pt::kFlagOutNonfinite;
 }
 
 }  // namespace
@@ -304,16 +224,17 @@ namespace ptk {
 
 hipError_t launch_spec_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
   const int kmax = max(D.ka, D.nf_dm);
-  const int nblk = kmax * D.c_pad + D.n_prep;
-  if (nblk == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_spec_fwd, dim3(nblk), dim3(256), 0, s, D, x);
+  const int nseg = max(1, min(pt::kSpecSeg, kmax));
+  if (D.c_pad == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_spec_fwd, dim3(D.c_pad, nseg), dim3(256), 0, s, D, x);
   return hipGetLastError();
 }
 
 hipError_t launch_spec_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s) {
+  if (D.n_chains == 0) return hipSuccess;
   const int kmax = max(D.ka, D.nf_dm);
-  if (kmax == 0 || D.n_chains == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_spec_bwd, dim3(kmax, D.n_chains), dim3(256), 0, s, D, x, grad);
+  const int nseg = max(1, min(pt::kSpecSeg, kmax));
+  hipLaunchKernelGGL(k_spec_bwd, dim3(D.n_chains, nseg), dim3(256), 0, s, D, x, grad);
   return hipGetLastError();
 }
 

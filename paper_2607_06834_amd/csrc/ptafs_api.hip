@@ -54,11 +54,10 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-int n_prep_of(int n_toa) { return (n_toa + pt::kPrepToas - 1) / pt::kPrepToas; }
 
 struct WsLayout {
-  size_t coef_rn, coef_dm, lstore, cwc, part_rn, part_dm, part_chi, part_cw, invn, lnn_blk, bar_rn,
-      bar_dm, chi_p, cw_p, dth_k, drn_k, ddm_k, zsq_k, flag_k, st_pre, total;
+  size_t coef_rn, coef_dm, lstore, cwc, part_rn, part_dm, part_chi, part_cw, zz_seg, fin_seg,
+      bar_rn, bar_dm, chi_p, cw_p, dth_k, drn_k, ddm_k, flag_k, st_pre, total;
 };
 
 WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
@@ -80,8 +79,8 @@ WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
   L.part_dm = take(nwg * B.rows_dm * 16 * D8);
   L.part_chi = take(nwg * 16 * D8);
   L.part_cw = take(nwg * 8 * 16 * D8);
-  L.invn = take(((size_t)B.n_toa + pt::kToaPad) * D8);
-  L.lnn_blk = take((size_t)n_prep_of(B.n_toa) * D8);
+  L.zz_seg = take(cp * pt::kSpecSeg * D8);
+  L.fin_seg = take(cp * pt::kSpecSeg * sizeof(int32_t));
   L.bar_rn = take(n * B.rows_rn * cp * D8);
   L.bar_dm = take(n * B.rows_dm * cp * D8);
   L.chi_p = take(n * cp * D8);
@@ -89,7 +88,6 @@ WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
   L.dth_k = take(cp * B.ka * 2 * D8);
   L.drn_k = take(cp * B.ka * n * 2 * D8);
   L.ddm_k = take(cp * B.nf_dm * n * 2 * D8);
-  L.zsq_k = take(cp * kmax * D8);
   L.flag_k = take(cp * kmax * sizeof(int32_t));
   L.st_pre = take(cp * sizeof(int32_t));
   L.total = o;
@@ -174,9 +172,8 @@ pt::Dev make_dev(const ptafs_dataset *ds, int n_chains) {
   D.part_rn = reinterpret_cast<double *>(w + L.part_rn);
   D.part_dm = reinterpret_cast<double *>(w + L.part_dm);
   D.part_chi = reinterpret_cast<double *>(w + L.part_chi);
-  D.invn = reinterpret_cast<double *>(w + L.invn);
-  D.lnn_blk = reinterpret_cast<double *>(w + L.lnn_blk);
-  D.n_prep = n_prep_of(D.n_toa);
+  D.zz_seg = reinterpret_cast<double *>(w + L.zz_seg);
+  D.fin_seg = reinterpret_cast<int32_t *>(w + L.fin_seg);
   D.part_cw = reinterpret_cast<double *>(w + L.part_cw);
   D.bar_rn = reinterpret_cast<double *>(w + L.bar_rn);
   D.bar_dm = reinterpret_cast<double *>(w + L.bar_dm);
@@ -185,7 +182,6 @@ pt::Dev make_dev(const ptafs_dataset *ds, int n_chains) {
   D.dth_k = reinterpret_cast<double *>(w + L.dth_k);
   D.drn_k = reinterpret_cast<double *>(w + L.drn_k);
   D.ddm_k = reinterpret_cast<double *>(w + L.ddm_k);
-  D.zsq_k = reinterpret_cast<double *>(w + L.zsq_k);
   D.flag_k = reinterpret_cast<int32_t *>(w + L.flag_k);
   D.st_pre = reinterpret_cast<int32_t *>(w + L.st_pre);
   return D;
@@ -293,6 +289,13 @@ int plan(const ptafs_dataset_desc *d, pt::Dev &B) {
   B.jt_dm = d->nf_dm > 0 ? pt::tiles_for_pairs(d->nf_dm) : 0;
   B.rows_rn = 16 * B.jt_rn;
   B.rows_dm = 16 * B.jt_dm;
+  B.n_free_rn = B.n_free_dm = 0;
+  for (int r = 0; r < B.rows_rn; ++r) {
+    const pt::Slot sl = pt::rn_slot(r, kb);
+    if (sl.kind != 0 || sl.harm > ka) B.free_rn[B.n_free_rn++] = (int16_t)r;
+  }
+  for (int r = 0; r < B.rows_dm; ++r)
+    if (pt::dm_slot(r, d->nf_dm).kind != 0) B.free_dm[B.n_free_dm++] = (int16_t)r;
   int o = 0;
   B.off_gw = o; o += d->nf_gw > 0 ? 2 : 0;
   B.off_rn = o; o += d->nf_rn > 0 ? 2 * n : 0;
@@ -336,7 +339,7 @@ size_t dataset_bytes_of(const pt::Dev &B, int n_chunks) {
   auto a = [](size_t count, size_t size) { return std::max<size_t>(count, 1) * size; };
   const int nt = pt::chol_tiles(B.n_psr);
   const size_t tiles = nt <= pt::kTileMaxNT ? (size_t)(nt * (nt + 1) / 2) * 256 : 0;
-  size_t b = 6 * a(npad, 8) + 2 * a(ntoa, 8) + a(ntoa, 4) + 2 * a(B.n_backend, 8) + a(n + 1, 8) +
+  size_t b = 7 * a(npad, 8) + 2 * a(ntoa, 8) + a(ntoa, 4) + 2 * a(B.n_backend, 8) + a(n + 1, 8) +
              2 * a(n, 8) + a(3 * n, 8) + a(n * n, 8) + a(n * (n + 1) / 2, 8) + 2 * a(tiles, 8) +
              2 * a(B.n_theta, 8);
   b += (size_t)(3 * n_chunks + n + 1) * sizeof(int32_t);
@@ -436,7 +439,8 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
   // per-TOA basis phases, zero-padded for the prefetch of the TOA pass
   const size_t npad = (size_t)ntoa + pt::kToaPad;
   std::vector<double> vs(npad, 0.0), vc(npad, 0.0), vt(npad, 0.0), vw(npad, 0.0), vdt(npad, 0.0),
-      vtt(npad, 0.0);
+      vtt(npad, 0.0), vin(npad, 0.0);
+  double lnn = 0.0;
   for (int p = 0; p < n; ++p)
     for (int64_t i = d->toa_offsets[p]; i < d->toa_offsets[p + 1]; ++i) {
       const double ph = pt::kTwoPi * (d->t[i] / d->tspan);
@@ -446,6 +450,11 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
       vw[i] = d->dm_scale / (d->nu[i] * d->nu[i]);
       vdt[i] = d->dt[i];
       vtt[i] = d->t[i];
+      const int be = d->backend[i];
+      const double es = d->efac[be] * d->sigma[i], eq = d->equad[be];
+      const double N = es * es + eq * eq;
+      vin[i] = 1.0 / N;
+      lnn += std::log(N);
     }
 
   int rc = PTAFS_OK;
@@ -456,6 +465,8 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
   chk(upload(ds, vc.data(), npad, &B.cth));
   chk(upload(ds, vt.data(), npad, &B.tau));
   chk(upload(ds, vw.data(), npad, &B.wdm));
+  chk(upload(ds, vin.data(), npad, &B.invn));
+  B.lnn_total = lnn;
   chk(upload(ds, d->sigma, ntoa, &B.sigma));
   chk(upload(ds, d->nu, ntoa, &B.nu));
   chk(upload(ds, d->backend, ntoa, &B.backend));
