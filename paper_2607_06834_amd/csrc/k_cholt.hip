@@ -64,20 +64,31 @@ __device__ inline v4d mfma4(const v4d &a, const v4d &b, v4d acc) {
 }
 
 __host__ __device__ constexpr int tidx(int I, int J) { return I * (I + 1) / 2 + J; }
+
+// independent (frequency, chain) problems per workgroup, one wave each
+constexpr int kProbPerGroup = 4;
+
 __device__ inline int pi16(int c) { return 4 * (c & 3) + (c >> 2); }
 
 // ---------------------------------------------------------------------------
-// Forward: grid (nf_gw, c_pad), block 64.
+// Forward: one wave per (frequency, chain) problem, nf_gw * c_pad problems.
 // ---------------------------------------------------------------------------
 template <int NT>
-__global__ __launch_bounds__(64) void k_cholt_fwd(Dev D, const double *__restrict__ x) {
+__global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const double *__restrict__ x) {
   constexpr int NP = 16 * NT;
   constexpr int NTILE = NT * (NT + 1) / 2;
-  __shared__ double colb[2][NT][16];             // scaled column, double-buffered
-  __shared__ double zb[NP][2];
-  __shared__ double kb[NP];
-  const int k0 = blockIdx.x, c = blockIdx.y;
-  const int l = threadIdx.x, c16 = l & 15, q = l >> 4;
+  __shared__ double colb_[kProbPerGroup][2][NT][16];   // scaled column, double-buffered
+  __shared__ double zb_[kProbPerGroup][NP][2];
+  __shared__ double kb_[kProbPerGroup][NP];
+  // one wave per (frequency, chain) problem, kProbPerGroup problems per workgroup
+  const int w = threadIdx.x >> 6;
+  const int prob = blockIdx.x * kProbPerGroup + w;
+  if (prob >= D.nf_gw * D.c_pad) return;
+  const int k0 = prob % D.nf_gw, c = prob / D.nf_gw;
+  const int l = threadIdx.x & 63, c16 = l & 15, q = l >> 4;
+  double(*colb)[NT][16] = colb_[w];
+  double(*zb)[2] = zb_[w];
+  double *kb = kb_[w];
   const int n = D.n_psr;
   const size_t cp = D.c_pad;
   const int rs = pt::harm_row(k0 + 1, 0), rc = pt::harm_row(k0 + 1, 1);
@@ -133,6 +144,8 @@ __global__ __launch_bounds__(64) void k_cholt_fwd(Dev D, const double *__restric
     //      leaves the finished columns (and column cc) untouched.
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
+      // padding columns of the last tile: pivot 1, zero column, nothing to do
+      if (J == NT - 1 && 16 * J + cc >= n) continue;
       const double piv = readlane_d(A[tidx(J, J)][cc >> 2], cc + 16 * (cc & 3));
       pd = pd && (piv > 0.0) && isfinite(piv);
       const double rd = rsqrt_nr(piv);
@@ -214,7 +227,7 @@ __global__ __launch_bounds__(64) void k_cholt_fwd(Dev D, const double *__restric
 }
 
 // ---------------------------------------------------------------------------
-// Backward: grid (nf_gw, n_chains), block 64.
+// Backward: one wave per (frequency, chain) problem, nf_gw * n_chains problems.
 // ---------------------------------------------------------------------------
 struct ScanState {
   double rs, rc, q;   // running column sums of z x (sin, cos) and the quadratic form
@@ -257,7 +270,7 @@ __device__ inline void scan_tile(const v4d &X, int row0, const double (*vz)[4], 
 }
 
 template <int NT>
-__global__ __launch_bounds__(64) void k_cholt_bwd(Dev D, const double *__restrict__ x,
+__global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const double *__restrict__ x,
                                                   double *__restrict__ grad,
                                                   const double *__restrict__ lst,
                                                   const double *__restrict__ gch,
@@ -265,10 +278,18 @@ __global__ __launch_bounds__(64) void k_cholt_bwd(Dev D, const double *__restric
   constexpr int NP = 16 * NT;
   constexpr int NTILE = NT * (NT + 1) / 2;
   constexpr int TS = 17;                              // LDS row stride of a tile
-  __shared__ double vz[NP][4];                        // v_sin, v_cos, z_sin, z_cos
-  __shared__ double tl[NTILE > 2 * NT ? NTILE : 2 * NT][16 * TS];
-  const int k0 = blockIdx.x, c = blockIdx.y;
-  const int l = threadIdx.x, c16 = l & 15, q = l >> 4;
+  constexpr int NTL = NTILE > 2 * NT ? NTILE : 2 * NT;
+  __shared__ double vz_[kProbPerGroup][NP][4];         // v_sin, v_cos, z_sin, z_cos
+  __shared__ double tl_[kProbPerGroup][NTL][16 * TS];
+  __shared__ double ab_[kProbPerGroup][NP][2];
+  const int w = threadIdx.x >> 6;
+  const int prob = blockIdx.x * kProbPerGroup + w;
+  if (prob >= D.nf_gw * D.n_chains) return;
+  const int k0 = prob % D.nf_gw, c = prob / D.nf_gw;
+  const int l = threadIdx.x & 63, c16 = l & 15, q = l >> 4;
+  double(*vz)[4] = vz_[w];
+  double(*tl)[16 * TS] = tl_[w];
+  double(*ab)[2] = ab_[w];
   const int n = D.n_psr;
   const int kmax = max(D.ka, D.nf_dm);
   const size_t cp = D.c_pad;
@@ -296,7 +317,6 @@ __global__ __launch_bounds__(64) void k_cholt_bwd(Dev D, const double *__restric
 
   // ---- v_c = C^T abar_c: lane (c16, q) sums rows 16K + 4q + v of column
   //      16J + c16, then the four lane groups are added
-  __shared__ double ab[NP][2];
   for (int m = l; m < NP; m += 64) {
     double as = 0.0, ac = 0.0;
     if (m < n) {
@@ -394,8 +414,6 @@ __global__ __launch_bounds__(64) void k_cholt_bwd(Dev D, const double *__restric
   for (int I = 1; I < NT; ++I)
 #pragma unroll
     for (int J = 0; J < I; ++J) {
-      // keep the scheduler from hoisting every tile load of the kernel here
-      __builtin_amdgcn_sched_barrier(0);
       v4d U = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int K = J; K < I; ++K) {
@@ -413,7 +431,6 @@ __global__ __launch_bounds__(64) void k_cholt_bwd(Dev D, const double *__restric
   double dkap[NT];
 #pragma unroll
   for (int J = 0; J < NT; ++J) {
-    __builtin_amdgcn_sched_barrier(0);
     ScanState st{0.0, 0.0, 0.0};
 #pragma unroll
     for (int I = J; I < NT; ++I) scan_tile(Wb[tidx(I, J)], 16 * I, vz, st, l, c16, q);
@@ -442,7 +459,6 @@ __global__ __launch_bounds__(64) void k_cholt_bwd(Dev D, const double *__restric
     ScanState st{0.0, 0.0, 0.0};
 #pragma unroll
     for (int I = J; I < NT; ++I) {
-      __builtin_amdgcn_sched_barrier(0);
       v4d Mt = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int K = J; K <= I; ++K) {
@@ -495,13 +511,17 @@ __global__ __launch_bounds__(64) void k_cholt_bwd(Dev D, const double *__restric
 
 template <int NT>
 hipError_t launch_fwd_t(const Dev &D, const double *x, hipStream_t s) {
-  hipLaunchKernelGGL(k_cholt_fwd<NT>, dim3(D.nf_gw, D.c_pad), dim3(64), 0, s, D, x);
+  const int nprob = D.nf_gw * D.c_pad;
+  hipLaunchKernelGGL(k_cholt_fwd<NT>, dim3((nprob + kProbPerGroup - 1) / kProbPerGroup),
+                     dim3(64 * kProbPerGroup), 0, s, D, x);
   return hipGetLastError();
 }
 
 template <int NT>
 hipError_t launch_bwd_t(const Dev &D, const double *x, double *grad, hipStream_t s) {
-  hipLaunchKernelGGL(k_cholt_bwd<NT>, dim3(D.nf_gw, D.n_chains), dim3(64), 0, s, D, x, grad,
+  const int nprob = D.nf_gw * D.n_chains;
+  hipLaunchKernelGGL(k_cholt_bwd<NT>, dim3((nprob + kProbPerGroup - 1) / kProbPerGroup),
+                     dim3(64 * kProbPerGroup), 0, s, D, x, grad,
                      (const double *)D.lstore, D.gtile, (const double *)D.bar_rn);
   return hipGetLastError();
 }

@@ -159,6 +159,19 @@ def test_many_pulsars_max(api):
     check(ds, X, run(api, ds, X))
 
 
+@pytest.mark.parametrize("n", [17, 33, 49, 63, 65, 80, 81, 97, 113])
+def test_pulsar_counts_across_tile_paths(api, n):
+    """Array sizes on both sides of every 16-row tile boundary: the
+    matrix-core per-frequency kernels (up to 80 pulsars) and the
+    one-row-per-thread kernels beyond."""
+    ds = synth.make_array(50 + n, n, [12 + (i % 5) for i in range(n)], 10 * synth.YEAR_S,
+                          backends_per_psr=[1 + i % 2 for i in range(n)],
+                          nu_range=(0.4e9, 2e9), nf_rn=3, nf_gw=2, nf_dm=2)
+    X = np.concatenate([near(ds, 5, 9), synth.random_points(ds, 3, 10)])
+    ref = check(ds, X, run(api, ds, X))
+    check(ds, X, run(api, ds, X, plain=True), ref=ref)
+
+
 @pytest.mark.parametrize("tuning", [(1, 1, 0), (2, 2, 1), (3, 4, 0), (64, 4, 1), (7, 1, 1)])
 def test_tunings(api, tuning):
     counts, nb, kr, kg, kd = EDGE["single_toa_and_tile_edges"]
