@@ -147,7 +147,10 @@ struct Dev {
   double *drn_k;               // [c_pad][ka][n_psr][2]
   double *ddm_k;               // [c_pad][nf_dm][n_psr][2]
 
-  int32_t *flag_k;             // [c_pad][kmax] per-frequency condition bits (kFlag*)
+  int32_t *flag_k;             // [c_pad][kmax] kFlagNotPD of the diagonal frequencies (k_spec_fwd)
+  int32_t *flag_dense;         // [c_pad][nf_gw] kFlagNotPD of the dense frequencies (k_cholt/k_chol)
+  int32_t *flag_out;           // [c_pad][kmax + kSpecSeg] kFlagOutNonfinite of the adjoints:
+                               //   [k] dense frequency k (k < nf_gw), [kmax + seg] k_spec_bwd segment
   int32_t *st_pre;             // [c_pad] status from the input checks
 };
 
@@ -159,6 +162,16 @@ constexpr int kCwConst = 16;   // rows of the per (chain, pulsar) CW constant ta
 }  // namespace pt
 
 namespace pt {
+
+// Prior box of a chain's hyper-parameters, checked by one wave.
+__device__ inline bool theta_in_box_wave(const Dev &D, const double *xc) {
+  bool ok = true;
+  for (int i = (int)(threadIdx.x & 63); i < D.n_theta; i += 64) {
+    const double v = xc[i];
+    if (!(v >= D.prior_lo[i] && v <= D.prior_hi[i])) ok = false;
+  }
+  return __all(ok);
+}
 
 // Wave64 / workgroup reductions in a fixed order (deterministic).
 __device__ inline double wave_sum(double v) {

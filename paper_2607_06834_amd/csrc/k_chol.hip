@@ -65,14 +65,23 @@ __global__ __launch_bounds__(NMAX > 64 ? 128 : 64) void k_chol_fwd(Dev D, const 
   double *out_s = D.coef_rn + ((size_t)i * D.rows_rn + rs) * cp + c;
   double *out_c = D.coef_rn + ((size_t)i * D.rows_rn + rc) * cp + c;
   // padding chains and chains outside the prior box carry zero coefficients
-  if (c >= D.n_chains || D.st_pre[c] == PTAFS_ST_PRIOR) {
+  // (the prior box is checked here, so nothing is read from k_spec_fwd)
+  int32_t *flag = D.flag_dense + (size_t)c * D.nf_gw + k0;
+  const double *xc = x + (size_t)(c < D.n_chains ? c : 0) * D.d;
+  bool ok = c < D.n_chains;
+  if (ok)
+    for (int t = i; t < D.n_theta; t += 64 * NW) {
+      const double v = xc[t];
+      if (!(v >= D.prior_lo[t] && v <= D.prior_hi[t])) ok = false;
+    }
+  if (!__syncthreads_and(ok)) {
     if (row) {
       *out_s = 0.0;
       *out_c = 0.0;
     }
+    if (i == 0) *flag = 0;
     return;
   }
-  const double *xc = x + (size_t)c * D.d;
   const double f = (k0 + 1) / D.tspan;
   const double rho = pt::powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
   double kap = 0.0;
@@ -144,12 +153,10 @@ __global__ __launch_bounds__(NMAX > 64 ? 128 : 64) void k_chol_fwd(Dev D, const 
       *out_s = 0.0;
       *out_c = 0.0;
     }
-    if (i == 0) {
-      const int kmax = max(D.ka, D.nf_dm);
-      D.flag_k[(size_t)c * kmax + k0] |= pt::kFlagNotPD;
-    }
+    if (i == 0) *flag = pt::kFlagNotPD;
     return;
   }
+  if (i == 0) *flag = 0;
   if (row) {
     const double r = 1.0 / sqrt(piv[i]);
     const double *zc = xc + D.off_z + (size_t)i * 2 * D.ka + 2 * k0;
@@ -257,8 +264,10 @@ __global__ __launch_bounds__(64) void k_chol_bwd(Dev D, const double *__restrict
   double *gz = grad + (size_t)c * D.d + D.off_z + 2 * k0;
   double *drn = D.drn_k + ((size_t)c * D.ka + k0) * n * 2;
   double *dth = D.dth_k + ((size_t)c * D.ka + k0) * 2;
-  const int fl0 = D.flag_k[(size_t)c * kmax + k0];
+  const int fl0 = D.flag_k[(size_t)c * kmax + k0] | D.flag_dense[(size_t)c * D.nf_gw + k0];
+  int32_t *fout = D.flag_out + (size_t)c * (kmax + pt::kSpecSeg) + k0;
   if (D.st_pre[c] != 0 || fl0 != 0) {
+    if (l == 0) *fout = 0;
     for (int I = l; I < n; I += 64) {
       gz[(size_t)I * K2] = 0.0;
       gz[(size_t)I * K2 + 1] = 0.0;
@@ -354,8 +363,7 @@ __global__ __launch_bounds__(64) void k_chol_bwd(Dev D, const double *__restrict
     const double rho = pt::powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
     dth[0] = dr * rho * 2.0 * pt::kLn10;
     dth[1] = dr * rho * (-lnfy);
-    if (nbad || !isfinite(dth[0]) || !isfinite(dth[1]))
-      D.flag_k[(size_t)c * kmax + k0] = fl0 | pt::kFlagOutNonfinite;
+    *fout = (nbad || !isfinite(dth[0]) || !isfinite(dth[1])) ? pt::kFlagOutNonfinite : 0;
   }
 }
 

@@ -95,14 +95,17 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const d
   auto coef = [&](int r, int sc) -> double & {
     return D.coef_rn[((size_t)r * D.rows_rn + (sc ? rc : rs)) * cp + c];
   };
-  if (c >= D.n_chains || D.st_pre[c] == PTAFS_ST_PRIOR) {
+  int32_t *flag = D.flag_dense + (size_t)c * D.nf_gw + k0;
+  const double *xc = x + (size_t)(c < D.n_chains ? c : 0) * D.d;
+  // (the prior box is checked here, so nothing is read from k_spec_fwd)
+  if (c >= D.n_chains || !pt::theta_in_box_wave(D, xc)) {
     for (int r = l; r < n; r += 64) {
       coef(r, 0) = 0.0;
       coef(r, 1) = 0.0;
     }
+    if (l == 0) *flag = 0;
     return;
   }
-  const double *xc = x + (size_t)c * D.d;
   const double f = (k0 + 1) / D.tspan;
   const double rho = pt::powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
   for (int r = l; r < NP; r += 64) {
@@ -183,12 +186,10 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const d
       coef(r, 0) = 0.0;
       coef(r, 1) = 0.0;
     }
-    if (l == 0) {
-      const int kmax = max(D.ka, D.nf_dm);
-      D.flag_k[(size_t)c * kmax + k0] |= pt::kFlagNotPD;
-    }
+    if (l == 0) *flag = pt::kFlagNotPD;
     return;
   }
+  if (l == 0) *flag = 0;
   // zero the upper part of the diagonal tiles
 #pragma unroll
   for (int I = 0; I < NT; ++I)
@@ -299,8 +300,10 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const d
   double *gz = grad + (size_t)c * D.d + D.off_z + 2 * k0;
   double *drn = D.drn_k + ((size_t)c * D.ka + k0) * n * 2;
   double *dth = D.dth_k + ((size_t)c * D.ka + k0) * 2;
-  const int fl0 = D.flag_k[(size_t)c * kmax + k0];
+  const int fl0 = D.flag_k[(size_t)c * kmax + k0] | D.flag_dense[(size_t)c * D.nf_gw + k0];
+  int32_t *fout = D.flag_out + (size_t)c * (kmax + pt::kSpecSeg) + k0;
   if (D.st_pre[c] != 0 || fl0 != 0) {
+    if (l == 0) *fout = 0;
     for (int I = l; I < n; I += 64) {
       gz[(size_t)I * K2] = 0.0;
       gz[(size_t)I * K2 + 1] = 0.0;
@@ -504,8 +507,7 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const d
     const double rho = pt::powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
     dth[0] = dr * rho * 2.0 * pt::kLn10;
     dth[1] = dr * rho * (-lnfy);
-    if (nbad || !isfinite(dth[0]) || !isfinite(dth[1]))
-      D.flag_k[(size_t)c * kmax + k0] = fl0 | pt::kFlagOutNonfinite;
+    *fout = (nbad || !isfinite(dth[0]) || !isfinite(dth[1])) ? pt::kFlagOutNonfinite : 0;
   }
 }
 

@@ -42,11 +42,14 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restric
 
   // ---- per-chain condition, in the order: prior box, non-finite input,
   //      CW coalescence, phi not positive definite, non-finite output
+  const int nseg = max(1, min(pt::kSpecSeg, kmax));
+  const int32_t *fo = D.flag_out + (size_t)c * (kmax + pt::kSpecSeg);
   int fl = 0;
   for (int k = t; k < kmax; k += 256) fl |= D.flag_k[(size_t)c * kmax + k];
+  for (int k = t; k < D.nf_gw; k += 256) fl |= D.flag_dense[(size_t)c * D.nf_gw + k] | fo[k];
+  for (int k = t; k < nseg; k += 256) fl |= fo[kmax + k];
   fl = pt::block_or256(fl, ired);
   // finiteness and squared norm of (u, z, z_dm), from the slices of k_spec_fwd
-  const int nseg = max(1, min(pt::kSpecSeg, kmax));
   double zz = 0.0;
   bool fin_in = true;
   for (int s = 0; s < nseg; ++s) {

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_spec_fwd(Dev D, const double *__restric
     }
   }
   __syncthreads();
-  // owned flags; the dense frequencies add kFlagNotPD later (k_cholt / k_chol)
+  // owned flags (the dense frequencies flag themselves in flag_dense)
   for (int j = tid; j < nks; j += 256) {
     const int k0 = seg + pt::kSpecSeg * j;
     D.flag_k[(size_t)c * kmax + k0] = bad ? 0 : kflag[k0];
@@ -155,6 +155,7 @@ __global__ __launch_bounds__(256) void k_spec_bwd(Dev D, const double *__restric
   const size_t cp = D.c_pad;
   int fl = 0;
   for (int k = tid; k < kmax; k += 256) fl |= D.flag_k[(size_t)c * kmax + k];
+  for (int k = tid; k < D.nf_gw; k += 256) fl |= D.flag_dense[(size_t)c * D.nf_gw + k];
   const bool skip = __syncthreads_or(fl != 0 || D.st_pre[c] != 0);
   bool fin = true;
 
@@ -214,8 +215,7 @@ __global__ __launch_bounds__(256) void k_spec_bwd(Dev D, const double *__restric
     }
   }
   fin = __syncthreads_and(fin);
-  // this segment's first frequency carries the flag (read only by k_finalize)
-  if (tid == 0 && !fin) D.flag_k[(size_t)c * kmax + seg] |= pt::kFlagOutNonfinite;
+  if (tid == 0) D.flag_out[(size_t)c * (kmax + pt::kSpecSeg) + kmax + seg] = fin ? 0 : pt::kFlagOutNonfinite;
 }
 
 }  // namespace

@@ -57,7 +57,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct WsLayout {
   size_t coef_rn, coef_dm, lstore, cwc, part_rn, part_dm, part_chi, part_cw, zz_seg, fin_seg,
-      bar_rn, bar_dm, chi_p, cw_p, dth_k, drn_k, ddm_k, flag_k, st_pre, total;
+      bar_rn, bar_dm, chi_p, cw_p, dth_k, drn_k, ddm_k, flag_k, flag_dense, flag_out, st_pre, total;
 };
 
 WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
@@ -89,6 +89,8 @@ WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
   L.drn_k = take(cp * B.ka * n * 2 * D8);
   L.ddm_k = take(cp * B.nf_dm * n * 2 * D8);
   L.flag_k = take(cp * kmax * sizeof(int32_t));
+  L.flag_dense = take(cp * B.nf_gw * sizeof(int32_t));
+  L.flag_out = take(cp * (kmax + pt::kSpecSeg) * sizeof(int32_t));
   L.st_pre = take(cp * sizeof(int32_t));
   L.total = o;
   return L;
@@ -183,6 +185,8 @@ pt::Dev make_dev(const ptafs_dataset *ds, int n_chains) {
   D.drn_k = reinterpret_cast<double *>(w + L.drn_k);
   D.ddm_k = reinterpret_cast<double *>(w + L.ddm_k);
   D.flag_k = reinterpret_cast<int32_t *>(w + L.flag_k);
+  D.flag_dense = reinterpret_cast<int32_t *>(w + L.flag_dense);
+  D.flag_out = reinterpret_cast<int32_t *>(w + L.flag_out);
   D.st_pre = reinterpret_cast<int32_t *>(w + L.st_pre);
   return D;
 }
