@@ -74,12 +74,6 @@ __host__ __device__ inline int tiles_for_pairs(int pairs) {
   return (steps + 3) / 4;
 }
 
-// Power-law spectrum A^2/(12 pi^2) yr^3 (f yr)^-gamma / T (Sec. IV.A, Eq.
-// power_law with yr^3), evaluated in logarithms.
-__device__ inline double powerlaw(double f, double log10A, double gamma, double tspan) {
-  const double c = 3.0 * log(kYear) - log(12.0 * kPi * kPi) - log(tspan);
-  return exp(2.0 * kLn10 * log10A - gamma * log(f * kYear) + c);
-}
 
 // Packed lower-triangular storage, row-major: row i holds columns 0..i.
 __host__ __device__ inline int pk(int i, int j) { return (i * (i + 1)) / 2 + j; }
@@ -128,14 +122,19 @@ struct Dev {
   const double *gtile;         // chol(Gamma) zero-padded, lower 16x16 tiles (up to kTileMaxNT)
   const double *gam_tile;      // Gamma zero-padded, lower 16x16 tiles (diagonal tiles full)
   const double *prior_lo, *prior_hi;
+  // power-law spectra: ln(f_k yr) for f_k = (k + 1) / T, k < PTAFS_MAX_HARM, and ln(yr^3 / (12 pi^2 T))
+  const double *lnfy;
+  double pl_c;
   // chunk table of the batched TOA pass
   int n_chunks, tiles_per_chunk;
   const int32_t *chunk_psr, *chunk_begin, *chunk_end, *psr_chunk0;
+  int n_cu;                    // compute units of the device
   // call
   int n_chains, c_pad, n_cb;
   // workspace
   double *coef_rn, *coef_dm;   // [n_psr][rows][c_pad]
   double *lstore;              // [c_pad][nf_gw][n_psr*(n_psr+1)/2]
+  double *sqk_rn, *sqk_dm;     // [c_pad][ka | nf_dm][n_psr] sqrt(kappa) of the diagonal frequencies
   double *cwc;                 // [n_psr][kCwConst][c_pad] per chain/pulsar CW constants
   double *part_rn, *part_dm;   // [n_wg][rows][16]
   double *part_chi, *part_cw;  // [n_wg][16], [n_wg][8][16]
@@ -153,6 +152,12 @@ struct Dev {
                                //   [k] dense frequency k (k < nf_gw), [kmax + seg] k_spec_bwd segment
   int32_t *st_pre;             // [c_pad] status from the input checks
 };
+
+// Power-law spectrum A^2/(12 pi^2) yr^3 (f yr)^-gamma / T at f_k = (k + 1) / T
+// (Sec. IV.A, Eq. power_law with yr^3), evaluated in logarithms.
+__device__ inline double powerlaw_k(const Dev &D, int k, double log10A, double gamma) {
+  return exp(2.0 * kLn10 * log10A - gamma * D.lnfy[k] + D.pl_c);
+}
 
 constexpr int kFlagNotPD = 1;          // phi_k not positive definite
 constexpr int kFlagOutNonfinite = 4;   // a non-finite gradient entry
@@ -202,10 +207,23 @@ __device__ inline int block_or256(int v, int *red4) {
   return red4[0] | red4[1] | red4[2] | red4[3];
 }
 
+// A leapfrog kick and drift that k_finalize applies to a chain right after
+// its gradient: p += eps grad, x += eps M^-1 p, and one more invalid
+// evaluation counted when the status is nonzero.
+struct Kick {
+  double eps;
+  const double *inv_mass;   // [d], or null for the identity
+  double *x;                // [n_chains][d], the evaluated points
+  double *p;                // [n_chains][d]
+  int64_t *n_invalid;       // [n_chains], or null
+};
+
 }  // namespace pt
 
 // Launch helpers implemented in the kernel translation units.
 namespace ptk {
+hipError_t launch_spectral_fwd(const pt::Dev &D, const double *x, hipStream_t s);
+hipError_t launch_spectral_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s);
 hipError_t launch_spec_fwd(const pt::Dev &D, const double *x, hipStream_t s);
 hipError_t launch_toa_mfma(const pt::Dev &D, int waves_per_block, int xcd_map, hipStream_t s);
 hipError_t launch_toa_plain_psr(const pt::Dev &D, int p, int n_chunks_p, hipStream_t s);
@@ -217,15 +235,12 @@ hipError_t launch_cholt_bwd(const pt::Dev &D, const double *x, double *grad, hip
 hipError_t launch_reduce_chunks(const pt::Dev &D, hipStream_t s);
 hipError_t launch_spec_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s);
 hipError_t launch_finalize(const pt::Dev &D, const double *x, double *logp, double *grad,
-                           int32_t *status, hipStream_t s);
+                           int32_t *status, hipStream_t s, const pt::Kick *kick = nullptr);
 // HMC pieces
 hipError_t launch_hmc_begin(const pt::Dev &D, int d, double eps, const double *inv_mass,
                             uint64_t seed, const uint64_t *traj, double *x, const double *logp,
                             const double *grad, double *p, double *x0, double *lp0, double *g0,
                             double *h0, hipStream_t s);
-hipError_t launch_hmc_kick_drift(int n_chains, int d, double eps, const double *inv_mass,
-                                 double *x, double *p, const double *grad, const int32_t *status,
-                                 int64_t *n_invalid, hipStream_t s);
 hipError_t launch_hmc_end(int n_chains, int d, double eps, const double *inv_mass, uint64_t seed,
                           const uint64_t *traj, double *x, double *logp,
                           double *grad, double *p, const double *x0, const double *lp0,

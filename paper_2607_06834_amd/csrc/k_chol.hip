@@ -82,10 +82,9 @@ __global__ __launch_bounds__(NMAX > 64 ? 128 : 64) void k_chol_fwd(Dev D, const 
     if (i == 0) *flag = 0;
     return;
   }
-  const double f = (k0 + 1) / D.tspan;
-  const double rho = pt::powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
+  const double rho = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
   double kap = 0.0;
-  if (row && k0 < D.nf_rn) kap = pt::powerlaw(f, xc[D.off_rn + 2 * i], xc[D.off_rn + 2 * i + 1], D.tspan);
+  if (row && k0 < D.nf_rn) kap = pt::powerlaw_k(D, k0, xc[D.off_rn + 2 * i], xc[D.off_rn + 2 * i + 1]);
   double pi0 = 0.0, pi1 = 0.0, pi2 = 0.0;
   if (row) {
     pi0 = D.pos[3 * i];
@@ -341,15 +340,14 @@ __global__ __launch_bounds__(64) void k_chol_bwd(Dev D, const double *__restrict
   // d/drho: sum over columns in a fixed order
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) dr += __shfl_xor(dr, o, 64);
-  const double f = (k0 + 1) / D.tspan;
-  const double lnfy = log(f * pt::kYear);
+  const double lnfy = D.lnfy[k0];
   bool fin = true;
   auto put = [&](int I, double vs, double vc, double zs, double zc, double dk) {
     const double g0 = vs - zs, g1 = vc - zc;
     gz[(size_t)I * K2] = g0;
     gz[(size_t)I * K2 + 1] = g1;
     const double kap = (k0 < D.nf_rn)
-                           ? pt::powerlaw(f, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1], D.tspan)
+                           ? pt::powerlaw_k(D, k0, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1])
                            : 0.0;
     const double d0 = dk * kap * 2.0 * pt::kLn10, d1 = dk * kap * (-lnfy);
     drn[2 * I] = d0;
@@ -360,7 +358,7 @@ __global__ __launch_bounds__(64) void k_chol_bwd(Dev D, const double *__restrict
   if (c2) put(I2, v2s, v2c, z2s, z2c, dk2);
   const int nbad = __popcll(__ballot(!fin));
   if (l == 0) {
-    const double rho = pt::powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
+    const double rho = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
     dth[0] = dr * rho * 2.0 * pt::kLn10;
     dth[1] = dr * rho * (-lnfy);
     *fout = (nbad || !isfinite(dth[0]) || !isfinite(dth[1])) ? pt::kFlagOutNonfinite : 0;
@@ -384,9 +382,26 @@ hipError_t launch_bwd_t(const Dev &D, const double *x, double *grad, hipStream_t
 
 namespace ptk {
 
+// Forward and adjoint spectral stages: the diagonal-frequency work
+// (k_spec) and the dense-frequency factorisation, in one launch where the
+// tiled kernels take both.
+hipError_t launch_spectral_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
+  if (D.c_pad == 0) return hipSuccess;
+  if (D.nf_gw > 0 && pt::chol_tiles(D.n_psr) <= pt::kTileMaxNT) return launch_cholt_fwd(D, x, s);
+  const hipError_t e = launch_spec_fwd(D, x, s);
+  return e == hipSuccess ? launch_chol_fwd(D, x, s) : e;
+}
+
+hipError_t launch_spectral_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s) {
+  if (D.n_chains == 0) return hipSuccess;
+  if (D.nf_gw > 0 && pt::chol_tiles(D.n_psr) <= pt::kTileMaxNT) return launch_cholt_bwd(D, x, grad, s);
+  const hipError_t e = launch_spec_bwd(D, x, grad, s);
+  return e == hipSuccess ? launch_chol_bwd(D, x, grad, s) : e;
+}
+
+// dense frequencies of more than kTileMaxNT tiles (the row-per-thread kernels)
 hipError_t launch_chol_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
   if (D.nf_gw == 0 || D.c_pad == 0) return hipSuccess;
-  if (pt::chol_tiles(D.n_psr) <= pt::kTileMaxNT) return launch_cholt_fwd(D, x, s);
   switch (pt::chol_tiles(D.n_psr)) {
     case 6: return launch_fwd_t<96>(D, x, s);
     case 7: return launch_fwd_t<112>(D, x, s);
@@ -397,7 +412,6 @@ hipError_t launch_chol_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
 
 hipError_t launch_chol_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s) {
   if (D.nf_gw == 0 || D.n_chains == 0) return hipSuccess;
-  if (pt::chol_tiles(D.n_psr) <= pt::kTileMaxNT) return launch_cholt_bwd(D, x, grad, s);
   switch (pt::chol_tiles(D.n_psr)) {
     case 6: return launch_bwd_t<96>(D, x, grad, s);
     case 7: return launch_bwd_t<112>(D, x, grad, s);

@@ -18,6 +18,11 @@
 // The quadratic forms with the semiseparable P are prefix sums down each
 // column, taken on the MFMA output layout.
 //
+// The launches also carry the diagonal-frequency work of the same stage
+// (spec_dev.h) in a few extra workgroups after the dense ones, each taking
+// whole chains: the two touch disjoint outputs, and the extra workgroups run
+// on the compute units the dense problems leave free.
+//
 // Register layouts of a 16x16 block X (lane l = c + 16 q, item v or slice s):
 //   forward, E(X):   X[c][q + 4s]       (operand A of X, operand B of X^T,
 //                                         and the result layout of X^T)
@@ -26,6 +31,7 @@
 // with pi(c) = 4 (c mod 4) + c / 4, so that lane group q of a result holds the
 // consecutive rows 4q .. 4q + 3 of every tile.
 #include "common.h"
+#include "spec_dev.h"
 
 namespace {
 
@@ -74,7 +80,16 @@ __device__ inline int pi16(int c) { return 4 * (c & 3) + (c >> 2); }
 // Forward: one wave per (frequency, chain) problem, nf_gw * c_pad problems.
 // ---------------------------------------------------------------------------
 template <int NT>
-__global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const double *__restrict__ x) {
+__global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const double *__restrict__ x,
+                                                                  int n_dense_groups) {
+  if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies, chains b, b + G, ...
+    const int G = gridDim.x - n_dense_groups;
+    for (int c = blockIdx.x - n_dense_groups; c < D.c_pad; c += G) {
+      pt::spec_fwd_block(D, x, c, 0, 1, 0, 1);
+      __syncthreads();
+    }
+    return;
+  }
   constexpr int NP = 16 * NT;
   constexpr int NTILE = NT * (NT + 1) / 2;
   __shared__ double colb_[kProbPerGroup][2][NT][16];   // scaled column, double-buffered
@@ -106,12 +121,11 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const d
     if (l == 0) *flag = 0;
     return;
   }
-  const double f = (k0 + 1) / D.tspan;
-  const double rho = pt::powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
+  const double rho = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
   for (int r = l; r < NP; r += 64) {
     double kap = 0.0, zs = 0.0, zc = 0.0;
     if (r < n) {
-      if (k0 < D.nf_rn) kap = pt::powerlaw(f, xc[D.off_rn + 2 * r], xc[D.off_rn + 2 * r + 1], D.tspan);
+      if (k0 < D.nf_rn) kap = pt::powerlaw_k(D, k0, xc[D.off_rn + 2 * r], xc[D.off_rn + 2 * r + 1]);
       const double *z = xc + D.off_z + (size_t)r * 2 * D.ka + 2 * k0;
       zs = z[0];
       zc = z[1];
@@ -275,7 +289,19 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const d
                                                   double *__restrict__ grad,
                                                   const double *__restrict__ lst,
                                                   const double *__restrict__ gch,
-                                                  const double *__restrict__ bar) {
+                                                  const double *__restrict__ bar,
+                                                  int n_dense_groups) {
+  if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies, chains b, b + G, ...
+    const int G = gridDim.x - n_dense_groups;
+    const int kmax = max(D.ka, D.nf_dm);
+    for (int c = blockIdx.x - n_dense_groups; c < D.n_chains; c += G) {
+      pt::spec_bwd_block(D, x, grad, c, 0, 1, 0);
+      if (threadIdx.x >= 1 && threadIdx.x < pt::kSpecSeg)
+        D.flag_out[(size_t)c * (kmax + pt::kSpecSeg) + kmax + threadIdx.x] = 0;
+      __syncthreads();
+    }
+    return;
+  }
   constexpr int NP = 16 * NT;
   constexpr int NTILE = NT * (NT + 1) / 2;
   constexpr int TS = 17;                              // LDS row stride of a tile
@@ -316,6 +342,15 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const d
     }
     return;
   }
+  // the spectra for the outputs, early (their loads and exponentials overlap the work below)
+  double kapo[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int I = l + 64 * h;
+    kapo[h] = (I < n && k0 < D.nf_rn) ? pt::powerlaw_k(D, k0, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1])
+                                      : 0.0;
+  }
+  const double rho_o = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
   const double *Cb = lst + ((size_t)c * D.nf_gw + k0) * (NTILE * 256);
 
   // ---- v_c = C^T abar_c: lane (c16, q) sums rows 16K + 4q + v of column
@@ -479,8 +514,7 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const d
   for (int o = 32; o > 0; o >>= 1) dr += __shfl_xor(dr, o, 64);
 
   // ---- outputs
-  const double f = (k0 + 1) / D.tspan;
-  const double lnfy = log(f * pt::kYear);
+  const double lnfy = D.lnfy[k0];
   bool fin = true;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -493,9 +527,7 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const d
       double dk = 0.0;
 #pragma unroll
       for (int J = 0; J < NT; ++J) dk = (J == (I >> 4)) ? dkap[J] : dk;
-      const double kap = (k0 < D.nf_rn)
-                             ? pt::powerlaw(f, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1], D.tspan)
-                             : 0.0;
+      const double kap = kapo[h];
       const double d0 = dk * kap * 2.0 * pt::kLn10, d1 = dk * kap * (-lnfy);
       drn[2 * I] = d0;
       drn[2 * I + 1] = d1;
@@ -504,27 +536,38 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const d
   }
   const int nbad = __popcll(__ballot(!fin));
   if (l == 0) {
-    const double rho = pt::powerlaw(f, xc[D.off_gw], xc[D.off_gw + 1], D.tspan);
+    const double rho = rho_o;
     dth[0] = dr * rho * 2.0 * pt::kLn10;
     dth[1] = dr * rho * (-lnfy);
     *fout = (nbad || !isfinite(dth[0]) || !isfinite(dth[1])) ? pt::kFlagOutNonfinite : 0;
   }
 }
 
+// Workgroups for the diagonal-frequency work of `chains` chains next to ng
+// dense workgroups: the compute units those leave free (one dense workgroup
+// fills a compute unit), at least 8, at most one per chain.
+int spec_groups(const Dev &D, int ng, int chains) {
+  return max(1, min(chains, max(8, D.n_cu - ng)));
+}
+
+// grid: the dense problems, kProbPerGroup per workgroup, then the
+// diagonal-frequency workgroups
 template <int NT>
 hipError_t launch_fwd_t(const Dev &D, const double *x, hipStream_t s) {
   const int nprob = D.nf_gw * D.c_pad;
-  hipLaunchKernelGGL(k_cholt_fwd<NT>, dim3((nprob + kProbPerGroup - 1) / kProbPerGroup),
-                     dim3(64 * kProbPerGroup), 0, s, D, x);
+  const int ng = (nprob + kProbPerGroup - 1) / kProbPerGroup;
+  hipLaunchKernelGGL(k_cholt_fwd<NT>, dim3(ng + spec_groups(D, ng, D.c_pad)),
+                     dim3(64 * kProbPerGroup), 0, s, D, x, ng);
   return hipGetLastError();
 }
 
 template <int NT>
 hipError_t launch_bwd_t(const Dev &D, const double *x, double *grad, hipStream_t s) {
   const int nprob = D.nf_gw * D.n_chains;
-  hipLaunchKernelGGL(k_cholt_bwd<NT>, dim3((nprob + kProbPerGroup - 1) / kProbPerGroup),
-                     dim3(64 * kProbPerGroup), 0, s, D, x, grad,
-                     (const double *)D.lstore, D.gtile, (const double *)D.bar_rn);
+  const int ng = (nprob + kProbPerGroup - 1) / kProbPerGroup;
+  hipLaunchKernelGGL(k_cholt_bwd<NT>, dim3(ng + spec_groups(D, ng, D.n_chains)),
+                     dim3(64 * kProbPerGroup), 0, s, D, x, grad, (const double *)D.lstore, D.gtile,
+                     (const double *)D.bar_rn, ng);
   return hipGetLastError();
 }
 

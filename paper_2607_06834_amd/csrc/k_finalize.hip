@@ -7,6 +7,8 @@
 //
 // Per-frequency contributions to the hyper-parameter gradient are summed in
 // frequency order; chains flagged by any stage get log p = -inf, gradient 0.
+// Inside a leapfrog trajectory the same workgroup then applies the kick and
+// drift to its chain (App. A, Eq. Hamilton's_eq), saving a launch.
 #include "common.h"
 
 namespace {
@@ -26,10 +28,9 @@ __device__ inline double sum32(const double *p, size_t stride, int K) {
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restrict__ x,
-                                                  double *__restrict__ logp,
-                                                  double *__restrict__ grad,
-                                                  int32_t *__restrict__ status) {
+__global__ __launch_bounds__(256) void k_finalize(Dev D, const double *x, double *__restrict__ logp,
+                                                  double *grad, int32_t *__restrict__ status,
+                                                  pt::Kick kick, int has_kick) {
   __shared__ double red[4];
   __shared__ int ired[4];
   const int c = blockIdx.x;
@@ -120,6 +121,32 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restric
     logp[c] = lp;
     status[c] = st;
   }
+  if (has_kick) {
+    __syncthreads();   // the workgroup's gradient stores are visible to all its threads
+    if (t == 0 && kick.n_invalid && st != 0) kick.n_invalid[c] += 1;
+    double *xw = kick.x + (size_t)c * D.d, *pw = kick.p + (size_t)c * D.d;
+    constexpr int B = 8;   // elements per thread whose loads are issued together
+    for (int i0 = t; i0 < D.d; i0 += 256 * B) {
+      double pv[B], gv[B], xv[B], iv[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = i0 + 256 * b;
+        const bool in = i < D.d;
+        pv[b] = in ? pw[i] : 0.0;
+        gv[b] = in ? gc[i] : 0.0;
+        xv[b] = in ? xw[i] : 0.0;
+        iv[b] = (in && kick.inv_mass) ? kick.inv_mass[i] : 1.0;
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = i0 + 256 * b;
+        if (i >= D.d) continue;
+        const double pi = pv[b] + kick.eps * gv[b];
+        pw[i] = pi;
+        xw[i] = xv[b] + kick.eps * iv[b] * pi;
+      }
+    }
+  }
 }
 
 }  // namespace
@@ -127,9 +154,11 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *__restric
 namespace ptk {
 
 hipError_t launch_finalize(const pt::Dev &D, const double *x, double *logp, double *grad,
-                           int32_t *status, hipStream_t s) {
+                           int32_t *status, hipStream_t s, const pt::Kick *kick) {
   if (D.n_chains == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(D.n_chains), dim3(256), 0, s, D, x, logp, grad, status);
+  const pt::Kick k = kick ? *kick : pt::Kick{};
+  hipLaunchKernelGGL(k_finalize, dim3(D.n_chains), dim3(256), 0, s, D, x, logp, grad, status, k,
+                     kick ? 1 : 0);
   return hipGetLastError();
 }
 

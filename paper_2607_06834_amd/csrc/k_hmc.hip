@@ -91,25 +91,6 @@ __global__ __launch_bounds__(256) void k_hmc_begin(int d, double eps, const doub
   }
 }
 
-// p += eps grad; x += eps M^-1 p  over n_chains * d elements
-__global__ __launch_bounds__(256) void k_hmc_kick_drift(size_t n, int d, double eps,
-                                                        const double *inv_mass, double *x,
-                                                        double *p, const double *grad,
-                                                        const int32_t *status,
-                                                        int64_t *n_invalid) {
-  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n) return;
-  const int i = (int)(e % d);
-  if (i == 0 && n_invalid) {
-    const size_t c = e / d;
-    if (status[c] != 0) n_invalid[c] += 1;
-  }
-  const double im = inv_mass ? inv_mass[i] : 1.0;
-  const double pi = p[e] + eps * grad[e];
-  p[e] = pi;
-  x[e] += eps * im * pi;
-}
-
 // final half kick, H1, accept / restore, optional sample
 __global__ __launch_bounds__(256) void k_hmc_end(int d, double eps, const double *inv_mass,
                                                  uint64_t seed, const uint64_t *traj, int n_chains, double *x, double *logp, double *grad,
@@ -173,15 +154,6 @@ hipError_t launch_hmc_begin(const pt::Dev &D, int d, double eps, const double *i
                             double *h0, hipStream_t s) {
   hipLaunchKernelGGL(k_hmc_begin, dim3(D.n_chains), dim3(256), 0, s, d, eps, inv_mass, seed, traj,
                      x, logp, grad, p, x0, lp0, g0, h0);
-  return hipGetLastError();
-}
-
-hipError_t launch_hmc_kick_drift(int n_chains, int d, double eps, const double *inv_mass,
-                                 double *x, double *p, const double *grad, const int32_t *status,
-                                 int64_t *n_invalid, hipStream_t s) {
-  const size_t n = (size_t)n_chains * d;
-  hipLaunchKernelGGL(k_hmc_kick_drift, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, d,
-                     eps, inv_mass, x, p, grad, status, n_invalid);
   return hipGetLastError();
 }
 

@@ -56,7 +56,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 
 struct WsLayout {
-  size_t coef_rn, coef_dm, lstore, cwc, part_rn, part_dm, part_chi, part_cw, zz_seg, fin_seg,
+  size_t coef_rn, coef_dm, lstore, sqk_rn, sqk_dm, cwc, part_rn, part_dm, part_chi, part_cw, zz_seg, fin_seg,
       bar_rn, bar_dm, chi_p, cw_p, dth_k, drn_k, ddm_k, flag_k, flag_dense, flag_out, st_pre, total;
 };
 
@@ -74,6 +74,8 @@ WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
   L.coef_rn = take(n * B.rows_rn * cp * D8);
   L.coef_dm = take(n * B.rows_dm * cp * D8);
   L.lstore = take(cp * B.nf_gw * pt::chol_store_doubles(B.n_psr) * D8);
+  L.sqk_rn = take(cp * B.ka * B.n_psr * D8);
+  L.sqk_dm = take(cp * B.nf_dm * B.n_psr * D8);
   L.cwc = take(B.has_cw ? n * pt::kCwConst * cp * D8 : 0);
   L.part_rn = take(nwg * B.rows_rn * 16 * D8);
   L.part_dm = take(nwg * B.rows_dm * 16 * D8);
@@ -170,6 +172,8 @@ pt::Dev make_dev(const ptafs_dataset *ds, int n_chains) {
   D.coef_rn = reinterpret_cast<double *>(w + L.coef_rn);
   D.coef_dm = reinterpret_cast<double *>(w + L.coef_dm);
   D.lstore = reinterpret_cast<double *>(w + L.lstore);
+  D.sqk_rn = reinterpret_cast<double *>(w + L.sqk_rn);
+  D.sqk_dm = reinterpret_cast<double *>(w + L.sqk_dm);
   D.cwc = reinterpret_cast<double *>(w + L.cwc);
   D.part_rn = reinterpret_cast<double *>(w + L.part_rn);
   D.part_dm = reinterpret_cast<double *>(w + L.part_dm);
@@ -200,19 +204,17 @@ void set_lds_limits() {
 }
 
 int enqueue_eval(ptafs_dataset *ds, int C, const double *x, double *logp, double *grad,
-                 int32_t *status, hipStream_t s, bool plain) {
+                 int32_t *status, hipStream_t s, bool plain, const pt::Kick *kick = nullptr) {
   const pt::Dev D = make_dev(ds, C);
-  PT_TRY(ptk::launch_spec_fwd(D, x, s));
-  PT_TRY(ptk::launch_chol_fwd(D, x, s));
+  PT_TRY(ptk::launch_spectral_fwd(D, x, s));
   if (plain) {
     for (int p = 0; p < D.n_psr; ++p) PT_TRY(ptk::launch_toa_plain_psr(D, p, ds->psr_nchunks[p], s));
   } else {
     PT_TRY(ptk::launch_toa_mfma(D, ds->wpb, ds->xcd_map, s));
   }
   PT_TRY(ptk::launch_reduce_chunks(D, s));
-  PT_TRY(ptk::launch_spec_bwd(D, x, grad, s));
-  PT_TRY(ptk::launch_chol_bwd(D, x, grad, s));
-  PT_TRY(ptk::launch_finalize(D, x, logp, grad, status, s));
+  PT_TRY(ptk::launch_spectral_bwd(D, x, grad, s));
+  PT_TRY(ptk::launch_finalize(D, x, logp, grad, status, s, kick));
   return PTAFS_OK;
 }
 
@@ -345,7 +347,7 @@ size_t dataset_bytes_of(const pt::Dev &B, int n_chunks) {
   const size_t tiles = nt <= pt::kTileMaxNT ? (size_t)(nt * (nt + 1) / 2) * 256 : 0;
   size_t b = 7 * a(npad, 8) + 2 * a(ntoa, 8) + a(ntoa, 4) + 2 * a(B.n_backend, 8) + a(n + 1, 8) +
              2 * a(n, 8) + a(3 * n, 8) + a(n * n, 8) + a(n * (n + 1) / 2, 8) + 2 * a(tiles, 8) +
-             2 * a(B.n_theta, 8);
+             2 * a(B.n_theta, 8) + a(PTAFS_MAX_HARM, 8);
   b += (size_t)(3 * n_chunks + n + 1) * sizeof(int32_t);
   return b;
 }
@@ -394,6 +396,10 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
   }
   pt::Dev &B = ds->base;
   B = plan_view;
+  if (hipDeviceGetAttribute(&B.n_cu, hipDeviceAttributeMultiprocessorCount, ds->device) != hipSuccess) {
+    free_all(ds);
+    return PTAFS_E_HIP;
+  }
   // per-pulsar timing-model centring and the Hellings-Downs matrix
   std::vector<double> tc(n), tsi(n), gam((size_t)n * n);
   for (int p = 0; p < n; ++p) {
@@ -511,6 +517,13 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
     }
     chk(upload(ds, ht.data(), ht.size(), &B.gam_tile));
   }
+  {
+    // power-law spectra at f_k = (k + 1) / T in logarithms
+    std::vector<double> lf(PTAFS_MAX_HARM);
+    for (int k = 0; k < PTAFS_MAX_HARM; ++k) lf[k] = std::log((k + 1) / d->tspan * pt::kYear);
+    chk(upload(ds, lf.data(), lf.size(), &B.lnfy));
+    B.pl_c = 3.0 * std::log(pt::kYear) - std::log(12.0 * pt::kPi * pt::kPi) - std::log(d->tspan);
+  }
   chk(upload(ds, d->prior_lo, B.n_theta, &B.prior_lo));
   chk(upload(ds, d->prior_hi, B.n_theta, &B.prior_hi));
   if (!rc) rc = ensure_chunks(ds);
@@ -623,9 +636,7 @@ int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, d
     };
     (void)hipEventRecord(ev[0], s);
     {
-      hipError_t e = ptk::launch_spec_fwd(D, x, s);
-      if (e == hipSuccess) e = ptk::launch_chol_fwd(D, x, s);
-      step(0, e);
+      step(0, ptk::launch_spectral_fwd(D, x, s));
     }
     if (plain) {
       hipError_t e = hipSuccess;
@@ -637,9 +648,7 @@ int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, d
     }
     step(2, ptk::launch_reduce_chunks(D, s));
     {
-      hipError_t e = ptk::launch_spec_bwd(D, x, grad, s);
-      if (e == hipSuccess) e = ptk::launch_chol_bwd(D, x, grad, s);
-      step(3, e);
+      step(3, ptk::launch_spectral_bwd(D, x, grad, s));
     }
     step(4, ptk::launch_finalize(D, x, logp, grad, status, s));
     if (hipEventSynchronize(ev[kStages]) != hipSuccess) err = PTAFS_E_HIP;
@@ -701,11 +710,12 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   const pt::Dev D = make_dev(ds, n_chains);
   auto one_traj = [&](hipStream_t q) -> int {
     PT_TRY(ptk::launch_hmc_begin(D, d, eps, inv_mass, seed, traj, x, logp, grad, p, x0, lp0, g0, h0, q));
+    // every evaluation but the last ends with the kick and drift of its chain
+    const pt::Kick kick{eps, inv_mass, x, p, n_invalid};
     for (int l = 0; l < n_leapfrog; ++l) {
-      int r = enqueue_eval(ds, n_chains, x, logp, grad, st, q, false);
+      int r = enqueue_eval(ds, n_chains, x, logp, grad, st, q, false,
+                           l + 1 < n_leapfrog ? &kick : nullptr);
       if (r) return r;
-      if (l + 1 < n_leapfrog)
-        PT_TRY(ptk::launch_hmc_kick_drift(n_chains, d, eps, inv_mass, x, p, grad, st, n_invalid, q));
     }
     PT_TRY(ptk::launch_hmc_end(n_chains, d, eps, inv_mass, seed, traj, x, logp, grad, p, x0, lp0,
                                g0, h0, n_accept, samples, st, n_invalid, q));

@@ -1,0 +1,295 @@
+// Per-chain work of the spectral side that needs no dense factorisation, as
+// device bodies: k_spec's kernels call them, and so do the dense-frequency
+// kernels, whose launches carry this work in extra workgroups.  It covers the
+// power-law spectra (Sec. IV.A, Eq. power_law), the diagonal prior of the
+// frequencies without the common process and the DM prior with their
+// whitening transforms (Sec. II.B, Eq. standardizing_transform, mu = 0) and
+// adjoints; the input checks, the timing-model rows of the coefficient
+// panels and the CW constants.  The frequencies that carry the common process (dense
+// phi_k = rho_k Gamma + diag kappa) are factorised in k_cholt / k_chol.
+//
+//   diagonal frequencies:  a_Ik = sqrt(kappa_Ik) z_Ik,  dz = sqrt(kappa) abar - z,
+//     d/dlog10A_I = ln10 sqrt(kappa) abar.z,  d/dgamma_I = -1/2 ln(f yr) sqrt(kappa) abar.z
+//   DM: the same with kappa^DM and abar^DM.
+#pragma once
+#include "common.h"
+#include "cw_dev.h"
+
+namespace pt {
+
+// items per thread whose loads are issued together
+constexpr int kSpecBatch = 4;
+
+// Forward of chain c (< c_pad): slice seg of nseg of the input checks
+// (segment 0 also does the per-chain work) and the diagonal and DM
+// frequencies k = k_first, k_first + k_step, ...  With nseg = 1 the chain's
+// other check slots are set neutral.  One block of 256 threads; every thread
+// of the block calls it.
+// ---------------------------------------------------------------------------
+__device__ inline void spec_fwd_block(const Dev &D, const double *__restrict__ x, int c, int seg,
+                                      int nseg, int k_first, int k_step) {
+  __shared__ double red[4];
+  __shared__ int kflag[PTAFS_MAX_HARM];
+  const int tid = threadIdx.x;
+  const int n = D.n_psr;
+  const int kmax = max(D.ka, D.nf_dm);
+  const bool real = c < D.n_chains;
+  const double *xc = x + (size_t)(real ? c : 0) * D.d;
+  const size_t cp = D.c_pad;
+
+  // ---- prior box (every segment needs it)
+  bool ok = real;
+  if (real)
+    for (int i = tid; i < D.n_theta; i += 256) {
+      const double v = xc[i];
+      if (!(v >= D.prior_lo[i] && v <= D.prior_hi[i])) ok = false;
+    }
+  const bool bad = !__syncthreads_and(ok);
+  if (tid < PTAFS_MAX_HARM) kflag[tid] = 0;
+  // finiteness and squared norm of this segment's slice of (u, z, z_dm)
+  {
+    const int len = D.d - D.off_u;
+    const int e0 = D.off_u + (int)(((long long)len * seg) / nseg);
+    const int e1 = D.off_u + (int)(((long long)len * (seg + 1)) / nseg);
+    double zz = 0.0;
+    bool fin = true;
+    if (real)
+      for (int e = e0 + tid; e < e1; e += 256 * kSpecBatch) {
+        double v[kSpecBatch];
+#pragma unroll
+        for (int b = 0; b < kSpecBatch; ++b) v[b] = (e + 256 * b < e1) ? xc[e + 256 * b] : 0.0;
+#pragma unroll
+        for (int b = 0; b < kSpecBatch; ++b) {
+          fin = fin && isfinite(v[b]);
+          zz += v[b] * v[b];
+        }
+      }
+    zz = pt::block_sum256(zz, red);
+    fin = __syncthreads_and(fin);
+    if (tid == 0) {
+      D.zz_seg[(size_t)c * pt::kSpecSeg + seg] = zz;
+      D.fin_seg[(size_t)c * pt::kSpecSeg + seg] = fin ? 1 : 0;
+    } else if (nseg == 1 && tid < pt::kSpecSeg) {
+      D.zz_seg[(size_t)c * pt::kSpecSeg + tid] = 0.0;
+      D.fin_seg[(size_t)c * pt::kSpecSeg + tid] = 1;
+    }
+  }
+
+  if (seg == 0) {
+    int st = 0;
+    if (real && bad) st = PTAFS_ST_PRIOR;
+    if (real && !bad && D.has_cw) {
+      const double *cw = xc + D.off_cw;
+      const double M = exp(pt::kLn10 * cw[2]) * pt::kTsun;
+      const double w0 = pt::kPi * exp(pt::kLn10 * cw[3]);
+      const double y = 256.0 / 5.0 * exp(5.0 / 3.0 * log(M) + 8.0 / 3.0 * log(w0)) * D.tmax;
+      if (!(y < 1.0)) st = PTAFS_ST_CW;
+    }
+    if (tid == 0) D.st_pre[c] = st;
+    const bool zero = bad || st != 0;
+    if (D.has_cw) {
+      // CW constants per pulsar (zero delay for padding and rejected chains)
+      const double *th = (real && !zero) ? xc + D.off_cw : nullptr;
+      for (int I = tid; I < n; I += 256) {
+        double v[pt::kCwRows];
+        pt::cw_constants(th, D.pos + 3 * I, v);
+        double *dst = D.cwc + (size_t)I * pt::kCwConst * cp + c;
+#pragma unroll
+        for (int j = 0; j < pt::kCwRows; ++j) dst[(size_t)j * cp] = v[j];
+      }
+    }
+    // coefficient rows no frequency owns: timing model b = sigma_b u, zeros
+    for (int idx = tid; idx < n * D.n_free_rn; idx += 256) {
+      const int I = idx / D.n_free_rn, row = D.free_rn[idx - I * D.n_free_rn];
+      const pt::Slot sl = pt::rn_slot(row, D.kb);
+      const double v = (sl.kind == 1 && !zero) ? D.sigma_b * xc[D.off_u + 3 * I + sl.tm] : 0.0;
+      D.coef_rn[((size_t)I * D.rows_rn + row) * cp + c] = v;
+    }
+    for (int idx = tid; idx < n * D.n_free_dm; idx += 256) {
+      const int I = idx / D.n_free_dm, row = D.free_dm[idx - I * D.n_free_dm];
+      D.coef_dm[((size_t)I * D.rows_dm + row) * cp + c] = 0.0;
+    }
+  }
+  __syncthreads();
+
+  // ---- the frequencies: diagonal prior (no common process),
+  //      L = diag(sqrt(kappa)), and the DM prior; thread = (frequency, pulsar)
+  const int nks = (kmax - k_first + k_step - 1) / k_step;
+  const int K2 = 2 * D.ka, K2d = 2 * D.nf_dm;
+  const int total = nks * n;
+  for (int base = tid; base < total; base += 256 * kSpecBatch) {
+    // the inputs of kSpecBatch items first (their loads overlap), then the items
+    double ra[kSpecBatch], rg[kSpecBatch], zs[kSpecBatch], zc[kSpecBatch];
+    double da[kSpecBatch], dg[kSpecBatch], ws[kSpecBatch], wc[kSpecBatch];
+#pragma unroll
+    for (int b = 0; b < kSpecBatch; ++b) {
+      const int idx = base + 256 * b;
+      ra[b] = rg[b] = zs[b] = zc[b] = da[b] = dg[b] = ws[b] = wc[b] = 0.0;
+      if (idx < total && !bad) {
+        const int j = idx / n, I = idx - j * n;
+        const int k0 = k_first + k_step * j;
+        if (k0 >= D.nf_gw && k0 < D.ka) {
+          if (k0 < D.nf_rn) {
+            ra[b] = xc[D.off_rn + 2 * I];
+            rg[b] = xc[D.off_rn + 2 * I + 1];
+          }
+          zs[b] = xc[D.off_z + I * K2 + 2 * k0];
+          zc[b] = xc[D.off_z + I * K2 + 2 * k0 + 1];
+        }
+        if (k0 < D.nf_dm) {
+          da[b] = xc[D.off_dm + 2 * I];
+          dg[b] = xc[D.off_dm + 2 * I + 1];
+          ws[b] = xc[D.off_zdm + I * K2d + 2 * k0];
+          wc[b] = xc[D.off_zdm + I * K2d + 2 * k0 + 1];
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kSpecBatch; ++b) {
+      const int idx = base + 256 * b;
+      if (idx >= total) continue;
+      const int j = idx / n, I = idx - j * n;
+      const int k0 = k_first + k_step * j;
+      const int rs = pt::harm_row(k0 + 1, 0), rc = pt::harm_row(k0 + 1, 1);
+      if (k0 >= D.nf_gw && k0 < D.ka) {
+        double vs = 0.0, vc = 0.0;
+        if (!bad) {
+          const double kap = (k0 < D.nf_rn) ? powerlaw_k(D, k0, ra[b], rg[b]) : 0.0;
+          if (!(kap > 0.0) || !isfinite(kap)) atomicOr(&kflag[k0], pt::kFlagNotPD);
+          const double sq = sqrt(kap);
+          vs = sq * zs[b];
+          vc = sq * zc[b];
+          D.sqk_rn[((size_t)c * D.ka + k0) * n + I] = sq;   // for the adjoint
+        }
+        D.coef_rn[((size_t)I * D.rows_rn + rs) * cp + c] = vs;
+        D.coef_rn[((size_t)I * D.rows_rn + rc) * cp + c] = vc;
+      }
+      if (k0 < D.nf_dm) {
+        double vs = 0.0, vc = 0.0;
+        if (!bad) {
+          const double sq = sqrt(powerlaw_k(D, k0, da[b], dg[b]));
+          vs = sq * ws[b];
+          vc = sq * wc[b];
+          D.sqk_dm[((size_t)c * D.nf_dm + k0) * n + I] = sq;
+        }
+        D.coef_dm[((size_t)I * D.rows_dm + rs) * cp + c] = vs;
+        D.coef_dm[((size_t)I * D.rows_dm + rc) * cp + c] = vc;
+      }
+    }
+  }
+  __syncthreads();
+  // owned flags (the dense frequencies flag themselves in flag_dense)
+  for (int j = tid; j < nks; j += 256) {
+    const int k0 = k_first + k_step * j;
+    D.flag_k[(size_t)c * kmax + k0] = bad ? 0 : kflag[k0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward of chain c (< n_chains) over the diagonal and DM frequencies
+// k = k_first, k_first + k_step, ... (the dense ones are in k_cholt / k_chol);
+// the non-finite flag goes to slot `slot` of the chain's segment flags.  One
+// block of 256 threads; every thread of the block calls it.
+// ---------------------------------------------------------------------------
+__device__ inline void spec_bwd_block(const Dev &D, const double *__restrict__ x,
+                                      double *__restrict__ grad, int c, int k_first, int k_step,
+                                      int slot) {
+  const int tid = threadIdx.x;
+  const int n = D.n_psr;
+  const int kmax = max(D.ka, D.nf_dm);
+  const double *xc = x + (size_t)c * D.d;
+  double *gc = grad + (size_t)c * D.d;
+  const size_t cp = D.c_pad;
+  int fl = 0;
+  for (int k = tid; k < kmax; k += 256) fl |= D.flag_k[(size_t)c * kmax + k];
+  for (int k = tid; k < D.nf_gw; k += 256) fl |= D.flag_dense[(size_t)c * D.nf_gw + k];
+  const bool skip = __syncthreads_or(fl != 0 || D.st_pre[c] != 0);
+  bool fin = true;
+
+  const int nks = (kmax - k_first + k_step - 1) / k_step;
+  const int K2 = 2 * D.ka, K2d = 2 * D.nf_dm;
+  const int total = nks * n;
+  for (int base = tid; base < total; base += 256 * kSpecBatch) {
+    // the inputs of kSpecBatch items first (their loads overlap), then the items
+    // (sqrt(kappa) as the forward stored it)
+    double sr[kSpecBatch], as_[kSpecBatch], ac_[kSpecBatch], zs[kSpecBatch], zc[kSpecBatch];
+    double sd[kSpecBatch], bs_[kSpecBatch], bc_[kSpecBatch], ws[kSpecBatch], wc[kSpecBatch];
+#pragma unroll
+    for (int b = 0; b < kSpecBatch; ++b) {
+      const int idx = base + 256 * b;
+      sr[b] = as_[b] = ac_[b] = zs[b] = zc[b] = 0.0;
+      sd[b] = bs_[b] = bc_[b] = ws[b] = wc[b] = 0.0;
+      if (idx < total && !skip) {
+        const int j = idx / n, I = idx - j * n;
+        const int k0 = k_first + k_step * j;
+        const int rs = pt::harm_row(k0 + 1, 0), rc = pt::harm_row(k0 + 1, 1);
+        if (k0 >= D.nf_gw && k0 < D.ka) {
+          sr[b] = D.sqk_rn[((size_t)c * D.ka + k0) * n + I];
+          as_[b] = D.bar_rn[((size_t)I * D.rows_rn + rs) * cp + c];
+          ac_[b] = D.bar_rn[((size_t)I * D.rows_rn + rc) * cp + c];
+          zs[b] = xc[D.off_z + I * K2 + 2 * k0];
+          zc[b] = xc[D.off_z + I * K2 + 2 * k0 + 1];
+        }
+        if (k0 < D.nf_dm) {
+          sd[b] = D.sqk_dm[((size_t)c * D.nf_dm + k0) * n + I];
+          bs_[b] = D.bar_dm[((size_t)I * D.rows_dm + rs) * cp + c];
+          bc_[b] = D.bar_dm[((size_t)I * D.rows_dm + rc) * cp + c];
+          ws[b] = xc[D.off_zdm + I * K2d + 2 * k0];
+          wc[b] = xc[D.off_zdm + I * K2d + 2 * k0 + 1];
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kSpecBatch; ++b) {
+      const int idx = base + 256 * b;
+      if (idx >= total) continue;
+      const int j = idx / n, I = idx - j * n;
+      const int k0 = k_first + k_step * j;
+      const double lnfy = D.lnfy[k0];
+      if (k0 >= D.nf_gw && k0 < D.ka) {
+        double *drn = D.drn_k + ((size_t)c * D.ka + k0) * n * 2;
+        double g_s = 0.0, g_c = 0.0, d0 = 0.0, d1 = 0.0;
+        if (!skip) {
+          const double sq = sr[b];
+          g_s = sq * as_[b] - zs[b];
+          g_c = sq * ac_[b] - zc[b];
+          // d sqrt(kappa)/d log10A = ln10 sqrt(kappa); d/dgamma = -1/2 ln(f yr) sqrt(kappa)
+          const double az = (as_[b] * zs[b] + ac_[b] * zc[b]) * sq;
+          d0 = (k0 < D.nf_rn) ? az * pt::kLn10 : 0.0;
+          d1 = (k0 < D.nf_rn) ? az * (-0.5 * lnfy) : 0.0;
+          fin = fin && isfinite(g_s) && isfinite(g_c) && isfinite(d0) && isfinite(d1);
+        }
+        gc[D.off_z + I * K2 + 2 * k0] = g_s;
+        gc[D.off_z + I * K2 + 2 * k0 + 1] = g_c;
+        drn[2 * I] = d0;
+        drn[2 * I + 1] = d1;
+        if (I == 0) {
+          double *dth = D.dth_k + ((size_t)c * D.ka + k0) * 2;
+          dth[0] = 0.0;
+          dth[1] = 0.0;
+        }
+      }
+      if (k0 < D.nf_dm) {
+        double *ddm = D.ddm_k + ((size_t)c * D.nf_dm + k0) * n * 2;
+        double g_s = 0.0, g_c = 0.0, d0 = 0.0, d1 = 0.0;
+        if (!skip) {
+          const double sq = sd[b];
+          g_s = sq * bs_[b] - ws[b];
+          g_c = sq * bc_[b] - wc[b];
+          const double az = (bs_[b] * ws[b] + bc_[b] * wc[b]) * sq;
+          d0 = az * pt::kLn10;
+          d1 = az * (-0.5 * lnfy);
+          fin = fin && isfinite(g_s) && isfinite(g_c) && isfinite(d0) && isfinite(d1);
+        }
+        gc[D.off_zdm + I * K2d + 2 * k0] = g_s;
+        gc[D.off_zdm + I * K2d + 2 * k0 + 1] = g_c;
+        ddm[2 * I] = d0;
+        ddm[2 * I + 1] = d1;
+      }
+    }
+  }
+  fin = __syncthreads_and(fin);
+  if (tid == 0) D.flag_out[(size_t)c * (kmax + pt::kSpecSeg) + kmax + slot] = fin ? 0 : pt::kFlagOutNonfinite;
+}
+
+}  // namespace pt
