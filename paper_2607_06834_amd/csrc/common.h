@@ -206,6 +206,31 @@ __device__ inline int block_or256(int v, int *red4) {
   __syncthreads();
   return red4[0] | red4[1] | red4[2] | red4[3];
 }
+// The same over a workgroup of NW waves (wave sums added in wave order).
+template <int NW>
+__device__ inline double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) s += red[i];
+  return s;
+}
+template <int NW>
+__device__ inline int block_or(int v, int *red) {
+  v = wave_or(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  int s = red[0];
+#pragma unroll
+  for (int i = 1; i < NW; ++i) s |= red[i];
+  return s;
+}
 
 // A leapfrog kick and drift that k_finalize applies to a chain right after
 // its gradient: p += eps grad, x += eps M^-1 p, and one more invalid

@@ -28,11 +28,15 @@ __device__ inline double sum32(const double *p, size_t stride, int K) {
   return s;
 }
 
-__global__ __launch_bounds__(256) void k_finalize(Dev D, const double *x, double *__restrict__ logp,
+// one workgroup of kFinT threads per chain
+constexpr int kFinT = 1024;
+constexpr int kFinW = kFinT / 64;
+
+__global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, double *__restrict__ logp,
                                                   double *grad, int32_t *__restrict__ status,
                                                   pt::Kick kick, int has_kick) {
-  __shared__ double red[4];
-  __shared__ int ired[4];
+  __shared__ double red[kFinW];
+  __shared__ int ired[kFinW];
   const int c = blockIdx.x;
   const int t = threadIdx.x;
   const double *xc = x + (size_t)c * D.d;
@@ -46,10 +50,10 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *x, double
   const int nseg = max(1, min(pt::kSpecSeg, kmax));
   const int32_t *fo = D.flag_out + (size_t)c * (kmax + pt::kSpecSeg);
   int fl = 0;
-  for (int k = t; k < kmax; k += 256) fl |= D.flag_k[(size_t)c * kmax + k];
-  for (int k = t; k < D.nf_gw; k += 256) fl |= D.flag_dense[(size_t)c * D.nf_gw + k] | fo[k];
-  for (int k = t; k < nseg; k += 256) fl |= fo[kmax + k];
-  fl = pt::block_or256(fl, ired);
+  for (int k = t; k < kmax; k += kFinT) fl |= D.flag_k[(size_t)c * kmax + k];
+  for (int k = t; k < D.nf_gw; k += kFinT) fl |= D.flag_dense[(size_t)c * D.nf_gw + k] | fo[k];
+  for (int k = t; k < nseg; k += kFinT) fl |= fo[kmax + k];
+  fl = pt::block_or<kFinW>(fl, ired);
   // finiteness and squared norm of (u, z, z_dm), from the slices of k_spec_fwd
   double zz = 0.0;
   bool fin_in = true;
@@ -67,8 +71,8 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *x, double
 
   // ---- log p
   double ch = 0.0;
-  for (int p = t; p < n; p += 256) ch += D.chi_p[(size_t)p * cp + c];
-  ch = pt::block_sum256(ch, red);
+  for (int p = t; p < n; p += kFinT) ch += D.chi_p[(size_t)p * cp + c];
+  ch = pt::block_sum<kFinW>(ch, red);
   const double dz = (double)(D.d - D.off_u);
   double lp = -0.5 * ch - 0.5 * D.lnn_total - 0.5 * (double)D.n_toa * pt::kLn2Pi -
               0.5 * zz - 0.5 * dz * pt::kLn2Pi + D.prior_const;
@@ -82,14 +86,14 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *x, double
       fin = fin && isfinite(s);
     }
     if (D.nf_rn > 0) {
-      for (int e = t; e < 2 * n; e += 256) {
+      for (int e = t; e < 2 * n; e += kFinT) {
         const double s = sum32(D.drn_k + (size_t)c * D.ka * n * 2 + e, (size_t)n * 2, D.ka);
         gc[D.off_rn + e] = s;
         fin = fin && isfinite(s);
       }
     }
     if (D.nf_dm > 0) {
-      for (int e = t; e < 2 * n; e += 256) {
+      for (int e = t; e < 2 * n; e += kFinT) {
         const double s = sum32(D.ddm_k + (size_t)c * D.nf_dm * n * 2 + e, (size_t)n * 2, D.nf_dm);
         gc[D.off_dm + e] = s;
         fin = fin && isfinite(s);
@@ -103,7 +107,7 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *x, double
       fin = fin && isfinite(s);
     }
     // timing model: d/du = sigma_b M^T g - u
-    for (int e = t; e < 3 * n; e += 256) {
+    for (int e = t; e < 3 * n; e += kFinT) {
       const int I = e / 3, ti = e % 3;
       const int row = pt::tm_row(ti, D.kb);
       const double g = D.sigma_b * D.bar_rn[((size_t)I * D.rows_rn + row) * cp + c] - xc[D.off_u + e];
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *x, double
     if (!allfin || !isfinite(lp)) st = PTAFS_ST_NONFINITE;
   }
   if (st != 0) {
-    for (int i = t; i < D.d; i += 256) gc[i] = 0.0;
+    for (int i = t; i < D.d; i += kFinT) gc[i] = 0.0;
     lp = -INFINITY;
   }
   if (t == 0) {
@@ -125,12 +129,12 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *x, double
     __syncthreads();   // the workgroup's gradient stores are visible to all its threads
     if (t == 0 && kick.n_invalid && st != 0) kick.n_invalid[c] += 1;
     double *xw = kick.x + (size_t)c * D.d, *pw = kick.p + (size_t)c * D.d;
-    constexpr int B = 8;   // elements per thread whose loads are issued together
-    for (int i0 = t; i0 < D.d; i0 += 256 * B) {
+    constexpr int B = 12;  // elements per thread whose loads are issued together
+    for (int i0 = t; i0 < D.d; i0 += kFinT * B) {
       double pv[B], gv[B], xv[B], iv[B];
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        const int i = i0 + 256 * b;
+        const int i = i0 + kFinT * b;
         const bool in = i < D.d;
         pv[b] = in ? pw[i] : 0.0;
         gv[b] = in ? gc[i] : 0.0;
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(256) void k_finalize(Dev D, const double *x, double
       }
 #pragma unroll
       for (int b = 0; b < B; ++b) {
-        const int i = i0 + 256 * b;
+        const int i = i0 + kFinT * b;
         if (i >= D.d) continue;
         const double pi = pv[b] + kick.eps * gv[b];
         pw[i] = pi;
@@ -157,7 +161,7 @@ hipError_t launch_finalize(const pt::Dev &D, const double *x, double *logp, doub
                            int32_t *status, hipStream_t s, const pt::Kick *kick) {
   if (D.n_chains == 0) return hipSuccess;
   const pt::Kick k = kick ? *kick : pt::Kick{};
-  hipLaunchKernelGGL(k_finalize, dim3(D.n_chains), dim3(256), 0, s, D, x, logp, grad, status, k,
+  hipLaunchKernelGGL(k_finalize, dim3(D.n_chains), dim3(kFinT), 0, s, D, x, logp, grad, status, k,
                      kick ? 1 : 0);
   return hipGetLastError();
 }

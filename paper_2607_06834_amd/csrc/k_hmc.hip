@@ -33,34 +33,24 @@ __device__ inline double u53(uint32_t a, uint32_t b) {
   return (double)(((uint64_t)a << 21) | (uint64_t)(b >> 11));
 }
 
-template <typename T>
-__device__ T block_sum256(T v, T *red) {
-  const int t = threadIdx.x;
-  red[t] = v;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) red[t] = red[t] + red[t + o];
-    __syncthreads();
-  }
-  const T r = red[0];
-  __syncthreads();
-  return r;
-}
+// one workgroup of kHmcT threads per chain
+constexpr int kHmcT = 1024;
+constexpr int kHmcW = kHmcT / 64;
 
-// grid = n_chains, block = 256
-__global__ __launch_bounds__(256) void k_hmc_begin(int d, double eps, const double *inv_mass,
+// grid = n_chains, block = kHmcT
+__global__ __launch_bounds__(kHmcT) void k_hmc_begin(int d, double eps, const double *inv_mass,
                                                    uint64_t seed, const uint64_t *traj, double *x,
                                                    const double *logp, const double *grad,
                                                    double *p, double *x0, double *lp0, double *g0,
                                                    double *h0) {
-  __shared__ double red[256];
+  __shared__ double red[kHmcW];
   const int c = blockIdx.x;
   const uint32_t j = (uint32_t)(*traj);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const size_t off = (size_t)c * d;
   double kin = 0.0;
   const int npair = (d + 1) / 2;
-  for (int m = threadIdx.x; m < npair; m += 256) {
+  for (int m = threadIdx.x; m < npair; m += kHmcT) {
     uint32_t ctr[4] = {(uint32_t)m, (uint32_t)c, j, 0u};
     philox10(ctr, k0, k1);
     const double u1 = (u53(ctr[0], ctr[1]) + 1.0) * 0x1.0p-53;
@@ -84,7 +74,7 @@ __global__ __launch_bounds__(256) void k_hmc_begin(int d, double eps, const doub
       p[off + i] = pi;
     }
   }
-  kin = block_sum256(kin, red);
+  kin = pt::block_sum<kHmcW>(kin, red);
   if (threadIdx.x == 0) {
     lp0[c] = logp[c];
     h0[c] = -logp[c] + kin;
@@ -92,25 +82,25 @@ __global__ __launch_bounds__(256) void k_hmc_begin(int d, double eps, const doub
 }
 
 // final half kick, H1, accept / restore, optional sample
-__global__ __launch_bounds__(256) void k_hmc_end(int d, double eps, const double *inv_mass,
+__global__ __launch_bounds__(kHmcT) void k_hmc_end(int d, double eps, const double *inv_mass,
                                                  uint64_t seed, const uint64_t *traj, int n_chains, double *x, double *logp, double *grad,
                                                  double *p, const double *x0, const double *lp0,
                                                  const double *g0, const double *h0,
                                                  int64_t *n_accept, double *samples,
                                                  const int32_t *status, int64_t *n_invalid) {
-  __shared__ double red[256];
+  __shared__ double red[kHmcW];
   __shared__ int acc_s;
   const int c = blockIdx.x;
   const uint64_t jj = traj[0];      // trajectory number; traj[1] = first of this run
   const uint32_t j = (uint32_t)jj;
   const size_t off = (size_t)c * d;
   double kin = 0.0;
-  for (int i = threadIdx.x; i < d; i += 256) {
+  for (int i = threadIdx.x; i < d; i += kHmcT) {
     const double im = inv_mass ? inv_mass[i] : 1.0;
     const double pi = p[off + i] + 0.5 * eps * grad[off + i];
     kin += 0.5 * im * pi * pi;
   }
-  kin = block_sum256(kin, red);
+  kin = pt::block_sum<kHmcW>(kin, red);
   if (threadIdx.x == 0) {
     if (n_invalid && status[c] != 0) n_invalid[c] += 1;
     const double H1 = -logp[c] + kin;
@@ -125,7 +115,7 @@ __global__ __launch_bounds__(256) void k_hmc_end(int d, double eps, const double
   __syncthreads();
   const int a = acc_s;
   double *smp = samples ? samples + ((size_t)(jj - traj[1]) * n_chains + c) * d : nullptr;
-  for (int i = threadIdx.x; i < d; i += 256) {
+  for (int i = threadIdx.x; i < d; i += kHmcT) {
     double xi = x[off + i];
     if (!a) {
       xi = x0[off + i];
@@ -152,7 +142,7 @@ hipError_t launch_hmc_begin(const pt::Dev &D, int d, double eps, const double *i
                             uint64_t seed, const uint64_t *traj, double *x, const double *logp,
                             const double *grad, double *p, double *x0, double *lp0, double *g0,
                             double *h0, hipStream_t s) {
-  hipLaunchKernelGGL(k_hmc_begin, dim3(D.n_chains), dim3(256), 0, s, d, eps, inv_mass, seed, traj,
+  hipLaunchKernelGGL(k_hmc_begin, dim3(D.n_chains), dim3(kHmcT), 0, s, d, eps, inv_mass, seed, traj,
                      x, logp, grad, p, x0, lp0, g0, h0);
   return hipGetLastError();
 }
@@ -162,7 +152,7 @@ hipError_t launch_hmc_end(int n_chains, int d, double eps, const double *inv_mas
                           double *grad, double *p, const double *x0, const double *lp0,
                           const double *g0, const double *h0, int64_t *n_accept, double *samples,
                           const int32_t *status, int64_t *n_invalid, hipStream_t s) {
-  hipLaunchKernelGGL(k_hmc_end, dim3(n_chains), dim3(256), 0, s, d, eps, inv_mass, seed, traj,
+  hipLaunchKernelGGL(k_hmc_end, dim3(n_chains), dim3(kHmcT), 0, s, d, eps, inv_mass, seed, traj,
                      n_chains, x, logp, grad, p, x0, lp0, g0, h0, n_accept, samples, status,
                      n_invalid);
   return hipGetLastError();
