@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--tuning", type=int, nargs=3, metavar=("TILES", "WAVES", "XCD"),
+                    help="TOA-pass tuning for --no-tune and --profile-evals (default 33 1 1)")
     ap.add_argument("--profile-evals", type=int, default=0,
                     help="only run this many batched evaluations (for profiler passes)")
     ap.add_argument("--serve-full", action="store_true",
@@ -189,13 +191,15 @@ def main():
     if args.profile_evals:
         # a fixed number of evaluations at the benchmark's launch configuration
         # and nothing else, for counter passes of a profiler
-        g.ptafs_set_tuning(16, 1, 0)
+        g.ptafs_set_tuning(*(args.tuning or (33, 1, 1)))
         for _ in range(args.profile_evals):
             g.ptafs_logp_grad(x)
         torch.cuda.synchronize()
         print(json.dumps({"profile_evals": args.profile_evals, "chains": C,
                           "tuning": g.ptafs_get_tuning()}))
         return
+    if args.tuning:
+        g.ptafs_set_tuning(*args.tuning)
     tuning = g.ptafs_get_tuning()
     tune_log = None
     if not args.no_tune:

@@ -84,6 +84,7 @@ class Dataset:
                    "ptafs_dataset_create")
         self._h = h
         self.prior_lo, self.prior_hi = lo.copy(), hi.copy()
+        self.toa_offsets = np.asarray(desc["toa_offsets"], dtype=np.int64).copy()
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.layout = self.ptafs_layout(0)
         self.d = int(self.layout.d)

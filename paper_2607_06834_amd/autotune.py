@@ -9,8 +9,36 @@ its results reproducible: the reduction order depends only on the tuning.
 """
 from __future__ import annotations
 
+import numpy as np
+
 CANDIDATES = tuple((tpc, wpb, xcd) for tpc in (8, 12, 16, 24, 32, 64) for wpb in (1, 2, 4)
                    for xcd in (0, 1))
+
+
+def round_fitting_tpcs(toa_offsets, n_chains, n_cu, rounds=(1, 2), waves_per_simd=(1, 2, 3, 4)):
+    """Tiles per chunk at which the TOA pass's one-wave workgroups (chunks x
+    16-chain blocks) just fit a whole number of rounds of the device's wave
+    slots (n_cu x 4 SIMDs x waves per SIMD): the smallest such chunk for each
+    round count and occupancy.  Chunks of a pulsar are split evenly, so these
+    launches run in full rounds of near-equal waves."""
+    off = np.asarray(toa_offsets, dtype=np.int64)
+    tiles = (np.diff(off) + 15) // 16
+    n_cb = (int(n_chains) + 15) // 16
+    out = set()
+    for r in rounds:
+        for occ in waves_per_simd:
+            slots = r * int(n_cu) * 4 * occ
+            lo, hi = 1, max(1, int(tiles.max()))
+            if int(np.maximum(1, -(-tiles // hi)).sum()) * n_cb > slots:
+                continue
+            while lo < hi:                      # smallest tpc with waves <= slots
+                mid = (lo + hi) // 2
+                if int(np.maximum(1, -(-tiles // mid)).sum()) * n_cb <= slots:
+                    hi = mid
+                else:
+                    lo = mid + 1
+            out.add(lo)
+    return sorted(out)
 
 _cache: dict = {}
 
@@ -21,9 +49,16 @@ def shape_key(ds, n_chains):
             int(n_chains))
 
 
-def tune(ds, x, reps=5, candidates=CANDIDATES, use_cache=True):
+def tune(ds, x, reps=5, candidates=None, use_cache=True):
     """Pick the fastest tuning for evaluating ``x`` on ``ds``; returns
-    (tuning, log) and leaves the data set set to that tuning."""
+    (tuning, log) and leaves the data set set to that tuning.  The default
+    candidates are CANDIDATES plus the round-fitting chunk sizes."""
+    if candidates is None:
+        import torch
+        n_cu = torch.cuda.get_device_properties(x.device).multi_processor_count
+        fit = round_fitting_tpcs(ds.toa_offsets, x.shape[0], n_cu)
+        candidates = CANDIDATES + tuple((tpc, 1, xcd) for tpc in fit for xcd in (0, 1)
+                                        if (tpc, 1, xcd) not in CANDIDATES)
     key = shape_key(ds, x.shape[0])
     if use_cache and key in _cache:
         best = _cache[key]

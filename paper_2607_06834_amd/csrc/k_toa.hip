@@ -46,7 +46,9 @@ __device__ inline int xcd_remap(int b, int G) {
 // and the per-call 1/N.
 // ---------------------------------------------------------------------------
 template <int JTR, int JTD, int WPB, bool CW>
-__global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
+// (at least two waves per SIMD without the CW terms: a single wave leaves the
+// matrix core idle half the time; the CW terms need more registers than that)
+__global__ __launch_bounds__(64 * WPB, CW ? 1 : 2) void k_toa_mfma(Dev D, int xcd_map) {
   constexpr int NSR = 4 * JTR;
   constexpr int NSD = 4 * JTD;
   constexpr int ROWS = 16 * JTR;
@@ -100,41 +102,35 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
   const double *__restrict__ ivn = D.invn;
   const double *__restrict__ wdm = D.wdm;
 
-  // one tile ahead: forward-layout (sin, cos, tau) of TOA base + col and
-  // output-layout (dt, 1/N, w) of TOAs base + q + 4v
-  int base = tb + 16 * wv;
-  double ps = sth[base + col], pc = cth[base + col], pt = tau[base + col];
-  double pdt[4], piv[4], pw[4], ptt[4];
+  // Per-tile inputs: forward-layout (sin, cos, tau) of TOA base + col and
+  // output-layout (dt, 1/N, w, t) of TOAs base + q + 4v.  The loop is unrolled
+  // by two over the register sets A and B: the inputs of the next tile load
+  // into the idle set while the current one is used, a tile ahead and with
+  // no copies between the sets.
+  struct TileIn {
+    double s, c, t, dt[4], iv[4], w[4], tt[4];
+  };
+  auto load_in = [&](TileIn &in, int b) {
+    in.s = sth[b + col];
+    in.c = cth[b + col];
+    in.t = tau[b + col];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    pdt[v] = dtp[base + q + 4 * v];
-    piv[v] = ivn[base + q + 4 * v];
-    pw[v] = wdm[base + q + 4 * v];
-    if constexpr (CW) ptt[v] = D.t[base + q + 4 * v];
-  }
-
-  for (; base < te; base += 16 * WPB) {
-    const double s1 = ps, c1 = pc, tv = pt;
+    for (int v = 0; v < 4; ++v) {
+      in.dt[v] = dtp[b + q + 4 * v];
+      in.iv[v] = ivn[b + q + 4 * v];
+      in.w[v] = wdm[b + q + 4 * v];
+      if constexpr (CW) in.tt[v] = D.t[b + q + 4 * v];
+    }
+  };
+  auto tile = [&](const TileIn &in, int base) {
+    const double s1 = in.s, c1 = in.c, tv = in.t;
     double cdt[4], civ[4], cw[4], ctt[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      cdt[v] = pdt[v];
-      civ[v] = (base + q + 4 * v < te) ? piv[v] : 0.0;   // rows past the chunk contribute nothing
-      cw[v] = pw[v];
-      ctt[v] = ptt[v];
-    }
-    {
-      const int nb = base + 16 * WPB;
-      ps = sth[nb + col];
-      pc = cth[nb + col];
-      pt = tau[nb + col];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        pdt[v] = dtp[nb + q + 4 * v];
-        piv[v] = ivn[nb + q + 4 * v];
-        pw[v] = wdm[nb + q + 4 * v];
-        if constexpr (CW) ptt[v] = D.t[nb + q + 4 * v];
-      }
+      cdt[v] = in.dt[v];
+      civ[v] = (base + q + 4 * v < te) ? in.iv[v] : 0.0;   // rows past the chunk contribute nothing
+      cw[v] = in.w[v];
+      ctt[v] = in.tt[v];
     }
     // ---- forward layout: lane (col, q) walks harmonics q+1, q+5, ... of TOA base + col
     const double s2 = 2.0 * s1 * c1, c2 = (c1 - s1) * (c1 + s1);
@@ -142,7 +138,10 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
     const double s4 = 2.0 * s2 * c2, c4 = (c2 - s2) * (c2 + s2);
     double sh = q == 0 ? s1 : (q == 1 ? s2 : (q == 2 ? s3 : s4));
     double ch = q == 0 ? c1 : (q == 1 ? c2 : (q == 2 ? c3 : c4));
-    double fv[NSR];
+    // ---- forward contraction R = F A, R_dm = F A_dm (16 TOA x 16 chains),
+    //      each k-step issued as soon as its basis pair exists
+    v4d rr = v4d{0.0, 0.0, 0.0, 0.0};
+    v4d rd = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < NSR / 2; ++m) {
       double fa, fb;
@@ -156,21 +155,15 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
         fa = (h < kb) ? sh : ta;
         fb = (h < kb) ? ch : tb2;
       }
-      fv[2 * m] = fa;
-      fv[2 * m + 1] = fb;
       ft[col * FS + 8 * m + q] = fa;
       ft[col * FS + 8 * m + 4 + q] = fb;
       const double sn = sh * c4 + ch * s4;
       ch = ch * c4 - sh * s4;
       sh = sn;
-    }
-    // ---- forward contraction: R = F A, R_dm = F A_dm (16 TOA x 16 chains)
-    v4d rr = v4d{0.0, 0.0, 0.0, 0.0};
-    v4d rd = v4d{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s < NSR; ++s) {
-      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fv[s], cr[s], rr, 0, 0, 0);
-      if (s < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fv[s], cd[s], rd, 0, 0, 0);
+      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, cr[2 * m], rr, 0, 0, 0);
+      if (2 * m < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, cd[2 * m], rd, 0, 0, 0);
+      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, cr[2 * m + 1], rr, 0, 0, 0);
+      if (2 * m + 1 < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, cd[2 * m + 1], rd, 0, 0, 0);
     }
     wave_sync();
     // ---- residuals: lane (col, q) holds TOAs base + q + 4v, chain col
@@ -201,6 +194,21 @@ __global__ __launch_bounds__(64 * WPB) void k_toa_mfma(Dev D, int xcd_map) {
       }
     }
     wave_sync();
+  };
+
+  // (the padding of the per-TOA arrays covers the load one tile past the chunk)
+  int base = tb + 16 * wv;
+  TileIn A, B;
+  load_in(A, base);
+  for (;;) {
+    if (base >= te) break;
+    load_in(B, base + 16 * WPB);
+    tile(A, base);
+    base += 16 * WPB;
+    if (base >= te) break;
+    load_in(A, base + 16 * WPB);
+    tile(B, base);
+    base += 16 * WPB;
   }
 
   // ---- per-wave chi^2 over the four lane groups (fixed order)

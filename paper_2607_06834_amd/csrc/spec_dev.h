@@ -17,8 +17,10 @@
 
 namespace pt {
 
-// items per thread whose loads are issued together
-constexpr int kSpecBatch = 4;
+// Items per thread whose loads are issued together: up to 10 loads an item,
+// within the 63 loads a wave can have in flight; single loads for |z|^2.
+constexpr int kSpecBatch = 6;
+constexpr int kZzBatch = 16;
 
 // Forward of chain c (< c_pad): slice seg of nseg of the input checks
 // (segment 0 also does the per-chain work) and the diagonal and DM
@@ -54,12 +56,12 @@ __device__ inline void spec_fwd_block(const Dev &D, const double *__restrict__ x
     double zz = 0.0;
     bool fin = true;
     if (real)
-      for (int e = e0 + tid; e < e1; e += 256 * kSpecBatch) {
-        double v[kSpecBatch];
+      for (int e = e0 + tid; e < e1; e += 256 * kZzBatch) {
+        double v[kZzBatch];
 #pragma unroll
-        for (int b = 0; b < kSpecBatch; ++b) v[b] = (e + 256 * b < e1) ? xc[e + 256 * b] : 0.0;
+        for (int b = 0; b < kZzBatch; ++b) v[b] = (e + 256 * b < e1) ? xc[e + 256 * b] : 0.0;
 #pragma unroll
-        for (int b = 0; b < kSpecBatch; ++b) {
+        for (int b = 0; b < kZzBatch; ++b) {
           fin = fin && isfinite(v[b]);
           zz += v[b] * v[b];
         }
