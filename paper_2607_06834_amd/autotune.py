@@ -15,15 +15,15 @@ CANDIDATES = tuple((tpc, wpb, xcd) for tpc in (8, 12, 16, 24, 32, 64) for wpb in
                    for xcd in (0, 1))
 
 
-def round_fitting_tpcs(toa_offsets, n_chains, n_cu, rounds=(1, 2), waves_per_simd=(1, 2, 3, 4)):
-    """Tiles per chunk at which the TOA pass's one-wave workgroups (chunks x
-    16-chain blocks) just fit a whole number of rounds of the device's wave
-    slots (n_cu x 4 SIMDs x waves per SIMD): the smallest such chunk for each
-    round count and occupancy.  Chunks of a pulsar are split evenly, so these
-    launches run in full rounds of near-equal waves."""
+def round_fitting_tpcs(toa_offsets, n_chains, n_cu, wpb=1, rounds=(1, 2), waves_per_simd=(1, 2, 3, 4)):
+    """Tiles per chunk at which the TOA pass's waves (chunks x 16-chain blocks
+    x wpb waves per workgroup) just fit a whole number of rounds of the
+    device's wave slots (n_cu x 4 SIMDs x waves per SIMD): the smallest such
+    chunk for each round count and occupancy.  Chunks of a pulsar are split
+    evenly, so these launches run in full rounds of near-equal waves."""
     off = np.asarray(toa_offsets, dtype=np.int64)
     tiles = (np.diff(off) + 15) // 16
-    n_cb = (int(n_chains) + 15) // 16
+    n_cb = (int(n_chains) + 15) // 16 * int(wpb)
     out = set()
     for r in rounds:
         for occ in waves_per_simd:
@@ -56,9 +56,11 @@ def tune(ds, x, reps=5, candidates=None, use_cache=True):
     if candidates is None:
         import torch
         n_cu = torch.cuda.get_device_properties(x.device).multi_processor_count
-        fit = round_fitting_tpcs(ds.toa_offsets, x.shape[0], n_cu)
-        candidates = CANDIDATES + tuple((tpc, 1, xcd) for tpc in fit for xcd in (0, 1)
-                                        if (tpc, 1, xcd) not in CANDIDATES)
+        fit = [(tpc, 1) for tpc in round_fitting_tpcs(ds.toa_offsets, x.shape[0], n_cu)]
+        fit += [(tpc, 4) for tpc in round_fitting_tpcs(ds.toa_offsets, x.shape[0], n_cu, wpb=4,
+                                                        waves_per_simd=(2, 3))]
+        candidates = CANDIDATES + tuple((tpc, wpb, xcd) for tpc, wpb in fit for xcd in (0, 1)
+                                        if (tpc, wpb, xcd) not in CANDIDATES)
     key = shape_key(ds, x.shape[0])
     if use_cache and key in _cache:
         best = _cache[key]

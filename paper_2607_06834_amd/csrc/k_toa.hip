@@ -45,17 +45,26 @@ __device__ inline int xcd_remap(int b, int G) {
 // leaves the arrays): sin/cos of 2 pi t / T, tau, DM weight w, residual dt,
 // and the per-call 1/N.
 // ---------------------------------------------------------------------------
+//
+// With four waves per workgroup (SHB) the waves share the coefficient panels
+// in LDS instead of holding them in registers, and keep one set of per-tile
+// inputs, reloaded once the residuals are formed: three waves per SIMD.  With
+// one or two waves per workgroup the panels live in registers and the inputs
+// alternate between two register sets: two waves per SIMD.  (A single wave
+// leaves the matrix core idle about half the time; the CW terms need more
+// registers than either bound allows.)
 template <int JTR, int JTD, int WPB, bool CW>
-// (at least two waves per SIMD without the CW terms: a single wave leaves the
-// matrix core idle half the time; the CW terms need more registers than that)
-__global__ __launch_bounds__(64 * WPB, CW ? 1 : 2) void k_toa_mfma(Dev D, int xcd_map) {
+__global__ __launch_bounds__(64 * WPB, CW ? 1 : (WPB == 4 ? 3 : 2))
+void k_toa_mfma(Dev D, int xcd_map) {
   constexpr int NSR = 4 * JTR;
   constexpr int NSD = 4 * JTD;
   constexpr int ROWS = 16 * JTR;
   constexpr int FS = ROWS + 1;                 // padded LDS row stride (doubles)
+  constexpr bool SHB = WPB == 4;
   __shared__ double ftab[WPB][16 * FS];
   __shared__ double cred[WPB][16];
   __shared__ double cwred[CW ? WPB : 1][8][16];
+  __shared__ double bop[SHB ? 4 * (NSR + NSD) * 16 : 1];   // panels [row][16 chains]
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, q = lane >> 4;
@@ -69,8 +78,15 @@ __global__ __launch_bounds__(64 * WPB, CW ? 1 : 2) void k_toa_mfma(Dev D, int xc
   const int kb = D.kb;
 
   // B operands: coefficient rows 4s + q for this lane's chain
-  double cr[NSR], cd[NSD > 0 ? NSD : 1];
-  {
+  double cr[SHB ? 1 : NSR], cd[(SHB || NSD == 0) ? 1 : NSD];
+  if constexpr (SHB) {
+    const double *pr = D.coef_rn + (size_t)p * D.rows_rn * cp + cb * 16;
+    for (int e = threadIdx.x; e < 4 * NSR * 16; e += 64 * WPB) bop[e] = pr[(size_t)(e >> 4) * cp + (e & 15)];
+    const double *pd = D.coef_dm + (size_t)p * D.rows_dm * cp + cb * 16;
+    for (int e = threadIdx.x; e < 4 * NSD * 16; e += 64 * WPB)
+      bop[4 * NSR * 16 + e] = pd[(size_t)(e >> 4) * cp + (e & 15)];
+    __syncthreads();
+  } else {
     const double *pr = D.coef_rn + (size_t)p * D.rows_rn * cp + chain;
 #pragma unroll
     for (int s = 0; s < NSR; ++s) cr[s] = pr[(size_t)(4 * s + q) * cp];
@@ -80,6 +96,10 @@ __global__ __launch_bounds__(64 * WPB, CW ? 1 : 2) void k_toa_mfma(Dev D, int xc
       for (int s = 0; s < NSD; ++s) cd[s] = pd[(size_t)(4 * s + q) * cp];
     }
   }
+  auto crs = [&](int s) -> double { return SHB ? bop[(4 * s + q) * 16 + col] : cr[SHB ? 0 : s]; };
+  auto cds = [&](int s) -> double {
+    return SHB ? bop[(4 * NSR + 4 * s + q) * 16 + col] : cd[(SHB || NSD == 0) ? 0 : s];
+  };
   v4d ar[JTR];
   v4d ad[JTD > 0 ? JTD : 1];
 #pragma unroll
@@ -103,10 +123,7 @@ __global__ __launch_bounds__(64 * WPB, CW ? 1 : 2) void k_toa_mfma(Dev D, int xc
   const double *__restrict__ wdm = D.wdm;
 
   // Per-tile inputs: forward-layout (sin, cos, tau) of TOA base + col and
-  // output-layout (dt, 1/N, w, t) of TOAs base + q + 4v.  The loop is unrolled
-  // by two over the register sets A and B: the inputs of the next tile load
-  // into the idle set while the current one is used, a tile ahead and with
-  // no copies between the sets.
+  // output-layout (dt, 1/N, w, t) of TOAs base + q + 4v.
   struct TileIn {
     double s, c, t, dt[4], iv[4], w[4], tt[4];
   };
@@ -122,7 +139,10 @@ __global__ __launch_bounds__(64 * WPB, CW ? 1 : 2) void k_toa_mfma(Dev D, int xc
       if constexpr (CW) in.tt[v] = D.t[b + q + 4 * v];
     }
   };
-  auto tile = [&](const TileIn &in, int base) {
+  // Front of a tile: basis, forward contraction and residuals (G into gr, gd;
+  // the transposed basis into ft); back: the adjoint contraction.
+  double gr[4], gd[4];
+  auto front = [&](const TileIn &in, int base) {
     const double s1 = in.s, c1 = in.c, tv = in.t;
     double cdt[4], civ[4], cw[4], ctt[4];
 #pragma unroll
@@ -160,15 +180,14 @@ __global__ __launch_bounds__(64 * WPB, CW ? 1 : 2) void k_toa_mfma(Dev D, int xc
       const double sn = sh * c4 + ch * s4;
       ch = ch * c4 - sh * s4;
       sh = sn;
-      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, cr[2 * m], rr, 0, 0, 0);
-      if (2 * m < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, cd[2 * m], rd, 0, 0, 0);
-      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, cr[2 * m + 1], rr, 0, 0, 0);
-      if (2 * m + 1 < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, cd[2 * m + 1], rd, 0, 0, 0);
+      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, crs(2 * m), rr, 0, 0, 0);
+      if (2 * m < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, cds(2 * m), rd, 0, 0, 0);
+      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, crs(2 * m + 1), rr, 0, 0, 0);
+      if (2 * m + 1 < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, cds(2 * m + 1), rd, 0, 0, 0);
     }
     wave_sync();
     // ---- residuals: lane (col, q) holds TOAs base + q + 4v, chain col
     // (v_mfma_f64_16x16x4f64 returns D[q + 4v][col] in item v of lane col + 16q)
-    double gr[4], gd[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       double r = cdt[v] - rr[v] - cw[v] * rd[v];
@@ -183,6 +202,8 @@ __global__ __launch_bounds__(64 * WPB, CW ? 1 : 2) void k_toa_mfma(Dev D, int xc
       gd[v] = cw[v] * g;
       if constexpr (CW) cwl.adjoint(cs, g, cacc);
     }
+  };
+  auto back = [&]() {
     // ---- adjoint contraction: Abar += F^T G, Abar_dm += F^T (w G)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -198,17 +219,32 @@ __global__ __launch_bounds__(64 * WPB, CW ? 1 : 2) void k_toa_mfma(Dev D, int xc
 
   // (the padding of the per-TOA arrays covers the load one tile past the chunk)
   int base = tb + 16 * wv;
-  TileIn A, B;
-  load_in(A, base);
-  for (;;) {
-    if (base >= te) break;
-    load_in(B, base + 16 * WPB);
-    tile(A, base);
-    base += 16 * WPB;
-    if (base >= te) break;
-    load_in(A, base + 16 * WPB);
-    tile(B, base);
-    base += 16 * WPB;
+  if constexpr (SHB) {
+    // one input set, refilled for the next tile during the adjoint
+    TileIn A;
+    load_in(A, base);
+    for (; base < te; base += 16 * WPB) {
+      front(A, base);
+      load_in(A, base + 16 * WPB);
+      back();
+    }
+  } else {
+    // two input sets: the next tile's inputs load into the idle one, a tile
+    // ahead and with no copies between the sets
+    TileIn A, B;
+    load_in(A, base);
+    for (;;) {
+      if (base >= te) break;
+      load_in(B, base + 16 * WPB);
+      front(A, base);
+      back();
+      base += 16 * WPB;
+      if (base >= te) break;
+      load_in(A, base + 16 * WPB);
+      front(B, base);
+      back();
+      base += 16 * WPB;
+    }
   }
 
   // ---- per-wave chi^2 over the four lane groups (fixed order)
