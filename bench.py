@@ -23,6 +23,11 @@ FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
 HBM_PEAK_GBS = 8000.0
 
 
+def _log(msg):
+    """Progress of the run on stderr (stdout carries only the JSON line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def toa_pass_flops(ds, n_chains):
     """Algorithmic flops of one TOA-pass launch: per TOA and chain,
     F a (2K sin/cos + 3 timing-model columns), F_dm a_dm, the residual,
@@ -141,6 +146,7 @@ def serving_bench(n_traj, rates, n_req, n_chains=16, n_leapfrog=20, quantum=10, 
     for rate in rates:
         r = run(rate, pool, max_slots)
         out.append(r)
+        _log(f"serving at {rate} req/s: p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms")
         if r["p50_ms"] > 20 * np.median(alone):
             break                            # saturated
     return dict(
@@ -204,6 +210,7 @@ def main():
     tune_log = None
     if not args.no_tune:
         tuning, tune_log = autotune.tune(g, x)
+        _log(f"autotuned {tuning}")
 
     # diagonal inverse mass from the local precision at the injection (App. A),
     # chains moved to the conditional mode of their coefficients, and the
@@ -233,6 +240,7 @@ def main():
         # every timed leapfrog evaluation must have been a full, valid one
         valid = 1.0 - float(bad.sum().item()) / (C * L * args.steps)
     ms_step = el / args.steps * 1e3
+    _log(f"{args.steps} trajectories in {el:.3f} s")
     value = C * L * args.steps / el
 
     # per-stage timing of the evaluation (HIP events on the launch stream)
@@ -242,11 +250,21 @@ def main():
     achieved = flops / (stages["toa"] * 1e-3) / 1e12
     plain = None
     if not args.no_plain:
-        ps = g.ptafs_profile_stages(x, reps=2, plain=True, stream=stream)
+        # the plain form at its own best chunking (its launches are per pulsar)
+        best = None
+        for tpc in (8, 16):
+            g.ptafs_set_tuning(tpc, 1, 0)
+            ps = g.ptafs_profile_stages(x, reps=2, plain=True, stream=stream)
+            if best is None or sum(ps.values()) < sum(best[1].values()):
+                best = (tpc, ps)
+        g.ptafs_set_tuning(*tuning)
+        tpc, ps = best
         plain = dict(value=C / (sum(ps.values()) * 1e-3), unit="grad evals/s",
                      ms_per_eval=round(sum(ps.values()), 4),
-                     toa_ms=round(ps["toa"], 4))
+                     toa_ms=round(ps["toa"], 4), tiles_per_chunk=tpc)
+    _log("stages and plain form done")
     cpu = None if args.no_cpu else cpu_baseline(ds, min_seconds=args.cpu_seconds)
+    _log("cpu baseline done")
     serving = None
     if not args.no_serve:
         if args.serve_full:
