@@ -81,11 +81,14 @@ __host__ __device__ inline int pk(int i, int j) { return (i * (i + 1)) / 2 + j; 
 // Dense per-frequency factors: up to kTileMaxNT 16-row tiles they are kept
 // tile-major (the lower tiles of the padded matrix, 256 doubles each, row-major
 // inside a tile); beyond that packed row-major.
+// The tiled adjoint (k_cholt_bwd) holds up to kTileMaxNT tiles in registers,
+// the tiled factorisation (k_cholt_fwd) up to kTileFwdMaxNT.
 constexpr int kTileMaxNT = 5;
+constexpr int kTileFwdMaxNT = 7;
 __host__ __device__ inline int chol_tiles(int n) { return (n + 15) / 16; }
 __host__ __device__ inline size_t chol_store_doubles(int n) {
   const int nt = chol_tiles(n);
-  return nt <= kTileMaxNT ? (size_t)(nt * (nt + 1) / 2) * 256 : (size_t)n * (n + 1) / 2;
+  return nt <= kTileFwdMaxNT ? (size_t)(nt * (nt + 1) / 2) * 256 : (size_t)n * (n + 1) / 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -120,7 +123,7 @@ struct Dev {
   const double *pos, *gamma;
   const double *gchol;         // chol(Gamma), packed row-major lower
   const double *gtile;         // chol(Gamma) zero-padded, lower 16x16 tiles (up to kTileMaxNT)
-  const double *gam_tile;      // Gamma zero-padded, lower 16x16 tiles (diagonal tiles full)
+  const double *gam_tile;      // Gamma zero-padded, lower 16x16 tiles, diagonal tiles full (up to kTileFwdMaxNT)
   const double *prior_lo, *prior_hi;
   // power-law spectra: ln(f_k yr) for f_k = (k + 1) / T, k < PTAFS_MAX_HARM, and ln(yr^3 / (12 pi^2 T))
   const double *lnfy;

@@ -1,7 +1,9 @@
 // Dense per-frequency prior covariance for the frequencies that carry the
-// common process (k <= nf_gw), for arrays of more than 80 pulsars (smaller
-// arrays use the matrix-core kernels of k_cholt): factorisation and
-// whitening transform (forward) and the adjoint of both (backward).
+// common process (k <= nf_gw), for the arrays the matrix-core kernels of
+// k_cholt do not take: the factorisation and whitening transform (forward)
+// beyond 112 pulsars, the adjoint of both (backward) beyond 80.  Up to 112
+// pulsars the adjoint reads k_cholt's tile-major factor; beyond, the packed
+// factor of the forward here.
 //
 // Forward (Sec. IV.A, Eqs. HD, prior_cov; Sec. II.B, Eq.
 // standardizing_transform with mu = 0):
@@ -197,6 +199,18 @@ __global__ __launch_bounds__(NMAX > 64 ? 128 : 64) void k_chol_fwd(Dev D, const 
 // l + 64 (the second only has rows >= 64).
 // ---------------------------------------------------------------------------
 // sum_c sum_i x_i v_ci (sum_{j<i} z_cj x_j + z_ci x_i / 2) over rows R0..n-1
+// Element (i, m), m <= i, of a stored factor: tile-major (lower 16x16 tiles,
+// row-major inside) up to kTileFwdMaxNT tiles, packed row-major beyond.
+template <int NMAX>
+__device__ inline double cel(const double *__restrict__ Cp, int i, int m) {
+  if constexpr (NMAX <= 16 * pt::kTileFwdMaxNT) {
+    const int I = i >> 4, J = m >> 4;
+    return Cp[(I * (I + 1) / 2 + J) * 256 + (i & 15) * 16 + (m & 15)];
+  } else {
+    return Cp[pk(i, m)];
+  }
+}
+
 template <int NMAX, int R0>
 __device__ inline double quad_form(const double (&X)[NMAX - R0], const double (*vz)[4], int n) {
   double ss = 0.0, sc = 0.0, q = 0.0;
@@ -222,19 +236,18 @@ __device__ inline void forward_subst(double (&X)[NMAX - R0], const double *__res
 #pragma unroll
   for (int i = R0; i < NMAX; ++i) {
     if (i < n) {
-      const double *r = Cp + pk(i, 0);
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
 #pragma unroll
       for (int m = R0; m < i; m += 4) {
-        a0 += r[m] * X[m - R0];
-        if (m + 1 < i) a1 += r[m + 1] * X[m + 1 - R0];
-        if (m + 2 < i) a2 += r[m + 2] * X[m + 2 - R0];
-        if (m + 3 < i) a3 += r[m + 3] * X[m + 3 - R0];
+        a0 += cel<NMAX>(Cp, i, m) * X[m - R0];
+        if (m + 1 < i) a1 += cel<NMAX>(Cp, i, m + 1) * X[m + 1 - R0];
+        if (m + 2 < i) a2 += cel<NMAX>(Cp, i, m + 2) * X[m + 2 - R0];
+        if (m + 3 < i) a3 += cel<NMAX>(Cp, i, m + 3) * X[m + 3 - R0];
       }
       double b;
       if constexpr (GCOL) b = (I <= i && I < n) ? gch[pk(i, I)] : 0.0;
       else b = (i == I) ? 1.0 : 0.0;
-      X[i - R0] = (b - ((a0 + a1) + (a2 + a3))) / r[i];
+      X[i - R0] = (b - ((a0 + a1) + (a2 + a3))) / cel<NMAX>(Cp, i, i);
     } else {
       X[i - R0] = 0.0;
     }
@@ -279,8 +292,7 @@ __global__ __launch_bounds__(64) void k_chol_bwd(Dev D, const double *__restrict
     }
     return;
   }
-  const int np = (n * (n + 1)) / 2;
-  const double *Cp = lst + ((size_t)c * D.nf_gw + k0) * np;
+  const double *Cp = lst + ((size_t)c * D.nf_gw + k0) * pt::chol_store_doubles(n);
 
   // v_c = C^T abar_c for both owned columns
   double v1s = 0.0, v1c = 0.0, v2s = 0.0, v2c = 0.0;
@@ -288,12 +300,11 @@ __global__ __launch_bounds__(64) void k_chol_bwd(Dev D, const double *__restrict
   for (int m = 0; m < n; ++m) {
     const double as = bar[((size_t)m * D.rows_rn + rs) * cp + c];
     const double ac = bar[((size_t)m * D.rows_rn + rc) * cp + c];
-    const double *row = Cp + pk(m, 0);
-    const double e1 = (c1 && I1 <= m) ? row[I1] : 0.0;
+    const double e1 = (c1 && I1 <= m) ? cel<NMAX>(Cp, m, I1) : 0.0;
     v1s += e1 * as;
     v1c += e1 * ac;
     if constexpr (TWO) {
-      const double e2 = (c2 && I2 <= m) ? row[I2] : 0.0;
+      const double e2 = (c2 && I2 <= m) ? cel<NMAX>(Cp, m, I2) : 0.0;
       v2s += e2 * as;
       v2c += e2 * ac;
     }
@@ -387,7 +398,7 @@ namespace ptk {
 // tiled kernels take both.
 hipError_t launch_spectral_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
   if (D.c_pad == 0) return hipSuccess;
-  if (D.nf_gw > 0 && pt::chol_tiles(D.n_psr) <= pt::kTileMaxNT) return launch_cholt_fwd(D, x, s);
+  if (D.nf_gw > 0 && pt::chol_tiles(D.n_psr) <= pt::kTileFwdMaxNT) return launch_cholt_fwd(D, x, s);
   const hipError_t e = launch_spec_fwd(D, x, s);
   return e == hipSuccess ? launch_chol_fwd(D, x, s) : e;
 }
@@ -403,8 +414,6 @@ hipError_t launch_spectral_bwd(const pt::Dev &D, const double *x, double *grad, 
 hipError_t launch_chol_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
   if (D.nf_gw == 0 || D.c_pad == 0) return hipSuccess;
   switch (pt::chol_tiles(D.n_psr)) {
-    case 6: return launch_fwd_t<96>(D, x, s);
-    case 7: return launch_fwd_t<112>(D, x, s);
     case 8: return launch_fwd_t<128>(D, x, s);
   }
   return hipErrorInvalidValue;

@@ -1,6 +1,8 @@
-// Dense per-frequency prior covariance on FP64 matrix cores, for arrays of up
-// to 80 pulsars (five 16-row tiles): one 64-lane wave per (frequency, chain)
-// holds the lower tiles of the padded matrix in registers.
+// Dense per-frequency prior covariance on FP64 matrix cores: one 64-lane wave
+// per (frequency, chain) holds the lower 16x16 tiles of the padded matrix in
+// registers.  The factorisation takes arrays of up to 112 pulsars (seven
+// tiles), the adjoint up to 80 (five tiles; beyond that k_chol's adjoint reads
+// the same tile-major factor).
 //
 // Forward (Sec. IV.A, Eqs. HD, prior_cov; Sec. II.B, Eq.
 // standardizing_transform with mu = 0): C = chol(rho_k Gamma + diag kappa_.k)
@@ -582,6 +584,8 @@ hipError_t launch_cholt_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
     case 3: return launch_fwd_t<3>(D, x, s);
     case 4: return launch_fwd_t<4>(D, x, s);
     case 5: return launch_fwd_t<5>(D, x, s);
+    case 6: return launch_fwd_t<6>(D, x, s);
+    case 7: return launch_fwd_t<7>(D, x, s);
   }
   return hipErrorInvalidValue;
 }

@@ -75,7 +75,7 @@ class Server:
     (``time.perf_counter`` seconds)."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 8, quantum: int = 10, device: int = 0,
-                 tuning=(16, 1, 1)):
+                 tuning=(16, 1, 1), use_graph: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("the server needs a HIP GPU")
         self.budget = int(budget_bytes)
@@ -83,6 +83,7 @@ class Server:
         self.quantum = max(1, int(quantum))
         self.device = int(device)
         self.tuning = tuning
+        self.use_graph = bool(use_graph)
         self._lock = threading.Condition()
         self._queue: collections.deque[_Req] = collections.deque()
         self._reqs: dict[int, _Req] = {}
@@ -190,7 +191,7 @@ class Server:
         with torch.cuda.stream(r.stream):
             r.ds.ptafs_hmc_run(r.x, r.lp, r.gr, r.acc, n_traj=q, n_leapfrog=r.n_leapfrog, eps=r.eps,
                                seed=r.seed, traj0=r.done_traj, inv_mass=r.im, samples=r.smp[:q],
-                               n_invalid=r.bad, stream=r.stream)
+                               n_invalid=r.bad, use_graph=self.use_graph, stream=r.stream)
             r.event = torch.cuda.Event()
             r.event.record(r.stream)
         r.pending = q
