@@ -81,8 +81,9 @@ __host__ __device__ inline int pk(int i, int j) { return (i * (i + 1)) / 2 + j; 
 // Dense per-frequency factors: up to kTileMaxNT 16-row tiles they are kept
 // tile-major (the lower tiles of the padded matrix, 256 doubles each, row-major
 // inside a tile); beyond that packed row-major.
-// The tiled adjoint (k_cholt_bwd) holds up to kTileMaxNT tiles in registers,
-// the tiled factorisation (k_cholt_fwd) up to kTileFwdMaxNT.
+// The tiled factorisation (k_cholt_fwd) holds up to kTileFwdMaxNT tiles in
+// registers; the tiled adjoint (k_cholt_bwd) all of C^-1 up to kTileMaxNT
+// tiles, one block column of it (the rest in LDS) up to kTileFwdMaxNT.
 constexpr int kTileMaxNT = 5;
 constexpr int kTileFwdMaxNT = 7;
 __host__ __device__ inline int chol_tiles(int n) { return (n + 15) / 16; }
@@ -122,7 +123,7 @@ struct Dev {
   double lnn_total;
   const double *pos, *gamma;
   const double *gchol;         // chol(Gamma), packed row-major lower
-  const double *gtile;         // chol(Gamma) zero-padded, lower 16x16 tiles (up to kTileMaxNT)
+  const double *gtile;         // chol(Gamma) zero-padded, lower 16x16 tiles (up to kTileFwdMaxNT)
   const double *gam_tile;      // Gamma zero-padded, lower 16x16 tiles, diagonal tiles full (up to kTileFwdMaxNT)
   const double *prior_lo, *prior_hi;
   // power-law spectra: ln(f_k yr) for f_k = (k + 1) / T, k < PTAFS_MAX_HARM, and ln(yr^3 / (12 pi^2 T))

@@ -405,9 +405,11 @@ hipError_t launch_spectral_fwd(const pt::Dev &D, const double *x, hipStream_t s)
 
 hipError_t launch_spectral_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s) {
   if (D.n_chains == 0) return hipSuccess;
-  if (D.nf_gw > 0 && pt::chol_tiles(D.n_psr) <= pt::kTileMaxNT) return launch_cholt_bwd(D, x, grad, s);
+  const int nt = pt::chol_tiles(D.n_psr);
+  if (D.nf_gw > 0 && nt <= pt::kTileMaxNT) return launch_cholt_bwd(D, x, grad, s);
   const hipError_t e = launch_spec_bwd(D, x, grad, s);
-  return e == hipSuccess ? launch_chol_bwd(D, x, grad, s) : e;
+  if (e != hipSuccess || D.nf_gw == 0) return e;
+  return nt <= pt::kTileFwdMaxNT ? launch_cholt_bwd(D, x, grad, s) : launch_chol_bwd(D, x, grad, s);
 }
 
 // dense frequencies of more than kTileMaxNT tiles (the row-per-thread kernels)
@@ -422,8 +424,6 @@ hipError_t launch_chol_fwd(const pt::Dev &D, const double *x, hipStream_t s) {
 hipError_t launch_chol_bwd(const pt::Dev &D, const double *x, double *grad, hipStream_t s) {
   if (D.nf_gw == 0 || D.n_chains == 0) return hipSuccess;
   switch (pt::chol_tiles(D.n_psr)) {
-    case 6: return launch_bwd_t<96>(D, x, grad, s);
-    case 7: return launch_bwd_t<112>(D, x, grad, s);
     case 8: return launch_bwd_t<128>(D, x, grad, s);
   }
   return hipErrorInvalidValue;

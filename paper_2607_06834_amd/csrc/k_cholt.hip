@@ -286,13 +286,22 @@ __device__ inline void scan_tile(const v4d &X, int row0, const double (*vz)[4], 
   st.rc += tc;
 }
 
+// Up to kTileMaxNT tiles all of W = C^-1 lives in registers, kProbPerGroup
+// problems per workgroup.  Beyond (COLW) the workgroup is one wave and one
+// problem: W is built one block column at a time in registers and kept in
+// LDS (the diagonal inverses in place of the diagonal tiles of C).
 template <int NT>
-__global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const double *__restrict__ x,
+constexpr int bwd_probs() { return NT > pt::kTileMaxNT ? 1 : kProbPerGroup; }
+
+template <int NT>
+__global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const double *__restrict__ x,
                                                   double *__restrict__ grad,
                                                   const double *__restrict__ lst,
                                                   const double *__restrict__ gch,
                                                   const double *__restrict__ bar,
                                                   int n_dense_groups) {
+  constexpr bool COLW = NT > pt::kTileMaxNT;
+  constexpr int PPG = bwd_probs<NT>();
   if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies, chains b, b + G, ...
     const int G = gridDim.x - n_dense_groups;
     const int kmax = max(D.ka, D.nf_dm);
@@ -307,12 +316,12 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const d
   constexpr int NP = 16 * NT;
   constexpr int NTILE = NT * (NT + 1) / 2;
   constexpr int TS = 17;                              // LDS row stride of a tile
-  constexpr int NTL = NTILE > 2 * NT ? NTILE : 2 * NT;
-  __shared__ double vz_[kProbPerGroup][NP][4];         // v_sin, v_cos, z_sin, z_cos
-  __shared__ double tl_[kProbPerGroup][NTL][16 * TS];
-  __shared__ double ab_[kProbPerGroup][NP][2];
+  constexpr int NTL = COLW ? NTILE : (NTILE > 2 * NT ? NTILE : 2 * NT);
+  __shared__ double vz_[PPG][NP][4];                   // v_sin, v_cos, z_sin, z_cos
+  __shared__ double tl_[PPG][NTL][16 * TS];
+  __shared__ double ab_[PPG][NP][2];
   const int w = threadIdx.x >> 6;
-  const int prob = blockIdx.x * kProbPerGroup + w;
+  const int prob = blockIdx.x * PPG + w;
   if (prob >= D.nf_gw * D.n_chains) return;
   const int k0 = prob % D.nf_gw, c = prob / D.nf_gw;
   const int l = threadIdx.x & 63, c16 = l & 15, q = l >> 4;
@@ -411,106 +420,197 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_bwd(Dev D, const d
     }
   }
 
-  // ---- inverses of the diagonal tiles: lane group g solves tile J = g (+4)
-  //      column c16 by forward substitution; C_JJ in tl[J], W_JJ in tl[NT + J]
-#pragma unroll
-  for (int J = 0; J < NT; ++J)
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      tl[J][(4 * q + v) * TS + c16] = Cb[tidx(J, J) * 256 + (4 * q + v) * 16 + c16];
-  wave_sync();
-#pragma unroll
-  for (int rnd = 0; rnd < (NT + 3) / 4; ++rnd) {
-    const int J = 4 * rnd + q;
-    if (J < NT) {
-      const double *T = tl[J];
-      double xs[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        __builtin_amdgcn_sched_barrier(0);     // bound the live LDS reads to one row
-        double s = (r == c16) ? 1.0 : 0.0;
-#pragma unroll
-        for (int m = 0; m < r; ++m) s -= T[r * TS + m] * xs[m];
-        xs[r] = s / T[r * TS + r];
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) tl[NT + J][r * TS + c16] = xs[r];
-    }
-  }
-  wave_sync();
-
-  // ---- W = C^-1 in B layout; -W_II in A layout
-  v4d Wb[NTILE];
-  v4d Wi[NT];
-  const int pc = pi16(c16);
-#pragma unroll
-  for (int I = 0; I < NT; ++I)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      Wb[tidx(I, I)][v] = tl[NT + I][(4 * q + v) * TS + c16];
-      Wi[I][v] = -tl[NT + I][pc * TS + 4 * q + v];
-    }
-#pragma unroll
-  for (int I = 1; I < NT; ++I)
-#pragma unroll
-    for (int J = 0; J < I; ++J) {
-      v4d U = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int K = J; K < I; ++K) {
-        v4d a;
-        const double *t = Cb + tidx(I, K) * 256 + pc * 16 + 4 * q;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) a[s] = t[s];
-        U = mfma4(a, Wb[tidx(K, J)], U);
-      }
-      Wb[tidx(I, J)] = mfma4(Wi[I], U, v4d{0.0, 0.0, 0.0, 0.0});
-    }
-  wave_sync();
-
-  // ---- d/dkappa: quadratic forms down the columns of W
   double dkap[NT];
-#pragma unroll
-  for (int J = 0; J < NT; ++J) {
-    ScanState st{0.0, 0.0, 0.0};
-#pragma unroll
-    for (int I = J; I < NT; ++I) scan_tile(Wb[tidx(I, J)], 16 * I, vz, st, l, c16, q);
-    double qq = st.q;
-    qq += __shfl_xor(qq, 16, 64);
-    qq += __shfl_xor(qq, 32, 64);
-    dkap[J] = qq;
-  }
-
-  // ---- W to A layout through LDS
-#pragma unroll
-  for (int T = 0; T < NTILE; ++T)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) tl[T][(4 * q + v) * TS + c16] = Wb[T][v];
-  wave_sync();
-  v4d Wa[NTILE];
-#pragma unroll
-  for (int T = 0; T < NTILE; ++T)
-#pragma unroll
-    for (int s = 0; s < 4; ++s) Wa[T][s] = tl[T][pc * TS + 4 * q + s];
-
-  // ---- d/drho: M = W G column block by column block, quadratic forms
   double dr = 0.0;
+  const int pc = pi16(c16);
+  if constexpr (COLW) {
+    // ---- inverses of the diagonal tiles, in place: lane group g solves
+    //      tile J = g (+4, ...) column c16 by forward substitution
 #pragma unroll
-  for (int J = 0; J < NT; ++J) {
-    ScanState st{0.0, 0.0, 0.0};
+    for (int J = 0; J < NT; ++J)
 #pragma unroll
-    for (int I = J; I < NT; ++I) {
-      v4d Mt = {0.0, 0.0, 0.0, 0.0};
+      for (int v = 0; v < 4; ++v)
+        tl[tidx(J, J)][(4 * q + v) * TS + c16] = Cb[tidx(J, J) * 256 + (4 * q + v) * 16 + c16];
+    wave_sync();
 #pragma unroll
-      for (int K = J; K <= I; ++K) {
-        v4d g;
-        const double *gt = gch + tidx(K, J) * 256 + 64 * q + c16;
+    for (int rnd = 0; rnd < (NT + 3) / 4; ++rnd) {
+      const int J = 4 * rnd + q;
+      if (J < NT) {
+        double *T = tl[tidx(J, J)];
+        double xs[16];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) g[v] = gt[16 * v];
-        Mt = mfma4(Wa[tidx(I, K)], g, Mt);
+        for (int r = 0; r < 16; ++r) {
+          __builtin_amdgcn_sched_barrier(0);   // bound the live LDS reads to one row
+          double s = (r == c16) ? 1.0 : 0.0;
+#pragma unroll
+          for (int m = 0; m < r; ++m) s -= T[r * TS + m] * xs[m];
+          xs[r] = s / T[r * TS + r];
+        }
+        // (the lanes of a group read all of C_JJ before any of them writes)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) T[r * TS + c16] = xs[r];
       }
-      scan_tile(Mt, 16 * I, vz, st, l, c16, q);
     }
-    dr += st.q;
+    wave_sync();
+    // ---- W = C^-1 by block columns: W_IJ = -W_II sum_{J<=K<I} C_IK W_KJ
+    //      (B layout), the column's d/dkappa, then the column into LDS
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      __builtin_amdgcn_sched_barrier(0);       // one block column live at a time
+      v4d Wc[NT];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Wc[J][v] = tl[tidx(J, J)][(4 * q + v) * TS + c16];
+#pragma unroll
+      for (int I = J + 1; I < NT; ++I) {
+        __builtin_amdgcn_sched_barrier(0);
+        v4d U = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int K = J; K < I; ++K) {
+          v4d a;
+          const double *t = Cb + tidx(I, K) * 256 + pc * 16 + 4 * q;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) a[s] = t[s];
+          U = mfma4(a, Wc[K], U);
+        }
+        v4d wi;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) wi[s] = -tl[tidx(I, I)][pc * TS + 4 * q + s];
+        Wc[I] = mfma4(wi, U, v4d{0.0, 0.0, 0.0, 0.0});
+      }
+      ScanState st{0.0, 0.0, 0.0};
+#pragma unroll
+      for (int I = J; I < NT; ++I) scan_tile(Wc[I], 16 * I, vz, st, l, c16, q);
+      double qq = st.q;
+      qq += __shfl_xor(qq, 16, 64);
+      qq += __shfl_xor(qq, 32, 64);
+      dkap[J] = qq;
+#pragma unroll
+      for (int I = J + 1; I < NT; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tl[tidx(I, J)][(4 * q + v) * TS + c16] = Wc[I][v];
+    }
+    wave_sync();
+    // ---- d/drho: M = W G column block by column block, W in A layout from LDS
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      ScanState st{0.0, 0.0, 0.0};
+#pragma unroll
+      for (int I = J; I < NT; ++I) {
+        __builtin_amdgcn_sched_barrier(0);     // one product tile live at a time
+        v4d Mt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int K = J; K <= I; ++K) {
+          v4d a, g;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) a[s] = tl[tidx(I, K)][pc * TS + 4 * q + s];
+          const double *gt = gch + tidx(K, J) * 256 + 64 * q + c16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) g[v] = gt[16 * v];
+          Mt = mfma4(a, g, Mt);
+        }
+        scan_tile(Mt, 16 * I, vz, st, l, c16, q);
+      }
+      dr += st.q;
+    }
+  } else {
+    // ---- inverses of the diagonal tiles: lane group g solves tile J = g (+4)
+    //      column c16 by forward substitution; C_JJ in tl[J], W_JJ in tl[NT + J]
+#pragma unroll
+    for (int J = 0; J < NT; ++J)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        tl[J][(4 * q + v) * TS + c16] = Cb[tidx(J, J) * 256 + (4 * q + v) * 16 + c16];
+    wave_sync();
+#pragma unroll
+    for (int rnd = 0; rnd < (NT + 3) / 4; ++rnd) {
+      const int J = 4 * rnd + q;
+      if (J < NT) {
+        const double *T = tl[J];
+        double xs[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          __builtin_amdgcn_sched_barrier(0);     // bound the live LDS reads to one row
+          double s = (r == c16) ? 1.0 : 0.0;
+#pragma unroll
+          for (int m = 0; m < r; ++m) s -= T[r * TS + m] * xs[m];
+          xs[r] = s / T[r * TS + r];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) tl[NT + J][r * TS + c16] = xs[r];
+      }
+    }
+    wave_sync();
+
+    // ---- W = C^-1 in B layout; -W_II in A layout
+    v4d Wb[NTILE];
+    v4d Wi[NT];
+#pragma unroll
+    for (int I = 0; I < NT; ++I)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Wb[tidx(I, I)][v] = tl[NT + I][(4 * q + v) * TS + c16];
+        Wi[I][v] = -tl[NT + I][pc * TS + 4 * q + v];
+      }
+#pragma unroll
+    for (int I = 1; I < NT; ++I)
+#pragma unroll
+      for (int J = 0; J < I; ++J) {
+        v4d U = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int K = J; K < I; ++K) {
+          v4d a;
+          const double *t = Cb + tidx(I, K) * 256 + pc * 16 + 4 * q;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) a[s] = t[s];
+          U = mfma4(a, Wb[tidx(K, J)], U);
+        }
+        Wb[tidx(I, J)] = mfma4(Wi[I], U, v4d{0.0, 0.0, 0.0, 0.0});
+      }
+    wave_sync();
+
+    // ---- d/dkappa: quadratic forms down the columns of W
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      ScanState st{0.0, 0.0, 0.0};
+#pragma unroll
+      for (int I = J; I < NT; ++I) scan_tile(Wb[tidx(I, J)], 16 * I, vz, st, l, c16, q);
+      double qq = st.q;
+      qq += __shfl_xor(qq, 16, 64);
+      qq += __shfl_xor(qq, 32, 64);
+      dkap[J] = qq;
+    }
+
+    // ---- W to A layout through LDS
+#pragma unroll
+    for (int T = 0; T < NTILE; ++T)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) tl[T][(4 * q + v) * TS + c16] = Wb[T][v];
+    wave_sync();
+    v4d Wa[NTILE];
+#pragma unroll
+    for (int T = 0; T < NTILE; ++T)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) Wa[T][s] = tl[T][pc * TS + 4 * q + s];
+
+    // ---- d/drho: M = W G column block by column block, quadratic forms
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      ScanState st{0.0, 0.0, 0.0};
+#pragma unroll
+      for (int I = J; I < NT; ++I) {
+        v4d Mt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int K = J; K <= I; ++K) {
+          v4d g;
+          const double *gt = gch + tidx(K, J) * 256 + 64 * q + c16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) g[v] = gt[16 * v];
+          Mt = mfma4(Wa[tidx(I, K)], g, Mt);
+        }
+        scan_tile(Mt, 16 * I, vz, st, l, c16, q);
+      }
+      dr += st.q;
+    }
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) dr += __shfl_xor(dr, o, 64);
@@ -563,13 +663,16 @@ hipError_t launch_fwd_t(const Dev &D, const double *x, hipStream_t s) {
   return hipGetLastError();
 }
 
+// (beyond kTileMaxNT tiles the workgroups are single waves: the
+// diagonal-frequency work runs in its own launch, k_spec_bwd)
 template <int NT>
 hipError_t launch_bwd_t(const Dev &D, const double *x, double *grad, hipStream_t s) {
+  constexpr int P = bwd_probs<NT>();
   const int nprob = D.nf_gw * D.n_chains;
-  const int ng = (nprob + kProbPerGroup - 1) / kProbPerGroup;
-  hipLaunchKernelGGL(k_cholt_bwd<NT>, dim3(ng + spec_groups(D, ng, D.n_chains)),
-                     dim3(64 * kProbPerGroup), 0, s, D, x, grad, (const double *)D.lstore, D.gtile,
-                     (const double *)D.bar_rn, ng);
+  const int ng = (nprob + P - 1) / P;
+  const int ns = NT > pt::kTileMaxNT ? 0 : spec_groups(D, ng, D.n_chains);
+  hipLaunchKernelGGL(k_cholt_bwd<NT>, dim3(ng + ns), dim3(64 * P), 0, s, D, x, grad,
+                     (const double *)D.lstore, D.gtile, (const double *)D.bar_rn, ng);
   return hipGetLastError();
 }
 
@@ -597,6 +700,8 @@ hipError_t launch_cholt_bwd(const pt::Dev &D, const double *x, double *grad, hip
     case 3: return launch_bwd_t<3>(D, x, grad, s);
     case 4: return launch_bwd_t<4>(D, x, grad, s);
     case 5: return launch_bwd_t<5>(D, x, grad, s);
+    case 6: return launch_bwd_t<6>(D, x, grad, s);
+    case 7: return launch_bwd_t<7>(D, x, grad, s);
   }
   return hipErrorInvalidValue;
 }

@@ -345,9 +345,9 @@ size_t dataset_bytes_of(const pt::Dev &B, int n_chunks) {
   auto a = [](size_t count, size_t size) { return std::max<size_t>(count, 1) * size; };
   const int nt = pt::chol_tiles(B.n_psr);
   const size_t ntile = (size_t)(nt * (nt + 1) / 2) * 256;
-  const size_t gtiles = nt <= pt::kTileMaxNT ? ntile : 0, htiles = nt <= pt::kTileFwdMaxNT ? ntile : 0;
+  const size_t tiles = nt <= pt::kTileFwdMaxNT ? ntile : 0;
   size_t b = 7 * a(npad, 8) + 2 * a(ntoa, 8) + a(ntoa, 4) + 2 * a(B.n_backend, 8) + a(n + 1, 8) +
-             2 * a(n, 8) + a(3 * n, 8) + a(n * n, 8) + a(n * (n + 1) / 2, 8) + a(gtiles, 8) + a(htiles, 8) +
+             2 * a(n, 8) + a(3 * n, 8) + a(n * n, 8) + a(n * (n + 1) / 2, 8) + 2 * a(tiles, 8) +
              2 * a(B.n_theta, 8) + a(PTAFS_MAX_HARM, 8);
   b += (size_t)(3 * n_chunks + n + 1) * sizeof(int32_t);
   return b;
@@ -494,7 +494,7 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
     // inside), for the matrix-core adjoint of small arrays
     const int nt = pt::chol_tiles(n);
     std::vector<double> gt;
-    if (nt <= pt::kTileMaxNT) {
+    if (nt <= pt::kTileFwdMaxNT) {
       gt.assign((size_t)(nt * (nt + 1) / 2) * 256, 0.0);
       for (int K = 0; K < nt; ++K)
         for (int J = 0; J <= K; ++J)
