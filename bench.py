@@ -40,24 +40,24 @@ def toa_pass_flops(ds, n_chains):
 
 def measured_traffic(tuning):
     """HBM bytes per TOA-pass launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source and tuning."""
+    summary (one entry per profiled tuning), if it was taken on the current
+    kernel source and covers this tuning."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_toa_mfma_traffic.md")
     if not os.path.exists(path):
         return None
+    key = "traffic_bytes_per_launch[" + " ".join(str(int(t)) for t in tuning) + "]"
     fields = {}
     for line in open(path):
-        if ":" in line and line.split(":")[0] in ("tuning", "traffic_bytes_per_launch", "source_sha256"):
+        if ":" in line:
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
     m = hashlib.sha256()
     for f in ("k_toa.hip", "common.h", "cw_dev.h"):
         m.update(open(os.path.join(ROOT, "paper_2607_06834_amd", "csrc", f), "rb").read())
-    if fields.get("source_sha256") != m.hexdigest():
+    if fields.get("source_sha256") != m.hexdigest() or key not in fields:
         return None
-    if fields.get("tuning") != " ".join(str(int(t)) for t in tuning):
-        return None
-    return float(fields["traffic_bytes_per_launch"])
+    return float(fields[key])
 
 
 def cpu_baseline(ds, n_chains_sample=8, min_seconds=10.0, seed=204):
@@ -88,6 +88,7 @@ def cpu_baseline(ds, n_chains_sample=8, min_seconds=10.0, seed=204):
 
 
 def serving_bench(n_traj, rates, n_req, n_chains=16, n_leapfrog=20, quantum=10, max_slots=8,
+                  use_graph=True,
                   budget=None, seed0=501, eps=1e-4):
     """Poisson arrivals of independent data sets (20-120 pulsars, 200-8000
     TOAs each, 10-30 frequencies, CW with probability 1/2) served with
@@ -113,7 +114,7 @@ def serving_bench(n_traj, rates, n_req, n_chains=16, n_leapfrog=20, quantum=10, 
     evals_per_req = n_traj * n_leapfrog * n_chains
 
     def run(rate, reqs, slots):
-        srv = serve.Server(budget_bytes=budget, max_slots=slots, quantum=quantum)
+        srv = serve.Server(budget_bytes=budget, max_slots=slots, quantum=quantum, use_graph=use_graph)
         rng = np.random.default_rng(7)
         gaps = rng.exponential(1.0 / rate, len(reqs)) if rate else np.zeros(len(reqs))
         ids = []
