@@ -48,13 +48,13 @@ __device__ inline int xcd_remap(int b, int G) {
 //
 // With four waves per workgroup (SHB) the waves share the coefficient panels
 // in LDS instead of holding them in registers, and keep one set of per-tile
-// inputs, reloaded once the residuals are formed: three waves per SIMD.  With
-// one or two waves per workgroup the panels live in registers and the inputs
-// alternate between two register sets: two waves per SIMD.  (A single wave
-// leaves the matrix core idle about half the time; the CW terms need more
-// registers than either bound allows.)
+// inputs, reloaded once the residuals are formed: three waves per SIMD (two
+// with the CW terms, a few registers spilled).  With one or two waves per
+// workgroup the panels live in registers and the inputs alternate between two
+// register sets: two waves per SIMD, one with the CW terms.  (A single wave
+// leaves the matrix core idle about half the time.)
 template <int JTR, int JTD, int WPB, bool CW>
-__global__ __launch_bounds__(64 * WPB, CW ? 1 : (WPB == 4 ? 3 : 2))
+__global__ __launch_bounds__(64 * WPB, CW ? (WPB == 4 ? 2 : 1) : (WPB == 4 ? 3 : 2))
 void k_toa_mfma(Dev D, int xcd_map) {
   constexpr int NSR = 4 * JTR;
   constexpr int NSD = 4 * JTD;
