@@ -12,8 +12,11 @@ footprint is known before any allocation (ptafs_estimate plus the server's
 own per-request buffers); a request that could never fit is rejected at
 submission.
 
-Every request's arithmetic depends only on its own data set, start point and
-seed: its samples are bit-identical whether it runs alone or in a mix.
+Every request's arithmetic depends only on its own data set, start point,
+seed and TOA-pass tuning: its samples are bit-identical whether it runs
+alone or in a mix.  The tuning is fixed by the caller, or picked by the
+autotuner among SERVE_CANDIDATES the first time a data-set shape (pulsars,
+TOAs, basis sizes, chains) is admitted and then reused for that shape.
 """
 from __future__ import annotations
 
@@ -25,7 +28,11 @@ import time
 import numpy as np
 import torch
 
-from . import api
+from . import api, autotune
+
+# TOA-pass tunings tried for a new request shape: small-chain requests want
+# short chunks, or four-wave workgroups sharing the coefficient panels
+SERVE_CANDIDATES = ((8, 1, 1), (22, 4, 1))
 
 
 class Rejected(RuntimeError):
@@ -46,6 +53,7 @@ class _Req:
     keep: str
     footprint: int
     t_arrival: float
+    tuning: tuple = ()
     t_admit: float = float("nan")
     t_done: float = float("nan")
     status: str = "queued"
@@ -75,7 +83,7 @@ class Server:
     (``time.perf_counter`` seconds)."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 8, quantum: int = 10, device: int = 0,
-                 tuning=(16, 1, 1), use_graph: bool = True):
+                 tuning=None, use_graph: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("the server needs a HIP GPU")
         self.budget = int(budget_bytes)
@@ -171,13 +179,17 @@ class Server:
         r.stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(r.stream):
             r.ds = api.Dataset(r.desc, stream=r.stream)
-            r.ds.ptafs_set_tuning(*self.tuning)
             C, d = r.x0.shape[0], r.ds.d
             if r.x0.shape[1] != d:
                 raise ValueError(f"x0 has {r.x0.shape[1]} columns, the data set needs {d}")
             r.ds.ptafs_reserve(C)
             dev = torch.device("cuda", self.device)
             r.x = torch.tensor(r.x0, device=dev)
+            if self.tuning is not None:
+                r.ds.ptafs_set_tuning(*self.tuning)
+            else:
+                autotune.tune(r.ds, r.x, reps=2, candidates=SERVE_CANDIDATES)
+            r.tuning = r.ds.ptafs_get_tuning()
             r.lp, r.gr, _ = r.ds.ptafs_logp_grad(r.x, stream=r.stream)
             r.acc = torch.zeros(C, dtype=torch.int64, device=dev)
             r.bad = torch.zeros(C, dtype=torch.int64, device=dev)
@@ -214,7 +226,7 @@ class Server:
                 logp=r.lp.cpu().numpy(), n_accept=r.acc.cpu().numpy(),
                 n_invalid=r.bad.cpu().numpy(), x=r.x.cpu().numpy(),
                 t_arrival=r.t_arrival, t_admit=r.t_admit, t_done=time.perf_counter(),
-                footprint=r.footprint)
+                footprint=r.footprint, tuning=tuple(r.tuning))
         r.t_done = r.result["t_done"]
         r.result["latency"] = r.t_done - r.t_arrival
         r.ds.close()

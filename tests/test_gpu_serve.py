@@ -61,11 +61,14 @@ def test_alone_equals_mix(mods):
 
 
 def test_server_equals_direct_hmc(mods):
-    """Quanta of trajectories give the same chain as one uninterrupted run."""
+    """Quanta of trajectories give the same chain as one uninterrupted run at
+    the TOA-pass tuning the server picked for the request."""
     api, serve = mods
     ds, x0 = request(7)
     (res,), _ = run_requests(serve, [(ds, x0)], budget_bytes=1 << 34, max_slots=2, quantum=2)
+    assert len(res["tuning"]) == 3
     g = api.Dataset(ds)
+    g.ptafs_set_tuning(*res["tuning"])
     x = torch.tensor(x0, device="cuda")
     lp, gr, _ = g.ptafs_logp_grad(x)
     acc = torch.zeros(x.shape[0], dtype=torch.int64, device="cuda")
