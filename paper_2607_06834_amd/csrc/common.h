@@ -124,7 +124,7 @@ struct Dev {
   const double *pos, *gamma;
   const double *gchol;         // chol(Gamma), packed row-major lower
   const double *gtile;         // chol(Gamma) zero-padded, lower 16x16 tiles (up to kTileFwdMaxNT)
-  const double *gam_tile;      // Gamma zero-padded, lower 16x16 tiles, diagonal tiles full (up to kTileFwdMaxNT)
+  const double *gam_tile;      // Gamma zero-padded, lower 16x16 tiles stored column-major, diagonal tiles full (up to kTileFwdMaxNT)
   const double *prior_lo, *prior_hi;
   // power-law spectra: ln(f_k yr) for f_k = (k + 1) / T, k < PTAFS_MAX_HARM, and ln(yr^3 / (12 pi^2 T))
   const double *lnfy;
@@ -142,8 +142,6 @@ struct Dev {
   double *cwc;                 // [n_psr][kCwConst][c_pad] per chain/pulsar CW constants
   double *part_rn, *part_dm;   // [n_wg][rows][16]
   double *part_chi, *part_cw;  // [n_wg][16], [n_wg][8][16]
-  double *zz_seg;              // [c_pad][kSpecSeg] partial |(u, z, z_dm)|^2
-  int32_t *fin_seg;            // [c_pad][kSpecSeg] 1 if that slice is finite
   double *bar_rn, *bar_dm;     // [n_psr][rows][c_pad]
   double *chi_p, *cw_p;        // [n_psr][c_pad], [n_psr][8][c_pad]
   double *dth_k;               // [c_pad][K][2] gw parts per frequency
@@ -174,10 +172,23 @@ namespace pt {
 
 // Prior box of a chain's hyper-parameters, checked by one wave.
 __device__ inline bool theta_in_box_wave(const Dev &D, const double *xc) {
+  // eight parameters per lane per batch, all loads issued together (indexes
+  // clamped to the last parameter, so no lane branches around a load)
+  constexpr int kB = 8;
   bool ok = true;
-  for (int i = (int)(threadIdx.x & 63); i < D.n_theta; i += 64) {
-    const double v = xc[i];
-    if (!(v >= D.prior_lo[i] && v <= D.prior_hi[i])) ok = false;
+  const int l = (int)(threadIdx.x & 63), last = D.n_theta - 1;
+  for (int i0 = 0; i0 < D.n_theta; i0 += 64 * kB) {
+    double v[kB], lo[kB], hi[kB];
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const int i = min(i0 + l + 64 * j, last);
+      v[j] = xc[i];
+      lo[j] = D.prior_lo[i];
+      hi[j] = D.prior_hi[i];
+    }
+#pragma unroll
+    for (int j = 0; j < kB; ++j)
+      if (!(v[j] >= lo[j] && v[j] <= hi[j])) ok = false;
   }
   return __all(ok);
 }

@@ -7,9 +7,9 @@
 // Forward (Sec. IV.A, Eqs. HD, prior_cov; Sec. II.B, Eq.
 // standardizing_transform with mu = 0): C = chol(rho_k Gamma + diag kappa_.k)
 // by a right-looking blocked factorisation.  A block column is factorised by
-// 16 rank-1 steps on the vector unit (pivot broadcast by readlane, the scaled
-// column through LDS); the trailing tiles are updated with 16x16x4 MFMAs.
-// Then a_.k,{sin,cos} = C z_.k,{sin,cos}.
+// 16 rank-1 steps on the vector unit, with every operand moved between lanes
+// by readlane, DPP and permlane swaps (no LDS); the trailing tiles are
+// updated with 16x16x4 MFMAs.  Then a_.k,{sin,cos} = C z_.k,{sin,cos}.
 //
 // Backward, with abar from the TOA pass and v_c = C^T abar_c:
 //   dz_c = v_c - z_c
@@ -62,6 +62,55 @@ __device__ inline double rsqrt_nr(double a) {
   return y;
 }
 
+// 1/a: hardware estimate refined by two Newton steps on e = 1 - a y
+__device__ inline double rcp_nr(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  y = fma(y, fma(-a, y, 1.0), y);
+  y = fma(y, fma(-a, y, 1.0), y);
+  return y;
+}
+
+template <int N>
+__device__ inline int dpp_row_share(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x150 + N, 0xF, 0xF, false);
+}
+
+// Lane n of every 16-lane row to all lanes of that row (DPP row broadcast);
+// n is a constant once the caller's loop is unrolled.
+__device__ inline double row_share_d(double v, int n) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)b, hi = (int)(b >> 32);
+  switch (n) {
+#define PT_ROW_SHARE(N)          \
+  case N:                        \
+    lo = dpp_row_share<N>(lo);   \
+    hi = dpp_row_share<N>(hi);   \
+    break;
+    PT_ROW_SHARE(0) PT_ROW_SHARE(1) PT_ROW_SHARE(2) PT_ROW_SHARE(3)
+    PT_ROW_SHARE(4) PT_ROW_SHARE(5) PT_ROW_SHARE(6) PT_ROW_SHARE(7)
+    PT_ROW_SHARE(8) PT_ROW_SHARE(9) PT_ROW_SHARE(10) PT_ROW_SHARE(11)
+    PT_ROW_SHARE(12) PT_ROW_SHARE(13) PT_ROW_SHARE(14) PT_ROW_SHARE(15)
+#undef PT_ROW_SHARE
+  }
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Row g (lanes 16g .. 16g + 15) to all four rows, lane for lane: a permlane16
+// swap gives rows (g mod 2) and 2 + (g mod 2) twice each, a permlane32 swap
+// then the chosen one four times.
+__device__ inline unsigned row_bcast_u(unsigned v, int g) {
+  const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  const unsigned y = (g & 1) ? p[1] : p[0];
+  const auto r = __builtin_amdgcn_permlane32_swap(y, y, false, false);
+  return (g & 2) ? r[1] : r[0];
+}
+
+__device__ inline double row_bcast_d(double v, int g) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = row_bcast_u((unsigned)b, g), hi = row_bcast_u((unsigned)(b >> 32), g);
+  return __longlong_as_double(((long long)hi << 32) | lo);
+}
+
 // acc += X Y for one 16x16x16 product given the four k-slices of both operands
 __device__ inline v4d mfma4(const v4d &a, const v4d &b, v4d acc) {
   acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc, 0, 0, 0);
@@ -87,23 +136,22 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const d
   if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies, chains b, b + G, ...
     const int G = gridDim.x - n_dense_groups;
     for (int c = blockIdx.x - n_dense_groups; c < D.c_pad; c += G) {
-      pt::spec_fwd_block(D, x, c, 0, 1, 0, 1);
+      pt::spec_fwd_block(D, x, c, 0, 0, 1);
       __syncthreads();
     }
     return;
   }
   constexpr int NP = 16 * NT;
   constexpr int NTILE = NT * (NT + 1) / 2;
-  __shared__ double colb_[kProbPerGroup][2][NT][16];   // scaled column, double-buffered
   __shared__ double zb_[kProbPerGroup][NP][2];
   __shared__ double kb_[kProbPerGroup][NP];
+  __shared__ double tb_[kProbPerGroup][16][17];   // tile transpose for the store of C
   // one wave per (frequency, chain) problem, kProbPerGroup problems per workgroup
   const int w = threadIdx.x >> 6;
   const int prob = blockIdx.x * kProbPerGroup + w;
   if (prob >= D.nf_gw * D.c_pad) return;
   const int k0 = prob % D.nf_gw, c = prob / D.nf_gw;
   const int l = threadIdx.x & 63, c16 = l & 15, q = l >> 4;
-  double(*colb)[NT][16] = colb_[w];
   double(*zb)[2] = zb_[w];
   double *kb = kb_[w];
   const int n = D.n_psr;
@@ -114,38 +162,47 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const d
   };
   int32_t *flag = D.flag_dense + (size_t)c * D.nf_gw + k0;
   const double *xc = x + (size_t)(c < D.n_chains ? c : 0) * D.d;
-  // (the prior box is checked here, so nothing is read from k_spec_fwd)
-  if (c >= D.n_chains || !pt::theta_in_box_wave(D, xc)) {
-    for (int r = l; r < n; r += 64) {
-      coef(r, 0) = 0.0;
-      coef(r, 1) = 0.0;
-    }
-    if (l == 0) *flag = 0;
-    return;
-  }
-  const double rho = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
-  for (int r = l; r < NP; r += 64) {
-    double kap = 0.0, zs = 0.0, zc = 0.0;
-    if (r < n) {
-      if (k0 < D.nf_rn) kap = pt::powerlaw_k(D, k0, xc[D.off_rn + 2 * r], xc[D.off_rn + 2 * r + 1]);
-      const double *z = xc + D.off_z + (size_t)r * 2 * D.ka + 2 * k0;
-      zs = z[0];
-      zc = z[1];
-    }
-    kb[r] = kap;
-    zb[r][0] = zs;
-    zb[r][1] = zc;
-  }
-  wave_sync();
 
+  // Set-up: every global load (Gamma tiles, spectra parameters, z and the
+  // prior box, which is checked here so nothing is read from k_spec_fwd) is
+  // issued before the first of them is used, and the out-of-box exit comes
+  // after the tiles are assembled, so the loads cost one round trip.
   // phi tiles in E layout: lane (c16, q), item v = phi[16I + c16][16J + q + 4v];
-  // the padding is the identity.  All tile loads are independent.
+  // the padding is the identity.  The E layout of a tile is its column-major
+  // image and the Gamma tiles are stored column-major, so every load reads
+  // 512 contiguous bytes.
   v4d A[NTILE];
-  const double *__restrict__ gt = D.gam_tile + c16 * 16 + q;
+  const double *__restrict__ gt = D.gam_tile + l;
 #pragma unroll
   for (int T = 0; T < NTILE; ++T)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) A[T][v] = rho * gt[T * 256 + 4 * v];
+    for (int v = 0; v < 4; ++v) A[T][v] = gt[T * 256 + 64 * v];
+  constexpr int NR = (NP + 63) / 64;
+  double kl[NR], kg[NR], zs[NR], zc[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int r = l + 64 * j, rr = r < n ? r : n - 1;
+    kl[j] = xc[D.off_rn + 2 * rr];
+    kg[j] = xc[D.off_rn + 2 * rr + 1];
+    const double *z = xc + D.off_z + (size_t)rr * 2 * D.ka + 2 * k0;
+    zs[j] = z[0];
+    zc[j] = z[1];
+  }
+  const double rho = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
+  const bool inbox = c < D.n_chains && pt::theta_in_box_wave(D, xc);
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    const int r = l + 64 * j;
+    if (r < NP) {
+      const bool real = r < n;
+      kb[r] = (real && k0 < D.nf_rn) ? pt::powerlaw_k(D, k0, kl[j], kg[j]) : 0.0;
+      zb[r][0] = real ? zs[j] : 0.0;
+      zb[r][1] = real ? zc[j] : 0.0;
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int T = 0; T < NTILE; ++T) A[T] *= rho;
 #pragma unroll
   for (int I = 0; I < NT; ++I) {
     const int r = 16 * I + c16;
@@ -155,39 +212,64 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const d
       if (c16 == q + 4 * v) A[tidx(I, I)][v] += dadd;
   }
 
+  if (!inbox) {
+    for (int r = l; r < n; r += 64) {
+      coef(r, 0) = 0.0;
+      coef(r, 1) = 0.0;
+    }
+    if (l == 0) *flag = 0;
+    return;
+  }
+
   bool pd = true;
 #pragma unroll
   for (int J = 0; J < NT; ++J) {
-    // ---- block column J: 16 rank-1 steps.  The broadcast column carries
-    //      zeros in the rows <= cc of the diagonal tile, so the update below
-    //      leaves the finished columns (and column cc) untouched.
+    // ---- block column J: 16 rank-1 steps on the unscaled column a
+    //      (a_r = A[r][cc]): A[r][c] -= a_r a_c / a_cc over the rows and
+    //      columns after cc.  The diagonal tile is updated on both sides of
+    //      its diagonal, so a_c for c > cc is also row cc of it, held by lane
+    //      cc of every lane group (DPP row broadcast); a_r is column cc, held
+    //      by lane group cc mod 4 (permlane broadcast).  Items v < cc / 4 of a
+    //      lane are finished columns and are left alone.  A step's pivot is
+    //      never touched by the later steps, so the scaling of the columns by
+    //      1/sqrt(pivot) and the pivot checks wait for the end of the block
+    //      column, where they are done four columns at a time.
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
       // padding columns of the last tile: pivot 1, zero column, nothing to do
       if (J == NT - 1 && 16 * J + cc >= n) continue;
-      const double piv = readlane_d(A[tidx(J, J)][cc >> 2], cc + 16 * (cc & 3));
-      pd = pd && (piv > 0.0) && isfinite(piv);
-      const double rd = rsqrt_nr(piv);
-      const bool own = q == (cc & 3);
-      double(*cb)[16] = colb[cc & 1];
-#pragma unroll
-      for (int I = J; I < NT; ++I) {
-        const double sv = A[tidx(I, J)][cc >> 2] * rd;
-        if (own) {
-          A[tidx(I, J)][cc >> 2] = sv;
-          cb[I][c16] = (I == J && c16 <= cc) ? 0.0 : sv;
-        }
-      }
-      wave_sync();
+      const int g0 = cc & 3, v0 = cc >> 2;
+      const double ri = rcp_nr(readlane_d(A[tidx(J, J)][v0], cc + 16 * g0));
       double lk[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) lk[v] = cb[J][q + 4 * v];
+      for (int v = v0; v < 4; ++v) {
+        const double t = row_share_d(A[tidx(J, J)][v], cc) * ri;
+        lk[v] = (v > v0 || q > g0) ? t : 0.0;
+      }
 #pragma unroll
       for (int I = J; I < NT; ++I) {
-        const double lr = cb[I][c16];
+        double ar = row_bcast_d(A[tidx(I, J)][v0], g0);
+        if (I == J && c16 <= cc) ar = 0.0;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) A[tidx(I, J)][v] -= lr * lk[v];
+        for (int v = v0; v < 4; ++v) A[tidx(I, J)][v] -= ar * lk[v];
       }
+    }
+    // pivots of the lane's columns q + 4v (lane q + 4v of its own lane
+    // group), then C[.][c] = a / sqrt(pivot_c); the padding pivots are 1
+    {
+      double rd[4];
+      bool ok = true;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double piv = __shfl(A[tidx(J, J)][v], 17 * q + 4 * v, 64);
+        ok = ok && (piv > 0.0) && isfinite(piv);
+        rd[v] = rsqrt_nr(piv);
+      }
+      pd = pd && __all(ok);
+#pragma unroll
+      for (int I = J; I < NT; ++I)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[tidx(I, J)][v] *= rd[v];
     }
     // ---- trailing tiles: A_IK -= C_IJ C_KJ^T  (as A_IK^T -= C_KJ C_IJ^T)
 #pragma unroll
@@ -235,12 +317,19 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const d
       coef(r, 1) = ac;
     }
   }
-  // keep C for the adjoint, tile-major
-  double *dst = D.lstore + ((size_t)c * D.nf_gw + k0) * (NTILE * 256);
+  // keep C for the adjoint, tile-major with row-major tiles: each tile is
+  // transposed through LDS so that every store writes 512 contiguous bytes
+  double *dst = D.lstore + ((size_t)c * D.nf_gw + k0) * (NTILE * 256) + l;
+  double(*tb)[17] = tb_[w];
 #pragma unroll
-  for (int T = 0; T < NTILE; ++T)
+  for (int T = 0; T < NTILE; ++T) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) dst[T * 256 + c16 * 16 + q + 4 * v] = A[T][v];
+    for (int v = 0; v < 4; ++v) tb[c16][q + 4 * v] = A[T][v];
+    wave_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) dst[T * 256 + 64 * v] = tb[4 * v + q][c16];
+    wave_sync();
+  }
 }
 
 // ---------------------------------------------------------------------------

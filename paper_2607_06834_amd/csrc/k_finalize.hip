@@ -54,12 +54,27 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
   for (int k = t; k < D.nf_gw; k += kFinT) fl |= D.flag_dense[(size_t)c * D.nf_gw + k] | fo[k];
   for (int k = t; k < nseg; k += kFinT) fl |= fo[kmax + k];
   fl = pt::block_or<kFinW>(fl, ired);
-  // finiteness and squared norm of (u, z, z_dm), from the slices of k_spec_fwd
+  // finiteness and squared norm of (u, z, z_dm): eight elements per thread
+  // with their loads issued together, then a fixed-order workgroup sum
   double zz = 0.0;
   bool fin_in = true;
-  for (int s = 0; s < nseg; ++s) {
-    zz += D.zz_seg[(size_t)c * pt::kSpecSeg + s];
-    fin_in = fin_in && D.fin_seg[(size_t)c * pt::kSpecSeg + s] != 0;
+  {
+    constexpr int B = 8;
+    for (int i0 = D.off_u + t; i0 < D.d; i0 += kFinT * B) {
+      double v[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        const int i = i0 + kFinT * b;
+        v[b] = i < D.d ? xc[i] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        fin_in = fin_in && isfinite(v[b]);
+        zz += v[b] * v[b];
+      }
+    }
+    zz = pt::block_sum<kFinW>(zz, red);
+    fin_in = __syncthreads_and(fin_in);
   }
   const int pre = D.st_pre[c];
   int st = 0;

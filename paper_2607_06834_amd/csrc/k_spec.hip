@@ -15,7 +15,7 @@ namespace {
 
 // grid (c_pad, segments), block 256
 __global__ __launch_bounds__(256) void k_spec_fwd(pt::Dev D, const double *__restrict__ x) {
-  pt::spec_fwd_block(D, x, blockIdx.x, blockIdx.y, gridDim.y, blockIdx.y, pt::kSpecSeg);
+  pt::spec_fwd_block(D, x, blockIdx.x, blockIdx.y, blockIdx.y, pt::kSpecSeg);
 }
 
 // grid (n_chains, segments), block 256

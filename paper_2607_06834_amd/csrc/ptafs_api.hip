@@ -56,7 +56,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 
 struct WsLayout {
-  size_t coef_rn, coef_dm, lstore, sqk_rn, sqk_dm, cwc, part_rn, part_dm, part_chi, part_cw, zz_seg, fin_seg,
+  size_t coef_rn, coef_dm, lstore, sqk_rn, sqk_dm, cwc, part_rn, part_dm, part_chi, part_cw,
       bar_rn, bar_dm, chi_p, cw_p, dth_k, drn_k, ddm_k, flag_k, flag_dense, flag_out, st_pre, total;
 };
 
@@ -81,8 +81,6 @@ WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
   L.part_dm = take(nwg * B.rows_dm * 16 * D8);
   L.part_chi = take(nwg * 16 * D8);
   L.part_cw = take(nwg * 8 * 16 * D8);
-  L.zz_seg = take(cp * pt::kSpecSeg * D8);
-  L.fin_seg = take(cp * pt::kSpecSeg * sizeof(int32_t));
   L.bar_rn = take(n * B.rows_rn * cp * D8);
   L.bar_dm = take(n * B.rows_dm * cp * D8);
   L.chi_p = take(n * cp * D8);
@@ -178,8 +176,6 @@ pt::Dev make_dev(const ptafs_dataset *ds, int n_chains) {
   D.part_rn = reinterpret_cast<double *>(w + L.part_rn);
   D.part_dm = reinterpret_cast<double *>(w + L.part_dm);
   D.part_chi = reinterpret_cast<double *>(w + L.part_chi);
-  D.zz_seg = reinterpret_cast<double *>(w + L.zz_seg);
-  D.fin_seg = reinterpret_cast<int32_t *>(w + L.fin_seg);
   D.part_cw = reinterpret_cast<double *>(w + L.part_cw);
   D.bar_rn = reinterpret_cast<double *>(w + L.bar_rn);
   D.bar_dm = reinterpret_cast<double *>(w + L.bar_dm);
@@ -513,7 +509,8 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
           for (int rr = 0; rr < 16; ++rr)
             for (int cc = 0; cc < 16; ++cc) {
               const int r = 16 * K + rr, k = 16 * J + cc;
-              if (r < n && k < n) ht[(size_t)(K * (K + 1) / 2 + J) * 256 + rr * 16 + cc] = gam[(size_t)r * n + k];
+              // column-major tiles (the register image of the forward's layout)
+              if (r < n && k < n) ht[(size_t)(K * (K + 1) / 2 + J) * 256 + cc * 16 + rr] = gam[(size_t)r * n + k];
             }
     }
     chk(upload(ds, ht.data(), ht.size(), &B.gam_tile));

@@ -18,19 +18,17 @@
 namespace pt {
 
 // Items per thread whose loads are issued together: up to 10 loads an item,
-// within the 63 loads a wave can have in flight; single loads for |z|^2.
+// within the 63 loads a wave can have in flight.
 constexpr int kSpecBatch = 6;
-constexpr int kZzBatch = 16;
 
-// Forward of chain c (< c_pad): slice seg of nseg of the input checks
-// (segment 0 also does the per-chain work) and the diagonal and DM
-// frequencies k = k_first, k_first + k_step, ...  With nseg = 1 the chain's
-// other check slots are set neutral.  One block of 256 threads; every thread
-// of the block calls it.
+// Forward of chain c (< c_pad) over the diagonal and DM frequencies
+// k = k_first, k_first + k_step, ...; segment 0 also does the per-chain work
+// (status of the prior box and the CW check, CW constants, timing-model
+// rows).  One block of 256 threads; every thread of the block calls it.  The
+// norm and finiteness of (u, z, z_dm) are taken in k_finalize.
 // ---------------------------------------------------------------------------
 __device__ inline void spec_fwd_block(const Dev &D, const double *__restrict__ x, int c, int seg,
-                                      int nseg, int k_first, int k_step) {
-  __shared__ double red[4];
+                                      int k_first, int k_step) {
   __shared__ int kflag[PTAFS_MAX_HARM];
   const int tid = threadIdx.x;
   const int n = D.n_psr;
@@ -39,43 +37,28 @@ __device__ inline void spec_fwd_block(const Dev &D, const double *__restrict__ x
   const double *xc = x + (size_t)(real ? c : 0) * D.d;
   const size_t cp = D.c_pad;
 
-  // ---- prior box (every segment needs it)
+  // ---- prior box (every segment needs it): four parameters per thread per
+  //      batch, loads issued together, indexes clamped to the last parameter
   bool ok = real;
-  if (real)
-    for (int i = tid; i < D.n_theta; i += 256) {
-      const double v = xc[i];
-      if (!(v >= D.prior_lo[i] && v <= D.prior_hi[i])) ok = false;
-    }
-  const bool bad = !__syncthreads_and(ok);
-  if (tid < PTAFS_MAX_HARM) kflag[tid] = 0;
-  // finiteness and squared norm of this segment's slice of (u, z, z_dm)
-  {
-    const int len = D.d - D.off_u;
-    const int e0 = D.off_u + (int)(((long long)len * seg) / nseg);
-    const int e1 = D.off_u + (int)(((long long)len * (seg + 1)) / nseg);
-    double zz = 0.0;
-    bool fin = true;
-    if (real)
-      for (int e = e0 + tid; e < e1; e += 256 * kZzBatch) {
-        double v[kZzBatch];
+  if (real) {
+    constexpr int kB = 4;
+    const int last = D.n_theta - 1;
+    for (int i0 = 0; i0 < D.n_theta; i0 += 256 * kB) {
+      double v[kB], lo[kB], hi[kB];
 #pragma unroll
-        for (int b = 0; b < kZzBatch; ++b) v[b] = (e + 256 * b < e1) ? xc[e + 256 * b] : 0.0;
-#pragma unroll
-        for (int b = 0; b < kZzBatch; ++b) {
-          fin = fin && isfinite(v[b]);
-          zz += v[b] * v[b];
-        }
+      for (int j = 0; j < kB; ++j) {
+        const int i = min(i0 + tid + 256 * j, last);
+        v[j] = xc[i];
+        lo[j] = D.prior_lo[i];
+        hi[j] = D.prior_hi[i];
       }
-    zz = pt::block_sum256(zz, red);
-    fin = __syncthreads_and(fin);
-    if (tid == 0) {
-      D.zz_seg[(size_t)c * pt::kSpecSeg + seg] = zz;
-      D.fin_seg[(size_t)c * pt::kSpecSeg + seg] = fin ? 1 : 0;
-    } else if (nseg == 1 && tid < pt::kSpecSeg) {
-      D.zz_seg[(size_t)c * pt::kSpecSeg + tid] = 0.0;
-      D.fin_seg[(size_t)c * pt::kSpecSeg + tid] = 1;
+#pragma unroll
+      for (int j = 0; j < kB; ++j)
+        if (!(v[j] >= lo[j] && v[j] <= hi[j])) ok = false;
     }
   }
+  const bool bad = !__syncthreads_and(ok);
+  if (tid < PTAFS_MAX_HARM) kflag[tid] = 0;
 
   if (seg == 0) {
     int st = 0;
