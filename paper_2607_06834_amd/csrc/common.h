@@ -73,6 +73,8 @@ __host__ __device__ inline int tiles_for_pairs(int pairs) {
   const int steps = 2 * ((pairs + 3) / 4);
   return (steps + 3) / 4;
 }
+// rows of a coefficient block: at most PTAFS_MAX_HARM + 2 pairs, four tiles
+constexpr int kMaxRows = 64;
 
 
 // Packed lower-triangular storage, row-major: row i holds columns 0..i.
@@ -104,7 +106,7 @@ struct Dev {
   int jt_rn, jt_dm, rows_rn, rows_dm;
   // coefficient rows no frequency owns (timing model, padding), per block
   int n_free_rn, n_free_dm;
-  int16_t free_rn[64], free_dm[64];
+  int16_t free_rn[kMaxRows], free_dm[kMaxRows];
   int n_theta, d;
   int off_gw, off_rn, off_dm, off_cw, off_u, off_z, off_zdm;
   double tspan, dm_scale, sigma_b, tmax, prior_const;
@@ -138,15 +140,15 @@ struct Dev {
   // workspace
   double *coef_rn, *coef_dm;   // [n_psr][rows][c_pad]
   double *lstore;              // [c_pad][nf_gw][n_psr*(n_psr+1)/2]
-  double *sqk_rn, *sqk_dm;     // [c_pad][ka | nf_dm][n_psr] sqrt(kappa) of the diagonal frequencies
+  double *sqk_rn, *sqk_dm;     // [ka | nf_dm][n_psr][c_pad] sqrt(kappa) of the diagonal frequencies
   double *cwc;                 // [n_psr][kCwConst][c_pad] per chain/pulsar CW constants
   double *part_rn, *part_dm;   // [n_wg][rows][16]
   double *part_chi, *part_cw;  // [n_wg][16], [n_wg][8][16]
   double *bar_rn, *bar_dm;     // [n_psr][rows][c_pad]
   double *chi_p, *cw_p;        // [n_psr][c_pad], [n_psr][8][c_pad]
   double *dth_k;               // [c_pad][K][2] gw parts per frequency
-  double *drn_k;               // [c_pad][ka][n_psr][2]
-  double *ddm_k;               // [c_pad][nf_dm][n_psr][2]
+  double *drn_k;               // [c_pad][n_psr][ka][2]
+  double *ddm_k;               // [c_pad][n_psr][nf_dm][2]
 
   int32_t *flag_k;             // [c_pad][kmax] kFlagNotPD of the diagonal frequencies (k_spec_fwd)
   int32_t *flag_dense;         // [c_pad][nf_gw] kFlagNotPD of the dense frequencies (k_cholt/k_chol)
@@ -157,8 +159,27 @@ struct Dev {
 
 // Power-law spectrum A^2/(12 pi^2) yr^3 (f yr)^-gamma / T at f_k = (k + 1) / T
 // (Sec. IV.A, Eq. power_law with yr^3), evaluated in logarithms.
+// Per-frequency parts of the red-noise and DM hyper-parameter gradient,
+// [c][I][k][2] with the frequency innermost (k_finalize sums them over k from
+// consecutive words), and sqrt(kappa) of the diagonal frequencies kept by the
+// forward for the adjoint, [k][I][c] (chain-minor like the coefficient
+// panels, so 16 consecutive chains fill 128 bytes).
+__device__ inline double *drn_at(const Dev &D, int c, int I, int k) {
+  return D.drn_k + (((size_t)c * D.n_psr + I) * D.ka + k) * 2;
+}
+__device__ inline double *ddm_at(const Dev &D, int c, int I, int k) {
+  return D.ddm_k + (((size_t)c * D.n_psr + I) * D.nf_dm + k) * 2;
+}
+__device__ inline size_t sqk_at(const Dev &D, int c, int I, int k) {
+  return ((size_t)k * D.n_psr + I) * D.c_pad + c;
+}
+
 __device__ inline double powerlaw_k(const Dev &D, int k, double log10A, double gamma) {
   return exp(2.0 * kLn10 * log10A - gamma * D.lnfy[k] + D.pl_c);
+}
+// sqrt of the same, as one exponential of half the exponent
+__device__ inline double powerlaw_sqrt_k(const Dev &D, int k, double log10A, double gamma) {
+  return exp(kLn10 * log10A - 0.5 * gamma * D.lnfy[k] + 0.5 * D.pl_c);
 }
 
 constexpr int kFlagNotPD = 1;          // phi_k not positive definite

@@ -274,7 +274,8 @@ __global__ __launch_bounds__(64) void k_chol_bwd(Dev D, const double *__restrict
   const bool c1 = I1 < n, c2 = TWO && I2 < n;
   const double *xc = x + (size_t)c * D.d;
   double *gz = grad + (size_t)c * D.d + D.off_z + 2 * k0;
-  double *drn = D.drn_k + ((size_t)c * D.ka + k0) * n * 2;
+  double *drn = pt::drn_at(D, c, 0, k0);   // pulsar I at drn[2 ka I]
+  const size_t dI = 2 * (size_t)D.ka;
   double *dth = D.dth_k + ((size_t)c * D.ka + k0) * 2;
   const int fl0 = D.flag_k[(size_t)c * kmax + k0] | D.flag_dense[(size_t)c * D.nf_gw + k0];
   int32_t *fout = D.flag_out + (size_t)c * (kmax + pt::kSpecSeg) + k0;
@@ -283,8 +284,8 @@ __global__ __launch_bounds__(64) void k_chol_bwd(Dev D, const double *__restrict
     for (int I = l; I < n; I += 64) {
       gz[(size_t)I * K2] = 0.0;
       gz[(size_t)I * K2 + 1] = 0.0;
-      drn[2 * I] = 0.0;
-      drn[2 * I + 1] = 0.0;
+      drn[dI * I] = 0.0;
+      drn[dI * I + 1] = 0.0;
     }
     if (l == 0) {
       dth[0] = 0.0;
@@ -361,8 +362,8 @@ __global__ __launch_bounds__(64) void k_chol_bwd(Dev D, const double *__restrict
                            ? pt::powerlaw_k(D, k0, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1])
                            : 0.0;
     const double d0 = dk * kap * 2.0 * pt::kLn10, d1 = dk * kap * (-lnfy);
-    drn[2 * I] = d0;
-    drn[2 * I + 1] = d1;
+    drn[dI * I] = d0;
+    drn[dI * I + 1] = d1;
     fin = fin && isfinite(g0) && isfinite(g1) && isfinite(d0) && isfinite(d1);
   };
   if (c1) put(I1, v1s, v1c, z1s, z1c, dk1);

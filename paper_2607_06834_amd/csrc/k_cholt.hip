@@ -125,6 +125,16 @@ __host__ __device__ constexpr int tidx(int I, int J) { return I * (I + 1) / 2 + 
 // independent (frequency, chain) problems per workgroup, one wave each
 constexpr int kProbPerGroup = 4;
 
+// Work of the extra workgroups: G = nb * ns workgroups (spec_groups) for nb
+// blocks of 16 chains and ns contiguous frequency segments.
+struct spec_split {
+  int G, nb, ns, kmax;
+  __device__ spec_split(const Dev &D, int groups, int chains)
+      : G(groups), nb((chains + pt::kCB - 1) / pt::kCB), ns(max(1, groups / nb)),
+        kmax(max(D.ka, D.nf_dm)) {}
+  __device__ int k_lo(int s) const { return kmax * s / ns; }
+};
+
 __device__ inline int pi16(int c) { return 4 * (c & 3) + (c >> 2); }
 
 // ---------------------------------------------------------------------------
@@ -133,10 +143,11 @@ __device__ inline int pi16(int c) { return 4 * (c & 3) + (c >> 2); }
 template <int NT>
 __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const double *__restrict__ x,
                                                                   int n_dense_groups) {
-  if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies, chains b, b + G, ...
-    const int G = gridDim.x - n_dense_groups;
-    for (int c = blockIdx.x - n_dense_groups; c < D.c_pad; c += G) {
-      pt::spec_fwd_block(D, x, c, 0, 0, 1);
+  if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies
+    const spec_split sp(D, gridDim.x - n_dense_groups, D.c_pad);
+    for (int it = blockIdx.x - n_dense_groups; it < sp.nb * sp.ns; it += sp.G) {
+      const int b = it / sp.ns, s = it - b * sp.ns;
+      pt::spec_fwd_cb(D, x, b * pt::kCB, sp.k_lo(s), sp.k_lo(s + 1), s);
       __syncthreads();
     }
     return;
@@ -391,13 +402,11 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
                                                   int n_dense_groups) {
   constexpr bool COLW = NT > pt::kTileMaxNT;
   constexpr int PPG = bwd_probs<NT>();
-  if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies, chains b, b + G, ...
-    const int G = gridDim.x - n_dense_groups;
-    const int kmax = max(D.ka, D.nf_dm);
-    for (int c = blockIdx.x - n_dense_groups; c < D.n_chains; c += G) {
-      pt::spec_bwd_block(D, x, grad, c, 0, 1, 0);
-      if (threadIdx.x >= 1 && threadIdx.x < pt::kSpecSeg)
-        D.flag_out[(size_t)c * (kmax + pt::kSpecSeg) + kmax + threadIdx.x] = 0;
+  if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies
+    const spec_split sp(D, gridDim.x - n_dense_groups, D.n_chains);
+    for (int it = blockIdx.x - n_dense_groups; it < sp.nb * sp.ns; it += sp.G) {
+      const int b = it / sp.ns, s = it - b * sp.ns;
+      pt::spec_bwd_cb(D, x, grad, b * pt::kCB, sp.k_lo(s), sp.k_lo(s + 1), s, sp.ns);
       __syncthreads();
     }
     return;
@@ -424,7 +433,8 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
   const int K2 = 2 * D.ka;
   const double *xc = x + (size_t)c * D.d;
   double *gz = grad + (size_t)c * D.d + D.off_z + 2 * k0;
-  double *drn = D.drn_k + ((size_t)c * D.ka + k0) * n * 2;
+  double *drn = pt::drn_at(D, c, 0, k0);   // pulsar I at drn[2 ka I]
+  const size_t dI = 2 * (size_t)D.ka;
   double *dth = D.dth_k + ((size_t)c * D.ka + k0) * 2;
   const int fl0 = D.flag_k[(size_t)c * kmax + k0] | D.flag_dense[(size_t)c * D.nf_gw + k0];
   int32_t *fout = D.flag_out + (size_t)c * (kmax + pt::kSpecSeg) + k0;
@@ -433,8 +443,8 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
     for (int I = l; I < n; I += 64) {
       gz[(size_t)I * K2] = 0.0;
       gz[(size_t)I * K2 + 1] = 0.0;
-      drn[2 * I] = 0.0;
-      drn[2 * I + 1] = 0.0;
+      drn[dI * I] = 0.0;
+      drn[dI * I + 1] = 0.0;
     }
     if (l == 0) {
       dth[0] = 0.0;
@@ -452,6 +462,17 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
   }
   const double rho_o = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
   const double *Cb = lst + ((size_t)c * D.nf_gw + k0) * (NTILE * 256);
+  // Up to kTileMaxNT tiles the factor is loaded into registers here, before
+  // anything waits on memory, in the B layout (row 4q + v, column c16 of each
+  // tile, 512 contiguous bytes per load): it serves v = C^T abar and the
+  // diagonal inverses.  (Beyond, there are no registers for it.)
+  v4d Cr[COLW ? 1 : NTILE];
+  if constexpr (!COLW) {
+#pragma unroll
+    for (int T = 0; T < NTILE; ++T)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Cr[T][v] = Cb[T * 256 + 64 * q + 16 * v + c16];
+  }
 
   // ---- v_c = C^T abar_c: lane (c16, q) sums rows 16K + 4q + v of column
   //      16J + c16, then the four lane groups are added
@@ -474,7 +495,9 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
       const double *t = Cb + tidx(K, J) * 256 + 64 * q + c16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double e = t[16 * v];
+        double e;
+        if constexpr (COLW) e = t[16 * v];
+        else e = Cr[tidx(K, J)][v];
         ss += e * ab[16 * K + 4 * q + v][0];
         sc += e * ab[16 * K + 4 * q + v][1];
       }
@@ -607,14 +630,18 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
 #pragma unroll
     for (int J = 0; J < NT; ++J)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        tl[J][(4 * q + v) * TS + c16] = Cb[tidx(J, J) * 256 + (4 * q + v) * 16 + c16];
+      for (int v = 0; v < 4; ++v) tl[J][(4 * q + v) * TS + c16] = Cr[tidx(J, J)][v];
     wave_sync();
 #pragma unroll
     for (int rnd = 0; rnd < (NT + 3) / 4; ++rnd) {
       const int J = 4 * rnd + q;
       if (J < NT) {
         const double *T = tl[J];
+        // reciprocals of the diagonal first (independent of each other), so
+        // the substitution's dependent chain has multiplies, not divisions
+        double rdg[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) rdg[r] = rcp_nr(T[r * TS + r]);
         double xs[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
@@ -622,7 +649,7 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
           double s = (r == c16) ? 1.0 : 0.0;
 #pragma unroll
           for (int m = 0; m < r; ++m) s -= T[r * TS + m] * xs[m];
-          xs[r] = s / T[r * TS + r];
+          xs[r] = s * rdg[r];
         }
 #pragma unroll
         for (int r = 0; r < 16; ++r) tl[NT + J][r * TS + c16] = xs[r];
@@ -720,8 +747,8 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
       for (int J = 0; J < NT; ++J) dk = (J == (I >> 4)) ? dkap[J] : dk;
       const double kap = kapo[h];
       const double d0 = dk * kap * 2.0 * pt::kLn10, d1 = dk * kap * (-lnfy);
-      drn[2 * I] = d0;
-      drn[2 * I + 1] = d1;
+      drn[dI * I] = d0;
+      drn[dI * I + 1] = d1;
       fin = fin && isfinite(g0) && isfinite(g1) && isfinite(d0) && isfinite(d1);
     }
   }
@@ -736,9 +763,13 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
 
 // Workgroups for the diagonal-frequency work of `chains` chains next to ng
 // dense workgroups: the compute units those leave free (one dense workgroup
-// fills a compute unit), at least 8, at most one per chain.
+// fills a compute unit), at least 8, split into blocks of 16 chains times
+// frequency segments (spec_split).
 int spec_groups(const Dev &D, int ng, int chains) {
-  return max(1, min(chains, max(8, D.n_cu - ng)));
+  const int nb = (chains + pt::kCB - 1) / pt::kCB;
+  const int kmax = max(D.ka, D.nf_dm);
+  const int ns = max(1, min(min(kmax, pt::kSpecSeg), max(8, D.n_cu - ng) / nb));
+  return nb * ns;
 }
 
 // grid: the dense problems, kProbPerGroup per workgroup, then the

@@ -102,14 +102,14 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
     }
     if (D.nf_rn > 0) {
       for (int e = t; e < 2 * n; e += kFinT) {
-        const double s = sum32(D.drn_k + (size_t)c * D.ka * n * 2 + e, (size_t)n * 2, D.ka);
+        const double s = sum32(pt::drn_at(D, c, e >> 1, 0) + (e & 1), 2, D.ka);
         gc[D.off_rn + e] = s;
         fin = fin && isfinite(s);
       }
     }
     if (D.nf_dm > 0) {
       for (int e = t; e < 2 * n; e += kFinT) {
-        const double s = sum32(D.ddm_k + (size_t)c * D.nf_dm * n * 2 + e, (size_t)n * 2, D.nf_dm);
+        const double s = sum32(pt::ddm_at(D, c, e >> 1, 0) + (e & 1), 2, D.nf_dm);
         gc[D.off_dm + e] = s;
         fin = fin && isfinite(s);
       }
