@@ -462,17 +462,6 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
   }
   const double rho_o = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
   const double *Cb = lst + ((size_t)c * D.nf_gw + k0) * (NTILE * 256);
-  // Up to kTileMaxNT tiles the factor is loaded into registers here, before
-  // anything waits on memory, in the B layout (row 4q + v, column c16 of each
-  // tile, 512 contiguous bytes per load): it serves v = C^T abar and the
-  // diagonal inverses.  (Beyond, there are no registers for it.)
-  v4d Cr[COLW ? 1 : NTILE];
-  if constexpr (!COLW) {
-#pragma unroll
-    for (int T = 0; T < NTILE; ++T)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Cr[T][v] = Cb[T * 256 + 64 * q + 16 * v + c16];
-  }
 
   // ---- v_c = C^T abar_c: lane (c16, q) sums rows 16K + 4q + v of column
   //      16J + c16, then the four lane groups are added
@@ -495,9 +484,7 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
       const double *t = Cb + tidx(K, J) * 256 + 64 * q + c16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        double e;
-        if constexpr (COLW) e = t[16 * v];
-        else e = Cr[tidx(K, J)][v];
+        const double e = t[16 * v];
         ss += e * ab[16 * K + 4 * q + v][0];
         sc += e * ab[16 * K + 4 * q + v][1];
       }
@@ -630,7 +617,7 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
 #pragma unroll
     for (int J = 0; J < NT; ++J)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) tl[J][(4 * q + v) * TS + c16] = Cr[tidx(J, J)][v];
+      for (int v = 0; v < 4; ++v) tl[J][(4 * q + v) * TS + c16] = Cb[tidx(J, J) * 256 + (4 * q + v) * 16 + c16];
     wave_sync();
 #pragma unroll
     for (int rnd = 0; rnd < (NT + 3) / 4; ++rnd) {
