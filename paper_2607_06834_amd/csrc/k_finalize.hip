@@ -28,6 +28,13 @@ __device__ inline double sum32(const double *p, size_t stride, int K) {
   return s;
 }
 
+// a gradient entry computed by this thread: stored (overwritten with zero
+// below if the chain's status turns out nonzero) and tested for finiteness
+__device__ inline void gtheta_or_u(double *gc, int i, double g, bool &fin) {
+  gc[i] = g;
+  fin = fin && isfinite(g);
+}
+
 // one workgroup of kFinT threads per chain
 constexpr int kFinT = 1024;
 constexpr int kFinW = kFinT / 64;
@@ -45,17 +52,20 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
   const int n = D.n_psr;
   const int kmax = max(D.ka, D.nf_dm);
 
-  // ---- per-chain condition, in the order: prior box, non-finite input,
-  //      CW coalescence, phi not positive definite, non-finite output
+  // Every input of the assembly (condition flags, the norm of the whitened
+  // inputs, the chi^2 partials, the per-frequency gradient parts) is loaded
+  // before the first reduction waits on it.  A thread computes the theta
+  // gradient entry t and the timing-model entry t whatever the status, and
+  // writes them (or zeros) once the status is known.
   const int nseg = max(1, min(pt::kSpecSeg, kmax));
   const int32_t *fo = D.flag_out + (size_t)c * (kmax + pt::kSpecSeg);
+  const int pre = D.st_pre[c];
   int fl = 0;
   for (int k = t; k < kmax; k += kFinT) fl |= D.flag_k[(size_t)c * kmax + k];
   for (int k = t; k < D.nf_gw; k += kFinT) fl |= D.flag_dense[(size_t)c * D.nf_gw + k] | fo[k];
   for (int k = t; k < nseg; k += kFinT) fl |= fo[kmax + k];
-  fl = pt::block_or<kFinW>(fl, ired);
   // finiteness and squared norm of (u, z, z_dm): eight elements per thread
-  // with their loads issued together, then a fixed-order workgroup sum
+  // with their loads issued together
   double zz = 0.0;
   bool fin_in = true;
   {
@@ -73,67 +83,57 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
         zz += v[b] * v[b];
       }
     }
-    zz = pt::block_sum<kFinW>(zz, red);
-    fin_in = __syncthreads_and(fin_in);
   }
-  const int pre = D.st_pre[c];
+  double ch = 0.0;
+  for (int p = t; p < n; p += kFinT) ch += D.chi_p[(size_t)p * cp + c];
+  // hyper-parameter gradient entries (frequency sums in order) and the
+  // timing model, d/du = sigma_b M^T g - u
+  bool fin = true;
+  for (int e = t; e < D.n_theta; e += kFinT) {
+    double s = 0.0;
+    if (D.nf_gw > 0 && e >= D.off_gw && e < D.off_gw + 2)
+      s = sum32(D.dth_k + (size_t)c * D.ka * 2 + (e - D.off_gw), 2, D.ka);
+    else if (D.nf_rn > 0 && e >= D.off_rn && e < D.off_rn + 2 * n)
+      s = sum32(pt::drn_at(D, c, (e - D.off_rn) >> 1, 0) + ((e - D.off_rn) & 1), 2, D.ka);
+    else if (D.nf_dm > 0 && e >= D.off_dm && e < D.off_dm + 2 * n)
+      s = sum32(pt::ddm_at(D, c, (e - D.off_dm) >> 1, 0) + ((e - D.off_dm) & 1), 2, D.nf_dm);
+    else if (D.has_cw && e >= D.off_cw && e < D.off_cw + 8)
+      for (int p0 = 0; p0 < n; p0 += 32)
+        s += sum32(D.cw_p + ((size_t)p0 * 8 + (e - D.off_cw)) * cp + c, 8 * cp, min(32, n - p0));
+    gtheta_or_u(gc, e, s, fin);
+  }
+  for (int e = t; e < 3 * n; e += kFinT) {
+    const int I = e / 3, ti = e % 3;
+    const int row = pt::tm_row(ti, D.kb);
+    const double g = D.sigma_b * D.bar_rn[((size_t)I * D.rows_rn + row) * cp + c] - xc[D.off_u + e];
+    gtheta_or_u(gc, D.off_u + e, g, fin);
+  }
+  // ---- the reductions: one OR (flags, and the two finiteness tests as
+  //      bits), two fixed-order sums
+  constexpr int kBitInput = 1 << 28, kBitOutput = 1 << 29;
+  fl = pt::block_or<kFinW>(fl | (fin_in ? 0 : kBitInput) | (fin ? 0 : kBitOutput), ired);
+  zz = pt::block_sum<kFinW>(zz, red);
+  ch = pt::block_sum<kFinW>(ch, red);
+
+  // ---- per-chain condition, in the order: prior box, non-finite input,
+  //      CW coalescence, phi not positive definite, non-finite output
   int st = 0;
   if (pre == PTAFS_ST_PRIOR) st = PTAFS_ST_PRIOR;
-  else if (!fin_in) st = PTAFS_ST_NONFINITE;
+  else if (fl & kBitInput) st = PTAFS_ST_NONFINITE;
   else if (pre == PTAFS_ST_CW) st = PTAFS_ST_CW;
   else if (fl & pt::kFlagNotPD) st = PTAFS_ST_NOTPD;
   else if (fl & pt::kFlagOutNonfinite) st = PTAFS_ST_NONFINITE;
 
   // ---- log p
-  double ch = 0.0;
-  for (int p = t; p < n; p += kFinT) ch += D.chi_p[(size_t)p * cp + c];
-  ch = pt::block_sum<kFinW>(ch, red);
   const double dz = (double)(D.d - D.off_u);
   double lp = -0.5 * ch - 0.5 * D.lnn_total - 0.5 * (double)D.n_toa * pt::kLn2Pi -
               0.5 * zz - 0.5 * dz * pt::kLn2Pi + D.prior_const;
-
-  // ---- hyper-parameter and timing-model gradient (frequency sums in order)
-  bool fin = true;
-  if (st == 0) {
-    if (D.nf_gw > 0 && t < 2) {
-      const double s = sum32(D.dth_k + (size_t)c * D.ka * 2 + t, 2, D.ka);
-      gc[D.off_gw + t] = s;
-      fin = fin && isfinite(s);
-    }
-    if (D.nf_rn > 0) {
-      for (int e = t; e < 2 * n; e += kFinT) {
-        const double s = sum32(pt::drn_at(D, c, e >> 1, 0) + (e & 1), 2, D.ka);
-        gc[D.off_rn + e] = s;
-        fin = fin && isfinite(s);
-      }
-    }
-    if (D.nf_dm > 0) {
-      for (int e = t; e < 2 * n; e += kFinT) {
-        const double s = sum32(pt::ddm_at(D, c, e >> 1, 0) + (e & 1), 2, D.nf_dm);
-        gc[D.off_dm + e] = s;
-        fin = fin && isfinite(s);
-      }
-    }
-    if (D.has_cw && t < 8) {
-      double s = 0.0;
-      for (int p0 = 0; p0 < n; p0 += 32)
-        s += sum32(D.cw_p + ((size_t)p0 * 8 + t) * cp + c, 8 * cp, min(32, n - p0));
-      gc[D.off_cw + t] = s;
-      fin = fin && isfinite(s);
-    }
-    // timing model: d/du = sigma_b M^T g - u
-    for (int e = t; e < 3 * n; e += kFinT) {
-      const int I = e / 3, ti = e % 3;
-      const int row = pt::tm_row(ti, D.kb);
-      const double g = D.sigma_b * D.bar_rn[((size_t)I * D.rows_rn + row) * cp + c] - xc[D.off_u + e];
-      gc[D.off_u + e] = g;
-      fin = fin && isfinite(g);
-    }
-    const bool allfin = __syncthreads_and(fin);
-    if (!allfin || !isfinite(lp)) st = PTAFS_ST_NONFINITE;
-  }
+  if (st == 0 && ((fl & kBitOutput) || !isfinite(lp))) st = PTAFS_ST_NONFINITE;
   if (st != 0) {
-    for (int i = t; i < D.d; i += kFinT) gc[i] = 0.0;
+    // the theta and u entries this thread computed, then the rest
+    for (int e = t; e < D.n_theta; e += kFinT) gc[e] = 0.0;
+    for (int e = t; e < 3 * n; e += kFinT) gc[D.off_u + e] = 0.0;
+    for (int i = D.off_z + t; i < D.d; i += kFinT) gc[i] = 0.0;
     lp = -INFINITY;
   }
   if (t == 0) {
