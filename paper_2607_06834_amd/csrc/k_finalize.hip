@@ -97,9 +97,18 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
       s = sum32(pt::drn_at(D, c, (e - D.off_rn) >> 1, 0) + ((e - D.off_rn) & 1), 2, D.ka);
     else if (D.nf_dm > 0 && e >= D.off_dm && e < D.off_dm + 2 * n)
       s = sum32(pt::ddm_at(D, c, (e - D.off_dm) >> 1, 0) + ((e - D.off_dm) & 1), 2, D.nf_dm);
-    else if (D.has_cw && e >= D.off_cw && e < D.off_cw + 8)
-      for (int p0 = 0; p0 < n; p0 += 32)
-        s += sum32(D.cw_p + ((size_t)p0 * 8 + (e - D.off_cw)) * cp + c, 8 * cp, min(32, n - p0));
+    else if (D.has_cw && e >= D.off_cw && e < D.off_cw + 8) {
+      // over the pulsars in order, eight loads at a time
+      const double *q = D.cw_p + (size_t)(e - D.off_cw) * cp + c;
+#pragma unroll 1
+      for (int p0 = 0; p0 < n; p0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = (p0 + k < n) ? q[(size_t)(p0 + k) * 8 * cp] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+      }
+    }
     gtheta_or_u(gc, e, s, fin);
   }
   for (int e = t; e < 3 * n; e += kFinT) {
