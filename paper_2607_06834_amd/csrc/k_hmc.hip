@@ -50,28 +50,47 @@ __global__ __launch_bounds__(kHmcT) void k_hmc_begin(int d, double eps, const do
   const size_t off = (size_t)c * d;
   double kin = 0.0;
   const int npair = (d + 1) / 2;
-  for (int m = threadIdx.x; m < npair; m += kHmcT) {
-    uint32_t ctr[4] = {(uint32_t)m, (uint32_t)c, j, 0u};
-    philox10(ctr, k0, k1);
-    const double u1 = (u53(ctr[0], ctr[1]) + 1.0) * 0x1.0p-53;
-    const double u2 = u53(ctr[2], ctr[3]) * 0x1.0p-53;
-    const double rad = sqrt(-2.0 * log(u1));
-    double sn, cs;
-    sincos(pt::kTwoPi * u2, &sn, &cs);
-    const double nz[2] = {rad * cs, rad * sn};
+  // kB pairs per thread per batch: their loads are issued before the first
+  // use (the pairs are independent; a plain loop would wait for each in turn)
+  constexpr int kB = 3;
+  for (int m0 = threadIdx.x; m0 < npair; m0 += kHmcT * kB) {
+    double xv[kB][2], gv[kB][2], iv[kB][2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = 2 * m + h;
-      if (i >= d) break;
-      const double im = inv_mass ? inv_mass[i] : 1.0;
-      double pi = im > 0.0 ? nz[h] / sqrt(im) : 0.0;
-      kin += 0.5 * im * pi * pi;
-      const double xi = x[off + i], gi = grad[off + i];
-      x0[off + i] = xi;
-      g0[off + i] = gi;
-      pi += 0.5 * eps * gi;                  // half kick
-      x[off + i] = xi + eps * im * pi;       // first drift
-      p[off + i] = pi;
+    for (int b = 0; b < kB; ++b)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = 2 * (m0 + kHmcT * b) + h;
+        const bool in = i < d;
+        xv[b][h] = in ? x[off + i] : 0.0;
+        gv[b][h] = in ? grad[off + i] : 0.0;
+        iv[b][h] = (in && inv_mass) ? inv_mass[i] : 1.0;
+      }
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const int m = m0 + kHmcT * b;
+      if (m >= npair) continue;
+      uint32_t ctr[4] = {(uint32_t)m, (uint32_t)c, j, 0u};
+      philox10(ctr, k0, k1);
+      const double u1 = (u53(ctr[0], ctr[1]) + 1.0) * 0x1.0p-53;
+      const double u2 = u53(ctr[2], ctr[3]) * 0x1.0p-53;
+      const double rad = sqrt(-2.0 * log(u1));
+      double sn, cs;
+      sincos(pt::kTwoPi * u2, &sn, &cs);
+      const double nz[2] = {rad * cs, rad * sn};
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = 2 * m + h;
+        if (i >= d) break;
+        const double im = iv[b][h];
+        double pi = im > 0.0 ? nz[h] / sqrt(im) : 0.0;
+        kin += 0.5 * im * pi * pi;
+        const double xi = xv[b][h], gi = gv[b][h];
+        x0[off + i] = xi;
+        g0[off + i] = gi;
+        pi += 0.5 * eps * gi;                  // half kick
+        x[off + i] = xi + eps * im * pi;       // first drift
+        p[off + i] = pi;
+      }
     }
   }
   kin = pt::block_sum<kHmcW>(kin, red);
@@ -94,11 +113,25 @@ __global__ __launch_bounds__(kHmcT) void k_hmc_end(int d, double eps, const doub
   const uint64_t jj = traj[0];      // trajectory number; traj[1] = first of this run
   const uint32_t j = (uint32_t)jj;
   const size_t off = (size_t)c * d;
+  // kB elements per thread per batch, their loads issued together
+  constexpr int kB = 8;
   double kin = 0.0;
-  for (int i = threadIdx.x; i < d; i += kHmcT) {
-    const double im = inv_mass ? inv_mass[i] : 1.0;
-    const double pi = p[off + i] + 0.5 * eps * grad[off + i];
-    kin += 0.5 * im * pi * pi;
+  for (int i0 = threadIdx.x; i0 < d; i0 += kHmcT * kB) {
+    double pv[kB], gv[kB], iv[kB];
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const int i = i0 + kHmcT * b;
+      const bool in = i < d;
+      pv[b] = in ? p[off + i] : 0.0;
+      gv[b] = in ? grad[off + i] : 0.0;
+      iv[b] = (in && inv_mass) ? inv_mass[i] : 1.0;
+    }
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      if (i0 + kHmcT * b >= d) continue;
+      const double pi = pv[b] + 0.5 * eps * gv[b];
+      kin += 0.5 * iv[b] * pi * pi;
+    }
   }
   kin = pt::block_sum<kHmcW>(kin, red);
   if (threadIdx.x == 0) {
@@ -115,14 +148,25 @@ __global__ __launch_bounds__(kHmcT) void k_hmc_end(int d, double eps, const doub
   __syncthreads();
   const int a = acc_s;
   double *smp = samples ? samples + ((size_t)(jj - traj[1]) * n_chains + c) * d : nullptr;
-  for (int i = threadIdx.x; i < d; i += kHmcT) {
-    double xi = x[off + i];
-    if (!a) {
-      xi = x0[off + i];
-      x[off + i] = xi;
-      grad[off + i] = g0[off + i];
+  for (int i0 = threadIdx.x; i0 < d; i0 += kHmcT * kB) {
+    double xv[kB], gv[kB];
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const int i = i0 + kHmcT * b;
+      const bool in = i < d;
+      xv[b] = in ? (a ? x[off + i] : x0[off + i]) : 0.0;
+      gv[b] = (in && !a) ? g0[off + i] : 0.0;
     }
-    if (smp) smp[i] = xi;
+#pragma unroll
+    for (int b = 0; b < kB; ++b) {
+      const int i = i0 + kHmcT * b;
+      if (i >= d) continue;
+      if (!a) {
+        x[off + i] = xv[b];
+        grad[off + i] = gv[b];
+      }
+      if (smp) smp[i] = xv[b];
+    }
   }
 }
 
