@@ -75,6 +75,9 @@ __host__ __device__ inline int tiles_for_pairs(int pairs) {
 }
 // rows of a coefficient block: at most PTAFS_MAX_HARM + 2 pairs, four tiles
 constexpr int kMaxRows = 64;
+// workgroups per chain of the HMC momentum draw (its kinetic energy in as
+// many partial sums, added in order by the accept step)
+constexpr int kHmcBeginG = 4;
 
 
 // Packed lower-triangular storage, row-major: row i holds columns 0..i.

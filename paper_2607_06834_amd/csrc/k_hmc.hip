@@ -44,22 +44,24 @@ __global__ __launch_bounds__(kHmcT) void k_hmc_begin(int d, double eps, const do
                                                    double *p, double *x0, double *lp0, double *g0,
                                                    double *h0) {
   __shared__ double red[kHmcW];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x, wg = blockIdx.y;   // chain, and which of its kHmcBeginG workgroups
   const uint32_t j = (uint32_t)(*traj);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const size_t off = (size_t)c * d;
   double kin = 0.0;
   const int npair = (d + 1) / 2;
-  // kB pairs per thread per batch: their loads are issued before the first
-  // use (the pairs are independent; a plain loop would wait for each in turn)
-  constexpr int kB = 3;
-  for (int m0 = threadIdx.x; m0 < npair; m0 += kHmcT * kB) {
+  // the chain's pairs are dealt to its workgroups' threads (tg of TG); kB
+  // pairs per thread per batch, their loads issued before the first use
+  // (the pairs are independent; a plain loop would wait for each in turn)
+  constexpr int kB = 3, TG = kHmcT * pt::kHmcBeginG;
+  const int tg = wg * kHmcT + (int)threadIdx.x;
+  for (int m0 = tg; m0 < npair; m0 += TG * kB) {
     double xv[kB][2], gv[kB][2], iv[kB][2];
 #pragma unroll
     for (int b = 0; b < kB; ++b)
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const int i = 2 * (m0 + kHmcT * b) + h;
+        const int i = 2 * (m0 + TG * b) + h;
         const bool in = i < d;
         xv[b][h] = in ? x[off + i] : 0.0;
         gv[b][h] = in ? grad[off + i] : 0.0;
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(kHmcT) void k_hmc_begin(int d, double eps, const do
       }
 #pragma unroll
     for (int b = 0; b < kB; ++b) {
-      const int m = m0 + kHmcT * b;
+      const int m = m0 + TG * b;
       if (m >= npair) continue;
       uint32_t ctr[4] = {(uint32_t)m, (uint32_t)c, j, 0u};
       philox10(ctr, k0, k1);
@@ -95,8 +97,8 @@ __global__ __launch_bounds__(kHmcT) void k_hmc_begin(int d, double eps, const do
   }
   kin = pt::block_sum<kHmcW>(kin, red);
   if (threadIdx.x == 0) {
-    lp0[c] = logp[c];
-    h0[c] = -logp[c] + kin;
+    if (wg == 0) lp0[c] = logp[c];
+    h0[(size_t)c * pt::kHmcBeginG + wg] = kin;   // partial kinetic energy
   }
 }
 
@@ -137,10 +139,13 @@ __global__ __launch_bounds__(kHmcT) void k_hmc_end(int d, double eps, const doub
   if (threadIdx.x == 0) {
     if (n_invalid && status[c] != 0) n_invalid[c] += 1;
     const double H1 = -logp[c] + kin;
+    double kin0 = 0.0;
+    for (int g = 0; g < pt::kHmcBeginG; ++g) kin0 += h0[(size_t)c * pt::kHmcBeginG + g];
+    const double H0 = -lp0[c] + kin0;
     uint32_t ctr[4] = {0u, (uint32_t)c, j, 1u};
     philox10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
     const double u = (u53(ctr[0], ctr[1]) + 1.0) * 0x1.0p-53;
-    const int a = (isfinite(H1) && log(u) < h0[c] - H1) ? 1 : 0;
+    const int a = (isfinite(H1) && log(u) < H0 - H1) ? 1 : 0;
     acc_s = a;
     if (a) n_accept[c] += 1;
     else logp[c] = lp0[c];
@@ -186,7 +191,7 @@ hipError_t launch_hmc_begin(const pt::Dev &D, int d, double eps, const double *i
                             uint64_t seed, const uint64_t *traj, double *x, const double *logp,
                             const double *grad, double *p, double *x0, double *lp0, double *g0,
                             double *h0, hipStream_t s) {
-  hipLaunchKernelGGL(k_hmc_begin, dim3(D.n_chains), dim3(kHmcT), 0, s, d, eps, inv_mass, seed, traj,
+  hipLaunchKernelGGL(k_hmc_begin, dim3(D.n_chains, pt::kHmcBeginG), dim3(kHmcT), 0, s, d, eps, inv_mass, seed, traj,
                      x, logp, grad, p, x0, lp0, g0, h0);
   return hipGetLastError();
 }

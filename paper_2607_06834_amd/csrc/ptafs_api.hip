@@ -352,7 +352,8 @@ size_t dataset_bytes_of(const pt::Dev &B, int n_chunks) {
 // Scratch of ptafs_hmc_run for n_chains.
 size_t hmc_bytes_of(const pt::Dev &B, int n_chains) {
   const size_t cd = (size_t)n_chains * B.d;
-  return align256(3 * cd * sizeof(double)) + align256(2 * (size_t)n_chains * sizeof(double)) +
+  return align256(3 * cd * sizeof(double)) +
+         align256((1 + pt::kHmcBeginG) * (size_t)n_chains * sizeof(double)) +
          align256((size_t)n_chains * sizeof(int32_t)) + 256;
 }
 
@@ -676,7 +677,8 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   if (rc) return rc;
   const int d = ds->base.d;
   const size_t cd = (size_t)n_chains * d;
-  // scratch: p, x0, g0 [C][d], lp0, h0, status [C], trajectory counter
+  // scratch: p, x0, g0 [C][d], lp0 [C], kinetic-energy partials [C][kHmcBeginG],
+  // status [C], trajectory counter
   const size_t need = hmc_bytes_of(ds->base, n_chains);
   if (need > ds->hmc_bytes) {
     PT_TRY(hipDeviceSynchronize());
@@ -697,7 +699,7 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   char *h2 = h + align256(3 * cd * sizeof(double));
   double *lp0 = reinterpret_cast<double *>(h2);
   double *h0 = lp0 + n_chains;
-  char *h3 = h2 + align256(2 * (size_t)n_chains * sizeof(double));
+  char *h3 = h2 + align256((1 + pt::kHmcBeginG) * (size_t)n_chains * sizeof(double));
   int32_t *st = reinterpret_cast<int32_t *>(h3);
   uint64_t *traj = reinterpret_cast<uint64_t *>(h3 + align256((size_t)n_chains * sizeof(int32_t)));
 
