@@ -21,9 +21,10 @@
 // column, taken on the MFMA output layout.
 //
 // The launches also carry the diagonal-frequency work of the same stage
-// (spec_dev.h) in a few extra workgroups after the dense ones, each taking
-// whole chains: the two touch disjoint outputs, and the extra workgroups run
-// on the compute units the dense problems leave free.
+// (spec_dev.h) in a few extra workgroups after the dense ones, each taking a
+// block of 16 chains and a segment of the frequencies: the two touch disjoint
+// outputs, and the extra workgroups run on the compute units the dense
+// problems leave free.
 //
 // Register layouts of a 16x16 block X (lane l = c + 16 q, item v or slice s):
 //   forward, E(X):   X[c][q + 4s]       (operand A of X, operand B of X^T,

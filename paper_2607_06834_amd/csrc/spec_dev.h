@@ -1,6 +1,7 @@
-// Per-chain work of the spectral side that needs no dense factorisation, as
-// device bodies: k_spec's kernels call them, and so do the dense-frequency
-// kernels, whose launches carry this work in extra workgroups.  It covers the
+// Work of the spectral side that needs no dense factorisation, as device
+// bodies: k_spec's kernels call the per-chain forms (spec_fwd_block,
+// spec_bwd_block), and the dense-frequency launches carry the 16-chain-block
+// forms (spec_fwd_cb, spec_bwd_cb) in extra workgroups.  It covers the
 // power-law spectra (Sec. IV.A, Eq. power_law), the diagonal prior of the
 // frequencies without the common process and the DM prior with their
 // whitening transforms (Sec. II.B, Eq. standardizing_transform, mu = 0) and
