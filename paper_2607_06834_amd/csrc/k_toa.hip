@@ -162,6 +162,10 @@ void k_toa_mfma(Dev D, int xcd_map) {
     //      each k-step issued as soon as its basis pair exists
     v4d rr = v4d{0.0, 0.0, 0.0, 0.0};
     v4d rd = v4d{0.0, 0.0, 0.0, 0.0};
+    // raised wave priority while the forward's MFMAs issue: with several
+    // waves per SIMD the others' loads, LDS and vector work then fill the
+    // matrix core's gaps instead of delaying this chain
+    __builtin_amdgcn_s_setprio(1);
 #pragma unroll
     for (int m = 0; m < NSR / 2; ++m) {
       double fa, fb;
@@ -185,6 +189,7 @@ void k_toa_mfma(Dev D, int xcd_map) {
       rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, crs(2 * m + 1), rr, 0, 0, 0);
       if (2 * m + 1 < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, cds(2 * m + 1), rd, 0, 0, 0);
     }
+    __builtin_amdgcn_s_setprio(0);
     wave_sync();
     // ---- residuals: lane (col, q) holds TOAs base + q + 4v, chain col
     // (v_mfma_f64_16x16x4f64 returns D[q + 4v][col] in item v of lane col + 16q)
