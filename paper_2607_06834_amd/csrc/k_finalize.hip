@@ -42,7 +42,7 @@ constexpr int kFinW = kFinT / 64;
 __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, double *__restrict__ logp,
                                                   double *grad, int32_t *__restrict__ status,
                                                   pt::Kick kick, int has_kick) {
-  __shared__ double red[kFinW];
+  __shared__ double red[kFinW], red2[kFinW];
   __shared__ int ired[kFinW];
   const int c = blockIdx.x;
   const int t = threadIdx.x;
@@ -64,12 +64,23 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
   for (int k = t; k < kmax; k += kFinT) fl |= D.flag_k[(size_t)c * kmax + k];
   for (int k = t; k < D.nf_gw; k += kFinT) fl |= D.flag_dense[(size_t)c * D.nf_gw + k] | fo[k];
   for (int k = t; k < nseg; k += kFinT) fl |= fo[kmax + k];
-  // finiteness and squared norm of (u, z, z_dm): eight elements per thread
-  // with their loads issued together
+  // every theta entry, timing-model entry and pulsar has one thread
+  static_assert(4 * PTAFS_MAX_PSR + 10 <= kFinT && 3 * PTAFS_MAX_PSR <= kFinT, "one entry per thread");
+  // the timing-model gradient's inputs and the chi^2 partial first (their
+  // loads overlap those below)
+  double ub = 0.0, ux = 0.0;
+  if (t < 3 * n) {
+    const int I = t / 3, row = pt::tm_row(t % 3, D.kb);
+    ub = D.bar_rn[((size_t)I * D.rows_rn + row) * cp + c];
+    ux = xc[D.off_u + t];
+  }
+  double ch = (t < n) ? D.chi_p[(size_t)t * cp + c] : 0.0;
+  // finiteness and squared norm of (u, z, z_dm): twelve elements per thread
+  // with their loads issued together (one pass up to 12288 of them)
   double zz = 0.0;
   bool fin_in = true;
   {
-    constexpr int B = 8;
+    constexpr int B = 12;
     for (int i0 = D.off_u + t; i0 < D.d; i0 += kFinT * B) {
       double v[B];
 #pragma unroll
@@ -84,8 +95,6 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
       }
     }
   }
-  double ch = 0.0;
-  for (int p = t; p < n; p += kFinT) ch += D.chi_p[(size_t)p * cp + c];
   // hyper-parameter gradient entries (frequency sums in order) and the
   // timing model, d/du = sigma_b M^T g - u
   bool fin = true;
@@ -111,18 +120,33 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
     }
     gtheta_or_u(gc, e, s, fin);
   }
-  for (int e = t; e < 3 * n; e += kFinT) {
-    const int I = e / 3, ti = e % 3;
-    const int row = pt::tm_row(ti, D.kb);
-    const double g = D.sigma_b * D.bar_rn[((size_t)I * D.rows_rn + row) * cp + c] - xc[D.off_u + e];
-    gtheta_or_u(gc, D.off_u + e, g, fin);
-  }
+  if (t < 3 * n) gtheta_or_u(gc, D.off_u + t, D.sigma_b * ub - ux, fin);
   // ---- the reductions: one OR (flags, and the two finiteness tests as
   //      bits), two fixed-order sums
   constexpr int kBitInput = 1 << 28, kBitOutput = 1 << 29;
-  fl = pt::block_or<kFinW>(fl | (fin_in ? 0 : kBitInput) | (fin ? 0 : kBitOutput), ired);
-  zz = pt::block_sum<kFinW>(zz, red);
-  ch = pt::block_sum<kFinW>(ch, red);
+  {
+    // all three in one pass: wave reductions, one barrier, then the waves'
+    // values in wave order (the same sums as pt::block_sum)
+    int f = pt::wave_or(fl | (fin_in ? 0 : kBitInput) | (fin ? 0 : kBitOutput));
+    const double z = pt::wave_sum(zz), h = pt::wave_sum(ch);
+    const int w = t >> 6;
+    if ((t & 63) == 0) {
+      ired[w] = f;
+      red[w] = z;
+      red2[w] = h;
+    }
+    __syncthreads();
+    f = ired[0];
+    zz = red[0];
+    ch = red2[0];
+#pragma unroll
+    for (int i = 1; i < kFinW; ++i) {
+      f |= ired[i];
+      zz += red[i];
+      ch += red2[i];
+    }
+    fl = f;
+  }
 
   // ---- per-chain condition, in the order: prior box, non-finite input,
   //      CW coalescence, phi not positive definite, non-finite output
