@@ -115,8 +115,24 @@ __global__ __launch_bounds__(kHmcT) void k_hmc_end(int d, double eps, const doub
   const uint64_t jj = traj[0];      // trajectory number; traj[1] = first of this run
   const uint32_t j = (uint32_t)jj;
   const size_t off = (size_t)c * d;
-  // kB elements per thread per batch, their loads issued together
-  constexpr int kB = 8;
+  // the accept test's inputs other than the kinetic energy, on thread 0
+  // before the sum (its loads and the uniform draw overlap the loop)
+  int st_c = 0;
+  double lp_c = 0.0, lp0_c = 0.0, H0 = 0.0, log_u = 0.0;
+  if (threadIdx.x == 0) {
+    st_c = status[c];
+    lp_c = logp[c];
+    double kin0 = 0.0;
+    for (int g = 0; g < pt::kHmcBeginG; ++g) kin0 += h0[(size_t)c * pt::kHmcBeginG + g];
+    lp0_c = lp0[c];
+    H0 = -lp0_c + kin0;
+    uint32_t ctr[4] = {0u, (uint32_t)c, j, 1u};
+    philox10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
+    log_u = log((u53(ctr[0], ctr[1]) + 1.0) * 0x1.0p-53);
+  }
+  // kB elements per thread per batch, their loads issued together (one
+  // pass up to 12288 parameters)
+  constexpr int kB = 12;
   double kin = 0.0;
   for (int i0 = threadIdx.x; i0 < d; i0 += kHmcT * kB) {
     double pv[kB], gv[kB], iv[kB];
@@ -137,18 +153,12 @@ __global__ __launch_bounds__(kHmcT) void k_hmc_end(int d, double eps, const doub
   }
   kin = pt::block_sum<kHmcW>(kin, red);
   if (threadIdx.x == 0) {
-    if (n_invalid && status[c] != 0) n_invalid[c] += 1;
-    const double H1 = -logp[c] + kin;
-    double kin0 = 0.0;
-    for (int g = 0; g < pt::kHmcBeginG; ++g) kin0 += h0[(size_t)c * pt::kHmcBeginG + g];
-    const double H0 = -lp0[c] + kin0;
-    uint32_t ctr[4] = {0u, (uint32_t)c, j, 1u};
-    philox10(ctr, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const double u = (u53(ctr[0], ctr[1]) + 1.0) * 0x1.0p-53;
-    const int a = (isfinite(H1) && log(u) < H0 - H1) ? 1 : 0;
+    if (n_invalid && st_c != 0) n_invalid[c] += 1;
+    const double H1 = -lp_c + kin;
+    const int a = (isfinite(H1) && log_u < H0 - H1) ? 1 : 0;
     acc_s = a;
     if (a) n_accept[c] += 1;
-    else logp[c] = lp0[c];
+    else logp[c] = lp0_c;
   }
   __syncthreads();
   const int a = acc_s;
