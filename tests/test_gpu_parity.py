@@ -181,8 +181,10 @@ def test_tunings(api, tuning):
     check(ds, X, run(api, ds, X, tuning=tuning))
 
 
-@pytest.mark.parametrize("n_chains", [1, 15, 17, 33])
+@pytest.mark.parametrize("n_chains", [1, 15, 17, 33, 256])
 def test_chain_counts(api, n_chains):
+    # (256: the dense problems outnumber the compute units, and the
+    # diagonal-frequency work runs one segment per block of 16 chains)
     ds = synth.cfg1()
     X = near(ds, n_chains, 21)
     check(ds, X, run(api, ds, X))
