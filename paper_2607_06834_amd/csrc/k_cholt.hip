@@ -127,13 +127,28 @@ __host__ __device__ constexpr int tidx(int I, int J) { return I * (I + 1) / 2 + 
 constexpr int kProbPerGroup = 4;
 
 // Work of the extra workgroups: G = nb * ns workgroups (spec_groups) for nb
-// blocks of 16 chains and ns contiguous frequency segments.
+// blocks of 16 chains and ns contiguous frequency segments.  The forward's
+// items cost about the same whatever parts they carry, so its segments hold
+// equal numbers of frequencies; the adjoint's segments are balanced by cost,
+// a frequency costing one unit per part it carries (diagonal red noise, DM).
 struct spec_split {
-  int G, nb, ns, kmax;
-  __device__ spec_split(const Dev &D, int groups, int chains)
+  int G, nb, ns, kmax, nf_gw, ka, nf_dm;
+  bool by_cost;
+  __device__ spec_split(const Dev &D, int groups, int chains, bool balanced)
       : G(groups), nb((chains + pt::kCB - 1) / pt::kCB), ns(max(1, groups / nb)),
-        kmax(max(D.ka, D.nf_dm)) {}
-  __device__ int k_lo(int s) const { return kmax * s / ns; }
+        kmax(max(D.ka, D.nf_dm)), nf_gw(D.nf_gw), ka(D.ka), nf_dm(D.nf_dm), by_cost(balanced) {}
+  __device__ int cost(int k) const { return (k >= nf_gw && k < ka ? 1 : 0) + (k < nf_dm ? 1 : 0); }
+  // first frequency of segment s (every segment keeps at least one: ns <= kmax)
+  __device__ int k_lo(int s) const {
+    if (s <= 0) return 0;
+    if (s >= ns) return kmax;
+    if (!by_cost) return kmax * s / ns;
+    int total = 0;
+    for (int k = 0; k < kmax; ++k) total += cost(k);
+    int run = 0, k = 0;
+    while (k < kmax && (long long)run * ns < (long long)total * s) run += cost(k++);
+    return min(max(k, s), kmax - (ns - s));
+  }
 };
 
 __device__ inline int pi16(int c) { return 4 * (c & 3) + (c >> 2); }
@@ -145,7 +160,7 @@ template <int NT>
 __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const double *__restrict__ x,
                                                                   int n_dense_groups) {
   if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies
-    const spec_split sp(D, gridDim.x - n_dense_groups, D.c_pad);
+    const spec_split sp(D, gridDim.x - n_dense_groups, D.c_pad, false);
     for (int it = blockIdx.x - n_dense_groups; it < sp.nb * sp.ns; it += sp.G) {
       const int b = it / sp.ns, s = it - b * sp.ns;
       pt::spec_fwd_cb(D, x, b * pt::kCB, sp.k_lo(s), sp.k_lo(s + 1), s);
@@ -404,7 +419,7 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
   constexpr bool COLW = NT > pt::kTileMaxNT;
   constexpr int PPG = bwd_probs<NT>();
   if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies
-    const spec_split sp(D, gridDim.x - n_dense_groups, D.n_chains);
+    const spec_split sp(D, gridDim.x - n_dense_groups, D.n_chains, true);
     for (int it = blockIdx.x - n_dense_groups; it < sp.nb * sp.ns; it += sp.G) {
       const int b = it / sp.ns, s = it - b * sp.ns;
       pt::spec_bwd_cb(D, x, grad, b * pt::kCB, sp.k_lo(s), sp.k_lo(s + 1), s, sp.ns);
