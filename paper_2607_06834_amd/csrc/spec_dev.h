@@ -408,17 +408,38 @@ __device__ inline void spec_fwd_cb(const Dev &D, const double *__restrict__ x, i
     const int nk = k_hi - k_lo;
     const int K2 = 2 * D.ka, K2d = 2 * D.nf_dm;
     const int total = nk * n * kCB;
+    // a thread's items are 256 apart: item it = idx / 16 steps by 16, i.e.
+    // the pulsar by q16 and the frequency by r16 (with carry), so a batch
+    // needs one division
+    const int q16 = nk > 0 ? 16 / nk : 0, r16 = 16 - q16 * nk;
+    const int cc = tid & (kCB - 1);   // the same chain for all of a thread's items
+    const bool bad_c = (badm >> cc) & 1;
+    const double *xc = row(cc);
     for (int base = tid; base < total; base += 256 * kSpecBatch) {
       double ra[kSpecBatch], rg[kSpecBatch], zs[kSpecBatch], zc[kSpecBatch];
       double da[kSpecBatch], dg[kSpecBatch], ws[kSpecBatch], wc[kSpecBatch];
+      int Ib[kSpecBatch], kb_[kSpecBatch];
+      {
+        const int it0 = base / kCB;
+        int I = it0 / nk, kk = it0 - I * nk;
+#pragma unroll
+        for (int b = 0; b < kSpecBatch; ++b) {
+          Ib[b] = I;
+          kb_[b] = k_lo + kk;
+          I += q16;
+          kk += r16;
+          if (kk >= nk) {
+            kk -= nk;
+            ++I;
+          }
+        }
+      }
 #pragma unroll
       for (int b = 0; b < kSpecBatch; ++b) {
         const int idx = base + 256 * b;
         ra[b] = rg[b] = zs[b] = zc[b] = da[b] = dg[b] = ws[b] = wc[b] = 0.0;
-        const int cc = idx & (kCB - 1), it = idx / kCB;
-        if (idx < total && !((badm >> cc) & 1)) {
-          const int I = it / nk, k0 = k_lo + (it - I * nk);
-          const double *xc = row(cc);
+        if (idx < total && !bad_c) {
+          const int I = Ib[b], k0 = kb_[b];
           if (k0 >= D.nf_gw && k0 < D.ka) {
             if (k0 < D.nf_rn) {
               ra[b] = xc[D.off_rn + 2 * I];
@@ -439,9 +460,8 @@ __device__ inline void spec_fwd_cb(const Dev &D, const double *__restrict__ x, i
       for (int b = 0; b < kSpecBatch; ++b) {
         const int idx = base + 256 * b;
         if (idx >= total) continue;
-        const int cc = idx & (kCB - 1), it = idx / kCB, c = c0 + cc;
-        const int I = it / nk, k0 = k_lo + (it - I * nk);
-        const bool bad = (badm >> cc) & 1;
+        const int c = c0 + cc, I = Ib[b], k0 = kb_[b];
+        const bool bad = bad_c;
         const int rs = harm_row(k0 + 1, 0), rc = harm_row(k0 + 1, 1);
         if (k0 >= D.nf_gw && k0 < D.ka) {
           double vs = 0.0, vc = 0.0;
