@@ -22,6 +22,11 @@ namespace pt {
 // within the 63 loads a wave can have in flight.
 constexpr int kSpecBatch = 6;
 
+// sqrt of a power-law spectrum (powerlaw_sqrt_k) given ln(f_k yr) already loaded
+__device__ inline double powerlaw_sqrt_l(const Dev &D, double lnfy_k, double log10A, double gamma) {
+  return exp(kLn10 * log10A - 0.5 * gamma * lnfy_k + 0.5 * D.pl_c);
+}
+
 // Forward of chain c (< c_pad) over the diagonal and DM frequencies
 // k = k_first, k_first + k_step, ...; segment 0 also does the per-chain work
 // (status of the prior box and the CW check, CW constants, timing-model
@@ -417,7 +422,7 @@ __device__ inline void spec_fwd_cb(const Dev &D, const double *__restrict__ x, i
     const double *xc = row(cc);
     for (int base = tid; base < total; base += 256 * kSpecBatch) {
       double ra[kSpecBatch], rg[kSpecBatch], zs[kSpecBatch], zc[kSpecBatch];
-      double da[kSpecBatch], dg[kSpecBatch], ws[kSpecBatch], wc[kSpecBatch];
+      double da[kSpecBatch], dg[kSpecBatch], ws[kSpecBatch], wc[kSpecBatch], lf[kSpecBatch];
       int Ib[kSpecBatch], kb_[kSpecBatch];
       {
         const int it0 = base / kCB;
@@ -438,6 +443,7 @@ __device__ inline void spec_fwd_cb(const Dev &D, const double *__restrict__ x, i
       for (int b = 0; b < kSpecBatch; ++b) {
         const int idx = base + 256 * b;
         ra[b] = rg[b] = zs[b] = zc[b] = da[b] = dg[b] = ws[b] = wc[b] = 0.0;
+        lf[b] = D.lnfy[kb_[b]];   // the frequency's ln(f yr), with the other inputs
         if (idx < total && !bad_c) {
           const int I = Ib[b], k0 = kb_[b];
           if (k0 >= D.nf_gw && k0 < D.ka) {
@@ -466,7 +472,7 @@ __device__ inline void spec_fwd_cb(const Dev &D, const double *__restrict__ x, i
         if (k0 >= D.nf_gw && k0 < D.ka) {
           double vs = 0.0, vc = 0.0;
           if (!bad) {
-            const double sq = (k0 < D.nf_rn) ? powerlaw_sqrt_k(D, k0, ra[b], rg[b]) : 0.0;
+            const double sq = (k0 < D.nf_rn) ? powerlaw_sqrt_l(D, lf[b], ra[b], rg[b]) : 0.0;
             const double kap = sq * sq;
             if (!(kap > 0.0) || !isfinite(kap)) atomicOr(&kflag[cc][k0], kFlagNotPD);
             vs = sq * zs[b];
@@ -479,7 +485,7 @@ __device__ inline void spec_fwd_cb(const Dev &D, const double *__restrict__ x, i
         if (k0 < D.nf_dm) {
           double vs = 0.0, vc = 0.0;
           if (!bad) {
-            const double sq = powerlaw_sqrt_k(D, k0, da[b], dg[b]);
+            const double sq = powerlaw_sqrt_l(D, lf[b], da[b], dg[b]);
             vs = sq * ws[b];
             vc = sq * wc[b];
             D.sqk_dm[sqk_at(D, c, I, k0)] = sq;
