@@ -111,11 +111,13 @@ __device__ inline void spec_fwd_block(const Dev &D, const double *__restrict__ x
   for (int base = tid; base < total; base += 256 * kSpecBatch) {
     // the inputs of kSpecBatch items first (their loads overlap), then the items
     double ra[kSpecBatch], rg[kSpecBatch], zs[kSpecBatch], zc[kSpecBatch];
-    double da[kSpecBatch], dg[kSpecBatch], ws[kSpecBatch], wc[kSpecBatch];
+    double da[kSpecBatch], dg[kSpecBatch], ws[kSpecBatch], wc[kSpecBatch], lf[kSpecBatch];
 #pragma unroll
     for (int b = 0; b < kSpecBatch; ++b) {
       const int idx = base + 256 * b;
       ra[b] = rg[b] = zs[b] = zc[b] = da[b] = dg[b] = ws[b] = wc[b] = 0.0;
+      // the frequency's ln(f yr), with the other inputs
+      lf[b] = D.lnfy[min(k_first + k_step * ((idx < total ? idx : 0) / n), kmax - 1)];
       if (idx < total && !bad) {
         const int j = idx / n, I = idx - j * n;
         const int k0 = k_first + k_step * j;
@@ -145,7 +147,7 @@ __device__ inline void spec_fwd_block(const Dev &D, const double *__restrict__ x
       if (k0 >= D.nf_gw && k0 < D.ka) {
         double vs = 0.0, vc = 0.0;
         if (!bad) {
-          const double sq = (k0 < D.nf_rn) ? powerlaw_sqrt_k(D, k0, ra[b], rg[b]) : 0.0;
+          const double sq = (k0 < D.nf_rn) ? powerlaw_sqrt_l(D, lf[b], ra[b], rg[b]) : 0.0;
           const double kap = sq * sq;
           if (!(kap > 0.0) || !isfinite(kap)) atomicOr(&kflag[k0], pt::kFlagNotPD);
           vs = sq * zs[b];
@@ -158,7 +160,7 @@ __device__ inline void spec_fwd_block(const Dev &D, const double *__restrict__ x
       if (k0 < D.nf_dm) {
         double vs = 0.0, vc = 0.0;
         if (!bad) {
-          const double sq = powerlaw_sqrt_k(D, k0, da[b], dg[b]);
+          const double sq = powerlaw_sqrt_l(D, lf[b], da[b], dg[b]);
           vs = sq * ws[b];
           vc = sq * wc[b];
           D.sqk_dm[sqk_at(D, c, I, k0)] = sq;
@@ -205,11 +207,14 @@ __device__ inline void spec_bwd_block(const Dev &D, const double *__restrict__ x
     // (sqrt(kappa) as the forward stored it)
     double sr[kSpecBatch], as_[kSpecBatch], ac_[kSpecBatch], zs[kSpecBatch], zc[kSpecBatch];
     double sd[kSpecBatch], bs_[kSpecBatch], bc_[kSpecBatch], ws[kSpecBatch], wc[kSpecBatch];
+    double lf[kSpecBatch];
 #pragma unroll
     for (int b = 0; b < kSpecBatch; ++b) {
       const int idx = base + 256 * b;
       sr[b] = as_[b] = ac_[b] = zs[b] = zc[b] = 0.0;
       sd[b] = bs_[b] = bc_[b] = ws[b] = wc[b] = 0.0;
+      // the frequency's ln(f yr), with the other inputs
+      lf[b] = D.lnfy[min(k_first + k_step * ((idx < total ? idx : 0) / n), kmax - 1)];
       if (idx < total && !skip) {
         const int j = idx / n, I = idx - j * n;
         const int k0 = k_first + k_step * j;
@@ -236,7 +241,7 @@ __device__ inline void spec_bwd_block(const Dev &D, const double *__restrict__ x
       if (idx >= total) continue;
       const int j = idx / n, I = idx - j * n;
       const int k0 = k_first + k_step * j;
-      const double lnfy = D.lnfy[k0];
+      const double lnfy = lf[b];
       if (k0 >= D.nf_gw && k0 < D.ka) {
         double *drn = drn_at(D, c, I, k0);
         double g_s = 0.0, g_c = 0.0, d0 = 0.0, d1 = 0.0;
@@ -545,17 +550,39 @@ __device__ inline void spec_bwd_cb(const Dev &D, const double *__restrict__ x,
   const int nk = k_hi - k_lo;
   const int K2 = 2 * D.ka, K2d = 2 * D.nf_dm;
   const int total = nk * n * kCB;
+  // a thread keeps one chain; its items step by 16 (pulsar by q16, frequency
+  // by r16 with carry), so a batch needs one division
+  const int cc = tid & (kCB - 1), c = c0 + cc;
+  const bool skip_c = (skipm >> cc) & 1;
+  const int q16 = nk > 0 ? 16 / nk : 0, r16 = 16 - q16 * nk;
   for (int base = tid; base < total; base += 256 * kSpecBatch) {
     double sr[kSpecBatch], as_[kSpecBatch], ac_[kSpecBatch], zs[kSpecBatch], zc[kSpecBatch];
     double sd[kSpecBatch], bs_[kSpecBatch], bc_[kSpecBatch], ws[kSpecBatch], wc[kSpecBatch];
+    double lf[kSpecBatch];
+    int Ib[kSpecBatch], kb_[kSpecBatch];
+    {
+      const int it0 = base / kCB;
+      int I = it0 / nk, kk = it0 - I * nk;
+#pragma unroll
+      for (int b = 0; b < kSpecBatch; ++b) {
+        Ib[b] = I;
+        kb_[b] = k_lo + kk;
+        I += q16;
+        kk += r16;
+        if (kk >= nk) {
+          kk -= nk;
+          ++I;
+        }
+      }
+    }
 #pragma unroll
     for (int b = 0; b < kSpecBatch; ++b) {
       const int idx = base + 256 * b;
       sr[b] = as_[b] = ac_[b] = zs[b] = zc[b] = 0.0;
       sd[b] = bs_[b] = bc_[b] = ws[b] = wc[b] = 0.0;
-      const int cc = idx & (kCB - 1), it = idx / kCB, c = c0 + cc;
-      if (idx < total && c < D.n_chains && !((skipm >> cc) & 1)) {
-        const int I = it / nk, k0 = k_lo + (it - I * nk);
+      lf[b] = D.lnfy[kb_[b]];   // the frequency's ln(f yr), with the other inputs
+      if (idx < total && c < D.n_chains && !skip_c) {
+        const int I = Ib[b], k0 = kb_[b];
         const int rs = harm_row(k0 + 1, 0), rc = harm_row(k0 + 1, 1);
         const double *xc = x + (size_t)c * D.d;
         if (k0 >= D.nf_gw && k0 < D.ka) {
@@ -577,11 +604,10 @@ __device__ inline void spec_bwd_cb(const Dev &D, const double *__restrict__ x,
 #pragma unroll
     for (int b = 0; b < kSpecBatch; ++b) {
       const int idx = base + 256 * b;
-      const int cc = idx & (kCB - 1), it = idx / kCB, c = c0 + cc;
       if (idx >= total || c >= D.n_chains) continue;
-      const bool skip = (skipm >> cc) & 1;
-      const int I = it / nk, k0 = k_lo + (it - I * nk);
-      const double lnfy = D.lnfy[k0];
+      const bool skip = skip_c;
+      const int I = Ib[b], k0 = kb_[b];
+      const double lnfy = lf[b];
       double *gc = grad + (size_t)c * D.d;
       bool fin = true;
       if (k0 >= D.nf_gw && k0 < D.ka) {
