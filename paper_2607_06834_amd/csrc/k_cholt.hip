@@ -477,6 +477,7 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
                                       : 0.0;
   }
   const double rho_o = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
+  const double lnfy = D.lnfy[k0];   // for the outputs (loaded here, not after the barriers)
   const double *Cb = lst + ((size_t)c * D.nf_gw + k0) * (NTILE * 256);
 
   // ---- v_c = C^T abar_c: lane (c16, q) sums rows 16K + 4q + v of column
@@ -735,7 +736,6 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
   for (int o = 32; o > 0; o >>= 1) dr += __shfl_xor(dr, o, 64);
 
   // ---- outputs
-  const double lnfy = D.lnfy[k0];
   bool fin = true;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
