@@ -127,11 +127,22 @@ void build_chunks(ptafs_dataset *ds, std::vector<int32_t> &tab) {
   tab.insert(tab.end(), first.begin(), first.end());
 }
 
+// A captured trajectory graph holds the addresses of the chunk table, the
+// workspace and the HMC buffer in its kernel arguments: it is dropped whenever
+// one of them is freed (after a device synchronisation, so it is not running).
+void drop_graph(ptafs_dataset *ds) {
+  if (ds->gexec) (void)hipGraphExecDestroy(ds->gexec);
+  if (ds->graph) (void)hipGraphDestroy(ds->graph);
+  ds->gexec = nullptr;
+  ds->graph = nullptr;
+}
+
 int ensure_chunks(ptafs_dataset *ds) {
   if (!ds->chunks_dirty) return PTAFS_OK;
   std::vector<int32_t> tab;
   build_chunks(ds, tab);
   PT_TRY(hipDeviceSynchronize());
+  drop_graph(ds);
   if (ds->d_chunk) PT_TRY(hipFree(ds->d_chunk));
   ds->d_chunk = nullptr;
   if (hipMalloc(&ds->d_chunk, tab.size() * sizeof(int32_t)) != hipSuccess) return PTAFS_E_NOMEM;
@@ -151,6 +162,7 @@ int ensure_ws(ptafs_dataset *ds, int n_chains) {
   const WsLayout L = ws_layout(ds->base, cpad_of(n_chains), ds->n_chunks);
   if (L.total <= ds->ws_bytes) return PTAFS_OK;
   PT_TRY(hipDeviceSynchronize());
+  drop_graph(ds);
   if (ds->ws) PT_TRY(hipFree(ds->ws));
   ds->ws = nullptr;
   ds->ws_bytes = 0;
@@ -682,10 +694,7 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   const size_t need = hmc_bytes_of(ds->base, n_chains);
   if (need > ds->hmc_bytes) {
     PT_TRY(hipDeviceSynchronize());
-    if (ds->gexec) (void)hipGraphExecDestroy(ds->gexec);
-    if (ds->graph) (void)hipGraphDestroy(ds->graph);
-    ds->gexec = nullptr;
-    ds->graph = nullptr;
+    drop_graph(ds);
     if (ds->hmc) PT_TRY(hipFree(ds->hmc));
     ds->hmc = nullptr;
     ds->hmc_bytes = 0;

@@ -81,6 +81,40 @@ def test_hmc_graph_replay_equals_eager(api):
         np.testing.assert_array_equal(u, v)
 
 
+def test_hmc_graph_dropped_when_tuning_round_trips(api):
+    """A tuning change rebuilds the chunk table that a captured trajectory
+    graph reads: after 1 -> 2 -> 1 tiles per chunk, with every buffer of the
+    call unchanged, the graph is captured again and its trajectories equal the
+    eager ones at the same tuning."""
+    ds = small_ds(6)
+    th = synth.injected_theta(ds, 9, rn=(-14.0, 3.5), dm=(-14.0, 3.5))
+    X0 = torch.tensor(synth.random_points(ds, 16, 10, theta=th, theta_jitter=0.2), device="cuda")
+    g = api.Dataset(ds)
+    x = X0.clone()
+    lp = torch.empty(16, dtype=torch.float64, device="cuda")
+    gr = torch.empty_like(x)
+    st = torch.empty(16, dtype=torch.int32, device="cuda")
+    acc = torch.zeros(16, dtype=torch.int64, device="cuda")
+
+    def run(use_graph):
+        x.copy_(X0)
+        acc.zero_()
+        g.ptafs_logp_grad(x, out=(lp, gr, st))
+        g.ptafs_hmc_run(x, lp, gr, acc, n_traj=3, n_leapfrog=4, eps=0.03, seed=77, use_graph=use_graph)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), lp.cpu().numpy(), gr.cpu().numpy(), acc.cpu().numpy()
+
+    g.ptafs_set_tuning(1, 1, 1)
+    run(True)
+    g.ptafs_set_tuning(2, 1, 1)
+    g.ptafs_set_tuning(1, 1, 1)
+    a = run(True)
+    b = run(False)
+    g.close()
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
 def test_hmc_linear_gaussian_moments(api):
     """Hyper-parameters frozen (inverse mass 0): the coefficients (u, z, z_dm)
     have the closed-form Gaussian posterior of the dense time-domain model."""
