@@ -11,6 +11,8 @@
 // over 16-TOA x 16-chain tiles; the basis is generated in registers from one
 // sincos per TOA and an angle-addition step, and transposed through LDS for
 // the adjoint.  The plain form is a vector-ALU kernel launched per pulsar.
+#include <type_traits>
+
 #include "common.h"
 #include "cw_dev.h"
 
@@ -166,29 +168,40 @@ void k_toa_mfma(Dev D, int xcd_map) {
     // waves per SIMD the others' loads, LDS and vector work then fill the
     // matrix core's gaps instead of delaying this chain
     __builtin_amdgcn_s_setprio(1);
+    auto steps = [&](auto all_harmonic) {
+      // ALL: every lane group is on a harmonic in every step but the last
 #pragma unroll
-    for (int m = 0; m < NSR / 2; ++m) {
-      double fa, fb;
-      if (4 * m + 3 < kb) {            // every lane group on a harmonic (uniform branch)
-        fa = sh;
-        fb = ch;
-      } else {                         // harmonic, timing-model column (1, tau, tau^2) or zero
-        const int h = 4 * m + q;
-        const double ta = (h == kb) ? 1.0 : ((h == kb + 1) ? tv * tv : 0.0);
-        const double tb2 = (h == kb) ? tv : 0.0;
-        fa = (h < kb) ? sh : ta;
-        fb = (h < kb) ? ch : tb2;
+      for (int m = 0; m < NSR / 2; ++m) {
+        constexpr bool ALL = decltype(all_harmonic)::value;
+        double fa, fb;
+        if ((ALL && m < NSR / 2 - 1) || (!ALL && 4 * m + 3 < kb)) {
+          fa = sh;
+          fb = ch;
+        } else {                       // harmonic, timing-model column (1, tau, tau^2) or zero
+          const int h = 4 * m + q;
+          const double ta = (h == kb) ? 1.0 : ((h == kb + 1) ? tv * tv : 0.0);
+          const double tb2 = (h == kb) ? tv : 0.0;
+          fa = (h < kb) ? sh : ta;
+          fb = (h < kb) ? ch : tb2;
+        }
+        ft[col * FS + 8 * m + q] = fa;
+        ft[col * FS + 8 * m + 4 + q] = fb;
+        const double sn = sh * c4 + ch * s4;
+        ch = ch * c4 - sh * s4;
+        sh = sn;
+        rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, crs(2 * m), rr, 0, 0, 0);
+        if (2 * m < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, cds(2 * m), rd, 0, 0, 0);
+        rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, crs(2 * m + 1), rr, 0, 0, 0);
+        if (2 * m + 1 < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, cds(2 * m + 1), rd, 0, 0, 0);
       }
-      ft[col * FS + 8 * m + q] = fa;
-      ft[col * FS + 8 * m + 4 + q] = fb;
-      const double sn = sh * c4 + ch * s4;
-      ch = ch * c4 - sh * s4;
-      sh = sn;
-      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, crs(2 * m), rr, 0, 0, 0);
-      if (2 * m < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, cds(2 * m), rd, 0, 0, 0);
-      rr = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, crs(2 * m + 1), rr, 0, 0, 0);
-      if (2 * m + 1 < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, cds(2 * m + 1), rd, 0, 0, 0);
-    }
+    };
+    // In the usual case (kb >= 2 NSR - 4) the forward is one branch-free block,
+    // so the compiler schedules the panel loads and the recurrence across steps;
+    // with a branch per step it could not.
+    if (4 * (NSR / 2 - 2) + 3 < kb)
+      steps(std::true_type{});
+    else
+      steps(std::false_type{});
     __builtin_amdgcn_s_setprio(0);
     wave_sync();
     // ---- residuals: lane (col, q) holds TOAs base + q + 4v, chain col
