@@ -156,10 +156,15 @@ void k_toa_mfma(Dev D, int xcd_map) {
     }
     // ---- forward layout: lane (col, q) walks harmonics q+1, q+5, ... of TOA base + col
     const double s2 = 2.0 * s1 * c1, c2 = (c1 - s1) * (c1 + s1);
-    const double s3 = s2 * c1 + c2 * s1, c3 = c2 * c1 - s2 * s1;
     const double s4 = 2.0 * s2 * c2, c4 = (c2 - s2) * (c2 + s2);
-    double sh = q == 0 ? s1 : (q == 1 ? s2 : (q == 2 ? s3 : s4));
-    double ch = q == 0 ? c1 : (q == 1 ? c2 : (q == 2 ? c3 : c4));
+    // harmonic q + 1 as base (0 or 2) plus step (1 or 2), both chosen by
+    // selects: a divergent branch here would split the tile's code into
+    // blocks the compiler schedules separately
+    const bool upper = q >= 2, even_q = (q & 1) == 0;
+    const double bs = upper ? s2 : 0.0, bc = upper ? c2 : 1.0;
+    const double ss = even_q ? s1 : s2, sc = even_q ? c1 : c2;
+    double sh = bs * sc + bc * ss;
+    double ch = bc * sc - bs * ss;
     // ---- forward contraction R = F A, R_dm = F A_dm (16 TOA x 16 chains),
     //      each k-step issued as soon as its basis pair exists
     v4d rr = v4d{0.0, 0.0, 0.0, 0.0};
