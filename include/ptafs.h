@@ -188,7 +188,10 @@ int ptafs_get_tuning(const ptafs_dataset *ds, int32_t *tiles_per_chunk, int32_t 
  *   samples      device [n_traj][n_chains][d] or NULL: state after each trajectory
  *   n_invalid    device [n_chains] int64 or NULL: incremented for every leapfrog
  *                evaluation of the chain that returned a nonzero status
- * use_graph: 1 captures one trajectory as a HIP graph and replays it.
+ * use_graph: 1 captures one trajectory as a HIP graph and replays it.  The
+ *   graph is kept for later calls with the same arguments (chain count, leapfrog
+ *   count, eps, seed, buffers, tuning) and dropped whenever the data set frees
+ *   memory it reads (a tuning change, workspace or HMC-buffer growth).
  */
 int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n_leapfrog,
                   double eps, const double *inv_mass, uint64_t seed, uint64_t traj0, double *x,
