@@ -234,8 +234,9 @@ _CFG2_REF = {}
 
 
 # launch configurations the autotuner picks for the benchmark: 16-tile chunks,
-# one round of one-wave workgroups, four-wave workgroups sharing the panels
-@pytest.mark.parametrize("tuning", [(16, 1, 1), (33, 1, 0), (96, 4, 1)])
+# one round of one-wave workgroups (with and without the XCD-aware map),
+# four-wave workgroups sharing the panels
+@pytest.mark.parametrize("tuning", [(16, 1, 1), (33, 1, 1), (33, 1, 0), (96, 4, 1)])
 def test_cfg2_full_size_sampled(api, tuning):
     """The 67-pulsar, 250k-TOA workload with 64 chains in the launch
     configurations the benchmark times; the oracle checks a sample of chains."""
