@@ -173,13 +173,14 @@ void k_toa_mfma(Dev D, int xcd_map) {
     // waves per SIMD the others' loads, LDS and vector work then fill the
     // matrix core's gaps instead of delaying this chain
     __builtin_amdgcn_s_setprio(1);
-    auto steps = [&](auto all_harmonic) {
-      // ALL: every lane group is on a harmonic in every step but the last
+    auto steps = [&](auto tail) {
+      // the last TAIL steps may hold timing-model or zero columns, the others
+      // hold harmonics in every lane group (TAIL 0: decided step by step)
 #pragma unroll
       for (int m = 0; m < NSR / 2; ++m) {
-        constexpr bool ALL = decltype(all_harmonic)::value;
+        constexpr int TAIL = decltype(tail)::value;
         double fa, fb;
-        if ((ALL && m < NSR / 2 - 1) || (!ALL && 4 * m + 3 < kb)) {
+        if ((TAIL > 0 && m < NSR / 2 - TAIL) || (TAIL == 0 && 4 * m + 3 < kb)) {
           fa = sh;
           fb = ch;
         } else {                       // harmonic, timing-model column (1, tau, tau^2) or zero
@@ -200,13 +201,19 @@ void k_toa_mfma(Dev D, int xcd_map) {
         if (2 * m + 1 < NSD) rd = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, cds(2 * m + 1), rd, 0, 0, 0);
       }
     };
-    // In the usual case (kb >= 2 NSR - 4) the forward is one branch-free block,
-    // so the compiler schedules the panel loads and the recurrence across steps;
-    // with a branch per step it could not.
-    if (4 * (NSR / 2 - 2) + 3 < kb)
-      steps(std::true_type{});
+    // The first kb / 4 steps hold harmonics only.  With NSR = 4 ceil((kb + 2) / 8)
+    // the rest is one to three steps, so the forward is always one branch-free
+    // block, which lets the compiler schedule the panel loads and the
+    // recurrence across steps (a branch per step keeps it from doing so).
+    const int tail = NSR / 2 - kb / 4;
+    if (tail == 1)
+      steps(std::integral_constant<int, 1>{});
+    else if (tail == 2)
+      steps(std::integral_constant<int, 2>{});
+    else if (tail == 3)
+      steps(std::integral_constant<int, 3>{});
     else
-      steps(std::false_type{});
+      steps(std::integral_constant<int, 0>{});
     __builtin_amdgcn_s_setprio(0);
     wave_sync();
     // ---- residuals: lane (col, q) holds TOAs base + q + 4v, chain col
