@@ -51,6 +51,10 @@ def test_funnel_standardized_moments():
     assert abs(vch.mean() - cf["funnel_var_y"]) < 5 * vch.std() / np.sqrt(C)
     xch = x.mean(axis=(0, 2))
     assert abs(xch.mean() - cf["funnel_mean_x"]) < 5 * xch.std() / np.sqrt(C)
+    # Var x_i = E[e^y] + Var(y^2) = e^(9/2) + 162: heavy-tailed (e^y), so the
+    # per-chain estimates scatter widely; the bound uses their own spread
+    vx = ((x - x.mean()) ** 2).mean(axis=(0, 2))
+    assert abs(vx.mean() - cf["funnel_var_x"]) < 5 * vx.std() / np.sqrt(C)
 
 
 def test_linear_gaussian_moments():
@@ -70,17 +74,18 @@ def test_linear_gaussian_moments():
         return o["logp"], o["grad"]
 
     C = 48
-    rng = np.random.default_rng(5)
     x0 = np.zeros((C, lay.d))
     x0[:, : lay.n_theta] = theta
-    # start at stationarity (draws from the exact joint posterior)
-    x0[:, lay.u:] = m + rng.standard_normal((C, m.size)) @ np.linalg.cholesky(S).T
-    _, _, _, nacc, samp = hmc.run(lpg, x0, n_traj=120, n_leapfrog=16, eps=0.08, seed=99,
+    # every chain starts at the prior mean u = z = z_dm = 0, away from the
+    # posterior mean m: the moments below test convergence to N(m, S), not
+    # only that the sampler keeps a distribution it starts in
+    n_traj, burn = 200, 40
+    _, _, _, nacc, samp = hmc.run(lpg, x0, n_traj=n_traj, n_leapfrog=16, eps=0.08, seed=99,
                                   inv_mass=inv_mass, keep_samples=True)
     # frozen coordinates never move
     assert np.all(samp[:, :, : lay.n_theta] == theta)
-    samp = samp[10:, :, lay.u:]
-    assert nacc.mean() / 120 > 0.7
+    samp = samp[burn:, :, lay.u:]
+    assert nacc.mean() / n_traj > 0.7
     chm = samp.mean(0)                                   # (C, dw)
     zsc = (chm.mean(0) - m) / (chm.std(0) / np.sqrt(C))
     assert np.max(np.abs(zsc)) < 5.0, np.max(np.abs(zsc))

@@ -427,3 +427,121 @@ def test_momentum_normals_distribution():
     n = philox.momentum_normals(1234, 3, 7, 200001)
     assert abs(n.mean()) < 0.01 and abs(n.var() - 1.0) < 0.01
     assert np.all(np.isfinite(n))
+
+
+# ------------------------------------------------- basis and DM weight -----
+
+def _golden_basis():
+    rows, chi2 = [], None
+    for line in open(os.path.join(GOLD, "basis_rows.txt")):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "row":
+            v = [float(s) for s in f[1:]]
+            rows.append((int(v[0]), np.array(v[1:5]), np.array(v[5:9]), np.array(v[9:12])))
+        elif f[0] == "chi2_forward":
+            chi2 = float(f[1])
+    return rows, chi2
+
+
+def _basis_ds(dt):
+    """One pulsar, TOAs at T/8, T/4, 3T/8 (the hand-derived data set of
+    tests/golden/basis_rows.txt)."""
+    T = 10.0 * synth.YEAR_S
+    lo, hi = synth.theta_box(1, 2, 0, 2, False)
+    return dict(n_psr=1, toa_offsets=np.array([0, 3]), t=np.array([T / 8, T / 4, 3 * T / 8]),
+                dt=np.asarray(dt, np.float64), sigma=np.full(3, 1e-6), nu=np.full(3, 1e9),
+                backend=np.zeros(3, np.int32), n_backend=1, efac=np.array([1.0]),
+                equad=np.array([0.0]), psr_pos=np.array([[0.0, 0.0, 1.0]]), tspan=T,
+                nf_rn=2, nf_gw=0, nf_dm=2, dm_scale=1.4e9 ** 2, sigma_b=1e-5, has_cw=0,
+                prior_lo=lo, prior_hi=hi)
+
+
+def test_basis_rows_golden():
+    """Sec. III.C (Eqs. Fourier_series, RN=Fa, F_DM) and Eq. TM=Me: the basis
+    rows the likelihood uses at three hand-placed TOAs, read off the gradient
+    at a = 0 with a one-TOA residual (derivation in the golden file).  A
+    cos-before-sin column order, a k = 0..K-1 grid, a shifted time origin,
+    a wrong DM weight or a wrong tau normalisation all fail here."""
+    rows, _ = _golden_basis()
+    rho1 = _closed()["sqrt_rho1_m14_g4_T10yr"]
+    for j, gz, gzdm, gu in rows:
+        dt = np.zeros(3)
+        dt[j] = 1e-12                                        # = N_j
+        ds = _basis_ds(dt)
+        prep = model.Prepared(ds)
+        lay = prep.lay
+        x = np.zeros(lay.d)
+        x[lay.rn:lay.rn + 2] = [-14.0, 4.0]
+        x[lay.dm:lay.dm + 2] = [-14.0, 4.0]
+        g = model.logp_grad(prep, x)["grad"][0]
+        np.testing.assert_allclose(g[lay.z:lay.z + 4] / rho1, gz, rtol=2e-6, atol=1e-12)
+        np.testing.assert_allclose(g[lay.zdm:lay.zdm + 4] / rho1, gzdm, rtol=2e-6, atol=1e-12)
+        np.testing.assert_allclose(g[lay.u:lay.u + 3] / ds["sigma_b"], gu, rtol=1e-12, atol=1e-12)
+
+
+def test_basis_forward_golden():
+    """The forward residual with a single nonzero coefficient a_(2,sin) =
+    1e-6 s: chi^2 = 2 by hand (golden file); log p is then the a = 0 normal
+    constants plus -chi^2/2."""
+    _, chi2 = _golden_basis()
+    ds = _basis_ds(np.zeros(3))
+    prep = model.Prepared(ds)
+    lay = prep.lay
+    x = np.zeros(lay.d)
+    x[lay.rn:lay.rn + 2] = [-14.0, 4.0]
+    x[lay.dm:lay.dm + 2] = [-14.0, 4.0]
+    sq2 = _closed()["sqrt_rho1_m14_g4_T10yr"] / 4.0          # sqrt(kappa_2) = sqrt(kappa_1)/4
+    x[lay.z + 2] = 1e-6 / sq2
+    lp = model.logp_grad(prep, x)["logp"][0]
+    const = -0.5 * 3 * np.log(2 * np.pi * 1e-12)
+    prior = -0.5 * x[lay.z + 2] ** 2 - 0.5 * (lay.d - lay.u) * np.log(2 * np.pi) \
+        - np.sum(np.log(ds["prior_hi"] - ds["prior_lo"]))
+    assert lp - const - prior == pytest.approx(-0.5 * chi2, rel=5e-6)
+
+
+# ------------------------------------------------- CW antenna pattern ------
+
+def test_cw_antenna_identity():
+    """Sec. III.D (Earth term): with m, n and Omega = -s_hat orthonormal,
+    F+^2 + Fx^2 = ((m.p)^2 + (n.p)^2)^2 / (4 (1 + Omega.p)^2)
+    = (1 - (Omega.p)^2)^2 / (4 (1 + Omega.p)^2) = (1 + s_hat.p)^2 / 4.
+    A sign error in the 1 + Omega.p denominator (or in Omega) breaks it; the
+    pattern vanishes for a pulsar at p = Omega."""
+    rng = np.random.default_rng(17)
+    for _ in range(200):
+        p = rng.standard_normal(3)
+        p /= np.linalg.norm(p)
+        cth, phi = rng.uniform(-1, 1), rng.uniform(0, 2 * np.pi)
+        sth = np.sqrt(1 - cth * cth)
+        s = np.array([sth * np.cos(phi), sth * np.sin(phi), cth])
+        fp, fx, _ = ocw.antenna(p, cth, phi)
+        assert fp * fp + fx * fx == pytest.approx(0.25 * (1.0 + s @ p) ** 2, rel=1e-11, abs=1e-15)
+        fp0, fx0, _ = ocw.antenna(-s, cth, phi)                # pulsar at p = Omega
+        assert abs(fp0) < 1e-15 and abs(fx0) < 1e-15
+
+
+def test_cw_face_on_amplitude():
+    """Face-on source (cos iota = 1): the two polarisations are in quadrature
+    with equal amplitude 2 alpha, so as the reference phase Phi0 varies the
+    delay at t = 0 is a sinusoid of amplitude 2 alpha sqrt(F+^2 + Fx^2) =
+    alpha (1 + s_hat.p), with alpha = h / (2 w0) at t = 0 (w(0) = w0)."""
+    rng = np.random.default_rng(23)
+    p = rng.standard_normal(3)
+    p /= np.linalg.norm(p)
+    th = np.array([0.2, 2.0, 9.0, -8.0, 0.0, 1.0, 0.4, -13.0])
+    sth = np.sqrt(1 - th[0] ** 2)
+    s = np.array([sth * np.cos(th[1]), sth * np.sin(th[1]), th[0]])
+    w0 = np.pi * 10 ** th[3]
+    amp = 10 ** th[7] / (2 * w0) * (1 + s @ p)
+    def h0(ph):
+        th[4] = ph
+        return ocw.delay(np.array([0.0]), p, th, False)[0][0]
+
+    # a phase shift of pi/4 in Phi0 turns 2 Phi by pi/2: the pair is in
+    # quadrature, so h(Phi0)^2 + h(Phi0 + pi/4)^2 is the squared amplitude
+    for ph in np.linspace(0, np.pi, 13):
+        assert np.hypot(h0(ph), h0(ph + np.pi / 4)) == pytest.approx(amp, rel=1e-12)
+    vals = np.abs([h0(ph) for ph in np.linspace(0, np.pi, 721)])
+    assert vals.max() == pytest.approx(amp, rel=1e-5)
