@@ -88,12 +88,13 @@ def cpu_baseline(ds, n_chains_sample=8, min_seconds=10.0, seed=204):
 
 
 def serving_bench(n_traj, rates, n_req, n_chains=16, n_leapfrog=20, quantum=10, max_slots=8,
-                  use_graph=True,
-                  budget=None, seed0=501, eps=1e-4):
+                  use_graph=True, budget=None, seed0=501, eps=1e-4):
     """Poisson arrivals of independent data sets (20-120 pulsars, 200-8000
-    TOAs each, 10-30 frequencies, CW with probability 1/2) served with
-    continuous batching; p50/p99 of completion - arrival per rate."""
-    import threading
+    TOAs each, 10-30 frequencies, CW with probability 1/2), each asking for
+    n_traj trajectories of n_chains chains, served with continuous batching.
+    Every request is first run alone on the idle GPU (its service time); then
+    for each rate: p50/p99 of completion - arrival, and p50/p99 of each
+    request's slowdown (its latency over its own alone service time)."""
     import numpy as np
     import synth
     from paper_2607_06834_amd import serve
@@ -134,27 +135,99 @@ def serving_bench(n_traj, rates, n_req, n_chains=16, n_leapfrog=20, quantum=10, 
         t_last = max(r["t_done"] for r in res)
         bad = sum(int(r["n_invalid"].sum()) for r in res)
         acc = sum(int(r["n_accept"].sum()) for r in res) / (n_chains * n_traj * len(res))
-        return dict(rate=rate, completed=len(res), p50_ms=float(np.percentile(lat, 50) * 1e3),
-                    p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
-                    evals_per_s=evals_per_req * len(res) / (t_last - t_first),
-                    valid_eval_fraction=1.0 - bad / (evals_per_req * len(res) / 1.0),
-                    accept_rate=acc, **stats)
+        return lat, dict(rate=rate, completed=len(res), p50_ms=float(np.percentile(lat, 50) * 1e3),
+                         p99_ms=float(np.percentile(lat, 99) * 1e3), mean_ms=float(lat.mean() * 1e3),
+                         evals_per_s=evals_per_req * len(res) / (t_last - t_first),
+                         valid_eval_fraction=1.0 - bad / (evals_per_req * len(res)),
+                         accept_rate=acc, **stats)
 
     run(0.0, pool[:1], 1)                  # warm-up (code objects, first graph capture)
-    # service time of a request on an idle GPU (each submitted after the last finished)
-    alone = [run(0.0, [p], 1)["p50_ms"] for p in pool[:6]]
+    # service time of every request on an idle GPU (one request at a time)
+    alone = np.array([run(0.0, [p], 1)[0][0] for p in pool])
+    _log(f"serving: alone service times {np.round(alone * 1e3, 1).tolist()} ms")
     out = []
     for rate in rates:
-        r = run(rate, pool, max_slots)
+        lat, r = run(rate, pool, max_slots)
+        slow = lat / alone
+        r["slowdown_p50"] = float(np.percentile(slow, 50))
+        r["slowdown_p99"] = float(np.percentile(slow, 99))
         out.append(r)
-        _log(f"serving at {rate} req/s: p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms")
-        if r["p50_ms"] > 20 * np.median(alone):
+        _log(f"serving at {rate} req/s: p50 {r['p50_ms']:.1f} ms, p99 {r['p99_ms']:.1f} ms, "
+             f"slowdown p50 {r['slowdown_p50']:.2f} p99 {r['slowdown_p99']:.2f}")
+        if r["p50_ms"] > 20 * np.median(alone) * 1e3:
             break                            # saturated
     return dict(
         requests_per_rate=n_req, n_traj=n_traj, n_leapfrog=n_leapfrog, n_chains=n_chains,
         quantum=quantum, max_slots=max_slots, budget_bytes=budget,
         footprint_bytes_median=int(np.median(fps)), footprint_bytes_max=int(max(fps)),
-        alone_ms_median=float(np.median(alone)), rates=out)
+        alone_ms_median=float(np.median(alone) * 1e3), alone_ms_p99=float(np.percentile(alone, 99) * 1e3),
+        alone_ms=[round(float(a) * 1e3, 2) for a in alone], rates=out)
+
+
+def cfg4_bench(n_chains=256, n_leapfrog=20, n_traj=10, n_plain=20):
+    """The 3-pulsar, 1500-TOA array (config 1) with 256 chains: batched form
+    (ragged MFMA TOA pass, HIP-graph trajectories) against the plain form
+    (one TOA-pass launch per pulsar, vector ALU, each evaluation launched from
+    Python); both checked against the oracle on a sample of chains first."""
+    import numpy as np
+    import torch
+    import synth
+    from oracle import model
+    from paper_2607_06834_amd import api
+
+    ds = synth.cfg1()
+    th = synth.injected_theta(ds, 403, rn=(-14.0, 4.0))
+    X0 = synth.random_points(ds, n_chains, 404, theta=th, theta_jitter=0.1)
+    g = api.Dataset(ds)
+    x = torch.tensor(X0, device="cuda")
+    lp_b, gr_b, st_b = g.ptafs_logp_grad(x)
+    lp_p, gr_p, st_p = g.ptafs_logp_grad_plain(x)
+    idx = np.arange(0, n_chains, 37)
+    ref = model.logp_grad(model.Prepared(ds), X0[idx])
+    for lp, gr in ((lp_b, gr_b), (lp_p, gr_p)):
+        lpn, grn = lp.cpu().numpy()[idx], gr.cpu().numpy()[idx]
+        assert np.all(np.abs(lpn - ref["logp"]) <= 1e-9 * np.abs(ref["logp"]))
+        assert np.all(np.abs(grn - ref["grad"]) <= 1e-7 * np.maximum(np.abs(ref["grad"]), ref["scale"]))
+    lay = model.Prepared(ds).lay
+    im = torch.ones(g.d, dtype=torch.float64, device="cuda")
+    im[: lay.n_theta] = 1e-4
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        lp, gr, _ = g.ptafs_logp_grad(x, stream=stream)
+        acc = torch.zeros(n_chains, dtype=torch.int64, device="cuda")
+        g.ptafs_hmc_run(x, lp, gr, acc, n_traj=2, n_leapfrog=n_leapfrog, eps=0.01, seed=403,
+                        inv_mass=im, stream=stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        g.ptafs_hmc_run(x, lp, gr, acc, n_traj=n_traj, n_leapfrog=n_leapfrog, eps=0.01, seed=403,
+                        traj0=2, inv_mass=im, stream=stream)
+        stream.synchronize()
+        el_b = time.perf_counter() - t0
+        out = (torch.empty_like(lp), torch.empty_like(gr), torch.empty(n_chains, dtype=torch.int32,
+                                                                        device="cuda"))
+        for _ in range(3):
+            g.ptafs_logp_grad_plain(x, out=out, stream=stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_plain):
+            g.ptafs_logp_grad_plain(x, out=out, stream=stream)
+        stream.synchronize()
+        el_p = time.perf_counter() - t0
+        for _ in range(3):
+            g.ptafs_logp_grad(x, out=out, stream=stream)
+        stream.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n_plain):
+            g.ptafs_logp_grad(x, out=out, stream=stream)
+        stream.synchronize()
+        el_e = time.perf_counter() - t0
+    g.close()
+    batched = n_chains * n_leapfrog * n_traj / el_b
+    plain = n_chains * n_plain / el_p
+    return dict(workload="3 psr / 1500 TOA (config 1), 256 chains, leapfrog 20",
+                batched_graph_evals_per_s=batched, batched_eager_evals_per_s=n_chains * n_plain / el_e,
+                plain_evals_per_s=plain, batched_over_plain=batched / plain,
+                parity_checked_chains=int(idx.size))
 
 
 def main():
@@ -175,7 +248,8 @@ def main():
     ap.add_argument("--profile-evals", type=int, default=0,
                     help="only run this many batched evaluations (for profiler passes)")
     ap.add_argument("--serve-full", action="store_true",
-                    help="500 trajectories per request, rates 0.25..8 req/s (long)")
+                    help="16 requests per rate over 0.25..8 req/s (long)")
+    ap.add_argument("--no-cfg4", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -266,12 +340,18 @@ def main():
     _log("stages and plain form done")
     cpu = None if args.no_cpu else cpu_baseline(ds, min_seconds=args.cpu_seconds)
     _log("cpu baseline done")
+    cfg4 = None
+    if not args.no_cfg4:
+        cfg4 = cfg4_bench()
+        _log(f"config 4: batched {cfg4['batched_graph_evals_per_s']:.0f} vs plain "
+             f"{cfg4['plain_evals_per_s']:.0f} grad evals/s")
     serving = None
     if not args.no_serve:
+        # config 5: 500 trajectories x 16 chains per request
         if args.serve_full:
-            serving = serving_bench(500, (0.25, 0.5, 1, 2, 4, 8), 48)
+            serving = serving_bench(500, (0.25, 0.5, 1, 2, 4, 8), 16)
         else:
-            serving = serving_bench(20, (4, 16, 64), 32)
+            serving = serving_bench(500, (0.25, 1, 4), 8)
 
     out = {
         "metric": "grad evals/s, 67 psr/250k TOA FP64: batched vs plain; serve p50/p99 latency",
@@ -312,6 +392,7 @@ def main():
         "accept_rate": float(acc.sum().item()) / (C * args.steps),
         "valid_eval_fraction": valid,
         "cpu_baseline": cpu,
+        "cfg4": cfg4,
         "serving": serving,
     }
     if tune_log is not None:

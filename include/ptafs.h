@@ -35,7 +35,10 @@
  *     (hipStream_t passed as void*, NULL = default stream) and the calls return
  *     without synchronising, except where stated.
  *   - Threading: a dataset may be used by one stream at a time (its workspace
- *     is shared by all its calls).
+ *     is shared by all its calls).  Each call is ordered after the data set's
+ *     previous call even when that one ran on another stream (an event the
+ *     library records at the end of every call).  No call synchronises the
+ *     whole device.
  */
 #ifndef PTAFS_H
 #define PTAFS_H
@@ -118,11 +121,15 @@ typedef struct {
 } ptafs_layout_info;
 
 /* Copy a data set to the current HIP device and prepare it (per-pulsar tau
- * centring, HD matrix of Eq. HD, backend table).  Synchronises `stream`.
- * On success *out owns device memory until ptafs_dataset_destroy. */
+ * centring, HD matrix of Eq. HD, backend table).  Synchronises `stream` (and
+ * only it).  On success *out owns device memory until ptafs_dataset_destroy.
+ * Device memory of data sets comes from a stream-ordered pool the library
+ * keeps per device: blocks released by destroyed data sets are reused. */
 int ptafs_dataset_create(const ptafs_dataset_desc *desc, void *stream, ptafs_dataset **out);
 
-/* Release a data set and its workspace (synchronises the device). NULL is a no-op. */
+/* Release a data set and its workspace.  Waits on the host for the data set's
+ * own last enqueued work (not for other streams) and returns the memory to the
+ * library's pool in stream order.  NULL is a no-op. */
 void ptafs_dataset_destroy(ptafs_dataset *ds);
 
 /* Layout of the parameter vector and memory needs for n_chains (>= 0). */
@@ -134,9 +141,9 @@ int ptafs_layout(const ptafs_dataset *ds, int32_t n_chains, ptafs_layout_info *o
  * by memory footprint.  Chunking assumes the default tuning. */
 int ptafs_estimate(const ptafs_dataset_desc *desc, int32_t n_chains, ptafs_layout_info *out);
 
-/* Grow the data set's workspace to serve up to n_chains per call
- * (synchronises the device when it allocates).  Calls with more chains than
- * reserved grow it themselves. */
+/* Grow the data set's workspace to serve up to n_chains per call, on the
+ * library's stream after the data set's previous work (no synchronisation).
+ * Calls with more chains than reserved grow it themselves, on their stream. */
 int ptafs_reserve(ptafs_dataset *ds, int32_t n_chains);
 
 /*
@@ -166,7 +173,9 @@ int ptafs_logp_grad_plain(ptafs_dataset *ds, int32_t n_chains, const double *x, 
  * Tuning of the batched TOA pass.  tiles_per_chunk: 16-TOA tiles a workgroup
  * covers (ragged pulsars are cut into chunks of this many tiles);
  * waves_per_block: 1, 2 or 4 waves splitting a chunk; xcd_map: 1 places the
- * chain blocks of one chunk on the same XCD.  Takes effect on the next call.
+ * chain blocks of one chunk on the same XCD.  Takes effect on the next call; a
+ * new chunk length waits on the host for the data set's own previous work and
+ * rebuilds the chunk table on the library's stream.
  */
 int ptafs_set_tuning(ptafs_dataset *ds, int32_t tiles_per_chunk, int32_t waves_per_block,
                      int32_t xcd_map);

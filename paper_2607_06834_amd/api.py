@@ -13,6 +13,14 @@ import torch
 from . import _lib
 
 
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+
 def _ptr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
 
@@ -119,22 +127,44 @@ class Dataset:
                    "ptafs_get_tuning")
         return a.value, b.value, c.value
 
-    def _check_x(self, x):
+    def _check_x(self, x, inplace=False):
+        """x as the library reads it.  A non-contiguous x is copied for
+        read-only calls; calls that update x in place refuse it (the update
+        would land in the copy)."""
         if not (isinstance(x, torch.Tensor) and x.dtype == torch.float64 and x.is_cuda):
             raise TypeError("x must be a float64 CUDA tensor")
         if x.dim() != 2 or x.shape[1] != self.d:
             raise ValueError(f"x must have shape (n_chains, {self.d})")
-        return x.contiguous()
+        if not x.is_contiguous():
+            if inplace:
+                raise ValueError("x is updated in place and must be contiguous")
+            x = x.contiguous()
+        return x
+
+    @staticmethod
+    def _check_out(t, dtype, shape, name):
+        if not (isinstance(t, torch.Tensor) and t.dtype == dtype and t.is_cuda
+                and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape {tuple(shape)}")
 
     def _call(self, fn, x, out=None, stream=None):
         x = self._check_x(x)
         n = x.shape[0]
         if out is None:
-            logp = torch.empty(n, dtype=torch.float64, device=x.device)
-            grad = torch.empty_like(x)
-            status = torch.empty(n, dtype=torch.int32, device=x.device)
+            # outputs (and the copy of a non-contiguous x) belong to the launch
+            # stream, so the caching allocator does not hand them out again
+            # while that stream still writes them
+            if stream is not None:
+                x.record_stream(stream)
+            with torch.cuda.stream(stream) if stream is not None else _nullctx():
+                logp = torch.empty(n, dtype=torch.float64, device=x.device)
+                grad = torch.empty_like(x)
+                status = torch.empty(n, dtype=torch.int32, device=x.device)
         else:
             logp, grad, status = out
+            self._check_out(logp, torch.float64, (n,), "logp")
+            self._check_out(grad, torch.float64, (n, self.d), "grad")
+            self._check_out(status, torch.int32, (n,), "status")
         _lib.check(fn(self._h, n, C.c_void_p(x.data_ptr()), C.c_void_p(logp.data_ptr()),
                       C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()),
                       _stream_handle(stream)), fn.__name__)
@@ -151,7 +181,8 @@ class Dataset:
     STAGES = ("spec_fwd", "toa", "reduce", "spec_bwd", "finalize")
 
     def ptafs_profile_stages(self, x, reps=10, plain=False, stream=None):
-        """Mean ms per pipeline stage over ``reps`` evaluations (HIP events)."""
+        """Mean ms per pipeline stage over ``reps`` evaluations (HIP events;
+        synchronises the stream, so its temporaries are idle on return)."""
         x = self._check_x(x)
         n = x.shape[0]
         logp = torch.empty(n, dtype=torch.float64, device=x.device)
@@ -169,18 +200,20 @@ class Dataset:
         """Fixed-step HMC in place on (x, logp, grad); n_accept int64 [C];
         n_invalid (int64 [C], optional) counts leapfrog evaluations with a
         nonzero status."""
-        x = self._check_x(x)
+        x = self._check_x(x, inplace=True)
         n = x.shape[0]
-        for t in (logp, grad):
-            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
-        assert n_accept.dtype == torch.int64 and n_accept.is_cuda
+        self._check_out(logp, torch.float64, (n,), "logp")
+        self._check_out(grad, torch.float64, (n, self.d), "grad")
+        self._check_out(n_accept, torch.int64, (n,), "n_accept")
+        if inv_mass is not None:
+            self._check_out(inv_mass, torch.float64, (self.d,), "inv_mass")
+        if n_invalid is not None:
+            self._check_out(n_invalid, torch.int64, (n,), "n_invalid")
+        if samples is not None:
+            self._check_out(samples, torch.float64, (n_traj, n, self.d), "samples")
         im = C.c_void_p(inv_mass.data_ptr()) if inv_mass is not None else C.c_void_p()
         sm = C.c_void_p(samples.data_ptr()) if samples is not None else C.c_void_p()
         nv = C.c_void_p(n_invalid.data_ptr()) if n_invalid is not None else C.c_void_p()
-        if n_invalid is not None:
-            assert n_invalid.dtype == torch.int64 and n_invalid.is_cuda
-        if samples is not None:
-            assert samples.shape == (n_traj, n, self.d) and samples.dtype == torch.float64
         _lib.check(_lib.load().ptafs_hmc_run(
             self._h, n, int(n_traj), int(n_leapfrog), float(eps), im, C.c_uint64(seed),
             C.c_uint64(traj0), C.c_void_p(x.data_ptr()), C.c_void_p(logp.data_ptr()),

@@ -43,6 +43,18 @@ def round_fitting_tpcs(toa_offsets, n_chains, n_cu, wpb=1, rounds=(1, 2), waves_
 _cache: dict = {}
 
 
+def serving_tuning(toa_offsets, n_chains, n_cu):
+    """TOA-pass tuning of a served request as a fixed function of its shape
+    (no timing, so the choice, and with it the reduction order and the
+    request's bits, cannot depend on what else runs on the device): one-wave
+    workgroups, XCD-aware placement, and the chunk length at which the
+    request's waves fill one round of the device at two waves per SIMD (the
+    one-wave form's occupancy), kept between 4 and 32 tiles."""
+    fit = round_fitting_tpcs(toa_offsets, n_chains, n_cu, wpb=1, rounds=(1,), waves_per_simd=(2,))
+    tpc = fit[0] if fit else 32
+    return (int(min(32, max(4, tpc))), 1, 1)
+
+
 def shape_key(ds, n_chains):
     lay = ds.layout
     return (int(lay.n_psr), int(lay.n_toa), int(lay.k_coef), int(lay.k_dm), int(lay.d),

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -11,16 +12,26 @@
 
 constexpr int kDefaultTilesPerChunk = 16;
 
+// Device memory of a data set comes from a library-owned stream-ordered pool
+// (one per device) and goes back to it with hipFreeAsync: neither allocation
+// nor release synchronises the device, so data sets created and destroyed on
+// their own streams do not stall the work of other streams.  Every call
+// orders itself after the data set's previous work (an event recorded at the
+// end of each call) and host waits are on that event only.
 struct ptafs_dataset {
   int device = 0;
   pt::Dev base{};
   std::vector<int64_t> off;
   std::vector<void *> allocs;
   size_t ds_bytes = 0;
+  hipMemPool_t pool = nullptr;
+  hipStream_t aux = nullptr;          // library stream of the device (tuning changes, release)
+  hipEvent_t done = nullptr;          // recorded after the data set's last enqueued work
   // tuning and chunk table of the TOA pass
   int tiles_per_chunk = kDefaultTilesPerChunk, wpb = 1, xcd_map = 1;
   bool chunks_dirty = true;
   int32_t *d_chunk = nullptr;
+  std::vector<int32_t> chunk_host;    // source of the last chunk-table upload
   std::vector<int> psr_nchunks;
   int n_chunks = 0;
   // workspace
@@ -52,7 +63,69 @@ namespace {
     if (e_ != hipSuccess) return PTAFS_E_HIP;         \
   } while (0)
 
+#define PT_RC(expr)                                   \
+  do {                                                \
+    const int r_ = (expr);                            \
+    if (r_) return r_;                                \
+  } while (0)
+
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// One pool and one library stream per device, created on first use and kept
+// until the process ends.  Freed blocks stay in the pool (no release
+// threshold), so the next data set reuses them without a runtime allocation.
+struct DevRes {
+  hipMemPool_t pool = nullptr;
+  hipStream_t aux = nullptr;
+};
+std::mutex g_res_mu;
+std::map<int, DevRes> g_res;
+
+int device_res(int dev, DevRes *out) {
+  std::lock_guard<std::mutex> lk(g_res_mu);
+  auto it = g_res.find(dev);
+  if (it != g_res.end()) {
+    *out = it->second;
+    return PTAFS_OK;
+  }
+  DevRes r;
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  PT_TRY(hipMemPoolCreate(&r.pool, &props));
+  uint64_t keep = UINT64_MAX;
+  PT_TRY(hipMemPoolSetAttribute(r.pool, hipMemPoolAttrReleaseThreshold, &keep));
+  PT_TRY(hipStreamCreateWithFlags(&r.aux, hipStreamNonBlocking));
+  g_res[dev] = r;
+  *out = r;
+  return PTAFS_OK;
+}
+
+int dalloc(ptafs_dataset *ds, void **p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  if (hipMallocFromPoolAsync(p, std::max<size_t>(bytes, 8), ds->pool, s) != hipSuccess) {
+    *p = nullptr;
+    return PTAFS_E_NOMEM;
+  }
+  return PTAFS_OK;
+}
+
+void dfree(void *p, hipStream_t s) {
+  if (p) (void)hipFreeAsync(p, s);
+}
+
+// Order a call on stream s after the data set's previous work (which may have
+// been enqueued on another stream); mark the end of a call.
+int begin_call(ptafs_dataset *ds, hipStream_t s) {
+  PT_TRY(hipStreamWaitEvent(s, ds->done, 0));
+  return PTAFS_OK;
+}
+int end_call(ptafs_dataset *ds, hipStream_t s) {
+  PT_TRY(hipEventRecord(ds->done, s));
+  return PTAFS_OK;
+}
 
 
 struct WsLayout {
@@ -129,24 +202,37 @@ void build_chunks(ptafs_dataset *ds, std::vector<int32_t> &tab) {
 
 // A captured trajectory graph holds the addresses of the chunk table, the
 // workspace and the HMC buffer in its kernel arguments: it is dropped whenever
-// one of them is freed (after a device synchronisation, so it is not running).
-void drop_graph(ptafs_dataset *ds) {
+// one of them is released.  The host first waits for the data set's own last
+// work (the graph may still be running), never for the whole device.
+int drop_graph(ptafs_dataset *ds) {
+  if (!ds->gexec && !ds->graph) return PTAFS_OK;
+  PT_TRY(hipEventSynchronize(ds->done));
   if (ds->gexec) (void)hipGraphExecDestroy(ds->gexec);
   if (ds->graph) (void)hipGraphDestroy(ds->graph);
   ds->gexec = nullptr;
   ds->graph = nullptr;
+  return PTAFS_OK;
 }
 
-int ensure_chunks(ptafs_dataset *ds) {
+// (Re)build the chunk table on stream s, ordered after the data set's
+// previous work; the old table goes back to the pool in stream order.
+int ensure_chunks(ptafs_dataset *ds, hipStream_t s) {
   if (!ds->chunks_dirty) return PTAFS_OK;
-  std::vector<int32_t> tab;
-  build_chunks(ds, tab);
-  PT_TRY(hipDeviceSynchronize());
-  drop_graph(ds);
-  if (ds->d_chunk) PT_TRY(hipFree(ds->d_chunk));
+  int rc = drop_graph(ds);
+  if (rc) return rc;
+  // the host table of the previous upload may still be read by that copy
+  PT_TRY(hipEventSynchronize(ds->done));
+  build_chunks(ds, ds->chunk_host);
+  const std::vector<int32_t> &tab = ds->chunk_host;
+  PT_RC(begin_call(ds, s));
+  dfree(ds->d_chunk, s);
   ds->d_chunk = nullptr;
-  if (hipMalloc(&ds->d_chunk, tab.size() * sizeof(int32_t)) != hipSuccess) return PTAFS_E_NOMEM;
-  PT_TRY(hipMemcpy(ds->d_chunk, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  void *p = nullptr;
+  rc = dalloc(ds, &p, tab.size() * sizeof(int32_t), s);
+  if (rc) return rc;
+  ds->d_chunk = static_cast<int32_t *>(p);
+  PT_TRY(hipMemcpyAsync(ds->d_chunk, tab.data(), tab.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  PT_RC(end_call(ds, s));
   const int nc = ds->n_chunks;
   ds->base.n_chunks = nc;
   ds->base.tiles_per_chunk = ds->tiles_per_chunk;
@@ -158,27 +244,29 @@ int ensure_chunks(ptafs_dataset *ds) {
   return PTAFS_OK;
 }
 
-int ensure_ws(ptafs_dataset *ds, int n_chains) {
+// Grow the workspace on stream s (after begin_call on s).
+int ensure_ws(ptafs_dataset *ds, int n_chains, hipStream_t s) {
   const WsLayout L = ws_layout(ds->base, cpad_of(n_chains), ds->n_chunks);
   if (L.total <= ds->ws_bytes) return PTAFS_OK;
-  PT_TRY(hipDeviceSynchronize());
-  drop_graph(ds);
-  if (ds->ws) PT_TRY(hipFree(ds->ws));
+  int rc = drop_graph(ds);
+  if (rc) return rc;
+  dfree(ds->ws, s);
   ds->ws = nullptr;
   ds->ws_bytes = 0;
-  if (hipMalloc(&ds->ws, L.total) != hipSuccess) return PTAFS_E_NOMEM;
-  PT_TRY(hipMemset(ds->ws, 0, L.total));   // keeps the 1/N padding at zero
+  rc = dalloc(ds, &ds->ws, L.total, s);
+  if (rc) return rc;
+  PT_TRY(hipMemsetAsync(ds->ws, 0, L.total, s));   // every region starts at zero
   ds->ws_bytes = L.total;
   return PTAFS_OK;
 }
 
-pt::Dev make_dev(const ptafs_dataset *ds, int n_chains) {
+pt::Dev make_dev(const ptafs_dataset *ds, int n_chains, void *ws) {
   pt::Dev D = ds->base;
   D.n_chains = n_chains;
   D.c_pad = cpad_of(n_chains);
   D.n_cb = D.c_pad / 16;
   const WsLayout L = ws_layout(ds->base, D.c_pad, ds->n_chunks);
-  char *w = static_cast<char *>(ds->ws);
+  char *w = static_cast<char *>(ws);
   D.coef_rn = reinterpret_cast<double *>(w + L.coef_rn);
   D.coef_dm = reinterpret_cast<double *>(w + L.coef_dm);
   D.lstore = reinterpret_cast<double *>(w + L.lstore);
@@ -212,8 +300,9 @@ void set_lds_limits() {
 }
 
 int enqueue_eval(ptafs_dataset *ds, int C, const double *x, double *logp, double *grad,
-                 int32_t *status, hipStream_t s, bool plain, const pt::Kick *kick = nullptr) {
-  const pt::Dev D = make_dev(ds, C);
+                 int32_t *status, hipStream_t s, bool plain, const pt::Kick *kick = nullptr,
+                 void *ws = nullptr) {
+  const pt::Dev D = make_dev(ds, C, ws ? ws : ds->ws);
   PT_TRY(ptk::launch_spectral_fwd(D, x, s));
   if (plain) {
     for (int p = 0; p < D.n_psr; ++p) PT_TRY(ptk::launch_toa_plain_psr(D, p, ds->psr_nchunks[p], s));
@@ -231,37 +320,47 @@ int eval(ptafs_dataset *ds, int C, const double *x, double *logp, double *grad, 
   if (!ds || C < 0) return PTAFS_E_ARG;
   if (C == 0) return PTAFS_OK;
   if (!x || !logp || !grad || !status) return PTAFS_E_ARG;
+  hipStream_t s = (hipStream_t)stream;
   PT_TRY(hipSetDevice(ds->device));
-  int rc = ensure_chunks(ds);
+  int rc = ensure_chunks(ds, s);
   if (rc) return rc;
-  rc = ensure_ws(ds, C);
+  PT_RC(begin_call(ds, s));
+  rc = ensure_ws(ds, C, s);
   if (rc) return rc;
-  return enqueue_eval(ds, C, x, logp, grad, status, (hipStream_t)stream, plain);
+  rc = enqueue_eval(ds, C, x, logp, grad, status, s, plain);
+  if (rc) return rc;
+  return end_call(ds, s);
 }
 
 template <typename T>
-int upload(ptafs_dataset *ds, const T *src, size_t count, const T **dst) {
+int upload(ptafs_dataset *ds, const T *src, size_t count, const T **dst, hipStream_t s) {
   void *p = nullptr;
   const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-  if (hipMalloc(&p, bytes) != hipSuccess) return PTAFS_E_NOMEM;
+  const int rc = dalloc(ds, &p, bytes, s);
+  if (rc) return rc;
   ds->allocs.push_back(p);
   ds->ds_bytes += bytes;
-  if (count) PT_TRY(hipMemcpy(p, src, count * sizeof(T), hipMemcpyHostToDevice));
+  if (count) PT_TRY(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, s));
   *dst = static_cast<const T *>(p);
   return PTAFS_OK;
 }
 
+// Release everything a data set holds: wait for its own last work, then hand
+// the blocks back to the pool on the library stream (no device-wide wait).
 void free_all(ptafs_dataset *ds) {
   if (!ds) return;
   (void)hipSetDevice(ds->device);
-  (void)hipDeviceSynchronize();
+  if (ds->done) (void)hipEventSynchronize(ds->done);
   if (ds->gexec) (void)hipGraphExecDestroy(ds->gexec);
   if (ds->graph) (void)hipGraphDestroy(ds->graph);
   if (ds->cap) (void)hipStreamDestroy(ds->cap);
-  for (void *p : ds->allocs) (void)hipFree(p);
-  if (ds->d_chunk) (void)hipFree(ds->d_chunk);
-  if (ds->ws) (void)hipFree(ds->ws);
-  if (ds->hmc) (void)hipFree(ds->hmc);
+  if (ds->aux) {
+    for (void *p : ds->allocs) dfree(p, ds->aux);
+    dfree(ds->d_chunk, ds->aux);
+    dfree(ds->ws, ds->aux);
+    dfree(ds->hmc, ds->aux);
+  }
+  if (ds->done) (void)hipEventDestroy(ds->done);
   delete ds;
 }
 
@@ -373,7 +472,6 @@ size_t hmc_bytes_of(const pt::Dev &B, int n_chains) {
 
 extern "C" {
 
-
 const char *ptafs_strerror(int code) {
   switch (code) {
     case PTAFS_OK: return "success";
@@ -404,6 +502,17 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
     delete ds;
     return PTAFS_E_HIP;
   }
+  {
+    DevRes res;
+    const int r = device_res(ds->device, &res);
+    if (r || hipEventCreateWithFlags(&ds->done, hipEventDisableTiming) != hipSuccess) {
+      free_all(ds);
+      return r ? r : PTAFS_E_HIP;
+    }
+    ds->pool = res.pool;
+    ds->aux = res.aux;
+  }
+  hipStream_t s = (hipStream_t)stream;
   pt::Dev &B = ds->base;
   B = plan_view;
   if (hipDeviceGetAttribute(&B.n_cu, hipDeviceAttributeMultiprocessorCount, ds->device) != hipSuccess) {
@@ -438,13 +547,13 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
   {
     std::vector<double> Lf((size_t)n * n, 0.0);
     for (int j = 0; j < n; ++j) {
-      double s = gam[(size_t)j * n + j];
-      for (int m = 0; m < j; ++m) s -= Lf[(size_t)j * n + m] * Lf[(size_t)j * n + m];
-      if (!(s > 0.0)) {
-        delete ds;
+      double piv = gam[(size_t)j * n + j];
+      for (int m = 0; m < j; ++m) piv -= Lf[(size_t)j * n + m] * Lf[(size_t)j * n + m];
+      if (!(piv > 0.0)) {
+        free_all(ds);
         return PTAFS_E_ARG;      // Gamma must be positive definite
       }
-      const double ljj = std::sqrt(s);
+      const double ljj = std::sqrt(piv);
       Lf[(size_t)j * n + j] = ljj;
       for (int i = j + 1; i < n; ++i) {
         double t = gam[(size_t)i * n + j];
@@ -477,32 +586,33 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
       lnn += std::log(N);
     }
 
+  // host sources of the asynchronous uploads: alive until the stream is synchronised
+  std::vector<double> gt, ht, lf;
   int rc = PTAFS_OK;
   auto chk = [&](int r) { if (r && !rc) rc = r; };
-  chk(upload(ds, vtt.data(), npad, &B.t));
-  chk(upload(ds, vdt.data(), npad, &B.dt));
-  chk(upload(ds, vs.data(), npad, &B.sth));
-  chk(upload(ds, vc.data(), npad, &B.cth));
-  chk(upload(ds, vt.data(), npad, &B.tau));
-  chk(upload(ds, vw.data(), npad, &B.wdm));
-  chk(upload(ds, vin.data(), npad, &B.invn));
+  chk(upload(ds, vtt.data(), npad, &B.t, s));
+  chk(upload(ds, vdt.data(), npad, &B.dt, s));
+  chk(upload(ds, vs.data(), npad, &B.sth, s));
+  chk(upload(ds, vc.data(), npad, &B.cth, s));
+  chk(upload(ds, vt.data(), npad, &B.tau, s));
+  chk(upload(ds, vw.data(), npad, &B.wdm, s));
+  chk(upload(ds, vin.data(), npad, &B.invn, s));
   B.lnn_total = lnn;
-  chk(upload(ds, d->sigma, ntoa, &B.sigma));
-  chk(upload(ds, d->nu, ntoa, &B.nu));
-  chk(upload(ds, d->backend, ntoa, &B.backend));
-  chk(upload(ds, d->efac, d->n_backend, &B.efac));
-  chk(upload(ds, d->equad, d->n_backend, &B.equad));
-  chk(upload(ds, d->toa_offsets, (size_t)n + 1, &B.toa_off));
-  chk(upload(ds, tc.data(), n, &B.tau_c));
-  chk(upload(ds, tsi.data(), n, &B.tau_sinv));
-  chk(upload(ds, d->psr_pos, (size_t)3 * n, &B.pos));
-  chk(upload(ds, gam.data(), (size_t)n * n, &B.gamma));
-  chk(upload(ds, gch.data(), gch.size(), &B.gchol));
+  chk(upload(ds, d->sigma, ntoa, &B.sigma, s));
+  chk(upload(ds, d->nu, ntoa, &B.nu, s));
+  chk(upload(ds, d->backend, ntoa, &B.backend, s));
+  chk(upload(ds, d->efac, d->n_backend, &B.efac, s));
+  chk(upload(ds, d->equad, d->n_backend, &B.equad, s));
+  chk(upload(ds, d->toa_offsets, (size_t)n + 1, &B.toa_off, s));
+  chk(upload(ds, tc.data(), n, &B.tau_c, s));
+  chk(upload(ds, tsi.data(), n, &B.tau_sinv, s));
+  chk(upload(ds, d->psr_pos, (size_t)3 * n, &B.pos, s));
+  chk(upload(ds, gam.data(), (size_t)n * n, &B.gamma, s));
+  chk(upload(ds, gch.data(), gch.size(), &B.gchol, s));
   {
     // the same factor as 16x16 tiles (tile (K, J) at K (K + 1) / 2 + J, row-major
     // inside), for the matrix-core adjoint of small arrays
     const int nt = pt::chol_tiles(n);
-    std::vector<double> gt;
     if (nt <= pt::kTileFwdMaxNT) {
       gt.assign((size_t)(nt * (nt + 1) / 2) * 256, 0.0);
       for (int K = 0; K < nt; ++K)
@@ -513,8 +623,7 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
               if (r < n && k <= r) gt[(size_t)(K * (K + 1) / 2 + J) * 256 + rr * 16 + cc] = gch[pt::pk(r, k)];
             }
     }
-    chk(upload(ds, gt.data(), gt.size(), &B.gtile));
-    std::vector<double> ht;
+    chk(upload(ds, gt.data(), gt.size(), &B.gtile, s));
     if (nt <= pt::kTileFwdMaxNT) {
       ht.assign((size_t)(nt * (nt + 1) / 2) * 256, 0.0);
       for (int K = 0; K < nt; ++K)
@@ -526,19 +635,23 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
               if (r < n && k < n) ht[(size_t)(K * (K + 1) / 2 + J) * 256 + cc * 16 + rr] = gam[(size_t)r * n + k];
             }
     }
-    chk(upload(ds, ht.data(), ht.size(), &B.gam_tile));
+    chk(upload(ds, ht.data(), ht.size(), &B.gam_tile, s));
   }
   {
     // power-law spectra at f_k = (k + 1) / T in logarithms
-    std::vector<double> lf(PTAFS_MAX_HARM);
+    lf.assign(PTAFS_MAX_HARM, 0.0);
     for (int k = 0; k < PTAFS_MAX_HARM; ++k) lf[k] = std::log((k + 1) / d->tspan * pt::kYear);
-    chk(upload(ds, lf.data(), lf.size(), &B.lnfy));
+    chk(upload(ds, lf.data(), lf.size(), &B.lnfy, s));
     B.pl_c = 3.0 * std::log(pt::kYear) - std::log(12.0 * pt::kPi * pt::kPi) - std::log(d->tspan);
   }
-  chk(upload(ds, d->prior_lo, B.n_theta, &B.prior_lo));
-  chk(upload(ds, d->prior_hi, B.n_theta, &B.prior_hi));
-  if (!rc) rc = ensure_chunks(ds);
-  if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = PTAFS_E_HIP;
+  chk(upload(ds, d->prior_lo, B.n_theta, &B.prior_lo, s));
+  chk(upload(ds, d->prior_hi, B.n_theta, &B.prior_hi, s));
+  if (!rc) rc = end_call(ds, s);
+  if (!rc) rc = ensure_chunks(ds, s);
+  // the host arrays above are the sources of the copies: wait for this
+  // stream (the data set's own work) before they go out of scope, also on
+  // the error path (the blocks go back to the pool only after the copies)
+  if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = PTAFS_E_HIP;
   if (rc) {
     free_all(ds);
     return rc;
@@ -588,9 +701,13 @@ int ptafs_estimate(const ptafs_dataset_desc *desc, int32_t n_chains, ptafs_layou
 int ptafs_reserve(ptafs_dataset *ds, int32_t n_chains) {
   if (!ds || n_chains < 0) return PTAFS_E_ARG;
   PT_TRY(hipSetDevice(ds->device));
-  int rc = ensure_chunks(ds);
+  hipStream_t s = ds->aux;
+  int rc = ensure_chunks(ds, s);
   if (rc) return rc;
-  return ensure_ws(ds, n_chains);
+  PT_RC(begin_call(ds, s));
+  rc = ensure_ws(ds, n_chains, s);
+  if (rc) return rc;
+  return end_call(ds, s);
 }
 
 int ptafs_logp_grad(ptafs_dataset *ds, int32_t n_chains, const double *x, double *logp,
@@ -612,7 +729,7 @@ int ptafs_set_tuning(ptafs_dataset *ds, int32_t tiles_per_chunk, int32_t waves_p
   ds->wpb = waves_per_block;
   ds->xcd_map = xcd_map ? 1 : 0;
   PT_TRY(hipSetDevice(ds->device));
-  return ensure_chunks(ds);
+  return ensure_chunks(ds, ds->aux);
 }
 
 int ptafs_get_tuning(const ptafs_dataset *ds, int32_t *tiles_per_chunk, int32_t *waves_per_block,
@@ -630,11 +747,12 @@ int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, d
   if (!ds || n_chains < 1 || reps < 1 || !ms_out || !x || !logp || !grad || !status) return PTAFS_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   PT_TRY(hipSetDevice(ds->device));
-  int rc = ensure_chunks(ds);
+  int rc = ensure_chunks(ds, s);
   if (rc) return rc;
-  rc = ensure_ws(ds, n_chains);
+  PT_RC(begin_call(ds, s));
+  rc = ensure_ws(ds, n_chains, s);
   if (rc) return rc;
-  const pt::Dev D = make_dev(ds, n_chains);
+  const pt::Dev D = make_dev(ds, n_chains, ds->ws);
   constexpr int kStages = 5;
   hipEvent_t ev[kStages + 1];
   for (auto &e : ev) PT_TRY(hipEventCreate(&e));
@@ -671,6 +789,7 @@ int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, d
   }
   for (auto &e : ev) (void)hipEventDestroy(e);
   for (int i = 0; i < kStages; ++i) ms_out[i] = acc[i] / reps;
+  if (!err) err = end_call(ds, s);
   return err;
 }
 
@@ -683,9 +802,10 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   if (!x || !logp || !grad || !n_accept) return PTAFS_E_ARG;
   hipStream_t s = (hipStream_t)stream;
   PT_TRY(hipSetDevice(ds->device));
-  int rc = ensure_chunks(ds);
+  int rc = ensure_chunks(ds, s);
   if (rc) return rc;
-  rc = ensure_ws(ds, n_chains);
+  PT_RC(begin_call(ds, s));
+  rc = ensure_ws(ds, n_chains, s);
   if (rc) return rc;
   const int d = ds->base.d;
   const size_t cd = (size_t)n_chains * d;
@@ -693,12 +813,13 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   // status [C], trajectory counter
   const size_t need = hmc_bytes_of(ds->base, n_chains);
   if (need > ds->hmc_bytes) {
-    PT_TRY(hipDeviceSynchronize());
-    drop_graph(ds);
-    if (ds->hmc) PT_TRY(hipFree(ds->hmc));
+    rc = drop_graph(ds);
+    if (rc) return rc;
+    dfree(ds->hmc, s);
     ds->hmc = nullptr;
     ds->hmc_bytes = 0;
-    if (hipMalloc(&ds->hmc, need) != hipSuccess) return PTAFS_E_NOMEM;
+    rc = dalloc(ds, &ds->hmc, need, s);
+    if (rc) return rc;
     ds->hmc_bytes = need;
   }
   char *h = static_cast<char *>(ds->hmc);
@@ -716,7 +837,7 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   // (no host memory to keep alive, no synchronisation)
   PT_TRY(ptk::launch_traj_set(traj, traj0, s));
 
-  const pt::Dev D = make_dev(ds, n_chains);
+  const pt::Dev D = make_dev(ds, n_chains, ds->ws);
   auto one_traj = [&](hipStream_t q) -> int {
     PT_TRY(ptk::launch_hmc_begin(D, d, eps, inv_mass, seed, traj, x, logp, grad, p, x0, lp0, g0, h0, q));
     // every evaluation but the last ends with the kick and drift of its chain
@@ -737,7 +858,7 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
       rc = one_traj(s);
       if (rc) return rc;
     }
-    return PTAFS_OK;
+    return end_call(ds, s);
   }
   ptafs_dataset::GraphKey key{};
   std::memset(&key, 0, sizeof(key));
@@ -758,13 +879,10 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
   key.ws = ds->ws;
   key.hmc = ds->hmc;
   if (!ds->gexec || !(key == ds->gkey)) {
-    if (ds->gexec) {
-      PT_TRY(hipStreamSynchronize(s));
-      (void)hipGraphExecDestroy(ds->gexec);
-      (void)hipGraphDestroy(ds->graph);
-      ds->gexec = nullptr;
-      ds->graph = nullptr;
-    }
+    // the previous graph may still run on the stream of an earlier call:
+    // drop_graph waits for the data set's last work before destroying it
+    rc = drop_graph(ds);
+    if (rc) return rc;
     // Capture on a private stream (the caller's may be the null stream, which
     // cannot be captured); the graph is then launched on the caller's stream.
     if (!ds->cap) PT_TRY(hipStreamCreateWithFlags(&ds->cap, hipStreamNonBlocking));
@@ -785,7 +903,7 @@ int ptafs_hmc_run(ptafs_dataset *ds, int32_t n_chains, int32_t n_traj, int32_t n
     ds->gkey = key;
   }
   for (int j = 0; j < n_traj; ++j) PT_TRY(hipGraphLaunch(ds->gexec, s));
-  return PTAFS_OK;
+  return end_call(ds, s);
 }
 
 }  // extern "C"

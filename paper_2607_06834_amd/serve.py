@@ -14,9 +14,17 @@ submission.
 
 Every request's arithmetic depends only on its own data set, start point,
 seed and TOA-pass tuning: its samples are bit-identical whether it runs
-alone or in a mix.  The tuning is fixed by the caller, or picked by the
-autotuner among SERVE_CANDIDATES the first time a data-set shape (pulsars,
-TOAs, basis sizes, chains) is admitted and then reused for that shape.
+alone or in a mix.  The tuning is fixed by the caller, or else a fixed
+function of the request's shape (autotune.serving_tuning), never a timing
+taken under the load of other requests.
+
+Two threads share the work.  The admission thread creates each admitted
+request's data set, workspace and first evaluation on the request's own
+stream; the scheduler thread only collects finished quanta and launches the
+next ones, so admitting or retiring a request never stalls the others (the
+library synchronises nothing device-wide: its memory comes from a
+stream-ordered pool that is reused across requests, and a data set waits
+only for its own work when it is released).
 """
 from __future__ import annotations
 
@@ -29,11 +37,6 @@ import numpy as np
 import torch
 
 from . import api, autotune
-
-# TOA-pass tunings tried for a new request shape: small-chain requests want
-# short chunks, or four-wave workgroups sharing the coefficient panels
-SERVE_CANDIDATES = ((8, 1, 1), (22, 4, 1))
-
 
 class Rejected(RuntimeError):
     """The request can never fit the server's memory budget (or its
@@ -101,7 +104,13 @@ class Server:
         self.max_active = 0
         self._stop = False
         self._err = None
+        self._n_cu = torch.cuda.get_device_properties(self.device).multi_processor_count
+        self._to_admit: collections.deque[_Req] = collections.deque()
+        self._ready: collections.deque[_Req] = collections.deque()
+        self._admitting = 0
         self._thread = threading.Thread(target=self._run, name="ptafs-serve", daemon=True)
+        self._admit_thread = threading.Thread(target=self._admit_loop, name="ptafs-admit", daemon=True)
+        self._admit_thread.start()
         self._thread.start()
 
     # ------------------------------------------------------------------ API
@@ -164,6 +173,7 @@ class Server:
             self._stop = True
             self._lock.notify_all()
         self._thread.join()
+        self._admit_thread.join()
         if self._err is not None:
             raise RuntimeError("server stopped after an error") from self._err
 
@@ -175,28 +185,56 @@ class Server:
 
     # ------------------------------------------------------------ scheduler
     def _admit(self, r: _Req):
+        """Create the request's device state on its own stream (admission
+        thread); the scheduler launches its first quantum once it is ready."""
         r.t_admit = time.perf_counter()
+        torch.cuda.set_device(self.device)
         r.stream = torch.cuda.Stream(device=self.device)
         with torch.cuda.stream(r.stream):
             r.ds = api.Dataset(r.desc, stream=r.stream)
             C, d = r.x0.shape[0], r.ds.d
             if r.x0.shape[1] != d:
                 raise ValueError(f"x0 has {r.x0.shape[1]} columns, the data set needs {d}")
+            tuning = self.tuning if self.tuning is not None else \
+                autotune.serving_tuning(r.ds.toa_offsets, C, self._n_cu)
+            r.ds.ptafs_set_tuning(*tuning)
+            r.tuning = r.ds.ptafs_get_tuning()
             r.ds.ptafs_reserve(C)
             dev = torch.device("cuda", self.device)
             r.x = torch.tensor(r.x0, device=dev)
-            if self.tuning is not None:
-                r.ds.ptafs_set_tuning(*self.tuning)
-            else:
-                autotune.tune(r.ds, r.x, reps=2, candidates=SERVE_CANDIDATES)
-            r.tuning = r.ds.ptafs_get_tuning()
             r.lp, r.gr, _ = r.ds.ptafs_logp_grad(r.x, stream=r.stream)
             r.acc = torch.zeros(C, dtype=torch.int64, device=dev)
             r.bad = torch.zeros(C, dtype=torch.int64, device=dev)
             r.im = None if r.inv_mass is None else torch.tensor(r.inv_mass, device=dev)
             r.smp = torch.empty((self.quantum, C, d), dtype=torch.float64, device=dev)
         r.status = "running"
-        self._launch(r)
+
+    def _admit_loop(self):
+        try:
+            torch.cuda.set_device(self.device)
+            while True:
+                with self._lock:
+                    while not self._to_admit and not self._stop:
+                        self._lock.wait(0.05)
+                    if not self._to_admit and self._stop:
+                        return
+                    r = self._to_admit.popleft()
+                try:
+                    self._admit(r)
+                    with self._lock:
+                        self._ready.append(r)
+                        self._admitting -= 1
+                        self._lock.notify_all()
+                except Exception as e:  # this request only
+                    if r.ds is not None:
+                        r.ds.close()
+                    with self._lock:
+                        self._admitting -= 1
+                    self._release(r, "error", repr(e))
+        except Exception as e:  # a failure of the admission thread itself
+            with self._lock:
+                self._err = e
+                self._lock.notify_all()
 
     def _launch(self, r: _Req):
         q = min(self.quantum, r.n_traj - r.done_traj)
@@ -244,28 +282,31 @@ class Server:
         active: list[_Req] = []
         try:
             while True:
-                # admission (first come first served, by slot and footprint)
-                admit = []
+                # admission (first come first served, by slot and footprint):
+                # the admission thread builds the device state, and the request
+                # joins the active set when it is ready
+                started = []
                 with self._lock:
-                    while self._queue and len(active) + len(admit) < self.max_slots and \
-                            self._used + self._queue[0].footprint <= self.budget:
+                    if self._err is not None:
+                        raise self._err
+                    while self._queue and len(active) + self._admitting + len(self._ready) < self.max_slots \
+                            and self._used + self._queue[0].footprint <= self.budget:
                         r = self._queue.popleft()
                         self._used += r.footprint
                         self.max_used = max(self.max_used, self._used)
-                        admit.append(r)
-                    if not active and not admit:
-                        if self._stop and not self._queue:
+                        self._admitting += 1
+                        self._to_admit.append(r)
+                        self._lock.notify_all()
+                    while self._ready:
+                        started.append(self._ready.popleft())
+                    if not active and not started:
+                        if self._stop and not self._queue and not self._admitting:
                             return
-                        self._lock.wait(0.05)
+                        self._lock.wait(0.002)
                         continue
-                for r in admit:
-                    try:
-                        self._admit(r)
-                        active.append(r)
-                    except Exception as e:  # this request only
-                        if r.ds is not None:
-                            r.ds.close()
-                        self._release(r, "error", repr(e))
+                for r in started:
+                    active.append(r)
+                    self._launch(r)
                 self.max_active = max(self.max_active, len(active))
                 # progress: collect finished quanta, launch the next ones
                 progressed = False
@@ -284,6 +325,7 @@ class Server:
         except Exception as e:  # a failure of the scheduler itself
             with self._lock:
                 self._err = e
-                for r in active + list(self._queue):
+                self._stop = True
+                for r in active + list(self._queue) + list(self._ready):
                     r.status, r.error = "error", repr(e)
                 self._lock.notify_all()

@@ -3,6 +3,7 @@ rounds of the device's wave slots."""
 import numpy as np
 import pytest
 
+import synth
 from paper_2607_06834_amd import autotune
 
 
@@ -41,3 +42,16 @@ def test_round_fitting_benchmark_shape():
     got = autotune.round_fitting_tpcs(ds["toa_offsets"], 64, 256)
     assert 33 in got
     assert waves(ds["toa_offsets"], 64, 33) <= 2048 < waves(ds["toa_offsets"], 64, 32)
+
+
+def test_serving_tuning_is_a_function_of_shape():
+    """The serving tuning is fixed by the request's shape and the device's
+    compute-unit count alone (never timed), so a request gets the same
+    reduction order alone and in any mix."""
+    ds = synth.cfg1()
+    a = autotune.serving_tuning(ds["toa_offsets"], 16, 256)
+    b = autotune.serving_tuning(ds["toa_offsets"], 16, 256)
+    assert a == b and a[1] == 1 and a[2] == 1 and 4 <= a[0] <= 32
+    big = synth.serving_request(505)
+    t = autotune.serving_tuning(big["toa_offsets"], 16, 256)
+    assert 4 <= t[0] <= 32

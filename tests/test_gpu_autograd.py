@@ -33,6 +33,19 @@ def points(ds, n, seed):
     return synth.random_points(ds, n, seed + 1, theta=th, theta_jitter=0.2)
 
 
+def _margins(err, ref):
+    """Achieved gradient error against |g*| and against the magnitude
+    companion S_j; the 1e-7 bar without the floor on the elements that
+    dominate their own sums (|g*| >= S_j / 100)."""
+    g, S = ref["grad"], ref["scale"]
+    dom = (np.abs(g) >= S / 100.0) & (np.abs(g) > 0)
+    nz = np.abs(g) > 0
+    print(f"[margins] |g-g*|/|g*| max {np.max(err[nz] / np.abs(g[nz])):.2e}  "
+          f"|g-g*|/S max {np.max(err[S > 0] / S[S > 0]):.2e}  dominant "
+          f"{int(dom.sum())}/{dom.size} max {np.max(err[dom] / np.abs(g[dom])):.2e}", flush=True)
+    assert np.all(err[dom] <= 1e-7 * np.abs(g[dom]))
+
+
 def test_gradcheck_tiny(api):
     """torch.autograd.gradcheck in FP64 on 2 chains of a 3-pulsar array with
     red noise, DM, the HD common process and a CW."""
@@ -63,7 +76,9 @@ def test_backward_composes(api):
     assert torch.equal(x.grad, w[:, None] * gr2)
     ref = model.logp_grad(model.Prepared(ds), X)
     tol = 1e-7 * np.maximum(np.abs(ref["grad"]), ref["scale"])
-    assert np.all(np.abs(gr2.cpu().numpy() - ref["grad"]) <= tol)
+    err = np.abs(gr2.cpu().numpy() - ref["grad"])
+    assert np.all(err <= tol)
+    _margins(err, ref)
     g.close()
 
 
@@ -101,4 +116,50 @@ def test_finite_differences_cfg3(api):
     err = np.abs(fd - an)
     tol = 1e-5 * np.abs(an) + 1e-12 * np.abs(lp.item()) / H
     assert np.all(err <= tol), (np.array(idx)[err > tol], fd[err > tol], an[err > tol])
+    g.close()
+
+
+def test_finite_differences_cfg3_100_points(api):
+    """Config 3: the gradient behind LogPosterior against central finite
+    differences at h = 1e-6 relative (h_i = 1e-6 max(|x_i|, 1)) on 100
+    points near the injection, every coordinate, all shifted points in one
+    batched call; the same 100 gradients against the oracle at the parity
+    bar.  The finite-difference error is estimated from the h and h/2
+    differences (their disagreement plus the rounding of log p over h)."""
+    ds = synth.cfg3()
+    g = api.Dataset(ds)
+    prep = model.Prepared(ds)
+    d = prep.lay.d
+    X = points(ds, 100, 31)
+    x = torch.tensor(X, device="cuda", requires_grad=True)
+    lp, st = api.LogPosterior.apply(x, g)
+    lp.sum().backward()
+    grad = x.grad.cpu().numpy()
+    lp0 = lp.detach().cpu().numpy()
+    assert torch.all(st == 0)
+    H = 1e-6 * np.maximum(np.abs(X), 1.0)                    # (100, d)
+    steps = np.stack([H, -H, H / 2, -H / 2])                 # (4, 100, d)
+    rows = np.repeat(X[None, :, None, :], 4, axis=0).repeat(d, axis=2)   # (4, 100, d, d)
+    idx = np.arange(d)
+    rows[:, :, idx, idx] += steps
+    with torch.no_grad():
+        lpb, _, stb = g.ptafs_logp_grad(torch.tensor(rows.reshape(-1, d), device="cuda"))
+    assert torch.all(stb == 0)
+    lpb = lpb.cpu().numpy().reshape(4, 100, d)
+    d1 = (lpb[0] - lpb[1]) / (2 * H)
+    d2 = (lpb[2] - lpb[3]) / H
+    est = np.abs(d1 - d2) + 4.0 * np.spacing(np.abs(lp0))[:, None] / H
+    err = np.abs(d2 - grad)
+    tol = 10.0 * est + 1e-6 * np.abs(grad)
+    bad = err > tol
+    print(f"[fd] 100 points x {d} coordinates: max |fd - g|/|g| "
+          f"{np.max(err / np.maximum(np.abs(grad), 1e-300)):.2e}, max err/est {np.max(err / est):.2f}",
+          flush=True)
+    assert not bad.any(), (np.argwhere(bad)[:5], err[bad][:5], tol[bad][:5])
+    ref = model.logp_grad(prep, X)
+    tol_o = 1e-7 * np.maximum(np.abs(ref["grad"]), ref["scale"])
+    err_o = np.abs(grad - ref["grad"])
+    assert np.all(err_o <= tol_o)
+    _margins(err_o, ref)
+    assert np.all(np.abs(lp0 - ref["logp"]) <= 1e-9 * np.abs(ref["logp"]))
     g.close()

@@ -127,19 +127,56 @@ def test_hmc_linear_gaussian_moments(api):
     im = np.zeros(lay.d)
     im[lay.u:] = np.diag(S)
     C = 256
-    rng = np.random.default_rng(5)
     X0 = np.zeros((C, lay.d))
     X0[:, : lay.n_theta] = theta
-    # start at stationarity (draws from the exact joint posterior), so that the
-    # sample moments are unbiased whatever the mixing speed of each direction
-    X0[:, lay.u:] = m + rng.standard_normal((C, m.size)) @ np.linalg.cholesky(S).T
-    x, lp, gr, acc, samp = gpu_hmc(api, ds, X0, n_traj=120, L=16, eps=0.08, seed=99, inv_mass=im)
+    # every chain starts at the prior mean u = z = z_dm = 0, away from the
+    # posterior mean: the moments test convergence, not only invariance
+    n_traj, burn = 200, 40
+    x, lp, gr, acc, samp = gpu_hmc(api, ds, X0, n_traj=n_traj, L=16, eps=0.08, seed=99, inv_mass=im)
     assert np.all(samp[:, :, : lay.n_theta] == theta)
-    samp = samp[10:, :, lay.u:]
-    assert acc.mean() / 120 > 0.7
+    samp = samp[burn:, :, lay.u:]
+    assert acc.mean() / n_traj > 0.7
     chm = samp.mean(0)
     zsc = (chm.mean(0) - m) / (chm.std(0) / np.sqrt(C))
     assert np.max(np.abs(zsc)) < 5.0, np.max(np.abs(zsc))
     var = ((samp - m) ** 2).mean(0)
     zv = (var.mean(0) - np.diag(S)) / (var.std(0) / np.sqrt(C))
     assert np.max(np.abs(zv)) < 5.0, np.max(np.abs(zv))
+
+
+def test_hmc_cfg1_200_trajectories_vs_oracle(api):
+    """Config 1: residuals drawn from the model at the injection (oracle
+    simulator), 200 fixed-step trajectories of 8 chains (leapfrog 10, step
+    0.05 from an oracle pilot over {0.2, 0.1, 0.05, 0.02}, the largest with
+    acceptance >= 0.6), hyper-parameters sampled with a small inverse mass;
+    the GPU sampler against the oracle sampler trajectory by trajectory
+    (App. A: Eqs. Hamiltonian, Gaussian_momentum, HMC_acceptance)."""
+    from oracle import simulate
+    ds0 = synth.cfg1()
+    th = synth.injected_theta(ds0, 103, rn=(-14.0, 4.0))
+    ds = simulate.model_residuals(ds0, th, ds0["draws"])
+    prep = model.Prepared(ds)
+    lay = prep.lay
+    m, Sw = dense.posterior_moments(prep, th)
+    C = 8
+    X0 = synth.random_points(ds, C, 104, theta=th, theta_jitter=0.1)
+    X0[:, lay.u:] = m + np.random.default_rng(105).standard_normal((C, m.size)) * np.sqrt(np.diag(Sw))
+    im = np.ones(lay.d)
+    im[: lay.n_theta] = 0.01
+    im[lay.u:] = np.diag(Sw)
+    n_traj, L, eps = 200, 10, 0.05
+    x, lp, gr, acc, S = gpu_hmc(api, ds, X0, n_traj=n_traj, L=L, eps=eps, seed=103, inv_mass=im)
+
+    def lpg(Xb):
+        o = model.logp_grad(prep, Xb, with_scale=False)
+        return o["logp"], o["grad"]
+
+    ox, olp, ogr, oacc, OS = hmc.run(lpg, X0, n_traj=n_traj, n_leapfrog=L, eps=eps, seed=103,
+                                     inv_mass=im, keep_samples=True)
+    dev = np.abs(S - OS) / (np.abs(OS) + 1e-3)
+    print(f"[hmc cfg1] accepted {acc.sum()}/{C * n_traj}, max sample deviation "
+          f"{dev.max():.2e} (last trajectory {dev[-1].max():.2e})", flush=True)
+    np.testing.assert_array_equal(acc, oacc)
+    assert 0 < acc.sum() < C * n_traj
+    np.testing.assert_allclose(S, OS, rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(lp, olp, rtol=1e-9)
