@@ -162,6 +162,23 @@ int ptafs_logp_grad(ptafs_dataset *ds, int32_t n_chains, const double *x, double
                     double *grad, int32_t *status, void *stream);
 
 /*
+ * ptafs_logp_grad without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, kernels and results (bit-identical to
+ * ptafs_logp_grad at the same tuning); the workspace is a static array of the
+ * library of PTAFS_NOALLOC_SCRATCH_BYTES per device instead of the data set's
+ * own.  Returns PTAFS_E_LIMIT when the workspace for n_chains (the
+ * workspace_bytes of ptafs_layout) exceeds that size.  Every call on a device
+ * shares that device's array, and no region of it needs to start at zero
+ * (each call writes every part it reads), so calls that overlap in time on one
+ * device race: serialise them (one stream, or events).  Makes no hipMalloc,
+ * hipFree or other allocating call and never synchronises.
+ */
+#define PTAFS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int ptafs_logp_grad_noalloc(ptafs_dataset *ds, int32_t n_chains, const double *x, double *logp,
+                            double *grad, int32_t *status, void *stream);
+
+/*
  * Same result through the plain form: one TOA-pass launch per pulsar with a
  * vector-ALU kernel (no matrix cores), everything else as above.  A
  * reference point for the batched form; same arguments and outputs.

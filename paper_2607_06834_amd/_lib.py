@@ -59,7 +59,8 @@ class LayoutInfo(C.Structure):
 EXPORTS = (
     "ptafs_dataset_create", "ptafs_dataset_destroy", "ptafs_layout", "ptafs_estimate",
     "ptafs_reserve",
-    "ptafs_logp_grad", "ptafs_logp_grad_plain", "ptafs_set_tuning", "ptafs_get_tuning",
+    "ptafs_logp_grad", "ptafs_logp_grad_plain", "ptafs_logp_grad_noalloc",
+    "ptafs_set_tuning", "ptafs_get_tuning",
     "ptafs_hmc_run", "ptafs_profile_stages", "ptafs_strerror",
 )
 
@@ -86,7 +87,7 @@ def load():
     lib.ptafs_estimate.restype = C.c_int
     lib.ptafs_reserve.argtypes = [vp, C.c_int32]
     lib.ptafs_reserve.restype = C.c_int
-    for name in ("ptafs_logp_grad", "ptafs_logp_grad_plain"):
+    for name in ("ptafs_logp_grad", "ptafs_logp_grad_plain", "ptafs_logp_grad_noalloc"):
         f = getattr(lib, name)
         f.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp]
         f.restype = C.c_int

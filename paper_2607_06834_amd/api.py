@@ -174,6 +174,11 @@ class Dataset:
         """Batched form: returns (logp [C], grad [C, d], status [C])."""
         return self._call(_lib.load().ptafs_logp_grad, x, out, stream)
 
+    def ptafs_logp_grad_noalloc(self, x, out=None, stream=None):
+        """Batched form on the library's static per-device workspace (no
+        device allocation in the library call); same outputs."""
+        return self._call(_lib.load().ptafs_logp_grad_noalloc, x, out, stream)
+
     def ptafs_logp_grad_plain(self, x, out=None, stream=None):
         """Plain (launch per pulsar, vector ALU) form; same outputs."""
         return self._call(_lib.load().ptafs_logp_grad_plain, x, out, stream)

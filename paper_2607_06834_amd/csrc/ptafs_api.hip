@@ -468,9 +468,53 @@ size_t hmc_bytes_of(const pt::Dev &B, int n_chains) {
          align256((size_t)n_chains * sizeof(int32_t)) + 256;
 }
 
+// Workspace of ptafs_logp_grad_noalloc: one array per device, part of the
+// code object's data (each device that loads the library holds it until the
+// process ends).  Host code never uses the symbol itself as an address: its
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_ptr(int dev, void **out) {
+  if (dev < 0 || dev >= kMaxDevices) return PTAFS_E_LIMIT;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    PT_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));   // the current device is dev
+    if (!p) return PTAFS_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PTAFS_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int ptafs_logp_grad_noalloc(ptafs_dataset *ds, int32_t n_chains, const double *x, double *logp,
+                            double *grad, int32_t *status, void *stream) {
+  if (!ds || n_chains < 0) return PTAFS_E_ARG;
+  if (n_chains == 0) return PTAFS_OK;
+  if (!x || !logp || !grad || !status) return PTAFS_E_ARG;
+  // the chunk table is built by ptafs_dataset_create and ptafs_set_tuning;
+  // rebuilding it here would allocate
+  if (ds->chunks_dirty) return PTAFS_E_ARG;
+  const WsLayout L = ws_layout(ds->base, cpad_of(n_chains), ds->n_chunks);
+  if (L.total > kScratchBytes) return PTAFS_E_LIMIT;
+  hipStream_t s = (hipStream_t)stream;
+  PT_TRY(hipSetDevice(ds->device));
+  void *ws = nullptr;
+  PT_RC(scratch_ptr(ds->device, &ws));
+  PT_RC(begin_call(ds, s));
+  PT_RC(enqueue_eval(ds, n_chains, x, logp, grad, status, s, false, nullptr, ws));
+  return end_call(ds, s);
+}
+
 
 const char *ptafs_strerror(int code) {
   switch (code) {
