@@ -18,5 +18,10 @@ dense   structurally different forms used as pins: the Gram (compressed)
         Gaussian marginal, the dense-phi whitened-prior identity.
 philox  Philox4x32-10 counter-based generator (Salmon et al., SC'11).
 hmc     fixed-step leapfrog HMC with Metropolis-Hastings accept (App. A).
+std     the paper's standardized posterior: timing model marginalised
+        (Eq. Gmatrix_proj), CURN standardizing transform a = a_hat + L z
+        (Eqs. PTA_standard_transform_curn, standardized_stochastic_posterior),
+        tempered likelihood (App. B), power-law or free spectra; PyTorch CPU
+        FP64 with autograd for the gradient.
 simulate  residuals drawn from the model (for tests that want them).
 """

@@ -1,0 +1,303 @@
+"""Oracle: the paper's standardized posterior (CURN standardizing transform)
+with the timing model marginalised (FP64, PyTorch on the CPU).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+What is computed, per parameter vector x = [theta | z] (Sec. IV.B):
+
+  timing model  N~^-1 = G (G^T N G)^-1 G^T with G an orthonormal basis of the
+                complement of the timing-model columns (Eq. Gmatrix_proj; G
+                from the QR decomposition of M, the paper's alternative).
+                M is the stored design matrix of the pulsar, or [1, tau, tau^2];
+                linearly dependent columns are dropped by a column-pivoted QR.
+  likelihood    log L(a) = -1/2 (dt - T a)^T N~^-1 (dt - T a)
+                           - 1/2 ln det(2 pi G^T N G)
+                per pulsar, T = [F, w F_dm] (Eqs. likelihood, raw_posterior,
+                with every constant kept), written in the Gram form of
+                Eq. posterior_implemented:
+                -1/2 c + a^T d - 1/2 a^T S0 a - 1/2 ln det(2 pi G^T N G),
+                S0 = T^T N~^-1 T, d = T^T N~^-1 dt, c = dt^T N~^-1 dt.
+  prior         a ~ N(0, phi), phi per frequency rho_k Gamma + diag kappa_.k
+                (Eqs. prior_cov, HD, power_law), DM diagonal kappa_dm.
+  CURN factor   phi_CURN,I = diag(rho_k + kappa_Ik, ..., kappa_dm,Ik, ...)
+                Sigma_I = (beta S0_I + phi_CURN,I^-1)^-1, L_I = chol(Sigma_I)
+                (lower Cholesky factor), a_hat_I = beta Sigma_I d_I
+                (Eqs. PTA_standard_transform_curn, and mv_normal_post_temp of
+                App. B for the tempered likelihood p(dt|a)^beta).
+  transform     a_I = a_hat_I + L_I z_I
+  density       log p~ = beta log L(a) + log N(a; 0, phi) + sum_I ln det L_I
+                         + log pi(theta)
+                (Eq. standardized_stochastic_posterior with the Jacobian and
+                the constants the paper drops put back).
+
+Spectra are the power law of Eq. power_law (theta = log10 A, gamma per
+process) or the free spectrum of Sec. IV.A (theta = log10 rho_k per
+frequency, rho_k = 10^theta_k in s^2).  Uniform hyper-priors.
+
+The gradient is PyTorch autograd of this plain definition (library
+Cholesky, inverse and triangular solves), so it needs no hand derivation.
+Per-chain conditions: 1 outside the prior box or non-finite theta,
+2 a factorisation fails (not positive definite), 4 non-finite z or result.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import torch
+
+from .model import YR, hd_matrix
+
+LN2PI = float(np.log(2.0 * np.pi))
+ST_OK, ST_PRIOR, ST_NOTPD, ST_NONFINITE = 0, 1, 2, 4
+
+
+class StdLayout:
+    """[theta | z]: theta = [gw | rn per pulsar | dm per pulsar], each process
+    2 entries (power law: log10 A, gamma) or one per frequency (free
+    spectrum: log10 rho_k); z per pulsar: 2 Ka entries (k = 1 sin, k = 1 cos,
+    ...) for the red/common block, then 2 Kdm for DM."""
+
+    def __init__(self, n_psr, nf_rn, nf_gw, nf_dm, free):
+        self.n_psr, self.nf_rn, self.nf_gw, self.nf_dm, self.free = n_psr, nf_rn, nf_gw, nf_dm, free
+        self.Ka = max(nf_rn, nf_gw)
+        self.Kdm = nf_dm
+        self.P = 2 * self.Ka + 2 * self.Kdm
+        w = (lambda k: k) if free else (lambda k: 2)
+        o = 0
+        self.gw = o; o += w(nf_gw) if nf_gw > 0 else 0
+        self.rn = o; o += n_psr * w(nf_rn) if nf_rn > 0 else 0
+        self.dm = o; o += n_psr * w(nf_dm) if nf_dm > 0 else 0
+        self.n_theta = o
+        self.z = o; o += n_psr * self.P
+        self.d = o
+        self.w_gw = w(nf_gw) if nf_gw > 0 else 0
+        self.w_rn = w(nf_rn) if nf_rn > 0 else 0
+        self.w_dm = w(nf_dm) if nf_dm > 0 else 0
+
+
+def _rank_columns(M, tol=1e-12):
+    """Indices of a linearly independent subset of M's columns (column-pivoted
+    QR of the column-normalised matrix, pivots above tol of the largest)."""
+    if M.shape[1] == 0:
+        return np.zeros(0, np.int64)
+    nrm = np.linalg.norm(M, axis=0)
+    keep = np.nonzero(nrm > 0)[0]
+    if keep.size == 0:
+        return keep
+    Ms = M[:, keep] / nrm[keep]
+    _, R, piv = sla.qr(Ms, mode="economic", pivoting=True)
+    d = np.abs(np.diag(R))
+    r = int(np.sum(d > tol * d[0]))
+    return np.sort(keep[piv[:r]])
+
+
+def projection(M, N, explicit):
+    """N~^-1 as a function X -> N~^-1 X, and ln det(G^T N G), n - r.
+
+    explicit=True builds G from the complete QR of the independent columns of
+    M (Eq. Gmatrix_proj with Q_2); otherwise the same operator through
+    N^-1 - N^-1 M (M^T N^-1 M)^-1 M^T N^-1 and
+    ln det(G^T N G) = ln det N + ln det(M^T N^-1 M) - ln det(M^T M)
+    (equal when G is orthonormal and the columns independent; tests pin the
+    two against each other)."""
+    cols = _rank_columns(M)
+    Mr = M[:, cols]
+    n, r = M.shape[0], cols.size
+    if explicit:
+        if r:
+            Q, _ = np.linalg.qr(Mr, mode="complete")
+            G = Q[:, r:]
+        else:
+            G = np.eye(n)
+        GNG = G.T @ (N[:, None] * G)
+        Lg = np.linalg.cholesky(GNG)
+        logdet = 2.0 * np.sum(np.log(np.diag(Lg)))
+
+        def apply(X):
+            Y = sla.cho_solve((Lg, True), G.T @ X)
+            return G @ Y
+        return apply, logdet, n - r
+    Ni = 1.0 / N
+    if r:
+        MNM = Mr.T @ (Ni[:, None] * Mr)
+        Lm = np.linalg.cholesky(MNM)
+        Lmm = np.linalg.cholesky(Mr.T @ Mr)
+    logdet = float(np.sum(np.log(N)))
+    if r:
+        logdet += 2.0 * np.sum(np.log(np.diag(Lm))) - 2.0 * np.sum(np.log(np.diag(Lmm)))
+
+    def apply(X):
+        Y = Ni.reshape((-1,) + (1,) * (X.ndim - 1)) * X
+        if r:
+            Y = Y - Ni.reshape((-1,) + (1,) * (X.ndim - 1)) * (Mr @ sla.cho_solve((Lm, True), Mr.T @ Y))
+        return Y
+    return apply, logdet, n - r
+
+
+class StdPrepared:
+    """Per-pulsar Gram quantities of one data set (computed once, as the
+    paper stores them), the HD matrix and the prior box."""
+
+    def __init__(self, ds, explicit=None):
+        self.ds = ds
+        n = self.n_psr = int(ds["n_psr"])
+        self.free = ds.get("spectrum", "powerlaw") == "free"
+        self.lay = StdLayout(n, int(ds["nf_rn"]), int(ds["nf_gw"]), int(ds["nf_dm"]), self.free)
+        lay = self.lay
+        self.T = float(ds["tspan"])
+        self.freqs = np.arange(1, max(lay.Ka, lay.Kdm, 1) + 1) / self.T
+        self.Gamma = hd_matrix(np.asarray(ds["psr_pos"], np.float64))
+        self.lo = np.asarray(ds["prior_lo"], np.float64)
+        self.hi = np.asarray(ds["prior_hi"], np.float64)
+        off = np.asarray(ds["toa_offsets"], np.int64)
+        t_all = np.asarray(ds["t"], np.float64)
+        tm = ds.get("tm")
+        self.S0, self.dvec, self.cval, self.const = [], [], [], []
+        kk = np.arange(1, max(lay.Ka, lay.Kdm, 1) + 1)
+        for I in range(n):
+            s, e = int(off[I]), int(off[I + 1])
+            tt = t_all[s:e]
+            if tm is None:
+                c = 0.5 * (tt.min() + tt.max())
+                hs = 0.5 * (tt.max() - tt.min())
+                hs = hs if hs > 0 else 1.0
+                tau = (tt - c) / hs
+                M = np.stack([np.ones_like(tau), tau, tau * tau], axis=1)
+            else:
+                M = np.asarray(tm, np.float64)[s:e]
+            arg = 2.0 * np.pi * np.outer(tt, kk) / self.T
+            F = np.empty((tt.size, 2 * kk.size))
+            F[:, 0::2] = np.sin(arg)
+            F[:, 1::2] = np.cos(arg)
+            w = float(ds["dm_scale"]) / np.asarray(ds["nu"][s:e], np.float64) ** 2
+            Tm = np.concatenate([F[:, : 2 * lay.Ka], w[:, None] * F[:, : 2 * lay.Kdm]], axis=1)
+            be = np.asarray(ds["backend"][s:e], np.int64)
+            N = (np.asarray(ds["efac"])[be] * np.asarray(ds["sigma"][s:e])) ** 2 + np.asarray(ds["equad"])[be] ** 2
+            dt = np.asarray(ds["dt"][s:e], np.float64)
+            ex = (e - s) <= 1500 if explicit is None else explicit
+            apply, logdet, nprime = projection(M, N, ex)
+            NT = apply(Tm)
+            self.S0.append(Tm.T @ NT)
+            self.dvec.append(NT.T @ dt)
+            self.cval.append(float(dt @ apply(dt)))
+            self.const.append(-0.5 * (nprime * LN2PI + logdet))
+
+    def spectra(self, th):
+        """rho (Ka), kappa (Np, Ka), kappa_dm (Np, Kdm) as torch tensors."""
+        lay, n = self.lay, self.n_psr
+        f = torch.tensor(self.freqs, dtype=torch.float64)
+        lnfy = torch.log(f * YR)
+
+        def pl(l10a, gam, K):
+            return 10.0 ** (2.0 * l10a) / (12.0 * np.pi ** 2) * YR ** 3 * torch.exp(-gam * lnfy[:K]) / self.T
+
+        zero = torch.zeros((), dtype=torch.float64)
+        rho = torch.zeros(lay.Ka, dtype=torch.float64)
+        if lay.nf_gw > 0:
+            seg = th[lay.gw:lay.gw + lay.w_gw]
+            r = 10.0 ** seg if self.free else pl(seg[0], seg[1], lay.nf_gw)
+            rho = torch.cat([r, zero.repeat(lay.Ka - lay.nf_gw)])
+        kap = torch.zeros((n, lay.Ka), dtype=torch.float64)
+        if lay.nf_rn > 0:
+            rows = []
+            for I in range(n):
+                seg = th[lay.rn + I * lay.w_rn: lay.rn + (I + 1) * lay.w_rn]
+                r = 10.0 ** seg if self.free else pl(seg[0], seg[1], lay.nf_rn)
+                rows.append(torch.cat([r, zero.repeat(lay.Ka - lay.nf_rn)]))
+            kap = torch.stack(rows)
+        kdm = torch.zeros((n, lay.Kdm), dtype=torch.float64)
+        if lay.nf_dm > 0:
+            rows = []
+            for I in range(n):
+                seg = th[lay.dm + I * lay.w_dm: lay.dm + (I + 1) * lay.w_dm]
+                rows.append(10.0 ** seg if self.free else pl(seg[0], seg[1], lay.nf_dm))
+            kdm = torch.stack(rows)
+        return rho, kap, kdm
+
+    def transform(self, th, z, beta):
+        """a (Np, P), sum_I ln det L_I, beta sum_I log L(a_I) for one point."""
+        lay, n = self.lay, self.n_psr
+        rho, kap, kdm = self.spectra(th)
+        a_all, jac, lik = [], 0.0, 0.0
+        for I in range(n):
+            D = torch.cat([(rho + kap[I]).repeat_interleave(2), kdm[I].repeat_interleave(2)])
+            S0 = torch.tensor(self.S0[I])
+            d = torch.tensor(self.dvec[I])
+            A = beta * S0 + torch.diag(1.0 / D)
+            Sig = torch.linalg.inv(A)
+            Sig = 0.5 * (Sig + Sig.T)
+            L = torch.linalg.cholesky(Sig)
+            ahat = Sig @ (beta * d)
+            a = ahat + L @ z[I]
+            a_all.append(a)
+            jac = jac + torch.sum(torch.log(torch.diagonal(L)))
+            lik = lik + beta * (-0.5 * self.cval[I] + a @ d - 0.5 * a @ (S0 @ a) + self.const[I])
+        return torch.stack(a_all), jac, lik, (rho, kap, kdm)
+
+    def log_prior_a(self, a, spec):
+        """log N(a; 0, phi): per frequency rho_k Gamma + diag kappa_.k for the
+        red/common block (sin and cos share it), diagonal for DM."""
+        lay, n = self.lay, self.n_psr
+        rho, kap, kdm = spec
+        G = torch.tensor(self.Gamma)
+        out = 0.0
+        for k in range(lay.Ka):
+            phi = rho[k] * G + torch.diag(kap[:, k])
+            Lk = torch.linalg.cholesky(phi)
+            ld = 2.0 * torch.sum(torch.log(torch.diagonal(Lk)))
+            for c in range(2):
+                y = torch.linalg.solve_triangular(Lk, a[:, 2 * k + c].unsqueeze(1), upper=False)
+                out = out - 0.5 * torch.sum(y * y) - 0.5 * (n * LN2PI + ld)
+        for k in range(lay.Kdm):
+            for c in range(2):
+                v = a[:, 2 * lay.Ka + 2 * k + c]
+                out = out - 0.5 * torch.sum(v * v / kdm[:, k]) - 0.5 * torch.sum(torch.log(2 * np.pi * kdm[:, k]))
+        return out
+
+    def logp_one(self, x, beta):
+        lay = self.lay
+        th = x[: lay.n_theta]
+        z = x[lay.z:].reshape(self.n_psr, lay.P)
+        a, jac, lik, spec = self.transform(th, z, beta)
+        return lik + jac + self.log_prior_a(a, spec) - float(np.sum(np.log(self.hi - self.lo)))
+
+
+def logp_grad(prep: StdPrepared, X, beta=None):
+    """log p~, its gradient (autograd) and a status per chain; X (C, d)."""
+    X = np.atleast_2d(np.asarray(X, np.float64))
+    C, d = X.shape
+    lay = prep.lay
+    assert d == lay.d
+    beta = np.ones(C) if beta is None else np.broadcast_to(np.asarray(beta, np.float64), (C,))
+    logp = np.full(C, -np.inf)
+    grad = np.zeros((C, d))
+    status = np.zeros(C, np.int32)
+    for c in range(C):
+        th = X[c, : lay.n_theta]
+        if not (np.all(np.isfinite(th)) and np.all(th >= prep.lo) and np.all(th <= prep.hi)):
+            status[c] = ST_PRIOR
+            continue
+        if not np.all(np.isfinite(X[c])):
+            status[c] = ST_NONFINITE
+            continue
+        x = torch.tensor(X[c], requires_grad=True)
+        try:
+            lp = prep.logp_one(x, float(beta[c]))
+            (g,) = torch.autograd.grad(lp, x)
+        except torch.linalg.LinAlgError:
+            status[c] = ST_NOTPD
+            continue
+        lpv, gv = float(lp.detach()), g.numpy()
+        if not (np.isfinite(lpv) and np.all(np.isfinite(gv))):
+            status[c] = ST_NONFINITE
+            continue
+        logp[c], grad[c] = lpv, gv
+    return dict(logp=logp, grad=grad, status=status)
+
+
+def coefficients(prep: StdPrepared, x, beta=1.0):
+    """The Fourier coefficients a (Np, P) that a point maps to."""
+    lay = prep.lay
+    xt = torch.tensor(np.asarray(x, np.float64))
+    a, _, _, _ = prep.transform(xt[: lay.n_theta], xt[lay.z:].reshape(prep.n_psr, lay.P), beta)
+    return a.numpy()
