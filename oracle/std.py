@@ -37,7 +37,8 @@ frequency, rho_k = 10^theta_k in s^2).  Uniform hyper-priors.
 The gradient is PyTorch autograd of this plain definition (library
 Cholesky, inverse and triangular solves), so it needs no hand derivation.
 Per-chain conditions: 1 outside the prior box or non-finite theta,
-2 a factorisation fails (not positive definite), 4 non-finite z or result.
+2 a factorisation fails or a CURN variance is not positive and finite (a
+prior covariance that is not positive definite), 4 non-finite z or result.
 """
 from __future__ import annotations
 
@@ -49,6 +50,10 @@ from .model import YR, hd_matrix
 
 LN2PI = float(np.log(2.0 * np.pi))
 ST_OK, ST_PRIOR, ST_NOTPD, ST_NONFINITE = 0, 1, 2, 4
+
+
+class NotPositiveDefinite(Exception):
+    """A prior covariance of the transform is not positive definite."""
 
 
 class StdLayout:
@@ -221,6 +226,10 @@ class StdPrepared:
         a_all, jac, lik = [], 0.0, 0.0
         for I in range(n):
             D = torch.cat([(rho + kap[I]).repeat_interleave(2), kdm[I].repeat_interleave(2)])
+            if not bool(torch.all(torch.isfinite(D) & (D > 0))):
+                # a CURN variance of 0 or inf (a spectrum that underflows or
+                # overflows): phi_CURN is not positive definite
+                raise NotPositiveDefinite("CURN prior variance not positive and finite")
             S0 = torch.tensor(self.S0[I])
             d = torch.tensor(self.dvec[I])
             A = beta * S0 + torch.diag(1.0 / D)
@@ -284,7 +293,7 @@ def logp_grad(prep: StdPrepared, X, beta=None):
         try:
             lp = prep.logp_one(x, float(beta[c]))
             (g,) = torch.autograd.grad(lp, x)
-        except torch.linalg.LinAlgError:
+        except (torch.linalg.LinAlgError, NotPositiveDefinite):
             status[c] = ST_NOTPD
             continue
         lpv, gv = float(lp.detach()), g.numpy()

@@ -320,4 +320,12 @@ def test_status_codes():
     X[1, lay.z + 2] = np.nan             # non-finite coefficient
     out = std.logp_grad(prep, X)
     assert list(out["status"]) == [1, 4, 0]
+    # spectra underflowing to 0 in a widened box: phi_CURN not positive definite
+    ds2 = dict(ds)
+    ds2["prior_lo"] = np.full_like(ds["prior_lo"], -400.0)
+    prep2 = std.StdPrepared(ds2)
+    x = X[2].copy()
+    x[lay.gw] = -300.0
+    x[lay.rn:lay.rn + 2 * prep.n_psr:2] = -300.0
+    assert std.logp_grad(prep2, x)["status"][0] == 2
     assert out["logp"][0] == -np.inf and np.all(out["grad"][0] == 0)
