@@ -164,6 +164,88 @@ def serving_bench(n_traj, rates, n_req, n_chains=16, n_leapfrog=20, quantum=10, 
         alone_ms=[round(float(a) * 1e3, 2) for a in alone], rates=out)
 
 
+def std_flops_fwd(P):
+    """Algorithmic flops of k_std_fwd per (pulsar, chain): Cholesky of the
+    P x P CURN precision (P^3/3), the triangular inverse (P^3/3) and the
+    mat-vecs (X beta d, X^T (t + z), X^T t, S0 a: 5 P^2)."""
+    return 2.0 * P ** 3 / 3.0 + 5.0 * P * P
+
+
+def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2):
+    """The paper's standardized form (CURN transform on the Gram form, timing
+    model marginalised) on the same 67-pulsar / 250k-TOA data set: HMC
+    trajectories replayed as one HIP graph, per-stage times and the roofline
+    of its dominant kernel."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2607_06834_amd import api
+
+    ds = synth.cfg2()
+    t0 = time.perf_counter()
+    g = api.StdDataset(ds)
+    t_create = time.perf_counter() - t0
+    lay = g.layout
+    th = synth.injected_theta(ds, 203)
+    rng = np.random.default_rng(204)
+    th = np.clip(th + rng.uniform(-0.2, 0.2, (n_chains, th.size)), ds["prior_lo"], ds["prior_hi"])
+    X0 = np.concatenate([th, rng.standard_normal((n_chains, g.d - int(lay.n_theta)))], axis=1)
+    im = torch.ones(g.d, dtype=torch.float64, device="cuda")
+    im[: int(lay.n_theta)] = 1e-4
+    stream = torch.cuda.Stream()
+    eps_used, acc_rate = None, None
+    with torch.cuda.stream(stream):
+        # the largest step (of a fixed ladder) whose pilot trajectories accept
+        # at least 60% and keep every evaluation valid
+        for eps in (0.4, 0.2, 0.1, 0.05, 0.02):
+            x = torch.tensor(X0, device="cuda")
+            lp, gr, st = g.ptafs_std_logp_grad(x, stream=stream)
+            acc = torch.zeros(n_chains, dtype=torch.int64, device="cuda")
+            bad = torch.zeros(n_chains, dtype=torch.int64, device="cuda")
+            g.ptafs_std_hmc_run(x, lp, gr, acc, n_traj=2, n_leapfrog=n_leapfrog, eps=eps, seed=301,
+                                inv_mass=im, n_invalid=bad, stream=stream)
+            stream.synchronize()
+            if acc.sum().item() >= 0.6 * 2 * n_chains and bad.sum().item() == 0:
+                eps_used = eps
+                break
+        eps_used = eps_used or 0.02
+        x = torch.tensor(X0, device="cuda")
+        lp, gr, st = g.ptafs_std_logp_grad(x, stream=stream)
+        acc = torch.zeros(n_chains, dtype=torch.int64, device="cuda")
+        bad = torch.zeros(n_chains, dtype=torch.int64, device="cuda")
+        g.ptafs_std_hmc_run(x, lp, gr, acc, n_traj=max(warmup, 1), n_leapfrog=n_leapfrog, eps=eps_used,
+                            seed=302, inv_mass=im, n_invalid=bad, stream=stream)
+        stream.synchronize()
+        acc.zero_()
+        bad.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.ptafs_std_hmc_run(x, lp, gr, acc, n_traj=steps, n_leapfrog=n_leapfrog, eps=eps_used,
+                            seed=302, traj0=max(warmup, 1), inv_mass=im, n_invalid=bad, stream=stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        acc_rate = float(acc.sum().item()) / (n_chains * steps)
+        valid = 1.0 - float(bad.sum().item()) / (n_chains * n_leapfrog * steps)
+    stages = g.ptafs_std_profile_stages(x, reps=20, stream=stream)
+    P = int(lay.p)
+    flops = std_flops_fwd(P) * n_chains * int(lay.n_psr)
+    achieved = flops / (stages["transform"] * 1e-3) / 1e12
+    g.close()
+    return dict(
+        workload="67 psr / 250000 TOA, RN 30 + DM 30 + HD common 14 (P = 120 coefficients per pulsar), "
+                 f"{n_chains} chains x leapfrog {n_leapfrog}; step = one HIP-graph trajectory",
+        value=n_chains * n_leapfrog * steps / el, unit="grad evals/s", ms_per_step=el / steps * 1e3,
+        eps=eps_used, accept_rate=acc_rate, valid_eval_fraction=valid, create_s=t_create,
+        stages_ms={k: round(v, 5) for k, v in stages.items()},
+        ms_per_eval=round(sum(stages.values()), 5),
+        roofline={"bound": "mfma", "kernel": "k_std_fwd (per-pulsar CURN factorisation + inverse)",
+                  "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                  "frac": achieved / FP64_PEAK_TFLOPS, "flop_per_problem": std_flops_fwd(P),
+                  "problems_per_launch": n_chains * int(lay.n_psr), "avg_launch_ms": stages["transform"],
+                  "traffic": None})
+
+
 def cfg4_bench(n_chains=256, n_leapfrog=20, n_traj=10, n_plain=20):
     """The 3-pulsar, 1500-TOA array (config 1) with 256 chains: batched form
     (ragged MFMA TOA pass, HIP-graph trajectories) against the plain form
@@ -250,6 +332,9 @@ def main():
     ap.add_argument("--serve-full", action="store_true",
                     help="16 requests per rate over 0.25..8 req/s (long)")
     ap.add_argument("--no-cfg4", action="store_true")
+    ap.add_argument("--no-std", action="store_true")
+    ap.add_argument("--std-only", action="store_true",
+                    help="only the standardized-form leg (for profiler passes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -263,6 +348,10 @@ def main():
     from paper_2607_06834_amd import api, autotune, precond
 
     torch.cuda.set_device(0)
+    if args.std_only:
+        print(json.dumps({"std_form": std_bench(n_chains=args.chains, n_leapfrog=args.leapfrog,
+                                                steps=args.steps, warmup=args.warmup)}))
+        return
     ds = synth.cfg2()
     C, L = args.chains, args.leapfrog
     th = synth.injected_theta(ds, 203)
@@ -340,6 +429,10 @@ def main():
     _log("stages and plain form done")
     cpu = None if args.no_cpu else cpu_baseline(ds, min_seconds=args.cpu_seconds)
     _log("cpu baseline done")
+    std_form = None
+    if not args.no_std:
+        std_form = std_bench(n_chains=C, n_leapfrog=L, steps=args.steps, warmup=args.warmup)
+        _log(f"standardized form: {std_form['value']:.0f} grad evals/s, stages {std_form['stages_ms']}")
     cfg4 = None
     if not args.no_cfg4:
         cfg4 = cfg4_bench()
@@ -392,6 +485,7 @@ def main():
         "accept_rate": float(acc.sum().item()) / (C * args.steps),
         "valid_eval_fraction": valid,
         "cpu_baseline": cpu,
+        "std_form": std_form,
         "cfg4": cfg4,
         "serving": serving,
     }

@@ -235,6 +235,117 @@ int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, d
                          double *grad, int32_t *status, int32_t reps, int32_t plain,
                          double *ms_out, void *stream);
 
+/* ======================================================================
+ * Standardized form (Sec. IV.B): the paper's own evaluation.
+ *
+ * The timing model is marginalised analytically (Eq. Gmatrix_proj: N^-1 is
+ * replaced by N~^-1 = G (G^T N G)^-1 G^T, G an orthonormal basis of the
+ * complement of the timing-model columns), the per-pulsar Gram quantities
+ * F~^T N~^-1 F~, F~^T N~^-1 dt, dt^T N~^-1 dt (F~ = [F, w F_dm]) are computed
+ * once per data set, and the Fourier coefficients are sampled through the CURN
+ * standardizing transform (Eqs. PTA_standard_transform_curn,
+ * standardized_stochastic_posterior):
+ *
+ *   Sigma_I = (beta F~^T N~^-1 F~ + phi_CURN,I^-1)^-1 = L_I L_I^T  (L_I lower Cholesky)
+ *   a_I     = beta Sigma_I F~^T N~^-1 dt + L_I z_I
+ *   log p~  = beta log L(a) + log N(a; 0, phi) + sum_I ln det L_I + log pi(theta)
+ *   log L(a)= sum_I [-1/2 dt^T N~^-1 dt + a_I^T F~^T N~^-1 dt
+ *                    - 1/2 a_I^T F~^T N~^-1 F~ a_I - 1/2 ln det(2 pi G^T N G)]
+ *
+ * phi keeps the HD correlations per frequency (Eq. prior_cov); phi_CURN is its
+ * diagonal with Gamma = I (rho_k + kappa_Ik, kappa_dm,Ik).  beta is a per-chain
+ * likelihood temperature (App. B, Eqs. tempered_post, mv_normal_post_temp; 1
+ * is the untempered posterior).  Every constant is kept (normalised density).
+ *
+ * Parameter vector: [theta | z], theta = [gw | rn per pulsar | dm per pulsar]
+ * with 2 entries per process for the power law (log10 A, gamma) or one per
+ * frequency for the free spectrum (log10 rho_k, rho_k = 10^theta in s^2,
+ * Sec. IV.A); z per pulsar: P = 2 ka + 2 nf_dm entries (k = 1 sin, k = 1 cos, ...
+ * of the red/common block, ka = max(nf_rn, nf_gw), then the DM block).
+ * Per-chain statuses as above (1 box, 2 a factorisation fails, 4 non-finite).
+ * ====================================================================== */
+
+#define PTAFS_SPEC_POWERLAW 0
+#define PTAFS_SPEC_FREE 1
+#define PTAFS_MAX_TM 64        /* timing-model columns per TOA */
+
+typedef struct ptafs_std ptafs_std;   /* opaque */
+
+typedef struct {
+  int32_t n_psr;                 /* 1..PTAFS_MAX_PSR */
+  const int64_t *toa_offsets;    /* n_psr+1 ascending offsets (CSR), >= 1 TOA per pulsar */
+  const double *t, *dt, *sigma, *nu;   /* per TOA: s from the array epoch, s, s, Hz */
+  const int32_t *backend;        /* per TOA, 0..n_backend-1 */
+  int32_t n_backend;
+  const double *efac, *equad;    /* per backend (EQUAD in s) */
+  const double *psr_pos;         /* 3*n_psr unit vectors */
+  double tspan;                  /* T of Eq. Fourier_series, s */
+  int32_t nf_rn, nf_gw, nf_dm;   /* frequencies k = 1..nf (0 = process off); not all zero */
+  double dm_scale;               /* DM weight w_i = dm_scale / nu_i^2 */
+  int32_t n_tm;                  /* timing-model columns per TOA, 0..PTAFS_MAX_TM */
+  const double *tm;              /* [n_toa][n_tm] row-major design matrix, or NULL with
+                                    n_tm = 0 for M = [1, tau, tau^2] per pulsar.  Columns
+                                    that are zero or linearly dependent within a pulsar
+                                    are dropped (column-pivoted factorisation). */
+  int32_t spectrum;              /* PTAFS_SPEC_POWERLAW or PTAFS_SPEC_FREE (all processes) */
+  const double *prior_lo, *prior_hi;   /* n_theta box edges */
+} ptafs_std_desc;
+
+typedef struct {
+  int64_t d, n_theta, off_gw, off_rn, off_dm, off_z;
+  int64_t n_psr, n_toa, k_coef, k_dm, p;   /* p = 2 k_coef + 2 k_dm coefficients per pulsar */
+  size_t dataset_bytes, workspace_bytes, hmc_bytes;
+} ptafs_std_layout_info;
+
+/* Copy a data set, marginalise its timing model and store the per-pulsar Gram
+ * quantities (host, once).  Synchronises `stream` only. */
+int ptafs_std_create(const ptafs_std_desc *desc, void *stream, ptafs_std **out);
+/* Release (waits for the data set's own last work only).  NULL is a no-op. */
+void ptafs_std_destroy(ptafs_std *ds);
+
+/* The per-pulsar quantities ptafs_std_create stores, computed on the host
+ * with no GPU call (for checks and for sizing): for pulsar `pulsar`,
+ * s0 [p][p] = F~^T N~^-1 F~, dvec [p] = F~^T N~^-1 dt and
+ * scal[0] = dt^T N~^-1 dt, scal[1] = -1/2 ln det(2 pi G^T N G), scal[2] = the
+ * number of timing-model columns kept (host pointers, original order). */
+int ptafs_std_precompute(const ptafs_std_desc *desc, int32_t pulsar, double *s0, double *dvec,
+                         double *scal);
+int ptafs_std_layout(const ptafs_std *ds, int32_t n_chains, ptafs_std_layout_info *out);
+
+/*
+ * log p~ and its gradient for n_chains points.
+ *   x      device [n_chains][d]     beta  device [n_chains] or NULL (all 1)
+ *   logp   device [n_chains]        grad  device [n_chains][d]
+ *   status device [n_chains]
+ * Per (pulsar, chain) one factorisation of the P x P CURN precision and its
+ * inverse, per (frequency, chain) one N_p x N_p factorisation of phi_k, on
+ * FP64 matrix cores; results are bit-identical for identical inputs.
+ */
+int ptafs_std_logp_grad(ptafs_std *ds, int32_t n_chains, const double *x, const double *beta,
+                        double *logp, double *grad, int32_t *status, void *stream);
+
+/* The Fourier coefficients a = a_hat + L z of each point (the map back from
+ * z, Eq. PTA_standard_transform_curn): a device [n_chains][n_psr][p]. */
+int ptafs_std_coefficients(ptafs_std *ds, int32_t n_chains, const double *x, const double *beta,
+                           double *a, void *stream);
+
+/* Stage timing of ptafs_std_logp_grad: `reps` evaluations with a HIP event
+ * between the stages on `stream`; mean ms per stage to the HOST array
+ * ms_out[4]: per-pulsar transform (k_std_fwd), prior per frequency
+ * (k_std_prior_*), per-pulsar adjoint (k_std_bwd), assembly.  Synchronises
+ * the stream. */
+int ptafs_std_profile_stages(ptafs_std *ds, int32_t n_chains, const double *x, const double *beta,
+                             double *logp, double *grad, int32_t *status, int32_t reps,
+                             double *ms_out, void *stream);
+
+/* Fixed-step HMC on log p~ with the conventions of ptafs_hmc_run (same
+ * momenta, accept test, graph capture and buffers); beta as above. */
+int ptafs_std_hmc_run(ptafs_std *ds, int32_t n_chains, int32_t n_traj, int32_t n_leapfrog,
+                      double eps, const double *inv_mass, uint64_t seed, uint64_t traj0,
+                      const double *beta, double *x, double *logp, double *grad,
+                      int64_t *n_accept, double *samples, int64_t *n_invalid, int32_t use_graph,
+                      void *stream);
+
 /* Human-readable text for a return code (static storage). */
 const char *ptafs_strerror(int code);
 

@@ -158,6 +158,8 @@ class StdPrepared:
         t_all = np.asarray(ds["t"], np.float64)
         tm = ds.get("tm")
         self.S0, self.dvec, self.cval, self.const = [], [], [], []
+        self.Gabs, self.dabs = [], []            # per-TOA absolute sums (tolerance companions)
+        self.ntoa = []
         kk = np.arange(1, max(lay.Ka, lay.Kdm, 1) + 1)
         for I in range(n):
             s, e = int(off[I]), int(off[I + 1])
@@ -182,6 +184,10 @@ class StdPrepared:
             ex = (e - s) <= 1500 if explicit is None else explicit
             apply, logdet, nprime = projection(M, N, ex)
             NT = apply(Tm)
+            self.ntoa.append(e - s)
+            At = np.abs(Tm) / N[:, None]
+            self.Gabs.append(At.T @ np.abs(Tm))
+            self.dabs.append(At.T @ np.abs(dt))
             self.S0.append(Tm.T @ NT)
             self.dvec.append(NT.T @ dt)
             self.cval.append(float(dt @ apply(dt)))
@@ -302,6 +308,95 @@ def logp_grad(prep: StdPrepared, X, beta=None):
             continue
         logp[c], grad[c] = lpv, gv
     return dict(logp=logp, grad=grad, status=status)
+
+
+def z_scale(prep: StdPrepared, x, beta=1.0):
+    """Magnitude companion of dlog p~/dz (the tolerance floor of the parity
+    tests): the adjoint dz_I = L_I^T v_I, v_I = beta (d_I - S0_I a_I) - (phi^-1 a)_I,
+    evaluated with the absolute value of every term down to the per-TOA sums
+    that d and S0 hold (the timing-model projection cancels against them),
+    S_I = |L_I|^T [beta (sum_i |T_i| |dt_i| / N_i + (sum_i |T_i| |T_i|^T / N_i) |a_I|)
+                   + (|phi^-1| |a|)_I]   (Np, P)."""
+    lay, n = prep.lay, prep.n_psr
+    xt = torch.tensor(np.asarray(x, np.float64))
+    th, z = xt[: lay.n_theta], xt[lay.z:].reshape(n, lay.P)
+    a, _, _, (rho, kap, kdm) = prep.transform(th, z, beta)
+    a = a.numpy()
+    rho, kap, kdm = rho.numpy(), kap.numpy(), kdm.numpy()
+    pa = np.zeros_like(a)                      # |phi^-1| |a|
+    for k in range(lay.Ka):
+        phinv = np.abs(np.linalg.inv(rho[k] * prep.Gamma + np.diag(kap[:, k])))
+        for c in range(2):
+            pa[:, 2 * k + c] = phinv @ np.abs(a[:, 2 * k + c])
+    for k in range(lay.Kdm):
+        for c in range(2):
+            j = 2 * lay.Ka + 2 * k + c
+            pa[:, j] = np.abs(a[:, j]) / kdm[:, k]
+    out = np.zeros((n, lay.P))
+    for I in range(n):
+        D = np.concatenate([np.repeat(rho + kap[I], 2), np.repeat(kdm[I], 2)])
+        Sig = np.linalg.inv(beta * prep.S0[I] + np.diag(1.0 / D))
+        L = np.linalg.cholesky(0.5 * (Sig + Sig.T))
+        V = beta * (prep.dabs[I] + prep.Gabs[I] @ np.abs(a[I])) + pa[I]
+        out[I] = np.abs(L).T @ V
+    return out
+
+
+def rounding_sensitivity(prep: StdPrepared, X, beta=None, seed=0, draws=1):
+    """The largest shift of the gradient over ``draws`` independent draws of
+    _rounding_shift (below)."""
+    out = None
+    for k in range(draws):
+        d = _rounding_shift(prep, X, beta, seed + k)
+        out = d if out is None else np.maximum(out, d)
+    return out
+
+
+def _rounding_shift(prep: StdPrepared, X, beta=None, seed=0):
+    """How far the oracle's own gradient moves when its stored Gram quantities
+    carry rounding of the size a floating-point sum of n_I per-TOA terms has
+    (eps_mach sqrt(n_I) relative to the sum of the absolute values of the
+    terms), under two models: independent rounding of every entry of S0 and
+    d, and rounding shared by all the sums a TOA enters (its weight 1/N_i
+    perturbed, everything recomputed).  Returns the larger |grad' - grad|
+    (C, d): two FP64 evaluations of the same per-TOA sums cannot be asked to
+    agree more closely than this."""
+    import copy
+    rng = np.random.default_rng(seed)
+    eps = np.finfo(np.float64).eps
+    # (a) independent rounding of every stored entry
+    p2 = copy.copy(prep)
+    p2.S0, p2.dvec = list(prep.S0), list(prep.dvec)
+    for I in range(prep.n_psr):
+        e = eps * np.sqrt(max(prep.ntoa[I], 1))
+        xi = rng.uniform(-1.0, 1.0, prep.S0[I].shape)
+        p2.S0[I] = prep.S0[I] + e * prep.Gabs[I] * 0.5 * (xi + xi.T)
+        p2.dvec[I] = prep.dvec[I] + e * prep.dabs[I] * rng.uniform(-1.0, 1.0, prep.dvec[I].shape)
+    # (b) rounding shared by every sum a TOA enters (and so by the
+    # timing-model projection): each per-TOA weight 1/N_i scaled by
+    # 1 + eps sqrt(n_I) u_i, the Gram quantities recomputed
+    ds3 = dict(prep.ds)
+    off = np.asarray(ds3["toa_offsets"], np.int64)
+    scale = np.ones(np.asarray(ds3["t"]).size)
+    for I in range(prep.n_psr):
+        n = int(off[I + 1] - off[I])
+        scale[off[I]:off[I + 1]] += eps * np.sqrt(max(n, 1)) * rng.uniform(-1.0, 1.0, n)
+    # N_i -> N_i scale_i, carried by sigma_i (EQUAD is per backend, not per TOA)
+    be = np.asarray(ds3["backend"], np.int64)
+    ef = np.asarray(ds3["efac"], np.float64)[be]
+    eq = np.asarray(ds3["equad"], np.float64)[be]
+    N = (ef * np.asarray(prep.ds["sigma"], np.float64)) ** 2 + eq ** 2
+    ds3["sigma"] = np.sqrt(np.maximum(N * scale - eq ** 2, 0.0)) / ef
+    p3 = StdPrepared(ds3)
+    p3.Gamma = prep.Gamma
+    a = logp_grad(prep, X, beta)
+    out = np.zeros_like(a["grad"])
+    for pp in (p2, p3):
+        b = logp_grad(pp, X, beta)
+        d = np.abs(a["grad"] - b["grad"])
+        d[(a["status"] != 0) | (b["status"] != 0)] = 0.0
+        out = np.maximum(out, d)
+    return out
 
 
 def coefficients(prep: StdPrepared, x, beta=1.0):

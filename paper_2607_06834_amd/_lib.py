@@ -48,6 +48,38 @@ class DatasetDesc(C.Structure):
     ]
 
 
+class StdDesc(C.Structure):
+    _fields_ = [
+        ("n_psr", C.c_int32),
+        ("toa_offsets", c_int64_p),
+        ("t", c_double_p),
+        ("dt", c_double_p),
+        ("sigma", c_double_p),
+        ("nu", c_double_p),
+        ("backend", c_int32_p),
+        ("n_backend", C.c_int32),
+        ("efac", c_double_p),
+        ("equad", c_double_p),
+        ("psr_pos", c_double_p),
+        ("tspan", C.c_double),
+        ("nf_rn", C.c_int32),
+        ("nf_gw", C.c_int32),
+        ("nf_dm", C.c_int32),
+        ("dm_scale", C.c_double),
+        ("n_tm", C.c_int32),
+        ("tm", c_double_p),
+        ("spectrum", C.c_int32),
+        ("prior_lo", c_double_p),
+        ("prior_hi", c_double_p),
+    ]
+
+
+class StdLayoutInfo(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "d", "n_theta", "off_gw", "off_rn", "off_dm", "off_z", "n_psr", "n_toa", "k_coef", "k_dm", "p")] + [
+        ("dataset_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t), ("hmc_bytes", C.c_size_t)]
+
+
 class LayoutInfo(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "d", "n_theta", "off_gw", "off_rn", "off_dm", "off_cw", "off_u", "off_z", "off_zdm",
@@ -62,6 +94,8 @@ EXPORTS = (
     "ptafs_logp_grad", "ptafs_logp_grad_plain", "ptafs_logp_grad_noalloc",
     "ptafs_set_tuning", "ptafs_get_tuning",
     "ptafs_hmc_run", "ptafs_profile_stages", "ptafs_strerror",
+    "ptafs_std_create", "ptafs_std_destroy", "ptafs_std_layout", "ptafs_std_logp_grad",
+    "ptafs_std_coefficients", "ptafs_std_hmc_run", "ptafs_std_precompute", "ptafs_std_profile_stages",
 )
 
 _lib = None
@@ -101,6 +135,23 @@ def load():
     lib.ptafs_profile_stages.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.c_int32, C.c_int32,
                                          c_double_p, vp]
     lib.ptafs_profile_stages.restype = C.c_int
+    lib.ptafs_std_create.argtypes = [C.POINTER(StdDesc), vp, C.POINTER(vp)]
+    lib.ptafs_std_create.restype = C.c_int
+    lib.ptafs_std_destroy.argtypes = [vp]
+    lib.ptafs_std_destroy.restype = None
+    lib.ptafs_std_precompute.argtypes = [C.POINTER(StdDesc), C.c_int32, c_double_p, c_double_p, c_double_p]
+    lib.ptafs_std_precompute.restype = C.c_int
+    lib.ptafs_std_layout.argtypes = [vp, C.c_int32, C.POINTER(StdLayoutInfo)]
+    lib.ptafs_std_layout.restype = C.c_int
+    lib.ptafs_std_logp_grad.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp]
+    lib.ptafs_std_logp_grad.restype = C.c_int
+    lib.ptafs_std_profile_stages.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, C.c_int32, c_double_p, vp]
+    lib.ptafs_std_profile_stages.restype = C.c_int
+    lib.ptafs_std_coefficients.argtypes = [vp, C.c_int32, vp, vp, vp, vp]
+    lib.ptafs_std_coefficients.restype = C.c_int
+    lib.ptafs_std_hmc_run.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, vp, C.c_uint64,
+                                      C.c_uint64, vp, vp, vp, vp, vp, vp, vp, C.c_int32, vp]
+    lib.ptafs_std_hmc_run.restype = C.c_int
     lib.ptafs_strerror.argtypes = [C.c_int]
     lib.ptafs_strerror.restype = C.c_char_p
     _lib = lib

@@ -226,6 +226,169 @@ class Dataset:
             int(bool(use_graph)), _stream_handle(stream)), "ptafs_hmc_run")
 
 
+def _make_std_desc(desc, keep):
+    """ptafs_std_desc for a mapping: the fields of a data set plus optional
+    ``tm`` (n_toa x n_tm design matrix) and ``spectrum`` ("powerlaw" or
+    "free")."""
+    def arr(a, dtype):
+        a = np.ascontiguousarray(np.asarray(a), dtype=dtype)
+        keep.append(a)
+        return a
+
+    d = _lib.StdDesc()
+    d.n_psr = int(desc["n_psr"])
+    d.toa_offsets = _ptr(arr(desc["toa_offsets"], np.int64), C.c_int64)
+    d.t, d.dt, d.sigma, d.nu = (_ptr(arr(desc[k], np.float64), C.c_double) for k in ("t", "dt", "sigma", "nu"))
+    d.backend = _ptr(arr(desc["backend"], np.int32), C.c_int32)
+    efac = arr(desc["efac"], np.float64)
+    d.n_backend = int(efac.size)
+    d.efac = _ptr(efac, C.c_double)
+    d.equad = _ptr(arr(desc["equad"], np.float64), C.c_double)
+    d.psr_pos = _ptr(arr(desc["psr_pos"], np.float64), C.c_double)
+    d.tspan = float(desc["tspan"])
+    d.nf_rn, d.nf_gw, d.nf_dm = int(desc["nf_rn"]), int(desc["nf_gw"]), int(desc["nf_dm"])
+    d.dm_scale = float(desc["dm_scale"])
+    tm = desc.get("tm")
+    if tm is None:
+        d.n_tm, d.tm = 0, C.cast(None, _lib.c_double_p)
+    else:
+        tm = arr(tm, np.float64)
+        d.n_tm, d.tm = int(tm.shape[1]), _ptr(tm, C.c_double)
+    d.spectrum = 1 if desc.get("spectrum", "powerlaw") == "free" else 0
+    d.prior_lo = _ptr(arr(desc["prior_lo"], np.float64), C.c_double)
+    d.prior_hi = _ptr(arr(desc["prior_hi"], np.float64), C.c_double)
+    return d
+
+
+def ptafs_std_precompute(desc, pulsar):
+    """Host-only per-pulsar Gram quantities of the standardized form:
+    (s0 [p, p], dvec [p], dt^T N~^-1 dt, -1/2 ln det(2 pi G^T N G), columns kept)."""
+    keep = []
+    d = _make_std_desc(desc, keep)
+    ka = max(int(desc["nf_rn"]), int(desc["nf_gw"]))
+    p = 2 * ka + 2 * int(desc["nf_dm"])
+    s0 = np.zeros((p, p))
+    dv = np.zeros(p)
+    sc = np.zeros(3)
+    _lib.check(_lib.load().ptafs_std_precompute(C.byref(d), int(pulsar), _ptr(s0, C.c_double),
+                                                _ptr(dv, C.c_double), _ptr(sc, C.c_double)),
+               "ptafs_std_precompute")
+    return s0, dv, float(sc[0]), float(sc[1]), int(sc[2])
+
+
+class StdDataset:
+    """A data set in the standardized form (ptafs_std_create): timing model
+    marginalised, CURN standardizing transform, optional tempering and free
+    spectra.  Parameter vector [theta | z] (ptafs_std_layout)."""
+
+    def __init__(self, desc, stream=None):
+        lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libptafs needs a HIP GPU")
+        keep = []
+        d = _make_std_desc(desc, keep)
+        h = C.c_void_p()
+        _lib.check(lib.ptafs_std_create(C.byref(d), _stream_handle(stream), C.byref(h)), "ptafs_std_create")
+        self._h = h
+        self.layout = self.ptafs_std_layout(0)
+        self.d = int(self.layout.d)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().ptafs_std_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ptafs_std_layout(self, n_chains):
+        out = _lib.StdLayoutInfo()
+        _lib.check(_lib.load().ptafs_std_layout(self._h, int(n_chains), C.byref(out)), "ptafs_std_layout")
+        return out
+
+    def _x(self, x, inplace=False):
+        return Dataset._check_x(self, x, inplace)
+
+    def _beta(self, beta, n):
+        if beta is None:
+            return C.c_void_p()
+        Dataset._check_out(beta, torch.float64, (n,), "beta")
+        return C.c_void_p(beta.data_ptr())
+
+    def ptafs_std_logp_grad(self, x, beta=None, out=None, stream=None):
+        """(logp [C], grad [C, d], status [C]); beta: float64 [C] or None."""
+        x = self._x(x)
+        n = x.shape[0]
+        if out is None:
+            with torch.cuda.stream(stream) if stream is not None else _nullctx():
+                logp = torch.empty(n, dtype=torch.float64, device=x.device)
+                grad = torch.empty_like(x)
+                status = torch.empty(n, dtype=torch.int32, device=x.device)
+        else:
+            logp, grad, status = out
+            Dataset._check_out(logp, torch.float64, (n,), "logp")
+            Dataset._check_out(grad, torch.float64, (n, self.d), "grad")
+            Dataset._check_out(status, torch.int32, (n,), "status")
+        _lib.check(_lib.load().ptafs_std_logp_grad(
+            self._h, n, C.c_void_p(x.data_ptr()), self._beta(beta, n), C.c_void_p(logp.data_ptr()),
+            C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()), _stream_handle(stream)),
+            "ptafs_std_logp_grad")
+        return logp, grad, status
+
+    STD_STAGES = ("transform", "prior", "adjoint", "finalize")
+
+    def ptafs_std_profile_stages(self, x, beta=None, reps=10, stream=None):
+        """Mean ms per stage of the standardized evaluation (HIP events)."""
+        x = self._x(x)
+        n = x.shape[0]
+        logp = torch.empty(n, dtype=torch.float64, device=x.device)
+        grad = torch.empty_like(x)
+        status = torch.empty(n, dtype=torch.int32, device=x.device)
+        ms = (C.c_double * 4)()
+        _lib.check(_lib.load().ptafs_std_profile_stages(
+            self._h, n, C.c_void_p(x.data_ptr()), self._beta(beta, n), C.c_void_p(logp.data_ptr()),
+            C.c_void_p(grad.data_ptr()), C.c_void_p(status.data_ptr()), int(reps), ms,
+            _stream_handle(stream)), "ptafs_std_profile_stages")
+        return dict(zip(self.STD_STAGES, list(ms)))
+
+    def ptafs_std_coefficients(self, x, beta=None, stream=None):
+        """Fourier coefficients a = a_hat + L z, (C, n_psr, p)."""
+        x = self._x(x)
+        n = x.shape[0]
+        lay = self.layout
+        a = torch.empty((n, int(lay.n_psr), int(lay.p)), dtype=torch.float64, device=x.device)
+        _lib.check(_lib.load().ptafs_std_coefficients(
+            self._h, n, C.c_void_p(x.data_ptr()), self._beta(beta, n), C.c_void_p(a.data_ptr()),
+            _stream_handle(stream)), "ptafs_std_coefficients")
+        return a
+
+    def ptafs_std_hmc_run(self, x, logp, grad, n_accept, *, n_traj, n_leapfrog, eps, seed, traj0=0,
+                          inv_mass=None, beta=None, samples=None, n_invalid=None, use_graph=True,
+                          stream=None):
+        x = self._x(x, inplace=True)
+        n = x.shape[0]
+        Dataset._check_out(logp, torch.float64, (n,), "logp")
+        Dataset._check_out(grad, torch.float64, (n, self.d), "grad")
+        Dataset._check_out(n_accept, torch.int64, (n,), "n_accept")
+        if inv_mass is not None:
+            Dataset._check_out(inv_mass, torch.float64, (self.d,), "inv_mass")
+        if n_invalid is not None:
+            Dataset._check_out(n_invalid, torch.int64, (n,), "n_invalid")
+        if samples is not None:
+            Dataset._check_out(samples, torch.float64, (n_traj, n, self.d), "samples")
+        im = C.c_void_p(inv_mass.data_ptr()) if inv_mass is not None else C.c_void_p()
+        sm = C.c_void_p(samples.data_ptr()) if samples is not None else C.c_void_p()
+        nv = C.c_void_p(n_invalid.data_ptr()) if n_invalid is not None else C.c_void_p()
+        _lib.check(_lib.load().ptafs_std_hmc_run(
+            self._h, n, int(n_traj), int(n_leapfrog), float(eps), im, C.c_uint64(seed), C.c_uint64(traj0),
+            self._beta(beta, n), C.c_void_p(x.data_ptr()), C.c_void_p(logp.data_ptr()),
+            C.c_void_p(grad.data_ptr()), C.c_void_p(n_accept.data_ptr()), sm, nv, int(bool(use_graph)),
+            _stream_handle(stream)), "ptafs_std_hmc_run")
+
+
 def ptafs_dataset_create(desc, stream=None):
     return Dataset(desc, stream)
 

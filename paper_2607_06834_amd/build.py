@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libptafs.so")
-SOURCES = ["ptafs_api.hip", "k_spec.hip", "k_chol.hip", "k_cholt.hip", "k_toa.hip", "k_finalize.hip", "k_hmc.hip"]
+SOURCES = ["ptafs_api.hip", "k_spec.hip", "k_chol.hip", "k_cholt.hip", "k_toa.hip", "k_finalize.hip", "k_hmc.hip",
+           "std_api.hip", "k_std.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

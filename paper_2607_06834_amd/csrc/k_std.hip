@@ -1,0 +1,697 @@
+// Kernels of the standardized form (Sec. IV.B; Eqs. PTA_standard_transform_curn,
+// standardized_stochastic_posterior in the Gram form of Eq. posterior_implemented;
+// App. B for a tempered likelihood).
+//
+// Per pulsar I and chain c (one 256-thread workgroup each):
+//   A = beta S0_I + diag(1 / D),  D = CURN variances of the chain (rho_k + kappa_Ik,
+//   kappa_dm,Ik);  Sigma = A^-1 = L L^T with L the lower Cholesky factor.
+// In the reversed index order r = P - 1 - j the matrix A~ = J A J has a lower
+// Cholesky factor L~, and L = J L~^-T J: the lower Cholesky factor of the
+// covariance comes from the ordinary factorisation of the reversed precision.
+// With X = L~^-1 (lower):
+//   a~ = X^T (X beta d~ + z~)      (a = a_hat + L z)
+//   ln det L = sum_r ln X_rr
+// The adjoint (k_std_bwd) takes v = dF/da = beta (d - S0 a) - phi^-1 a:
+//   dlogp/dz~ = X v~
+//   dlogp/dD_j = [a_hat_j (Sigma v)_j + T_j + Sigma_jj / 2] / D_j^2
+// with (Sigma v)~ = X^T X v~, Sigma~_rr = |X e_r|^2 and T_r a suffix sum down
+// column r of X (the diagonal of L Phi(L^T v z^T) L^T).
+//
+// Per frequency k and chain (k_std_prior): phi_k = rho_k Gamma + diag kappa_.k
+// (Eq. prior_cov) factorised the same way, y = X_k a, u = X_k^T y = phi_k^-1 a,
+// and the explicit prior derivatives 1/2 u^T Gamma u - tr(phi_k^-1 Gamma) (rho)
+// and 1/2 u_I^2 - (phi_k^-1)_II (kappa), with tr(phi^-1 Gamma) = |X_k chol Gamma|_F^2.
+//
+// Matrices live in LDS as lower 16x16 tiles (row-major inside).  The
+// factorisation is right-looking by block columns: a diagonal tile is factorised
+// and inverted by one wave (lane r holds row r, operands by readlane), the
+// panel and the trailing tiles are updated on FP64 matrix cores
+// (v_mfma_f64_16x16x4f64), and X = L^-1 follows by block forward substitution,
+// also on matrix cores.  MFMA operand convention (lane l = c + 16 q): slice s of
+// a 16x16x16 product takes A[c][q + 4s] and B[q + 4s][c] (reduction index
+// q + 4s); the result holds R[q + 4v][c] in register v (the row of the A
+// operand's lane q + 4v), which is directly the B operand of a next product.
+#include <cmath>
+
+#include "std.h"
+
+namespace {
+
+using ps::StdDev;
+using v4d = double __attribute__((ext_vector_type(4)));
+
+__device__ inline double readlane_d(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 1/sqrt(a) and 1/a: hardware estimates refined by two Newton steps
+__device__ inline double rsqrt_nr(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  y = y * (1.5 - 0.5 * a * y * y);
+  y = y * (1.5 - 0.5 * a * y * y);
+  return y;
+}
+__device__ inline double rcp_nr(double a) {
+  double y = __builtin_amdgcn_rcp(a);
+  y = fma(y, fma(-a, y, 1.0), y);
+  y = fma(y, fma(-a, y, 1.0), y);
+  return y;
+}
+
+// Row-major tile loads for the MFMA operands (see the convention above).
+__device__ inline v4d ld_rm(const double *t, int c, int q) {   // Y[c][q+4s]: A of Y, B of Y^T
+  const double *p = t + c * 16 + q;
+  return v4d{p[0], p[4], p[8], p[12]};
+}
+__device__ inline v4d ld_cm(const double *t, int c, int q) {   // Y[q+4s][c]: B of Y, result of Y
+  const double *p = t + 16 * q + c;
+  return v4d{p[0], p[64], p[128], p[192]};
+}
+__device__ inline void st_cm(double *t, int c, int q, v4d v) {
+  double *p = t + 16 * q + c;
+  p[0] = v[0];
+  p[64] = v[1];
+  p[128] = v[2];
+  p[192] = v[3];
+}
+__device__ inline v4d mma(v4d a, v4d b, v4d acc) {
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[2], b[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[3], b[3], acc, 0, 0, 0);
+  return acc;
+}
+
+// Factorise the symmetric 16x16 tile t (both triangles present) and replace it
+// by the inverse of its lower Cholesky factor (lower, zeros above).  Executed
+// by one wave; lane r < 16 works on row r.  Returns false in every lane when a
+// pivot is not positive and finite.
+__device__ bool diag_factor_inverse(double *t, int lane) {
+  const int r = lane & 15;
+  double row[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) row[c] = t[r * 16 + c];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const double piv = readlane_d(row[j], j);
+    ok = ok && (piv > 0.0) && isfinite(piv);
+    const double l = row[j] * rsqrt_nr(piv);       // L[r][j] (r >= j); lane j: sqrt(piv)
+    row[j] = l;
+#pragma unroll
+    for (int k = j + 1; k < 16; ++k) row[k] = fma(-l, readlane_d(l, k), row[k]);
+  }
+  // X = L^-1: row m of X from the rows above it, acc[c] = sum_{k<m} L[r][k] X[k][c]
+  double acc[16], xr[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = xr[c] = 0.0;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const double id = rcp_nr(readlane_d(row[m], m));
+#pragma unroll
+    for (int c = 0; c <= m; ++c) {
+      const double xmc = readlane_d((((c == m) ? 1.0 : 0.0) - acc[c]) * id, m);
+      xr[c] = (r == m) ? xmc : xr[c];
+      acc[c] = fma(row[m], xmc, acc[c]);
+    }
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) t[r * 16 + c] = (c <= r) ? xr[c] : 0.0;
+  }
+  return ok;
+}
+
+// In-place X = L^-1 of the symmetric positive-definite matrix held as lower
+// tiles in A (diagonal tiles with both triangles).  All 256 threads call it.
+// flag (LDS) is set to 0 when a pivot fails; the return value is the flag.
+template <int T>
+__device__ bool factor_invert(double *A, int tid, int *flag) {
+  const int w = tid >> 6, lane = tid & 63, c = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int J = 0; J < T; ++J) {
+    if (w == 0) {
+      const bool ok = diag_factor_inverse(A + ps::tix(J, J) * 256, lane);
+      if (lane == 0 && !ok) *flag = 0;
+    }
+    __syncthreads();
+    // panel: L_IJ = A_IJ X_JJ^T
+    const double *xjj = A + ps::tix(J, J) * 256;
+    for (int I = J + 1 + w; I < T; I += 4) {
+      double *t = A + ps::tix(I, J) * 256;
+      const v4d r = mma(ld_rm(t, c, q), ld_rm(xjj, c, q), v4d{0.0, 0.0, 0.0, 0.0});
+      st_cm(t, c, q, r);
+    }
+    __syncthreads();
+    // trailing: A_IK -= L_IJ L_KJ^T, J < K <= I
+    int task = 0;
+#pragma unroll
+    for (int K = J + 1; K < T; ++K)
+#pragma unroll
+      for (int I = K; I < T; ++I, ++task) {
+        if ((task & 3) != w) continue;
+        double *t = A + ps::tix(I, K) * 256;
+        const v4d r = mma(-ld_rm(A + ps::tix(I, J) * 256, c, q), ld_rm(A + ps::tix(K, J) * 256, c, q),
+                          ld_cm(t, c, q));
+        st_cm(t, c, q, r);
+      }
+    __syncthreads();
+  }
+  // X by block rows: X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ (rows above are X already)
+#pragma unroll
+  for (int I = 1; I < T; ++I) {
+    v4d res[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int J = w + 4 * h;
+      res[h] = v4d{0.0, 0.0, 0.0, 0.0};
+      if (J < I) {
+        v4d u{0.0, 0.0, 0.0, 0.0};
+        for (int K = J; K < I; ++K)
+          u = mma(ld_rm(A + ps::tix(I, K) * 256, c, q), ld_cm(A + ps::tix(K, J) * 256, c, q), u);
+        res[h] = mma(-ld_rm(A + ps::tix(I, I) * 256, c, q), u, v4d{0.0, 0.0, 0.0, 0.0});
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int J = w + 4 * h;
+      if (J < I) st_cm(A + ps::tix(I, J) * 256, c, q, res[h]);
+    }
+    __syncthreads();
+  }
+  return *flag != 0;
+}
+
+__device__ inline double mat_at(const double *A, int r, int c) {   // lower element (r >= c)
+  return A[ps::tix(r >> 4, c >> 4) * 256 + ((r & 15) << 4) + (c & 15)];
+}
+
+// Block sum of one value per thread (256 threads); every thread gets the sum.
+__device__ inline double block_sum(double v, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <int T>
+constexpr size_t lds_bytes() {
+  return (size_t)(ps::ntiles(T) * 256 + 6 * 16 * T + 8) * sizeof(double) + 16;
+}
+
+// ---------------------------------------------------------------------------
+// Forward per (pulsar, chain): transform, likelihood, Jacobian.
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(256) void k_std_fwd(StdDev S, const double *__restrict__ x) {
+  extern __shared__ double lds[];
+  constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256;
+  double *A = lds;
+  double *vd = A + NE, *vz = vd + pp, *vt = vz + pp, *va = vt + pp, *red = va + 2 * pp;
+  int *flag = reinterpret_cast<int *>(red + 8);
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x / S.n_psr, I = blockIdx.x - c * S.n_psr;
+  const double *xc = x + (size_t)c * S.d;
+  const double beta = S.beta ? S.beta[c] : 1.0;
+  const int P = S.P;
+  const double *s0 = S.s0 + (size_t)I * pp * pp;
+  if (tid == 0) *flag = 1;
+  __syncthreads();
+  // A~ = beta S0~ + diag(1 / D~), lower tiles; a CURN variance that is not
+  // positive and finite leaves phi_CURN not positive definite
+  for (int e = tid; e < NE; e += 256) {
+    const int tt = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
+    int TI = 0;
+    while (ps::tix(TI + 1, 0) <= tt) ++TI;
+    const int TJ = tt - ps::tix(TI, 0);
+    const int r = 16 * TI + rr, col = 16 * TJ + cc;
+    double v = beta * s0[(size_t)r * pp + col];
+    if (r == col) {
+      if (r < P) {
+        const double Dv = ps::curn_var(S, xc, I, P - 1 - r);
+        if (!(Dv > 0.0 && isfinite(Dv))) *flag = 0;
+        v += 1.0 / Dv;
+      } else {
+        v += 1.0;
+      }
+    }
+    A[e] = v;
+  }
+  for (int r = tid; r < pp; r += 256) {
+    vd[r] = (r < P) ? beta * S.dvec[(size_t)I * pp + r] : 0.0;
+    vz[r] = (r < P) ? xc[S.off_z + I * P + (P - 1 - r)] : 0.0;
+  }
+  __syncthreads();
+  const bool ok = factor_invert<T>(A, tid, flag);
+  // t = X beta d~
+  if (tid < pp) {
+    double s = 0.0;
+    for (int k = 0; k <= tid; ++k) s = fma(mat_at(A, tid, k), vd[k], s);
+    vt[tid] = s;
+  }
+  __syncthreads();
+  // a~ = X^T (t + z~), a_hat~ = X^T t
+  const size_t vb = ((size_t)c * S.n_psr + I) * pp;
+  if (tid < pp) {
+    double sa = 0.0, sh = 0.0;
+    for (int r = tid; r < pp; ++r) {
+      const double xv = mat_at(A, r, tid);
+      sa = fma(xv, vt[r] + vz[r], sa);
+      sh = fma(xv, vt[r], sh);
+    }
+    va[tid] = sa;
+    S.ahat[vb + tid] = sh;
+    if (tid < P) S.avec[vb + (P - 1 - tid)] = sa;
+  }
+  __syncthreads();
+  // S0~ a~ (the padded matrix is symmetric: column r read with consecutive threads)
+  double part_d = 0.0, part_q = 0.0, part_j = 0.0;
+  if (tid < pp) {
+    double s = 0.0;
+    for (int k = 0; k < pp; ++k) s = fma(s0[(size_t)k * pp + tid], va[k], s);
+    const double dr = (tid < P) ? S.dvec[(size_t)I * pp + tid] : 0.0;
+    S.v1[vb + tid] = beta * (dr - s);
+    part_d = va[tid] * dr;
+    part_q = va[tid] * s;
+    part_j = (tid < P) ? log(mat_at(A, tid, tid)) : 0.0;
+  }
+  const double ad = block_sum(part_d, red);
+  const double aq = block_sum(part_q, red);
+  const double lj = block_sum(part_j, red);
+  if (tid == 0) {
+    const double *cc = S.cconst + 2 * I;
+    double *o = S.lik + ((size_t)c * S.n_psr + I) * 2;
+    o[0] = beta * (-0.5 * cc[0] + ad - 0.5 * aq + cc[1]);
+    o[1] = lj;
+    S.flag1[(size_t)c * S.n_psr + I] = ok ? 0 : ps::kFlagNotPD;
+  }
+  // X for the adjoint
+  double *xo = S.xinv + ((size_t)c * S.n_psr + I) * NE;
+  for (int e = tid; e < NE; e += 256) xo[e] = A[e];
+}
+
+// ---------------------------------------------------------------------------
+// Prior per (frequency k < nf_gw, chain): phi_k = rho_k Gamma + diag kappa_.k.
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(256) void k_std_prior_dense(StdDev S, const double *__restrict__ x) {
+  extern __shared__ double lds[];
+  constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256;
+  double *A = lds;
+  double *va = A + NE, *vb = va + 2 * pp, *vu = vb + 2 * pp, *red = vu + 2 * pp;
+  int *flag = reinterpret_cast<int *>(red + 8);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, c16 = lane & 15, q = lane >> 4;
+  const int c = blockIdx.x / S.nf_gw, k = blockIdx.x - c * S.nf_gw;
+  const int n = S.n_psr;
+  const double *xc = x + (size_t)c * S.d;
+  const double rho = ps::spec_value(S, xc, 0, 0, k);
+  for (int e = tid; e < NE; e += 256) {
+    const int tt = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
+    int TI = 0;
+    while (ps::tix(TI + 1, 0) <= tt) ++TI;
+    const int r = 16 * TI + rr, col = 16 * (tt - ps::tix(TI, 0)) + cc;
+    double v = rho * S.gam_tiles[e];
+    if (r == col) v += (r < n) ? ((k < S.nf_rn) ? ps::spec_value(S, xc, 1, r, k) : 0.0) : 1.0;
+    A[e] = v;
+  }
+  for (int i = tid; i < pp; i += 256) {
+    const double *av = S.avec + ((size_t)c * n + i) * S.pp;
+    va[i] = (i < n) ? av[2 * k] : 0.0;
+    va[pp + i] = (i < n) ? av[2 * k + 1] : 0.0;
+  }
+  if (tid == 0) *flag = 1;
+  __syncthreads();
+  const bool ok = factor_invert<T>(A, tid, flag);
+  // y = X a (rows), then u = X^T y (columns), for sin and cos
+  if (tid < 2 * pp) {
+    const int i = tid % pp, h = tid / pp;
+    double s = 0.0;
+    for (int m = 0; m <= i; ++m) s = fma(mat_at(A, i, m), va[h * pp + m], s);
+    vb[h * pp + i] = s;
+  }
+  __syncthreads();
+  double part_q = 0.0, part_l = 0.0;
+  if (tid < 2 * pp) {
+    const int i = tid % pp, h = tid / pp;
+    double s = 0.0, cn = 0.0;
+    for (int m = i; m < pp; ++m) {
+      const double xv = mat_at(A, m, i);
+      s = fma(xv, vb[h * pp + m], s);
+      cn = fma(xv, xv, cn);
+    }
+    vu[h * pp + i] = s;
+    part_q = vb[h * pp + i] * vb[h * pp + i];
+    if (h == 0 && i < n) {
+      part_l = -2.0 * log(mat_at(A, i, i));
+      va[i] = cn;                                // (phi^-1)_II; a (sin) is no longer read
+    }
+  }
+  __syncthreads();
+  // Gamma u (columns of the symmetric Gamma, coalesced) for the rho term
+  double part_g = 0.0;
+  if (tid < 2 * pp) {
+    const int i = tid % pp, h = tid / pp;
+    if (i < n) {
+      double s = 0.0;
+      for (int m = 0; m < n; ++m) s = fma(S.gamma[(size_t)m * n + i], vu[h * pp + m], s);
+      part_g = s * vu[h * pp + i];
+    }
+  }
+  // tr(phi^-1 Gamma) = |X G|_F^2, G = chol(Gamma): tiles (X G)_IJ = sum_{K=J}^{I} X_IK G_KJ
+  double part_t = 0.0;
+  {
+    int task = 0;
+#pragma unroll
+    for (int I = 0; I < T; ++I)
+#pragma unroll
+      for (int J = 0; J <= I; ++J, ++task) {
+        if ((task & 3) != w) continue;
+        v4d r{0.0, 0.0, 0.0, 0.0};
+        for (int K = J; K <= I; ++K)
+          r = mma(ld_rm(A + ps::tix(I, K) * 256, c16, q), ld_cm(S.gch_tiles + ps::tix(K, J) * 256, c16, q), r);
+        part_t += (r[0] * r[0] + r[1] * r[1]) + (r[2] * r[2] + r[3] * r[3]);
+      }
+  }
+  const double quad = block_sum(part_q, red);
+  const double ldet = block_sum(part_l, red);
+  const double ugu = block_sum(part_g, red);
+  const double tr = block_sum(part_t, red);
+  if (tid < n) {
+    const double u0 = vu[tid], u1 = vu[pp + tid];
+    S.dkap_e[((size_t)c * n + tid) * S.ka + k] = 0.5 * (u0 * u0 + u1 * u1) - va[tid];
+    double *v2 = S.v2 + ((size_t)c * n + tid) * S.pp;
+    v2[2 * k] = -u0;
+    v2[2 * k + 1] = -u1;
+  }
+  if (tid == 0) {
+    double *o = S.quad_k + ((size_t)c * S.ka + k) * 2;
+    o[0] = quad;
+    o[1] = ldet;
+    S.drho_e[(size_t)c * S.ka + k] = 0.5 * ugu - tr;
+    S.flag2[(size_t)c * S.ka + k] = ok ? 0 : ps::kFlagNotPD;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Prior of the diagonal items: red-noise frequencies beyond the common process
+// (phi_k = diag kappa_.k) and DM (diag kappa_dm): one thread per (chain, pulsar,
+// item), items k in [nf_gw, ka) then the DM frequencies.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_std_prior_diag(StdDev S, const double *__restrict__ x) {
+  const int nrn = S.ka - S.nf_gw, per = nrn + S.kdm;
+  const size_t total = (size_t)S.n_chains * S.n_psr * per;
+  const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int it = (int)(e % per);
+  const size_t ci = e / per;
+  const int I = (int)(ci % S.n_psr), c = (int)(ci / S.n_psr);
+  const double *xc = x + (size_t)c * S.d;
+  int k, col;
+  double kap;
+  if (it < nrn) {
+    k = S.nf_gw + it;
+    col = 2 * k;
+    kap = ps::spec_value(S, xc, 1, I, k);
+  } else {
+    k = it - nrn;
+    col = 2 * S.ka + 2 * k;
+    kap = ps::spec_value(S, xc, 2, I, k);
+  }
+  const double *av = S.avec + ((size_t)c * S.n_psr + I) * S.pp;
+  const double a0 = av[col], a1 = av[col + 1];
+  const double ik = 1.0 / kap;
+  const double u0 = a0 * ik, u1 = a1 * ik;
+  double *v2 = S.v2 + ((size_t)c * S.n_psr + I) * S.pp;
+  v2[col] = -u0;
+  v2[col + 1] = -u1;
+  const double dk = 0.5 * (u0 * u0 + u1 * u1) - ik;
+  if (it < nrn) S.dkap_e[((size_t)c * S.n_psr + I) * S.ka + k] = dk;
+  else S.ddm_e[((size_t)c * S.n_psr + I) * S.kdm + k] = dk;
+  double *o = S.diag_q + (((size_t)c * S.n_psr + I) * (S.ka + S.kdm) + (it < nrn ? k : S.ka + k)) * 2;
+  o[0] = a0 * u0 + a1 * u1;
+  o[1] = log(kap);
+  S.flag3[((size_t)c * S.n_psr + I) * (S.ka + S.kdm) + (it < nrn ? k : S.ka + k)] =
+      ((kap > 0.0) && isfinite(kap)) ? 0 : ps::kFlagNotPD;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint per (pulsar, chain): dlogp/dz and dlogp/dD.
+// ---------------------------------------------------------------------------
+template <int T>
+__global__ __launch_bounds__(256) void k_std_bwd(StdDev S, const double *__restrict__ x,
+                                                  double *__restrict__ grad) {
+  extern __shared__ double lds[];
+  constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256;
+  double *A = lds;
+  double *vv = A + NE, *vz = vv + pp, *vw = vz + pp, *vh = vw + pp, *gd = vh + pp;
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x / S.n_psr, I = blockIdx.x - c * S.n_psr;
+  const double *xc = x + (size_t)c * S.d;
+  const int P = S.P;
+  const size_t vb = ((size_t)c * S.n_psr + I) * pp;
+  const double *xi = S.xinv + ((size_t)c * S.n_psr + I) * NE;
+  for (int e = tid; e < NE; e += 256) A[e] = xi[e];
+  for (int r = tid; r < pp; r += 256) {
+    vv[r] = (r < P) ? S.v1[vb + r] + S.v2[vb + (P - 1 - r)] : 0.0;
+    vz[r] = (r < P) ? xc[S.off_z + I * P + (P - 1 - r)] : 0.0;
+    vh[r] = S.ahat[vb + r];
+  }
+  __syncthreads();
+  // w~ = X v~  (dlogp/dz~)
+  if (tid < pp) {
+    double s = 0.0;
+    for (int k = 0; k <= tid; ++k) s = fma(mat_at(A, tid, k), vv[k], s);
+    vw[tid] = s;
+    if (tid < P) grad[(size_t)c * S.d + S.off_z + I * P + (P - 1 - tid)] = s;
+  }
+  __syncthreads();
+  // per column r: (Sigma v)~_r = sum_a X_ar w~_a, Sigma~_rr = sum_a X_ar^2, and the
+  // suffix sum T_r = sum_a X_ar w~_a (sum_{b>a} X_br z~_b + X_ar z~_a / 2)
+  if (tid < P) {
+    double sv = 0.0, ss = 0.0, tt = 0.0, suf = 0.0;
+    for (int a = pp - 1; a >= tid; --a) {
+      const double xv = mat_at(A, a, tid);
+      sv = fma(xv, vw[a], sv);
+      ss = fma(xv, xv, ss);
+      tt = fma(xv * vw[a], fma(0.5 * xv, vz[a], suf), tt);
+      suf = fma(xv, vz[a], suf);
+    }
+    const double Dv = ps::curn_var(S, xc, I, P - 1 - tid);
+    gd[tid] = (vh[tid] * sv + tt + 0.5 * ss) / (Dv * Dv);
+  }
+  __syncthreads();
+  if (tid < S.ka) {
+    const int r0 = P - 1 - 2 * tid, r1 = r0 - 1;
+    S.dD_rn[((size_t)c * S.n_psr + I) * S.ka + tid] = gd[r0] + gd[r1];
+  } else if (tid >= 64 && tid - 64 < S.kdm) {
+    const int k = tid - 64, r0 = P - 1 - (2 * S.ka + 2 * k), r1 = r0 - 1;
+    S.dD_dm[((size_t)c * S.n_psr + I) * S.kdm + k] = gd[r0] + gd[r1];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Assembly per chain: log p, the hyper-parameter gradient and the status.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
+                                                       double *__restrict__ logp, double *__restrict__ grad,
+                                                       int32_t *__restrict__ status, ps::StdKick kick,
+                                                       int has_kick) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x, c = blockIdx.x;
+  const int n = S.n_psr;
+  const double *xc = x + (size_t)c * S.d;
+  double *gc = grad + (size_t)c * S.d;
+  const double beta = S.beta ? S.beta[c] : 1.0;
+  // input checks
+  int bad_box = 0, bad_in = 0;
+  for (int i = tid; i < S.n_theta; i += 256) {
+    const double v = xc[i];
+    if (!(v >= S.prior_lo[i] && v <= S.prior_hi[i])) bad_box = 1;
+  }
+  for (int i = S.n_theta + tid; i < S.d; i += 256)
+    if (!isfinite(xc[i])) bad_in = 1;
+  // factorisation flags
+  int fl = 0;
+  for (int i = tid; i < n; i += 256) fl |= S.flag1[(size_t)c * n + i];
+  for (int k = tid; k < S.nf_gw; k += 256) fl |= S.flag2[(size_t)c * S.ka + k];
+  const int nd = n * (S.ka + S.kdm);
+  for (int i = tid; i < nd; i += 256) {
+    const int kk = i % (S.ka + S.kdm);
+    if (kk >= S.nf_gw) fl |= S.flag3[(size_t)c * nd + i];
+  }
+  // log p parts
+  double lp = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    const double *o = S.lik + ((size_t)c * n + i) * 2;
+    lp += o[0] + o[1];
+  }
+  for (int k = tid; k < S.nf_gw; k += 256) {
+    const double *o = S.quad_k + ((size_t)c * S.ka + k) * 2;
+    lp += -0.5 * o[0] - (n * ps::kLn2Pi + o[1]);
+  }
+  for (int i = tid; i < nd; i += 256) {
+    const int kk = i % (S.ka + S.kdm);
+    if (kk < S.nf_gw) continue;
+    const double *o = S.diag_q + ((size_t)c * nd + i) * 2;
+    lp += -0.5 * o[0] - (ps::kLn2Pi + o[1]);
+  }
+  // hyper-parameter gradient: every process entry is a sum over its frequencies
+  for (int e = tid; e < S.n_theta; e += 256) {
+    int proc, I, slot, K;
+    if (e < S.off_rn) { proc = 0; I = 0; slot = e - S.off_gw; K = S.nf_gw; }
+    else if (e < S.off_dm) { proc = 1; I = (e - S.off_rn) / S.w_rn; slot = (e - S.off_rn) - I * S.w_rn; K = S.nf_rn; }
+    else { proc = 2; I = (e - S.off_dm) / S.w_dm; slot = (e - S.off_dm) - I * S.w_dm; K = S.kdm; }
+    double g = 0.0;
+    const int k0 = S.free_spec ? slot : 0, k1 = S.free_spec ? slot + 1 : K;
+    for (int k = k0; k < k1; ++k) {
+      double dd;
+      if (proc == 0) {
+        dd = S.drho_e[(size_t)c * S.ka + k];
+        for (int J = 0; J < n; ++J) dd += S.dD_rn[((size_t)c * n + J) * S.ka + k];
+      } else if (proc == 1) {
+        dd = S.dkap_e[((size_t)c * n + I) * S.ka + k] + S.dD_rn[((size_t)c * n + I) * S.ka + k];
+      } else {
+        dd = S.ddm_e[((size_t)c * n + I) * S.kdm + k] + S.dD_dm[((size_t)c * n + I) * S.kdm + k];
+      }
+      const double v = ps::spec_value(S, xc, proc, I, k) * dd;
+      if (S.free_spec) g += ps::kLn10 * v;
+      else g += (slot == 0) ? 2.0 * ps::kLn10 * v : -S.lnfy[k] * v;
+    }
+    gc[e] = g;
+  }
+  // reduce the flags and log p
+  {
+    double v = lp;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int bb = __any(bad_box), bi = __any(bad_in), bf = __any(fl != 0);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __shared__ int sb[4][3];
+    if ((tid & 63) == 0) {
+      sb[tid >> 6][0] = bb;
+      sb[tid >> 6][1] = bi;
+      sb[tid >> 6][2] = bf;
+    }
+    __syncthreads();
+    lp = (red[0] + red[1]) + (red[2] + red[3]);
+    bad_box = sb[0][0] | sb[1][0] | sb[2][0] | sb[3][0];
+    bad_in = sb[0][1] | sb[1][1] | sb[2][1] | sb[3][1];
+    fl = sb[0][2] | sb[1][2] | sb[2][2] | sb[3][2];
+  }
+  lp += S.prior_const;
+  // output finiteness
+  int nonfin = !isfinite(lp);
+  __syncthreads();
+  for (int i = tid; i < S.d; i += 256)
+    if (!isfinite(gc[i])) nonfin = 1;
+  nonfin = __syncthreads_or(nonfin);
+  int st = PTAFS_ST_OK;
+  if (bad_box) st = PTAFS_ST_PRIOR;
+  else if (bad_in) st = PTAFS_ST_NONFINITE;
+  else if (fl) st = PTAFS_ST_NOTPD;
+  else if (nonfin) st = PTAFS_ST_NONFINITE;
+  (void)beta;
+  if (st != PTAFS_ST_OK)
+    for (int i = tid; i < S.d; i += 256) gc[i] = 0.0;
+  if (tid == 0) {
+    logp[c] = (st == PTAFS_ST_OK) ? lp : -INFINITY;
+    status[c] = st;
+  }
+  if (has_kick) {
+    // inside a trajectory: kick and drift of this chain (every entry of its
+    // gradient row is final after the barrier)
+    __syncthreads();
+    if (tid == 0 && kick.n_invalid && st != PTAFS_ST_OK) kick.n_invalid[c] += 1;
+    double *xw = kick.x + (size_t)c * S.d, *pw = kick.p + (size_t)c * S.d;
+    for (int i = tid; i < S.d; i += 256) {
+      const double pi = pw[i] + kick.eps * gc[i];
+      pw[i] = pi;
+      xw[i] += kick.eps * (kick.inv_mass ? kick.inv_mass[i] : 1.0) * pi;
+    }
+  }
+}
+
+template <int T>
+hipError_t set_attr_t() {
+  hipError_t e = hipFuncSetAttribute((const void *)k_std_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_bytes<T>());
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_std_prior_dense<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_bytes<T>());
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void *)k_std_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds_bytes<T>());
+}
+
+}  // namespace
+
+namespace psk {
+
+hipError_t init_attributes() {
+  hipError_t e;
+  if ((e = set_attr_t<1>()) != hipSuccess) return e;
+  if ((e = set_attr_t<2>()) != hipSuccess) return e;
+  if ((e = set_attr_t<3>()) != hipSuccess) return e;
+  if ((e = set_attr_t<4>()) != hipSuccess) return e;
+  if ((e = set_attr_t<5>()) != hipSuccess) return e;
+  if ((e = set_attr_t<6>()) != hipSuccess) return e;
+  if ((e = set_attr_t<7>()) != hipSuccess) return e;
+  return set_attr_t<8>();
+}
+
+#define PS_DISPATCH(TT, KERNEL, GRID, ...)                                                          \
+  switch (TT) {                                                                                     \
+    case 1: hipLaunchKernelGGL(KERNEL<1>, dim3(GRID), dim3(256), lds_bytes<1>(), s, __VA_ARGS__); break; \
+    case 2: hipLaunchKernelGGL(KERNEL<2>, dim3(GRID), dim3(256), lds_bytes<2>(), s, __VA_ARGS__); break; \
+    case 3: hipLaunchKernelGGL(KERNEL<3>, dim3(GRID), dim3(256), lds_bytes<3>(), s, __VA_ARGS__); break; \
+    case 4: hipLaunchKernelGGL(KERNEL<4>, dim3(GRID), dim3(256), lds_bytes<4>(), s, __VA_ARGS__); break; \
+    case 5: hipLaunchKernelGGL(KERNEL<5>, dim3(GRID), dim3(256), lds_bytes<5>(), s, __VA_ARGS__); break; \
+    case 6: hipLaunchKernelGGL(KERNEL<6>, dim3(GRID), dim3(256), lds_bytes<6>(), s, __VA_ARGS__); break; \
+    case 7: hipLaunchKernelGGL(KERNEL<7>, dim3(GRID), dim3(256), lds_bytes<7>(), s, __VA_ARGS__); break; \
+    case 8: hipLaunchKernelGGL(KERNEL<8>, dim3(GRID), dim3(256), lds_bytes<8>(), s, __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                                           \
+  }
+
+hipError_t launch_std_fwd(const StdDev &S, const double *x, hipStream_t s) {
+  const int grid = S.n_chains * S.n_psr;
+  if (grid == 0) return hipSuccess;
+  PS_DISPATCH(S.tp, k_std_fwd, grid, S, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_std_prior(const StdDev &S, const double *x, hipStream_t s) {
+  if (S.nf_gw > 0) {
+    const int grid = S.n_chains * S.nf_gw;
+    PS_DISPATCH(S.tg, k_std_prior_dense, grid, S, x);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const size_t items = (size_t)S.n_chains * S.n_psr * (S.ka - S.nf_gw + S.kdm);
+  if (items) hipLaunchKernelGGL(k_std_prior_diag, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, S, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_std_bwd(const StdDev &S, const double *x, double *grad, hipStream_t s) {
+  const int grid = S.n_chains * S.n_psr;
+  if (grid == 0) return hipSuccess;
+  PS_DISPATCH(S.tp, k_std_bwd, grid, S, x, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_std_finalize(const StdDev &S, const double *x, double *logp, double *grad,
+                               int32_t *status, hipStream_t s, const ps::StdKick *kick) {
+  if (S.n_chains == 0) return hipSuccess;
+  const ps::StdKick k = kick ? *kick : ps::StdKick{};
+  hipLaunchKernelGGL(k_std_finalize, dim3(S.n_chains), dim3(256), 0, s, S, x, logp, grad, status, k,
+                     kick ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace psk

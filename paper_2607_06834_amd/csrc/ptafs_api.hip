@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.h"
+#include "pool.h"
 
 constexpr int kDefaultTilesPerChunk = 16;
 
@@ -493,6 +494,17 @@ int scratch_ptr(int dev, void **out) {
 }
 
 }  // namespace
+
+namespace ptr {
+int device_pool(int dev, hipMemPool_t *pool, hipStream_t *aux) {
+  DevRes r;
+  const int rc = device_res(dev, &r);
+  if (rc) return rc;
+  *pool = r.pool;
+  *aux = r.aux;
+  return PTAFS_OK;
+}
+}  // namespace ptr
 
 extern "C" {
 
