@@ -349,6 +349,21 @@ def main():
 
     torch.cuda.set_device(0)
     if args.std_only:
+        if args.profile_evals:
+            # a fixed number of standardized-form evaluations and nothing else
+            import numpy as np
+            dss = synth.cfg2()
+            gs = api.StdDataset(dss)
+            th = synth.injected_theta(dss, 203)
+            rng = np.random.default_rng(204)
+            th = np.clip(th + rng.uniform(-0.2, 0.2, (args.chains, th.size)), dss["prior_lo"], dss["prior_hi"])
+            Xs = np.concatenate([th, rng.standard_normal((args.chains, gs.d - th.shape[1]))], axis=1)
+            xs = torch.tensor(Xs, device="cuda")
+            for _ in range(args.profile_evals):
+                gs.ptafs_std_logp_grad(xs)
+            torch.cuda.synchronize()
+            print(json.dumps({"std_profile_evals": args.profile_evals, "chains": args.chains}))
+            return
         print(json.dumps({"std_form": std_bench(n_chains=args.chains, n_leapfrog=args.leapfrog,
                                                 steps=args.steps, warmup=args.warmup)}))
         return

@@ -61,21 +61,29 @@ __device__ inline double rcp_nr(double a) {
   return y;
 }
 
-// Row-major tile loads for the MFMA operands (see the convention above).
+// LDS tiles are row-major with the column index XOR-ed with the row index,
+// element (r, c) at 16 r + (c ^ r): the 16 lanes that read one column (a row
+// each), or one row (a column each), or an MFMA operand, hit 16 different
+// banks.
+__device__ inline int sw(int r, int c) { return (r << 4) + (c ^ r); }
+
+// Tile loads for the MFMA operands (see the convention above).
 __device__ inline v4d ld_rm(const double *t, int c, int q) {   // Y[c][q+4s]: A of Y, B of Y^T
-  const double *p = t + c * 16 + q;
-  return v4d{p[0], p[4], p[8], p[12]};
+  return v4d{t[sw(c, q)], t[sw(c, q + 4)], t[sw(c, q + 8)], t[sw(c, q + 12)]};
 }
 __device__ inline v4d ld_cm(const double *t, int c, int q) {   // Y[q+4s][c]: B of Y, result of Y
-  const double *p = t + 16 * q + c;
-  return v4d{p[0], p[64], p[128], p[192]};
+  return v4d{t[sw(q, c)], t[sw(q + 4, c)], t[sw(q + 8, c)], t[sw(q + 12, c)]};
 }
 __device__ inline void st_cm(double *t, int c, int q, v4d v) {
-  double *p = t + 16 * q + c;
-  p[0] = v[0];
-  p[64] = v[1];
-  p[128] = v[2];
-  p[192] = v[3];
+  t[sw(q, c)] = v[0];
+  t[sw(q + 4, c)] = v[1];
+  t[sw(q + 8, c)] = v[2];
+  t[sw(q + 12, c)] = v[3];
+}
+// the same from a plain row-major tile in global memory
+__device__ inline v4d ldg_cm(const double *t, int c, int q) {
+  const double *p = t + 16 * q + c;
+  return v4d{p[0], p[64], p[128], p[192]};
 }
 __device__ inline v4d mma(v4d a, v4d b, v4d acc) {
   acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc, 0, 0, 0);
@@ -87,40 +95,76 @@ __device__ inline v4d mma(v4d a, v4d b, v4d acc) {
 
 // Factorise the symmetric 16x16 tile t (both triangles present) and replace it
 // by the inverse of its lower Cholesky factor (lower, zeros above).  Executed
-// by one wave; lane r < 16 works on row r.  Returns false in every lane when a
-// pivot is not positive and finite.
-__device__ bool diag_factor_inverse(double *t, int lane) {
+// by one wave with ws, 48 doubles of LDS, as scratch.  The factorisation is
+// right-looking with lane r holding row r: the pivot and the next row's
+// multiplier come by readlane, the rest of column j of L by broadcast reads of
+// an LDS copy.  The inverse is solved by columns, lane c computing column c of
+// X from L x = e_c with L read from the tile (the same address in every lane).
+// Returns false in every lane when a pivot is not positive and finite.
+__device__ inline void wave_sync() {   // LDS writes of the wave visible to its later reads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bool diag_factor_inverse(double *t, double *ws, int lane) {
   const int r = lane & 15;
+  double *idg = ws + 32;   // 1 / L_jj
   double row[16];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) row[c] = t[r * 16 + c];
+  for (int c = 0; c < 16; ++c) row[c] = t[sw(r, c)];
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const double piv = readlane_d(row[j], j);
     ok = ok && (piv > 0.0) && isfinite(piv);
-    const double l = row[j] * rsqrt_nr(piv);       // L[r][j] (r >= j); lane j: sqrt(piv)
+    const double rs = rsqrt_nr(piv);
+    const double l = row[j] * rs;       // L[r][j] (r >= j)
     row[j] = l;
+    if (lane == 0) idg[j] = rs;
+    if (j < 15) {
+      double *bc = ws + 16 * (j & 1);   // two buffers: pivot j + 1 never overwrites what j still reads
+      if (lane < 16) bc[r] = l;
+      wave_sync();
+      row[j + 1] = fma(-l, readlane_d(l, j + 1), row[j + 1]);
 #pragma unroll
-    for (int k = j + 1; k < 16; ++k) row[k] = fma(-l, readlane_d(l, k), row[k]);
-  }
-  // X = L^-1: row m of X from the rows above it, acc[c] = sum_{k<m} L[r][k] X[k][c]
-  double acc[16], xr[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) acc[c] = xr[c] = 0.0;
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const double id = rcp_nr(readlane_d(row[m], m));
-#pragma unroll
-    for (int c = 0; c <= m; ++c) {
-      const double xmc = readlane_d((((c == m) ? 1.0 : 0.0) - acc[c]) * id, m);
-      xr[c] = (r == m) ? xmc : xr[c];
-      acc[c] = fma(row[m], xmc, acc[c]);
+      for (int k = j + 2; k < 16; ++k) row[k] = fma(-l, bc[k], row[k]);
     }
+    __builtin_amdgcn_sched_barrier(0);   // one pivot's loads and updates together (registers)
   }
+  // L (lower triangle) back to the tile
   if (lane < 16) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) t[r * 16 + c] = (c <= r) ? xr[c] : 0.0;
+    for (int c = 0; c < 16; ++c)
+      if (c <= r) t[sw(r, c)] = row[c];
+  }
+  wave_sync();
+  // column c of X: x_m = (delta_mc - sum_{k<m} L_mk x_k) / L_mm, zero for m < c;
+  // column m + 1 of L is loaded while column m is applied.  The solve and the
+  // stores sit in one branch: the wave's loads all precede its stores.
+  if (lane < 16) {
+    double acc[16], xc[16], lc[2][16], dg[2];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) acc[m] = 0.0;
+    dg[0] = idg[0];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) lc[0][k] = t[sw(k, 0)];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int b = m & 1;
+      if (m < 15) {
+        dg[b ^ 1] = idg[m + 1];
+#pragma unroll
+        for (int k = m + 2; k < 16; ++k) lc[b ^ 1][k] = t[sw(k, m + 1)];
+      }
+      const double xm = (((m == r) ? 1.0 : 0.0) - acc[m]) * dg[b];
+      xc[m] = xm;
+#pragma unroll
+      for (int k = m + 1; k < 16; ++k) acc[k] = fma(lc[b][k], xm, acc[k]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) t[sw(m, r)] = (m >= r) ? xc[m] : 0.0;
   }
   return ok;
 }
@@ -128,13 +172,14 @@ __device__ bool diag_factor_inverse(double *t, int lane) {
 // In-place X = L^-1 of the symmetric positive-definite matrix held as lower
 // tiles in A (diagonal tiles with both triangles).  All 256 threads call it.
 // flag (LDS) is set to 0 when a pivot fails; the return value is the flag.
+// ws: 48 doubles of LDS scratch for the diagonal tiles.
 template <int T>
-__device__ bool factor_invert(double *A, int tid, int *flag) {
+__device__ __forceinline__ bool factor_invert(double *A, int tid, int *flag, double *ws) {
   const int w = tid >> 6, lane = tid & 63, c = lane & 15, q = lane >> 4;
-#pragma unroll
+#pragma unroll 1
   for (int J = 0; J < T; ++J) {
     if (w == 0) {
-      const bool ok = diag_factor_inverse(A + ps::tix(J, J) * 256, lane);
+      const bool ok = diag_factor_inverse(A + ps::tix(J, J) * 256, ws, lane);
       if (lane == 0 && !ok) *flag = 0;
     }
     __syncthreads();
@@ -146,22 +191,22 @@ __device__ bool factor_invert(double *A, int tid, int *flag) {
       st_cm(t, c, q, r);
     }
     __syncthreads();
-    // trailing: A_IK -= L_IJ L_KJ^T, J < K <= I
-    int task = 0;
-#pragma unroll
-    for (int K = J + 1; K < T; ++K)
-#pragma unroll
-      for (int I = K; I < T; ++I, ++task) {
-        if ((task & 3) != w) continue;
-        double *t = A + ps::tix(I, K) * 256;
-        const v4d r = mma(-ld_rm(A + ps::tix(I, J) * 256, c, q), ld_rm(A + ps::tix(K, J) * 256, c, q),
-                          ld_cm(t, c, q));
-        st_cm(t, c, q, r);
-      }
+    // trailing: A_IK -= L_IJ L_KJ^T, J < K <= I, the (K, I) pairs in order dealt
+    // to the waves in turn
+    const int m = T - 1 - J;
+    for (int task = w; task < m * (m + 1) / 2; task += 4) {
+      int K = J + 1, rem = task;
+      while (rem >= T - K) { rem -= T - K; ++K; }
+      const int I = K + rem;
+      double *t = A + ps::tix(I, K) * 256;
+      const v4d r = mma(-ld_rm(A + ps::tix(I, J) * 256, c, q), ld_rm(A + ps::tix(K, J) * 256, c, q),
+                        ld_cm(t, c, q));
+      st_cm(t, c, q, r);
+    }
     __syncthreads();
   }
   // X by block rows: X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ (rows above are X already)
-#pragma unroll
+#pragma unroll 1
   for (int I = 1; I < T; ++I) {
     v4d res[2];
 #pragma unroll
@@ -187,7 +232,7 @@ __device__ bool factor_invert(double *A, int tid, int *flag) {
 }
 
 __device__ inline double mat_at(const double *A, int r, int c) {   // lower element (r >= c)
-  return A[ps::tix(r >> 4, c >> 4) * 256 + ((r & 15) << 4) + (c & 15)];
+  return A[ps::tix(r >> 4, c >> 4) * 256 + sw(r & 15, c & 15)];
 }
 
 // Block sum of one value per thread (256 threads); every thread gets the sum.
@@ -203,7 +248,9 @@ __device__ inline double block_sum(double v, double *red) {
 
 template <int T>
 constexpr size_t lds_bytes() {
-  return (size_t)(ps::ntiles(T) * 256 + 6 * 16 * T + 8) * sizeof(double) + 16;
+  // tiles, six vectors of 16 T, 8 reduction slots, the flag (two doubles' room)
+  // and 48 doubles of scratch for the diagonal tiles
+  return (size_t)(ps::ntiles(T) * 256 + 6 * 16 * T + 8 + 2 + 48) * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -242,14 +289,14 @@ __global__ __launch_bounds__(256) void k_std_fwd(StdDev S, const double *__restr
         v += 1.0;
       }
     }
-    A[e] = v;
+    A[(tt << 8) + sw(rr, cc)] = v;
   }
   for (int r = tid; r < pp; r += 256) {
     vd[r] = (r < P) ? beta * S.dvec[(size_t)I * pp + r] : 0.0;
     vz[r] = (r < P) ? xc[S.off_z + I * P + (P - 1 - r)] : 0.0;
   }
   __syncthreads();
-  const bool ok = factor_invert<T>(A, tid, flag);
+  const bool ok = factor_invert<T>(A, tid, flag, red + 10);
   // t = X beta d~
   if (tid < pp) {
     double s = 0.0;
@@ -275,6 +322,7 @@ __global__ __launch_bounds__(256) void k_std_fwd(StdDev S, const double *__restr
   double part_d = 0.0, part_q = 0.0, part_j = 0.0;
   if (tid < pp) {
     double s = 0.0;
+#pragma unroll 16
     for (int k = 0; k < pp; ++k) s = fma(s0[(size_t)k * pp + tid], va[k], s);
     const double dr = (tid < P) ? S.dvec[(size_t)I * pp + tid] : 0.0;
     S.v1[vb + tid] = beta * (dr - s);
@@ -319,7 +367,7 @@ __global__ __launch_bounds__(256) void k_std_prior_dense(StdDev S, const double 
     const int r = 16 * TI + rr, col = 16 * (tt - ps::tix(TI, 0)) + cc;
     double v = rho * S.gam_tiles[e];
     if (r == col) v += (r < n) ? ((k < S.nf_rn) ? ps::spec_value(S, xc, 1, r, k) : 0.0) : 1.0;
-    A[e] = v;
+    A[(tt << 8) + sw(rr, cc)] = v;
   }
   for (int i = tid; i < pp; i += 256) {
     const double *av = S.avec + ((size_t)c * n + i) * S.pp;
@@ -328,7 +376,7 @@ __global__ __launch_bounds__(256) void k_std_prior_dense(StdDev S, const double 
   }
   if (tid == 0) *flag = 1;
   __syncthreads();
-  const bool ok = factor_invert<T>(A, tid, flag);
+  const bool ok = factor_invert<T>(A, tid, flag, red + 10);
   // y = X a (rows), then u = X^T y (columns), for sin and cos
   if (tid < 2 * pp) {
     const int i = tid % pp, h = tid / pp;
@@ -375,7 +423,7 @@ __global__ __launch_bounds__(256) void k_std_prior_dense(StdDev S, const double 
         if ((task & 3) != w) continue;
         v4d r{0.0, 0.0, 0.0, 0.0};
         for (int K = J; K <= I; ++K)
-          r = mma(ld_rm(A + ps::tix(I, K) * 256, c16, q), ld_cm(S.gch_tiles + ps::tix(K, J) * 256, c16, q), r);
+          r = mma(ld_rm(A + ps::tix(I, K) * 256, c16, q), ldg_cm(S.gch_tiles + ps::tix(K, J) * 256, c16, q), r);
         part_t += (r[0] * r[0] + r[1] * r[1]) + (r[2] * r[2] + r[3] * r[3]);
       }
   }
@@ -542,6 +590,25 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
     const double *o = S.diag_q + ((size_t)c * nd + i) * 2;
     lp += -0.5 * o[0] - (ps::kLn2Pi + o[1]);
   }
+  // d/drho_k in total: the explicit prior part plus the transform's part summed
+  // over the pulsars, 8 threads per frequency, partials combined in a fixed order
+  __shared__ double drho_part[8][ps::kMaxRhoK];
+  __shared__ double drho_tot[ps::kMaxRhoK];
+  {
+    const int k = tid >> 3, h = tid & 7;
+    double sacc = 0.0;
+    if (k < S.nf_gw)
+      for (int J = h; J < n; J += 8) sacc += S.dD_rn[((size_t)c * n + J) * S.ka + k];
+    if (k < ps::kMaxRhoK) drho_part[h][k] = sacc;
+    __syncthreads();
+    if (tid < S.nf_gw) {
+      double t = S.drho_e[(size_t)c * S.ka + tid];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) t += drho_part[q][tid];
+      drho_tot[tid] = t;
+    }
+    __syncthreads();
+  }
   // hyper-parameter gradient: every process entry is a sum over its frequencies
   for (int e = tid; e < S.n_theta; e += 256) {
     int proc, I, slot, K;
@@ -553,8 +620,7 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
     for (int k = k0; k < k1; ++k) {
       double dd;
       if (proc == 0) {
-        dd = S.drho_e[(size_t)c * S.ka + k];
-        for (int J = 0; J < n; ++J) dd += S.dD_rn[((size_t)c * n + J) * S.ka + k];
+        dd = drho_tot[k];
       } else if (proc == 1) {
         dd = S.dkap_e[((size_t)c * n + I) * S.ka + k] + S.dD_rn[((size_t)c * n + I) * S.ka + k];
       } else {

@@ -14,6 +14,7 @@ constexpr double kLn10 = 2.30258509299404568401799145468;
 constexpr double kLn2Pi = 1.83787706640934548356065947281;
 constexpr int kThreads = 256;                    // threads per problem workgroup
 constexpr int kMaxTiles = 8;                     // 16-wide tiles per dimension (128)
+constexpr int kMaxRhoK = 32;                     // frequencies of the common process (>= PTAFS_MAX_HARM)
 
 // Lower tiles of a 16T x 16T matrix: tile (I, J), J <= I, at I (I + 1) / 2 + J,
 // row-major inside (element (r, c) of the tile at 16 r + c).
