@@ -107,7 +107,9 @@ __device__ inline void wave_sync() {   // LDS writes of the wave visible to its 
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ bool diag_factor_inverse(double *t, double *ws, int lane) {
+template <bool LZ>
+__device__ __forceinline__ bool diag_factor_inverse(double *t, double *ws, int lane, const double *zJ,
+                                                    double *lzJ, double *yJ) {
   const int r = lane & 15;
   double *idg = ws + 32;   // 1 / L_jj
   double row[16];
@@ -132,11 +134,17 @@ __device__ __forceinline__ bool diag_factor_inverse(double *t, double *ws, int l
     }
     __builtin_amdgcn_sched_barrier(0);   // one pivot's loads and updates together (registers)
   }
-  // L (lower triangle) back to the tile
+  // L (lower triangle) back to the tile; with LZ, the tile's part of L z
   if (lane < 16) {
 #pragma unroll
     for (int c = 0; c < 16; ++c)
       if (c <= r) t[sw(r, c)] = row[c];
+    if (LZ) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) s = fma((c <= r) ? row[c] : 0.0, zJ[c], s);
+      lzJ[r] += s;
+    }
   }
   wave_sync();
   // column c of X: x_m = (delta_mc - sum_{k<m} L_mk x_k) / L_mm, zero for m < c;
@@ -165,66 +173,149 @@ __device__ __forceinline__ bool diag_factor_inverse(double *t, double *ws, int l
     }
 #pragma unroll
     for (int m = 0; m < 16; ++m) t[sw(m, r)] = (m >= r) ? xc[m] : 0.0;
+    if (LZ) {   // y = X^T z: the panel tiles' part of L z is A_IJ y
+      double s = 0.0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) s = fma((m >= r) ? xc[m] : 0.0, zJ[m], s);
+      yJ[r] = s;
+    }
   }
   return ok;
+}
+
+// Trailing update A_IK -= L_IJ L_KJ^T of two tiles at once (two independent
+// MFMA chains); the second is computed but not stored when has1 is false.
+__device__ inline void trail_pair(double *A, int J, int I0, int K0, int I1, int K1, bool has1, int c, int q) {
+  double *t0 = A + ps::tix(I0, K0) * 256, *t1 = A + ps::tix(I1, K1) * 256;
+  const v4d a0 = ld_rm(A + ps::tix(I0, J) * 256, c, q), b0 = ld_rm(A + ps::tix(K0, J) * 256, c, q);
+  const v4d a1 = ld_rm(A + ps::tix(I1, J) * 256, c, q), b1 = ld_rm(A + ps::tix(K1, J) * 256, c, q);
+  const v4d r0 = mma(-a0, b0, ld_cm(t0, c, q));
+  const v4d r1 = mma(-a1, b1, ld_cm(t1, c, q));
+  st_cm(t0, c, q, r0);
+  if (has1) st_cm(t1, c, q, r1);
+}
+
+// (K, I) of trailing task n at step J: the pairs J < K <= I < T in order
+template <int T>
+__device__ inline void task_ki(int J, int n, int &K, int &I) {
+  K = J + 1;
+  while (n >= T - K) { n -= T - K; ++K; }
+  I = K + n;
 }
 
 // In-place X = L^-1 of the symmetric positive-definite matrix held as lower
 // tiles in A (diagonal tiles with both triangles).  All 256 threads call it.
 // flag (LDS) is set to 0 when a pivot fails; the return value is the flag.
-// ws: 48 doubles of LDS scratch for the diagonal tiles.
-template <int T>
-__device__ __forceinline__ bool factor_invert(double *A, int tid, int *flag, double *ws) {
+// ws: 64 doubles of LDS scratch.  With LZ the product L z of the factor with
+// the vector z (LDS, 16 T) is accumulated into lz (LDS, zero on entry).
+//
+// Factorisation: right-looking by block columns with a lookahead of one: at
+// step J, after the panel, wave 0 updates the next diagonal tile and
+// factorises and inverts it while waves 1-3 apply the rest of the trailing
+// update.  Inverse: X_CA = -X_CC (L_CA X_AA) for neighbouring diagonal blocks
+// A and C of s tiles, s = 1, 2, 4, ... (rows of L_CA X_AA, then columns of X_CA
+// dealt to the waves).
+template <int T, bool LZ>
+__device__ __forceinline__ bool factor_invert(double *A, int tid, int *flag, double *ws,
+                                              const double *z, double *lz) {
   const int w = tid >> 6, lane = tid & 63, c = lane & 15, q = lane >> 4;
+  double *yJ = ws + 48;
+  if (w == 0) {
+    const bool ok = diag_factor_inverse<LZ>(A, ws, lane, z, lz, yJ);
+    if (lane == 0 && !ok) *flag = 0;
+  }
+  __syncthreads();
 #pragma unroll 1
   for (int J = 0; J < T; ++J) {
-    if (w == 0) {
-      const bool ok = diag_factor_inverse(A + ps::tix(J, J) * 256, ws, lane);
-      if (lane == 0 && !ok) *flag = 0;
-    }
-    __syncthreads();
-    // panel: L_IJ = A_IJ X_JJ^T
+    // panel: L_IJ = A_IJ X_JJ^T (and L_IJ z_J = A_IJ y_J)
     const double *xjj = A + ps::tix(J, J) * 256;
     for (int I = J + 1 + w; I < T; I += 4) {
       double *t = A + ps::tix(I, J) * 256;
-      const v4d r = mma(ld_rm(t, c, q), ld_rm(xjj, c, q), v4d{0.0, 0.0, 0.0, 0.0});
-      st_cm(t, c, q, r);
-    }
-    __syncthreads();
-    // trailing: A_IK -= L_IJ L_KJ^T, J < K <= I, the (K, I) pairs in order dealt
-    // to the waves in turn
-    const int m = T - 1 - J;
-    for (int task = w; task < m * (m + 1) / 2; task += 4) {
-      int K = J + 1, rem = task;
-      while (rem >= T - K) { rem -= T - K; ++K; }
-      const int I = K + rem;
-      double *t = A + ps::tix(I, K) * 256;
-      const v4d r = mma(-ld_rm(A + ps::tix(I, J) * 256, c, q), ld_rm(A + ps::tix(K, J) * 256, c, q),
-                        ld_cm(t, c, q));
-      st_cm(t, c, q, r);
-    }
-    __syncthreads();
-  }
-  // X by block rows: X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ (rows above are X already)
-#pragma unroll 1
-  for (int I = 1; I < T; ++I) {
-    v4d res[2];
+      const v4d a = ld_rm(t, c, q);
+      const v4d r = mma(a, ld_rm(xjj, c, q), v4d{0.0, 0.0, 0.0, 0.0});
+      if (LZ) {
+        // B[k][c] = y[k] for every c: every column of the product is A_IJ y
+        const v4d yb{yJ[q], yJ[q + 4], yJ[q + 8], yJ[q + 12]};
+        const v4d u = mma(a, yb, v4d{0.0, 0.0, 0.0, 0.0});
+        if (c == 0) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int J = w + 4 * h;
-      res[h] = v4d{0.0, 0.0, 0.0, 0.0};
-      if (J < I) {
-        v4d u{0.0, 0.0, 0.0, 0.0};
-        for (int K = J; K < I; ++K)
-          u = mma(ld_rm(A + ps::tix(I, K) * 256, c, q), ld_cm(A + ps::tix(K, J) * 256, c, q), u);
-        res[h] = mma(-ld_rm(A + ps::tix(I, I) * 256, c, q), u, v4d{0.0, 0.0, 0.0, 0.0});
+          for (int v = 0; v < 4; ++v) lz[16 * I + q + 4 * v] += u[v];
+        }
+      }
+      st_cm(t, c, q, r);
+    }
+    __syncthreads();
+    if (J + 1 == T) break;
+    if (w == 0) {
+      // lookahead: tile (J+1, J+1), then its factorisation and inverse
+      double *t = A + ps::tix(J + 1, J + 1) * 256;
+      const v4d l = ld_rm(A + ps::tix(J + 1, J) * 256, c, q);
+      st_cm(t, c, q, mma(-l, l, ld_cm(t, c, q)));
+      wave_sync();
+      const bool ok = diag_factor_inverse<LZ>(t, ws, lane, z + 16 * (J + 1), lz + 16 * (J + 1), yJ);
+      if (lane == 0 && !ok) *flag = 0;
+    } else {
+      // the other trailing tiles (task 0 is the diagonal tile), two per pass
+      const int m = T - 1 - J, ntask = m * (m + 1) / 2;
+      for (int n0 = w; n0 < ntask; n0 += 6) {
+        const int n1 = n0 + 3;
+        const bool has1 = n1 < ntask;
+        int K0, I0, K1, I1;
+        task_ki<T>(J, n0, K0, I0);
+        task_ki<T>(J, has1 ? n1 : n0, K1, I1);
+        trail_pair(A, J, I0, K0, I1, K1, has1, c, q);
       }
     }
     __syncthreads();
+  }
+  // X from the diagonal inverses by doubling
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int J = w + 4 * h;
-      if (J < I) st_cm(A + ps::tix(I, J) * 256, c, q, res[h]);
+  for (int sb = 1; sb < T; sb *= 2) {
+    // rows i of Y = L_CA X_AA over L_CA: block b (A = [b, b+sb), C = [b+sb, min(b+2sb, T)))
+    {
+      int item = 0;
+#pragma unroll
+      for (int b = 0; b + sb < T; b += 2 * sb) {
+#pragma unroll
+        for (int i = b + sb; i < b + 2 * sb && i < T; ++i, ++item) {
+          if ((item & 3) != w) continue;
+          v4d yv[4];
+#pragma unroll
+          for (int j = b; j < b + sb; ++j) {
+            v4d u{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = j; k < b + sb; ++k)
+              u = mma(ld_rm(A + ps::tix(i, k) * 256, c, q), ld_cm(A + ps::tix(k, j) * 256, c, q), u);
+            yv[j - b] = u;
+          }
+#pragma unroll
+          for (int j = b; j < b + sb; ++j) st_cm(A + ps::tix(i, j) * 256, c, q, yv[j - b]);
+        }
+      }
+    }
+    __syncthreads();
+    // columns j of X_CA = -X_CC Y over Y
+    {
+      int item = 0;
+#pragma unroll
+      for (int b = 0; b + sb < T; b += 2 * sb) {
+        const int e = (b + 2 * sb < T) ? b + 2 * sb : T;
+#pragma unroll
+        for (int j = b; j < b + sb; ++j, ++item) {
+          if ((item & 3) != w) continue;
+          v4d xv[4];
+#pragma unroll
+          for (int i = b + sb; i < e; ++i) {
+            v4d u{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = b + sb; k <= i; ++k)
+              u = mma(ld_rm(A + ps::tix(i, k) * 256, c, q), ld_cm(A + ps::tix(k, j) * 256, c, q), u);
+            xv[i - b - sb] = -u;
+          }
+#pragma unroll
+          for (int i = b + sb; i < e; ++i) st_cm(A + ps::tix(i, j) * 256, c, q, xv[i - b - sb]);
+        }
+      }
     }
     __syncthreads();
   }
@@ -249,19 +340,20 @@ __device__ inline double block_sum(double v, double *red) {
 template <int T>
 constexpr size_t lds_bytes() {
   // tiles, six vectors of 16 T, 8 reduction slots, the flag (two doubles' room)
-  // and 48 doubles of scratch for the diagonal tiles
-  return (size_t)(ps::ntiles(T) * 256 + 6 * 16 * T + 8 + 2 + 48) * sizeof(double);
+  // and 64 doubles of scratch for the factorisation
+  return (size_t)(ps::ntiles(T) * 256 + 6 * 16 * T + 8 + 2 + 64) * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
 // Forward per (pulsar, chain): transform, likelihood, Jacobian.
 // ---------------------------------------------------------------------------
 template <int T>
-__global__ __launch_bounds__(256) void k_std_fwd(StdDev S, const double *__restrict__ x) {
+__global__ __launch_bounds__(256, 2) void k_std_fwd(StdDev S, const double *__restrict__ x) {
   extern __shared__ double lds[];
-  constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256;
+  constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256, NT = ps::ntiles(T);
   double *A = lds;
-  double *vd = A + NE, *vz = vd + pp, *vt = vz + pp, *va = vt + pp, *red = va + 2 * pp;
+  double *vd = A + NE, *vz = vd + pp, *vt = vz + pp, *va = vt + pp, *vdi = va + pp, *lz = vdi + pp;
+  double *red = lz + pp;
   int *flag = reinterpret_cast<int *>(red + 8);
   const int tid = threadIdx.x;
   const int c = blockIdx.x / S.n_psr, I = blockIdx.x - c * S.n_psr;
@@ -269,87 +361,116 @@ __global__ __launch_bounds__(256) void k_std_fwd(StdDev S, const double *__restr
   const double beta = S.beta ? S.beta[c] : 1.0;
   const int P = S.P;
   const double *s0 = S.s0 + (size_t)I * pp * pp;
-  if (tid == 0) *flag = 1;
-  __syncthreads();
-  // A~ = beta S0~ + diag(1 / D~), lower tiles; a CURN variance that is not
-  // positive and finite leaves phi_CURN not positive definite
-  for (int e = tid; e < NE; e += 256) {
-    const int tt = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
+  // A~ = beta S0~ + diag(1 / D~), lower tiles: thread tid holds element
+  // (tid / 16, tid % 16) of every tile; all loads are issued before any use
+  const int rr = tid >> 4, cc = tid & 15;
+  double sv[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
     int TI = 0;
     while (ps::tix(TI + 1, 0) <= tt) ++TI;
     const int TJ = tt - ps::tix(TI, 0);
-    const int r = 16 * TI + rr, col = 16 * TJ + cc;
-    double v = beta * s0[(size_t)r * pp + col];
-    if (r == col) {
-      if (r < P) {
-        const double Dv = ps::curn_var(S, xc, I, P - 1 - r);
-        if (!(Dv > 0.0 && isfinite(Dv))) *flag = 0;
-        v += 1.0 / Dv;
-      } else {
-        v += 1.0;
-      }
-    }
-    A[(tt << 8) + sw(rr, cc)] = v;
+    sv[tt] = s0[(size_t)(16 * TI + rr) * pp + 16 * TJ + cc];
   }
+  int bad = 0;
   for (int r = tid; r < pp; r += 256) {
     vd[r] = (r < P) ? beta * S.dvec[(size_t)I * pp + r] : 0.0;
     vz[r] = (r < P) ? xc[S.off_z + I * P + (P - 1 - r)] : 0.0;
+    lz[r] = 0.0;
+    // a CURN variance that is not positive and finite leaves phi_CURN not
+    // positive definite
+    double di = 1.0;
+    if (r < P) {
+      const double Dv = ps::curn_var(S, xc, I, P - 1 - r);
+      if (!(Dv > 0.0 && isfinite(Dv))) bad = 1;
+      di = 1.0 / Dv;
+    }
+    vdi[r] = di;
+  }
+  bad = __syncthreads_or(bad);
+  if (tid == 0) *flag = bad ? 0 : 1;
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    int TI = 0;
+    while (ps::tix(TI + 1, 0) <= tt) ++TI;
+    const int TJ = tt - ps::tix(TI, 0);
+    double v = beta * sv[tt];
+    if (TI == TJ && rr == cc) v += vdi[16 * TI + rr];
+    A[(tt << 8) + sw(rr, cc)] = v;
   }
   __syncthreads();
-  const bool ok = factor_invert<T>(A, tid, flag, red + 10);
-  // t = X beta d~
+  // X = L~^-1 and L~ z~
+  const bool ok = factor_invert<T, true>(A, tid, flag, red + 10, vz, lz);
+  // t = X beta d~: row r, tiles K <= r / 16 (the diagonal tiles hold zeros above)
   if (tid < pp) {
+    const int R = tid >> 4, r16 = tid & 15;
     double s = 0.0;
-    for (int k = 0; k <= tid; ++k) s = fma(mat_at(A, tid, k), vd[k], s);
+#pragma unroll
+    for (int K = 0; K < T; ++K) {
+      if (K > R) break;
+      const double *t = A + ps::tix(R, K) * 256;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) s = fma(t[sw(r16, k)], vd[16 * K + k], s);
+    }
     vt[tid] = s;
   }
   __syncthreads();
-  // a~ = X^T (t + z~), a_hat~ = X^T t
+  // a~ = X^T (t + z~), a_hat~ = X^T t: column r, tiles K >= r / 16
   const size_t vb = ((size_t)c * S.n_psr + I) * pp;
+  double part_d = 0.0, part_v = 0.0, part_j = 0.0;
   if (tid < pp) {
+    const int R = tid >> 4, r16 = tid & 15;
     double sa = 0.0, sh = 0.0;
-    for (int r = tid; r < pp; ++r) {
-      const double xv = mat_at(A, r, tid);
-      sa = fma(xv, vt[r] + vz[r], sa);
-      sh = fma(xv, vt[r], sh);
+#pragma unroll
+    for (int K = 0; K < T; ++K) {
+      if (K < R) continue;
+      const double *t = A + ps::tix(K, R) * 256;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const double xv = t[sw(k, r16)], tv = vt[16 * K + k];
+        sa = fma(xv, tv + vz[16 * K + k], sa);
+        sh = fma(xv, tv, sh);
+      }
     }
-    va[tid] = sa;
     S.ahat[vb + tid] = sh;
     if (tid < P) S.avec[vb + (P - 1 - tid)] = sa;
-  }
-  __syncthreads();
-  // S0~ a~ (the padded matrix is symmetric: column r read with consecutive threads)
-  double part_d = 0.0, part_q = 0.0, part_j = 0.0;
-  if (tid < pp) {
-    double s = 0.0;
-#pragma unroll 16
-    for (int k = 0; k < pp; ++k) s = fma(s0[(size_t)k * pp + tid], va[k], s);
+    // beta (d - S0 a) in the reversed order: A~ a~ = L~ (t + z~) = beta d~ + L~ z~,
+    // so beta S0~ a~ = beta d~ + L~ z~ - a~ / D~ and v1 = a~ / D~ - L~ z~
+    const double v1 = sa * vdi[tid] - lz[tid];
+    S.v1[vb + tid] = v1;
     const double dr = (tid < P) ? S.dvec[(size_t)I * pp + tid] : 0.0;
-    S.v1[vb + tid] = beta * (dr - s);
-    part_d = va[tid] * dr;
-    part_q = va[tid] * s;
-    part_j = (tid < P) ? log(mat_at(A, tid, tid)) : 0.0;
+    part_d = sa * dr;
+    part_v = sa * v1;
+    part_j = (tid < P) ? log(A[ps::tix(R, R) * 256 + sw(r16, r16)]) : 0.0;
   }
   const double ad = block_sum(part_d, red);
-  const double aq = block_sum(part_q, red);
+  const double av = block_sum(part_v, red);
   const double lj = block_sum(part_j, red);
   if (tid == 0) {
-    const double *cc = S.cconst + 2 * I;
+    // beta log L = beta (-dt N~^-1 dt / 2 + a.d - a.S0 a / 2 + c1), with
+    // beta a.S0 a = beta a.d - a.v1
+    const double *k2 = S.cconst + 2 * I;
     double *o = S.lik + ((size_t)c * S.n_psr + I) * 2;
-    o[0] = beta * (-0.5 * cc[0] + ad - 0.5 * aq + cc[1]);
+    o[0] = beta * (k2[1] - 0.5 * k2[0]) + 0.5 * beta * ad + 0.5 * av;
     o[1] = lj;
     S.flag1[(size_t)c * S.n_psr + I] = ok ? 0 : ps::kFlagNotPD;
   }
-  // X for the adjoint
-  double *xo = S.xinv + ((size_t)c * S.n_psr + I) * NE;
-  for (int e = tid; e < NE; e += 256) xo[e] = A[e];
+  // X for the adjoint (16-byte copies)
+  double2 *xo = reinterpret_cast<double2 *>(S.xinv + ((size_t)c * S.n_psr + I) * NE);
+  const double2 *xa = reinterpret_cast<const double2 *>(A);
+  constexpr int N2 = NE / 2;
+#pragma unroll
+  for (int i = 0; i < (N2 + 255) / 256; ++i) {
+    const int e = tid + 256 * i;
+    if (e < N2) xo[e] = xa[e];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Prior per (frequency k < nf_gw, chain): phi_k = rho_k Gamma + diag kappa_.k.
 // ---------------------------------------------------------------------------
 template <int T>
-__global__ __launch_bounds__(256) void k_std_prior_dense(StdDev S, const double *__restrict__ x) {
+__global__ __launch_bounds__(256, 2) void k_std_prior_dense(StdDev S, const double *__restrict__ x) {
   extern __shared__ double lds[];
   constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256;
   double *A = lds;
@@ -376,7 +497,7 @@ __global__ __launch_bounds__(256) void k_std_prior_dense(StdDev S, const double 
   }
   if (tid == 0) *flag = 1;
   __syncthreads();
-  const bool ok = factor_invert<T>(A, tid, flag, red + 10);
+  const bool ok = factor_invert<T, false>(A, tid, flag, red + 10, nullptr, nullptr);
   // y = X a (rows), then u = X^T y (columns), for sin and cos
   if (tid < 2 * pp) {
     const int i = tid % pp, h = tid / pp;
