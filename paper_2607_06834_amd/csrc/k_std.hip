@@ -93,48 +93,63 @@ __device__ inline v4d mma(v4d a, v4d b, v4d acc) {
   return acc;
 }
 
-// Factorise the symmetric 16x16 tile t (both triangles present) and replace it
-// by the inverse of its lower Cholesky factor (lower, zeros above).  Executed
-// by one wave with ws, 48 doubles of LDS, as scratch.  The factorisation is
-// right-looking with lane r holding row r: the pivot and the next row's
-// multiplier come by readlane, the rest of column j of L by broadcast reads of
-// an LDS copy.  The inverse is solved by columns, lane c computing column c of
-// X from L x = e_c with L read from the tile (the same address in every lane).
-// Returns false in every lane when a pivot is not positive and finite.
+// Keeps a register row computed here: the updates before it happen before the
+// loads after it (no load is hoisted above, no update sunk below).
+__device__ inline void pin_row(double (&v)[16]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) asm volatile("" : "+v"(v[k]));
+  asm volatile("" ::: "memory");
+}
+
 __device__ inline void wave_sync() {   // LDS writes of the wave visible to its later reads
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Cholesky factor of the symmetric 16x16 tile t (both triangles present), in
+// place in the lower triangle (the upper one is left undefined).  Executed by
+// one wave; lane r holds row r.  Right-looking: pivot j's multipliers reach
+// rows j + 1 and j + 2 at once by readlane, the other rows through an LDS copy
+// of column j (bc, three buffers of 16) read two pivots later, when the store
+// has long completed (a wave's LDS accesses are executed in order).  idg
+// receives 1 / L_jj.  With LZ, lzJ[r] += sum_c L_rc zJ[c].  Returns false in
+// every lane when a pivot is not positive and finite.
 template <bool LZ>
-__device__ __forceinline__ bool diag_factor_inverse(double *t, double *ws, int lane, const double *zJ,
-                                                    double *lzJ, double *yJ) {
+__device__ __forceinline__ bool diag_factor(double *t, double *bc, double *idg, int lane, const double *zJ,
+                                            double *lzJ) {
   const int r = lane & 15;
-  double *idg = ws + 32;   // 1 / L_jj
   double row[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) row[c] = t[sw(r, c)];
   bool ok = true;
+  double l1 = 0.0, l2 = 0.0;   // this lane's multipliers of the two previous pivots
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const double piv = readlane_d(row[j], j);
+    double bv[16];
+    const bool def = (j >= 2) && (j <= 14);   // pivot j - 2 still owes rows j + 1 ...
+    if (def) {
+      const double *bp = bc + 16 * ((j - 2) % 3);
+#pragma unroll
+      for (int k = j + 1; k < 16; ++k) bv[k] = bp[k];
+    }
     ok = ok && (piv > 0.0) && isfinite(piv);
     const double rs = rsqrt_nr(piv);
+    if (def) {
+#pragma unroll
+      for (int k = j + 1; k < 16; ++k) row[k] = fma(-l2, bv[k], row[k]);
+    }
     const double l = row[j] * rs;       // L[r][j] (r >= j)
     row[j] = l;
+    if (j + 1 < 16) row[j + 1] = fma(-l, readlane_d(l, j + 1), row[j + 1]);
+    if (j + 2 < 16) row[j + 2] = fma(-l, readlane_d(l, j + 2), row[j + 2]);
+    if (j <= 12 && lane < 16) bc[16 * (j % 3) + r] = l;
     if (lane == 0) idg[j] = rs;
-    if (j < 15) {
-      double *bc = ws + 16 * (j & 1);   // two buffers: pivot j + 1 never overwrites what j still reads
-      if (lane < 16) bc[r] = l;
-      wave_sync();
-      row[j + 1] = fma(-l, readlane_d(l, j + 1), row[j + 1]);
-#pragma unroll
-      for (int k = j + 2; k < 16; ++k) row[k] = fma(-l, bc[k], row[k]);
-    }
-    __builtin_amdgcn_sched_barrier(0);   // one pivot's loads and updates together (registers)
+    l2 = l1;
+    l1 = l;
+    pin_row(row);   // one pivot's loads and updates together (registers, order)
   }
-  // L (lower triangle) back to the tile; with LZ, the tile's part of L z
   if (lane < 16) {
 #pragma unroll
     for (int c = 0; c < 16; ++c)
@@ -146,10 +161,17 @@ __device__ __forceinline__ bool diag_factor_inverse(double *t, double *ws, int l
       lzJ[r] += s;
     }
   }
-  wave_sync();
-  // column c of X: x_m = (delta_mc - sum_{k<m} L_mk x_k) / L_mm, zero for m < c;
-  // column m + 1 of L is loaded while column m is applied.  The solve and the
-  // stores sit in one branch: the wave's loads all precede its stores.
+  return ok;
+}
+
+// The lower-triangular tile t (L, upper triangle undefined) replaced by
+// X = L^-1 (zeros above); idg = 1 / L_jj.  Executed by one wave: lane c < 16
+// solves L x = e_c for column c, x_m = (delta_mc - sum_{k<m} L_mk x_k) / L_mm,
+// with L read from the tile at the same address in every lane.  Column m + 1
+// of L is loaded while column m is applied; the solve and the stores sit in
+// one branch so that the wave's loads all precede its stores.
+__device__ __forceinline__ void diag_inverse(double *t, const double *idg, int lane) {
+  const int r = lane & 15;
   if (lane < 16) {
     double acc[16], xc[16], lc[2][16], dg[2];
 #pragma unroll
@@ -169,18 +191,46 @@ __device__ __forceinline__ bool diag_factor_inverse(double *t, double *ws, int l
       xc[m] = xm;
 #pragma unroll
       for (int k = m + 1; k < 16; ++k) acc[k] = fma(lc[b][k], xm, acc[k]);
-      __builtin_amdgcn_sched_barrier(0);
+      pin_row(acc);
     }
 #pragma unroll
     for (int m = 0; m < 16; ++m) t[sw(m, r)] = (m >= r) ? xc[m] : 0.0;
-    if (LZ) {   // y = X^T z: the panel tiles' part of L z is A_IJ y
-      double s = 0.0;
-#pragma unroll
-      for (int m = 0; m < 16; ++m) s = fma((m >= r) ? xc[m] : 0.0, zJ[m], s);
-      yJ[r] = s;
-    }
   }
-  return ok;
+}
+
+// Row r of a panel tile: L_IJ = A_IJ L_JJ^-T by substitution,
+// x_c = (a_c - sum_{k<c} x_k L_ck) / L_cc, one row per thread, L_JJ (lower)
+// read at the same address by every lane.  With LZ, lzI[r] += sum_c x_c zJ[c].
+template <bool LZ>
+__device__ __forceinline__ void panel_row(double *t, const double *ljj, const double *idg, int r,
+                                          const double *zJ, double *lzI) {
+  double x[16], lc[2][16], dg[2];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) x[c] = t[sw(r, c)];
+  dg[0] = idg[0];
+#pragma unroll
+  for (int k = 1; k < 16; ++k) lc[0][k] = ljj[sw(k, 0)];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    const int b = c & 1;
+    if (c < 15) {   // column c + 1 of L_JJ while column c is applied
+      dg[b ^ 1] = idg[c + 1];
+#pragma unroll
+      for (int k = c + 2; k < 16; ++k) lc[b ^ 1][k] = ljj[sw(k, c + 1)];
+    }
+    x[c] *= dg[b];
+#pragma unroll
+    for (int k = c + 1; k < 16; ++k) x[k] = fma(-x[c], lc[b][k], x[k]);
+    pin_row(x);
+  }
+#pragma unroll
+  for (int c = 0; c < 16; ++c) t[sw(r, c)] = x[c];
+  if (LZ) {
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) s = fma(x[c], zJ[c], s);
+    lzI[r] += s;
+  }
 }
 
 // Trailing update A_IK -= L_IJ L_KJ^T of two tiles at once (two independent
@@ -206,68 +256,68 @@ __device__ inline void task_ki(int J, int n, int &K, int &I) {
 // In-place X = L^-1 of the symmetric positive-definite matrix held as lower
 // tiles in A (diagonal tiles with both triangles).  All 256 threads call it.
 // flag (LDS) is set to 0 when a pivot fails; the return value is the flag.
-// ws: 64 doubles of LDS scratch.  With LZ the product L z of the factor with
-// the vector z (LDS, 16 T) is accumulated into lz (LDS, zero on entry).
+// ws: 48 + 16 T doubles of LDS scratch.  With LZ the product L z of the factor
+// with the vector z (LDS, 16 T) is accumulated into lz (LDS, zero on entry).
 //
 // Factorisation: right-looking by block columns with a lookahead of one: at
-// step J, after the panel, wave 0 updates the next diagonal tile and
-// factorises and inverts it while waves 1-3 apply the rest of the trailing
-// update.  Inverse: X_CA = -X_CC (L_CA X_AA) for neighbouring diagonal blocks
-// A and C of s tiles, s = 1, 2, 4, ... (rows of L_CA X_AA, then columns of X_CA
-// dealt to the waves).
+// step J the panel is solved against L_JJ (all waves, a row per thread), then
+// wave 0 updates the next diagonal tile and factorises it while waves 1-3
+// apply the rest of the trailing update.  Inverse: the diagonal tiles are
+// inverted (two per wave), then X_CA = -X_CC (L_CA X_AA) for neighbouring
+// diagonal blocks A and C of s tiles, s = 1, 2, 4, ... (rows of L_CA X_AA, then
+// columns of X_CA dealt to the waves).
 template <int T, bool LZ>
 __device__ __forceinline__ bool factor_invert(double *A, int tid, int *flag, double *ws,
                                               const double *z, double *lz) {
   const int w = tid >> 6, lane = tid & 63, c = lane & 15, q = lane >> 4;
-  double *yJ = ws + 48;
+  double *bc = ws, *idg = ws + 48;   // idg: 16 per diagonal tile
   if (w == 0) {
-    const bool ok = diag_factor_inverse<LZ>(A, ws, lane, z, lz, yJ);
+    const bool ok = diag_factor<LZ>(A, bc, idg, lane, z, lz);
     if (lane == 0 && !ok) *flag = 0;
   }
   __syncthreads();
 #pragma unroll 1
   for (int J = 0; J < T; ++J) {
-    // panel: L_IJ = A_IJ X_JJ^T (and L_IJ z_J = A_IJ y_J)
-    const double *xjj = A + ps::tix(J, J) * 256;
-    for (int I = J + 1 + w; I < T; I += 4) {
-      double *t = A + ps::tix(I, J) * 256;
-      const v4d a = ld_rm(t, c, q);
-      const v4d r = mma(a, ld_rm(xjj, c, q), v4d{0.0, 0.0, 0.0, 0.0});
-      if (LZ) {
-        // B[k][c] = y[k] for every c: every column of the product is A_IJ y
-        const v4d yb{yJ[q], yJ[q + 4], yJ[q + 8], yJ[q + 12]};
-        const v4d u = mma(a, yb, v4d{0.0, 0.0, 0.0, 0.0});
-        if (c == 0) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) lz[16 * I + q + 4 * v] += u[v];
-        }
-      }
-      st_cm(t, c, q, r);
+    {
+      const int I = J + 1 + (tid >> 4);
+      if (I < T)
+        panel_row<LZ>(A + ps::tix(I, J) * 256, A + ps::tix(J, J) * 256, idg + 16 * J, tid & 15,
+                      LZ ? z + 16 * J : nullptr, LZ ? lz + 16 * I : nullptr);
     }
     __syncthreads();
     if (J + 1 == T) break;
     if (w == 0) {
-      // lookahead: tile (J+1, J+1), then its factorisation and inverse
+      // lookahead: tile (J+1, J+1), then its factorisation
       double *t = A + ps::tix(J + 1, J + 1) * 256;
       const v4d l = ld_rm(A + ps::tix(J + 1, J) * 256, c, q);
       st_cm(t, c, q, mma(-l, l, ld_cm(t, c, q)));
       wave_sync();
-      const bool ok = diag_factor_inverse<LZ>(t, ws, lane, z + 16 * (J + 1), lz + 16 * (J + 1), yJ);
+      const bool ok = diag_factor<LZ>(t, bc, idg + 16 * (J + 1), lane, LZ ? z + 16 * (J + 1) : nullptr,
+                                      LZ ? lz + 16 * (J + 1) : nullptr);
       if (lane == 0 && !ok) *flag = 0;
     } else {
-      // the other trailing tiles (task 0 is the diagonal tile), two per pass
-      const int m = T - 1 - J, ntask = m * (m + 1) / 2;
-      for (int n0 = w; n0 < ntask; n0 += 6) {
-        const int n1 = n0 + 3;
-        const bool has1 = n1 < ntask;
+      // the other trailing tiles (task 0 is the diagonal tile) in contiguous
+      // ranges, two per pass; wave 1 also inverts tile J (its panel is done),
+      // counted as six tiles' work
+      const int m = T - 1 - J, nt = m * (m + 1) / 2 - 1;
+      const int per = (nt + 6 + 2) / 3;
+      const int n1 = min(max(per - 6, 0), nt), n2 = (nt - n1 + 1) / 2;
+      const int lo = 1 + (w == 1 ? 0 : (w == 2 ? n1 : n1 + n2));
+      const int hi = 1 + (w == 1 ? n1 : (w == 2 ? n1 + n2 : nt));
+      if (w == 1) diag_inverse(A + ps::tix(J, J) * 256, idg + 16 * J, lane);
+      for (int n0 = lo; n0 < hi; n0 += 2) {
+        const bool has1 = n0 + 1 < hi;
         int K0, I0, K1, I1;
         task_ki<T>(J, n0, K0, I0);
-        task_ki<T>(J, has1 ? n1 : n0, K1, I1);
+        task_ki<T>(J, has1 ? n0 + 1 : n0, K1, I1);
         trail_pair(A, J, I0, K0, I1, K1, has1, c, q);
       }
     }
     __syncthreads();
   }
+  // the last diagonal tile's inverse
+  if (w == 0) diag_inverse(A + ps::tix(T - 1, T - 1) * 256, idg + 16 * (T - 1), lane);
+  __syncthreads();
   // X from the diagonal inverses by doubling
 #pragma unroll
   for (int sb = 1; sb < T; sb *= 2) {
@@ -337,11 +387,41 @@ __device__ inline double block_sum(double v, double *red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Problem index of block b in a grid of n: consecutive blocks are dealt to
+// the 8 XCDs in turn, so XCD x = b % 8 is given the x-th contiguous range of
+// problem indices (with pulsar-major problems, a few pulsars' data per L2).
+__device__ inline int xcd_index(int b, int n) {
+  const int x = b & 7, k = b >> 3, q = n >> 3, rm = n & 7;
+  return x * q + (x < rm ? x : rm) + k;
+}
+
+// Block sum of three values per thread (256 threads) in one pass; red: 12
+// doubles of LDS.  Every thread gets the three sums.
+__device__ inline void block_sum3(double &a, double &b, double &c, double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+    c += __shfl_xor(c, o, 64);
+  }
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if ((tid & 63) == 0) {
+    red[tid >> 6] = a;
+    red[4 + (tid >> 6)] = b;
+    red[8 + (tid >> 6)] = c;
+  }
+  __syncthreads();
+  a = (red[0] + red[1]) + (red[2] + red[3]);
+  b = (red[4] + red[5]) + (red[6] + red[7]);
+  c = (red[8] + red[9]) + (red[10] + red[11]);
+}
+
 template <int T>
 constexpr size_t lds_bytes() {
   // tiles, six vectors of 16 T, 8 reduction slots, the flag (two doubles' room)
-  // and 64 doubles of scratch for the factorisation
-  return (size_t)(ps::ntiles(T) * 256 + 6 * 16 * T + 8 + 2 + 64) * sizeof(double);
+  // and 48 + 16 T doubles of scratch for the factorisation
+  return (size_t)(ps::ntiles(T) * 256 + 6 * 16 * T + 8 + 2 + 48 + 16 * T) * sizeof(double);
 }
 
 // ---------------------------------------------------------------------------
@@ -356,7 +436,8 @@ __global__ __launch_bounds__(256, 2) void k_std_fwd(StdDev S, const double *__re
   double *red = lz + pp;
   int *flag = reinterpret_cast<int *>(red + 8);
   const int tid = threadIdx.x;
-  const int c = blockIdx.x / S.n_psr, I = blockIdx.x - c * S.n_psr;
+  const int pi = xcd_index(blockIdx.x, gridDim.x);
+  const int I = pi / S.n_chains, c = pi - I * S.n_chains;
   const double *xc = x + (size_t)c * S.d;
   const double beta = S.beta ? S.beta[c] : 1.0;
   const int P = S.P;
@@ -373,8 +454,10 @@ __global__ __launch_bounds__(256, 2) void k_std_fwd(StdDev S, const double *__re
     sv[tt] = s0[(size_t)(16 * TI + rr) * pp + 16 * TJ + cc];
   }
   int bad = 0;
+  double dr = 0.0;   // d~_r (unscaled) of this thread's row, kept for the likelihood
   for (int r = tid; r < pp; r += 256) {
-    vd[r] = (r < P) ? beta * S.dvec[(size_t)I * pp + r] : 0.0;
+    dr = (r < P) ? S.dvec[(size_t)I * pp + r] : 0.0;
+    vd[r] = beta * dr;
     vz[r] = (r < P) ? xc[S.off_z + I * P + (P - 1 - r)] : 0.0;
     lz[r] = 0.0;
     // a CURN variance that is not positive and finite leaves phi_CURN not
@@ -401,58 +484,72 @@ __global__ __launch_bounds__(256, 2) void k_std_fwd(StdDev S, const double *__re
   __syncthreads();
   // X = L~^-1 and L~ z~
   const bool ok = factor_invert<T, true>(A, tid, flag, red + 10, vz, lz);
-  // t = X beta d~: row r, tiles K <= r / 16 (the diagonal tiles hold zeros above)
-  if (tid < pp) {
-    const int R = tid >> 4, r16 = tid & 15;
+  // t = X beta d~ by rows: row r of X over tiles K <= r / 16 (the diagonal
+  // tiles hold zeros above), the tiles split by parity between threads r and
+  // r + 128; va and vd hold the second thread's partial sums
+  const int h = tid >> 7, r = tid & 127, R = r >> 4, r16 = r & 15;
+  const bool live = r < pp;
+  {
     double s = 0.0;
+    if (live) {
 #pragma unroll
-    for (int K = 0; K < T; ++K) {
-      if (K > R) break;
-      const double *t = A + ps::tix(R, K) * 256;
+      for (int K = 0; K < T; ++K) {
+        if ((K & 1) != h || K > R) continue;
+        const double *t = A + ps::tix(R, K) * 256;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) s = fma(t[sw(r16, k)], vd[16 * K + k], s);
+        for (int k = 0; k < 16; ++k) s = fma(t[sw(r16, k)], vd[16 * K + k], s);
+      }
+      if (h == 1) va[r] = s;
     }
-    vt[tid] = s;
+    __syncthreads();
+    if (live && h == 0) vt[r] = s + va[r];
+    __syncthreads();
   }
-  __syncthreads();
-  // a~ = X^T (t + z~), a_hat~ = X^T t: column r, tiles K >= r / 16
+  // a~ = X^T (t + z~), a_hat~ = X^T t by columns: column r over tiles K >= r / 16
   const size_t vb = ((size_t)c * S.n_psr + I) * pp;
   double part_d = 0.0, part_v = 0.0, part_j = 0.0;
-  if (tid < pp) {
-    const int R = tid >> 4, r16 = tid & 15;
+  {
     double sa = 0.0, sh = 0.0;
+    if (live) {
 #pragma unroll
-    for (int K = 0; K < T; ++K) {
-      if (K < R) continue;
-      const double *t = A + ps::tix(K, R) * 256;
+      for (int K = 0; K < T; ++K) {
+        if ((K & 1) != h || K < R) continue;
+        const double *t = A + ps::tix(K, R) * 256;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const double xv = t[sw(k, r16)], tv = vt[16 * K + k];
-        sa = fma(xv, tv + vz[16 * K + k], sa);
-        sh = fma(xv, tv, sh);
+        for (int k = 0; k < 16; ++k) {
+          const double xv = t[sw(k, r16)], tv = vt[16 * K + k];
+          sa = fma(xv, tv + vz[16 * K + k], sa);
+          sh = fma(xv, tv, sh);
+        }
+      }
+      if (h == 1) {
+        va[r] = sa;
+        vd[r] = sh;
       }
     }
-    S.ahat[vb + tid] = sh;
-    if (tid < P) S.avec[vb + (P - 1 - tid)] = sa;
-    // beta (d - S0 a) in the reversed order: A~ a~ = L~ (t + z~) = beta d~ + L~ z~,
-    // so beta S0~ a~ = beta d~ + L~ z~ - a~ / D~ and v1 = a~ / D~ - L~ z~
-    const double v1 = sa * vdi[tid] - lz[tid];
-    S.v1[vb + tid] = v1;
-    const double dr = (tid < P) ? S.dvec[(size_t)I * pp + tid] : 0.0;
-    part_d = sa * dr;
-    part_v = sa * v1;
-    part_j = (tid < P) ? log(A[ps::tix(R, R) * 256 + sw(r16, r16)]) : 0.0;
+    __syncthreads();
+    if (live && h == 0) {
+      sa += va[r];
+      sh += vd[r];
+      S.ahat[vb + r] = sh;
+      if (r < P) S.avec[vb + (P - 1 - r)] = sa;
+      // beta (d - S0 a) in the reversed order: A~ a~ = L~ (t + z~) = beta d~ + L~ z~,
+      // so beta S0~ a~ = beta d~ + L~ z~ - a~ / D~ and v1 = a~ / D~ - L~ z~
+      const double v1 = sa * vdi[r] - lz[r];
+      S.v1[vb + r] = v1;
+      part_d = sa * dr;
+      part_v = sa * v1;
+      part_j = (r < P) ? log(A[ps::tix(R, R) * 256 + sw(r16, r16)]) : 0.0;
+    }
   }
-  const double ad = block_sum(part_d, red);
-  const double av = block_sum(part_v, red);
-  const double lj = block_sum(part_j, red);
+  block_sum3(part_d, part_v, part_j, red + 10);
   if (tid == 0) {
     // beta log L = beta (-dt N~^-1 dt / 2 + a.d - a.S0 a / 2 + c1), with
     // beta a.S0 a = beta a.d - a.v1
     const double *k2 = S.cconst + 2 * I;
     double *o = S.lik + ((size_t)c * S.n_psr + I) * 2;
-    o[0] = beta * (k2[1] - 0.5 * k2[0]) + 0.5 * beta * ad + 0.5 * av;
-    o[1] = lj;
+    o[0] = beta * (k2[1] - 0.5 * k2[0]) + 0.5 * beta * part_d + 0.5 * part_v;
+    o[1] = part_j;
     S.flag1[(size_t)c * S.n_psr + I] = ok ? 0 : ps::kFlagNotPD;
   }
   // X for the adjoint (16-byte copies)
@@ -619,41 +716,84 @@ __global__ __launch_bounds__(256) void k_std_bwd(StdDev S, const double *__restr
   extern __shared__ double lds[];
   constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256;
   double *A = lds;
-  double *vv = A + NE, *vz = vv + pp, *vw = vz + pp, *vh = vw + pp, *gd = vh + pp;
+  double *vv = A + NE, *vz = vv + pp, *vw = vz + pp, *vh = vw + pp, *gd = vh + pp, *tmp = gd + pp;
   const int tid = threadIdx.x;
-  const int c = blockIdx.x / S.n_psr, I = blockIdx.x - c * S.n_psr;
+  const int pi = xcd_index(blockIdx.x, gridDim.x);
+  const int I = pi / S.n_chains, c = pi - I * S.n_chains;
   const double *xc = x + (size_t)c * S.d;
   const int P = S.P;
   const size_t vb = ((size_t)c * S.n_psr + I) * pp;
-  const double *xi = S.xinv + ((size_t)c * S.n_psr + I) * NE;
-  for (int e = tid; e < NE; e += 256) A[e] = xi[e];
+  {
+    const double2 *xi = reinterpret_cast<const double2 *>(S.xinv + ((size_t)c * S.n_psr + I) * NE);
+    double2 *xa = reinterpret_cast<double2 *>(A);
+    constexpr int N2 = NE / 2;
+#pragma unroll
+    for (int i = 0; i < (N2 + 255) / 256; ++i) {
+      const int e = tid + 256 * i;
+      if (e < N2) xa[e] = xi[e];
+    }
+  }
   for (int r = tid; r < pp; r += 256) {
     vv[r] = (r < P) ? S.v1[vb + r] + S.v2[vb + (P - 1 - r)] : 0.0;
     vz[r] = (r < P) ? xc[S.off_z + I * P + (P - 1 - r)] : 0.0;
     vh[r] = S.ahat[vb + r];
   }
   __syncthreads();
-  // w~ = X v~  (dlogp/dz~)
-  if (tid < pp) {
+  const int h = tid >> 7, r = tid & 127, R = r >> 4, r16 = r & 15;
+  // w~ = X v~ (dlogp/dz~) by rows, the tiles split by parity between threads r
+  // and r + 128
+  {
     double s = 0.0;
-    for (int k = 0; k <= tid; ++k) s = fma(mat_at(A, tid, k), vv[k], s);
-    vw[tid] = s;
-    if (tid < P) grad[(size_t)c * S.d + S.off_z + I * P + (P - 1 - tid)] = s;
+    if (r < pp) {
+#pragma unroll
+      for (int K = 0; K < T; ++K) {
+        if ((K & 1) != h || K > R) continue;
+        const double *t = A + ps::tix(R, K) * 256;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s = fma(t[sw(r16, k)], vv[16 * K + k], s);
+      }
+      if (h == 1) tmp[r] = s;
+    }
+    __syncthreads();
+    if (r < pp && h == 0) {
+      s += tmp[r];
+      vw[r] = s;
+      if (r < P) grad[(size_t)c * S.d + S.off_z + I * P + (P - 1 - r)] = s;
+    }
+    __syncthreads();
+  }
+  // per column r, over rows a >= r from the bottom: (Sigma v)~_r = sum_a X_ar w~_a,
+  // Sigma~_rr = sum_a X_ar^2 and T_r = sum_a X_ar w~_a (sum_{b>a} X_br z~_b + X_ar z~_a / 2),
+  // dlogp/dD~_r = (a_hat~_r (Sigma v)~_r + T_r + Sigma~_rr / 2) / D~_r^2.
+  // Thread r + 128 takes the lower tiles K >= M, thread r the tiles R..M-1; the
+  // upper part's suffix sums miss the lower part's s = sum_b X_br z~_b, which
+  // adds s times the upper part's sum_a X_ar w~_a.  The lower part hands over
+  // s and its own a_hat (Sigma v) + T + Sigma / 2.
+  double sv = 0.0, ss = 0.0, tt = 0.0, suf = 0.0;
+  if (r < P) {
+    const int M = R + (T - R + 1) / 2;
+#pragma unroll
+    for (int K = T - 1; K >= 0; --K) {
+      if (K < R || (h == 1) != (K >= M)) continue;
+      const double *t = A + ps::tix(K, R) * 256;
+#pragma unroll
+      for (int k = 15; k >= 0; --k) {
+        const double xv = t[sw(k, r16)], wv = vw[16 * K + k], zv = vz[16 * K + k];
+        sv = fma(xv, wv, sv);
+        ss = fma(xv, xv, ss);
+        tt = fma(xv * wv, fma(0.5 * xv, zv, suf), tt);
+        suf = fma(xv, zv, suf);
+      }
+    }
+    if (h == 1) {
+      tmp[r] = suf;
+      tmp[pp + r] = fma(vh[r], sv, tt + 0.5 * ss);
+    }
   }
   __syncthreads();
-  // per column r: (Sigma v)~_r = sum_a X_ar w~_a, Sigma~_rr = sum_a X_ar^2, and the
-  // suffix sum T_r = sum_a X_ar w~_a (sum_{b>a} X_br z~_b + X_ar z~_a / 2)
-  if (tid < P) {
-    double sv = 0.0, ss = 0.0, tt = 0.0, suf = 0.0;
-    for (int a = pp - 1; a >= tid; --a) {
-      const double xv = mat_at(A, a, tid);
-      sv = fma(xv, vw[a], sv);
-      ss = fma(xv, xv, ss);
-      tt = fma(xv * vw[a], fma(0.5 * xv, vz[a], suf), tt);
-      suf = fma(xv, vz[a], suf);
-    }
-    const double Dv = ps::curn_var(S, xc, I, P - 1 - tid);
-    gd[tid] = (vh[tid] * sv + tt + 0.5 * ss) / (Dv * Dv);
+  if (r < P && h == 0) {
+    const double Dv = ps::curn_var(S, xc, I, P - 1 - r);
+    gd[r] = (fma(sv, vh[r] + tmp[r], tt + 0.5 * ss) + tmp[pp + r]) / (Dv * Dv);
   }
   __syncthreads();
   if (tid < S.ka) {
