@@ -136,19 +136,26 @@ __device__ __forceinline__ bool diag_factor(double *t, double *bc, double *idg, 
     }
     ok = ok && (piv > 0.0) && isfinite(piv);
     const double rs = rsqrt_nr(piv);
-    if (def) {
-#pragma unroll
-      for (int k = j + 1; k < 16; ++k) row[k] = fma(-l2, bv[k], row[k]);
-    }
     const double l = row[j] * rs;       // L[r][j] (r >= j)
     row[j] = l;
-    if (j + 1 < 16) row[j + 1] = fma(-l, readlane_d(l, j + 1), row[j + 1]);
+    // the next pivot's column first (the path from pivot to pivot), then the rest
+    if (j + 1 < 16) {
+      if (def) row[j + 1] = fma(-l2, bv[j + 1], row[j + 1]);
+      row[j + 1] = fma(-l, readlane_d(l, j + 1), row[j + 1]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (def) {
+#pragma unroll
+      for (int k = j + 2; k < 16; ++k) row[k] = fma(-l2, bv[k], row[k]);
+    }
     if (j + 2 < 16) row[j + 2] = fma(-l, readlane_d(l, j + 2), row[j + 2]);
+    pin_row(row);   // the updates before the stores: a wait for the loads then
+                    // does not also wait for the stores (LDS completes in order)
     if (j <= 12 && lane < 16) bc[16 * (j % 3) + r] = l;
     if (lane == 0) idg[j] = rs;
     l2 = l1;
     l1 = l;
-    pin_row(row);   // one pivot's loads and updates together (registers, order)
+    asm volatile("" ::: "memory");
   }
   if (lane < 16) {
 #pragma unroll
@@ -255,23 +262,25 @@ __device__ inline void task_ki(int J, int n, int &K, int &I) {
 
 // In-place X = L^-1 of the symmetric positive-definite matrix held as lower
 // tiles in A (diagonal tiles with both triangles).  All 256 threads call it.
-// flag (LDS) is set to 0 when a pivot fails; the return value is the flag.
-// ws: 48 + 16 T doubles of LDS scratch.  With LZ the product L z of the factor
+// flag (LDS) is set to 0 when a pivot fails; the return value is the flag;
+// flag[1] serves as a work counter.  ws: 48 + 16 T doubles of LDS scratch.  With LZ the product L z of the factor
 // with the vector z (LDS, 16 T) is accumulated into lz (LDS, zero on entry).
 //
 // Factorisation: right-looking by block columns with a lookahead of one: at
-// step J the panel is solved against L_JJ (all waves, a row per thread), then
-// wave 0 updates the next diagonal tile and factorises it while waves 1-3
-// apply the rest of the trailing update.  Inverse: the diagonal tiles are
-// inverted (two per wave), then X_CA = -X_CC (L_CA X_AA) for neighbouring
-// diagonal blocks A and C of s tiles, s = 1, 2, 4, ... (rows of L_CA X_AA, then
-// columns of X_CA dealt to the waves).
+// step J the panel is solved against L_JJ (a row per thread), then one wave
+// updates the next diagonal tile and factorises it while the other waves take
+// the rest of the trailing update and the inverse of tile J from a shared
+// counter (the factorising wave joins when done).  Inverse: X_CA = -X_CC (L_CA X_AA) for
+// neighbouring diagonal blocks A and C of s tiles, s = 1, 2, 4, ... (rows of
+// L_CA X_AA, then columns of X_CA dealt to the waves).
 template <int T, bool LZ>
 __device__ __forceinline__ bool factor_invert(double *A, int tid, int *flag, double *ws,
                                               const double *z, double *lz) {
+  int *ctr = flag + 1;   // work counter of the trailing phases
   const int w = tid >> 6, lane = tid & 63, c = lane & 15, q = lane >> 4;
+  const int wd = 0;   // the wave that factorises the diagonal tiles
   double *bc = ws, *idg = ws + 48;   // idg: 16 per diagonal tile
-  if (w == 0) {
+  if (w == wd) {
     const bool ok = diag_factor<LZ>(A, bc, idg, lane, z, lz);
     if (lane == 0 && !ok) *flag = 0;
   }
@@ -284,9 +293,10 @@ __device__ __forceinline__ bool factor_invert(double *A, int tid, int *flag, dou
         panel_row<LZ>(A + ps::tix(I, J) * 256, A + ps::tix(J, J) * 256, idg + 16 * J, tid & 15,
                       LZ ? z + 16 * J : nullptr, LZ ? lz + 16 * I : nullptr);
     }
+    if (tid == 0) *ctr = 0;
     __syncthreads();
     if (J + 1 == T) break;
-    if (w == 0) {
+    if (w == wd) {
       // lookahead: tile (J+1, J+1), then its factorisation
       double *t = A + ps::tix(J + 1, J + 1) * 256;
       const v4d l = ld_rm(A + ps::tix(J + 1, J) * 256, c, q);
@@ -295,18 +305,24 @@ __device__ __forceinline__ bool factor_invert(double *A, int tid, int *flag, dou
       const bool ok = diag_factor<LZ>(t, bc, idg + 16 * (J + 1), lane, LZ ? z + 16 * (J + 1) : nullptr,
                                       LZ ? lz + 16 * (J + 1) : nullptr);
       if (lane == 0 && !ok) *flag = 0;
-    } else {
-      // the other trailing tiles (task 0 is the diagonal tile) in contiguous
-      // ranges, two per pass; wave 1 also inverts tile J (its panel is done),
-      // counted as six tiles' work
+    }
+    // the rest of the step's work, taken two items at a time from a counter:
+    // item 0 inverts tile J (its panel is done), items 1..nt are the other
+    // trailing tiles (trailing task 0 is the diagonal tile); the factorising
+    // wave joins when done
+    {
       const int m = T - 1 - J, nt = m * (m + 1) / 2 - 1;
-      const int per = (nt + 6 + 2) / 3;
-      const int n1 = min(max(per - 6, 0), nt), n2 = (nt - n1 + 1) / 2;
-      const int lo = 1 + (w == 1 ? 0 : (w == 2 ? n1 : n1 + n2));
-      const int hi = 1 + (w == 1 ? n1 : (w == 2 ? n1 + n2 : nt));
-      if (w == 1) diag_inverse(A + ps::tix(J, J) * 256, idg + 16 * J, lane);
-      for (int n0 = lo; n0 < hi; n0 += 2) {
-        const bool has1 = n0 + 1 < hi;
+      for (;;) {
+        int n0 = 0;
+        if (lane == 0) n0 = atomicAdd(ctr, 2);
+        n0 = __builtin_amdgcn_readfirstlane(n0);
+        if (n0 > nt) break;
+        if (n0 == 0) {
+          diag_inverse(A + ps::tix(J, J) * 256, idg + 16 * J, lane);
+          if (nt < 1) continue;
+          n0 = 1;
+        }
+        const bool has1 = n0 > 1 && n0 + 1 <= nt;
         int K0, I0, K1, I1;
         task_ki<T>(J, n0, K0, I0);
         task_ki<T>(J, has1 ? n0 + 1 : n0, K1, I1);
