@@ -166,9 +166,9 @@ def serving_bench(n_traj, rates, n_req, n_chains=16, n_leapfrog=20, quantum=10, 
 
 def std_flops_fwd(P):
     """Algorithmic flops of k_std_fwd per (pulsar, chain): Cholesky of the
-    P x P CURN precision (P^3/3), the triangular inverse (P^3/3) and the
-    mat-vecs (X beta d, X^T (t + z), X^T t, S0 a: 5 P^2)."""
-    return 2.0 * P ** 3 / 3.0 + 5.0 * P * P
+    P x P CURN precision (P^3/3), the triangular inverse (P^3/3) and four
+    triangular mat-vecs (X beta d, X^T (t + z), X^T t, L z: 4 P^2)."""
+    return 2.0 * P ** 3 / 3.0 + 4.0 * P * P
 
 
 def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2):
