@@ -30,6 +30,23 @@ What is computed, per parameter vector x = [theta | z] (Sec. IV.B):
                 (Eq. standardized_stochastic_posterior with the Jacobian and
                 the constants the paper drops put back).
 
+Deterministic signal (Sec. IV.C, Eqs. det_F_basis, stoch_det_posterior,
+det_mean, decenter_det_PTA, standardized_det_posterior), when the data set
+has a CW: h = F_D a_D(theta_cw) per pulsar, F_D the sin/cos basis of
+frequencies k / T_D, k = 1..K_D, on an extended span T_D, and a_D the
+discrete Fourier transform of the time-domain CW delay (the Earth-term
+waveform of cw.py) sampled at M = 2 K_D + 1 equally spaced times
+t_j = j T_D / M: a_(k,sin) = (2/M) sum_j h_j sin(2 pi k j / M),
+a_(k,cos) = (2/M) sum_j h_j cos(2 pi k j / M) (the mean of the samples, the
+constant the timing model absorbs, is dropped).  With the stored products
+S_D = T^T N~^-1 F_D, e_D = F_D^T N~^-1 dt, Q_D = F_D^T N~^-1 F_D the data
+enter through
+  d_bar = d - S_D a_D = T^T N~^-1 (dt - h),
+  c_bar = c - 2 e_D^T a_D + a_D^T Q_D a_D = (dt - h)^T N~^-1 (dt - h),
+so the transform centres on a_bar = beta Sigma d_bar (the shifted MAP of
+Eq. det_mean) and the likelihood is the one of dt - h.  Status 3 when the CW
+coalesces within [0, T_D) (evolution variable y >= 1 at a sample time).
+
 Spectra are the power law of Eq. power_law (theta = log10 A, gamma per
 process) or the free spectrum of Sec. IV.A (theta = log10 rho_k per
 frequency, rho_k = 10^theta_k in s^2).  Uniform hyper-priors.
@@ -38,7 +55,9 @@ The gradient is PyTorch autograd of this plain definition (library
 Cholesky, inverse and triangular solves), so it needs no hand derivation.
 Per-chain conditions: 1 outside the prior box or non-finite theta,
 2 a factorisation fails or a CURN variance is not positive and finite (a
-prior covariance that is not positive definite), 4 non-finite z or result.
+prior covariance that is not positive definite), 3 the CW coalesces within
+the extended span, 4 non-finite z or result (precedence 1, 4 for inputs, 3,
+2, 4 for results).
 """
 from __future__ import annotations
 
@@ -46,10 +65,11 @@ import numpy as np
 import scipy.linalg as sla
 import torch
 
+from . import cw as cwmod
 from .model import YR, hd_matrix
 
 LN2PI = float(np.log(2.0 * np.pi))
-ST_OK, ST_PRIOR, ST_NOTPD, ST_NONFINITE = 0, 1, 2, 4
+ST_OK, ST_PRIOR, ST_NOTPD, ST_CW, ST_NONFINITE = 0, 1, 2, 3, 4
 
 
 class NotPositiveDefinite(Exception):
@@ -57,13 +77,15 @@ class NotPositiveDefinite(Exception):
 
 
 class StdLayout:
-    """[theta | z]: theta = [gw | rn per pulsar | dm per pulsar], each process
-    2 entries (power law: log10 A, gamma) or one per frequency (free
-    spectrum: log10 rho_k); z per pulsar: 2 Ka entries (k = 1 sin, k = 1 cos,
-    ...) for the red/common block, then 2 Kdm for DM."""
+    """[theta | z]: theta = [gw | rn per pulsar | dm per pulsar | cw (8)],
+    each process 2 entries (power law: log10 A, gamma) or one per frequency
+    (free spectrum: log10 rho_k), the CW parameters in the order of cw.py;
+    z per pulsar: 2 Ka entries (k = 1 sin, k = 1 cos, ...) for the
+    red/common block, then 2 Kdm for DM."""
 
-    def __init__(self, n_psr, nf_rn, nf_gw, nf_dm, free):
+    def __init__(self, n_psr, nf_rn, nf_gw, nf_dm, free, has_cw=False):
         self.n_psr, self.nf_rn, self.nf_gw, self.nf_dm, self.free = n_psr, nf_rn, nf_gw, nf_dm, free
+        self.has_cw = bool(has_cw)
         self.Ka = max(nf_rn, nf_gw)
         self.Kdm = nf_dm
         self.P = 2 * self.Ka + 2 * self.Kdm
@@ -72,6 +94,7 @@ class StdLayout:
         self.gw = o; o += w(nf_gw) if nf_gw > 0 else 0
         self.rn = o; o += n_psr * w(nf_rn) if nf_rn > 0 else 0
         self.dm = o; o += n_psr * w(nf_dm) if nf_dm > 0 else 0
+        self.cw = o; o += 8 if has_cw else 0
         self.n_theta = o
         self.z = o; o += n_psr * self.P
         self.d = o
@@ -147,9 +170,21 @@ class StdPrepared:
         self.ds = ds
         n = self.n_psr = int(ds["n_psr"])
         self.free = ds.get("spectrum", "powerlaw") == "free"
-        self.lay = StdLayout(n, int(ds["nf_rn"]), int(ds["nf_gw"]), int(ds["nf_dm"]), self.free)
+        self.has_cw = bool(ds.get("has_cw", 0))
+        self.lay = StdLayout(n, int(ds["nf_rn"]), int(ds["nf_gw"]), int(ds["nf_dm"]), self.free, self.has_cw)
         lay = self.lay
         self.T = float(ds["tspan"])
+        self.pos = np.asarray(ds["psr_pos"], np.float64).reshape(n, 3)
+        if self.has_cw:
+            self.Kd = int(ds.get("cw_nf", 60))
+            self.Td = float(ds.get("cw_tspan", 2.0 * self.T))
+            self.Md = 2 * self.Kd + 1
+            self.ts_d = np.arange(self.Md) * self.Td / self.Md
+            jk = 2.0 * np.pi * np.outer(np.arange(1, self.Kd + 1), np.arange(self.Md)) / self.Md
+            self.dft = np.empty((2 * self.Kd, self.Md))
+            self.dft[0::2] = (2.0 / self.Md) * np.sin(jk)
+            self.dft[1::2] = (2.0 / self.Md) * np.cos(jk)
+            self.SD, self.eD, self.QD, self.GabsD = [], [], [], []
         self.freqs = np.arange(1, max(lay.Ka, lay.Kdm, 1) + 1) / self.T
         self.Gamma = hd_matrix(np.asarray(ds["psr_pos"], np.float64))
         self.lo = np.asarray(ds["prior_lo"], np.float64)
@@ -192,6 +227,16 @@ class StdPrepared:
             self.dvec.append(NT.T @ dt)
             self.cval.append(float(dt @ apply(dt)))
             self.const.append(-0.5 * (nprime * LN2PI + logdet))
+            if self.has_cw:
+                argd = 2.0 * np.pi * np.outer(tt, np.arange(1, self.Kd + 1)) / self.Td
+                FD = np.empty((tt.size, 2 * self.Kd))
+                FD[:, 0::2] = np.sin(argd)
+                FD[:, 1::2] = np.cos(argd)
+                NFD = apply(FD)
+                self.SD.append(Tm.T @ NFD)
+                self.eD.append(NFD.T @ dt)
+                self.QD.append(FD.T @ NFD)
+                self.GabsD.append(At.T @ np.abs(FD))
 
     def spectra(self, th):
         """rho (Ka), kappa (Np, Ka), kappa_dm (Np, Kdm) as torch tensors."""
@@ -225,10 +270,30 @@ class StdPrepared:
             kdm = torch.stack(rows)
         return rho, kap, kdm
 
+    def cw_coefficients(self, th):
+        """a_D (Np, 2 K_D) of the CW at theta (torch, differentiable): the DFT
+        of the delay sampled at t_j = j T_D / M (Eq. det_F_basis)."""
+        H = _CWSamples.apply(th[self.lay.cw:self.lay.cw + 8], self)
+        return H @ torch.tensor(self.dft.T)
+
+    def data_terms(self, th):
+        """d_bar_I and c_bar_I (the data minus the deterministic signal), or d, c."""
+        n = self.n_psr
+        if not self.has_cw:
+            return [torch.tensor(self.dvec[I]) for I in range(n)], [self.cval[I] for I in range(n)]
+        aD = self.cw_coefficients(th)
+        dbar, cbar = [], []
+        for I in range(n):
+            v = aD[I]
+            dbar.append(torch.tensor(self.dvec[I]) - torch.tensor(self.SD[I]) @ v)
+            cbar.append(self.cval[I] - 2.0 * (torch.tensor(self.eD[I]) @ v) + v @ (torch.tensor(self.QD[I]) @ v))
+        return dbar, cbar
+
     def transform(self, th, z, beta):
         """a (Np, P), sum_I ln det L_I, beta sum_I log L(a_I) for one point."""
         lay, n = self.lay, self.n_psr
         rho, kap, kdm = self.spectra(th)
+        dbar, cbar = self.data_terms(th)
         a_all, jac, lik = [], 0.0, 0.0
         for I in range(n):
             D = torch.cat([(rho + kap[I]).repeat_interleave(2), kdm[I].repeat_interleave(2)])
@@ -237,7 +302,7 @@ class StdPrepared:
                 # overflows): phi_CURN is not positive definite
                 raise NotPositiveDefinite("CURN prior variance not positive and finite")
             S0 = torch.tensor(self.S0[I])
-            d = torch.tensor(self.dvec[I])
+            d = dbar[I]
             A = beta * S0 + torch.diag(1.0 / D)
             Sig = torch.linalg.inv(A)
             Sig = 0.5 * (Sig + Sig.T)
@@ -246,7 +311,7 @@ class StdPrepared:
             a = ahat + L @ z[I]
             a_all.append(a)
             jac = jac + torch.sum(torch.log(torch.diagonal(L)))
-            lik = lik + beta * (-0.5 * self.cval[I] + a @ d - 0.5 * a @ (S0 @ a) + self.const[I])
+            lik = lik + beta * (-0.5 * cbar[I] + a @ d - 0.5 * a @ (S0 @ a) + self.const[I])
         return torch.stack(a_all), jac, lik, (rho, kap, kdm)
 
     def log_prior_a(self, a, spec):
@@ -277,6 +342,27 @@ class StdPrepared:
         return lik + jac + self.log_prior_a(a, spec) - float(np.sum(np.log(self.hi - self.lo)))
 
 
+class _CWSamples(torch.autograd.Function):
+    """The CW delay h_I(t_j) (Np, M) at the sample times of the deterministic
+    basis, with the waveform's own derivative dh/dtheta (cw.py) as backward."""
+
+    @staticmethod
+    def forward(ctx, th_cw, prep):
+        t = th_cw.detach().numpy()
+        H, G = [], []
+        for I in range(prep.n_psr):
+            h, g = cwmod.delay(prep.ts_d, prep.pos[I], t, want_grad=True)
+            H.append(h)
+            G.append(g)
+        ctx.save_for_backward(torch.tensor(np.stack(G)))
+        return torch.tensor(np.stack(H))
+
+    @staticmethod
+    def backward(ctx, gH):
+        (G,) = ctx.saved_tensors
+        return torch.einsum("ij,ijk->k", gH, G), None
+
+
 def logp_grad(prep: StdPrepared, X, beta=None):
     """log p~, its gradient (autograd) and a status per chain; X (C, d)."""
     X = np.atleast_2d(np.asarray(X, np.float64))
@@ -294,6 +380,9 @@ def logp_grad(prep: StdPrepared, X, beta=None):
             continue
         if not np.all(np.isfinite(X[c])):
             status[c] = ST_NONFINITE
+            continue
+        if prep.has_cw and cwmod.max_y(th[lay.cw:lay.cw + 8], prep.ts_d[-1]) >= 1.0:
+            status[c] = ST_CW
             continue
         x = torch.tensor(X[c], requires_grad=True)
         try:
@@ -321,8 +410,9 @@ def z_scale(prep: StdPrepared, x, beta=1.0):
     xt = torch.tensor(np.asarray(x, np.float64))
     th, z = xt[: lay.n_theta], xt[lay.z:].reshape(n, lay.P)
     a, _, _, (rho, kap, kdm) = prep.transform(th, z, beta)
-    a = a.numpy()
-    rho, kap, kdm = rho.numpy(), kap.numpy(), kdm.numpy()
+    a = a.detach().numpy()
+    aD = prep.cw_coefficients(th).detach().numpy() if prep.has_cw else None
+    rho, kap, kdm = rho.detach().numpy(), kap.detach().numpy(), kdm.detach().numpy()
     pa = np.zeros_like(a)                      # |phi^-1| |a|
     for k in range(lay.Ka):
         phinv = np.abs(np.linalg.inv(rho[k] * prep.Gamma + np.diag(kap[:, k])))
@@ -337,7 +427,8 @@ def z_scale(prep: StdPrepared, x, beta=1.0):
         D = np.concatenate([np.repeat(rho + kap[I], 2), np.repeat(kdm[I], 2)])
         Sig = np.linalg.inv(beta * prep.S0[I] + np.diag(1.0 / D))
         L = np.linalg.cholesky(0.5 * (Sig + Sig.T))
-        V = beta * (prep.dabs[I] + prep.Gabs[I] @ np.abs(a[I])) + pa[I]
+        dab = prep.dabs[I] if not prep.has_cw else prep.dabs[I] + prep.GabsD[I] @ np.abs(aD[I])
+        V = beta * (dab + prep.Gabs[I] @ np.abs(a[I])) + pa[I]
         out[I] = np.abs(L).T @ V
     return out
 
@@ -367,11 +458,15 @@ def _rounding_shift(prep: StdPrepared, X, beta=None, seed=0):
     # (a) independent rounding of every stored entry
     p2 = copy.copy(prep)
     p2.S0, p2.dvec = list(prep.S0), list(prep.dvec)
+    if prep.has_cw:
+        p2.SD = list(prep.SD)
     for I in range(prep.n_psr):
         e = eps * np.sqrt(max(prep.ntoa[I], 1))
         xi = rng.uniform(-1.0, 1.0, prep.S0[I].shape)
         p2.S0[I] = prep.S0[I] + e * prep.Gabs[I] * 0.5 * (xi + xi.T)
         p2.dvec[I] = prep.dvec[I] + e * prep.dabs[I] * rng.uniform(-1.0, 1.0, prep.dvec[I].shape)
+        if prep.has_cw:
+            p2.SD[I] = prep.SD[I] + e * prep.GabsD[I] * rng.uniform(-1.0, 1.0, prep.SD[I].shape)
     # (b) rounding shared by every sum a TOA enters (and so by the
     # timing-model projection): each per-TOA weight 1/N_i scaled by
     # 1 + eps sqrt(n_I) u_i, the Gram quantities recomputed
@@ -404,4 +499,4 @@ def coefficients(prep: StdPrepared, x, beta=1.0):
     lay = prep.lay
     xt = torch.tensor(np.asarray(x, np.float64))
     a, _, _, _ = prep.transform(xt[: lay.n_theta], xt[lay.z:].reshape(prep.n_psr, lay.P), beta)
-    return a.numpy()
+    return a.detach().numpy()
