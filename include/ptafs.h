@@ -257,17 +257,33 @@ int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, d
  * likelihood temperature (App. B, Eqs. tempered_post, mv_normal_post_temp; 1
  * is the untempered posterior).  Every constant is kept (normalised density).
  *
- * Parameter vector: [theta | z], theta = [gw | rn per pulsar | dm per pulsar]
- * with 2 entries per process for the power law (log10 A, gamma) or one per
- * frequency for the free spectrum (log10 rho_k, rho_k = 10^theta in s^2,
- * Sec. IV.A); z per pulsar: P = 2 ka + 2 nf_dm entries (k = 1 sin, k = 1 cos, ...
- * of the red/common block, ka = max(nf_rn, nf_gw), then the DM block).
- * Per-chain statuses as above (1 box, 2 a factorisation fails, 4 non-finite).
+ * Deterministic signal (Sec. IV.C, Eqs. det_F_basis, stoch_det_posterior,
+ * det_mean, decenter_det_PTA, standardized_det_posterior), optional: a CW
+ * (the Earth-term waveform of the per-TOA form) represented per pulsar as
+ * h = F_D a_D(theta_cw) in its own basis F_D of frequencies k / T_D,
+ * k = 1..K_D, on an extended span T_D.  a_D is the discrete Fourier transform
+ * of the delay sampled at M = 2 K_D + 1 times t_j = j T_D / M:
+ * a_(k,sin) = 2/M sum_j h_j sin(2 pi k j / M), a_(k,cos) likewise with cos
+ * (the samples' mean, which the timing model absorbs, is dropped).  The data
+ * set stores F~^T N~^-1 F_D, F_D^T N~^-1 dt and F_D^T N~^-1 F_D per pulsar;
+ * per evaluation d and dt^T N~^-1 dt above become those of dt - h, so the
+ * transform centres on the shifted MAP a_bar_CURN (Eq. det_mean) and the
+ * likelihood is that of dt - h.
+ *
+ * Parameter vector: [theta | z], theta = [gw | rn per pulsar | dm per pulsar |
+ * cw (8, with a CW)] with 2 entries per process for the power law (log10 A,
+ * gamma) or one per frequency for the free spectrum (log10 rho_k,
+ * rho_k = 10^theta in s^2, Sec. IV.A), the CW parameters in the order of the
+ * per-TOA form; z per pulsar: P = 2 ka + 2 nf_dm entries (k = 1 sin, k = 1 cos,
+ * ... of the red/common block, ka = max(nf_rn, nf_gw), then the DM block).
+ * Per-chain statuses as above (1 box, 2 a factorisation fails, 3 the CW
+ * coalesces at a sample time of [0, T_D), 4 non-finite).
  * ====================================================================== */
 
 #define PTAFS_SPEC_POWERLAW 0
 #define PTAFS_SPEC_FREE 1
 #define PTAFS_MAX_TM 64        /* timing-model columns per TOA */
+#define PTAFS_MAX_CW_HARM 64   /* K_D of the deterministic basis */
 
 typedef struct ptafs_std ptafs_std;   /* opaque */
 
@@ -289,12 +305,16 @@ typedef struct {
                                     are dropped (column-pivoted factorisation). */
   int32_t spectrum;              /* PTAFS_SPEC_POWERLAW or PTAFS_SPEC_FREE (all processes) */
   const double *prior_lo, *prior_hi;   /* n_theta box edges */
+  int32_t has_cw;                /* 1: a CW in the deterministic basis (8 more theta entries) */
+  int32_t cw_nf;                 /* K_D, 1..PTAFS_MAX_CW_HARM (ignored without a CW) */
+  double cw_tspan;               /* T_D > 0, s (ignored without a CW) */
 } ptafs_std_desc;
 
 typedef struct {
   int64_t d, n_theta, off_gw, off_rn, off_dm, off_z;
   int64_t n_psr, n_toa, k_coef, k_dm, p;   /* p = 2 k_coef + 2 k_dm coefficients per pulsar */
   size_t dataset_bytes, workspace_bytes, hmc_bytes;
+  int64_t off_cw;                /* first CW entry of theta, -1 without a CW */
 } ptafs_std_layout_info;
 
 /* Copy a data set, marginalise its timing model and store the per-pulsar Gram
@@ -307,9 +327,14 @@ void ptafs_std_destroy(ptafs_std *ds);
  * with no GPU call (for checks and for sizing): for pulsar `pulsar`,
  * s0 [p][p] = F~^T N~^-1 F~, dvec [p] = F~^T N~^-1 dt and
  * scal[0] = dt^T N~^-1 dt, scal[1] = -1/2 ln det(2 pi G^T N G), scal[2] = the
- * number of timing-model columns kept (host pointers, original order). */
+ * number of timing-model columns kept (host pointers, original order).
+ * ptafs_std_precompute_cw gives the CW products of a data set with a CW:
+ * sd [p][2 K_D] = F~^T N~^-1 F_D, ed [2 K_D] = F_D^T N~^-1 dt,
+ * qd [2 K_D][2 K_D] = F_D^T N~^-1 F_D (basis order k = 1 sin, k = 1 cos, ...). */
 int ptafs_std_precompute(const ptafs_std_desc *desc, int32_t pulsar, double *s0, double *dvec,
                          double *scal);
+int ptafs_std_precompute_cw(const ptafs_std_desc *desc, int32_t pulsar, double *sd, double *ed,
+                            double *qd);
 int ptafs_std_layout(const ptafs_std *ds, int32_t n_chains, ptafs_std_layout_info *out);
 
 /*

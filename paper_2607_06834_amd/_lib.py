@@ -71,13 +71,17 @@ class StdDesc(C.Structure):
         ("spectrum", C.c_int32),
         ("prior_lo", c_double_p),
         ("prior_hi", c_double_p),
+        ("has_cw", C.c_int32),
+        ("cw_nf", C.c_int32),
+        ("cw_tspan", C.c_double),
     ]
 
 
 class StdLayoutInfo(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "d", "n_theta", "off_gw", "off_rn", "off_dm", "off_z", "n_psr", "n_toa", "k_coef", "k_dm", "p")] + [
-        ("dataset_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t), ("hmc_bytes", C.c_size_t)]
+        ("dataset_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t), ("hmc_bytes", C.c_size_t),
+        ("off_cw", C.c_int64)]
 
 
 class LayoutInfo(C.Structure):
@@ -95,7 +99,8 @@ EXPORTS = (
     "ptafs_set_tuning", "ptafs_get_tuning",
     "ptafs_hmc_run", "ptafs_profile_stages", "ptafs_strerror",
     "ptafs_std_create", "ptafs_std_destroy", "ptafs_std_layout", "ptafs_std_logp_grad",
-    "ptafs_std_coefficients", "ptafs_std_hmc_run", "ptafs_std_precompute", "ptafs_std_profile_stages",
+    "ptafs_std_coefficients", "ptafs_std_hmc_run", "ptafs_std_precompute", "ptafs_std_precompute_cw",
+    "ptafs_std_profile_stages",
 )
 
 _lib = None
@@ -141,6 +146,8 @@ def load():
     lib.ptafs_std_destroy.restype = None
     lib.ptafs_std_precompute.argtypes = [C.POINTER(StdDesc), C.c_int32, c_double_p, c_double_p, c_double_p]
     lib.ptafs_std_precompute.restype = C.c_int
+    lib.ptafs_std_precompute_cw.argtypes = [C.POINTER(StdDesc), C.c_int32, c_double_p, c_double_p, c_double_p]
+    lib.ptafs_std_precompute_cw.restype = C.c_int
     lib.ptafs_std_layout.argtypes = [vp, C.c_int32, C.POINTER(StdLayoutInfo)]
     lib.ptafs_std_layout.restype = C.c_int
     lib.ptafs_std_logp_grad.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, vp]

@@ -228,8 +228,9 @@ class Dataset:
 
 def _make_std_desc(desc, keep):
     """ptafs_std_desc for a mapping: the fields of a data set plus optional
-    ``tm`` (n_toa x n_tm design matrix) and ``spectrum`` ("powerlaw" or
-    "free")."""
+    ``tm`` (n_toa x n_tm design matrix), ``spectrum`` ("powerlaw" or "free")
+    and, with ``has_cw``, ``cw_nf`` (K_D, default 60) and ``cw_tspan`` (T_D,
+    default twice ``tspan``) of the deterministic basis."""
     def arr(a, dtype):
         a = np.ascontiguousarray(np.asarray(a), dtype=dtype)
         keep.append(a)
@@ -257,7 +258,25 @@ def _make_std_desc(desc, keep):
     d.spectrum = 1 if desc.get("spectrum", "powerlaw") == "free" else 0
     d.prior_lo = _ptr(arr(desc["prior_lo"], np.float64), C.c_double)
     d.prior_hi = _ptr(arr(desc["prior_hi"], np.float64), C.c_double)
+    d.has_cw = 1 if desc.get("has_cw", 0) else 0
+    d.cw_nf = int(desc.get("cw_nf", 60)) if d.has_cw else 0
+    d.cw_tspan = float(desc.get("cw_tspan", 2.0 * float(desc["tspan"]))) if d.has_cw else 0.0
     return d
+
+
+def ptafs_std_precompute_cw(desc, pulsar):
+    """Host-only CW products of the standardized form for one pulsar:
+    (F~^T N~^-1 F_D [p, 2 K_D], F_D^T N~^-1 dt [2 K_D], F_D^T N~^-1 F_D [2 K_D, 2 K_D])."""
+    keep = []
+    d = _make_std_desc(desc, keep)
+    ka = max(int(desc["nf_rn"]), int(desc["nf_gw"]))
+    p = 2 * ka + 2 * int(desc["nf_dm"])
+    k2 = 2 * int(d.cw_nf)
+    sd, ed, qd = np.zeros((p, k2)), np.zeros(k2), np.zeros((k2, k2))
+    _lib.check(_lib.load().ptafs_std_precompute_cw(C.byref(d), int(pulsar), _ptr(sd, C.c_double),
+                                                   _ptr(ed, C.c_double), _ptr(qd, C.c_double)),
+               "ptafs_std_precompute_cw")
+    return sd, ed, qd
 
 
 def ptafs_std_precompute(desc, pulsar):

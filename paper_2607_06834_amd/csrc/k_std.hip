@@ -22,6 +22,13 @@
 // and the explicit prior derivatives 1/2 u^T Gamma u - tr(phi_k^-1 Gamma) (rho)
 // and 1/2 u_I^2 - (phi_k^-1)_II (kappa), with tr(phi^-1 Gamma) = |X_k chol Gamma|_F^2.
 //
+// With a deterministic CW in its own basis (Sec. IV.C), k_std_cw_fwd replaces
+// d and dt^T N~^-1 dt of each (pulsar, chain) by those of dt - F_D a_D before
+// the transform, and k_std_cw_bwd takes dlog p / d d_bar = beta (a + Sigma v)
+// (the likelihood's explicit term plus the shift of a_hat) back to the CW
+// parameters through S_D, Q_D, e_D, the transform of the samples and the
+// waveform's derivative.
+//
 // Matrices live in LDS as lower 16x16 tiles (row-major inside).  The
 // factorisation is right-looking by block columns: a diagonal tile is factorised
 // and inverted by one wave (lane r holds row r, operands by readlane), the
@@ -33,6 +40,7 @@
 // operand's lane q + 4v), which is directly the B operand of a next product.
 #include <cmath>
 
+#include "cw_dev.h"
 #include "std.h"
 
 namespace {
@@ -471,8 +479,10 @@ __global__ __launch_bounds__(256, 2) void k_std_fwd(StdDev S, const double *__re
   }
   int bad = 0;
   double dr = 0.0;   // d~_r (unscaled) of this thread's row, kept for the likelihood
+  // d of the data, or of the data minus the deterministic signal
+  const double *dsrc = S.has_cw ? S.dbar + ((size_t)c * S.n_psr + I) * pp : S.dvec + (size_t)I * pp;
   for (int r = tid; r < pp; r += 256) {
-    dr = (r < P) ? S.dvec[(size_t)I * pp + r] : 0.0;
+    dr = (r < P) ? dsrc[r] : 0.0;
     vd[r] = beta * dr;
     vz[r] = (r < P) ? xc[S.off_z + I * P + (P - 1 - r)] : 0.0;
     lz[r] = 0.0;
@@ -563,8 +573,9 @@ __global__ __launch_bounds__(256, 2) void k_std_fwd(StdDev S, const double *__re
     // beta log L = beta (-dt N~^-1 dt / 2 + a.d - a.S0 a / 2 + c1), with
     // beta a.S0 a = beta a.d - a.v1
     const double *k2 = S.cconst + 2 * I;
+    const double c0 = S.has_cw ? S.cbar[(size_t)c * S.n_psr + I] : k2[0];
     double *o = S.lik + ((size_t)c * S.n_psr + I) * 2;
-    o[0] = beta * (k2[1] - 0.5 * k2[0]) + 0.5 * beta * part_d + 0.5 * part_v;
+    o[0] = beta * (k2[1] - 0.5 * c0) + 0.5 * beta * part_d + 0.5 * part_v;
     o[1] = part_j;
     S.flag1[(size_t)c * S.n_psr + I] = ok ? 0 : ps::kFlagNotPD;
   }
@@ -804,12 +815,19 @@ __global__ __launch_bounds__(256) void k_std_bwd(StdDev S, const double *__restr
     if (h == 1) {
       tmp[r] = suf;
       tmp[pp + r] = fma(vh[r], sv, tt + 0.5 * ss);
+      vv[r] = sv;   // v~ is no longer read
     }
   }
   __syncthreads();
   if (r < P && h == 0) {
     const double Dv = ps::curn_var(S, xc, I, P - 1 - r);
     gd[r] = (fma(sv, vh[r] + tmp[r], tt + 0.5 * ss) + tmp[pp + r]) / (Dv * Dv);
+    if (S.has_cw) {
+      // dlog p / d d_bar (original order): beta a (likelihood) + beta Sigma v (a_hat)
+      const double beta = S.beta ? S.beta[c] : 1.0;
+      const int j = P - 1 - r;
+      S.gdbar[((size_t)c * S.n_psr + I) * P + j] = beta * (S.avec[vb + j] + (sv + vv[r]));
+    }
   }
   __syncthreads();
   if (tid < S.ka) {
@@ -819,6 +837,124 @@ __global__ __launch_bounds__(256) void k_std_bwd(StdDev S, const double *__restr
     const int k = tid - 64, r0 = P - 1 - (2 * S.ka + 2 * k), r1 = r0 - 1;
     S.dD_dm[((size_t)c * S.n_psr + I) * S.kdm + k] = gd[r0] + gd[r1];
   }
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic CW in its own basis (Sec. IV.C), per (pulsar, chain).
+// ---------------------------------------------------------------------------
+__device__ inline pt::CwLane cw_lane(const double cst[pt::kCwRows]) {
+  pt::CwLane L;
+  L.K1 = cst[pt::kCwK1];
+  L.inv32X = cst[pt::kCwInv32X];
+  L.phi0 = cst[pt::kCwPhi0];
+  L.a0 = cst[pt::kCwA0];
+  L.ci = cst[pt::kCwCi];
+  L.U = cst[pt::kCwU];
+  L.V = cst[pt::kCwV];
+  L.c2s = cst[pt::kCwC2s];
+  L.s2s = cst[pt::kCwS2s];
+  return L;
+}
+
+// The delay at the md sample times t_j = j T_D / md (one thread each), its
+// transform a_D (Eq. det_F_basis), then d_bar = d - S_D a_D (reversed order,
+// zero-padded, as k_std_fwd reads it) and
+// c_bar = c - 2 e_D^T a_D + a_D^T Q_D a_D.
+__global__ __launch_bounds__(256) void k_std_cw_fwd(StdDev S, const double *__restrict__ x) {
+  __shared__ double hs[ps::kMaxCwM], ad[ps::kMaxCw2], red[4];
+  const int tid = threadIdx.x;
+  const int pi = xcd_index(blockIdx.x, gridDim.x);
+  const int I = pi / S.n_chains, c = pi - I * S.n_chains;
+  const double *xc = x + (size_t)c * S.d;
+  const int K2 = 2 * S.kd, M = S.md, P = S.P, pp = S.pp;
+  const size_t q = (size_t)c * S.n_psr + I;
+  if (tid < M) {
+    double cst[pt::kCwRows];
+    pt::cw_constants(xc + S.off_cw, S.cw_pos + 3 * I, cst);
+    hs[tid] = cw_lane(cst).delay((double)tid * S.td / M).h;
+  }
+  __syncthreads();
+  if (tid < K2) {
+    const double *f = S.cw_dft + (size_t)tid * M;
+    double s = 0.0;
+    for (int j = 0; j < M; ++j) s = fma(f[j], hs[j], s);
+    ad[tid] = s;
+    S.cw_ad[q * K2 + tid] = s;
+  }
+  __syncthreads();
+  for (int r = tid; r < pp; r += 256) {
+    double v = 0.0;
+    if (r < P) {
+      const double *sd = S.cw_sd + ((size_t)I * P + (P - 1 - r)) * K2;
+      double s = 0.0;
+      for (int k = 0; k < K2; ++k) s = fma(sd[k], ad[k], s);
+      v = S.dvec[(size_t)I * pp + r] - s;
+    }
+    S.dbar[q * pp + r] = v;
+  }
+  double part = 0.0;
+  if (tid < K2) {
+    const double *qd = S.cw_qd + ((size_t)I * K2 + tid) * K2;
+    double s = 0.0;
+    for (int k = 0; k < K2; ++k) s = fma(qd[k], ad[k], s);
+    part = ad[tid] * (s - 2.0 * S.cw_ed[(size_t)I * K2 + tid]);
+  }
+  part = block_sum(part, red);
+  if (tid == 0) S.cbar[q] = S.cconst[2 * I] + part;
+}
+
+// dlog p / d a_D = -S_D^T g + beta (e_D - Q_D a_D) with g = dlog p / d d_bar
+// (k_std_bwd), then g_h = (transform)^T dlog p / d a_D at the sample times and
+// the pulsar's part of dlog p / d theta_cw = sum_j g_h,j dh_j / d theta.
+__global__ __launch_bounds__(256) void k_std_cw_bwd(StdDev S, const double *__restrict__ x) {
+  __shared__ double gd[ps::kMaxTiles * 16], ad[ps::kMaxCw2], ga[ps::kMaxCw2], red[4][8];
+  const int tid = threadIdx.x;
+  const int pi = xcd_index(blockIdx.x, gridDim.x);
+  const int I = pi / S.n_chains, c = pi - I * S.n_chains;
+  const double *xc = x + (size_t)c * S.d;
+  const int K2 = 2 * S.kd, M = S.md, P = S.P;
+  const size_t q = (size_t)c * S.n_psr + I;
+  const double beta = S.beta ? S.beta[c] : 1.0;
+  for (int j = tid; j < P; j += 256) gd[j] = S.gdbar[q * P + j];
+  if (tid < K2) ad[tid] = S.cw_ad[q * K2 + tid];
+  __syncthreads();
+  if (tid < K2) {
+    const double *sd = S.cw_sd + (size_t)I * P * K2 + tid;
+    const double *qd = S.cw_qd + (size_t)I * K2 * K2 + tid;   // Q_D is symmetric: column tid
+    double s1 = 0.0, s2 = 0.0;
+    for (int j = 0; j < P; ++j) s1 = fma(sd[(size_t)j * K2], gd[j], s1);
+    for (int k = 0; k < K2; ++k) s2 = fma(qd[(size_t)k * K2], ad[k], s2);
+    ga[tid] = beta * (S.cw_ed[(size_t)I * K2 + tid] - s2) - s1;
+  }
+  __syncthreads();
+  double out[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (tid < M) {
+    double gh = 0.0;
+    for (int k = 0; k < K2; ++k) gh = fma(S.cw_dft[(size_t)k * M + tid], ga[k], gh);
+    double cst[pt::kCwRows];
+    pt::cw_constants(xc + S.off_cw, S.cw_pos + 3 * I, cst);
+    const pt::CwLane L = cw_lane(cst);
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    L.adjoint(L.delay((double)tid * S.td / M), gh, acc);
+    // the sky pair through the antenna derivatives, ln 10 for the log10 parameters
+    out[0] = -(cst[pt::kCwDfpC] * acc[0] + cst[pt::kCwDfxC] * acc[1]);
+    out[1] = -(cst[pt::kCwDfpP] * acc[0] + cst[pt::kCwDfxP] * acc[1]);
+    out[2] = ps::kLn10 * acc[2];
+    out[3] = ps::kLn10 * acc[3];
+    out[4] = acc[4];
+    out[5] = acc[5];
+    out[6] = acc[6];
+    out[7] = ps::kLn10 * acc[7];
+  }
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    double t = out[v];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6][v] = t;
+  }
+  __syncthreads();
+  if (tid < 8) S.dcw[q * 8 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
 // ---------------------------------------------------------------------------
@@ -842,6 +978,15 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
   }
   for (int i = S.n_theta + tid; i < S.d; i += 256)
     if (!isfinite(xc[i])) bad_in = 1;
+  // the CW must not coalesce before the last sample time of its basis
+  int bad_cw = 0;
+  if (S.has_cw && tid == 0) {
+    const double *tc = xc + S.off_cw;
+    const double M = exp(ps::kLn10 * tc[2]) * pt::kTsun, w0 = pt::kPi * exp(ps::kLn10 * tc[3]);
+    const double K1 = 256.0 / 5.0 * exp((5.0 / 3.0) * log(M * w0)) * w0;
+    const double y = K1 * ((double)(S.md - 1) * S.td / S.md);
+    bad_cw = !(y < 1.0);
+  }
   // factorisation flags
   int fl = 0;
   for (int i = tid; i < n; i += 256) fl |= S.flag1[(size_t)c * n + i];
@@ -909,24 +1054,32 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
     }
     gc[e] = g;
   }
+  // dlog p / d theta_cw: the pulsars' parts in order
+  if (S.has_cw && tid < 8) {
+    double g = 0.0;
+    for (int I = 0; I < n; ++I) g += S.dcw[((size_t)c * n + I) * 8 + tid];
+    gc[S.off_cw + tid] = g;
+  }
   // reduce the flags and log p
   {
     double v = lp;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    const int bb = __any(bad_box), bi = __any(bad_in), bf = __any(fl != 0);
+    const int bb = __any(bad_box), bi = __any(bad_in), bf = __any(fl != 0), bc = __any(bad_cw);
     if ((tid & 63) == 0) red[tid >> 6] = v;
-    __shared__ int sb[4][3];
+    __shared__ int sb[4][4];
     if ((tid & 63) == 0) {
       sb[tid >> 6][0] = bb;
       sb[tid >> 6][1] = bi;
       sb[tid >> 6][2] = bf;
+      sb[tid >> 6][3] = bc;
     }
     __syncthreads();
     lp = (red[0] + red[1]) + (red[2] + red[3]);
     bad_box = sb[0][0] | sb[1][0] | sb[2][0] | sb[3][0];
     bad_in = sb[0][1] | sb[1][1] | sb[2][1] | sb[3][1];
     fl = sb[0][2] | sb[1][2] | sb[2][2] | sb[3][2];
+    bad_cw = sb[0][3] | sb[1][3] | sb[2][3] | sb[3][3];
   }
   lp += S.prior_const;
   // output finiteness
@@ -938,6 +1091,7 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
   int st = PTAFS_ST_OK;
   if (bad_box) st = PTAFS_ST_PRIOR;
   else if (bad_in) st = PTAFS_ST_NONFINITE;
+  else if (bad_cw) st = PTAFS_ST_CW;
   else if (fl) st = PTAFS_ST_NOTPD;
   else if (nonfin) st = PTAFS_ST_NONFINITE;
   (void)beta;
@@ -1001,6 +1155,20 @@ hipError_t init_attributes() {
     case 8: hipLaunchKernelGGL(KERNEL<8>, dim3(GRID), dim3(256), lds_bytes<8>(), s, __VA_ARGS__); break; \
     default: return hipErrorInvalidValue;                                                           \
   }
+
+hipError_t launch_std_cw_fwd(const StdDev &S, const double *x, hipStream_t s) {
+  const int grid = S.n_chains * S.n_psr;
+  if (grid == 0 || !S.has_cw) return hipSuccess;
+  hipLaunchKernelGGL(k_std_cw_fwd, dim3(grid), dim3(256), 0, s, S, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_std_cw_bwd(const StdDev &S, const double *x, hipStream_t s) {
+  const int grid = S.n_chains * S.n_psr;
+  if (grid == 0 || !S.has_cw) return hipSuccess;
+  hipLaunchKernelGGL(k_std_cw_bwd, dim3(grid), dim3(256), 0, s, S, x);
+  return hipGetLastError();
+}
 
 hipError_t launch_std_fwd(const StdDev &S, const double *x, hipStream_t s) {
   const int grid = S.n_chains * S.n_psr;

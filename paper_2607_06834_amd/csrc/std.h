@@ -15,6 +15,8 @@ constexpr double kLn2Pi = 1.83787706640934548356065947281;
 constexpr int kThreads = 256;                    // threads per problem workgroup
 constexpr int kMaxTiles = 8;                     // 16-wide tiles per dimension (128)
 constexpr int kMaxRhoK = 32;                     // frequencies of the common process (>= PTAFS_MAX_HARM)
+constexpr int kMaxCw2 = 2 * PTAFS_MAX_CW_HARM;   // coefficients of the deterministic basis
+constexpr int kMaxCwM = kMaxCw2 + 1;             // its sample times
 
 // Lower tiles of a 16T x 16T matrix: tile (I, J), J <= I, at I (I + 1) / 2 + J,
 // row-major inside (element (r, c) of the tile at 16 r + c).
@@ -46,6 +48,15 @@ struct StdDev {
   const double *prior_lo, *prior_hi;
   const double *lnfy;            // ln(f_k yr), k < PTAFS_MAX_HARM
   double pl_c;                   // ln(yr^3 / (12 pi^2 T))
+  // deterministic CW in its own basis (has_cw): K_D = kd frequencies k / td,
+  // md = 2 kd + 1 sample times j td / md
+  int has_cw, kd, md, off_cw;
+  double td;
+  const double *cw_sd;           // [n_psr][P][2 kd] F~^T N~^-1 F_D (original coefficient order)
+  const double *cw_ed;           // [n_psr][2 kd] F_D^T N~^-1 dt
+  const double *cw_qd;           // [n_psr][2 kd][2 kd] F_D^T N~^-1 F_D
+  const double *cw_dft;          // [2 kd][md] the transform of the samples to a_D
+  const double *cw_pos;          // [n_psr][3] pulsar unit vectors
   // call
   int n_chains;
   const double *beta;            // [n_chains] or nullptr (1)
@@ -66,6 +77,11 @@ struct StdDev {
   int32_t *flag1;                // [n_chains][n_psr] factorisation failures of the transform
   int32_t *flag2;                // [n_chains][ka] dense prior factorisations
   int32_t *flag3;                // [n_chains][n_psr][ka + kdm] diagonal items
+  double *cw_ad;                 // [n_chains][n_psr][2 kd] a_D of each chain
+  double *dbar;                  // [n_chains][n_psr][pp] d of dt - h, reversed order, zero-padded
+  double *cbar;                  // [n_chains][n_psr] dt~^T N~^-1 dt~ of dt~ = dt - h
+  double *gdbar;                 // [n_chains][n_psr][P] dlog p / d d_bar (original order)
+  double *dcw;                   // [n_chains][n_psr][8] the pulsar's part of dlog p / d theta_cw
 };
 
 // Spectrum of process proc (0 common, 1 red noise of pulsar I, 2 DM of pulsar
@@ -115,4 +131,6 @@ hipError_t launch_std_prior(const ps::StdDev &S, const double *x, hipStream_t s)
 hipError_t launch_std_bwd(const ps::StdDev &S, const double *x, double *grad, hipStream_t s);
 hipError_t launch_std_finalize(const ps::StdDev &S, const double *x, double *logp, double *grad,
                                int32_t *status, hipStream_t s, const ps::StdKick *kick = nullptr);
+hipError_t launch_std_cw_fwd(const ps::StdDev &S, const double *x, hipStream_t s);
+hipError_t launch_std_cw_bwd(const ps::StdDev &S, const double *x, hipStream_t s);
 }  // namespace psk

@@ -130,6 +130,16 @@ int plan(const ptafs_std_desc *d, ps::StdDev &B, int64_t &ntoa) {
   B.off_gw = o; o += B.w_gw;
   B.off_rn = o; o += n * B.w_rn;
   B.off_dm = o; o += n * B.w_dm;
+  B.has_cw = d->has_cw ? 1 : 0;
+  B.off_cw = B.has_cw ? o : -1;
+  if (B.has_cw) {
+    if (d->cw_nf < 1 || !(d->cw_tspan > 0.0) || !std::isfinite(d->cw_tspan)) return PTAFS_E_ARG;
+    if (d->cw_nf > PTAFS_MAX_CW_HARM) return PTAFS_E_LIMIT;
+    B.kd = d->cw_nf;
+    B.md = 2 * B.kd + 1;
+    B.td = d->cw_tspan;
+    o += 8;
+  }
   B.n_theta = o;
   B.off_z = o; o += n * B.P;
   B.d = o;
@@ -145,13 +155,18 @@ int plan(const ptafs_std_desc *d, ps::StdDev &B, int64_t &ntoa) {
 
 size_t dataset_bytes_of(const ps::StdDev &B) {
   const size_t n = B.n_psr, pp = B.pp, nt = ps::ntiles(B.tg) * 256;
-  return (n * pp * pp + n * pp + 2 * n + 2 * nt + n * n + 2 * std::max(B.n_theta, 1) + PTAFS_MAX_HARM) *
-             sizeof(double) + 16 * 256;
+  size_t cw = 0;
+  if (B.has_cw) {
+    const size_t k2 = 2 * (size_t)B.kd;
+    cw = n * B.P * k2 + n * k2 + n * k2 * k2 + k2 * B.md + 3 * n;
+  }
+  return (n * pp * pp + n * pp + 2 * n + 2 * nt + n * n + 2 * std::max(B.n_theta, 1) + PTAFS_MAX_HARM + cw) *
+             sizeof(double) + 21 * 256;
 }
 
 struct WsLayout {
   size_t xinv, avec, ahat, v1, v2, lik, quad_k, drho_e, dkap_e, ddm_e, diag_q, dD_rn, dD_dm, flag1,
-      flag2, flag3, total;
+      flag2, flag3, cw_ad, dbar, cbar, gdbar, dcw, total;
 };
 WsLayout ws_layout(const ps::StdDev &B, int C) {
   WsLayout L{};
@@ -179,6 +194,13 @@ WsLayout ws_layout(const ps::StdDev &B, int C) {
   L.flag1 = take(c * n * I4);
   L.flag2 = take(c * ka * I4);
   L.flag3 = take(c * n * (ka + kd) * I4);
+  if (B.has_cw) {
+    L.cw_ad = take(c * n * 2 * (size_t)B.kd * D8);
+    L.dbar = take(c * n * pp * D8);
+    L.cbar = take(c * n * D8);
+    L.gdbar = take(c * n * (size_t)B.P * D8);
+    L.dcw = take(c * n * 8 * D8);
+  }
   L.total = o;
   return L;
 }
@@ -223,23 +245,33 @@ ps::StdDev make_dev(const ptafs_std *ds, int C, const double *beta) {
   S.flag1 = reinterpret_cast<int32_t *>(w + L.flag1);
   S.flag2 = reinterpret_cast<int32_t *>(w + L.flag2);
   S.flag3 = reinterpret_cast<int32_t *>(w + L.flag3);
+  if (S.has_cw) {
+    S.cw_ad = reinterpret_cast<double *>(w + L.cw_ad);
+    S.dbar = reinterpret_cast<double *>(w + L.dbar);
+    S.cbar = reinterpret_cast<double *>(w + L.cbar);
+    S.gdbar = reinterpret_cast<double *>(w + L.gdbar);
+    S.dcw = reinterpret_cast<double *>(w + L.dcw);
+  }
   return S;
 }
 
 int enqueue_eval(ptafs_std *ds, int C, const double *x, const double *beta, double *logp, double *grad,
                  int32_t *status, hipStream_t s, const ps::StdKick *kick = nullptr) {
   const ps::StdDev S = make_dev(ds, C, beta);
+  PS_TRY(psk::launch_std_cw_fwd(S, x, s));
   PS_TRY(psk::launch_std_fwd(S, x, s));
   PS_TRY(psk::launch_std_prior(S, x, s));
   PS_TRY(psk::launch_std_bwd(S, x, grad, s));
+  PS_TRY(psk::launch_std_cw_bwd(S, x, s));
   PS_TRY(psk::launch_std_finalize(S, x, logp, grad, status, s, kick));
   return PTAFS_OK;
 }
 
 // ------------------------------------------------------ Gram precompute ---
 //
-// Per pulsar: the weighted Gram matrix of B = [F~ | M | dt] with weights 1/N,
-// then the timing model is marginalised.  With the columns of M scaled to
+// Per pulsar: the weighted Gram matrix of B = [F~ | F_D | M | dt] with weights
+// 1/N (F_D, the basis of the deterministic signal, only with a CW), then the
+// timing model is marginalised.  With the columns of M scaled to
 // unit weighted norm, a column-pivoted Cholesky factorisation of M^T N^-1 M
 // (the same R factor as a column-pivoted QR of N^-1/2 M) selects r
 // independent columns S (pivots below 1e-10 of the first end the
@@ -250,13 +282,16 @@ int enqueue_eval(ptafs_std *ds, int C, const double *x, const double *beta, doub
 //   ln det(G^T N G) = ln det N + ln det(M_S^T N^-1 M_S) - ln det(M_S^T M_S).
 struct PsrGram {
   std::vector<double> s0, dv;   // P x P, P (original order)
+  std::vector<double> sd, ed, qd;   // with a CW: P x 2K_D, 2K_D, 2K_D x 2K_D
   double c = 0.0, cst = 0.0;
   int rank = 0;
 };
 
 void gram_pulsar(const ptafs_std_desc *d, const ps::StdDev &B, int I, PsrGram &out) {
   const int64_t b = d->toa_offsets[I], e = d->toa_offsets[I + 1];
-  const int P = B.P, ka = B.ka, kdm = B.kdm, kmax = std::max(ka, kdm);
+  const int ka = B.ka, kdm = B.kdm, kmax = std::max(ka, kdm);
+  const int PS = B.P, K2 = B.has_cw ? 2 * B.kd : 0;
+  const int P = PS + K2;   // the projected basis columns: F~, then F_D
   const int m = d->n_tm > 0 ? d->n_tm : 3;
   const int Q = P + m + 1;
   std::vector<double> G((size_t)Q * Q, 0.0), MMu((size_t)m * m, 0.0), row(Q), sn(kmax), cs(kmax);
@@ -282,6 +317,15 @@ void gram_pulsar(const ptafs_std_desc *d, const ps::StdDev &B, int I, PsrGram &o
     for (int k = 0; k < kdm; ++k) {
       row[o++] = w * sn[k];
       row[o++] = w * cs[k];
+    }
+    if (K2) {
+      const double phd = 2.0 * M_PI * d->t[i] / B.td;
+      for (int k = 0; k < B.kd; ++k) {
+        double sv, cv;
+        sincos((k + 1) * phd, &sv, &cv);
+        row[o++] = sv;
+        row[o++] = cv;
+      }
     }
     if (d->n_tm > 0) {
       for (int j = 0; j < m; ++j) row[o++] = d->tm[(size_t)i * d->n_tm + j];
@@ -356,17 +400,34 @@ void gram_pulsar(const ptafs_std_desc *d, const ps::StdDev &B, int I, PsrGram &o
       Y[(size_t)i * NC + j] = v / Lm[(size_t)i * m + i];
     }
   }
-  out.s0.assign((size_t)P * P, 0.0);
-  out.dv.assign(P, 0.0);
+  // the projected Gram matrix of the basis columns and their products with dt
+  std::vector<double> sg((size_t)P * P), dg(P);
   for (int a = 0; a < P; ++a) {
     for (int c = 0; c < P; ++c) {
       double v = g(a, c);
       for (int k = 0; k < r; ++k) v -= Y[(size_t)k * NC + a] * Y[(size_t)k * NC + c];
-      out.s0[(size_t)a * P + c] = v;
+      sg[(size_t)a * P + c] = v;
     }
     double v = g(a, P + m);
     for (int k = 0; k < r; ++k) v -= Y[(size_t)k * NC + a] * Y[(size_t)k * NC + P];
-    out.dv[a] = v;
+    dg[a] = v;
+  }
+  out.s0.assign((size_t)PS * PS, 0.0);
+  out.dv.assign(PS, 0.0);
+  for (int a = 0; a < PS; ++a) {
+    for (int c = 0; c < PS; ++c) out.s0[(size_t)a * PS + c] = sg[(size_t)a * P + c];
+    out.dv[a] = dg[a];
+  }
+  if (K2) {
+    out.sd.assign((size_t)PS * K2, 0.0);
+    out.ed.assign(K2, 0.0);
+    out.qd.assign((size_t)K2 * K2, 0.0);
+    for (int a = 0; a < PS; ++a)
+      for (int j = 0; j < K2; ++j) out.sd[(size_t)a * K2 + j] = sg[(size_t)a * P + PS + j];
+    for (int j = 0; j < K2; ++j) {
+      out.ed[j] = dg[PS + j];
+      for (int k = 0; k < K2; ++k) out.qd[(size_t)j * K2 + k] = sg[(size_t)(PS + j) * P + PS + k];
+    }
   }
   double cc = g(P + m, P + m);
   for (int k = 0; k < r; ++k) cc -= Y[(size_t)k * NC + P] * Y[(size_t)k * NC + P];
@@ -440,6 +501,7 @@ void fill_layout(const ps::StdDev &B, int64_t ntoa, int C, ptafs_std_layout_info
   out->dataset_bytes = dataset_bytes_of(B);
   out->workspace_bytes = ws_layout(B, C).total;
   out->hmc_bytes = hmc_bytes_of(B, C);
+  out->off_cw = B.has_cw ? B.off_cw : -1;
 }
 
 }  // namespace
@@ -543,6 +605,32 @@ int ptafs_std_create(const ptafs_std_desc *d, void *stream, ptafs_std **out) {
   chk(upload(ds, lf.data(), lf.size(), &D.lnfy, s));
   chk(upload(ds, d->prior_lo, (size_t)B.n_theta, &D.prior_lo, s));
   chk(upload(ds, d->prior_hi, (size_t)B.n_theta, &D.prior_hi, s));
+  std::vector<double> sd, ed, qd, dft;
+  if (B.has_cw) {
+    const int K2 = 2 * B.kd, M = B.md;
+    sd.resize((size_t)n * P * K2);
+    ed.resize((size_t)n * K2);
+    qd.resize((size_t)n * K2 * K2);
+    for (int I = 0; I < n; ++I) {
+      std::memcpy(&sd[(size_t)I * P * K2], gr[I].sd.data(), (size_t)P * K2 * sizeof(double));
+      std::memcpy(&ed[(size_t)I * K2], gr[I].ed.data(), (size_t)K2 * sizeof(double));
+      std::memcpy(&qd[(size_t)I * K2 * K2], gr[I].qd.data(), (size_t)K2 * K2 * sizeof(double));
+    }
+    // a_(k,sin) = 2/M sum_j h_j sin(2 pi k j / M), a_(k,cos) likewise; the
+    // angle reduced to k j mod M first, so that it is exact in the argument
+    dft.resize((size_t)K2 * M);
+    for (int k = 1; k <= B.kd; ++k)
+      for (int j = 0; j < M; ++j) {
+        const double ang = 2.0 * M_PI * (double)(((int64_t)k * j) % M) / M;
+        dft[(size_t)(2 * k - 2) * M + j] = 2.0 / M * std::sin(ang);
+        dft[(size_t)(2 * k - 1) * M + j] = 2.0 / M * std::cos(ang);
+      }
+    chk(upload(ds, sd.data(), sd.size(), &D.cw_sd, s));
+    chk(upload(ds, ed.data(), ed.size(), &D.cw_ed, s));
+    chk(upload(ds, qd.data(), qd.size(), &D.cw_qd, s));
+    chk(upload(ds, dft.data(), dft.size(), &D.cw_dft, s));
+    chk(upload(ds, d->psr_pos, (size_t)3 * n, &D.cw_pos, s));
+  }
   if (!rc) rc = end_call(ds, s);
   if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = PTAFS_E_HIP;
   if (rc) {
@@ -568,6 +656,20 @@ int ptafs_std_precompute(const ptafs_std_desc *desc, int32_t pulsar, double *s0,
   scal[0] = g.c;
   scal[1] = g.cst;
   scal[2] = g.rank;
+  return PTAFS_OK;
+}
+
+int ptafs_std_precompute_cw(const ptafs_std_desc *desc, int32_t pulsar, double *sd, double *ed,
+                            double *qd) {
+  ps::StdDev B;
+  int64_t ntoa = 0;
+  PS_RC(plan(desc, B, ntoa));
+  if (!B.has_cw || pulsar < 0 || pulsar >= B.n_psr || !sd || !ed || !qd) return PTAFS_E_ARG;
+  PsrGram g;
+  gram_pulsar(desc, B, pulsar, g);
+  std::memcpy(sd, g.sd.data(), g.sd.size() * sizeof(double));
+  std::memcpy(ed, g.ed.data(), g.ed.size() * sizeof(double));
+  std::memcpy(qd, g.qd.data(), g.qd.size() * sizeof(double));
   return PTAFS_OK;
 }
 
@@ -610,9 +712,11 @@ int ptafs_std_profile_stages(ptafs_std *ds, int32_t n_chains, const double *x, c
       (void)hipEventRecord(ev[i + 1], s);
     };
     (void)hipEventRecord(ev[0], s);
-    step(0, psk::launch_std_fwd(S, x, s));
+    const hipError_t e0 = psk::launch_std_cw_fwd(S, x, s);
+    step(0, e0 != hipSuccess ? e0 : psk::launch_std_fwd(S, x, s));
     step(1, psk::launch_std_prior(S, x, s));
-    step(2, psk::launch_std_bwd(S, x, grad, s));
+    const hipError_t e2 = psk::launch_std_bwd(S, x, grad, s);
+    step(2, e2 != hipSuccess ? e2 : psk::launch_std_cw_bwd(S, x, s));
     step(3, psk::launch_std_finalize(S, x, logp, grad, status, s));
     if (hipEventSynchronize(ev[kStages]) != hipSuccess) err = PTAFS_E_HIP;
     for (int i = 0; i < kStages && !err; ++i) {
@@ -637,6 +741,7 @@ int ptafs_std_coefficients(ptafs_std *ds, int32_t n_chains, const double *x, con
   PS_RC(begin_call(ds, s));
   PS_RC(ensure_ws(ds, n_chains, s));
   const ps::StdDev S = make_dev(ds, n_chains, beta);
+  PS_TRY(psk::launch_std_cw_fwd(S, x, s));
   PS_TRY(psk::launch_std_fwd(S, x, s));
   PS_TRY(hipMemcpy2DAsync(a, (size_t)S.P * sizeof(double), S.avec, (size_t)S.pp * sizeof(double),
                           (size_t)S.P * sizeof(double), (size_t)n_chains * S.n_psr, hipMemcpyDeviceToDevice, s));

@@ -46,13 +46,26 @@ def general_tm(ds):
     return np.stack([np.ones_like(t), t, t * t, np.sin(yr), np.cos(yr), 2.0 * t], axis=1)
 
 
-def make(seed, counts, nf, free=False, tm=False, span=9.0):
+# a CW well inside its box: it does not coalesce within twice a 16-yr span
+THETA_CW = np.array([0.3, 1.0, 8.7, -8.2, 0.5, 0.6, 0.9, -14.0])
+
+
+def make(seed, counts, nf, free=False, tm=False, span=9.0, cw=None):
+    """cw: None, or (K_D, T_D / T) of a deterministic CW in its own basis."""
     ds = synth.make_array(seed, len(counts), list(counts), span * synth.YEAR_S,
                           backends_per_psr=[1 + i % 3 for i in range(len(counts))],
-                          nu_range=(0.4e9, 2.0e9), nf_rn=nf[0], nf_gw=nf[1], nf_dm=nf[2])
+                          nu_range=(0.4e9, 2.0e9), nf_rn=nf[0], nf_gw=nf[1], nf_dm=nf[2],
+                          has_cw=cw is not None)
+    if cw is not None:
+        ds["cw_nf"] = int(cw[0])
+        ds["cw_tspan"] = float(cw[1]) * ds["tspan"]
     if free:
         ds["spectrum"] = "free"
-        ds["prior_lo"], ds["prior_hi"] = free_box(ds)
+        lo, hi = free_box(ds)
+        if cw is not None:
+            lo = np.concatenate([lo, ds["prior_lo"][-8:]])
+            hi = np.concatenate([hi, ds["prior_hi"][-8:]])
+        ds["prior_lo"], ds["prior_hi"] = lo, hi
     if tm:
         ds["tm"] = general_tm(ds)
     return ds
@@ -61,10 +74,14 @@ def make(seed, counts, nf, free=False, tm=False, span=9.0):
 def points(ds, prep, n, seed, jitter=0.3):
     rng = np.random.default_rng(seed)
     lay = prep.lay
+    cw = THETA_CW if lay.has_cw else None
     if prep.free:
         th = rng.uniform(-15.5, -12.5, (n, lay.n_theta))
+        if lay.has_cw:
+            th[:, lay.cw:] = np.clip(cw + rng.uniform(-jitter, jitter, (n, 8)),
+                                     ds["prior_lo"][lay.cw:], ds["prior_hi"][lay.cw:])
     else:
-        th0 = synth.injected_theta(ds, seed, rn=(-14.0, 3.5), dm=(-14.0, 3.5))
+        th0 = synth.injected_theta(ds, seed, rn=(-14.0, 3.5), dm=(-14.0, 3.5), cw=cw)
         th = np.clip(th0 + rng.uniform(-jitter, jitter, (n, th0.size)), ds["prior_lo"], ds["prior_hi"])
     return np.concatenate([th, rng.standard_normal((n, lay.d - lay.n_theta))], axis=1)
 
@@ -95,8 +112,10 @@ def check(prep, X, got, beta=None, ref=None, draws=1, strict=True):
     g_ref, g = ref["grad"][ok], gr[ok]
     betas = np.ones(X.shape[0]) if beta is None else np.broadcast_to(np.asarray(beta, np.float64), (X.shape[0],))
     Sc = np.zeros_like(g_ref)
-    if lay.n_theta:
-        Sc[:, :lay.n_theta] = 1e-2 * np.abs(g_ref[:, :lay.n_theta]).max(axis=1, keepdims=True)
+    blocks = [(0, lay.cw), (lay.cw, lay.cw + 8)] if lay.has_cw else [(0, lay.n_theta)]
+    for b0, b1 in blocks:
+        if b1 > b0:
+            Sc[:, b0:b1] = 1e-2 * np.abs(g_ref[:, b0:b1]).max(axis=1, keepdims=True)
     for i, c in enumerate(np.nonzero(ok)[0]):
         Sc[i, lay.z:] = std.z_scale(prep, X[c], float(betas[c])).reshape(-1)
     R = std.rounding_sensitivity(prep, X[ok], betas[ok], draws=draws)
@@ -210,6 +229,61 @@ def test_std_coefficients(api):
     for c in range(4):
         ref = std.coefficients(prep, X[c])
         np.testing.assert_allclose(a[c], ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+
+
+CW_CASES = {
+    # name: (counts, (nf_rn, nf_gw, nf_dm), free, tm, (K_D, T_D / T))
+    "cw_hd_dm": ([30, 45, 60], (5, 3, 4), False, False, (20, 2.0)),
+    "cw_general_tm": ([44, 38, 51], (4, 4, 2), False, True, (12, 2.0)),
+    "cw_kd60": ([40, 55], (4, 4, 2), False, False, (60, 2.0)),
+    "cw_kd64_short_span": ([35, 41, 29], (3, 3, 0), False, False, (64, 1.5)),
+    "cw_free_spectrum": ([35, 42, 48], (4, 3, 2), True, False, (16, 2.0)),
+    "cw_one_toa_pulsar": ([1, 60, 45], (3, 3, 2), False, False, (10, 2.0)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CW_CASES))
+def test_std_cw_parity(api, name):
+    """The deterministic CW in its own Fourier basis (Sec. IV.C): K_D up to
+    the largest 64 (129 samples), extended spans, free spectra, a design
+    matrix, a one-TOA pulsar."""
+    counts, nf, free, tm, cw = CW_CASES[name]
+    ds = make(81, counts, nf, free, tm, cw=cw)
+    prep = std.StdPrepared(ds)
+    X = points(ds, prep, 9, 15)
+    check(prep, X, run(api, ds, X))
+
+
+def test_std_cw_tempered_and_coefficients(api):
+    ds = make(82, [40, 55, 33], (5, 4, 3), cw=(24, 2.0))
+    prep = std.StdPrepared(ds)
+    X = points(ds, prep, 8, 16)
+    betas = np.array([0.3, 1.0, 0.5, 0.1, 1.0, 0.9, 0.02, 0.7])
+    check(prep, X, run(api, ds, X, beta=betas), beta=betas)
+    g = api.StdDataset(ds)
+    a = g.ptafs_std_coefficients(torch.tensor(X[:3], device="cuda")).cpu().numpy()
+    g.close()
+    for c in range(3):
+        ref = std.coefficients(prep, X[c])
+        np.testing.assert_allclose(a[c], ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+
+
+def test_std_cw_status(api):
+    """Status 3 when the CW coalesces before the last sample time of its
+    basis; box violations keep status 1 (precedence 1, 4 in, 3, 2, 4 out)."""
+    ds = make(83, [30, 41, 52], (4, 3, 2), cw=(16, 2.0))
+    lay = std.StdPrepared(ds).lay
+    ds["prior_hi"] = ds["prior_hi"].copy()
+    ds["prior_hi"][lay.cw + 2], ds["prior_hi"][lay.cw + 3] = 10.5, -7.0
+    prep = std.StdPrepared(ds)
+    X = points(ds, prep, 5, 17)
+    X[0, lay.cw + 2], X[0, lay.cw + 3] = 10.5, -7.0     # coalesces within T_D
+    X[1, lay.cw + 2], X[1, lay.cw + 3] = 10.5, -7.0
+    X[1, 1] = 99.0                                      # and outside the box
+    X[2, lay.cw + 2], X[2, lay.cw + 3] = 10.5, -7.0
+    X[2, lay.z + 4] = np.nan                            # and a non-finite input
+    ref = check(prep, X, run(api, ds, X))
+    assert list(ref["status"]) == [3, 1, 4, 0, 0]
 
 
 def test_std_hmc_matches_oracle(api):

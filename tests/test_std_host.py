@@ -60,3 +60,37 @@ def test_precompute_rejects_bad_descriptors(api):
     bad["nf_rn"] = bad["nf_gw"] = 0
     with pytest.raises(RuntimeError):
         api.ptafs_std_precompute(bad, 0)
+
+
+@pytest.mark.parametrize("case", ["default_tm", "general_tm"])
+def test_precompute_cw_matches_oracle(api, case):
+    """The products of the deterministic basis (Sec. IV.C): F~^T N~^-1 F_D,
+    F_D^T N~^-1 dt and F_D^T N~^-1 F_D on an extended span T_D = 2 T."""
+    ds = synth.make_array(6, 3, [30, 45, 60], 9 * synth.YEAR_S, backends_per_psr=[2, 3, 1],
+                          nu_range=(0.4e9, 2.0e9), nf_rn=5, nf_gw=3, nf_dm=4, has_cw=True)
+    ds["cw_nf"] = 20
+    ds["cw_tspan"] = 2.0 * ds["tspan"]
+    if case == "general_tm":
+        ds["tm"] = general_tm(ds)
+    prep = std.StdPrepared(ds)
+    off = ds["toa_offsets"]
+    for I in range(ds["n_psr"]):
+        sd, ed, qd = api.ptafs_std_precompute_cw(ds, I)
+        sl = slice(off[I], off[I + 1])
+        N = (ds["efac"][ds["backend"][sl]] * ds["sigma"][sl]) ** 2 + ds["equad"][ds["backend"][sl]] ** 2
+        w = max(1.0, float(np.max(ds["dm_scale"] / ds["nu"][sl] ** 2)))
+        gram = float(np.sum(1.0 / N)) * w
+        np.testing.assert_allclose(sd, prep.SD[I], rtol=1e-9, atol=1e-13 * gram)
+        np.testing.assert_allclose(qd, prep.QD[I], rtol=1e-9, atol=1e-13 * gram)
+        dscale = float(np.sum(np.abs(ds["dt"][sl]) / N))
+        np.testing.assert_allclose(ed, prep.eD[I], rtol=1e-8, atol=1e-13 * dscale)
+
+
+def test_precompute_cw_rejects_bad_descriptors(api):
+    ds = synth.make_array(5, 2, [10, 12], 9 * synth.YEAR_S, backends_per_psr=[1, 1],
+                          nf_rn=2, nf_gw=2, nf_dm=0, has_cw=True)
+    for key, val in (("cw_nf", 65), ("cw_nf", 0), ("cw_tspan", -1.0)):
+        bad = dict(ds)
+        bad[key] = val
+        with pytest.raises(RuntimeError):
+            api.ptafs_std_precompute_cw(bad, 0)
