@@ -171,9 +171,10 @@ def std_flops_fwd(P):
     return 2.0 * P ** 3 / 3.0 + 4.0 * P * P
 
 
-def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2):
+def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2, cw=False):
     """The paper's standardized form (CURN transform on the Gram form, timing
-    model marginalised) on the same 67-pulsar / 250k-TOA data set: HMC
+    model marginalised) on the same 67-pulsar / 250k-TOA data set, or (cw)
+    on the simulated CW array with the CW in its own Fourier basis: HMC
     trajectories replayed as one HIP graph, per-stage times and the roofline
     of its dominant kernel."""
     import numpy as np
@@ -181,12 +182,12 @@ def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2):
     import synth
     from paper_2607_06834_amd import api
 
-    ds = synth.cfg2()
+    ds = synth.cw_array() if cw else synth.cfg2()
     t0 = time.perf_counter()
     g = api.StdDataset(ds)
     t_create = time.perf_counter() - t0
     lay = g.layout
-    th = synth.injected_theta(ds, 203)
+    th = synth.injected_theta(ds, 203, cw=synth.CW_PAPER if cw else None)
     rng = np.random.default_rng(204)
     th = np.clip(th + rng.uniform(-0.2, 0.2, (n_chains, th.size)), ds["prior_lo"], ds["prior_hi"])
     X0 = np.concatenate([th, rng.standard_normal((n_chains, g.d - int(lay.n_theta)))], axis=1)
@@ -232,9 +233,15 @@ def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2):
     flops = std_flops_fwd(P) * n_chains * int(lay.n_psr)
     achieved = flops / (stages["transform"] * 1e-3) / 1e12
     g.close()
+    if cw:
+        wl = (f"{int(lay.n_psr)} psr x 180 TOA over 15 yr, RN 30 + HD common 14 (P = {P}), CW in its own "
+              f"basis of 60 frequencies on 2T, {n_chains} chains x leapfrog {n_leapfrog}; "
+              "step = one HIP-graph trajectory")
+    else:
+        wl = ("67 psr / 250000 TOA, RN 30 + DM 30 + HD common 14 (P = 120 coefficients per pulsar), "
+              f"{n_chains} chains x leapfrog {n_leapfrog}; step = one HIP-graph trajectory")
     return dict(
-        workload="67 psr / 250000 TOA, RN 30 + DM 30 + HD common 14 (P = 120 coefficients per pulsar), "
-                 f"{n_chains} chains x leapfrog {n_leapfrog}; step = one HIP-graph trajectory",
+        workload=wl,
         value=n_chains * n_leapfrog * steps / el, unit="grad evals/s", ms_per_step=el / steps * 1e3,
         eps=eps_used, accept_rate=acc_rate, valid_eval_fraction=valid, create_s=t_create,
         stages_ms={k: round(v, 5) for k, v in stages.items()},
@@ -364,8 +371,11 @@ def main():
             torch.cuda.synchronize()
             print(json.dumps({"std_profile_evals": args.profile_evals, "chains": args.chains}))
             return
-        print(json.dumps({"std_form": std_bench(n_chains=args.chains, n_leapfrog=args.leapfrog,
-                                                steps=args.steps, warmup=args.warmup)}))
+        out = {"std_form": std_bench(n_chains=args.chains, n_leapfrog=args.leapfrog,
+                                     steps=args.steps, warmup=args.warmup)}
+        out["std_form_cw"] = std_bench(n_chains=args.chains, n_leapfrog=args.leapfrog,
+                                       steps=args.steps, warmup=args.warmup, cw=True)
+        print(json.dumps(out))
         return
     ds = synth.cfg2()
     C, L = args.chains, args.leapfrog
@@ -444,10 +454,12 @@ def main():
     _log("stages and plain form done")
     cpu = None if args.no_cpu else cpu_baseline(ds, min_seconds=args.cpu_seconds)
     _log("cpu baseline done")
-    std_form = None
+    std_form = std_cw = None
     if not args.no_std:
         std_form = std_bench(n_chains=C, n_leapfrog=L, steps=args.steps, warmup=args.warmup)
         _log(f"standardized form: {std_form['value']:.0f} grad evals/s, stages {std_form['stages_ms']}")
+        std_cw = std_bench(n_chains=C, n_leapfrog=L, steps=args.steps, warmup=args.warmup, cw=True)
+        _log(f"standardized form with CW: {std_cw['value']:.0f} grad evals/s, stages {std_cw['stages_ms']}")
     cfg4 = None
     if not args.no_cfg4:
         cfg4 = cfg4_bench()
@@ -501,6 +513,7 @@ def main():
         "valid_eval_fraction": valid,
         "cpu_baseline": cpu,
         "std_form": std_form,
+        "std_form_cw": std_cw,
         "cfg4": cfg4,
         "serving": serving,
     }

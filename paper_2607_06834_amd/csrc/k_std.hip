@@ -856,105 +856,211 @@ __device__ inline pt::CwLane cw_lane(const double cst[pt::kCwRows]) {
   return L;
 }
 
-// The delay at the md sample times t_j = j T_D / md (one thread each), its
-// transform a_D (Eq. det_F_basis), then d_bar = d - S_D a_D (reversed order,
-// zero-padded, as k_std_fwd reads it) and
-// c_bar = c - 2 e_D^T a_D + a_D^T Q_D a_D.
-__global__ __launch_bounds__(256) void k_std_cw_fwd(StdDev S, const double *__restrict__ x) {
-  __shared__ double hs[ps::kMaxCwM], ad[ps::kMaxCw2], red[4];
+// The CW kernels take a pulsar and a block of kCwChains chains per workgroup,
+// so that every table entry (the transform, S_D, Q_D) is loaded once for the
+// block; thread t works on row t % 128 for the chains of half t / 128.
+constexpr int kCwChains = 16;
+
+// Constants of the block's chains for pulsar I (cst: kCwChains x kCwRows, LDS).
+__device__ inline void cw_block_constants(const StdDev &S, const double *x, int I, int c0, int nc,
+                                          double *cst) {
   const int tid = threadIdx.x;
+  if (tid < nc) pt::cw_constants(x + (size_t)(c0 + tid) * S.d + S.off_cw, S.cw_pos + 3 * I,
+                                 cst + tid * pt::kCwRows);
+}
+
+// Forward: the delay at the md sample times t_j = j T_D / md, its transform a_D
+// (Eq. det_F_basis), then d_bar = d - S_D a_D (reversed order, zero-padded, as
+// k_std_fwd reads it) and c_bar = c - 2 e_D^T a_D + a_D^T Q_D a_D.
+__global__ __launch_bounds__(256) void k_std_cw_fwd(StdDev S, const double *__restrict__ x) {
+  constexpr int H = kCwChains / 2;
+  __shared__ double cst[kCwChains * pt::kCwRows];
+  __shared__ double hs[kCwChains][ps::kMaxCwM];
+  __shared__ double ad[kCwChains][ps::kMaxCw2];
+  __shared__ double cpart[2][kCwChains][4];
+  const int tid = threadIdx.x;
+  const int nb = (S.n_chains + kCwChains - 1) / kCwChains;
   const int pi = xcd_index(blockIdx.x, gridDim.x);
-  const int I = pi / S.n_chains, c = pi - I * S.n_chains;
-  const double *xc = x + (size_t)c * S.d;
+  const int I = pi / nb, c0 = (pi - I * nb) * kCwChains;
+  const int nc = min(kCwChains, S.n_chains - c0);
   const int K2 = 2 * S.kd, M = S.md, P = S.P, pp = S.pp;
-  const size_t q = (size_t)c * S.n_psr + I;
-  if (tid < M) {
-    double cst[pt::kCwRows];
-    pt::cw_constants(xc + S.off_cw, S.cw_pos + 3 * I, cst);
-    hs[tid] = cw_lane(cst).delay((double)tid * S.td / M).h;
+  cw_block_constants(S, x, I, c0, nc, cst);
+  __syncthreads();
+  for (int e = tid; e < kCwChains * M; e += 256) {
+    const int ch = e / M, j = e - ch * M;
+    hs[ch][j] = ch < nc ? cw_lane(cst + ch * pt::kCwRows).delay((double)j * S.td / M).h : 0.0;
   }
   __syncthreads();
-  if (tid < K2) {
-    const double *f = S.cw_dft + (size_t)tid * M;
-    double s = 0.0;
-    for (int j = 0; j < M; ++j) s = fma(f[j], hs[j], s);
-    ad[tid] = s;
-    S.cw_ad[q * K2 + tid] = s;
-  }
-  __syncthreads();
-  for (int r = tid; r < pp; r += 256) {
-    double v = 0.0;
-    if (r < P) {
-      const double *sd = S.cw_sd + ((size_t)I * P + (P - 1 - r)) * K2;
-      double s = 0.0;
-      for (int k = 0; k < K2; ++k) s = fma(sd[k], ad[k], s);
-      v = S.dvec[(size_t)I * pp + r] - s;
+  const int row = tid & 127, h0 = (tid >> 7) * H;
+  // a_D
+  if (row < K2) {
+    double acc[H];
+#pragma unroll
+    for (int u = 0; u < H; ++u) acc[u] = 0.0;
+    const double *f = S.cw_dft + (size_t)row * M;
+    for (int j = 0; j < M; ++j) {
+      const double fv = f[j];
+#pragma unroll
+      for (int u = 0; u < H; ++u) acc[u] = fma(fv, hs[h0 + u][j], acc[u]);
     }
-    S.dbar[q * pp + r] = v;
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      ad[h0 + u][row] = acc[u];
+      if (h0 + u < nc) S.cw_ad[((size_t)(c0 + h0 + u) * S.n_psr + I) * K2 + row] = acc[u];
+    }
   }
-  double part = 0.0;
-  if (tid < K2) {
-    const double *qd = S.cw_qd + ((size_t)I * K2 + tid) * K2;
-    double s = 0.0;
-    for (int k = 0; k < K2; ++k) s = fma(qd[k], ad[k], s);
-    part = ad[tid] * (s - 2.0 * S.cw_ed[(size_t)I * K2 + tid]);
+  __syncthreads();
+  // d_bar, row = the reversed index r
+  if (row < pp) {
+    double acc[H];
+#pragma unroll
+    for (int u = 0; u < H; ++u) acc[u] = 0.0;
+    if (row < P) {
+      const double *sd = S.cw_sd + ((size_t)I * P + (P - 1 - row)) * K2;
+      for (int k = 0; k < K2; ++k) {
+        const double sv = sd[k];
+#pragma unroll
+        for (int u = 0; u < H; ++u) acc[u] = fma(sv, ad[h0 + u][k], acc[u]);
+      }
+    }
+    const double dv = row < P ? S.dvec[(size_t)I * pp + row] : 0.0;
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+      if (h0 + u < nc) S.dbar[((size_t)(c0 + h0 + u) * S.n_psr + I) * pp + row] = row < P ? dv - acc[u] : 0.0;
   }
-  part = block_sum(part, red);
-  if (tid == 0) S.cbar[q] = S.cconst[2 * I] + part;
+  // c_bar: a_D^T (Q_D a_D - 2 e_D) per chain, summed over the rows of each wave
+  {
+    double part[H];
+#pragma unroll
+    for (int u = 0; u < H; ++u) part[u] = 0.0;
+    if (row < K2) {
+      double acc[H];
+#pragma unroll
+      for (int u = 0; u < H; ++u) acc[u] = 0.0;
+      const double *qd = S.cw_qd + (size_t)I * K2 * K2 + row;   // Q_D is symmetric: column row
+      for (int k = 0; k < K2; ++k) {
+        const double qv = qd[(size_t)k * K2];
+#pragma unroll
+        for (int u = 0; u < H; ++u) acc[u] = fma(qv, ad[h0 + u][k], acc[u]);
+      }
+      const double ev = S.cw_ed[(size_t)I * K2 + row];
+#pragma unroll
+      for (int u = 0; u < H; ++u) part[u] = ad[h0 + u][row] * (acc[u] - 2.0 * ev);
+    }
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      double v = part[u];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+      if ((tid & 63) == 0) cpart[tid >> 7][h0 + u][(tid >> 6) & 1] = v;
+    }
+    __syncthreads();
+    if (tid < nc) {
+      const int hh = tid / H;
+      const double v = cpart[hh][tid][0] + cpart[hh][tid][1];
+      S.cbar[(size_t)(c0 + tid) * S.n_psr + I] = S.cconst[2 * I] + v;
+    }
+  }
 }
 
 // dlog p / d a_D = -S_D^T g + beta (e_D - Q_D a_D) with g = dlog p / d d_bar
 // (k_std_bwd), then g_h = (transform)^T dlog p / d a_D at the sample times and
 // the pulsar's part of dlog p / d theta_cw = sum_j g_h,j dh_j / d theta.
 __global__ __launch_bounds__(256) void k_std_cw_bwd(StdDev S, const double *__restrict__ x) {
-  __shared__ double gd[ps::kMaxTiles * 16], ad[ps::kMaxCw2], ga[ps::kMaxCw2], red[4][8];
+  constexpr int H = kCwChains / 2;
+  __shared__ double cst[kCwChains * pt::kCwRows];
+  __shared__ double gb[kCwChains][ps::kMaxCwM];   // dlog p / d d_bar, later g_h
+  __shared__ double ad[kCwChains][ps::kMaxCw2];
+  __shared__ double ga[kCwChains][ps::kMaxCw2];
   const int tid = threadIdx.x;
+  const int nb = (S.n_chains + kCwChains - 1) / kCwChains;
   const int pi = xcd_index(blockIdx.x, gridDim.x);
-  const int I = pi / S.n_chains, c = pi - I * S.n_chains;
-  const double *xc = x + (size_t)c * S.d;
+  const int I = pi / nb, c0 = (pi - I * nb) * kCwChains;
+  const int nc = min(kCwChains, S.n_chains - c0);
   const int K2 = 2 * S.kd, M = S.md, P = S.P;
-  const size_t q = (size_t)c * S.n_psr + I;
-  const double beta = S.beta ? S.beta[c] : 1.0;
-  for (int j = tid; j < P; j += 256) gd[j] = S.gdbar[q * P + j];
-  if (tid < K2) ad[tid] = S.cw_ad[q * K2 + tid];
-  __syncthreads();
-  if (tid < K2) {
-    const double *sd = S.cw_sd + (size_t)I * P * K2 + tid;
-    const double *qd = S.cw_qd + (size_t)I * K2 * K2 + tid;   // Q_D is symmetric: column tid
-    double s1 = 0.0, s2 = 0.0;
-    for (int j = 0; j < P; ++j) s1 = fma(sd[(size_t)j * K2], gd[j], s1);
-    for (int k = 0; k < K2; ++k) s2 = fma(qd[(size_t)k * K2], ad[k], s2);
-    ga[tid] = beta * (S.cw_ed[(size_t)I * K2 + tid] - s2) - s1;
+  cw_block_constants(S, x, I, c0, nc, cst);
+  for (int e = tid; e < kCwChains * P; e += 256) {
+    const int ch = e / P, j = e - ch * P;
+    gb[ch][j] = ch < nc ? S.gdbar[((size_t)(c0 + ch) * S.n_psr + I) * P + j] : 0.0;
+  }
+  for (int e = tid; e < kCwChains * K2; e += 256) {
+    const int ch = e / K2, k = e - ch * K2;
+    ad[ch][k] = ch < nc ? S.cw_ad[((size_t)(c0 + ch) * S.n_psr + I) * K2 + k] : 0.0;
   }
   __syncthreads();
-  double out[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (tid < M) {
-    double gh = 0.0;
-    for (int k = 0; k < K2; ++k) gh = fma(S.cw_dft[(size_t)k * M + tid], ga[k], gh);
-    double cst[pt::kCwRows];
-    pt::cw_constants(xc + S.off_cw, S.cw_pos + 3 * I, cst);
-    const pt::CwLane L = cw_lane(cst);
-    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    L.adjoint(L.delay((double)tid * S.td / M), gh, acc);
-    // the sky pair through the antenna derivatives, ln 10 for the log10 parameters
-    out[0] = -(cst[pt::kCwDfpC] * acc[0] + cst[pt::kCwDfxC] * acc[1]);
-    out[1] = -(cst[pt::kCwDfpP] * acc[0] + cst[pt::kCwDfxP] * acc[1]);
-    out[2] = ps::kLn10 * acc[2];
-    out[3] = ps::kLn10 * acc[3];
-    out[4] = acc[4];
-    out[5] = acc[5];
-    out[6] = acc[6];
-    out[7] = ps::kLn10 * acc[7];
-  }
+  const int row = tid & 127, h0 = (tid >> 7) * H;
+  if (row < K2) {
+    double s1[H], s2[H];
 #pragma unroll
-  for (int v = 0; v < 8; ++v) {
-    double t = out[v];
+    for (int u = 0; u < H; ++u) s1[u] = s2[u] = 0.0;
+    const double *sd = S.cw_sd + (size_t)I * P * K2 + row;
+    for (int j = 0; j < P; ++j) {
+      const double sv = sd[(size_t)j * K2];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-    if ((tid & 63) == 0) red[tid >> 6][v] = t;
+      for (int u = 0; u < H; ++u) s1[u] = fma(sv, gb[h0 + u][j], s1[u]);
+    }
+    const double *qd = S.cw_qd + (size_t)I * K2 * K2 + row;   // Q_D is symmetric: column row
+    for (int k = 0; k < K2; ++k) {
+      const double qv = qd[(size_t)k * K2];
+#pragma unroll
+      for (int u = 0; u < H; ++u) s2[u] = fma(qv, ad[h0 + u][k], s2[u]);
+    }
+    const double ev = S.cw_ed[(size_t)I * K2 + row];
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      const int ch = h0 + u;
+      const double beta = (ch < nc && S.beta) ? S.beta[c0 + ch] : 1.0;
+      ga[ch][row] = beta * (ev - s2[u]) - s1[u];
+    }
   }
   __syncthreads();
-  if (tid < 8) S.dcw[q * 8 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  // g_h at the sample times (up to 129 of them: rows 0..127, then 128)
+  for (int j = row; j < M; j += 128) {
+    double acc[H];
+#pragma unroll
+    for (int u = 0; u < H; ++u) acc[u] = 0.0;
+    for (int k = 0; k < K2; ++k) {
+      const double fv = S.cw_dft[(size_t)k * M + j];
+#pragma unroll
+      for (int u = 0; u < H; ++u) acc[u] = fma(fv, ga[h0 + u][k], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < H; ++u) gb[h0 + u][j] = acc[u];
+  }
+  __syncthreads();
+  // the waveform's derivative: chain tid / 16, samples tid % 16 + 16 i, then
+  // the 16 lanes of the chain summed in order
+  {
+    const int ch = tid >> 4, l16 = tid & 15;
+    double out[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ch < nc) {
+      const double *cc = cst + ch * pt::kCwRows;
+      const pt::CwLane L = cw_lane(cc);
+      double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int j = l16; j < M; j += 16) L.adjoint(L.delay((double)j * S.td / M), gb[ch][j], acc);
+      // the sky pair through the antenna derivatives, ln 10 for the log10 parameters
+      out[0] = -(cc[pt::kCwDfpC] * acc[0] + cc[pt::kCwDfxC] * acc[1]);
+      out[1] = -(cc[pt::kCwDfpP] * acc[0] + cc[pt::kCwDfxP] * acc[1]);
+      out[2] = ps::kLn10 * acc[2];
+      out[3] = ps::kLn10 * acc[3];
+      out[4] = acc[4];
+      out[5] = acc[5];
+      out[6] = acc[6];
+      out[7] = ps::kLn10 * acc[7];
+    }
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      double t = out[v];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+      out[v] = t;
+    }
+    if (ch < nc && l16 == 0) {
+      double *o = S.dcw + ((size_t)(c0 + ch) * S.n_psr + I) * 8;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) o[v] = out[v];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1157,14 +1263,14 @@ hipError_t init_attributes() {
   }
 
 hipError_t launch_std_cw_fwd(const StdDev &S, const double *x, hipStream_t s) {
-  const int grid = S.n_chains * S.n_psr;
+  const int grid = ((S.n_chains + kCwChains - 1) / kCwChains) * S.n_psr;
   if (grid == 0 || !S.has_cw) return hipSuccess;
   hipLaunchKernelGGL(k_std_cw_fwd, dim3(grid), dim3(256), 0, s, S, x);
   return hipGetLastError();
 }
 
 hipError_t launch_std_cw_bwd(const StdDev &S, const double *x, hipStream_t s) {
-  const int grid = S.n_chains * S.n_psr;
+  const int grid = ((S.n_chains + kCwChains - 1) / kCwChains) * S.n_psr;
   if (grid == 0 || !S.has_cw) return hipSuccess;
   hipLaunchKernelGGL(k_std_cw_bwd, dim3(grid), dim3(256), 0, s, S, x);
   return hipGetLastError();

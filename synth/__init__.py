@@ -264,6 +264,32 @@ def cfg2(seed=201, n_psr=67, total=250_000):
                       nu_range=(0.4e9, 2.0e9), nf_rn=30, nf_gw=14, nf_dm=30)
 
 
+def cw_array(seed=301, n_psr=100, n_toa=180):
+    """The simulated CW array of the paper's results section, stand-in: 100
+    pulsars uniform on the sky, ~monthly TOAs (180 over 15 yr), TOA
+    uncertainty 0.5 us, EFAC 1, negligible EQUAD, 30 intrinsic red-noise and
+    14 common (HD) frequencies, no DM, and a CW represented in its own basis
+    of 60 frequencies on twice the span.  The CW box is widened to hold the
+    paper's injected source (log10 Mc = 8.4, log10 f = -8.4)."""
+    ds = make_array(seed, n_psr, [n_toa] * n_psr, 15.0 * YEAR_S, backends_per_psr=[1] * n_psr,
+                    nf_rn=30, nf_gw=14, nf_dm=0, has_cw=True, efac=1.0, log10_equad=-12.0)
+    rng = np.random.default_rng(seed + 1)
+    ds["sigma"] = np.full(ds["t"].size, 0.5e-6)
+    ds["dt"] = 0.5e-6 * rng.standard_normal(ds["t"].size)
+    ds["cw_nf"] = 60
+    ds["cw_tspan"] = 2.0 * ds["tspan"]
+    lo, hi = ds["prior_lo"].copy(), ds["prior_hi"].copy()
+    c0 = lo.size - 8
+    lo[c0 + 2], hi[c0 + 2] = 7.0, 10.0
+    lo[c0 + 3], hi[c0 + 3] = -9.0, -7.5
+    ds["prior_lo"], ds["prior_hi"] = lo, hi
+    return ds
+
+
+# the paper's injected CW: cos(theta), phi, log10 Mc, log10 f, Phi0, cos(iota), psi, log10 h
+CW_PAPER = (np.sqrt(2.0) / 2.0, np.pi / 4.0, 8.4, -8.4, np.pi / 4.0, np.sqrt(2.0) / 2.0, np.pi / 3.0, -14.4)
+
+
 def serving_request(seed):
     """One independent data set of the request stream: 20-120 pulsars,
     200-8000 TOAs each (lognormal), 10-30 frequencies shared by intrinsic,

@@ -341,3 +341,19 @@ def test_std_full_size_sampled(api):
     idx = np.array([0, 21, 37, 63])
     assert np.all(got[2] == 0)
     check(prep, X[idx], tuple(v[idx] for v in got), draws=4, strict=False)
+
+
+def test_std_cw_full_size_sampled(api):
+    """The simulated CW array (100 pulsars x 180 TOA, RN 30 + HD common 14,
+    CW in 60 frequencies on twice the span) at the paper's injection, 64
+    chains; the oracle checks one chain of every 16."""
+    ds = synth.cw_array()
+    prep = std.StdPrepared(ds)
+    th = synth.injected_theta(ds, 203, cw=synth.CW_PAPER)
+    rng = np.random.default_rng(204)
+    th = np.clip(th + rng.uniform(-0.2, 0.2, (64, th.size)), ds["prior_lo"], ds["prior_hi"])
+    X = np.concatenate([th, rng.standard_normal((64, prep.lay.d - prep.lay.n_theta))], axis=1)
+    got = run(api, ds, X)
+    idx = np.array([0, 21, 37, 63])
+    assert np.all(got[2] == 0)
+    check(prep, X[idx], tuple(v[idx] for v in got), draws=2, strict=False)
