@@ -20,6 +20,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6      # MI355X dense FP64 (vector and matrix)
+VALU_PEAK_TFLOPS = 67.3      # FP64 vector FMA as measured by microbench/peaks on MI355X
 HBM_PEAK_GBS = 8000.0
 
 
@@ -441,16 +442,21 @@ def main():
     if not args.no_plain:
         # the plain form at its own best chunking (its launches are per pulsar)
         best = None
-        for tpc in (8, 16):
+        for tpc in (2, 4, 8, 16):
             g.ptafs_set_tuning(tpc, 1, 0)
             ps = g.ptafs_profile_stages(x, reps=2, plain=True, stream=stream)
             if best is None or sum(ps.values()) < sum(best[1].values()):
                 best = (tpc, ps)
         g.ptafs_set_tuning(*tuning)
         tpc, ps = best
+        # the same algorithmic flops as the batched pass, on the vector unit:
+        # against the measured FP64 vector-FMA peak (microbench/peaks)
+        plain_tf = flops / (ps["toa"] * 1e-3) / 1e12
         plain = dict(value=C / (sum(ps.values()) * 1e-3), unit="grad evals/s",
                      ms_per_eval=round(sum(ps.values()), 4),
-                     toa_ms=round(ps["toa"], 4), tiles_per_chunk=tpc)
+                     toa_ms=round(ps["toa"], 4), tiles_per_chunk=tpc,
+                     toa_tflops=plain_tf, valu_peak_tflops=VALU_PEAK_TFLOPS,
+                     valu_frac=plain_tf / VALU_PEAK_TFLOPS)
     _log("stages and plain form done")
     cpu = None if args.no_cpu else cpu_baseline(ds, min_seconds=args.cpu_seconds)
     _log("cpu baseline done")

@@ -369,99 +369,163 @@ void k_toa_mfma(Dev D, int xcd_map) {
 }
 
 // ---------------------------------------------------------------------------
-// Plain TOA pass: one launch per pulsar, lane = chain, vector ALU only.
-// grid = (chunks of pulsar p, ceil(c_pad / 64)), block = 64.
-// LDS: coef [rows][64] for both blocks, then the adjoint accumulators.
+// Plain TOA pass: one launch per pulsar, one 64-lane wave per (TOA chunk,
+// 16-chain block), lane = TOA, a loop over the block's chains, vector ALU only
+// (no matrix cores).
+// grid = (chunks of pulsar p, chain blocks), block = 64.  Per chain and 64-TOA group the lane
+// forms the residual of its TOA (the basis by angle addition), then its
+// contributions to the adjoint rows, 8 harmonics (16 rows of each block) at a
+// time; those are summed over the 64 TOAs through an LDS transpose (lane l then
+// holds row l / 2 of the group, half l % 2) and accumulated per lane over the
+// chunk's TOA groups.
+// LDS: the coefficient rows of the block's chains [rows_rn + rows_dm][16] and
+// the transpose buffer [64 lanes][32 rows], rows padded to 33 so that the
+// column reads of the sum fall on distinct banks.
 // ---------------------------------------------------------------------------
+constexpr int kPlainMaxGroups = 8;   // 16-row groups per block (rows <= 128)
+
 __global__ __launch_bounds__(64) void k_toa_plain(Dev D, int p) {
   extern __shared__ double lds[];
   const int lane = threadIdx.x;
   const int chunk = D.psr_chunk0[p] + blockIdx.x;
-  const int chain = blockIdx.y * 64 + lane;
-  const bool real = chain < D.c_pad;
   const int nr = D.rows_rn, nd = D.rows_dm;
-  double *cf = lds;                       // [nr][64]
-  double *cfd = cf + nr * 64;             // [nd][64]
-  double *ab = cfd + nd * 64;             // [nr][64]
-  double *abd = ab + nr * 64;             // [nd][64]
+  const int gr = nr / 16, gd = nd / 16;
+  double *cfb = lds;                // [nr + nd][16] coefficients of the block's chains
+  double *tb = cfb + (nr + nd) * 16;   // [64][33] transpose buffer
   const size_t cp = D.c_pad;
-  for (int r = 0; r < nr; ++r) {
-    cf[r * 64 + lane] = real ? D.coef_rn[((size_t)p * nr + r) * cp + chain] : 0.0;
-    ab[r * 64 + lane] = 0.0;
-  }
-  for (int r = 0; r < nd; ++r) {
-    cfd[r * 64 + lane] = real ? D.coef_dm[((size_t)p * nd + r) * cp + chain] : 0.0;
-    abd[r * 64 + lane] = 0.0;
-  }
-  const int tb = D.chunk_begin[chunk], te = D.chunk_end[chunk];
+  const int t_beg = D.chunk_begin[chunk], t_end = D.chunk_end[chunk];
   const double tc = D.tau_c[p], tsi = D.tau_sinv[p];
   const double wfac = pt::kTwoPi / D.tspan;
   const int kb = D.kb, kdm = D.nf_dm;
   const int t0 = pt::tm_row(0, kb), t1 = pt::tm_row(1, kb), t2 = pt::tm_row(2, kb);
-  double chi = 0.0;
-  const bool cwon = D.has_cw && real;
-  pt::CwLane cwl;
-  double cacc[8];
-  for (int j = 0; j < 8; ++j) cacc[j] = 0.0;
-  if (cwon) cwl.load(D.cwc, cp, p, chain);
-  for (int i = tb; i < te; ++i) {
-    const double t = D.t[i];
-    const int be = D.backend[i];
-    const double es = D.efac[be] * D.sigma[i], eq = D.equad[be];
-    const double N = es * es + eq * eq;
-    const double w = D.dm_scale / (D.nu[i] * D.nu[i]);
-    double s1, c1;
-    sincos(wfac * t, &s1, &c1);
-    const double tau = (t - tc) * tsi;
-    double R = cf[t0 * 64 + lane] + tau * cf[t1 * 64 + lane] + tau * tau * cf[t2 * 64 + lane];
-    double Rd = 0.0;
-    double sk = s1, ck = c1;
-    for (int k = 1; k <= kb; ++k) {
-      const int rs = pt::harm_row(k, 0), rc = pt::harm_row(k, 1);
-      R += sk * cf[rs * 64 + lane] + ck * cf[rc * 64 + lane];
-      if (k <= kdm) Rd += sk * cfd[rs * 64 + lane] + ck * cfd[rc * 64 + lane];
-      const double sn = sk * c1 + ck * s1;
-      ck = ck * c1 - sk * s1;
-      sk = sn;
-    }
-    double r = D.dt[i] - R - w * Rd;
-    pt::CwToa cs;
-    if (cwon) {
-      cs = cwl.delay(t);
-      r -= cs.h;
-    }
-    const double g = r / N;
-    const double wg = w * g;
-    chi += r * g;
-    if (cwon) cwl.adjoint(cs, g, cacc);
-    sk = s1;
-    ck = c1;
-    for (int k = 1; k <= kb; ++k) {
-      const int rs = pt::harm_row(k, 0), rc = pt::harm_row(k, 1);
-      ab[rs * 64 + lane] += sk * g;
-      ab[rc * 64 + lane] += ck * g;
-      if (k <= kdm) {
-        abd[rs * 64 + lane] += sk * wg;
-        abd[rc * 64 + lane] += ck * wg;
-      }
-      const double sn = sk * c1 + ck * s1;
-      ck = ck * c1 - sk * s1;
-      sk = sn;
-    }
-    ab[t0 * 64 + lane] += g;
-    ab[t1 * 64 + lane] += tau * g;
-    ab[t2 * 64 + lane] += tau * tau * g;
+  const int cb_row = lane >> 1, half = lane & 1;
+  // the coefficient rows of the block's 16 chains (16 consecutive words per row)
+  const int cb = blockIdx.y;
+  for (int e = lane; e < (nr + nd) * 16; e += 64) {
+    const int r = e >> 4, c16 = e & 15;
+    cfb[e] = r < nr ? D.coef_rn[((size_t)p * nr + r) * cp + cb * 16 + c16]
+                    : D.coef_dm[((size_t)p * nd + (r - nr)) * cp + cb * 16 + c16];
   }
-  if (!real) return;
-  const int cb = chain >> 4, col = chain & 15;
-  const size_t wg = (size_t)chunk * D.n_cb + cb;
-  for (int r = 0; r < nr; ++r) D.part_rn[(wg * nr + r) * 16 + col] = ab[r * 64 + lane];
-  for (int r = 0; r < nd; ++r) D.part_dm[(wg * nd + r) * 16 + col] = abd[r * 64 + lane];
-  D.part_chi[wg * 16 + col] = chi;
-  if (cwon) {
-    double o[8];
-    pt::cw_finish(D.cwc, cp, p, chain, cacc, o);
-    for (int j = 0; j < 8; ++j) D.part_cw[(wg * 8 + j) * 16 + col] = o[j];
+  wave_sync();
+  for (int col = 0; col < 16; ++col) {
+    const int chain = cb * 16 + col;
+    // row r of the chain at cfb[16 r + col]
+    const double *cf = cfb + col;
+    const bool cwon = D.has_cw;
+    pt::CwLane cwl;
+    if (cwon) cwl.load(D.cwc, cp, p, chain);
+    double acc[2 * kPlainMaxGroups], chi = 0.0, cacc[8];
+#pragma unroll
+    for (int g = 0; g < 2 * kPlainMaxGroups; ++g) acc[g] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) cacc[j] = 0.0;
+    for (int i0 = t_beg; i0 < t_end; i0 += 64) {
+      const int i = i0 + lane;
+      const bool on = i < t_end;
+      const int ii = on ? i : t_beg;
+      const double t = D.t[ii];
+      const int be = D.backend[ii];
+      const double es = D.efac[be] * D.sigma[ii], eq = D.equad[be];
+      const double N = es * es + eq * eq;
+      const double w = D.dm_scale / (D.nu[ii] * D.nu[ii]);
+      double s1, c1;
+      sincos(wfac * t, &s1, &c1);
+      const double tau = (t - tc) * tsi;
+      // forward
+      double R = cf[16 * t0] + tau * cf[16 * t1] + tau * tau * cf[16 * t2];
+      double Rd = 0.0;
+      double sk = s1, ck = c1;
+      for (int k = 1; k <= kb; ++k) {
+        const int rs = pt::harm_row(k, 0), rc = pt::harm_row(k, 1);
+        R = fma(sk, cf[16 * rs], fma(ck, cf[16 * rc], R));
+        if (k <= kdm) Rd = fma(sk, cf[16 * (nr + rs)], fma(ck, cf[16 * (nr + rc)], Rd));
+        const double sn = sk * c1 + ck * s1;
+        ck = ck * c1 - sk * s1;
+        sk = sn;
+      }
+      double r = D.dt[ii] - R - w * Rd;
+      pt::CwToa cs;
+      if (cwon) {
+        cs = cwl.delay(t);
+        r -= cs.h;
+      }
+      const double g = on ? r / N : 0.0;
+      chi = fma(r, g, chi);
+      if (cwon && on) cwl.adjoint(cs, g, cacc);
+      const double wg = w * g;
+      // adjoint rows, 8 harmonics (16 rows per block) per group
+      sk = s1;
+      ck = c1;
+      const int ng = gr > gd ? gr : gd;
+#pragma unroll
+      for (int grp = 0; grp < kPlainMaxGroups; ++grp) {
+        if (grp >= ng) break;
+        double hs[8], hc[8];
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+          hs[h] = sk;
+          hc[h] = ck;
+          const double sn = sk * c1 + ck * s1;
+          ck = ck * c1 - sk * s1;
+          sk = sn;
+        }
+        // the lane's 16 red-noise and 16 DM contributions of this group
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int row = 16 * grp + j;
+          const int q = j & 3, sc = (j >> 2) & 1, mloc = j >> 3, hl = 4 * mloc + q;
+          double vr = 0.0, vd = 0.0;
+          if (grp < gr) {
+            const pt::Slot sl = pt::rn_slot(row, kb);
+            if (sl.kind == 0) vr = (sc ? hc[hl] : hs[hl]) * g;
+            else if (sl.kind == 1) vr = (sl.tm == 0 ? 1.0 : (sl.tm == 1 ? tau : tau * tau)) * g;
+          }
+          if (grp < gd) {
+            const pt::Slot sl = pt::dm_slot(row, kdm);
+            if (sl.kind == 0) vd = (sc ? hc[hl] : hs[hl]) * wg;
+          }
+          tb[lane * 33 + j] = vr;
+          tb[lane * 33 + 16 + j] = vd;
+        }
+        wave_sync();
+        double sum = 0.0;
+        const double *src = tb + 32 * half * 33 + cb_row;
+#pragma unroll
+        for (int l = 0; l < 32; ++l) sum += src[33 * l];
+        sum += __shfl_xor(sum, 1, 64);
+        wave_sync();
+        if (cb_row < 16) {
+          if (grp < gr) acc[grp] += sum;
+        } else if (grp < gd) {
+          acc[kPlainMaxGroups + grp] += sum;
+        }
+      }
+    }
+    // chi^2 and the CW sums over the chunk's TOAs
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) chi += __shfl_xor(chi, o, 64);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) cacc[j] += __shfl_xor(cacc[j], o, 64);
+    }
+    const size_t wg = (size_t)chunk * D.n_cb + cb;
+    if (half == 0) {
+      const int j = cb_row & 15;
+#pragma unroll
+      for (int grp = 0; grp < kPlainMaxGroups; ++grp) {
+        if (cb_row < 16 && grp < gr) D.part_rn[(wg * nr + 16 * grp + j) * 16 + col] = acc[grp];
+        if (cb_row >= 16 && grp < gd) D.part_dm[(wg * nd + 16 * grp + j) * 16 + col] = acc[kPlainMaxGroups + grp];
+      }
+    }
+    if (lane == 0) {
+      D.part_chi[wg * 16 + col] = chi;
+      if (cwon) {
+        double o[8];
+        pt::cw_finish(D.cwc, cp, p, chain, cacc, o);
+        for (int j = 0; j < 8; ++j) D.part_cw[(wg * 8 + j) * 16 + col] = o[j];
+      }
+    }
   }
 }
 
@@ -559,9 +623,11 @@ hipError_t launch_toa_mfma(const pt::Dev &D, int wpb, int xcd, hipStream_t s) {
 }
 
 hipError_t launch_toa_plain_psr(const pt::Dev &D, int p, int n_chunks_p, hipStream_t s) {
-  const size_t lds = (size_t)2 * (D.rows_rn + D.rows_dm) * 64 * sizeof(double);
-  const int cg = (D.c_pad + 63) / 64;
-  hipLaunchKernelGGL(k_toa_plain, dim3(n_chunks_p, cg), dim3(64), lds, s, D, p);
+  if (D.rows_rn > 16 * kPlainMaxGroups || D.rows_dm > 16 * kPlainMaxGroups || D.rows_rn % 16 ||
+      D.rows_dm % 16)
+    return hipErrorInvalidValue;
+  const size_t lds = (size_t)((D.rows_rn + D.rows_dm) * 16 + 64 * 33) * sizeof(double);
+  hipLaunchKernelGGL(k_toa_plain, dim3(n_chunks_p, D.n_cb), dim3(64), lds, s, D, p);
   return hipGetLastError();
 }
 
