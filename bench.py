@@ -61,8 +61,10 @@ def measured_traffic(tuning):
     return float(fields[key])
 
 
-def cpu_baseline(ds, n_chains_sample=8, min_seconds=10.0, seed=204):
-    """The oracle timed on the host cores on a bounded sample of the workload."""
+def cpu_baseline(ds, n_chains_sample=8, min_seconds=10.0, seed=204, repeats=3, label="67 psr / 250k TOA"):
+    """The oracle timed on the host cores on a bounded sample of the workload:
+    ``repeats`` timed samples of at least min_seconds / repeats each, the
+    median reported (the spread beside it)."""
     import numpy as np
     import synth
     from oracle import model
@@ -75,17 +77,23 @@ def cpu_baseline(ds, n_chains_sample=8, min_seconds=10.0, seed=204):
     X = synth.random_points(ds, n_chains_sample, seed, theta=th, theta_jitter=0.2)
     prep = model.Prepared(ds)
     model.logp_grad(prep, X[:1], with_scale=False)
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        model.logp_grad(prep, X, with_scale=False)
-        n += X.shape[0]
-        el = time.perf_counter() - t0
-        if el >= min_seconds:
-            break
-    return dict(value=n / el, unit="grad evals/s", cores=int(threads), kind="oracle",
-                sample=f"{n} chain-evaluations ({n_chains_sample} chains per call) of the "
-                       f"67 psr / 250k TOA workload, {el:.1f} s")
+    rates, total_n, total_s = [], 0, 0.0
+    for _ in range(repeats):
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            model.logp_grad(prep, X, with_scale=False)
+            n += X.shape[0]
+            el = time.perf_counter() - t0
+            if el >= min_seconds / repeats:
+                break
+        rates.append(n / el)
+        total_n += n
+        total_s += el
+    return dict(value=float(np.median(rates)), unit="grad evals/s", cores=int(threads), kind="oracle",
+                samples=[round(r, 3) for r in rates],
+                sample=f"median of {repeats} samples, {total_n} chain-evaluations in all ({n_chains_sample} "
+                       f"chains per call) of the {label} workload, {total_s:.1f} s")
 
 
 def serving_bench(n_traj, rates, n_req, n_chains=16, n_leapfrog=20, quantum=10, max_slots=8,
@@ -459,6 +467,9 @@ def main():
                      valu_frac=plain_tf / VALU_PEAK_TFLOPS)
     _log("stages and plain form done")
     cpu = None if args.no_cpu else cpu_baseline(ds, min_seconds=args.cpu_seconds)
+    if cpu is not None:
+        # config 1 beside it (3 psr x 500 TOA): a second point of the oracle's rate
+        cpu["config1"] = cpu_baseline(synth.cfg1(), min_seconds=3.0, label="3 psr / 1500 TOA (config 1)")
     _log("cpu baseline done")
     std_form = std_cw = None
     if not args.no_std:
