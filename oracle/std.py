@@ -47,6 +47,22 @@ so the transform centres on a_bar = beta Sigma d_bar (the shifted MAP of
 Eq. det_mean) and the likelihood is the one of dt - h.  Status 3 when the CW
 coalesces within [0, T_D) (evolution variable y >= 1 at a sample time).
 
+Split coefficients (App. C, Eqs. separated_post, split_map_a,
+split_standardizing_transform), when the data set asks for them: the common
+process and the pulsar's own noise get separate coefficient sets on the same
+basis, a_G (k = 1..K_gw) and a_R (k = 1..K_rn, then the DM block), with
+a = E_G a_G + E_R a_R in the likelihood, priors a_G,k ~ N(0, rho_k Gamma) per
+frequency and a_R ~ N(0, diag kappa), and
+  Sigma_G = (beta S0_GG + diag rho^-1)^-1 = L_G L_G^T   (CURN: Gamma = I)
+  Sigma_R = (beta S0_RR + diag phi_R^-1)^-1 = L_R L_R^T
+  a_G = a_hat_G + L_G z_G,  a_R = a_hat_R + L_R z_R,
+with (a_hat_G, a_hat_R) the MAP of the joint system of Eq. split_map_a under
+the CURN prior.  Both sets share the basis, so that system is solved by the
+CURN MAP of the combined coefficients a_hat = (beta S0 + D^-1)^-1 beta d,
+D = rho + kappa, split in proportion to the prior variances:
+a_hat_G = rho / D a_hat, a_hat_R = phi_R / D a_hat (the pins check this
+against a direct solve of the joint system).  z per pulsar is [z_G | z_R].
+
 Spectra are the power law of Eq. power_law (theta = log10 A, gamma per
 process) or the free spectrum of Sec. IV.A (theta = log10 rho_k per
 frequency, rho_k = 10^theta_k in s^2).  Uniform hyper-priors.
@@ -83,12 +99,19 @@ class StdLayout:
     z per pulsar: 2 Ka entries (k = 1 sin, k = 1 cos, ...) for the
     red/common block, then 2 Kdm for DM."""
 
-    def __init__(self, n_psr, nf_rn, nf_gw, nf_dm, free, has_cw=False):
+    def __init__(self, n_psr, nf_rn, nf_gw, nf_dm, free, has_cw=False, split=False):
         self.n_psr, self.nf_rn, self.nf_gw, self.nf_dm, self.free = n_psr, nf_rn, nf_gw, nf_dm, free
         self.has_cw = bool(has_cw)
+        self.split = bool(split)
+        if self.split and (nf_gw < 1 or nf_rn < 1):
+            raise ValueError("split coefficients need a common process and pulsar red noise")
         self.Ka = max(nf_rn, nf_gw)
         self.Kdm = nf_dm
-        self.P = 2 * self.Ka + 2 * self.Kdm
+        self.P = 2 * self.Ka + 2 * self.Kdm     # combined coefficients (the likelihood's)
+        # z per pulsar: the combined set, or [z_G (2 K_gw) | z_R (2 K_rn + 2 K_dm)]
+        self.PG = 2 * nf_gw if self.split else 0
+        self.PR = 2 * nf_rn + 2 * nf_dm if self.split else 0
+        self.Pz = self.PG + self.PR if self.split else self.P
         w = (lambda k: k) if free else (lambda k: 2)
         o = 0
         self.gw = o; o += w(nf_gw) if nf_gw > 0 else 0
@@ -96,7 +119,7 @@ class StdLayout:
         self.dm = o; o += n_psr * w(nf_dm) if nf_dm > 0 else 0
         self.cw = o; o += 8 if has_cw else 0
         self.n_theta = o
-        self.z = o; o += n_psr * self.P
+        self.z = o; o += n_psr * self.Pz
         self.d = o
         self.w_gw = w(nf_gw) if nf_gw > 0 else 0
         self.w_rn = w(nf_rn) if nf_rn > 0 else 0
@@ -171,7 +194,9 @@ class StdPrepared:
         n = self.n_psr = int(ds["n_psr"])
         self.free = ds.get("spectrum", "powerlaw") == "free"
         self.has_cw = bool(ds.get("has_cw", 0))
-        self.lay = StdLayout(n, int(ds["nf_rn"]), int(ds["nf_gw"]), int(ds["nf_dm"]), self.free, self.has_cw)
+        self.split = bool(ds.get("split", 0))
+        self.lay = StdLayout(n, int(ds["nf_rn"]), int(ds["nf_gw"]), int(ds["nf_dm"]), self.free, self.has_cw,
+                             self.split)
         lay = self.lay
         self.T = float(ds["tspan"])
         self.pos = np.asarray(ds["psr_pos"], np.float64).reshape(n, 3)
@@ -314,6 +339,85 @@ class StdPrepared:
             lik = lik + beta * (-0.5 * cbar[I] + a @ d - 0.5 * a @ (S0 @ a) + self.const[I])
         return torch.stack(a_all), jac, lik, (rho, kap, kdm)
 
+    def split_rows(self):
+        """Combined-row indices of the G set (k <= K_gw, sin/cos) and of the R
+        set (k <= K_rn, then the DM block)."""
+        lay = self.lay
+        g = np.arange(2 * lay.nf_gw)
+        r = np.concatenate([np.arange(2 * lay.nf_rn), 2 * lay.Ka + np.arange(2 * lay.Kdm)])
+        return g, r
+
+    def split_variances(self, I, spec):
+        """D (combined rows), rho on the G rows, phi_R on the R rows of pulsar I."""
+        lay = self.lay
+        rho, kap, kdm = spec
+        D = torch.cat([(rho + kap[I]).repeat_interleave(2), kdm[I].repeat_interleave(2)])
+        g, r = self.split_rows()
+        vg = rho[: lay.nf_gw].repeat_interleave(2)
+        vr = torch.cat([kap[I, : lay.nf_rn].repeat_interleave(2), kdm[I].repeat_interleave(2)])
+        for v in (D, vg, vr):
+            if not bool(torch.all(torch.isfinite(v) & (v > 0))):
+                raise NotPositiveDefinite("prior variance not positive and finite")
+        return D, vg, vr
+
+    def split_map(self, th, beta):
+        """(a_hat_G, a_hat_R) per pulsar: the CURN MAP of the combined
+        coefficients split in proportion to the prior variances."""
+        spec = self.spectra(th)
+        dbar, _ = self.data_terms(th)
+        g, r = self.split_rows()
+        out = []
+        for I in range(self.n_psr):
+            D, vg, vr = self.split_variances(I, spec)
+            A = beta * torch.tensor(self.S0[I]) + torch.diag(1.0 / D)
+            ah = torch.linalg.solve(A, beta * dbar[I])
+            out.append((vg / D[g] * ah[g], vr / D[r] * ah[r]))
+        return out
+
+    def transform_split(self, th, z, beta):
+        """Split sets: a (Np, P) combined, a_G (Np, PG), a_R (Np, PR), sum of
+        ln det L_G + ln det L_R, beta sum_I log L(a_I)."""
+        lay, n = self.lay, self.n_psr
+        spec = self.spectra(th)
+        dbar, cbar = self.data_terms(th)
+        g, r = self.split_rows()
+        gt, rt = torch.tensor(g), torch.tensor(r)
+        a_all, ag_all, ar_all, jac, lik = [], [], [], 0.0, 0.0
+        for I in range(n):
+            D, vg, vr = self.split_variances(I, spec)
+            S0 = torch.tensor(self.S0[I])
+            d = dbar[I]
+            ah = torch.linalg.solve(beta * S0 + torch.diag(1.0 / D), beta * d)
+            SG = torch.linalg.inv(beta * S0[gt][:, gt] + torch.diag(1.0 / vg))
+            SR = torch.linalg.inv(beta * S0[rt][:, rt] + torch.diag(1.0 / vr))
+            LG = torch.linalg.cholesky(0.5 * (SG + SG.T))
+            LR = torch.linalg.cholesky(0.5 * (SR + SR.T))
+            ag = vg / D[gt] * ah[gt] + LG @ z[I, : lay.PG]
+            ar = vr / D[rt] * ah[rt] + LR @ z[I, lay.PG:]
+            a = torch.zeros(lay.P, dtype=torch.float64)
+            a = a.index_add(0, gt, ag).index_add(0, rt, ar)
+            a_all.append(a)
+            ag_all.append(ag)
+            ar_all.append(ar)
+            jac = jac + torch.sum(torch.log(torch.diagonal(LG))) + torch.sum(torch.log(torch.diagonal(LR)))
+            lik = lik + beta * (-0.5 * cbar[I] + a @ d - 0.5 * a @ (S0 @ a) + self.const[I])
+        return torch.stack(a_all), torch.stack(ag_all), torch.stack(ar_all), jac, lik, spec
+
+    def log_prior_split(self, ag, ar, spec):
+        """log N(a_G; 0, rho_k Gamma per frequency) + log N(a_R; 0, diag kappa)."""
+        lay, n = self.lay, self.n_psr
+        rho, kap, kdm = spec
+        Lg = torch.linalg.cholesky(torch.tensor(self.Gamma))
+        ldg = 2.0 * torch.sum(torch.log(torch.diagonal(Lg)))
+        out = 0.0
+        for k in range(lay.nf_gw):
+            for c in range(2):
+                y = torch.linalg.solve_triangular(Lg, ag[:, 2 * k + c].unsqueeze(1), upper=False)
+                out = out - 0.5 * torch.sum(y * y) / rho[k] - 0.5 * (n * LN2PI + n * torch.log(rho[k]) + ldg)
+        vr = torch.cat([kap[:, : lay.nf_rn].repeat_interleave(2, dim=1), kdm.repeat_interleave(2, dim=1)], dim=1)
+        out = out - 0.5 * torch.sum(ar * ar / vr) - 0.5 * torch.sum(torch.log(2 * np.pi * vr))
+        return out
+
     def log_prior_a(self, a, spec):
         """log N(a; 0, phi): per frequency rho_k Gamma + diag kappa_.k for the
         red/common block (sin and cos share it), diagonal for DM."""
@@ -337,9 +441,13 @@ class StdPrepared:
     def logp_one(self, x, beta):
         lay = self.lay
         th = x[: lay.n_theta]
-        z = x[lay.z:].reshape(self.n_psr, lay.P)
+        z = x[lay.z:].reshape(self.n_psr, lay.Pz)
+        box = float(np.sum(np.log(self.hi - self.lo)))
+        if self.split:
+            _, ag, ar, jac, lik, spec = self.transform_split(th, z, beta)
+            return lik + jac + self.log_prior_split(ag, ar, spec) - box
         a, jac, lik, spec = self.transform(th, z, beta)
-        return lik + jac + self.log_prior_a(a, spec) - float(np.sum(np.log(self.hi - self.lo)))
+        return lik + jac + self.log_prior_a(a, spec) - box
 
 
 class _CWSamples(torch.autograd.Function):
@@ -495,8 +603,13 @@ def _rounding_shift(prep: StdPrepared, X, beta=None, seed=0):
 
 
 def coefficients(prep: StdPrepared, x, beta=1.0):
-    """The Fourier coefficients a (Np, P) that a point maps to."""
+    """The Fourier coefficients a (Np, P) that a point maps to; with split
+    sets [a_G | a_R] (Np, PG + PR)."""
     lay = prep.lay
     xt = torch.tensor(np.asarray(x, np.float64))
-    a, _, _, _ = prep.transform(xt[: lay.n_theta], xt[lay.z:].reshape(prep.n_psr, lay.P), beta)
+    z = xt[lay.z:].reshape(prep.n_psr, lay.Pz)
+    if prep.split:
+        _, ag, ar, _, _, _ = prep.transform_split(xt[: lay.n_theta], z, beta)
+        return torch.cat([ag, ar], dim=1).detach().numpy()
+    a, _, _, _ = prep.transform(xt[: lay.n_theta], z, beta)
     return a.detach().numpy()
