@@ -270,12 +270,33 @@ int ptafs_profile_stages(ptafs_dataset *ds, int32_t n_chains, const double *x, d
  * transform centres on the shifted MAP a_bar_CURN (Eq. det_mean) and the
  * likelihood is that of dt - h.
  *
+ * Split coefficients (App. C, Eqs. separated_post, split_map_a,
+ * split_standardizing_transform), optional: the common process and the
+ * pulsar noise get coefficient sets of their own on the same basis, a_G over
+ * k = 1..nf_gw and a_R over k = 1..nf_rn then the DM block, with
+ * a = a_G + a_R in the likelihood (each on its rows), priors
+ * a_G,k ~ N(0, rho_k Gamma) per frequency (HD) and a_R ~ N(0, diag kappa), and
+ *   Sigma_G = (beta F~^T N~^-1 F~|_GG + diag rho^-1)^-1 = L_G L_G^T,
+ *   Sigma_R = (beta F~^T N~^-1 F~|_RR + diag phi_R^-1)^-1 = L_R L_R^T,
+ *   a_G = a_hat_G + L_G z_G,  a_R = a_hat_R + L_R z_R,
+ *   log p~ = beta log L(a) + log N(a_G; 0, phi_GWB) + log N(a_R; 0, phi_RN)
+ *            + sum_I (ln det L_G,I + ln det L_R,I) + log pi(theta).
+ * (a_hat_G, a_hat_R) is the MAP of the joint linear system (Eq. split_map_a)
+ * under the CURN prior (Gamma = I, as for the transform above).  Since both
+ * sets share the basis it equals the CURN MAP a_hat of the combined
+ * coefficients split in proportion to the prior variances:
+ * a_hat_G = rho / (rho + phi_R) a_hat, a_hat_R = phi_R / (rho + phi_R) a_hat.
+ * Per (pulsar, chain) this takes the combined factorisation and one of each
+ * set; Gamma^-1 is formed once per data set.  Needs nf_gw >= 1 and nf_rn >= 1.
+ *
  * Parameter vector: [theta | z], theta = [gw | rn per pulsar | dm per pulsar |
  * cw (8, with a CW)] with 2 entries per process for the power law (log10 A,
  * gamma) or one per frequency for the free spectrum (log10 rho_k,
  * rho_k = 10^theta in s^2, Sec. IV.A), the CW parameters in the order of the
  * per-TOA form; z per pulsar: P = 2 ka + 2 nf_dm entries (k = 1 sin, k = 1 cos,
- * ... of the red/common block, ka = max(nf_rn, nf_gw), then the DM block).
+ * ... of the red/common block, ka = max(nf_rn, nf_gw), then the DM block);
+ * with split coefficients pz = 2 nf_gw + 2 nf_rn + 2 nf_dm entries per pulsar,
+ * z_G (k = 1 sin, k = 1 cos, ... up to nf_gw) then z_R (up to nf_rn, then DM).
  * Per-chain statuses as above (1 box, 2 a factorisation fails, 3 the CW
  * coalesces at a sample time of [0, T_D), 4 non-finite).
  * ====================================================================== */
@@ -308,6 +329,7 @@ typedef struct {
   int32_t has_cw;                /* 1: a CW in the deterministic basis (8 more theta entries) */
   int32_t cw_nf;                 /* K_D, 1..PTAFS_MAX_CW_HARM (ignored without a CW) */
   double cw_tspan;               /* T_D > 0, s (ignored without a CW) */
+  int32_t split;                 /* 1: split common-process / pulsar-noise coefficients */
 } ptafs_std_desc;
 
 typedef struct {
@@ -315,6 +337,7 @@ typedef struct {
   int64_t n_psr, n_toa, k_coef, k_dm, p;   /* p = 2 k_coef + 2 k_dm coefficients per pulsar */
   size_t dataset_bytes, workspace_bytes, hmc_bytes;
   int64_t off_cw;                /* first CW entry of theta, -1 without a CW */
+  int64_t pz;                    /* z entries per pulsar: p, or 2 (nf_gw + nf_rn + nf_dm) when split */
 } ptafs_std_layout_info;
 
 /* Copy a data set, marginalise its timing model and store the per-pulsar Gram
@@ -350,7 +373,9 @@ int ptafs_std_logp_grad(ptafs_std *ds, int32_t n_chains, const double *x, const 
                         double *logp, double *grad, int32_t *status, void *stream);
 
 /* The Fourier coefficients a = a_hat + L z of each point (the map back from
- * z, Eq. PTA_standard_transform_curn): a device [n_chains][n_psr][p]. */
+ * z, Eq. PTA_standard_transform_curn): a device [n_chains][n_psr][p]; with
+ * split coefficients [a_G | a_R] (Eq. split_standardizing_transform),
+ * a device [n_chains][n_psr][pz]. */
 int ptafs_std_coefficients(ptafs_std *ds, int32_t n_chains, const double *x, const double *beta,
                            double *a, void *stream);
 

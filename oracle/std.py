@@ -514,6 +514,8 @@ def z_scale(prep: StdPrepared, x, beta=1.0):
     that d and S0 hold (the timing-model projection cancels against them),
     S_I = |L_I|^T [beta (sum_i |T_i| |dt_i| / N_i + (sum_i |T_i| |T_i|^T / N_i) |a_I|)
                    + (|phi^-1| |a|)_I]   (Np, P)."""
+    if prep.split:
+        return _z_scale_split(prep, x, beta)
     lay, n = prep.lay, prep.n_psr
     xt = torch.tensor(np.asarray(x, np.float64))
     th, z = xt[: lay.n_theta], xt[lay.z:].reshape(n, lay.P)
@@ -538,6 +540,38 @@ def z_scale(prep: StdPrepared, x, beta=1.0):
         dab = prep.dabs[I] if not prep.has_cw else prep.dabs[I] + prep.GabsD[I] @ np.abs(aD[I])
         V = beta * (dab + prep.Gabs[I] @ np.abs(a[I])) + pa[I]
         out[I] = np.abs(L).T @ V
+    return out
+
+
+def _z_scale_split(prep: StdPrepared, x, beta):
+    """z_scale with split sets: dz_b = L_b^T g_b, g_b the likelihood's
+    beta (d - S0 a) on the set's rows plus the set's prior term, bounded the
+    same way term by term (Np, PG + PR)."""
+    lay, n = prep.lay, prep.n_psr
+    xt = torch.tensor(np.asarray(x, np.float64))
+    th, z = xt[: lay.n_theta], xt[lay.z:].reshape(n, lay.Pz)
+    a, ag, ar, _, _, spec = prep.transform_split(th, z, beta)
+    a, ag, ar = a.detach().numpy(), ag.detach().numpy(), ar.detach().numpy()
+    aD = prep.cw_coefficients(th).detach().numpy() if prep.has_cw else None
+    rho = spec[0].detach().numpy()
+    g, r = prep.split_rows()
+    Ginv = np.abs(np.linalg.inv(prep.Gamma))
+    pg = np.zeros_like(ag)                     # |phi_GWB^-1| |a_G|
+    for k in range(lay.nf_gw):
+        for c in range(2):
+            pg[:, 2 * k + c] = Ginv @ np.abs(ag[:, 2 * k + c]) / rho[k]
+    out = np.zeros((n, lay.Pz))
+    for I in range(n):
+        _, vg, vr = (v.detach().numpy() for v in prep.split_variances(I, spec))
+        S0 = prep.S0[I]
+        SG = np.linalg.inv(beta * S0[np.ix_(g, g)] + np.diag(1.0 / vg))
+        SR = np.linalg.inv(beta * S0[np.ix_(r, r)] + np.diag(1.0 / vr))
+        LG = np.linalg.cholesky(0.5 * (SG + SG.T))
+        LR = np.linalg.cholesky(0.5 * (SR + SR.T))
+        dab = prep.dabs[I] if not prep.has_cw else prep.dabs[I] + prep.GabsD[I] @ np.abs(aD[I])
+        V = beta * (dab + prep.Gabs[I] @ np.abs(a[I]))
+        out[I, : lay.PG] = np.abs(LG).T @ (V[g] + pg[I])
+        out[I, lay.PG:] = np.abs(LR).T @ (V[r] + np.abs(ar[I]) / vr)
     return out
 
 

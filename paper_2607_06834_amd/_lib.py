@@ -74,6 +74,7 @@ class StdDesc(C.Structure):
         ("has_cw", C.c_int32),
         ("cw_nf", C.c_int32),
         ("cw_tspan", C.c_double),
+        ("split", C.c_int32),
     ]
 
 
@@ -81,7 +82,8 @@ class StdLayoutInfo(C.Structure):
     _fields_ = [(n, C.c_int64) for n in (
         "d", "n_theta", "off_gw", "off_rn", "off_dm", "off_z", "n_psr", "n_toa", "k_coef", "k_dm", "p")] + [
         ("dataset_bytes", C.c_size_t), ("workspace_bytes", C.c_size_t), ("hmc_bytes", C.c_size_t),
-        ("off_cw", C.c_int64)]
+        ("off_cw", C.c_int64),
+        ("pz", C.c_int64)]
 
 
 class LayoutInfo(C.Structure):

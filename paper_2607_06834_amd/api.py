@@ -230,7 +230,8 @@ def _make_std_desc(desc, keep):
     """ptafs_std_desc for a mapping: the fields of a data set plus optional
     ``tm`` (n_toa x n_tm design matrix), ``spectrum`` ("powerlaw" or "free")
     and, with ``has_cw``, ``cw_nf`` (K_D, default 60) and ``cw_tspan`` (T_D,
-    default twice ``tspan``) of the deterministic basis."""
+    default twice ``tspan``) of the deterministic basis; ``split`` (0 or 1)
+    for separate common-process and pulsar-noise coefficient sets."""
     def arr(a, dtype):
         a = np.ascontiguousarray(np.asarray(a), dtype=dtype)
         keep.append(a)
@@ -261,6 +262,7 @@ def _make_std_desc(desc, keep):
     d.has_cw = 1 if desc.get("has_cw", 0) else 0
     d.cw_nf = int(desc.get("cw_nf", 60)) if d.has_cw else 0
     d.cw_tspan = float(desc.get("cw_tspan", 2.0 * float(desc["tspan"]))) if d.has_cw else 0.0
+    d.split = 1 if desc.get("split", 0) else 0
     return d
 
 
@@ -374,11 +376,12 @@ class StdDataset:
         return dict(zip(self.STD_STAGES, list(ms)))
 
     def ptafs_std_coefficients(self, x, beta=None, stream=None):
-        """Fourier coefficients a = a_hat + L z, (C, n_psr, p)."""
+        """Fourier coefficients a = a_hat + L z, (C, n_psr, p); with split
+        coefficients [a_G | a_R], (C, n_psr, pz)."""
         x = self._x(x)
         n = x.shape[0]
         lay = self.layout
-        a = torch.empty((n, int(lay.n_psr), int(lay.p)), dtype=torch.float64, device=x.device)
+        a = torch.empty((n, int(lay.n_psr), int(lay.pz)), dtype=torch.float64, device=x.device)
         _lib.check(_lib.load().ptafs_std_coefficients(
             self._h, n, C.c_void_p(x.data_ptr()), self._beta(beta, n), C.c_void_p(a.data_ptr()),
             _stream_handle(stream)), "ptafs_std_coefficients")

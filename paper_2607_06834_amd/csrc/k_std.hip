@@ -484,7 +484,8 @@ __global__ __launch_bounds__(256, 2) void k_std_fwd(StdDev S, const double *__re
   for (int r = tid; r < pp; r += 256) {
     dr = (r < P) ? dsrc[r] : 0.0;
     vd[r] = beta * dr;
-    vz[r] = (r < P) ? xc[S.off_z + I * P + (P - 1 - r)] : 0.0;
+    // with split coefficients this is the combined MAP only (z = 0)
+    vz[r] = (r < P && !S.split) ? xc[S.off_z + I * P + (P - 1 - r)] : 0.0;
     lz[r] = 0.0;
     // a CURN variance that is not positive and finite leaves phi_CURN not
     // positive definite
@@ -695,10 +696,12 @@ __global__ __launch_bounds__(256, 2) void k_std_prior_dense(StdDev S, const doub
 // ---------------------------------------------------------------------------
 // Prior of the diagonal items: red-noise frequencies beyond the common process
 // (phi_k = diag kappa_.k) and DM (diag kappa_dm): one thread per (chain, pulsar,
-// item), items k in [nf_gw, ka) then the DM frequencies.
+// item), items k in [nf_gw, ka) then the DM frequencies.  With split
+// coefficients: the whole pulsar-noise set a_R, items k < nf_rn then DM.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_std_prior_diag(StdDev S, const double *__restrict__ x) {
-  const int nrn = S.ka - S.nf_gw, per = nrn + S.kdm;
+  const int k0 = S.split ? 0 : S.nf_gw;
+  const int nrn = S.split ? S.nf_rn : S.ka - S.nf_gw, per = nrn + S.kdm;
   const size_t total = (size_t)S.n_chains * S.n_psr * per;
   const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
@@ -709,19 +712,19 @@ __global__ __launch_bounds__(256) void k_std_prior_diag(StdDev S, const double *
   int k, col;
   double kap;
   if (it < nrn) {
-    k = S.nf_gw + it;
+    k = k0 + it;
     col = 2 * k;
     kap = ps::spec_value(S, xc, 1, I, k);
   } else {
     k = it - nrn;
-    col = 2 * S.ka + 2 * k;
+    col = (S.split ? 2 * S.nf_rn : 2 * S.ka) + 2 * k;   // row in a_R, or in a
     kap = ps::spec_value(S, xc, 2, I, k);
   }
-  const double *av = S.avec + ((size_t)c * S.n_psr + I) * S.pp;
+  const double *av = S.split ? S.ar + ci * S.ppr : S.avec + ci * S.pp;
   const double a0 = av[col], a1 = av[col + 1];
   const double ik = 1.0 / kap;
   const double u0 = a0 * ik, u1 = a1 * ik;
-  double *v2 = S.v2 + ((size_t)c * S.n_psr + I) * S.pp;
+  double *v2 = S.split ? S.v2r + ci * S.ppr : S.v2 + ci * S.pp;
   v2[col] = -u0;
   v2[col + 1] = -u1;
   const double dk = 0.5 * (u0 * u0 + u1 * u1) - ik;
@@ -1096,12 +1099,15 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
   // factorisation flags
   int fl = 0;
   for (int i = tid; i < n; i += 256) fl |= S.flag1[(size_t)c * n + i];
+  if (S.split)
+    for (int i = tid; i < 2 * n; i += 256) fl |= S.flag_s[(size_t)c * 2 * n + i];
   for (int k = tid; k < S.nf_gw; k += 256) fl |= S.flag2[(size_t)c * S.ka + k];
+  // diagonal prior items: red-only frequencies and DM, or with split
+  // coefficients the whole pulsar-noise set
   const int nd = n * (S.ka + S.kdm);
-  for (int i = tid; i < nd; i += 256) {
-    const int kk = i % (S.ka + S.kdm);
-    if (kk >= S.nf_gw) fl |= S.flag3[(size_t)c * nd + i];
-  }
+  auto diag_item = [&](int kk) { return S.split ? (kk < S.nf_rn || kk >= S.ka) : kk >= S.nf_gw; };
+  for (int i = tid; i < nd; i += 256)
+    if (diag_item(i % (S.ka + S.kdm))) fl |= S.flag3[(size_t)c * nd + i];
   // log p parts
   double lp = 0.0;
   for (int i = tid; i < n; i += 256) {
@@ -1113,20 +1119,21 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
     lp += -0.5 * o[0] - (n * ps::kLn2Pi + o[1]);
   }
   for (int i = tid; i < nd; i += 256) {
-    const int kk = i % (S.ka + S.kdm);
-    if (kk < S.nf_gw) continue;
+    if (!diag_item(i % (S.ka + S.kdm))) continue;
     const double *o = S.diag_q + ((size_t)c * nd + i) * 2;
     lp += -0.5 * o[0] - (ps::kLn2Pi + o[1]);
   }
   // d/drho_k in total: the explicit prior part plus the transform's part summed
-  // over the pulsars, 8 threads per frequency, partials combined in a fixed order
+  // over the pulsars, 8 threads per frequency, partials combined in a fixed
+  // order (with split coefficients the pulsars' rho parts are drho_p, and
+  // dD_rn holds their kappa parts only)
   __shared__ double drho_part[8][ps::kMaxRhoK];
   __shared__ double drho_tot[ps::kMaxRhoK];
   {
     const int k = tid >> 3, h = tid & 7;
     double sacc = 0.0;
     if (k < S.nf_gw)
-      for (int J = h; J < n; J += 8) sacc += S.dD_rn[((size_t)c * n + J) * S.ka + k];
+      for (int J = h; J < n; J += 8) sacc += (S.split ? S.drho_p : S.dD_rn)[((size_t)c * n + J) * S.ka + k];
     if (k < ps::kMaxRhoK) drho_part[h][k] = sacc;
     __syncthreads();
     if (tid < S.nf_gw) {
@@ -1221,12 +1228,393 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
   }
 }
 
+// ---------------------------------------------------------------------------
+// Split coefficients (App. C, Eqs. separated_post, split_map_a,
+// split_standardizing_transform).  The common process and the pulsar noise
+// get coefficient sets of their own on the same basis, a = E_G a_G + E_R a_R,
+//   a_G = a_hat_G + L_G z_G,  L_G L_G^T = (beta S0_GG + diag rho^-1)^-1,
+//   a_R = a_hat_R + L_R z_R,  L_R L_R^T = (beta S0_RR + diag phi_R^-1)^-1,
+// and the MAP pair of the joint system is the CURN MAP of the combined
+// coefficients split in proportion to the prior variances:
+// a_hat_G = rho / D a_hat, a_hat_R = phi_R / D a_hat, D = rho + phi_R (a
+// shared row's likelihood sees only the sum, and for a fixed sum the two
+// independent Gaussian priors are largest at that split).  k_std_fwd with
+// z = 0 gives a_hat; k_split_fac factorises each set; k_split_comb forms
+// a_G, a_R, a and the likelihood.  The prior keeps the HD correlations on
+// a_G (rho_k Gamma per frequency, Gamma^-1 once per data set) and is
+// diagonal on a_R.
+// ---------------------------------------------------------------------------
+
+// Set b of pulsar I, chain c: A~ = beta S0_b~ + diag(1 / v~) factorised and
+// inverted as the CURN precision is; L_b z_b = X^T z~ and ln det L_b.
+template <int T>
+__global__ __launch_bounds__(256, 2) void k_split_fac(StdDev S, const double *__restrict__ x, int b) {
+  extern __shared__ double lds[];
+  constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256, NT = ps::ntiles(T);
+  double *A = lds;
+  double *vz = A + NE, *va = vz + pp, *red = va + pp;
+  int *flag = reinterpret_cast<int *>(red + 8);
+  const int tid = threadIdx.x;
+  const int pi = xcd_index(blockIdx.x, gridDim.x);
+  const int I = pi / S.n_chains, c = pi - I * S.n_chains;
+  const double *xc = x + (size_t)c * S.d;
+  const double beta = S.beta ? S.beta[c] : 1.0;
+  const int PB = b ? S.PR : S.PG;
+  const double *s0 = (b ? S.s0r : S.s0g) + (size_t)I * pp * pp;
+  const int rr = tid >> 4, cc = tid & 15;
+  double sv[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    int TI = 0;
+    while (ps::tix(TI + 1, 0) <= tt) ++TI;
+    const int TJ = tt - ps::tix(TI, 0);
+    sv[tt] = s0[(size_t)(16 * TI + rr) * pp + 16 * TJ + cc];
+  }
+  int bad = 0;
+  for (int r = tid; r < pp; r += 256) {
+    vz[r] = (r < PB) ? xc[S.off_z + I * S.pz + (b ? S.PG : 0) + (PB - 1 - r)] : 0.0;
+    double di = 1.0;
+    if (r < PB) {
+      const double v = ps::split_var(S, xc, I, b, PB - 1 - r);
+      if (!(v > 0.0 && isfinite(v))) bad = 1;
+      di = 1.0 / v;
+    }
+    va[r] = di;
+  }
+  bad = __syncthreads_or(bad);
+  if (tid == 0) *flag = bad ? 0 : 1;
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    int TI = 0;
+    while (ps::tix(TI + 1, 0) <= tt) ++TI;
+    const int TJ = tt - ps::tix(TI, 0);
+    double v = beta * sv[tt];
+    if (TI == TJ && rr == cc) v += va[16 * TI + rr];
+    A[(tt << 8) + sw(rr, cc)] = v;
+  }
+  __syncthreads();
+  const bool ok = factor_invert<T, false>(A, tid, flag, red + 10, nullptr, nullptr);
+  // X^T z~ by columns (column r over tiles K >= r / 16), the tiles split by
+  // parity between threads r and r + 128
+  const int h = tid >> 7, r = tid & 127, R = r >> 4, r16 = r & 15;
+  const size_t ci = (size_t)c * S.n_psr + I;
+  double part_j = 0.0;
+  {
+    double sa = 0.0;
+    if (r < pp) {
+#pragma unroll
+      for (int K = 0; K < T; ++K) {
+        if ((K & 1) != h || K < R) continue;
+        const double *t = A + ps::tix(K, R) * 256;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sa = fma(t[sw(k, r16)], vz[16 * K + k], sa);
+      }
+      if (h == 1) va[r] = sa;
+    }
+    __syncthreads();
+    if (r < PB && h == 0) {
+      (b ? S.lzr : S.lzg)[ci * pp + (PB - 1 - r)] = sa + va[r];
+      part_j = log(A[ps::tix(R, R) * 256 + sw(r16, r16)]);
+    }
+  }
+  part_j = block_sum(part_j, red);
+  if (tid == 0) {
+    S.jac_s[ci * 2 + b] = part_j;
+    S.flag_s[ci * 2 + b] = ok ? 0 : ps::kFlagNotPD;
+  }
+  double2 *xo = reinterpret_cast<double2 *>((b ? S.xr : S.xg) + ci * NE);
+  const double2 *xa = reinterpret_cast<const double2 *>(A);
+  constexpr int N2 = NE / 2;
+#pragma unroll
+  for (int i = 0; i < (N2 + 255) / 256; ++i) {
+    const int e = tid + 256 * i;
+    if (e < N2) xo[e] = xa[e];
+  }
+}
+
+// Per (pulsar, chain): a_G, a_R and a from the combined MAP (avec, written by
+// k_std_fwd with z = 0) and the sets' L_b z_b; v1 = beta (d - S0 a) and
+// beta log L(a) with S0 a formed directly (a is no longer a_hat + L z of one
+// factorisation); the Jacobian ln det L_G + ln det L_R.
+__global__ __launch_bounds__(256) void k_split_comb(StdDev S, const double *__restrict__ x) {
+  __shared__ double av[16 * ps::kMaxTiles];
+  __shared__ double red[12];
+  const int tid = threadIdx.x;
+  const int pi = xcd_index(blockIdx.x, gridDim.x);
+  const int I = pi / S.n_chains, c = pi - I * S.n_chains;
+  const double *xc = x + (size_t)c * S.d;
+  const double beta = S.beta ? S.beta[c] : 1.0;
+  const int P = S.P, pp = S.pp, j = tid;
+  const size_t ci = (size_t)c * S.n_psr + I, vb = ci * pp;
+  double a = 0.0, d = 0.0;
+  if (j < P) {
+    const double ah = S.avec[vb + j];
+    const double id = 1.0 / ps::curn_var(S, xc, I, j);
+    if (j < S.PG) {
+      const double g = ps::spec_value(S, xc, 0, I, j >> 1) * id * ah + S.lzg[ci * S.ppg + j];
+      S.ag[ci * S.ppg + j] = g;
+      a += g;
+    }
+    if (j < 2 * S.nf_rn || j >= 2 * S.ka) {
+      const int jr = j < 2 * S.nf_rn ? j : j - 2 * S.ka + 2 * S.nf_rn;
+      const double g = ps::split_var(S, xc, I, 1, jr) * id * ah + S.lzr[ci * S.ppr + jr];
+      S.ar[ci * S.ppr + jr] = g;
+      a += g;
+    }
+    av[j] = a;
+    d = (S.has_cw ? S.dbar + vb : S.dvec + (size_t)I * pp)[P - 1 - j];
+  }
+  __syncthreads();
+  double part_d = 0.0, part_q = 0.0, part_n = 0.0;
+  if (j < P) {
+    // (S0 a)_j down column P - 1 - j of the symmetric S0~ (coalesced over j)
+    const double *s0 = S.s0 + (size_t)I * pp * pp + (P - 1 - j);
+    double s = 0.0;
+    for (int m = 0; m < P; ++m) s = fma(s0[(size_t)(P - 1 - m) * pp], av[m], s);
+    S.avec[vb + j] = a;
+    S.v1[vb + (P - 1 - j)] = beta * (d - s);
+    part_d = a * d;
+    part_q = a * s;
+  }
+  block_sum3(part_d, part_q, part_n, red);
+  if (tid == 0) {
+    const double *k2 = S.cconst + 2 * I;
+    const double c0 = S.has_cw ? S.cbar[ci] : k2[0];
+    double *o = S.lik + ci * 2;
+    o[0] = beta * ((k2[1] - 0.5 * c0) + (part_d - 0.5 * part_q));
+    o[1] = S.jac_s[ci * 2] + S.jac_s[ci * 2 + 1];
+  }
+}
+
+// Prior of the common set per (frequency k < nf_gw, chain): a_G,k ~ N(0,
+// rho_k Gamma) for sin and cos; u = Gamma^-1 a, the quadratic form a^T u /
+// rho_k, ln det = N_p ln rho_k + ln det Gamma, -u / rho_k into v2 and the
+// explicit derivative (a_s^T u_s + a_c^T u_c) / (2 rho_k^2) - N_p / rho_k.
+__global__ __launch_bounds__(256) void k_split_prior_g(StdDev S, const double *__restrict__ x) {
+  __shared__ double as[2][16 * ps::kMaxTiles];
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x / S.nf_gw, k = blockIdx.x - c * S.nf_gw;
+  const int n = S.n_psr;
+  const double *xc = x + (size_t)c * S.d;
+  const double rho = ps::spec_value(S, xc, 0, 0, k);
+  const int i = tid & 127, h = tid >> 7;
+  if (i < n) as[h][i] = S.ag[((size_t)c * n + i) * S.ppg + 2 * k + h];
+  __syncthreads();
+  double part = 0.0;
+  if (i < n) {
+    double u = 0.0;
+    for (int m = 0; m < n; ++m) u = fma(S.gam_inv[(size_t)m * n + i], as[h][m], u);
+    part = as[h][i] * u;
+    S.v2[((size_t)c * n + i) * S.pp + 2 * k + h] = -u / rho;
+  }
+  const double q = block_sum(part, red);
+  if (tid == 0) {
+    double *o = S.quad_k + ((size_t)c * S.ka + k) * 2;
+    o[0] = q / rho;
+    o[1] = n * log(rho) + S.ldet_gamma;
+    S.drho_e[(size_t)c * S.ka + k] = 0.5 * q / (rho * rho) - n / rho;
+    S.flag2[(size_t)c * S.ka + k] = (rho > 0.0 && isfinite(rho)) ? 0 : ps::kFlagNotPD;
+  }
+}
+
+// Adjoint of set b per (pulsar, chain): g = dlog p / d a_b (the likelihood's
+// beta (d - S0 a) on the set's rows plus its prior term), dlog p / dz~ = X g~,
+// and the set's transform part of dlog p / dv_r, (T_r + Sigma~_rr / 2) / v_r^2
+// with T_r and Sigma~_rr as in k_std_bwd (no MAP term: the sets' MAP comes
+// from the combined problem).
+template <int T>
+__global__ __launch_bounds__(256) void k_split_bwd(StdDev S, const double *__restrict__ x,
+                                                    double *__restrict__ grad, int b) {
+  extern __shared__ double lds[];
+  constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256;
+  double *A = lds;
+  double *vv = A + NE, *vz = vv + pp, *vw = vz + pp, *tmp = vw + pp;
+  const int tid = threadIdx.x;
+  const int pi = xcd_index(blockIdx.x, gridDim.x);
+  const int I = pi / S.n_chains, c = pi - I * S.n_chains;
+  const double *xc = x + (size_t)c * S.d;
+  const int PB = b ? S.PR : S.PG, P = S.P;
+  const size_t ci = (size_t)c * S.n_psr + I;
+  {
+    const double2 *xi = reinterpret_cast<const double2 *>((b ? S.xr : S.xg) + ci * NE);
+    double2 *xa = reinterpret_cast<double2 *>(A);
+    constexpr int N2 = NE / 2;
+#pragma unroll
+    for (int i = 0; i < (N2 + 255) / 256; ++i) {
+      const int e = tid + 256 * i;
+      if (e < N2) xa[e] = xi[e];
+    }
+  }
+  const int zo = S.off_z + I * S.pz + (b ? S.PG : 0);
+  for (int r = tid; r < pp; r += 256) {
+    double g = 0.0, z = 0.0;
+    if (r < PB) {
+      const int j = PB - 1 - r, jc = ps::split_row(S, b, j);
+      g = S.v1[ci * S.pp + (P - 1 - jc)] + (b ? S.v2r[ci * pp + j] : S.v2[ci * S.pp + j]);
+      (b ? S.gar : S.gag)[ci * pp + j] = g;
+      z = xc[zo + j];
+    }
+    vv[r] = g;
+    vz[r] = z;
+  }
+  __syncthreads();
+  const int h = tid >> 7, r = tid & 127, R = r >> 4, r16 = r & 15;
+  {
+    double s = 0.0;
+    if (r < pp) {
+#pragma unroll
+      for (int K = 0; K < T; ++K) {
+        if ((K & 1) != h || K > R) continue;
+        const double *t = A + ps::tix(R, K) * 256;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s = fma(t[sw(r16, k)], vv[16 * K + k], s);
+      }
+      if (h == 1) tmp[r] = s;
+    }
+    __syncthreads();
+    if (r < pp && h == 0) {
+      s += tmp[r];
+      vw[r] = s;
+      if (r < PB) grad[(size_t)c * S.d + zo + (PB - 1 - r)] = s;
+    }
+    __syncthreads();
+  }
+  // column r from the bottom: Sigma~_rr = sum_a X_ar^2 and
+  // T_r = sum_a X_ar w~_a (sum_{b>a} X_br z~_b + X_ar z~_a / 2)
+  if (tid < PB) {
+    double ss = 0.0, tt = 0.0, suf = 0.0;
+    for (int K = T - 1; K >= R; --K) {
+      const double *t = A + ps::tix(K, R) * 256;
+#pragma unroll
+      for (int k = 15; k >= 0; --k) {
+        const double xv = t[sw(k, r16)], wv = vw[16 * K + k], zv = vz[16 * K + k];
+        ss = fma(xv, xv, ss);
+        tt = fma(xv * wv, fma(0.5 * xv, zv, suf), tt);
+        suf = fma(xv, zv, suf);
+      }
+    }
+    const int j = PB - 1 - r;
+    const double v = ps::split_var(S, xc, I, b, j);
+    (b ? S.ddr : S.ddg)[ci * pp + j] = (tt + 0.5 * ss) / (v * v);
+  }
+}
+
+// Adjoint of the combined MAP per (pulsar, chain) and the chain rule to the
+// prior variances.  Upstream of a_hat: g_j = (rho_j g_G,j + phi_j g_R,j) / D_j
+// (rho_j = 0 off the common rows, phi_j = 0 off the pulsar-noise rows);
+// dlog p / dD_j = a_hat_j (Sigma g)_j / D_j^2 through a_hat, and with
+// q_j = a_hat_j / D_j^2 the proportional split adds
+//   d/drho_j: phi_j q_j (g_G,j - g_R,j),   d/dphi_j: rho_j q_j (g_R,j - g_G,j);
+// each set adds its own transform part.  Rows summed in sin/cos pairs: the
+// pulsar's part of dlog p / drho_k (drho_p) and dlog p / dkappa (dD_rn, dD_dm).
+// With a CW, dlog p / d d_bar = beta (a + Sigma g).
+template <int T>
+__global__ __launch_bounds__(256) void k_split_bwd_c(StdDev S, const double *__restrict__ x) {
+  extern __shared__ double lds[];
+  constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256;
+  double *A = lds;
+  double *vv = A + NE, *vw = vv + pp, *tmp = vw + pp, *prt = tmp + pp, *pkt = prt + pp;
+  const int tid = threadIdx.x;
+  const int pi = xcd_index(blockIdx.x, gridDim.x);
+  const int I = pi / S.n_chains, c = pi - I * S.n_chains;
+  const double *xc = x + (size_t)c * S.d;
+  const int P = S.P;
+  const size_t ci = (size_t)c * S.n_psr + I, vb = ci * pp;
+  {
+    const double2 *xi = reinterpret_cast<const double2 *>(S.xinv + ci * NE);
+    double2 *xa = reinterpret_cast<double2 *>(A);
+    constexpr int N2 = NE / 2;
+#pragma unroll
+    for (int i = 0; i < (N2 + 255) / 256; ++i) {
+      const int e = tid + 256 * i;
+      if (e < N2) xa[e] = xi[e];
+    }
+  }
+  // this thread's row j (original order), kept for the chain rule
+  double rho = 0.0, phi = 0.0, gG = 0.0, gR = 0.0, D = 1.0;
+  int jr = -1;
+  if (tid < P) {
+    const int j = tid;
+    D = ps::curn_var(S, xc, I, j);
+    if (j < S.PG) {
+      rho = ps::spec_value(S, xc, 0, I, j >> 1);
+      gG = S.gag[ci * S.ppg + j];
+    }
+    if (j < 2 * S.nf_rn || j >= 2 * S.ka) {
+      jr = j < 2 * S.nf_rn ? j : j - 2 * S.ka + 2 * S.nf_rn;
+      phi = ps::split_var(S, xc, I, 1, jr);
+      gR = S.gar[ci * S.ppr + jr];
+    }
+  }
+  for (int r = tid; r < pp; r += 256) vv[r] = 0.0;
+  __syncthreads();
+  if (tid < P) vv[P - 1 - tid] = (rho * gG + phi * gR) / D;
+  __syncthreads();
+  const int h = tid >> 7, r = tid & 127, R = r >> 4, r16 = r & 15;
+  {
+    double s = 0.0;
+    if (r < pp) {
+#pragma unroll
+      for (int K = 0; K < T; ++K) {
+        if ((K & 1) != h || K > R) continue;
+        const double *t = A + ps::tix(R, K) * 256;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s = fma(t[sw(r16, k)], vv[16 * K + k], s);
+      }
+      if (h == 1) tmp[r] = s;
+    }
+    __syncthreads();
+    if (r < pp && h == 0) vw[r] = s + tmp[r];
+    __syncthreads();
+  }
+  // (Sigma g)~_r = sum_{a >= r} X_ar w~_a, one thread per column
+  if (tid < P) {
+    const int rc = P - 1 - tid, Rc = rc >> 4, rc16 = rc & 15;
+    double sg = 0.0;
+    for (int K = Rc; K < T; ++K) {
+      const double *t = A + ps::tix(K, Rc) * 256;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) sg = fma(t[sw(k, rc16)], vw[16 * K + k], sg);
+    }
+    const int j = tid;
+    const double ah = S.ahat[vb + rc];
+    const double q = ah / (D * D);
+    const double dD = sg * q;
+    prt[j] = (j < S.PG) ? dD + phi * q * (gG - gR) + S.ddg[ci * S.ppg + j] : 0.0;
+    pkt[j] = (jr >= 0) ? dD + rho * q * (gR - gG) + S.ddr[ci * S.ppr + jr] : 0.0;
+    if (S.has_cw) {
+      const double beta = S.beta ? S.beta[c] : 1.0;
+      S.gdbar[ci * P + j] = beta * (S.avec[vb + j] + sg);
+    }
+  }
+  __syncthreads();
+  if (tid < S.nf_gw) {
+    S.drho_p[ci * S.ka + tid] = prt[2 * tid] + prt[2 * tid + 1];
+  } else if (tid >= 64 && tid - 64 < S.nf_rn) {
+    const int k = tid - 64;
+    S.dD_rn[ci * S.ka + k] = pkt[2 * k] + pkt[2 * k + 1];
+  } else if (tid >= 128 && tid - 128 < S.kdm) {
+    const int k = tid - 128;
+    S.dD_dm[ci * S.kdm + k] = pkt[2 * S.ka + 2 * k] + pkt[2 * S.ka + 2 * k + 1];
+  }
+}
+
 template <int T>
 hipError_t set_attr_t() {
   hipError_t e = hipFuncSetAttribute((const void *)k_std_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds_bytes<T>());
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void *)k_std_prior_dense<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_bytes<T>());
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_split_fac<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_bytes<T>());
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_split_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lds_bytes<T>());
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_split_bwd_c<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)lds_bytes<T>());
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void *)k_std_bwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1286,11 +1674,13 @@ hipError_t launch_std_fwd(const StdDev &S, const double *x, hipStream_t s) {
 hipError_t launch_std_prior(const StdDev &S, const double *x, hipStream_t s) {
   if (S.nf_gw > 0) {
     const int grid = S.n_chains * S.nf_gw;
-    PS_DISPATCH(S.tg, k_std_prior_dense, grid, S, x);
+    if (S.split) hipLaunchKernelGGL(k_split_prior_g, dim3(grid), dim3(256), 0, s, S, x);
+    else PS_DISPATCH(S.tg, k_std_prior_dense, grid, S, x);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const size_t items = (size_t)S.n_chains * S.n_psr * (S.ka - S.nf_gw + S.kdm);
+  const size_t items =
+      (size_t)S.n_chains * S.n_psr * ((S.split ? S.nf_rn : S.ka - S.nf_gw) + S.kdm);
   if (items) hipLaunchKernelGGL(k_std_prior_diag, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s, S, x);
   return hipGetLastError();
 }
@@ -1299,6 +1689,28 @@ hipError_t launch_std_bwd(const StdDev &S, const double *x, double *grad, hipStr
   const int grid = S.n_chains * S.n_psr;
   if (grid == 0) return hipSuccess;
   PS_DISPATCH(S.tp, k_std_bwd, grid, S, x, grad);
+  return hipGetLastError();
+}
+
+// Split coefficients: the two sets' factorisations, then a_G, a_R, a and the
+// likelihood (after launch_std_fwd, which gives the combined MAP).
+hipError_t launch_split_fwd(const StdDev &S, const double *x, hipStream_t s) {
+  const int grid = S.n_chains * S.n_psr;
+  if (grid == 0 || !S.split) return hipSuccess;
+  PS_DISPATCH(S.tpg, k_split_fac, grid, S, x, 0);
+  PS_DISPATCH(S.tpr, k_split_fac, grid, S, x, 1);
+  hipLaunchKernelGGL(k_split_comb, dim3(grid), dim3(256), 0, s, S, x);
+  return hipGetLastError();
+}
+
+// Split coefficients: the sets' adjoints, then the combined MAP's and the
+// chain rule (in place of launch_std_bwd).
+hipError_t launch_split_bwd(const StdDev &S, const double *x, double *grad, hipStream_t s) {
+  const int grid = S.n_chains * S.n_psr;
+  if (grid == 0 || !S.split) return hipSuccess;
+  PS_DISPATCH(S.tpg, k_split_bwd, grid, S, x, grad, 0);
+  PS_DISPATCH(S.tpr, k_split_bwd, grid, S, x, grad, 1);
+  PS_DISPATCH(S.tp, k_split_bwd_c, grid, S, x);
   return hipGetLastError();
 }
 

@@ -57,6 +57,15 @@ struct StdDev {
   const double *cw_qd;           // [n_psr][2 kd][2 kd] F_D^T N~^-1 F_D
   const double *cw_dft;          // [2 kd][md] the transform of the samples to a_D
   const double *cw_pos;          // [n_psr][3] pulsar unit vectors
+  // split coefficients (App. C): a common-process set a_G over the rows
+  // k < nf_gw (PG = 2 nf_gw) and a pulsar-noise set a_R over the rows k < nf_rn
+  // then the DM block (PR = 2 nf_rn + 2 nf_dm), each with its own factorisation
+  // (tpg, tpr tiles); z per pulsar holds pz = PG + PR entries (P without split)
+  int split, PG, PR, tpg, tpr, ppg, ppr, pz;
+  const double *s0g;             // [n_psr][ppg][ppg] S0 on the common rows, reversed order, zero-padded
+  const double *s0r;             // [n_psr][ppr][ppr] S0 on the pulsar-noise rows, likewise
+  const double *gam_inv;         // Gamma^-1, n_psr x n_psr
+  double ldet_gamma;             // ln det Gamma
   // call
   int n_chains;
   const double *beta;            // [n_chains] or nullptr (1)
@@ -82,6 +91,17 @@ struct StdDev {
   double *cbar;                  // [n_chains][n_psr] dt~^T N~^-1 dt~ of dt~ = dt - h
   double *gdbar;                 // [n_chains][n_psr][P] dlog p / d d_bar (original order)
   double *dcw;                   // [n_chains][n_psr][8] the pulsar's part of dlog p / d theta_cw
+  // split coefficients (set b: 0 common, 1 pulsar noise; vectors in the set's
+  // original row order, strides ppg / ppr)
+  double *xg, *xr;               // [n_chains][n_psr][ntiles(tpg|tpr)][256] X of each set's reversed precision
+  double *lzg, *lzr;             // L_b z_b
+  double *ag, *ar;               // a_G, a_R
+  double *v2r;                   // -phi_R^-1 a_R (the common set's prior term goes to v2)
+  double *gag, *gar;             // dlog p / d a_b
+  double *ddg, *ddr;             // the set's transform part of dlog p / d(prior variance) per row
+  double *jac_s;                 // [n_chains][n_psr][2] ln det L_G, ln det L_R
+  int32_t *flag_s;               // [n_chains][n_psr][2] failures of the two factorisations
+  double *drho_p;                // [n_chains][n_psr][ka] the pulsar's part of dlog p / d rho_k
 };
 
 // Spectrum of process proc (0 common, 1 red noise of pulsar I, 2 DM of pulsar
@@ -110,6 +130,17 @@ __device__ inline double curn_var(const StdDev &S, const double *x, int I, int j
   return spec_value(S, x, 2, I, (j - 2 * S.ka) >> 1);
 }
 
+// Split coefficients: combined row of row j of set b, and the set's own prior
+// variance there (rho_k for the common set; kappa_Ik, then kappa_dm,Ik).
+__device__ inline int split_row(const StdDev &S, int b, int j) {
+  return (b == 0 || j < 2 * S.nf_rn) ? j : 2 * S.ka + (j - 2 * S.nf_rn);
+}
+__device__ inline double split_var(const StdDev &S, const double *x, int I, int b, int j) {
+  if (b == 0) return spec_value(S, x, 0, I, j >> 1);
+  if (j < 2 * S.nf_rn) return spec_value(S, x, 1, I, j >> 1);
+  return spec_value(S, x, 2, I, (j - 2 * S.nf_rn) >> 1);
+}
+
 constexpr int kFlagNotPD = 1;
 
 // Leapfrog kick and drift applied by k_std_finalize to its chain right after
@@ -133,4 +164,6 @@ hipError_t launch_std_finalize(const ps::StdDev &S, const double *x, double *log
                                int32_t *status, hipStream_t s, const ps::StdKick *kick = nullptr);
 hipError_t launch_std_cw_fwd(const ps::StdDev &S, const double *x, hipStream_t s);
 hipError_t launch_std_cw_bwd(const ps::StdDev &S, const double *x, hipStream_t s);
+hipError_t launch_split_fwd(const ps::StdDev &S, const double *x, hipStream_t s);
+hipError_t launch_split_bwd(const ps::StdDev &S, const double *x, double *grad, hipStream_t s);
 }  // namespace psk

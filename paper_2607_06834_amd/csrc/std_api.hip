@@ -141,7 +141,20 @@ int plan(const ptafs_std_desc *d, ps::StdDev &B, int64_t &ntoa) {
     o += 8;
   }
   B.n_theta = o;
-  B.off_z = o; o += n * B.P;
+  B.split = d->split ? 1 : 0;
+  B.pz = B.P;
+  if (B.split) {
+    // separate common-process and pulsar-noise sets need both processes
+    if (d->nf_gw < 1 || d->nf_rn < 1) return PTAFS_E_ARG;
+    B.PG = 2 * d->nf_gw;
+    B.PR = 2 * d->nf_rn + 2 * d->nf_dm;
+    B.tpg = ps::tiles_for(B.PG);
+    B.tpr = ps::tiles_for(B.PR);
+    B.ppg = 16 * B.tpg;
+    B.ppr = 16 * B.tpr;
+    B.pz = B.PG + B.PR;
+  }
+  B.off_z = o; o += n * B.pz;
   B.d = o;
   if (B.n_theta > 0 && (!d->prior_lo || !d->prior_hi)) return PTAFS_E_ARG;
   double pc = 0.0;
@@ -160,13 +173,15 @@ size_t dataset_bytes_of(const ps::StdDev &B) {
     const size_t k2 = 2 * (size_t)B.kd;
     cw = n * B.P * k2 + n * k2 + n * k2 * k2 + k2 * B.md + 3 * n;
   }
-  return (n * pp * pp + n * pp + 2 * n + 2 * nt + n * n + 2 * std::max(B.n_theta, 1) + PTAFS_MAX_HARM + cw) *
-             sizeof(double) + 21 * 256;
+  const size_t sp = B.split ? n * ((size_t)B.ppg * B.ppg + (size_t)B.ppr * B.ppr) + n * n : 0;
+  return (n * pp * pp + n * pp + 2 * n + 2 * nt + n * n + 2 * std::max(B.n_theta, 1) + PTAFS_MAX_HARM + cw +
+          sp) * sizeof(double) + 24 * 256;
 }
 
 struct WsLayout {
   size_t xinv, avec, ahat, v1, v2, lik, quad_k, drho_e, dkap_e, ddm_e, diag_q, dD_rn, dD_dm, flag1,
-      flag2, flag3, cw_ad, dbar, cbar, gdbar, dcw, total;
+      flag2, flag3, cw_ad, dbar, cbar, gdbar, dcw, xg, xr, lzg, lzr, ag, ar, v2r, gag, gar, ddg, ddr,
+      jac_s, flag_s, drho_p, total;
 };
 WsLayout ws_layout(const ps::StdDev &B, int C) {
   WsLayout L{};
@@ -200,6 +215,23 @@ WsLayout ws_layout(const ps::StdDev &B, int C) {
     L.cbar = take(c * n * D8);
     L.gdbar = take(c * n * (size_t)B.P * D8);
     L.dcw = take(c * n * 8 * D8);
+  }
+  if (B.split) {
+    const size_t pg = B.ppg, pr = B.ppr;
+    L.xg = take(c * n * ps::ntiles(B.tpg) * 256 * D8);
+    L.xr = take(c * n * ps::ntiles(B.tpr) * 256 * D8);
+    L.lzg = take(c * n * pg * D8);
+    L.lzr = take(c * n * pr * D8);
+    L.ag = take(c * n * pg * D8);
+    L.ar = take(c * n * pr * D8);
+    L.v2r = take(c * n * pr * D8);
+    L.gag = take(c * n * pg * D8);
+    L.gar = take(c * n * pr * D8);
+    L.ddg = take(c * n * pg * D8);
+    L.ddr = take(c * n * pr * D8);
+    L.jac_s = take(c * n * 2 * D8);
+    L.flag_s = take(c * n * 2 * I4);
+    L.drho_p = take(c * n * ka * D8);
   }
   L.total = o;
   return L;
@@ -252,6 +284,22 @@ ps::StdDev make_dev(const ptafs_std *ds, int C, const double *beta) {
     S.gdbar = reinterpret_cast<double *>(w + L.gdbar);
     S.dcw = reinterpret_cast<double *>(w + L.dcw);
   }
+  if (S.split) {
+    S.xg = reinterpret_cast<double *>(w + L.xg);
+    S.xr = reinterpret_cast<double *>(w + L.xr);
+    S.lzg = reinterpret_cast<double *>(w + L.lzg);
+    S.lzr = reinterpret_cast<double *>(w + L.lzr);
+    S.ag = reinterpret_cast<double *>(w + L.ag);
+    S.ar = reinterpret_cast<double *>(w + L.ar);
+    S.v2r = reinterpret_cast<double *>(w + L.v2r);
+    S.gag = reinterpret_cast<double *>(w + L.gag);
+    S.gar = reinterpret_cast<double *>(w + L.gar);
+    S.ddg = reinterpret_cast<double *>(w + L.ddg);
+    S.ddr = reinterpret_cast<double *>(w + L.ddr);
+    S.jac_s = reinterpret_cast<double *>(w + L.jac_s);
+    S.flag_s = reinterpret_cast<int32_t *>(w + L.flag_s);
+    S.drho_p = reinterpret_cast<double *>(w + L.drho_p);
+  }
   return S;
 }
 
@@ -260,8 +308,9 @@ int enqueue_eval(ptafs_std *ds, int C, const double *x, const double *beta, doub
   const ps::StdDev S = make_dev(ds, C, beta);
   PS_TRY(psk::launch_std_cw_fwd(S, x, s));
   PS_TRY(psk::launch_std_fwd(S, x, s));
+  PS_TRY(psk::launch_split_fwd(S, x, s));
   PS_TRY(psk::launch_std_prior(S, x, s));
-  PS_TRY(psk::launch_std_bwd(S, x, grad, s));
+  PS_TRY(S.split ? psk::launch_split_bwd(S, x, grad, s) : psk::launch_std_bwd(S, x, grad, s));
   PS_TRY(psk::launch_std_cw_bwd(S, x, s));
   PS_TRY(psk::launch_std_finalize(S, x, logp, grad, status, s, kick));
   return PTAFS_OK;
@@ -502,6 +551,7 @@ void fill_layout(const ps::StdDev &B, int64_t ntoa, int C, ptafs_std_layout_info
   out->workspace_bytes = ws_layout(B, C).total;
   out->hmc_bytes = hmc_bytes_of(B, C);
   out->off_cw = B.has_cw ? B.off_cw : -1;
+  out->pz = B.pz;
 }
 
 }  // namespace
@@ -602,6 +652,44 @@ int ptafs_std_create(const ptafs_std_desc *d, void *stream, ptafs_std **out) {
   chk(upload(ds, gt.data(), gt.size(), &D.gam_tiles, s));
   chk(upload(ds, ct.data(), ct.size(), &D.gch_tiles, s));
   chk(upload(ds, gam.data(), gam.size(), &D.gamma, s));
+  // split coefficients: S0 on each set's rows (reversed order, zero-padded),
+  // Gamma^-1 = chol(Gamma)^-T chol(Gamma)^-1 and ln det Gamma
+  std::vector<double> s0g, s0rr, ginv;
+  if (B.split) {
+    const int PG = B.PG, PR = B.PR, pg = B.ppg, pr = B.ppr;
+    auto rrow = [&](int j) { return j < 2 * B.nf_rn ? j : 2 * B.ka + (j - 2 * B.nf_rn); };
+    s0g.assign((size_t)n * pg * pg, 0.0);
+    s0rr.assign((size_t)n * pr * pr, 0.0);
+    for (int I = 0; I < n; ++I) {
+      for (int r = 0; r < PG; ++r)
+        for (int c = 0; c < PG; ++c)
+          s0g[((size_t)I * pg + r) * pg + c] = gr[I].s0[(size_t)(PG - 1 - r) * P + (PG - 1 - c)];
+      for (int r = 0; r < PR; ++r)
+        for (int c = 0; c < PR; ++c)
+          s0rr[((size_t)I * pr + r) * pr + c] = gr[I].s0[(size_t)rrow(PR - 1 - r) * P + rrow(PR - 1 - c)];
+    }
+    std::vector<double> li((size_t)n * n, 0.0);   // chol(Gamma)^-1, lower
+    double ldg = 0.0;
+    for (int j = 0; j < n; ++j) {
+      ldg += 2.0 * std::log(gch[(size_t)j * n + j]);
+      for (int i = j; i < n; ++i) {
+        double t = (i == j) ? 1.0 : 0.0;
+        for (int k = j; k < i; ++k) t -= gch[(size_t)i * n + k] * li[(size_t)k * n + j];
+        li[(size_t)i * n + j] = t / gch[(size_t)i * n + i];
+      }
+    }
+    ginv.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double t = 0.0;
+        for (int k = std::max(i, j); k < n; ++k) t += li[(size_t)k * n + i] * li[(size_t)k * n + j];
+        ginv[(size_t)i * n + j] = t;
+      }
+    D.ldet_gamma = ldg;
+    chk(upload(ds, s0g.data(), s0g.size(), &D.s0g, s));
+    chk(upload(ds, s0rr.data(), s0rr.size(), &D.s0r, s));
+    chk(upload(ds, ginv.data(), ginv.size(), &D.gam_inv, s));
+  }
   chk(upload(ds, lf.data(), lf.size(), &D.lnfy, s));
   chk(upload(ds, d->prior_lo, (size_t)B.n_theta, &D.prior_lo, s));
   chk(upload(ds, d->prior_hi, (size_t)B.n_theta, &D.prior_hi, s));
@@ -712,10 +800,11 @@ int ptafs_std_profile_stages(ptafs_std *ds, int32_t n_chains, const double *x, c
       (void)hipEventRecord(ev[i + 1], s);
     };
     (void)hipEventRecord(ev[0], s);
-    const hipError_t e0 = psk::launch_std_cw_fwd(S, x, s);
-    step(0, e0 != hipSuccess ? e0 : psk::launch_std_fwd(S, x, s));
+    hipError_t e0 = psk::launch_std_cw_fwd(S, x, s);
+    if (e0 == hipSuccess) e0 = psk::launch_std_fwd(S, x, s);
+    step(0, e0 != hipSuccess ? e0 : psk::launch_split_fwd(S, x, s));
     step(1, psk::launch_std_prior(S, x, s));
-    const hipError_t e2 = psk::launch_std_bwd(S, x, grad, s);
+    const hipError_t e2 = S.split ? psk::launch_split_bwd(S, x, grad, s) : psk::launch_std_bwd(S, x, grad, s);
     step(2, e2 != hipSuccess ? e2 : psk::launch_std_cw_bwd(S, x, s));
     step(3, psk::launch_std_finalize(S, x, logp, grad, status, s));
     if (hipEventSynchronize(ev[kStages]) != hipSuccess) err = PTAFS_E_HIP;
@@ -743,8 +832,15 @@ int ptafs_std_coefficients(ptafs_std *ds, int32_t n_chains, const double *x, con
   const ps::StdDev S = make_dev(ds, n_chains, beta);
   PS_TRY(psk::launch_std_cw_fwd(S, x, s));
   PS_TRY(psk::launch_std_fwd(S, x, s));
-  PS_TRY(hipMemcpy2DAsync(a, (size_t)S.P * sizeof(double), S.avec, (size_t)S.pp * sizeof(double),
-                          (size_t)S.P * sizeof(double), (size_t)n_chains * S.n_psr, hipMemcpyDeviceToDevice, s));
+  const size_t rows = (size_t)n_chains * S.n_psr, D8 = sizeof(double);
+  if (S.split) {
+    PS_TRY(psk::launch_split_fwd(S, x, s));
+    PS_TRY(hipMemcpy2DAsync(a, S.pz * D8, S.ag, S.ppg * D8, S.PG * D8, rows, hipMemcpyDeviceToDevice, s));
+    PS_TRY(hipMemcpy2DAsync(a + S.PG, S.pz * D8, S.ar, S.ppr * D8, S.PR * D8, rows, hipMemcpyDeviceToDevice,
+                            s));
+  } else {
+    PS_TRY(hipMemcpy2DAsync(a, S.P * D8, S.avec, S.pp * D8, S.P * D8, rows, hipMemcpyDeviceToDevice, s));
+  }
   return end_call(ds, s);
 }
 

@@ -1,0 +1,122 @@
+"""GPU parity of the standardized form with split common-process and
+pulsar-noise coefficients (App. C, Eqs. separated_post, split_map_a,
+split_standardizing_transform) against the oracle of oracle/std.py, through
+the C ABI, to the bar of test_gpu_std.py (log p to 1e-9 relative; per
+gradient element 1e-7 of max(|g*|, the oracle's magnitude companion) plus
+ten times the oracle's own rounding sensitivity; statuses identical).
+
+Cases: each set's factorisation across tile boundaries (2 nf_gw and
+2 nf_rn + 2 nf_dm on both sides of 16, 32, 64 and up to 120 rows), rows that
+only one set covers (common process above the pulsar noise and the reverse,
+the DM block), free spectra, a design matrix, tempered chains, a CW in its
+own basis, the map back to [a_G | a_R], failed factorisations."""
+import numpy as np
+import pytest
+
+from oracle import std
+from test_gpu_std import check, make, points, run
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2607_06834_amd import api as a
+    return a
+
+
+def make_split(*args, **kw):
+    ds = make(*args, **kw)
+    ds["split"] = 1
+    return ds
+
+
+SPLIT_CASES = {
+    # name: (counts, (nf_rn, nf_gw, nf_dm), free, tm)
+    "small_hd_dm": ([30, 45, 60], (5, 3, 4), False, False),
+    "common_above_noise": ([40, 50, 35], (3, 6, 2), False, False),
+    "no_dm": ([33, 47, 52, 61], (7, 2, 0), False, False),
+    "general_tm": ([44, 38, 51], (4, 4, 2), False, True),
+    "free_spectrum": ([35, 42, 48], (4, 3, 2), True, False),
+    "single_toa_pulsar": ([1, 60, 45], (3, 3, 2), False, False),
+    "one_pulsar": ([120], (8, 8, 4), False, False),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SPLIT_CASES))
+def test_split_parity(api, name):
+    counts, nf, free, tm = SPLIT_CASES[name]
+    ds = make_split(91, counts, nf, free, tm)
+    prep = std.StdPrepared(ds)
+    X = points(ds, prep, 9, 21)
+    check(prep, X, run(api, ds, X))
+
+
+@pytest.mark.parametrize("nf", [(8, 8, 0), (8, 9, 1), (16, 16, 0), (8, 8, 9), (30, 14, 30), (30, 30, 30)])
+def test_split_tiles(api, nf):
+    """(PG, PR) = (16, 16), (18, 18), (32, 32), (16, 34), (28, 120), (60, 120)
+    against the combined P = 32, 36, 64, 68, 120, 120."""
+    ds = make_split(92, [70, 90], nf, span=16.0)
+    prep = std.StdPrepared(ds)
+    X = points(ds, prep, 5, 22)
+    check(prep, X, run(api, ds, X))
+
+
+def test_split_tempered_and_pulsar_count(api):
+    ds = make_split(93, [12 + (i % 5) for i in range(33)], (3, 2, 1))
+    prep = std.StdPrepared(ds)
+    X = points(ds, prep, 6, 23)
+    betas = np.array([0.3, 1.0, 0.5, 0.1, 0.9, 0.02])
+    check(prep, X, run(api, ds, X, beta=betas), beta=betas)
+
+
+def test_split_cw(api):
+    """Split sets with a deterministic CW in its own basis: the transform
+    centres on the MAP of dt - h, and dlog p / d d_bar goes through the
+    combined MAP."""
+    ds = make_split(94, [40, 55, 33], (5, 4, 3), cw=(24, 2.0))
+    prep = std.StdPrepared(ds)
+    X = points(ds, prep, 6, 24)
+    betas = np.array([1.0, 0.4, 1.0, 0.7, 1.0, 0.2])
+    check(prep, X, run(api, ds, X, beta=betas), beta=betas)
+
+
+def test_split_coefficients_and_determinism(api):
+    """[a_G | a_R] of each point against the oracle's transform; repeated and
+    single-chain calls bit-identical."""
+    ds = make_split(95, [30, 41, 52], (4, 3, 2), tm=True)
+    prep = std.StdPrepared(ds)
+    X = points(ds, prep, 5, 25)
+    g = api.StdDataset(ds)
+    assert int(g.layout.pz) == 2 * (4 + 3 + 2)
+    a = g.ptafs_std_coefficients(torch.tensor(X, device="cuda"), beta=torch.full((5,), 0.6, device="cuda",
+                                                                                  dtype=torch.float64))
+    a = a.cpu().numpy()
+    g.close()
+    for c in range(5):
+        ref = std.coefficients(prep, X[c], beta=0.6)
+        np.testing.assert_allclose(a[c], ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+    u, v, w = run(api, ds, X), run(api, ds, X), run(api, ds, X[[2]])
+    for p, q, r in zip(u, v, w):
+        np.testing.assert_array_equal(p, q)
+        np.testing.assert_array_equal(p[[2]], r)
+
+
+def test_split_status_codes(api):
+    ds = make_split(96, [30, 41, 52], (4, 3, 2))
+    lay = std.StdPrepared(ds).lay
+    ds["prior_lo"] = ds["prior_lo"].copy()
+    amp = [lay.gw] + [lay.rn + 2 * I for I in range(3)] + [lay.dm + 2 * I for I in range(3)]
+    ds["prior_lo"][amp] = -400.0
+    prep = std.StdPrepared(ds)
+    X = points(ds, prep, 6, 26)
+    X[0, 1] = 99.0                   # outside the box
+    X[1, lay.z + 3] = np.nan         # non-finite coefficient
+    X[2, lay.gw] = -300.0            # rho 0: Sigma_G has no prior term
+    X[3, lay.rn + 2] = -300.0        # one pulsar's red noise 0
+    ref = check(prep, X, run(api, ds, X))
+    assert list(ref["status"]) == [1, 4, 2, 2, 0, 0]

@@ -94,3 +94,22 @@ def test_precompute_cw_rejects_bad_descriptors(api):
         bad[key] = val
         with pytest.raises(RuntimeError):
             api.ptafs_std_precompute_cw(bad, 0)
+
+
+def test_split_descriptors(api):
+    """Split coefficients (App. C) need both a common process and pulsar red
+    noise; a valid split descriptor plans (the stored Gram quantities are the
+    combined ones either way)."""
+    ds = synth.make_array(5, 2, [10, 12], 9 * synth.YEAR_S, backends_per_psr=[1, 1],
+                          nf_rn=2, nf_gw=2, nf_dm=1)
+    ok = dict(ds)
+    ok["split"] = 1
+    s0, dv, _, _, _ = api.ptafs_std_precompute(ok, 1)
+    s1, d1, _, _, _ = api.ptafs_std_precompute(ds, 1)
+    np.testing.assert_array_equal(s0, s1)
+    np.testing.assert_array_equal(dv, d1)
+    for nf in ((0, 2, 1), (2, 0, 1)):
+        bad = dict(ok)
+        bad["nf_rn"], bad["nf_gw"], bad["nf_dm"] = nf
+        with pytest.raises(RuntimeError):
+            api.ptafs_std_precompute(bad, 0)
