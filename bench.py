@@ -180,18 +180,29 @@ def std_flops_fwd(P):
     return 2.0 * P ** 3 / 3.0 + 4.0 * P * P
 
 
-def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2, cw=False):
+def std_flops_split(P, PG, PR):
+    """Algorithmic flops of the transform stage per (pulsar, chain) with split
+    coefficients: the combined factorisation (std_flops_fwd), each set's
+    Cholesky and inverse with one mat-vec (2 PB^3 / 3 + PB^2), and S0 a
+    (2 P^2)."""
+    return std_flops_fwd(P) + 2.0 * (PG ** 3 + PR ** 3) / 3.0 + PG * PG + PR * PR + 2.0 * P * P
+
+
+def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2, cw=False, split=False):
     """The paper's standardized form (CURN transform on the Gram form, timing
     model marginalised) on the same 67-pulsar / 250k-TOA data set, or (cw)
-    on the simulated CW array with the CW in its own Fourier basis: HMC
-    trajectories replayed as one HIP graph, per-stage times and the roofline
-    of its dominant kernel."""
+    on the simulated CW array with the CW in its own Fourier basis, or
+    (split) the 67-pulsar set with split common-process / pulsar-noise
+    coefficients: HMC trajectories replayed as one HIP graph, per-stage times
+    and the roofline of its dominant stage."""
     import numpy as np
     import torch
     import synth
     from paper_2607_06834_amd import api
 
     ds = synth.cw_array() if cw else synth.cfg2()
+    if split:
+        ds["split"] = 1
     t0 = time.perf_counter()
     g = api.StdDataset(ds)
     t_create = time.perf_counter() - t0
@@ -239,10 +250,21 @@ def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2, cw=False):
         valid = 1.0 - float(bad.sum().item()) / (n_chains * n_leapfrog * steps)
     stages = g.ptafs_std_profile_stages(x, reps=20, stream=stream)
     P = int(lay.p)
-    flops = std_flops_fwd(P) * n_chains * int(lay.n_psr)
+    fpp = std_flops_fwd(P)
+    kern = "k_std_fwd (per-pulsar CURN factorisation + inverse)"
+    if split:
+        PG, PR = 2 * int(ds["nf_gw"]), 2 * (int(ds["nf_rn"]) + int(ds["nf_dm"]))
+        fpp = std_flops_split(P, PG, PR)
+        kern = ("transform stage: k_std_fwd (combined MAP) + k_split_fac x 2 (common, pulsar-noise sets) "
+                "+ k_split_comb")
+    flops = fpp * n_chains * int(lay.n_psr)
     achieved = flops / (stages["transform"] * 1e-3) / 1e12
     g.close()
-    if cw:
+    if split:
+        wl = ("67 psr / 250000 TOA, RN 30 + DM 30 + HD common 14 with split coefficients (P = 120 combined, "
+              f"sets of {PG} and {PR}), {n_chains} chains x leapfrog {n_leapfrog}; "
+              "step = one HIP-graph trajectory")
+    elif cw:
         wl = (f"{int(lay.n_psr)} psr x 180 TOA over 15 yr, RN 30 + HD common 14 (P = {P}), CW in its own "
               f"basis of 60 frequencies on 2T, {n_chains} chains x leapfrog {n_leapfrog}; "
               "step = one HIP-graph trajectory")
@@ -255,9 +277,9 @@ def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2, cw=False):
         eps=eps_used, accept_rate=acc_rate, valid_eval_fraction=valid, create_s=t_create,
         stages_ms={k: round(v, 5) for k, v in stages.items()},
         ms_per_eval=round(sum(stages.values()), 5),
-        roofline={"bound": "mfma", "kernel": "k_std_fwd (per-pulsar CURN factorisation + inverse)",
+        roofline={"bound": "mfma", "kernel": kern,
                   "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                  "frac": achieved / FP64_PEAK_TFLOPS, "flop_per_problem": std_flops_fwd(P),
+                  "frac": achieved / FP64_PEAK_TFLOPS, "flop_per_problem": fpp,
                   "problems_per_launch": n_chains * int(lay.n_psr), "avg_launch_ms": stages["transform"],
                   "traffic": None})
 
@@ -384,6 +406,8 @@ def main():
                                      steps=args.steps, warmup=args.warmup)}
         out["std_form_cw"] = std_bench(n_chains=args.chains, n_leapfrog=args.leapfrog,
                                        steps=args.steps, warmup=args.warmup, cw=True)
+        out["std_form_split"] = std_bench(n_chains=args.chains, n_leapfrog=args.leapfrog,
+                                          steps=args.steps, warmup=args.warmup, split=True)
         print(json.dumps(out))
         return
     ds = synth.cfg2()
@@ -471,12 +495,15 @@ def main():
         # config 1 beside it (3 psr x 500 TOA): a second point of the oracle's rate
         cpu["config1"] = cpu_baseline(synth.cfg1(), min_seconds=3.0, label="3 psr / 1500 TOA (config 1)")
     _log("cpu baseline done")
-    std_form = std_cw = None
+    std_form = std_cw = std_split = None
     if not args.no_std:
         std_form = std_bench(n_chains=C, n_leapfrog=L, steps=args.steps, warmup=args.warmup)
         _log(f"standardized form: {std_form['value']:.0f} grad evals/s, stages {std_form['stages_ms']}")
         std_cw = std_bench(n_chains=C, n_leapfrog=L, steps=args.steps, warmup=args.warmup, cw=True)
         _log(f"standardized form with CW: {std_cw['value']:.0f} grad evals/s, stages {std_cw['stages_ms']}")
+        std_split = std_bench(n_chains=C, n_leapfrog=L, steps=args.steps, warmup=args.warmup, split=True)
+        _log(f"standardized form, split coefficients: {std_split['value']:.0f} grad evals/s, "
+             f"stages {std_split['stages_ms']}")
     cfg4 = None
     if not args.no_cfg4:
         cfg4 = cfg4_bench()
@@ -531,6 +558,7 @@ def main():
         "cpu_baseline": cpu,
         "std_form": std_form,
         "std_form_cw": std_cw,
+        "std_form_split": std_split,
         "cfg4": cfg4,
         "serving": serving,
     }
