@@ -1068,25 +1068,45 @@ __global__ __launch_bounds__(256) void k_std_cw_bwd(StdDev S, const double *__re
 
 // ---------------------------------------------------------------------------
 // Assembly per chain: log p, the hyper-parameter gradient and the status.
+// One workgroup of kFinT threads per chain.  Loops over the chain's entries
+// issue their loads together; every sum is taken in a fixed order (per-lane
+// strides, then fixed shuffle trees and wave partials in wave order).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
-                                                       double *__restrict__ logp, double *__restrict__ grad,
-                                                       int32_t *__restrict__ status, ps::StdKick kick,
-                                                       int has_kick) {
-  __shared__ double red[4];
-  const int tid = threadIdx.x, c = blockIdx.x;
+constexpr int kFinT = 1024, kFinW = kFinT / 64;
+
+// Sum over the 32 lanes of a half-wave (fixed tree).
+__device__ inline double half_sum(double v) {
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kFinT) void k_std_finalize(StdDev S, const double *x,
+                                                         double *__restrict__ logp, double *__restrict__ grad,
+                                                         int32_t *__restrict__ status, ps::StdKick kick,
+                                                         int has_kick) {
+  __shared__ double red[kFinW];
+  __shared__ int sb[kFinW][4];
+  __shared__ double drho_tot[ps::kMaxRhoK];
+  __shared__ double cwp[kFinW][8];
+  const int tid = threadIdx.x, c = blockIdx.x, wv = tid >> 6;
   const int n = S.n_psr;
   const double *xc = x + (size_t)c * S.d;
   double *gc = grad + (size_t)c * S.d;
-  const double beta = S.beta ? S.beta[c] : 1.0;
-  // input checks
+  // input checks: the box on theta, finiteness of z (four entries a step)
   int bad_box = 0, bad_in = 0;
-  for (int i = tid; i < S.n_theta; i += 256) {
+  for (int i = tid; i < S.n_theta; i += kFinT) {
     const double v = xc[i];
     if (!(v >= S.prior_lo[i] && v <= S.prior_hi[i])) bad_box = 1;
   }
-  for (int i = S.n_theta + tid; i < S.d; i += 256)
-    if (!isfinite(xc[i])) bad_in = 1;
+  for (int i0 = S.n_theta + tid; i0 < S.d; i0 += 4 * kFinT) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = (i0 + u * kFinT < S.d) ? xc[i0 + u * kFinT] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (!isfinite(v[u])) bad_in = 1;
+  }
   // the CW must not coalesce before the last sample time of its basis
   int bad_cw = 0;
   if (S.has_cw && tid == 0) {
@@ -1096,81 +1116,86 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
     const double y = K1 * ((double)(S.md - 1) * S.td / S.md);
     bad_cw = !(y < 1.0);
   }
-  // factorisation flags
+  // factorisation flags and the log p parts
   int fl = 0;
-  for (int i = tid; i < n; i += 256) fl |= S.flag1[(size_t)c * n + i];
-  if (S.split)
-    for (int i = tid; i < 2 * n; i += 256) fl |= S.flag_s[(size_t)c * 2 * n + i];
-  for (int k = tid; k < S.nf_gw; k += 256) fl |= S.flag2[(size_t)c * S.ka + k];
-  // diagonal prior items: red-only frequencies and DM, or with split
-  // coefficients the whole pulsar-noise set
-  const int nd = n * (S.ka + S.kdm);
-  auto diag_item = [&](int kk) { return S.split ? (kk < S.nf_rn || kk >= S.ka) : kk >= S.nf_gw; };
-  for (int i = tid; i < nd; i += 256)
-    if (diag_item(i % (S.ka + S.kdm))) fl |= S.flag3[(size_t)c * nd + i];
-  // log p parts
   double lp = 0.0;
-  for (int i = tid; i < n; i += 256) {
+  for (int i = tid; i < n; i += kFinT) {
+    fl |= S.flag1[(size_t)c * n + i];
     const double *o = S.lik + ((size_t)c * n + i) * 2;
     lp += o[0] + o[1];
   }
-  for (int k = tid; k < S.nf_gw; k += 256) {
+  if (S.split)
+    for (int i = tid; i < 2 * n; i += kFinT) fl |= S.flag_s[(size_t)c * 2 * n + i];
+  for (int k = tid; k < S.nf_gw; k += kFinT) {
+    fl |= S.flag2[(size_t)c * S.ka + k];
     const double *o = S.quad_k + ((size_t)c * S.ka + k) * 2;
     lp += -0.5 * o[0] - (n * ps::kLn2Pi + o[1]);
   }
-  for (int i = tid; i < nd; i += 256) {
-    if (!diag_item(i % (S.ka + S.kdm))) continue;
-    const double *o = S.diag_q + ((size_t)c * nd + i) * 2;
-    lp += -0.5 * o[0] - (ps::kLn2Pi + o[1]);
+  // diagonal prior items: red-only frequencies and DM, or with split
+  // coefficients the whole pulsar-noise set
+  const int nd = n * (S.ka + S.kdm);
+  for (int i = tid; i < nd; i += kFinT) {
+    const int kk = i % (S.ka + S.kdm);
+    if (S.split ? (kk < S.nf_rn || kk >= S.ka) : kk >= S.nf_gw) {
+      fl |= S.flag3[(size_t)c * nd + i];
+      const double *o = S.diag_q + ((size_t)c * nd + i) * 2;
+      lp += -0.5 * o[0] - (ps::kLn2Pi + o[1]);
+    }
   }
   // d/drho_k in total: the explicit prior part plus the transform's part summed
-  // over the pulsars, 8 threads per frequency, partials combined in a fixed
-  // order (with split coefficients the pulsars' rho parts are drho_p, and
-  // dD_rn holds their kappa parts only)
-  __shared__ double drho_part[8][ps::kMaxRhoK];
-  __shared__ double drho_tot[ps::kMaxRhoK];
+  // over the pulsars (with split coefficients the pulsars' rho parts are
+  // drho_p, and dD_rn holds their kappa parts only), 32 lanes per frequency
   {
-    const int k = tid >> 3, h = tid & 7;
-    double sacc = 0.0;
+    const int k = tid >> 5, h = tid & 31;
+    const double *src = S.split ? S.drho_p : S.dD_rn;
+    double s = 0.0;
     if (k < S.nf_gw)
-      for (int J = h; J < n; J += 8) sacc += (S.split ? S.drho_p : S.dD_rn)[((size_t)c * n + J) * S.ka + k];
-    if (k < ps::kMaxRhoK) drho_part[h][k] = sacc;
-    __syncthreads();
-    if (tid < S.nf_gw) {
-      double t = S.drho_e[(size_t)c * S.ka + tid];
+      for (int J = h; J < n; J += 32) s += src[((size_t)c * n + J) * S.ka + k];
+    s = half_sum(s);
+    if (h == 0 && k < S.nf_gw) drho_tot[k] = S.drho_e[(size_t)c * S.ka + k] + s;
+  }
+  // the CW parameters' parts, pulsars in order: lane groups of 8 per wave,
+  // then the waves in order
+  if (S.has_cw) {
+    const int v = tid & 7, I0 = tid >> 3;
+    double s = 0.0;
+    for (int I = I0; I < n; I += kFinT / 8) s += S.dcw[((size_t)c * n + I) * 8 + v];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) t += drho_part[q][tid];
-      drho_tot[tid] = t;
-    }
-    __syncthreads();
+    for (int o = 8; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+    if ((tid & 63) < 8) cwp[wv][v] = s;
   }
-  // hyper-parameter gradient: every process entry is a sum over its frequencies
-  for (int e = tid; e < S.n_theta; e += 256) {
-    int proc, I, slot, K;
-    if (e < S.off_rn) { proc = 0; I = 0; slot = e - S.off_gw; K = S.nf_gw; }
-    else if (e < S.off_dm) { proc = 1; I = (e - S.off_rn) / S.w_rn; slot = (e - S.off_rn) - I * S.w_rn; K = S.nf_rn; }
-    else { proc = 2; I = (e - S.off_dm) / S.w_dm; slot = (e - S.off_dm) - I * S.w_dm; K = S.kdm; }
-    double g = 0.0;
-    const int k0 = S.free_spec ? slot : 0, k1 = S.free_spec ? slot + 1 : K;
-    for (int k = k0; k < k1; ++k) {
+  __syncthreads();
+  // hyper-parameter gradient, 32 lanes per process instance (the common
+  // process, then red noise and DM per pulsar), lane k taking frequency k
+  for (int it = tid >> 5; it < 1 + 2 * n; it += kFinT / 32) {
+    const int k = tid & 31;
+    int proc, I, off, K;
+    if (it == 0) { proc = 0; I = 0; off = S.off_gw; K = S.nf_gw; }
+    else if (it <= n) { proc = 1; I = it - 1; off = S.off_rn + I * S.w_rn; K = S.nf_rn; }
+    else { proc = 2; I = it - 1 - n; off = S.off_dm + I * S.w_dm; K = S.kdm; }
+    if (K == 0) continue;
+    double v = 0.0;
+    if (k < K) {
       double dd;
-      if (proc == 0) {
-        dd = drho_tot[k];
-      } else if (proc == 1) {
-        dd = S.dkap_e[((size_t)c * n + I) * S.ka + k] + S.dD_rn[((size_t)c * n + I) * S.ka + k];
-      } else {
-        dd = S.ddm_e[((size_t)c * n + I) * S.kdm + k] + S.dD_dm[((size_t)c * n + I) * S.kdm + k];
-      }
-      const double v = ps::spec_value(S, xc, proc, I, k) * dd;
-      if (S.free_spec) g += ps::kLn10 * v;
-      else g += (slot == 0) ? 2.0 * ps::kLn10 * v : -S.lnfy[k] * v;
+      if (proc == 0) dd = drho_tot[k];
+      else if (proc == 1) dd = S.dkap_e[((size_t)c * n + I) * S.ka + k] + S.dD_rn[((size_t)c * n + I) * S.ka + k];
+      else dd = S.ddm_e[((size_t)c * n + I) * S.kdm + k] + S.dD_dm[((size_t)c * n + I) * S.kdm + k];
+      v = ps::spec_value(S, xc, proc, I, k) * dd;
     }
-    gc[e] = g;
+    if (S.free_spec) {
+      if (k < K) gc[off + k] = ps::kLn10 * v;
+    } else {
+      const double ga = half_sum(2.0 * ps::kLn10 * v);
+      const double gg = half_sum(k < K ? -S.lnfy[k] * v : 0.0);
+      if (k == 0) {
+        gc[off] = ga;
+        gc[off + 1] = gg;
+      }
+    }
   }
-  // dlog p / d theta_cw: the pulsars' parts in order
   if (S.has_cw && tid < 8) {
     double g = 0.0;
-    for (int I = 0; I < n; ++I) g += S.dcw[((size_t)c * n + I) * 8 + tid];
+    for (int w = 0; w < kFinW; ++w) g += cwp[w][tid];
     gc[S.off_cw + tid] = g;
   }
   // reduce the flags and log p
@@ -1179,27 +1204,35 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     const int bb = __any(bad_box), bi = __any(bad_in), bf = __any(fl != 0), bc = __any(bad_cw);
-    if ((tid & 63) == 0) red[tid >> 6] = v;
-    __shared__ int sb[4][4];
     if ((tid & 63) == 0) {
-      sb[tid >> 6][0] = bb;
-      sb[tid >> 6][1] = bi;
-      sb[tid >> 6][2] = bf;
-      sb[tid >> 6][3] = bc;
+      red[wv] = v;
+      sb[wv][0] = bb;
+      sb[wv][1] = bi;
+      sb[wv][2] = bf;
+      sb[wv][3] = bc;
     }
     __syncthreads();
-    lp = (red[0] + red[1]) + (red[2] + red[3]);
-    bad_box = sb[0][0] | sb[1][0] | sb[2][0] | sb[3][0];
-    bad_in = sb[0][1] | sb[1][1] | sb[2][1] | sb[3][1];
-    fl = sb[0][2] | sb[1][2] | sb[2][2] | sb[3][2];
-    bad_cw = sb[0][3] | sb[1][3] | sb[2][3] | sb[3][3];
+    lp = 0.0;
+    bad_box = bad_in = fl = bad_cw = 0;
+    for (int w = 0; w < kFinW; ++w) {
+      lp += red[w];
+      bad_box |= sb[w][0];
+      bad_in |= sb[w][1];
+      fl |= sb[w][2];
+      bad_cw |= sb[w][3];
+    }
   }
   lp += S.prior_const;
-  // output finiteness
+  // output finiteness (the theta entries written above by other threads)
   int nonfin = !isfinite(lp);
-  __syncthreads();
-  for (int i = tid; i < S.d; i += 256)
-    if (!isfinite(gc[i])) nonfin = 1;
+  for (int i0 = tid; i0 < S.d; i0 += 4 * kFinT) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = (i0 + u * kFinT < S.d) ? gc[i0 + u * kFinT] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (!isfinite(v[u])) nonfin = 1;
+  }
   nonfin = __syncthreads_or(nonfin);
   int st = PTAFS_ST_OK;
   if (bad_box) st = PTAFS_ST_PRIOR;
@@ -1207,9 +1240,8 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
   else if (bad_cw) st = PTAFS_ST_CW;
   else if (fl) st = PTAFS_ST_NOTPD;
   else if (nonfin) st = PTAFS_ST_NONFINITE;
-  (void)beta;
   if (st != PTAFS_ST_OK)
-    for (int i = tid; i < S.d; i += 256) gc[i] = 0.0;
+    for (int i = tid; i < S.d; i += kFinT) gc[i] = 0.0;
   if (tid == 0) {
     logp[c] = (st == PTAFS_ST_OK) ? lp : -INFINITY;
     status[c] = st;
@@ -1220,10 +1252,26 @@ __global__ __launch_bounds__(256) void k_std_finalize(StdDev S, const double *x,
     __syncthreads();
     if (tid == 0 && kick.n_invalid && st != PTAFS_ST_OK) kick.n_invalid[c] += 1;
     double *xw = kick.x + (size_t)c * S.d, *pw = kick.p + (size_t)c * S.d;
-    for (int i = tid; i < S.d; i += 256) {
-      const double pi = pw[i] + kick.eps * gc[i];
-      pw[i] = pi;
-      xw[i] += kick.eps * (kick.inv_mass ? kick.inv_mass[i] : 1.0) * pi;
+    for (int i0 = tid; i0 < S.d; i0 += 2 * kFinT) {
+      double gv[2], pv[2], xv[2], mv[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int i = i0 + u * kFinT;
+        const bool in = i < S.d;
+        gv[u] = in ? gc[i] : 0.0;
+        pv[u] = in ? pw[i] : 0.0;
+        xv[u] = in ? xw[i] : 0.0;
+        mv[u] = (in && kick.inv_mass) ? kick.inv_mass[i] : 1.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int i = i0 + u * kFinT;
+        if (i < S.d) {
+          const double pi = pv[u] + kick.eps * gv[u];
+          pw[i] = pi;
+          xw[i] = xv[u] + kick.eps * mv[u] * pi;
+        }
+      }
     }
   }
 }
@@ -1718,7 +1766,7 @@ hipError_t launch_std_finalize(const StdDev &S, const double *x, double *logp, d
                                int32_t *status, hipStream_t s, const ps::StdKick *kick) {
   if (S.n_chains == 0) return hipSuccess;
   const ps::StdKick k = kick ? *kick : ps::StdKick{};
-  hipLaunchKernelGGL(k_std_finalize, dim3(S.n_chains), dim3(256), 0, s, S, x, logp, grad, status, k,
+  hipLaunchKernelGGL(k_std_finalize, dim3(S.n_chains), dim3(kFinT), 0, s, S, x, logp, grad, status, k,
                      kick ? 1 : 0);
   return hipGetLastError();
 }
