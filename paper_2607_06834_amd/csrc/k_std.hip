@@ -597,7 +597,7 @@ __global__ __launch_bounds__(256, 2) void k_std_fwd(StdDev S, const double *__re
 template <int T>
 __global__ __launch_bounds__(256, 2) void k_std_prior_dense(StdDev S, const double *__restrict__ x) {
   extern __shared__ double lds[];
-  constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256;
+  constexpr int pp = 16 * T, NE = ps::ntiles(T) * 256, NT = ps::ntiles(T);
   double *A = lds;
   double *va = A + NE, *vb = va + 2 * pp, *vu = vb + 2 * pp, *red = vu + 2 * pp;
   int *flag = reinterpret_cast<int *>(red + 8);
@@ -605,20 +605,29 @@ __global__ __launch_bounds__(256, 2) void k_std_prior_dense(StdDev S, const doub
   const int c = blockIdx.x / S.nf_gw, k = blockIdx.x - c * S.nf_gw;
   const int n = S.n_psr;
   const double *xc = x + (size_t)c * S.d;
+  // phi_k tiles: thread tid holds element (tid / 16, tid % 16) of every tile
+  // and of every diagonal tile's diagonal; all loads are issued before any use
+  const int rr = tid >> 4, cc = tid & 15;
+  double gv[NT], dg[T];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) gv[tt] = S.gam_tiles[tt * 256 + rr * 16 + cc];
   const double rho = ps::spec_value(S, xc, 0, 0, k);
-  for (int e = tid; e < NE; e += 256) {
-    const int tt = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
-    int TI = 0;
-    while (ps::tix(TI + 1, 0) <= tt) ++TI;
-    const int r = 16 * TI + rr, col = 16 * (tt - ps::tix(TI, 0)) + cc;
-    double v = rho * S.gam_tiles[e];
-    if (r == col) v += (r < n) ? ((k < S.nf_rn) ? ps::spec_value(S, xc, 1, r, k) : 0.0) : 1.0;
-    A[(tt << 8) + sw(rr, cc)] = v;
+#pragma unroll
+  for (int TI = 0; TI < T; ++TI) {
+    const int r = 16 * TI + rr;
+    dg[TI] = (rr != cc) ? 0.0 : (r < n) ? ((k < S.nf_rn) ? ps::spec_value(S, xc, 1, r, k) : 0.0) : 1.0;
   }
   for (int i = tid; i < pp; i += 256) {
     const double *av = S.avec + ((size_t)c * n + i) * S.pp;
     va[i] = (i < n) ? av[2 * k] : 0.0;
     va[pp + i] = (i < n) ? av[2 * k + 1] : 0.0;
+  }
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    int TI = 0;
+    while (ps::tix(TI + 1, 0) <= tt) ++TI;
+    const int TJ = tt - ps::tix(TI, 0);
+    A[(tt << 8) + sw(rr, cc)] = (TI == TJ) ? fma(rho, gv[tt], dg[TI]) : rho * gv[tt];
   }
   if (tid == 0) *flag = 1;
   __syncthreads();
@@ -648,17 +657,27 @@ __global__ __launch_bounds__(256, 2) void k_std_prior_dense(StdDev S, const doub
     }
   }
   __syncthreads();
-  // Gamma u (columns of the symmetric Gamma, coalesced) for the rho term
+  // Gamma u (columns of the symmetric Gamma, coalesced) for the rho term,
+  // eight loads in flight at a time
   double part_g = 0.0;
   if (tid < 2 * pp) {
     const int i = tid % pp, h = tid / pp;
     if (i < n) {
       double s = 0.0;
-      for (int m = 0; m < n; ++m) s = fma(S.gamma[(size_t)m * n + i], vu[h * pp + m], s);
+      int m = 0;
+      for (; m + 8 <= n; m += 8) {
+        double g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) g[u] = S.gamma[(size_t)(m + u) * n + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s = fma(g[u], vu[h * pp + m + u], s);
+      }
+      for (; m < n; ++m) s = fma(S.gamma[(size_t)m * n + i], vu[h * pp + m], s);
       part_g = s * vu[h * pp + i];
     }
   }
-  // tr(phi^-1 Gamma) = |X G|_F^2, G = chol(Gamma): tiles (X G)_IJ = sum_{K=J}^{I} X_IK G_KJ
+  // tr(phi^-1 Gamma) = |X G|_F^2, G = chol(Gamma): tiles (X G)_IJ = sum_{K=J}^{I} X_IK G_KJ,
+  // a task's G tiles loaded together before its products
   double part_t = 0.0;
   {
     int task = 0;
@@ -667,9 +686,12 @@ __global__ __launch_bounds__(256, 2) void k_std_prior_dense(StdDev S, const doub
 #pragma unroll
       for (int J = 0; J <= I; ++J, ++task) {
         if ((task & 3) != w) continue;
+        v4d g[T];
+#pragma unroll
+        for (int K = J; K <= I; ++K) g[K - J] = ldg_cm(S.gch_tiles + ps::tix(K, J) * 256, c16, q);
         v4d r{0.0, 0.0, 0.0, 0.0};
-        for (int K = J; K <= I; ++K)
-          r = mma(ld_rm(A + ps::tix(I, K) * 256, c16, q), ldg_cm(S.gch_tiles + ps::tix(K, J) * 256, c16, q), r);
+#pragma unroll
+        for (int K = J; K <= I; ++K) r = mma(ld_rm(A + ps::tix(I, K) * 256, c16, q), g[K - J], r);
         part_t += (r[0] * r[0] + r[1] * r[1]) + (r[2] * r[2] + r[3] * r[3]);
       }
   }
