@@ -109,6 +109,9 @@ __device__ inline void pin_row(double (&v)[16]) {
   asm volatile("" ::: "memory");
 }
 
+// A pointer into LDS that stays one (DS instructions, not flat ones).
+using lds_dp = __attribute__((address_space(3))) double *;
+
 __device__ inline void wave_sync() {   // LDS writes of the wave visible to its later reads
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -124,7 +127,7 @@ __device__ inline void wave_sync() {   // LDS writes of the wave visible to its 
 // receives 1 / L_jj.  With LZ, lzJ[r] += sum_c L_rc zJ[c].  Returns false in
 // every lane when a pivot is not positive and finite.
 template <bool LZ>
-__device__ __forceinline__ bool diag_factor(double *t, double *bc, double *idg, int lane, const double *zJ,
+__device__ __forceinline__ bool diag_factor(double *t, lds_dp bc, lds_dp idg, int lane, const double *zJ,
                                             double *lzJ) {
   const int r = lane & 15;
   double row[16];
@@ -138,7 +141,7 @@ __device__ __forceinline__ bool diag_factor(double *t, double *bc, double *idg, 
     double bv[16];
     const bool def = (j >= 2) && (j <= 14);   // pivot j - 2 still owes rows j + 1 ...
     if (def) {
-      const double *bp = bc + 16 * ((j - 2) % 3);
+      const auto bp = bc + 16 * ((j - 2) % 3);
 #pragma unroll
       for (int k = j + 1; k < 16; ++k) bv[k] = bp[k];
     }
@@ -185,7 +188,7 @@ __device__ __forceinline__ bool diag_factor(double *t, double *bc, double *idg, 
 // with L read from the tile at the same address in every lane.  Column m + 1
 // of L is loaded while column m is applied; the solve and the stores sit in
 // one branch so that the wave's loads all precede its stores.
-__device__ __forceinline__ void diag_inverse(double *t, const double *idg, int lane) {
+__device__ __forceinline__ void diag_inverse(double *t, lds_dp idg, int lane) {
   const int r = lane & 15;
   if (lane < 16) {
     double acc[16], xc[16], lc[2][16], dg[2];
@@ -217,7 +220,7 @@ __device__ __forceinline__ void diag_inverse(double *t, const double *idg, int l
 // x_c = (a_c - sum_{k<c} x_k L_ck) / L_cc, one row per thread, L_JJ (lower)
 // read at the same address by every lane.  With LZ, lzI[r] += sum_c x_c zJ[c].
 template <bool LZ>
-__device__ __forceinline__ void panel_row(double *t, const double *ljj, const double *idg, int r,
+__device__ __forceinline__ void panel_row(double *t, const double *ljj, lds_dp idg, int r,
                                           const double *zJ, double *lzI) {
   double x[16], lc[2][16], dg[2];
 #pragma unroll
@@ -287,7 +290,13 @@ __device__ __forceinline__ bool factor_invert(double *A, int tid, int *flag, dou
   int *ctr = flag + 1;   // work counter of the trailing phases
   const int w = tid >> 6, lane = tid & 63, c = lane & 15, q = lane >> 4;
   const int wd = 0;   // the wave that factorises the diagonal tiles
-  double *bc = ws, *idg = ws + 48;   // idg: 16 per diagonal tile
+  // The scratch sits past 64 KB of LDS in the larger kernels, beyond a DS
+  // instruction's immediate offset: held in a register (the asm hides its
+  // constant value), its accesses take the offsets as immediates instead of
+  // forming each address anew.
+  lds_dp bc = (lds_dp)ws;
+  asm volatile("" : "+v"(bc));
+  lds_dp idg = bc + 48;   // idg: 16 per diagonal tile
   if (w == wd) {
     const bool ok = diag_factor<LZ>(A, bc, idg, lane, z, lz);
     if (lane == 0 && !ok) *flag = 0;
