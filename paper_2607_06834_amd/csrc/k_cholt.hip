@@ -112,6 +112,15 @@ __device__ inline double row_bcast_d(double v, int g) {
   return __longlong_as_double(((long long)hi << 32) | lo);
 }
 
+// The same through the LDS crossbar: every lane reads lane addr / 4 (addr =
+// 4 (c + 16 g) for row g), two DS instructions instead of the VALU swaps.
+__device__ inline double bperm_bcast_d(double v, int addr) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)b);
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // acc += X Y for one 16x16x16 product given the four k-slices of both operands
 __device__ inline v4d mfma4(const v4d &a, const v4d &b, v4d acc) {
   acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc, 0, 0, 0);
@@ -126,11 +135,12 @@ __host__ __device__ constexpr int tidx(int I, int J) { return I * (I + 1) / 2 + 
 // independent (frequency, chain) problems per workgroup, one wave each
 constexpr int kProbPerGroup = 4;
 
-// Work of the extra workgroups: G = nb * ns workgroups (spec_groups) for nb
-// blocks of 16 chains and ns contiguous frequency segments.  The forward's
-// items cost about the same whatever parts they carry, so its segments hold
-// equal numbers of frequencies; the adjoint's segments are balanced by cost,
-// a frequency costing one unit per part it carries (diagonal red noise, DM).
+// Work of the extra workgroups: G = nb * ns workgroups (spec_groups_fwd,
+// spec_groups) for nb blocks of 16 chains and ns contiguous frequency
+// segments.  The forward's segments hold equal numbers of frequencies (a
+// split by the parts a frequency carries was measured slower); the adjoint's
+// segments are balanced by cost, a frequency costing one unit per part it
+// carries (diagonal red noise, DM).
 struct spec_split {
   int G, nb, ns, kmax, nf_gw, ka, nf_dm;
   bool by_cost;
@@ -163,7 +173,7 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const d
     const spec_split sp(D, gridDim.x - n_dense_groups, D.c_pad, false);
     for (int it = blockIdx.x - n_dense_groups; it < sp.nb * sp.ns; it += sp.G) {
       const int b = it / sp.ns, s = it - b * sp.ns;
-      pt::spec_fwd_cb(D, x, b * pt::kCB, sp.k_lo(s), sp.k_lo(s + 1), s);
+      pt::spec_fwd_cb(D, x, b * pt::kCB, sp.k_lo(s), sp.k_lo(s + 1), s, sp.ns);
       __syncthreads();
     }
     return;
@@ -261,24 +271,41 @@ __global__ __launch_bounds__(64 * kProbPerGroup) void k_cholt_fwd(Dev D, const d
     //      never touched by the later steps, so the scaling of the columns by
     //      1/sqrt(pivot) and the pivot checks wait for the end of the block
     //      column, where they are done four columns at a time.
+    //      Each step is pipelined against the next: the diagonal tile is
+    //      updated first, then the next pivot's reciprocal is started, and
+    //      the tiles below (whose column arrived through the LDS crossbar
+    //      during the previous step) are updated under its latency, their
+    //      next column sent on its way.
+    double ri_next = rcp_nr(readlane_d(A[tidx(J, J)][0], 0));
+    double arn[NT];
+#pragma unroll
+    for (int I = J + 1; I < NT; ++I) arn[I] = bperm_bcast_d(A[tidx(I, J)][0], 4 * c16);
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
       // padding columns of the last tile: pivot 1, zero column, nothing to do
       if (J == NT - 1 && 16 * J + cc >= n) continue;
       const int g0 = cc & 3, v0 = cc >> 2;
-      const double ri = rcp_nr(readlane_d(A[tidx(J, J)][v0], cc + 16 * g0));
+      const int g1 = (cc + 1) & 3, v1 = (cc + 1) >> 2;
+      const double ri = ri_next;
       double lk[4];
 #pragma unroll
       for (int v = v0; v < 4; ++v) {
         const double t = row_share_d(A[tidx(J, J)][v], cc) * ri;
         lk[v] = (v > v0 || q > g0) ? t : 0.0;
       }
+      {
+        double ar = row_bcast_d(A[tidx(J, J)][v0], g0);
+        if (c16 <= cc) ar = 0.0;
 #pragma unroll
-      for (int I = J; I < NT; ++I) {
-        double ar = row_bcast_d(A[tidx(I, J)][v0], g0);
-        if (I == J && c16 <= cc) ar = 0.0;
+        for (int v = v0; v < 4; ++v) A[tidx(J, J)][v] -= ar * lk[v];
+      }
+      if (cc + 1 < 16) ri_next = rcp_nr(readlane_d(A[tidx(J, J)][v1], cc + 1 + 16 * g1));
+#pragma unroll
+      for (int I = J + 1; I < NT; ++I) {
+        const double ar = arn[I];
 #pragma unroll
         for (int v = v0; v < 4; ++v) A[tidx(I, J)][v] -= ar * lk[v];
+        if (cc + 1 < 16) arn[I] = bperm_bcast_d(A[tidx(I, J)][v1], 4 * (c16 + 16 * g1));
       }
     }
     // pivots of the lane's columns q + 4v (lane q + 4v of its own lane
@@ -775,13 +802,27 @@ int spec_groups(const Dev &D, int ng, int chains) {
   return nb * ns;
 }
 
+// The forward's diagonal-frequency workgroups: up to one frequency segment
+// per frequency, four per free compute unit's worth (the forward's segments
+// write no per-segment flags, so their number is free).  A dense forward wave
+// leaves room for one more wave on its SIMD; with fewer, longer segments these
+// workgroups outlast the dense waves (measured: a segment of one or two
+// frequencies of 16 chains and 67 pulsars takes about 30k-60k cycles, a
+// dense wave about 48k).
+int spec_groups_fwd(const Dev &D, int ng, int chains) {
+  const int nb = (chains + pt::kCB - 1) / pt::kCB;
+  const int kmax = max(D.ka, D.nf_dm);
+  const int ns = max(1, min(kmax, 4 * max(8, D.n_cu - ng) / nb));
+  return nb * ns;
+}
+
 // grid: the dense problems, kProbPerGroup per workgroup, then the
 // diagonal-frequency workgroups
 template <int NT>
 hipError_t launch_fwd_t(const Dev &D, const double *x, hipStream_t s) {
   const int nprob = D.nf_gw * D.c_pad;
   const int ng = (nprob + kProbPerGroup - 1) / kProbPerGroup;
-  hipLaunchKernelGGL(k_cholt_fwd<NT>, dim3(ng + spec_groups(D, ng, D.c_pad)),
+  hipLaunchKernelGGL(k_cholt_fwd<NT>, dim3(ng + spec_groups_fwd(D, ng, D.c_pad)),
                      dim3(64 * kProbPerGroup), 0, s, D, x, ng);
   return hipGetLastError();
 }

@@ -291,8 +291,9 @@ __device__ inline void spec_bwd_block(const Dev &D, const double *__restrict__ x
 // ---------------------------------------------------------------------------
 // Chain-blocked forms, for the extra workgroups of the dense launches: the
 // 16 chains c0 .. c0 + 15 over the frequencies [k_lo, k_hi); in the forward,
-// segment 0 also writes the chains' status and per-pulsar rows (CW
-// constants, timing-model rows, zero rows).  The chain runs fastest over the threads,
+// segment 0 also writes the chains' status, and segment seg of nseg the
+// seg-th share of the per-pulsar rows (CW constants, timing-model rows, zero
+// rows).  The chain runs fastest over the threads,
 // and a chain's frequencies next, so the chain-minor coefficient panels,
 // adjoint panels and sqrt(kappa) move 16 chains (128 bytes) per access, and a
 // chain's whitened inputs and gradient several frequencies at a time.  The
@@ -302,7 +303,7 @@ __device__ inline void spec_bwd_block(const Dev &D, const double *__restrict__ x
 constexpr int kCB = 16;
 
 __device__ inline void spec_fwd_cb(const Dev &D, const double *__restrict__ x, int c0, int k_lo,
-                                   int k_hi, int seg) {
+                                   int k_hi, int seg, int nseg) {
   __shared__ int ired[4];
   __shared__ int kflag[kCB][PTAFS_MAX_HARM];
   __shared__ int czero[kCB];
@@ -351,8 +352,8 @@ __device__ inline void spec_fwd_cb(const Dev &D, const double *__restrict__ x, i
       czero[tid] = (bad || st != 0) ? 1 : 0;
     }
     __syncthreads();
-    // segment 0 writes the per-pulsar rows, as (pulsar, chain) pairs
-    const int pr_lo = 0, pr_hi = (seg == 0) ? n * kCB : 0;
+    // the segments share the per-pulsar rows, as (pulsar, chain) pairs
+    const int pr_lo = n * kCB * seg / nseg, pr_hi = n * kCB * (seg + 1) / nseg;
     if (D.has_cw)
       for (int idx = pr_lo + tid; idx < pr_hi; idx += 256) {
         const int cc = idx & (kCB - 1), I = idx / kCB;
