@@ -112,6 +112,25 @@ __device__ inline double row_bcast_d(double v, int g) {
   return __longlong_as_double(((long long)hi << 32) | lo);
 }
 
+// v of the same lane in the partner row (row q ^ 1, by the permlane16 swap)
+// and in the partner half (row q ^ 2, by the permlane32 swap), q the caller's
+// row: the swaps give every lane the value of the lower and of the upper
+// member of its pair.
+__device__ inline double xor16_d(double v, int q) {
+  const long long b = __double_as_longlong(v);
+  const auto pl = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+  const auto ph = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  const unsigned lo = (q & 1) ? pl[0] : pl[1], hi = (q & 1) ? ph[0] : ph[1];
+  return __longlong_as_double(((long long)hi << 32) | lo);
+}
+__device__ inline double xor32_d(double v, int q) {
+  const long long b = __double_as_longlong(v);
+  const auto pl = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+  const auto ph = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  const unsigned lo = (q & 2) ? pl[0] : pl[1], hi = (q & 2) ? ph[0] : ph[1];
+  return __longlong_as_double(((long long)hi << 32) | lo);
+}
+
 // The same through the LDS crossbar: every lane reads lane addr / 4 (addr =
 // 4 (c + 16 g) for row g), two DS instructions instead of the VALU swaps.
 __device__ inline double bperm_bcast_d(double v, int addr) {
@@ -410,20 +429,19 @@ __device__ inline void scan_tile(const v4d &X, int row0, const double (*vz)[4], 
     sa += as;
     ca += ac;
   }
-  // exclusive prefix of the lane sums over the four lane groups of a column
-  double is = ls, ic = lc;
-  double us = __shfl_up(is, 16, 64), uc = __shfl_up(ic, 16, 64);
-  if (q >= 1) {
-    is += us;
-    ic += uc;
-  }
-  us = __shfl_up(is, 32, 64);
-  uc = __shfl_up(ic, 32, 64);
+  // inclusive prefix of the lane sums over the four lane groups of a column
+  // and their total, by the row swaps: with t the partner row's sum, the
+  // pair total is p = x + t, the prefix x (+ t on odd rows) (+ the other
+  // half's pair total on rows 2 and 3), the total p + that
+  const double ts1 = xor16_d(ls, q), tc1 = xor16_d(lc, q);
+  const double ps = ls + ts1, pc2 = lc + tc1;
+  const double os = xor32_d(ps, q), oc = xor32_d(pc2, q);
+  double is = (q & 1) ? ps : ls, ic = (q & 1) ? pc2 : lc;
   if (q >= 2) {
-    is += us;
-    ic += uc;
+    is += os;
+    ic += oc;
   }
-  const double ts = __shfl(is, c16 + 48, 64), tc = __shfl(ic, c16 + 48, 64);
+  const double ts = ps + os, tc = pc2 + oc;
   st.q += part + (st.rs + (is - ls)) * sa + (st.rc + (ic - lc)) * ca;
   st.rs += ts;
   st.rc += tc;
@@ -533,10 +551,10 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
         sc += e * ab[16 * K + 4 * q + v][1];
       }
     }
-    ss += __shfl_xor(ss, 16, 64);
-    sc += __shfl_xor(sc, 16, 64);
-    ss += __shfl_xor(ss, 32, 64);
-    sc += __shfl_xor(sc, 32, 64);
+    ss += xor16_d(ss, q);
+    sc += xor16_d(sc, q);
+    ss += xor32_d(ss, q);
+    sc += xor32_d(sc, q);
     vcol[J][0] = ss;
     vcol[J][1] = sc;
   }
@@ -624,8 +642,8 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
 #pragma unroll
       for (int I = J; I < NT; ++I) scan_tile(Wc[I], 16 * I, vz, st, l, c16, q);
       double qq = st.q;
-      qq += __shfl_xor(qq, 16, 64);
-      qq += __shfl_xor(qq, 32, 64);
+      qq += xor16_d(qq, q);
+      qq += xor32_d(qq, q);
       dkap[J] = qq;
 #pragma unroll
       for (int I = J + 1; I < NT; ++I)
@@ -688,7 +706,18 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
     }
     wave_sync();
 
-    // ---- W = C^-1 in B layout; -W_II in A layout
+    // ---- W = C^-1 in B layout; -W_II in A layout.  The off-diagonal
+    //      factor tiles (A layout) are loaded together first, so that the
+    //      dependent products below never wait on memory.
+    v4d Ca[NTILE];
+#pragma unroll
+    for (int I = 1; I < NT; ++I)
+#pragma unroll
+      for (int K = 0; K < I; ++K) {
+        const double *t = Cb + tidx(I, K) * 256 + pc * 16 + 4 * q;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Ca[tidx(I, K)][s] = t[s];
+      }
     v4d Wb[NTILE];
     v4d Wi[NT];
 #pragma unroll
@@ -704,13 +733,7 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
       for (int J = 0; J < I; ++J) {
         v4d U = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int K = J; K < I; ++K) {
-          v4d a;
-          const double *t = Cb + tidx(I, K) * 256 + pc * 16 + 4 * q;
-#pragma unroll
-          for (int s = 0; s < 4; ++s) a[s] = t[s];
-          U = mfma4(a, Wb[tidx(K, J)], U);
-        }
+        for (int K = J; K < I; ++K) U = mfma4(Ca[tidx(I, K)], Wb[tidx(K, J)], U);
         Wb[tidx(I, J)] = mfma4(Wi[I], U, v4d{0.0, 0.0, 0.0, 0.0});
       }
     wave_sync();
@@ -722,8 +745,8 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
 #pragma unroll
       for (int I = J; I < NT; ++I) scan_tile(Wb[tidx(I, J)], 16 * I, vz, st, l, c16, q);
       double qq = st.q;
-      qq += __shfl_xor(qq, 16, 64);
-      qq += __shfl_xor(qq, 32, 64);
+      qq += xor16_d(qq, q);
+      qq += xor32_d(qq, q);
       dkap[J] = qq;
     }
 
@@ -739,21 +762,24 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
 #pragma unroll
       for (int s = 0; s < 4; ++s) Wa[T][s] = tl[T][pc * TS + 4 * q + s];
 
-    // ---- d/drho: M = W G column block by column block, quadratic forms
+    // ---- d/drho: M = W G column block by column block, quadratic forms;
+    //      block column J of G is loaded once, all its tiles together, and
+    //      serves every row block I
 #pragma unroll
     for (int J = 0; J < NT; ++J) {
+      v4d G[NT];
+#pragma unroll
+      for (int K = J; K < NT; ++K) {
+        const double *gt = gch + tidx(K, J) * 256 + 64 * q + c16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) G[K][v] = gt[16 * v];
+      }
       ScanState st{0.0, 0.0, 0.0};
 #pragma unroll
       for (int I = J; I < NT; ++I) {
         v4d Mt = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int K = J; K <= I; ++K) {
-          v4d g;
-          const double *gt = gch + tidx(K, J) * 256 + 64 * q + c16;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) g[v] = gt[16 * v];
-          Mt = mfma4(Wa[tidx(I, K)], g, Mt);
-        }
+        for (int K = J; K <= I; ++K) Mt = mfma4(Wa[tidx(I, K)], G[K], Mt);
         scan_tile(Mt, 16 * I, vz, st, l, c16, q);
       }
       dr += st.q;
