@@ -61,6 +61,27 @@ def measured_traffic(tuning):
     return float(fields[key])
 
 
+def measured_std_traffic():
+    """HBM bytes per launch of k_std_fwd at the 67-pulsar shape from the
+    committed counter summary, if it was taken on the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "std_form_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    m = hashlib.sha256()
+    for f in ("k_std.hip", "std.h", "cw_dev.h"):
+        m.update(open(os.path.join(ROOT, "paper_2607_06834_amd", "csrc", f), "rb").read())
+    key = "traffic_bytes_per_launch[k_std_fwd 67psr]"
+    if fields.get("source_sha256") != m.hexdigest() or key not in fields:
+        return None
+    return float(fields[key])
+
+
 def cpu_baseline(ds, n_chains_sample=8, min_seconds=10.0, seed=204, repeats=3, label="67 psr / 250k TOA"):
     """The oracle timed on the host cores on a bounded sample of the workload:
     ``repeats`` timed samples of at least min_seconds / repeats each, the
@@ -281,7 +302,8 @@ def std_bench(n_chains=64, n_leapfrog=20, steps=10, warmup=2, cw=False, split=Fa
                   "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                   "frac": achieved / FP64_PEAK_TFLOPS, "flop_per_problem": fpp,
                   "problems_per_launch": n_chains * int(lay.n_psr), "avg_launch_ms": stages["transform"],
-                  "traffic": None})
+                  # counted for the shared form at 64 chains (profiles/std_form_traffic.md)
+                  "traffic": measured_std_traffic() if not (cw or split) and n_chains == 64 else None})
 
 
 def cfg4_bench(n_chains=256, n_leapfrog=20, n_traj=10, n_plain=20):
