@@ -366,8 +366,10 @@ int ptafs_std_layout(const ptafs_std *ds, int32_t n_chains, ptafs_std_layout_inf
  *   logp   device [n_chains]        grad  device [n_chains][d]
  *   status device [n_chains]
  * Per (pulsar, chain) one factorisation of the P x P CURN precision and its
- * inverse, per (frequency, chain) one N_p x N_p factorisation of phi_k, on
- * FP64 matrix cores; results are bit-identical for identical inputs.
+ * inverse (with split coefficients also one of each set's precision), per
+ * (frequency, chain) one N_p x N_p factorisation of phi_k (with split
+ * coefficients none: Gamma^-1 is formed once), on FP64 matrix cores; results
+ * are bit-identical for identical inputs.
  */
 int ptafs_std_logp_grad(ptafs_std *ds, int32_t n_chains, const double *x, const double *beta,
                         double *logp, double *grad, int32_t *status, void *stream);
@@ -381,9 +383,11 @@ int ptafs_std_coefficients(ptafs_std *ds, int32_t n_chains, const double *x, con
 
 /* Stage timing of ptafs_std_logp_grad: `reps` evaluations with a HIP event
  * between the stages on `stream`; mean ms per stage to the HOST array
- * ms_out[4]: per-pulsar transform (k_std_fwd), prior per frequency
- * (k_std_prior_*), per-pulsar adjoint (k_std_bwd), assembly.  Synchronises
- * the stream. */
+ * ms_out[4]: per-pulsar transform (k_std_fwd; with a CW its k_std_cw_fwd,
+ * with split coefficients the sets' factorisations and k_split_comb), prior
+ * per frequency (k_std_prior_* or k_split_prior_g), per-pulsar adjoint
+ * (k_std_bwd or the k_split_bwd kernels; with a CW k_std_cw_bwd), assembly.
+ * Synchronises the stream. */
 int ptafs_std_profile_stages(ptafs_std *ds, int32_t n_chains, const double *x, const double *beta,
                              double *logp, double *grad, int32_t *status, int32_t reps,
                              double *ms_out, void *stream);
