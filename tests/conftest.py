@@ -17,3 +17,10 @@ def pytest_configure(config):
 def gpu_available():
     import torch
     return torch.cuda.is_available()
+
+
+# A test may load another build of the library (the host-sanitized debug
+# build) in a process of its own by naming it here.
+if os.environ.get("PTAFS_TEST_LIB"):
+    from paper_2607_06834_amd import _lib as _ptafs_lib
+    _ptafs_lib.LIB_PATH = os.environ["PTAFS_TEST_LIB"]
