@@ -55,52 +55,6 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-ASAN_DIR = os.path.join(OUT_DIR, "asan")
-ASAN_LIB = os.path.join(ASAN_DIR, "libptafs_asan.so")
-# host pass only: AddressSanitizer and UndefinedBehaviorSanitizer on the host
-# code (descriptor checks, planning, G/QR and Gram precomputation, layouts);
-# the device code is built as in the product library
-ASAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
-             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
-
-
-def asan_runtime() -> str:
-    """The compiler's shared ASan runtime, which a process must preload to
-    load the sanitized library."""
-    r = subprocess.run([os.path.join(os.path.dirname(HIPCC), "amdclang++"),
-                        "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
-    path = r.stdout.strip()
-    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
-        raise RuntimeError(f"shared ASan runtime not found ({path or r.stderr.strip()})")
-    return path
-
-
-def _compile_asan(src):
-    obj = os.path.join(ASAN_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, *ASAN_HOST, "-c", os.path.join(CSRC, src), "-o", obj]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"hipcc (host ASan) failed for {src}:\n{r.stdout}\n{r.stderr}")
-    return obj
-
-
-def build_host_asan() -> str:
-    """Debug build of the library with the host code sanitized
-    (_build/asan/libptafs_asan.so).  It links the shared sanitizer runtime,
-    so a process that loads it preloads asan_runtime() first (LD_PRELOAD)."""
-    os.makedirs(ASAN_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile_asan, SOURCES))
-    tmp = ASAN_LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-shared-libsan",
-           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", *objs, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"link (host ASan) failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, ASAN_LIB)
-    return ASAN_LIB
-
-
 def build_microbench() -> str:
     """Peak-measurement program (FP64 MFMA / vector FMA / copy)."""
     exe = os.path.join(HERE, "microbench", "peaks")

@@ -1,7 +1,7 @@
 """The library's host code under AddressSanitizer and UndefinedBehaviorSanitizer
 (no GPU).
 
-The host-sanitized debug build (paper_2607_06834_amd/build.py,
+The host-sanitized debug build (paper_2607_06834_amd/build_asan.py,
 build_host_asan: host pass instrumented, device code as in the product
 library) is loaded, with the shared ASan runtime preloaded, in a pytest
 process of its own that runs the tests calling the host-only entry points:
@@ -26,13 +26,13 @@ def _stale(lib, build):
     t = os.path.getmtime(lib)
     srcs = [os.path.join(build.CSRC, f) for f in os.listdir(build.CSRC)]
     srcs += [os.path.join(build.INCLUDE, f) for f in os.listdir(build.INCLUDE)]
-    srcs.append(os.path.abspath(build.__file__))
+    srcs += [os.path.abspath(build.__file__), os.path.join(os.path.dirname(build.__file__), "build.py")]
     return any(os.path.getmtime(s) > t for s in srcs)
 
 
 @pytest.mark.slow
 def test_host_code_under_sanitizers():
-    from paper_2607_06834_amd import build
+    from paper_2607_06834_amd import build_asan as build
     lib = build.ASAN_LIB
     if _stale(lib, build):
         build.build_host_asan()
