@@ -15,19 +15,6 @@ namespace {
 
 using pt::Dev;
 
-// Sum of K <= 32 strided values in index order, with every load issued
-// before the first add (the loads are independent; a plain loop would wait
-// for each one in turn).
-__device__ inline double sum32(const double *p, size_t stride, int K) {
-  double v[32];
-#pragma unroll
-  for (int k = 0; k < 32; ++k) v[k] = (k < K) ? p[(size_t)k * stride] : 0.0;
-  double s = 0.0;
-#pragma unroll
-  for (int k = 0; k < 32; ++k) s += v[k];
-  return s;
-}
-
 // a gradient entry computed by this thread: stored (overwritten with zero
 // below if the chain's status turns out nonzero) and tested for finiteness
 __device__ inline void gtheta_or_u(double *gc, int i, double g, bool &fin) {
@@ -44,6 +31,8 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
                                                   pt::Kick kick, int has_kick) {
   __shared__ double red[kFinW], red2[kFinW];
   __shared__ int ired[kFinW];
+  // this kernel's gradient entries (theta, then the timing model), for the kick
+  __shared__ double g_s[4 * PTAFS_MAX_PSR + 10 + 3 * PTAFS_MAX_PSR];
   const int c = blockIdx.x;
   const int t = threadIdx.x;
   const double *xc = x + (size_t)c * D.d;
@@ -60,12 +49,20 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
   const int nseg = max(1, min(pt::kSpecSeg, kmax));
   const int32_t *fo = D.flag_out + (size_t)c * (kmax + pt::kSpecSeg);
   const int pre = D.st_pre[c];
-  int fl = 0;
-  for (int k = t; k < kmax; k += kFinT) fl |= D.flag_k[(size_t)c * kmax + k];
-  for (int k = t; k < D.nf_gw; k += kFinT) fl |= D.flag_dense[(size_t)c * D.nf_gw + k] | fo[k];
-  for (int k = t; k < nseg; k += kFinT) fl |= fo[kmax + k];
-  // every theta entry, timing-model entry and pulsar has one thread
+  // every frequency, segment, theta entry, timing-model entry and pulsar has
+  // one thread
   static_assert(4 * PTAFS_MAX_PSR + 10 <= kFinT && 3 * PTAFS_MAX_PSR <= kFinT, "one entry per thread");
+  static_assert(PTAFS_MAX_HARM <= kFinT && pt::kSpecSeg <= kFinT, "one frequency per thread");
+  // the condition flags: clamped indices under uniform conditions, selected
+  // when combined, so that no load waits for another
+  int f1 = 0, f2 = 0, f3 = 0, f4 = 0;
+  if (kmax > 0) f1 = D.flag_k[(size_t)c * kmax + min(t, kmax - 1)];
+  if (D.nf_gw > 0) {
+    const int k = min(t, D.nf_gw - 1);
+    f2 = D.flag_dense[(size_t)c * D.nf_gw + k];
+    f3 = fo[k];
+  }
+  f4 = fo[kmax + min(t, nseg - 1)];
   // the timing-model gradient's inputs and the chi^2 partial first (their
   // loads overlap those below)
   double ub = 0.0, ux = 0.0;
@@ -75,6 +72,27 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
     ux = xc[D.off_u + t];
   }
   double ch = (t < n) ? D.chi_p[(size_t)t * cp + c] : 0.0;
+  // the per-frequency parts of this thread's power-law entry (the common
+  // process's two, then red noise and DM per pulsar and component; the CW's
+  // follow below), loaded here, summed in frequency order after the norm
+  const int n_pl = D.has_cw ? D.off_cw : D.n_theta;
+  int K = 0;
+  double tv[32];
+  if (t < n_pl) {
+    const double *src;
+    if (t < D.off_rn) {
+      src = D.dth_k + (size_t)c * D.ka * 2 + (t - D.off_gw);
+      K = D.ka;
+    } else if (t < D.off_dm) {
+      src = pt::drn_at(D, c, (t - D.off_rn) >> 1, 0) + ((t - D.off_rn) & 1);
+      K = D.ka;
+    } else {
+      src = pt::ddm_at(D, c, (t - D.off_dm) >> 1, 0) + ((t - D.off_dm) & 1);
+      K = D.nf_dm;
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) tv[k] = src[2 * min(k, K - 1)];
+  }
   // finiteness and squared norm of (u, z, z_dm): twelve elements per thread
   // with their loads issued together (one pass up to 12288 of them)
   double zz = 0.0;
@@ -97,55 +115,73 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
   }
   // hyper-parameter gradient entries (frequency sums in order) and the
   // timing model, d/du = sigma_b M^T g - u
+  int fl = (t < kmax ? f1 : 0) | (t < D.nf_gw ? f2 | f3 : 0) | (t < nseg ? f4 : 0);
   bool fin = true;
-  for (int e = t; e < D.n_theta; e += kFinT) {
+  if (t < n_pl) {
     double s = 0.0;
-    if (D.nf_gw > 0 && e >= D.off_gw && e < D.off_gw + 2)
-      s = sum32(D.dth_k + (size_t)c * D.ka * 2 + (e - D.off_gw), 2, D.ka);
-    else if (D.nf_rn > 0 && e >= D.off_rn && e < D.off_rn + 2 * n)
-      s = sum32(pt::drn_at(D, c, (e - D.off_rn) >> 1, 0) + ((e - D.off_rn) & 1), 2, D.ka);
-    else if (D.nf_dm > 0 && e >= D.off_dm && e < D.off_dm + 2 * n)
-      s = sum32(pt::ddm_at(D, c, (e - D.off_dm) >> 1, 0) + ((e - D.off_dm) & 1), 2, D.nf_dm);
-    else if (D.has_cw && e >= D.off_cw && e < D.off_cw + 8) {
-      // over the pulsars in order, eight loads at a time
-      const double *q = D.cw_p + (size_t)(e - D.off_cw) * cp + c;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) s += (k < K) ? tv[k] : 0.0;
+    gtheta_or_u(gc, t, s, fin);
+    g_s[t] = s;
+  } else if (D.has_cw && t < D.n_theta) {
+    // the CW parameters' entries, over the pulsars in order, eight loads at a time
+    const double *q = D.cw_p + (size_t)(t - D.off_cw) * cp + c;
+    double s = 0.0;
 #pragma unroll 1
-      for (int p0 = 0; p0 < n; p0 += 8) {
-        double v[8];
+    for (int p0 = 0; p0 < n; p0 += 8) {
+      double v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = (p0 + k < n) ? q[(size_t)(p0 + k) * 8 * cp] : 0.0;
+      for (int k = 0; k < 8; ++k) v[k] = (p0 + k < n) ? q[(size_t)(p0 + k) * 8 * cp] : 0.0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s += v[k];
-      }
+      for (int k = 0; k < 8; ++k) s += v[k];
     }
-    gtheta_or_u(gc, e, s, fin);
+    gtheta_or_u(gc, t, s, fin);
+    g_s[t] = s;
   }
-  if (t < 3 * n) gtheta_or_u(gc, D.off_u + t, D.sigma_b * ub - ux, fin);
+  if (t < 3 * n) {
+    const double gu = D.sigma_b * ub - ux;
+    gtheta_or_u(gc, D.off_u + t, gu, fin);
+    g_s[D.off_u + t] = gu;
+  }
+  // Inside a trajectory, the kick's operands for the first BK elements per
+  // thread (all of them up to BK kFinT = 9216 coordinates): p, x, M^-1 and
+  // the gradient entries the earlier kernels wrote (from off_z on; this
+  // kernel's own come from g_s).  Issued here, with clamped in-range
+  // addresses and no branch between them, they arrive while the reductions
+  // below wait.
+  constexpr int BK = 9;
+  double kp[BK], kg[BK], kx[BK], km[BK];
+  if (has_kick) {
+    const double *pw = kick.p + (size_t)c * D.d, *xw = kick.x + (size_t)c * D.d;
+    const int last = D.d - 1;
+#pragma unroll
+    for (int b = 0; b < BK; ++b) {
+      const int ic = min(t + kFinT * b, last);
+      kp[b] = pw[ic];
+      kx[b] = xw[ic];
+      kg[b] = gc[max(ic, D.off_z)];
+      km[b] = kick.inv_mass ? kick.inv_mass[ic] : 1.0;
+    }
+  }
   // ---- the reductions: one OR (flags, and the two finiteness tests as
   //      bits), two fixed-order sums
   constexpr int kBitInput = 1 << 28, kBitOutput = 1 << 29;
   {
-    // all three in one pass: wave reductions, one barrier, then the waves'
-    // values in wave order (the same sums as pt::block_sum)
-    int f = pt::wave_or(fl | (fin_in ? 0 : kBitInput) | (fin ? 0 : kBitOutput));
+    // all three in one pass: wave reductions, one barrier, then in every
+    // wave lane i takes wave i's values and a second wave reduction combines
+    // them (a fixed order, in three registers)
+    const int f = pt::wave_or(fl | (fin_in ? 0 : kBitInput) | (fin ? 0 : kBitOutput));
     const double z = pt::wave_sum(zz), h = pt::wave_sum(ch);
-    const int w = t >> 6;
-    if ((t & 63) == 0) {
+    const int w = t >> 6, ln = t & 63;
+    if (ln == 0) {
       ired[w] = f;
       red[w] = z;
       red2[w] = h;
     }
     __syncthreads();
-    f = ired[0];
-    zz = red[0];
-    ch = red2[0];
-#pragma unroll
-    for (int i = 1; i < kFinW; ++i) {
-      f |= ired[i];
-      zz += red[i];
-      ch += red2[i];
-    }
-    fl = f;
+    fl = pt::wave_or(ln < kFinW ? ired[ln] : 0);
+    zz = pt::wave_sum(ln < kFinW ? red[ln] : 0.0);
+    ch = pt::wave_sum(ln < kFinW ? red2[ln] : 0.0);
   }
 
   // ---- per-chain condition, in the order: prior box, non-finite input,
@@ -174,11 +210,24 @@ __global__ __launch_bounds__(kFinT) void k_finalize(Dev D, const double *x, doub
     status[c] = st;
   }
   if (has_kick) {
-    __syncthreads();   // the workgroup's gradient stores are visible to all its threads
     if (t == 0 && kick.n_invalid && st != 0) kick.n_invalid[c] += 1;
     double *xw = kick.x + (size_t)c * D.d, *pw = kick.p + (size_t)c * D.d;
+#pragma unroll
+    for (int b = 0; b < BK; ++b) {
+      const int i = t + kFinT * b;
+      if (i >= D.d) continue;
+      // (the gradient is zero when the status is nonzero)
+      const double g = st != 0 ? 0.0 : (i < D.off_z ? g_s[i] : kg[b]);
+      const double pi = kp[b] + kick.eps * g;
+      pw[i] = pi;
+      xw[i] = kx[b] + kick.eps * km[b] * pi;
+    }
+    if (D.d <= BK * kFinT) return;
+    // the rest, beyond off_z: the gradient as stored (zeros when the status
+    // is nonzero)
+    __syncthreads();   // the workgroup's gradient stores are visible to all its threads
     constexpr int B = 12;  // elements per thread whose loads are issued together
-    for (int i0 = t; i0 < D.d; i0 += kFinT * B) {
+    for (int i0 = BK * kFinT + t; i0 < D.d; i0 += kFinT * B) {
       double pv[B], gv[B], xv[B], iv[B];
 #pragma unroll
       for (int b = 0; b < B; ++b) {

@@ -180,3 +180,46 @@ def test_hmc_cfg1_200_trajectories_vs_oracle(api):
     assert 0 < acc.sum() < C * n_traj
     np.testing.assert_allclose(S, OS, rtol=1e-7, atol=1e-9)
     np.testing.assert_allclose(lp, olp, rtol=1e-9)
+
+
+@pytest.mark.parametrize("n_psr", [67, 80, 128])
+def test_hmc_fused_kick_equals_plain_leapfrog(api, n_psr):
+    """The leapfrog kick and drift fused into the assembly kernel (and the
+    trajectory's first and last half kicks) against the oracle sampler's
+    plain leapfrog driven by the library's own eager log p and gradient, at
+    coordinate counts around and beyond the assembly's per-chain preload
+    (d = 8511 at 67 pulsars, 10162 at 80, 16258 at 128; RN 30, HD 14, DM 30),
+    with a non-uniform inverse mass."""
+    counts = [24 + (7 * I) % 11 for I in range(n_psr)]
+    ds = synth.make_array(200 + n_psr, n_psr, counts, 12 * synth.YEAR_S,
+                          backends_per_psr=[1 + I % 2 for I in range(n_psr)],
+                          nu_range=(0.4e9, 2.0e9), nf_rn=30, nf_gw=14, nf_dm=30)
+    lay = model.Prepared(ds).lay
+    C = 4
+    th = synth.injected_theta(ds, 11, rn=(-14.0, 3.5), dm=(-14.0, 3.5))
+    X0 = synth.random_points(ds, C, 12, theta=th, theta_jitter=0.05)
+    X0[:, lay.u:] = np.random.default_rng(13).standard_normal((C, lay.d - lay.u))
+    # the whitened timing-model coordinates are pinned by the data: start
+    # them at 0 with a small inverse mass (a step the oracle sampler accepts)
+    X0[:, lay.u:lay.z] = 0.0
+    im = np.random.default_rng(14).uniform(0.5, 1.5, lay.d)
+    im[: lay.n_theta] = 1e-4
+    im[lay.u:lay.z] = 1e-8
+    g = api.Dataset(ds)
+
+    def lpg(Xb):
+        lp, gr, st = g.ptafs_logp_grad(torch.tensor(Xb, device="cuda"))
+        torch.cuda.synchronize()
+        return lp.cpu().numpy(), gr.cpu().numpy()
+
+    ox, olp, ogr, oacc, OS = hmc.run(lpg, X0, n_traj=3, n_leapfrog=5, eps=0.05, seed=515, traj0=1,
+                                     inv_mass=im, keep_samples=True)
+    g.close()
+    x, lp, gr, acc, S = gpu_hmc(api, ds, X0, n_traj=3, L=5, eps=0.05, seed=515, inv_mass=im, traj0=1)
+    print(f"[hmc fused kick {n_psr} psr, d={lay.d}] accepted {acc.sum()}/{3 * C}", flush=True)
+    assert lay.d == {67: 8511, 80: 10162, 128: 16258}[n_psr]
+    np.testing.assert_array_equal(acc, oacc)
+    assert acc.sum() > 0
+    np.testing.assert_allclose(S, OS, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(lp, olp, rtol=1e-10)
+    np.testing.assert_allclose(gr, ogr, rtol=1e-8, atol=1e-9 * np.abs(ogr).max())
