@@ -189,10 +189,17 @@ int ptafs_logp_grad_plain(ptafs_dataset *ds, int32_t n_chains, const double *x, 
 /*
  * Tuning of the batched TOA pass.  tiles_per_chunk: 16-TOA tiles a workgroup
  * covers (ragged pulsars are cut into chunks of this many tiles);
- * waves_per_block: 1, 2 or 4 waves splitting a chunk; xcd_map: 1 places the
- * chain blocks of one chunk on the same XCD.  Takes effect on the next call; a
- * new chunk length waits on the host for the data set's own previous work and
- * rebuilds the chunk table on the library's stream.
+ * waves_per_block: 1, 2 or 4 waves splitting a chunk; xcd_map: 0 leaves the
+ * work items in launch order, 1 places the chain blocks of one chunk on the
+ * same XCD, 2 (balanced) also gives every compute unit chunks of near-equal
+ * total TOA count when the launch is one full round of resident workgroups
+ * (chunks x chain blocks a multiple of the compute units, at most 8 per unit,
+ * up to 256 chains; other launches fall back to 1); any other value is
+ * PTAFS_E_ARG.  The placement moves no arithmetic: results are bit-identical
+ * across xcd_map values at a given chunk length and waves per workgroup.
+ * Takes effect on the next call; a new chunk length waits on the host for the
+ * data set's own previous work and rebuilds the chunk table on the library's
+ * stream.
  */
 int ptafs_set_tuning(ptafs_dataset *ds, int32_t tiles_per_chunk, int32_t waves_per_block,
                      int32_t xcd_map);

@@ -1,8 +1,9 @@
 """Autotuner for the batched TOA pass.
 
 Times each candidate launch shape of the TOA pass (16-TOA tiles per chunk,
-waves per workgroup, XCD-aware placement) on the caller's data set and chain
-count with the library's event-timed stage profiler, and keeps the fastest.
+waves per workgroup, placement: launch order, XCD-grouped or balanced) on
+the caller's data set and chain count with the library's event-timed stage
+profiler, and keeps the fastest.
 The choice is cached per data-set shape (pulsar count, TOA count, basis sizes,
 chain count) so that a request always runs with the same tuning, which keeps
 its results reproducible: the reduction order depends only on the tuning.
@@ -49,10 +50,11 @@ def serving_tuning(toa_offsets, n_chains, n_cu):
     request's bits, cannot depend on what else runs on the device): one-wave
     workgroups, XCD-aware placement, and the chunk length at which the
     request's waves fill one round of the device at two waves per SIMD (the
-    one-wave form's occupancy), kept between 4 and 32 tiles."""
+    one-wave form's occupancy), kept between 4 and 32 tiles; the balanced
+    placement where that launch fills whole rounds (else the XCD-grouped one)."""
     fit = round_fitting_tpcs(toa_offsets, n_chains, n_cu, wpb=1, rounds=(1,), waves_per_simd=(2,))
     tpc = fit[0] if fit else 32
-    return (int(min(32, max(4, tpc))), 1, 1)
+    return (int(min(32, max(4, tpc))), 1, 2)
 
 
 def shape_key(ds, n_chains):
@@ -71,7 +73,8 @@ def tune(ds, x, reps=5, candidates=None, use_cache=True):
         fit = [(tpc, 1) for tpc in round_fitting_tpcs(ds.toa_offsets, x.shape[0], n_cu)]
         fit += [(tpc, 4) for tpc in round_fitting_tpcs(ds.toa_offsets, x.shape[0], n_cu, wpb=4,
                                                         waves_per_simd=(2, 3))]
-        candidates = CANDIDATES + tuple((tpc, wpb, xcd) for tpc, wpb in fit for xcd in (0, 1)
+        # (round-fitting launches also with the balanced placement, xcd 2)
+        candidates = CANDIDATES + tuple((tpc, wpb, xcd) for tpc, wpb in fit for xcd in (0, 1, 2)
                                         if (tpc, wpb, xcd) not in CANDIDATES)
     key = shape_key(ds, x.shape[0])
     if use_cache and key in _cache:

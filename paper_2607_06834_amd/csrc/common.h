@@ -137,7 +137,11 @@ struct Dev {
   // chunk table of the batched TOA pass
   int n_chunks, tiles_per_chunk;
   const int32_t *chunk_psr, *chunk_begin, *chunk_end, *psr_chunk0;
+  // work item (chunk * n_cb + chain block) of each TOA-pass workgroup under
+  // the balanced placement, or null (then the XCD-grouped order, or none)
+  const int32_t *wg_map;
   int n_cu;                    // compute units of the device
+  int n_xcd;                   // their XCDs (workgroups are dealt to them round-robin)
   // call
   int n_chains, c_pad, n_cb;
   // workspace

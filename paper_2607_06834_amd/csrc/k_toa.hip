@@ -71,7 +71,8 @@ void k_toa_mfma(Dev D, int xcd_map) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int col = lane & 15, q = lane >> 4;
   int wg = blockIdx.x;
-  if (xcd_map) wg = xcd_remap(wg, gridDim.x);
+  if (D.wg_map) wg = D.wg_map[blockIdx.x];
+  else if (xcd_map) wg = xcd_remap(wg, gridDim.x);
   const int chunk = wg / D.n_cb, cb = wg - chunk * D.n_cb;
   const int p = D.chunk_psr[chunk];
   const int tb = D.chunk_begin[chunk], te = D.chunk_end[chunk];

@@ -34,6 +34,9 @@ struct ptafs_dataset {
   int32_t *d_chunk = nullptr;
   std::vector<int32_t> chunk_host;    // source of the last chunk-table upload
   std::vector<int> psr_nchunks;
+  // offset in the chunk table of the balanced placement for n_cb chain
+  // blocks (index n_cb <= kMaxMapCb), or -1
+  std::vector<int> wgmap_off;
   int n_chunks = 0;
   // workspace
   void *ws = nullptr;
@@ -172,7 +175,88 @@ WsLayout ws_layout(const pt::Dev &B, int c_pad, int n_chunks) {
 
 int cpad_of(int n_chains) { return ((n_chains + 15) / 16) * 16; }
 
-// Split every pulsar into chunks of about `tpc` 16-TOA tiles (tile-aligned).
+constexpr int kMaxMapCb = 16;   // chain blocks (256 chains) up to which placements are built
+
+// Balanced placement of the TOA pass's work items on the compute units.  When
+// the whole grid is resident at once, workgroup b runs on XCD b % n_xcd and
+// shares its compute unit with b + n_cu, b + 2 n_cu, ... (the dispatcher's
+// order, measured), and a compute unit's time is set by the TOAs of the
+// chunks it holds.  The chunks go into bundles of k = workgroups per compute
+// unit with near-equal TOA sums (largest first, each to the lightest bundle
+// with room); a bundle's chain blocks take n_cb compute units of one XCD, one
+// chain block each, so that every compute unit holds one bundle and the n_cb
+// workgroups that read a chunk's TOAs share an L2.  The result only moves
+// work between workgroups: each work item, and the order in which its
+// partials are reduced, is the same under any placement.  Returns false when
+// the grid does not have this shape.
+bool balanced_map(const std::vector<int32_t> &cbg, const std::vector<int32_t> &cen, int n_cb, int n_cu,
+                  int n_xcd, std::vector<int32_t> &map) {
+  const int nc = (int)cbg.size();
+  const long G = (long)nc * n_cb;
+  if (nc == 0 || n_cb < 1 || n_cu <= 0 || n_xcd <= 0 || n_cu % n_xcd || G % n_cu) return false;
+  const int k = (int)(G / n_cu), m = n_cu / n_xcd;   // workgroups per CU, CUs per XCD
+  if (k < 1 || k > 8 || m % n_cb) return false;
+  const int nb = n_cu / n_cb;                         // bundles, k chunks each
+  if ((long)nb * k != nc) return false;
+  std::vector<int> ord(nc);
+  for (int c = 0; c < nc; ++c) ord[c] = c;
+  std::stable_sort(ord.begin(), ord.end(),
+                   [&](int a, int b) { return cen[a] - cbg[a] > cen[b] - cbg[b]; });
+  std::vector<long> load(nb, 0);
+  std::vector<int> cnt(nb, 0), memb((size_t)nb * k);
+  for (int c : ord) {
+    int best = -1;
+    for (int b = 0; b < nb; ++b)
+      if (cnt[b] < k && (best < 0 || load[b] < load[best])) best = b;
+    memb[(size_t)best * k + cnt[best]++] = c;
+    load[best] += cen[c] - cbg[c];
+  }
+  // then swap a chunk of the heaviest bundle with a lighter one of another
+  // bundle (lightest bundles first) while that lowers the heaviest load
+  auto sz = [&](int c) { return (long)(cen[c] - cbg[c]); };
+  std::vector<int> by_load(nb);
+  for (int it = 0; it < 4 * nc; ++it) {
+    const int hb = (int)(std::max_element(load.begin(), load.end()) - load.begin());
+    for (int b = 0; b < nb; ++b) by_load[b] = b;
+    std::stable_sort(by_load.begin(), by_load.end(), [&](int a, int b) { return load[a] < load[b]; });
+    bool moved = false;
+    for (int ob : by_load) {
+      if (ob == hb) continue;
+      for (int i = 0; i < k && !moved; ++i)
+        for (int j = 0; j < k && !moved; ++j) {
+          int &a = memb[(size_t)hb * k + i], &b = memb[(size_t)ob * k + j];
+          const long d = sz(a) - sz(b);
+          if (d > 0 && std::max(load[hb] - d, load[ob] + d) < load[hb]) {
+            std::swap(a, b);
+            load[hb] -= d;
+            load[ob] += d;
+            moved = true;
+          }
+        }
+      if (moved) break;
+    }
+    if (!moved) break;
+  }
+  map.assign((size_t)G, -1);
+  for (int b = 0; b < nb; ++b) {
+    const int x = b % n_xcd, r = b / n_xcd;
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j < n_cb; ++j) {
+        const long w = (long)i * n_cu + (long)(r * n_cb + j) * n_xcd + x;
+        map[(size_t)w] = memb[(size_t)b * k + i] * n_cb + j;
+      }
+  }
+  std::vector<char> seen((size_t)G, 0);   // a permutation of the work items
+  for (int32_t v : map) {
+    if (v < 0 || v >= G || seen[(size_t)v]) return false;
+    seen[(size_t)v] = 1;
+  }
+  return true;
+}
+
+// Split every pulsar into chunks of about `tpc` 16-TOA tiles (tile-aligned),
+// then append the balanced placements of the chain-block counts whose grid
+// has their shape.
 void build_chunks(ptafs_dataset *ds, std::vector<int32_t> &tab) {
   const int n = ds->base.n_psr;
   const int tpc = std::max(1, ds->tiles_per_chunk);
@@ -199,6 +283,13 @@ void build_chunks(ptafs_dataset *ds, std::vector<int32_t> &tab) {
   tab.insert(tab.end(), cbg.begin(), cbg.end());
   tab.insert(tab.end(), cen.begin(), cen.end());
   tab.insert(tab.end(), first.begin(), first.end());
+  ds->wgmap_off.assign(kMaxMapCb + 1, -1);
+  std::vector<int32_t> map;
+  for (int ncb = 1; ncb <= kMaxMapCb; ++ncb)
+    if (balanced_map(cbg, cen, ncb, ds->base.n_cu, ds->base.n_xcd, map)) {
+      ds->wgmap_off[ncb] = (int)tab.size();
+      tab.insert(tab.end(), map.begin(), map.end());
+    }
 }
 
 // A captured trajectory graph holds the addresses of the chunk table, the
@@ -266,6 +357,10 @@ pt::Dev make_dev(const ptafs_dataset *ds, int n_chains, void *ws) {
   D.n_chains = n_chains;
   D.c_pad = cpad_of(n_chains);
   D.n_cb = D.c_pad / 16;
+  D.wg_map = nullptr;
+  if (ds->xcd_map == 2 && D.n_cb <= kMaxMapCb && (int)ds->wgmap_off.size() > D.n_cb &&
+      ds->wgmap_off[D.n_cb] >= 0)
+    D.wg_map = ds->d_chunk + ds->wgmap_off[D.n_cb];
   const WsLayout L = ws_layout(ds->base, D.c_pad, ds->n_chunks);
   char *w = static_cast<char *>(ws);
   D.coef_rn = reinterpret_cast<double *>(w + L.coef_rn);
@@ -571,7 +666,8 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
   hipStream_t s = (hipStream_t)stream;
   pt::Dev &B = ds->base;
   B = plan_view;
-  if (hipDeviceGetAttribute(&B.n_cu, hipDeviceAttributeMultiprocessorCount, ds->device) != hipSuccess) {
+  if (hipDeviceGetAttribute(&B.n_cu, hipDeviceAttributeMultiprocessorCount, ds->device) != hipSuccess ||
+      hipDeviceGetAttribute(&B.n_xcd, hipDeviceAttributeNumberOfXccs, ds->device) != hipSuccess) {
     free_all(ds);
     return PTAFS_E_HIP;
   }
@@ -780,10 +876,11 @@ int ptafs_set_tuning(ptafs_dataset *ds, int32_t tiles_per_chunk, int32_t waves_p
                      int32_t xcd_map) {
   if (!ds || tiles_per_chunk < 1 || tiles_per_chunk > 4096) return PTAFS_E_ARG;
   if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4) return PTAFS_E_ARG;
+  if (xcd_map < 0 || xcd_map > 2) return PTAFS_E_ARG;
   if (tiles_per_chunk != ds->tiles_per_chunk) ds->chunks_dirty = true;
   ds->tiles_per_chunk = tiles_per_chunk;
   ds->wpb = waves_per_block;
-  ds->xcd_map = xcd_map ? 1 : 0;
+  ds->xcd_map = xcd_map;
   PT_TRY(hipSetDevice(ds->device));
   return ensure_chunks(ds, ds->aux);
 }

@@ -51,7 +51,7 @@ def test_serving_tuning_is_a_function_of_shape():
     ds = synth.cfg1()
     a = autotune.serving_tuning(ds["toa_offsets"], 16, 256)
     b = autotune.serving_tuning(ds["toa_offsets"], 16, 256)
-    assert a == b and a[1] == 1 and a[2] == 1 and 4 <= a[0] <= 32
+    assert a == b and a[1] == 1 and a[2] == 2 and 4 <= a[0] <= 32
     big = synth.serving_request(505)
     t = autotune.serving_tuning(big["toa_offsets"], 16, 256)
     assert 4 <= t[0] <= 32

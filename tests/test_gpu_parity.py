@@ -263,8 +263,8 @@ _CFG2_REF = {}
 
 # launch configurations the autotuner picks for the benchmark: 16-tile chunks,
 # one round of one-wave workgroups (with and without the XCD-aware map),
-# four-wave workgroups sharing the panels
-@pytest.mark.parametrize("tuning", [(16, 1, 1), (33, 1, 1), (33, 1, 0), (96, 4, 1)])
+# four-wave workgroups sharing the panels (XCD-grouped and balanced placement)
+@pytest.mark.parametrize("tuning", [(16, 1, 1), (33, 1, 1), (33, 1, 0), (96, 4, 1), (96, 4, 2)])
 def test_cfg2_full_size_sampled(api, tuning):
     """The 67-pulsar, 250k-TOA workload with 64 chains in the launch
     configurations the benchmark times; the oracle checks one chain of every
@@ -278,6 +278,33 @@ def test_cfg2_full_size_sampled(api, tuning):
         _CFG2_REF["ref"] = model.logp_grad(model.Prepared(ds), X[idx])
     check(ds, X[idx], got, ref=_CFG2_REF["ref"], idx=idx)
     assert np.all(got[2] == 0)
+    if tuning[:2] == (96, 4):
+        # the placement moves no arithmetic: every chain bit-identical across maps
+        if tuning[:2] in _CFG2_REF:
+            for u, v in zip(got, _CFG2_REF[tuning[:2]]):
+                np.testing.assert_array_equal(u, v)
+        _CFG2_REF[tuning[:2]] = got
+
+
+@pytest.mark.parametrize("n_chains", [64, 256])
+def test_balanced_placement_bit_identical(api, n_chains):
+    """Balanced placement of the TOA pass (tuning xcd_map 2) on a ragged array
+    cut into exactly 64 chunks (16 pulsars of 193-256 TOAs, 4-tile chunks), so
+    that chunks x chain blocks fill whole rounds of the compute units and the
+    placement table is used: bit-identical to the XCD-grouped and the plain
+    launch order for every chain, and equal to the oracle on sampled chains."""
+    n = 16
+    counts = [193 + (37 * i) % 64 for i in range(n)]
+    ds = synth.make_array(71, n, counts, 9 * synth.YEAR_S, backends_per_psr=[1 + i % 3 for i in range(n)],
+                          nu_range=(0.4e9, 2e9), nf_rn=5, nf_gw=3, nf_dm=2)
+    th = synth.injected_theta(ds, 72)
+    X = synth.random_points(ds, n_chains, 73, theta=th, theta_jitter=0.3)
+    outs = [run(api, ds, X, tuning=(4, 1, xm)) for xm in (2, 1, 0)]
+    for other in outs[1:]:
+        for u, v in zip(outs[0], other):
+            np.testing.assert_array_equal(u, v)
+    idx = np.array([0, 17, n_chains - 1])
+    check(ds, X[idx], outs[0], idx=idx)
 
 
 def test_status_not_positive_definite_forced(api):
