@@ -1117,20 +1117,99 @@ __global__ __launch_bounds__(kFinT) void k_std_finalize(StdDev S, const double *
                                                          int32_t *__restrict__ status, ps::StdKick kick,
                                                          int has_kick) {
   __shared__ double red[kFinW];
-  __shared__ int sb[kFinW][4];
+  __shared__ int sb[kFinW][1];
   __shared__ double drho_tot[ps::kMaxRhoK];
   __shared__ double cwp[kFinW][8];
   const int tid = threadIdx.x, c = blockIdx.x, wv = tid >> 6;
   const int n = S.n_psr;
   const double *xc = x + (size_t)c * S.d;
   double *gc = grad + (size_t)c * S.d;
-  // input checks: the box on theta, finiteness of z (four entries a step)
+  // Phase one: every load of the input checks, the flags and the log p parts
+  // is issued before any is used (fixed batches per thread with clamped
+  // in-range addresses, selected when consumed; a remainder loop beyond the
+  // batch), then they are combined in the same per-thread order.
   int bad_box = 0, bad_in = 0;
-  for (int i = tid; i < S.n_theta; i += kFinT) {
+  // the box on theta (two entries a thread per pass)
+  constexpr int BB = 2;
+  double bxv[BB], blo[BB], bhi[BB];
+  {
+    const int lt = max(S.n_theta - 1, 0);
+#pragma unroll
+    for (int u = 0; u < BB; ++u) {
+      const int i = min(tid + u * kFinT, lt);
+      bxv[u] = S.n_theta > 0 ? xc[i] : 0.0;
+      blo[u] = S.n_theta > 0 ? S.prior_lo[i] : 0.0;
+      bhi[u] = S.n_theta > 0 ? S.prior_hi[i] : 0.0;
+    }
+  }
+  // finiteness of z (eight entries a thread per pass)
+  constexpr int BZ = 8;
+  double zv[BZ];
+#pragma unroll
+  for (int u = 0; u < BZ; ++u) zv[u] = xc[min(S.n_theta + tid + u * kFinT, S.d - 1)];
+  // factorisation flags and the log p parts of the pulsars (one a thread)
+  int fl = 0;
+  double lp = 0.0;
+  int f1 = 0, fs = 0, f2 = 0;
+  double l0 = 0.0, l1 = 0.0, q0 = 0.0, q1 = 0.0;
+  {
+    const int i = min(tid, n - 1);
+    f1 = S.flag1[(size_t)c * n + i];
+    const double *o = S.lik + ((size_t)c * n + i) * 2;
+    l0 = o[0];
+    l1 = o[1];
+  }
+  // diagonal prior items: red-only frequencies and DM, or with split
+  // coefficients the whole pulsar-noise set (eight a thread per pass; the
+  // planner admits no data set without frequencies, so nd >= 1)
+  const int kt = S.ka + S.kdm, nd = n * kt;
+  constexpr int BD = 8;
+  int f3[BD];
+  double d0[BD], d1[BD];
+#pragma unroll
+  for (int u = 0; u < BD; ++u) {
+    const int i = min(tid + u * kFinT, nd - 1);
+    f3[u] = S.flag3[(size_t)c * nd + i];
+    const double *o = S.diag_q + ((size_t)c * nd + i) * 2;
+    d0[u] = o[0];
+    d1[u] = o[1];
+  }
+  // the loads that exist only with split coefficients or a common process
+  // come last (a wait their branches may take leaves the rest in flight)
+  if (S.split) fs = S.flag_s[(size_t)c * 2 * n + min(tid, 2 * n - 1)];
+  if (S.nf_gw > 0) {
+    const int k = min(tid, S.nf_gw - 1);
+    f2 = S.flag2[(size_t)c * S.ka + k];
+    const double *oq = S.quad_k + ((size_t)c * S.ka + k) * 2;
+    q0 = oq[0];
+    q1 = oq[1];
+  }
+  // d/drho_k in total: the explicit prior part plus the transform's part
+  // summed over the pulsars (with split coefficients the pulsars' rho parts
+  // are drho_p, and dD_rn holds their kappa parts only), 32 lanes per
+  // frequency, pulsars h, h + 32, ... in order
+  const int kr = tid >> 5, hr = tid & 31;
+  static_assert(4 * 32 >= PTAFS_MAX_PSR, "four passes of 32 lanes cover the pulsars");
+  double rv[4], re = 0.0;
+  if (S.nf_gw > 0) {
+    const double *src = S.split ? S.drho_p : S.dD_rn;
+    const int kc = min(kr, S.nf_gw - 1);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) rv[m] = src[((size_t)c * n + min(hr + 32 * m, n - 1)) * S.ka + kc];
+    re = S.drho_e[(size_t)c * S.ka + kc];
+  }
+  // the box and z checks
+#pragma unroll
+  for (int u = 0; u < BB; ++u)
+    if (tid + u * kFinT < S.n_theta && !(bxv[u] >= blo[u] && bxv[u] <= bhi[u])) bad_box = 1;
+  for (int i = tid + BB * kFinT; i < S.n_theta; i += kFinT) {
     const double v = xc[i];
     if (!(v >= S.prior_lo[i] && v <= S.prior_hi[i])) bad_box = 1;
   }
-  for (int i0 = S.n_theta + tid; i0 < S.d; i0 += 4 * kFinT) {
+#pragma unroll
+  for (int u = 0; u < BZ; ++u)
+    if (S.n_theta + tid + u * kFinT < S.d && !isfinite(zv[u])) bad_in = 1;
+  for (int i0 = S.n_theta + BZ * kFinT + tid; i0 < S.d; i0 += 4 * kFinT) {
     double v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) v[u] = (i0 + u * kFinT < S.d) ? xc[i0 + u * kFinT] : 0.0;
@@ -1147,43 +1226,40 @@ __global__ __launch_bounds__(kFinT) void k_std_finalize(StdDev S, const double *
     const double y = K1 * ((double)(S.md - 1) * S.td / S.md);
     bad_cw = !(y < 1.0);
   }
-  // factorisation flags and the log p parts
-  int fl = 0;
-  double lp = 0.0;
-  for (int i = tid; i < n; i += kFinT) {
-    fl |= S.flag1[(size_t)c * n + i];
-    const double *o = S.lik + ((size_t)c * n + i) * 2;
-    lp += o[0] + o[1];
+  if (tid < n) {
+    fl |= f1;
+    lp += l0 + l1;
   }
-  if (S.split)
-    for (int i = tid; i < 2 * n; i += kFinT) fl |= S.flag_s[(size_t)c * 2 * n + i];
-  for (int k = tid; k < S.nf_gw; k += kFinT) {
-    fl |= S.flag2[(size_t)c * S.ka + k];
-    const double *o = S.quad_k + ((size_t)c * S.ka + k) * 2;
-    lp += -0.5 * o[0] - (n * ps::kLn2Pi + o[1]);
+  if (S.split && tid < 2 * n) fl |= fs;
+  if (tid < S.nf_gw) {
+    fl |= f2;
+    lp += -0.5 * q0 - (n * ps::kLn2Pi + q1);
   }
-  // diagonal prior items: red-only frequencies and DM, or with split
-  // coefficients the whole pulsar-noise set
-  const int nd = n * (S.ka + S.kdm);
-  for (int i = tid; i < nd; i += kFinT) {
-    const int kk = i % (S.ka + S.kdm);
+#pragma unroll
+  for (int u = 0; u < BD; ++u) {
+    const int i = tid + u * kFinT;
+    const int kk = i % kt;
+    if (i < nd && (S.split ? (kk < S.nf_rn || kk >= S.ka) : kk >= S.nf_gw)) {
+      fl |= f3[u];
+      lp += -0.5 * d0[u] - (ps::kLn2Pi + d1[u]);
+    }
+  }
+  for (int i = tid + BD * kFinT; i < nd; i += kFinT) {
+    const int kk = i % kt;
     if (S.split ? (kk < S.nf_rn || kk >= S.ka) : kk >= S.nf_gw) {
       fl |= S.flag3[(size_t)c * nd + i];
       const double *o = S.diag_q + ((size_t)c * nd + i) * 2;
       lp += -0.5 * o[0] - (ps::kLn2Pi + o[1]);
     }
   }
-  // d/drho_k in total: the explicit prior part plus the transform's part summed
-  // over the pulsars (with split coefficients the pulsars' rho parts are
-  // drho_p, and dD_rn holds their kappa parts only), 32 lanes per frequency
-  {
-    const int k = tid >> 5, h = tid & 31;
-    const double *src = S.split ? S.drho_p : S.dD_rn;
+  // (d/drho_k: the pulsars' parts summed per frequency)
+  if (S.nf_gw > 0) {
     double s = 0.0;
-    if (k < S.nf_gw)
-      for (int J = h; J < n; J += 32) s += src[((size_t)c * n + J) * S.ka + k];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (kr < S.nf_gw && hr + 32 * m < n) s += rv[m];
     s = half_sum(s);
-    if (h == 0 && k < S.nf_gw) drho_tot[k] = S.drho_e[(size_t)c * S.ka + k] + s;
+    if (hr == 0 && kr < S.nf_gw) drho_tot[kr] = re + s;
   }
   // the CW parameters' parts, pulsars in order: lane groups of 8 per wave,
   // then the waves in order
@@ -1197,30 +1273,59 @@ __global__ __launch_bounds__(kFinT) void k_std_finalize(StdDev S, const double *
   }
   __syncthreads();
   // hyper-parameter gradient, 32 lanes per process instance (the common
-  // process, then red noise and DM per pulsar), lane k taking frequency k
-  for (int it = tid >> 5; it < 1 + 2 * n; it += kFinT / 32) {
-    const int k = tid & 31;
-    int proc, I, off, K;
-    if (it == 0) { proc = 0; I = 0; off = S.off_gw; K = S.nf_gw; }
-    else if (it <= n) { proc = 1; I = it - 1; off = S.off_rn + I * S.w_rn; K = S.nf_rn; }
-    else { proc = 2; I = it - 1 - n; off = S.off_dm + I * S.w_dm; K = S.kdm; }
-    if (K == 0) continue;
-    double v = 0.0;
-    if (k < K) {
-      double dd;
-      if (proc == 0) dd = drho_tot[k];
-      else if (proc == 1) dd = S.dkap_e[((size_t)c * n + I) * S.ka + k] + S.dD_rn[((size_t)c * n + I) * S.ka + k];
-      else dd = S.ddm_e[((size_t)c * n + I) * S.kdm + k] + S.dD_dm[((size_t)c * n + I) * S.kdm + k];
-      v = ps::spec_value(S, xc, proc, I, k) * dd;
+  // process, then red noise and DM per pulsar), lane k taking frequency k;
+  // a lane group's instances it = g, g + 32, ... take their loads together
+  {
+    constexpr int RB = (1 + 2 * PTAFS_MAX_PSR + kFinT / 32 - 1) / (kFinT / 32);
+    const int k = tid & 31, g = tid >> 5, n_it = 1 + 2 * n;
+    const int kl = min(k, PTAFS_MAX_HARM - 1);
+    double dd[RB], sa[RB], sb2[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int it = g + (kFinT / 32) * r;
+      int proc, I, off, K;
+      if (it == 0) { proc = 0; I = 0; off = S.off_gw; K = S.nf_gw; }
+      else if (it <= n) { proc = 1; I = it - 1; off = S.off_rn + I * S.w_rn; K = S.nf_rn; }
+      else { proc = 2; I = min(it - 1 - n, n - 1); off = S.off_dm + I * S.w_dm; K = S.kdm; }
+      const bool ok = it < n_it && k < K;
+      const int kc = ok ? k : 0;
+      dd[r] = 0.0;
+      if (ok && proc == 0) dd[r] = drho_tot[kc];
+      else if (ok && proc == 1)
+        dd[r] = S.dkap_e[((size_t)c * n + I) * S.ka + kc] + S.dD_rn[((size_t)c * n + I) * S.ka + kc];
+      else if (ok)
+        dd[r] = S.ddm_e[((size_t)c * n + I) * S.kdm + kc] + S.dD_dm[((size_t)c * n + I) * S.kdm + kc];
+      // the spectrum's inputs: theta_k (free spectrum) or (log10 A, gamma)
+      const int o1 = min(ok ? off + (S.free_spec ? kc : 0) : 0, S.d - 1);
+      sa[r] = xc[o1];
+      sb2[r] = S.free_spec ? 0.0 : xc[min(o1 + 1, S.d - 1)];
     }
-    if (S.free_spec) {
-      if (k < K) gc[off + k] = ps::kLn10 * v;
-    } else {
-      const double ga = half_sum(2.0 * ps::kLn10 * v);
-      const double gg = half_sum(k < K ? -S.lnfy[k] * v : 0.0);
-      if (k == 0) {
-        gc[off] = ga;
-        gc[off + 1] = gg;
+    const double lf = S.lnfy[kl];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int it = g + (kFinT / 32) * r;
+      if (it >= n_it) break;
+      int off, K;
+      if (it == 0) { off = S.off_gw; K = S.nf_gw; }
+      else if (it <= n) { off = S.off_rn + (it - 1) * S.w_rn; K = S.nf_rn; }
+      else { off = S.off_dm + (it - 1 - n) * S.w_dm; K = S.kdm; }
+      if (K == 0) continue;
+      double v = 0.0;
+      if (k < K) {
+        // the spectrum as spec_value forms it
+        const double sv = S.free_spec ? exp(ps::kLn10 * sa[r])
+                                      : exp(2.0 * ps::kLn10 * sa[r] - sb2[r] * lf + S.pl_c);
+        v = sv * dd[r];
+      }
+      if (S.free_spec) {
+        if (k < K) gc[off + k] = ps::kLn10 * v;
+      } else {
+        const double ga = half_sum(2.0 * ps::kLn10 * v);
+        const double gg = half_sum(k < K ? -lf * v : 0.0);
+        if (k == 0) {
+          gc[off] = ga;
+          gc[off + 1] = gg;
+        }
       }
     }
   }
@@ -1237,26 +1342,45 @@ __global__ __launch_bounds__(kFinT) void k_std_finalize(StdDev S, const double *
     const int bb = __any(bad_box), bi = __any(bad_in), bf = __any(fl != 0), bc = __any(bad_cw);
     if ((tid & 63) == 0) {
       red[wv] = v;
-      sb[wv][0] = bb;
-      sb[wv][1] = bi;
-      sb[wv][2] = bf;
-      sb[wv][3] = bc;
+      sb[wv][0] = bb | (bi << 1) | (bf << 2) | (bc << 3);
     }
     __syncthreads();
-    lp = 0.0;
-    bad_box = bad_in = fl = bad_cw = 0;
-    for (int w = 0; w < kFinW; ++w) {
-      lp += red[w];
-      bad_box |= sb[w][0];
-      bad_in |= sb[w][1];
-      fl |= sb[w][2];
-      bad_cw |= sb[w][3];
+    // lane i of every wave takes wave i's values, then a second wave
+    // reduction (a fixed tree; two registers instead of all waves' values)
+    const int ln = tid & 63;
+    double t = ln < kFinW ? red[ln] : 0.0;
+    int f = ln < kFinW ? sb[ln][0] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      t += __shfl_xor(t, o, 64);
+      f |= __shfl_xor(f, o, 64);
     }
+    lp = t;
+    bad_box = f & 1;
+    bad_in = (f >> 1) & 1;
+    fl = (f >> 2) & 1;
+    bad_cw = (f >> 3) & 1;
   }
   lp += S.prior_const;
   // output finiteness (the theta entries written above by other threads)
+  // and, inside a trajectory, the kick's operands: loaded together, nine
+  // entries a thread (every coordinate up to 9216), the rest after
+  constexpr int BK = 9;
+  double gv[BK], pv[BK], xv[BK], mv[BK];
+  double *xw = kick.x + (size_t)c * S.d, *pw = kick.p + (size_t)c * S.d;
+#pragma unroll
+  for (int u = 0; u < BK; ++u) {
+    const int i = min(tid + u * kFinT, S.d - 1);
+    gv[u] = gc[i];
+    pv[u] = has_kick ? pw[i] : 0.0;
+    xv[u] = has_kick ? xw[i] : 0.0;
+    mv[u] = (has_kick && kick.inv_mass) ? kick.inv_mass[i] : 1.0;
+  }
   int nonfin = !isfinite(lp);
-  for (int i0 = tid; i0 < S.d; i0 += 4 * kFinT) {
+#pragma unroll
+  for (int u = 0; u < BK; ++u)
+    if (tid + u * kFinT < S.d && !isfinite(gv[u])) nonfin = 1;
+  for (int i0 = BK * kFinT + tid; i0 < S.d; i0 += 4 * kFinT) {
     double v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) v[u] = (i0 + u * kFinT < S.d) ? gc[i0 + u * kFinT] : 0.0;
@@ -1278,29 +1402,38 @@ __global__ __launch_bounds__(kFinT) void k_std_finalize(StdDev S, const double *
     status[c] = st;
   }
   if (has_kick) {
-    // inside a trajectory: kick and drift of this chain (every entry of its
-    // gradient row is final after the barrier)
-    __syncthreads();
+    // inside a trajectory: kick and drift of this chain (the gradient is
+    // zero when the status is nonzero)
     if (tid == 0 && kick.n_invalid && st != PTAFS_ST_OK) kick.n_invalid[c] += 1;
-    double *xw = kick.x + (size_t)c * S.d, *pw = kick.p + (size_t)c * S.d;
-    for (int i0 = tid; i0 < S.d; i0 += 2 * kFinT) {
-      double gv[2], pv[2], xv[2], mv[2];
+#pragma unroll
+    for (int u = 0; u < BK; ++u) {
+      const int i = tid + u * kFinT;
+      if (i < S.d) {
+        const double pi = pv[u] + kick.eps * (st != PTAFS_ST_OK ? 0.0 : gv[u]);
+        pw[i] = pi;
+        xw[i] = xv[u] + kick.eps * mv[u] * pi;
+      }
+    }
+    if (S.d <= BK * kFinT) return;
+    __syncthreads();   // every entry of the gradient row is final
+    for (int i0 = BK * kFinT + tid; i0 < S.d; i0 += 2 * kFinT) {
+      double rg[2], rp[2], rx[2], rm[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int i = i0 + u * kFinT;
         const bool in = i < S.d;
-        gv[u] = in ? gc[i] : 0.0;
-        pv[u] = in ? pw[i] : 0.0;
-        xv[u] = in ? xw[i] : 0.0;
-        mv[u] = (in && kick.inv_mass) ? kick.inv_mass[i] : 1.0;
+        rg[u] = in ? gc[i] : 0.0;
+        rp[u] = in ? pw[i] : 0.0;
+        rx[u] = in ? xw[i] : 0.0;
+        rm[u] = (in && kick.inv_mass) ? kick.inv_mass[i] : 1.0;
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const int i = i0 + u * kFinT;
         if (i < S.d) {
-          const double pi = pv[u] + kick.eps * gv[u];
+          const double pi = rp[u] + kick.eps * rg[u];
           pw[i] = pi;
-          xw[i] = xv[u] + kick.eps * mv[u] * pi;
+          xw[i] = rx[u] + kick.eps * rm[u] * pi;
         }
       }
     }
