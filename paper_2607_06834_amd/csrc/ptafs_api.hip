@@ -666,10 +666,14 @@ int ptafs_dataset_create(const ptafs_dataset_desc *d, void *stream, ptafs_datase
   hipStream_t s = (hipStream_t)stream;
   pt::Dev &B = ds->base;
   B = plan_view;
-  if (hipDeviceGetAttribute(&B.n_cu, hipDeviceAttributeMultiprocessorCount, ds->device) != hipSuccess ||
-      hipDeviceGetAttribute(&B.n_xcd, hipDeviceAttributeNumberOfXccs, ds->device) != hipSuccess) {
+  if (hipDeviceGetAttribute(&B.n_cu, hipDeviceAttributeMultiprocessorCount, ds->device) != hipSuccess) {
     free_all(ds);
     return PTAFS_E_HIP;
+  }
+  // the XCD count only shapes the balanced placement: without it none is built
+  if (hipDeviceGetAttribute(&B.n_xcd, hipDeviceAttributeNumberOfXccs, ds->device) != hipSuccess) {
+    (void)hipGetLastError();
+    B.n_xcd = 0;
   }
   // per-pulsar timing-model centring and the Hellings-Downs matrix
   std::vector<double> tc(n), tsi(n), gam((size_t)n * n);
