@@ -447,15 +447,25 @@ __device__ inline void scan_tile(const v4d &X, int row0, const double (*vz)[4], 
   st.rc += tc;
 }
 
-// Up to kTileMaxNT tiles all of W = C^-1 lives in registers, kProbPerGroup
-// problems per workgroup.  Beyond (COLW) the workgroup is one wave and one
-// problem: W is built one block column at a time in registers and kept in
-// LDS (the diagonal inverses in place of the diagonal tiles of C).
+// Up to kTileMaxNT tiles all of W = C^-1 lives in registers and a problem
+// has two waves, kBwdProbs problems per workgroup: wave 0 of a problem forms
+// v = C^T abar and then the d/dkappa quadratic forms, wave 1 the diagonal
+// inverses and W and then M = W G and the d/drho forms (the two halves are
+// independent until W and v meet in LDS), at two waves a SIMD.  Beyond
+// (COLW) the workgroup is one wave and one problem: W is built one block
+// column at a time in registers and kept in LDS (the diagonal inverses in
+// place of the diagonal tiles of C).
+constexpr int kBwdProbs = 2;
 template <int NT>
-constexpr int bwd_probs() { return NT > pt::kTileMaxNT ? 1 : kProbPerGroup; }
+constexpr int bwd_probs() { return NT > pt::kTileMaxNT ? 1 : kBwdProbs; }
+template <int NT>
+constexpr int bwd_wpp() { return NT > pt::kTileMaxNT ? 1 : 2; }   // waves per problem
+template <int NT>
+constexpr int bwd_threads() { return 64 * bwd_probs<NT>() * bwd_wpp<NT>(); }
 
 template <int NT>
-__global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const double *__restrict__ x,
+__global__ __launch_bounds__(bwd_threads<NT>()) __attribute__((amdgpu_waves_per_eu(bwd_wpp<NT>())))
+void k_cholt_bwd(Dev D, const double *__restrict__ x,
                                                   double *__restrict__ grad,
                                                   const double *__restrict__ lst,
                                                   const double *__restrict__ gch,
@@ -463,6 +473,8 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
                                                   int n_dense_groups) {
   constexpr bool COLW = NT > pt::kTileMaxNT;
   constexpr int PPG = bwd_probs<NT>();
+  constexpr int WPP = bwd_wpp<NT>();
+  static_assert(COLW || bwd_threads<NT>() == 256, "the diagonal-frequency work runs on 256 threads");
   if ((int)blockIdx.x >= n_dense_groups) {   // diagonal frequencies
     const spec_split sp(D, gridDim.x - n_dense_groups, D.n_chains, true);
     for (int it = blockIdx.x - n_dense_groups; it < sp.nb * sp.ns; it += sp.G) {
@@ -479,7 +491,10 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
   __shared__ double vz_[PPG][NP][4];                   // v_sin, v_cos, z_sin, z_cos
   __shared__ double tl_[PPG][NTL][16 * TS];
   __shared__ double ab_[PPG][NP][2];
-  const int w = threadIdx.x >> 6;
+  __shared__ int nbad_[PPG];
+  const int w = (threadIdx.x >> 6) / WPP;          // problem slot
+  const int role = (threadIdx.x >> 6) - w * WPP;   // 0: v and d/dkappa, 1: W and d/drho
+  const bool do_v = COLW || role == 0;
   const int prob = blockIdx.x * PPG + w;
   if (prob >= D.nf_gw * D.n_chains) return;
   const int k0 = prob % D.nf_gw, c = prob / D.nf_gw;
@@ -500,6 +515,7 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
   const int fl0 = D.flag_k[(size_t)c * kmax + k0] | D.flag_dense[(size_t)c * D.nf_gw + k0];
   int32_t *fout = D.flag_out + (size_t)c * (kmax + pt::kSpecSeg) + k0;
   if (D.st_pre[c] != 0 || fl0 != 0) {
+    if (!do_v) return;
     if (l == 0) *fout = 0;
     for (int I = l; I < n; I += 64) {
       gz[(size_t)I * K2] = 0.0;
@@ -513,6 +529,119 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
     }
     return;
   }
+  const double lnfy = D.lnfy[k0];   // for the outputs (loaded here, not after the barriers)
+  const double *Cb = lst + ((size_t)c * D.nf_gw + k0) * (NTILE * 256);
+  const int pc = pi16(c16);
+  if constexpr (!COLW) {
+    if (role == 1) {
+      // ==== wave 1: W = C^-1, then M = W G and the d/drho quadratic forms
+      const double rho_o = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
+      // ---- inverses of the diagonal tiles: lane group g solves tile J = g (+4)
+      //      column c16 by forward substitution; C_JJ in tl[J], W_JJ in tl[NT + J]
+#pragma unroll
+      for (int J = 0; J < NT; ++J)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          tl[J][(4 * q + v) * TS + c16] = Cb[tidx(J, J) * 256 + (4 * q + v) * 16 + c16];
+      wave_sync();
+#pragma unroll
+      for (int rnd = 0; rnd < (NT + 3) / 4; ++rnd) {
+        const int J = 4 * rnd + q;
+        if (J < NT) {
+          const double *T = tl[J];
+          // reciprocals of the diagonal first (independent of each other), so
+          // the substitution's dependent chain has multiplies, not divisions
+          double rdg[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) rdg[r] = rcp_nr(T[r * TS + r]);
+          double xs[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            __builtin_amdgcn_sched_barrier(0);     // bound the live LDS reads to one row
+            double s = (r == c16) ? 1.0 : 0.0;
+#pragma unroll
+            for (int m = 0; m < r; ++m) s -= T[r * TS + m] * xs[m];
+            xs[r] = s * rdg[r];
+          }
+#pragma unroll
+          for (int r = 0; r < 16; ++r) tl[NT + J][r * TS + c16] = xs[r];
+        }
+      }
+      wave_sync();   // the diagonal inverses in LDS
+      // ---- W = C^-1 (B layout) one block column at a time (the products of
+      //      a column depend only on that column): W_IJ = -W_II sum_{J<=K<I}
+      //      C_IK W_KJ, -W_II (A layout) read where it is used
+      v4d Wb[NTILE];
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+        __builtin_amdgcn_sched_barrier(0);     // one block column live at a time
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Wb[tidx(J, J)][v] = tl[NT + J][(4 * q + v) * TS + c16];
+#pragma unroll
+        for (int I = J + 1; I < NT; ++I) {
+          v4d Wi;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Wi[v] = -tl[NT + I][pc * TS + 4 * q + v];
+          v4d U = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int K = J; K < I; ++K) {
+            v4d a;
+            const double *t = Cb + tidx(I, K) * 256 + pc * 16 + 4 * q;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) a[s] = t[s];
+            U = mfma4(a, Wb[tidx(K, J)], U);
+          }
+          Wb[tidx(I, J)] = mfma4(Wi, U, v4d{0.0, 0.0, 0.0, 0.0});
+        }
+      }
+      wave_sync();   // every read of the diagonal inverses done before W overwrites them
+#pragma unroll
+      for (int T = 0; T < NTILE; ++T)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tl[T][(4 * q + v) * TS + c16] = Wb[T][v];
+      __syncthreads();   // W (this wave) and v, z (wave 0) of every problem in LDS
+      double dr = 0.0;
+      // ---- d/drho: M = W G column block by column block, quadratic forms;
+      //      W in A layout from LDS; block column J of G is loaded once, all
+      //      its tiles together, and serves every row block I
+#pragma unroll
+      for (int J = 0; J < NT; ++J) {
+        __builtin_amdgcn_sched_barrier(0);     // one column block of G live at a time
+        v4d G[NT];
+#pragma unroll
+        for (int K = J; K < NT; ++K) {
+          const double *gt = gch + tidx(K, J) * 256 + 64 * q + c16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) G[K][v] = gt[16 * v];
+        }
+        ScanState st{0.0, 0.0, 0.0};
+#pragma unroll
+        for (int I = J; I < NT; ++I) {
+          v4d Mt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int K = J; K <= I; ++K) {
+            v4d a;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) a[s] = tl[tidx(I, K)][pc * TS + 4 * q + s];
+            Mt = mfma4(a, G[K], Mt);
+          }
+          scan_tile(Mt, 16 * I, vz, st, l, c16, q);
+        }
+        dr += st.q;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) dr += __shfl_xor(dr, o, 64);
+      __syncthreads();   // wave 0's count of non-finite outputs
+      if (l == 0) {
+        dth[0] = dr * rho_o * 2.0 * pt::kLn10;
+        dth[1] = dr * rho_o * (-lnfy);
+        *fout = (nbad_[w] || !isfinite(dth[0]) || !isfinite(dth[1])) ? pt::kFlagOutNonfinite : 0;
+      }
+      return;
+    }
+  }
+  // ==== wave 0 (the only wave in the column-wise form): v = C^T abar, then
+  //      the d/dkappa quadratic forms and the pulsars' outputs
   // the spectra for the outputs, early (their loads and exponentials overlap the work below)
   double kapo[2];
 #pragma unroll
@@ -521,10 +650,8 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
     kapo[h] = (I < n && k0 < D.nf_rn) ? pt::powerlaw_k(D, k0, xc[D.off_rn + 2 * I], xc[D.off_rn + 2 * I + 1])
                                       : 0.0;
   }
-  const double rho_o = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
-  const double lnfy = D.lnfy[k0];   // for the outputs (loaded here, not after the barriers)
-  const double *Cb = lst + ((size_t)c * D.nf_gw + k0) * (NTILE * 256);
-
+  double vv[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  double zz[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   // ---- v_c = C^T abar_c: lane (c16, q) sums rows 16K + 4q + v of column
   //      16J + c16, then the four lane groups are added
   for (int m = l; m < NP; m += 64) {
@@ -540,6 +667,7 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
   double vcol[NT][2];
 #pragma unroll
   for (int J = 0; J < NT; ++J) {
+    if constexpr (!COLW) __builtin_amdgcn_sched_barrier(0);   // one column's loads in flight at a time
     double ss = 0.0, sc = 0.0;
 #pragma unroll
     for (int K = J; K < NT; ++K) {
@@ -558,8 +686,6 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
     vcol[J][0] = ss;
     vcol[J][1] = sc;
   }
-  double vv[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  double zz[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int I = l + 64 * h;
@@ -581,9 +707,8 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
     }
   }
 
-  double dkap[NT];
+  double dkap[NT] = {};
   double dr = 0.0;
-  const int pc = pi16(c16);
   if constexpr (COLW) {
     // ---- inverses of the diagonal tiles, in place: lane group g solves
     //      tile J = g (+4, ...) column c16 by forward substitution
@@ -673,122 +798,33 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
       }
       dr += st.q;
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dr += __shfl_xor(dr, o, 64);
   } else {
-    // ---- inverses of the diagonal tiles: lane group g solves tile J = g (+4)
-    //      column c16 by forward substitution; C_JJ in tl[J], W_JJ in tl[NT + J]
+    __syncthreads();   // W (wave 1) and v, z (this wave) of every problem in LDS
+      // ---- d/dkappa: quadratic forms down the columns of W (B layout)
 #pragma unroll
-    for (int J = 0; J < NT; ++J)
+      for (int J = 0; J < NT; ++J) {
+        __builtin_amdgcn_sched_barrier(0);       // one block column live at a time
+        v4d Wc[NT];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) tl[J][(4 * q + v) * TS + c16] = Cb[tidx(J, J) * 256 + (4 * q + v) * 16 + c16];
-    wave_sync();
+        for (int I = J; I < NT; ++I)
 #pragma unroll
-    for (int rnd = 0; rnd < (NT + 3) / 4; ++rnd) {
-      const int J = 4 * rnd + q;
-      if (J < NT) {
-        const double *T = tl[J];
-        // reciprocals of the diagonal first (independent of each other), so
-        // the substitution's dependent chain has multiplies, not divisions
-        double rdg[16];
+          for (int v = 0; v < 4; ++v) Wc[I][v] = tl[tidx(I, J)][(4 * q + v) * TS + c16];
+        ScanState st{0.0, 0.0, 0.0};
 #pragma unroll
-        for (int r = 0; r < 16; ++r) rdg[r] = rcp_nr(T[r * TS + r]);
-        double xs[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          __builtin_amdgcn_sched_barrier(0);     // bound the live LDS reads to one row
-          double s = (r == c16) ? 1.0 : 0.0;
-#pragma unroll
-          for (int m = 0; m < r; ++m) s -= T[r * TS + m] * xs[m];
-          xs[r] = s * rdg[r];
+        for (int I = J; I < NT; ++I) {
+          if (I > J + 1) __builtin_amdgcn_sched_barrier(0);   // bound the live rows of v, z
+          scan_tile(Wc[I], 16 * I, vz, st, l, c16, q);
         }
-#pragma unroll
-        for (int r = 0; r < 16; ++r) tl[NT + J][r * TS + c16] = xs[r];
+        double qq = st.q;
+        qq += xor16_d(qq, q);
+        qq += xor32_d(qq, q);
+        dkap[J] = qq;
       }
-    }
-    wave_sync();
-
-    // ---- W = C^-1 in B layout; -W_II in A layout.  The off-diagonal
-    //      factor tiles (A layout) are loaded together first, so that the
-    //      dependent products below never wait on memory.
-    v4d Ca[NTILE];
-#pragma unroll
-    for (int I = 1; I < NT; ++I)
-#pragma unroll
-      for (int K = 0; K < I; ++K) {
-        const double *t = Cb + tidx(I, K) * 256 + pc * 16 + 4 * q;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) Ca[tidx(I, K)][s] = t[s];
-      }
-    v4d Wb[NTILE];
-    v4d Wi[NT];
-#pragma unroll
-    for (int I = 0; I < NT; ++I)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        Wb[tidx(I, I)][v] = tl[NT + I][(4 * q + v) * TS + c16];
-        Wi[I][v] = -tl[NT + I][pc * TS + 4 * q + v];
-      }
-#pragma unroll
-    for (int I = 1; I < NT; ++I)
-#pragma unroll
-      for (int J = 0; J < I; ++J) {
-        v4d U = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int K = J; K < I; ++K) U = mfma4(Ca[tidx(I, K)], Wb[tidx(K, J)], U);
-        Wb[tidx(I, J)] = mfma4(Wi[I], U, v4d{0.0, 0.0, 0.0, 0.0});
-      }
-    wave_sync();
-
-    // ---- d/dkappa: quadratic forms down the columns of W
-#pragma unroll
-    for (int J = 0; J < NT; ++J) {
-      ScanState st{0.0, 0.0, 0.0};
-#pragma unroll
-      for (int I = J; I < NT; ++I) scan_tile(Wb[tidx(I, J)], 16 * I, vz, st, l, c16, q);
-      double qq = st.q;
-      qq += xor16_d(qq, q);
-      qq += xor32_d(qq, q);
-      dkap[J] = qq;
-    }
-
-    // ---- W to A layout through LDS
-#pragma unroll
-    for (int T = 0; T < NTILE; ++T)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) tl[T][(4 * q + v) * TS + c16] = Wb[T][v];
-    wave_sync();
-    v4d Wa[NTILE];
-#pragma unroll
-    for (int T = 0; T < NTILE; ++T)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) Wa[T][s] = tl[T][pc * TS + 4 * q + s];
-
-    // ---- d/drho: M = W G column block by column block, quadratic forms;
-    //      block column J of G is loaded once, all its tiles together, and
-    //      serves every row block I
-#pragma unroll
-    for (int J = 0; J < NT; ++J) {
-      v4d G[NT];
-#pragma unroll
-      for (int K = J; K < NT; ++K) {
-        const double *gt = gch + tidx(K, J) * 256 + 64 * q + c16;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) G[K][v] = gt[16 * v];
-      }
-      ScanState st{0.0, 0.0, 0.0};
-#pragma unroll
-      for (int I = J; I < NT; ++I) {
-        v4d Mt = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int K = J; K <= I; ++K) Mt = mfma4(Wa[tidx(I, K)], G[K], Mt);
-        scan_tile(Mt, 16 * I, vz, st, l, c16, q);
-      }
-      dr += st.q;
-    }
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) dr += __shfl_xor(dr, o, 64);
 
-  // ---- outputs
+  // ---- outputs of the pulsars
   bool fin = true;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -809,22 +845,27 @@ __global__ __launch_bounds__(64 * bwd_probs<NT>()) void k_cholt_bwd(Dev D, const
     }
   }
   const int nbad = __popcll(__ballot(!fin));
-  if (l == 0) {
-    const double rho = rho_o;
-    dth[0] = dr * rho * 2.0 * pt::kLn10;
-    dth[1] = dr * rho * (-lnfy);
-    *fout = (nbad || !isfinite(dth[0]) || !isfinite(dth[1])) ? pt::kFlagOutNonfinite : 0;
+  if constexpr (!COLW) {
+    if (l == 0) nbad_[w] = nbad;
+    __syncthreads();   // read by wave 1, which writes d/drho and the flag
+  } else {
+    const double rho_o = pt::powerlaw_k(D, k0, xc[D.off_gw], xc[D.off_gw + 1]);
+    if (l == 0) {
+      dth[0] = dr * rho_o * 2.0 * pt::kLn10;
+      dth[1] = dr * rho_o * (-lnfy);
+      *fout = (nbad || !isfinite(dth[0]) || !isfinite(dth[1])) ? pt::kFlagOutNonfinite : 0;
+    }
   }
 }
 
 // Workgroups for the diagonal-frequency work of `chains` chains next to ng
-// dense workgroups: the compute units those leave free (one dense workgroup
-// fills a compute unit), at least 8, split into blocks of 16 chains times
+// dense workgroups, `per_cu` of which fill a compute unit: the workgroup
+// slots those leave free, at least 8, split into blocks of 16 chains times
 // frequency segments (spec_split).
-int spec_groups(const Dev &D, int ng, int chains) {
+int spec_groups(const Dev &D, int ng, int chains, int per_cu) {
   const int nb = (chains + pt::kCB - 1) / pt::kCB;
   const int kmax = max(D.ka, D.nf_dm);
-  const int ns = max(1, min(min(kmax, pt::kSpecSeg), max(8, D.n_cu - ng) / nb));
+  const int ns = max(1, min(min(kmax, pt::kSpecSeg), max(8, per_cu * D.n_cu - ng) / nb));
   return nb * ns;
 }
 
@@ -860,8 +901,9 @@ hipError_t launch_bwd_t(const Dev &D, const double *x, double *grad, hipStream_t
   constexpr int P = bwd_probs<NT>();
   const int nprob = D.nf_gw * D.n_chains;
   const int ng = (nprob + P - 1) / P;
-  const int ns = NT > pt::kTileMaxNT ? 0 : spec_groups(D, ng, D.n_chains);
-  hipLaunchKernelGGL(k_cholt_bwd<NT>, dim3(ng + ns), dim3(64 * P), 0, s, D, x, grad,
+  // two tiled workgroups share a compute unit (half its LDS and registers each)
+  const int ns = NT > pt::kTileMaxNT ? 0 : spec_groups(D, ng, D.n_chains, 2);
+  hipLaunchKernelGGL(k_cholt_bwd<NT>, dim3(ng + ns), dim3(bwd_threads<NT>()), 0, s, D, x, grad,
                      (const double *)D.lstore, D.gtile, (const double *)D.bar_rn, ng);
   return hipGetLastError();
 }
