@@ -17,7 +17,7 @@ constexpr double kTsun = 4.925490947641e-6;      // G Msun / c^3, s
 
 constexpr int kChainBlock = 16;                  // chains per MFMA column block
 constexpr int kToaPad = 128;                     // zero padding of per-TOA arrays
-constexpr int kSpecSeg = 8;                      // frequency segments per chain (spectral kernels)
+constexpr int kSpecSeg = 16;                     // frequency segments per chain (spectral kernels)
 constexpr int kTile = 16;                        // TOAs per MFMA row tile
 
 // ---------------------------------------------------------------------------
