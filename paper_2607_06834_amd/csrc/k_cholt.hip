@@ -413,16 +413,15 @@ struct ScanState {
 };
 
 // One 16-row tile of 16 columns (B layout: item v of lane group q is row
-// row0 + 4q + v) added to the column quadratic forms x^T P x.
-__device__ inline void scan_tile(const v4d &X, int row0, const double (*vz)[4], ScanState &st,
-                                 int l, int c16, int q) {
+// row0 + 4q + v) added to the column quadratic forms x^T P x; vr[v] holds
+// (v_sin, v_cos, z_sin, z_cos) of row row0 + 4q + v.
+__device__ inline void scan_rows(const v4d &X, const double (&vr)[4][4], ScanState &st, int q) {
   double ls = 0.0, lc = 0.0, part = 0.0, sa = 0.0, ca = 0.0;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int r = row0 + 4 * q + v;
     const double x = X[v];
-    const double bs = vz[r][2] * x, bc = vz[r][3] * x;
-    const double as = vz[r][0] * x, ac = vz[r][1] * x;
+    const double bs = vr[v][2] * x, bc = vr[v][3] * x;
+    const double as = vr[v][0] * x, ac = vr[v][1] * x;
     part += as * (ls + 0.5 * bs) + ac * (lc + 0.5 * bc);
     ls += bs;
     lc += bc;
@@ -445,6 +444,21 @@ __device__ inline void scan_tile(const v4d &X, int row0, const double (*vz)[4], 
   st.q += part + (st.rs + (is - ls)) * sa + (st.rc + (ic - lc)) * ca;
   st.rs += ts;
   st.rc += tc;
+}
+
+// this lane's rows of v and z for the row tile at row0
+__device__ inline void load_rows(const double (*vz)[4], int row0, int q, double (&vr)[4][4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) vr[v][k] = vz[row0 + 4 * q + v][k];
+}
+
+__device__ inline void scan_tile(const v4d &X, int row0, const double (*vz)[4], ScanState &st,
+                                 int l, int c16, int q) {
+  double vr[4][4];
+  load_rows(vz, row0, q, vr);
+  scan_rows(X, vr, st, q);
 }
 
 // Up to kTileMaxNT tiles all of W = C^-1 lives in registers and a problem
@@ -601,34 +615,41 @@ void k_cholt_bwd(Dev D, const double *__restrict__ x,
         for (int v = 0; v < 4; ++v) tl[T][(4 * q + v) * TS + c16] = Wb[T][v];
       __syncthreads();   // W (this wave) and v, z (wave 0) of every problem in LDS
       double dr = 0.0;
-      // ---- d/drho: M = W G column block by column block, quadratic forms;
-      //      W in A layout from LDS; block column J of G is loaded once, all
-      //      its tiles together, and serves every row block I
+      // ---- d/drho: M = W G and its quadratic forms, row tile by row tile
+      //      (each tile's rows of v and z read once); chol(Gamma) in
+      //      registers, W in A layout from LDS
+      v4d G[NTILE];
 #pragma unroll
-      for (int J = 0; J < NT; ++J) {
-        __builtin_amdgcn_sched_barrier(0);     // one column block of G live at a time
-        v4d G[NT];
+      for (int J = 0; J < NT; ++J)
 #pragma unroll
         for (int K = J; K < NT; ++K) {
           const double *gt = gch + tidx(K, J) * 256 + 64 * q + c16;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) G[K][v] = gt[16 * v];
+          for (int v = 0; v < 4; ++v) G[tidx(K, J)][v] = gt[16 * v];
         }
-        ScanState st{0.0, 0.0, 0.0};
+      ScanState st[NT];
 #pragma unroll
-        for (int I = J; I < NT; ++I) {
+      for (int J = 0; J < NT; ++J) st[J] = ScanState{0.0, 0.0, 0.0};
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        __builtin_amdgcn_sched_barrier(0);     // one row tile live at a time
+        double vr[4][4];
+        load_rows(vz, 16 * I, q, vr);
+        v4d a[NT];
+#pragma unroll
+        for (int K = 0; K <= I; ++K)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) a[K][s] = tl[tidx(I, K)][pc * TS + 4 * q + s];
+#pragma unroll
+        for (int J = 0; J <= I; ++J) {
           v4d Mt = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int K = J; K <= I; ++K) {
-            v4d a;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) a[s] = tl[tidx(I, K)][pc * TS + 4 * q + s];
-            Mt = mfma4(a, G[K], Mt);
-          }
-          scan_tile(Mt, 16 * I, vz, st, l, c16, q);
+          for (int K = J; K <= I; ++K) Mt = mfma4(a[K], G[tidx(K, J)], Mt);
+          scan_rows(Mt, vr, st[J], q);
         }
-        dr += st.q;
       }
+#pragma unroll
+      for (int J = 0; J < NT; ++J) dr += st[J].q;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) dr += __shfl_xor(dr, o, 64);
       __syncthreads();   // wave 0's count of non-finite outputs
@@ -802,22 +823,27 @@ void k_cholt_bwd(Dev D, const double *__restrict__ x,
     for (int o = 32; o > 0; o >>= 1) dr += __shfl_xor(dr, o, 64);
   } else {
     __syncthreads();   // W (wave 1) and v, z (this wave) of every problem in LDS
-      // ---- d/dkappa: quadratic forms down the columns of W (B layout)
+      // ---- d/dkappa: quadratic forms down the columns of W (B layout), row
+      //      tile by row tile, so that each tile's rows of v and z are read once
+      ScanState st[NT];
+#pragma unroll
+      for (int J = 0; J < NT; ++J) st[J] = ScanState{0.0, 0.0, 0.0};
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        __builtin_amdgcn_sched_barrier(0);       // one row tile live at a time
+        double vr[4][4];
+        load_rows(vz, 16 * I, q, vr);
+        v4d Wr[NT];
+#pragma unroll
+        for (int J = 0; J <= I; ++J)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Wr[J][v] = tl[tidx(I, J)][(4 * q + v) * TS + c16];
+#pragma unroll
+        for (int J = 0; J <= I; ++J) scan_rows(Wr[J], vr, st[J], q);
+      }
 #pragma unroll
       for (int J = 0; J < NT; ++J) {
-        __builtin_amdgcn_sched_barrier(0);       // one block column live at a time
-        v4d Wc[NT];
-#pragma unroll
-        for (int I = J; I < NT; ++I)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) Wc[I][v] = tl[tidx(I, J)][(4 * q + v) * TS + c16];
-        ScanState st{0.0, 0.0, 0.0};
-#pragma unroll
-        for (int I = J; I < NT; ++I) {
-          if (I > J + 1) __builtin_amdgcn_sched_barrier(0);   // bound the live rows of v, z
-          scan_tile(Wc[I], 16 * I, vz, st, l, c16, q);
-        }
-        double qq = st.q;
+        double qq = st[J].q;
         qq += xor16_d(qq, q);
         qq += xor32_d(qq, q);
         dkap[J] = qq;
