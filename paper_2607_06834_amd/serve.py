@@ -43,6 +43,10 @@ class Rejected(RuntimeError):
     descriptor is invalid)."""
 
 
+class Cancelled(RuntimeError):
+    """Raised by ``poll``/``wait`` for a request that was cancelled."""
+
+
 @dataclasses.dataclass
 class _Req:
     rid: int
@@ -61,6 +65,7 @@ class _Req:
     t_done: float = float("nan")
     status: str = "queued"
     error: str | None = None
+    cancel: bool = False
     # running state
     ds: object = None
     stream: object = None
@@ -83,7 +88,8 @@ class Server:
     ``poll(id)`` returns None until the request has finished, then a dict with
     the samples (n_traj, n_chains, n_theta or d), final log p, acceptance and
     invalid-evaluation counts and the arrival / admission / completion times
-    (``time.perf_counter`` seconds)."""
+    (``time.perf_counter`` seconds).  ``cancel(id)`` withdraws a queued request
+    or stops a running one at its next quantum boundary, freeing its memory."""
 
     def __init__(self, budget_bytes: int, max_slots: int = 8, quantum: int = 10, device: int = 0,
                  tuning=None, use_graph: bool = True):
@@ -153,14 +159,33 @@ class Server:
             r = self._reqs[rid]
             if r.status == "error":
                 raise RuntimeError(f"request {rid} failed: {r.error}")
+            if r.status == "cancelled":
+                raise Cancelled(f"request {rid} was cancelled after {r.done_traj} trajectories")
             return r.result if r.status == "done" else None
+
+    def cancel(self, rid: int) -> bool:
+        """Cancel a request.  A queued request leaves the queue at once; an
+        admitted one stops at its next quantum boundary (the quantum in flight
+        finishes on its own stream), and its device memory and budget are
+        released then.  Returns False if the request had already finished."""
+        with self._lock:
+            r = self._reqs[rid]
+            if r.status in ("done", "error", "cancelled"):
+                return False
+            if r.status == "queued" and r in self._queue:
+                self._queue.remove(r)
+                r.status = "cancelled"
+                self._lock.notify_all()
+                return True
+            r.cancel = True
+            return True
 
     def wait(self, rid: int, timeout: float | None = None):
         t_end = None if timeout is None else time.perf_counter() + timeout
         with self._lock:
             while True:
                 r = self._reqs[rid]
-                if r.status in ("done", "error") or self._err is not None:
+                if r.status in ("done", "error", "cancelled") or self._err is not None:
                     break
                 left = None if t_end is None else t_end - time.perf_counter()
                 if left is not None and left <= 0:
@@ -267,6 +292,10 @@ class Server:
                 footprint=r.footprint, tuning=tuple(r.tuning))
         r.t_done = r.result["t_done"]
         r.result["latency"] = r.t_done - r.t_arrival
+        self._drop(r)
+
+    def _drop(self, r: _Req):
+        # the data set waits for its own last work before its memory goes back
         r.ds.close()
         r.ds = r.stream = r.x = r.lp = r.gr = r.acc = r.bad = r.im = r.smp = r.event = None
         r.out = []
@@ -305,6 +334,10 @@ class Server:
                         self._lock.wait(0.002)
                         continue
                 for r in started:
+                    if r.cancel:   # cancelled while it was being admitted
+                        self._drop(r)
+                        self._release(r, "cancelled")
+                        continue
                     active.append(r)
                     self._launch(r)
                 self.max_active = max(self.max_active, len(active))
@@ -313,7 +346,11 @@ class Server:
                 for r in list(active):
                     if r.event is not None and r.event.query():
                         self._collect(r)
-                        if r.done_traj >= r.n_traj:
+                        if r.cancel and r.done_traj < r.n_traj:
+                            self._drop(r)
+                            active.remove(r)
+                            self._release(r, "cancelled")
+                        elif r.done_traj >= r.n_traj:
                             self._finish(r)
                             active.remove(r)
                             self._release(r, "done")

@@ -116,3 +116,53 @@ def test_estimate_matches_created_layout(mods):
               "hmc_bytes"):
         assert getattr(est, f) == getattr(lay, f), f
     g.close()
+
+
+def test_cancel_mid_flight_frees_the_request(mods):
+    """A request cancelled after its first quantum stops at the next quantum
+    boundary, gives back its budget and device state, and the request beside
+    it finishes with the result it has alone."""
+    import time
+    api, serve = mods
+    (dsa, xa), (dsb, xb) = request(0), request(1)
+    alone, _ = run_requests(serve, [(dsb, xb)], seeds=[77], budget_bytes=1 << 34, max_slots=1, quantum=3)
+    srv = serve.Server(budget_bytes=1 << 34, max_slots=8, quantum=3)
+    try:
+        ra = srv.submit(dsa, x0=xa, n_traj=3000, n_leapfrog=4, eps=0.01, seed=31, keep="all")
+        rb = srv.submit(dsb, x0=xb, n_traj=7, n_leapfrog=4, eps=0.01, seed=77, keep="all")
+        t_end = time.perf_counter() + 120
+        while srv._reqs[ra].done_traj < 3:
+            assert time.perf_counter() < t_end, "first quantum of the long request never finished"
+            time.sleep(0.01)
+        assert srv.cancel(ra)
+        with pytest.raises(serve.Cancelled):
+            srv.wait(ra, timeout=120)
+        got = srv.wait(rb, timeout=300)
+        assert 3 <= srv._reqs[ra].done_traj < 3000
+        assert srv._reqs[ra].ds is None and srv._reqs[ra].smp is None
+        assert srv._used == 0
+        assert not srv.cancel(rb)          # already finished
+        for key in ("samples", "logp", "n_accept", "n_invalid", "x"):
+            np.testing.assert_array_equal(alone[0][key], got[key])
+    finally:
+        srv.close()
+
+
+def test_cancel_queued_request(mods):
+    """A request cancelled while it waits for a slot is never admitted; the
+    one ahead of it completes."""
+    api, serve = mods
+    (dsa, xa), (dsb, xb) = request(2), request(3)
+    srv = serve.Server(budget_bytes=1 << 34, max_slots=1, quantum=3)
+    try:
+        ra = srv.submit(dsa, x0=xa, n_traj=30, n_leapfrog=4, eps=0.01, seed=31, keep="all")
+        rb = srv.submit(dsb, x0=xb, n_traj=7, n_leapfrog=4, eps=0.01, seed=32, keep="all")
+        assert srv.cancel(rb)
+        with pytest.raises(serve.Cancelled):
+            srv.poll(rb)
+        got = srv.wait(ra, timeout=300)
+        assert got["samples"].shape[0] == 30
+        assert srv._reqs[rb].ds is None and np.isnan(srv._reqs[rb].t_admit)
+        assert srv._used == 0
+    finally:
+        srv.close()
