@@ -557,6 +557,18 @@ void k_cholt_bwd(Dev D, const double *__restrict__ x,
 #pragma unroll
         for (int v = 0; v < 4; ++v)
           tl[J][(4 * q + v) * TS + c16] = Cb[tidx(J, J) * 256 + (4 * q + v) * 16 + c16];
+      // the off-diagonal factor tiles (A layout), issued now so that their
+      // loads run under the substitutions and the products below never wait
+      // on memory
+      v4d Ca[NTILE];
+#pragma unroll
+      for (int I = 1; I < NT; ++I)
+#pragma unroll
+        for (int K = 0; K < I; ++K) {
+          const double *t = Cb + tidx(I, K) * 256 + pc * 16 + 4 * q;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) Ca[tidx(I, K)][s] = t[s];
+        }
       wave_sync();
 #pragma unroll
       for (int rnd = 0; rnd < (NT + 3) / 4; ++rnd) {
@@ -598,13 +610,7 @@ void k_cholt_bwd(Dev D, const double *__restrict__ x,
           for (int v = 0; v < 4; ++v) Wi[v] = -tl[NT + I][pc * TS + 4 * q + v];
           v4d U = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int K = J; K < I; ++K) {
-            v4d a;
-            const double *t = Cb + tidx(I, K) * 256 + pc * 16 + 4 * q;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) a[s] = t[s];
-            U = mfma4(a, Wb[tidx(K, J)], U);
-          }
+          for (int K = J; K < I; ++K) U = mfma4(Ca[tidx(I, K)], Wb[tidx(K, J)], U);
           Wb[tidx(I, J)] = mfma4(Wi, U, v4d{0.0, 0.0, 0.0, 0.0});
         }
       }
